@@ -1,0 +1,278 @@
+"""Oracle Hamiltonian Monte Carlo sampler (test infrastructure only).
+
+Follows Section 3 of the paper: the Hamiltonian eq:Hamiltonian with the
+diagonal mass matrix eq:M_ab, Hamilton's equations eq:hamilton integrated by
+leapfrog (Section 3.3), fresh momenta for every trajectory and a
+Metropolis-Hastings test of the end point (Section 3.2), step-size tuning to
+an acceptance rate of 0.65 by dual averaging (Section 3.3, after Hoffman &
+Gelman's NUTS paper), and the Monte-Carlo mean eq:int_mc.
+
+Readings used here:
+  * Leapfrog is kick-drift-kick; the gradient at the end of a trajectory is
+    reused at the start of the next one (L gradients per trajectory).
+  * A rejected trajectory repeats the current state as a chain sample and
+    new momenta are drawn next iteration (standard Metropolis-Hastings; the
+    "start all over" wording of Section 3.2 read as retry-until-accept would
+    bias the chain).  The Monte-Carlo mean counts the repeats.
+  * Accept iff ln u < -dH with u in (0, 1]; a non-finite dH rejects.
+  * Mass matrix per real coordinate: M^-1 = sigma_k^2/2 for each of Re and Im
+    of a mode (P(k_j)/2 of eq:M_ab in discrete units), sigma_v^2/H0^2 for a
+    distance, 1 for s = sigma_NL/100.  Frozen distances or sigma_NL get no
+    momentum and do not move.
+"""
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import philox
+from .model import (H0, logpost_grad, mode_indices, mode_variance, pair_weight,
+                    retained_mask)
+
+
+# ----------------------------------------------------------------------------
+# Independent coordinates of the half spectrum
+# ----------------------------------------------------------------------------
+
+def mirror_mask(n):
+    """kz = 0 entries whose Hermitian partner is the canonical one.
+
+    Canonical half of the kz = 0 plane: ny > 0, or ny = 0 and nx > 0.
+    """
+    nx, ny, nz = mode_indices(n)
+    return retained_mask(n) & (nz == 0) & ((ny < 0) | ((ny == 0) & (nx < 0)))
+
+
+def canonical_mask(n):
+    return retained_mask(n) & ~mirror_mask(n)
+
+
+def partner_flat_index(n):
+    """Flat half-spectrum index of (-kx, -ky, kz) for every entry (kz = 0 use)."""
+    j = np.arange(n)
+    neg = (-j) % n
+    nh = n // 2 + 1
+    kz = np.arange(nh)
+    return (neg[:, None, None] * n + neg[None, :, None]) * nh + kz[None, None, :]
+
+
+def symmetrise(n, arr):
+    """Overwrite mirror entries with the conjugate of their canonical partner."""
+    out = np.array(arr, dtype=np.complex128, copy=True)
+    mm = mirror_mask(n)
+    flat = out.reshape(-1)
+    part = partner_flat_index(n).reshape(-1)
+    idx = np.nonzero(mm.reshape(-1))[0]
+    flat[idx] = np.conj(flat[part[idx]])
+    out[~retained_mask(n)] = 0.0
+    return out
+
+
+def pack_modes(n, dhat):
+    """Paper's flat order (eq:q): (Re of independent modes, Im of them)."""
+    sel = canonical_mask(n).reshape(-1)
+    v = np.asarray(dhat).reshape(-1)[sel]
+    return np.concatenate([v.real, v.imag])
+
+
+def unpack_modes(n, vec):
+    sel = canonical_mask(n).reshape(-1)
+    m = int(sel.sum())
+    out = np.zeros(n * n * (n // 2 + 1), dtype=np.complex128)
+    out[sel] = vec[:m] + 1j * vec[m:2 * m]
+    return symmetrise(n, out.reshape(n, n, n // 2 + 1))
+
+
+# ----------------------------------------------------------------------------
+# Phase-space state
+# ----------------------------------------------------------------------------
+
+@dataclass
+class State:
+    modes: np.ndarray     # complex (N, N, N/2+1)
+    dist: np.ndarray      # (n,)
+    s: float              # sigma_NL / 100 km/s
+
+    def copy(self):
+        return State(self.modes.copy(), self.dist.copy(), float(self.s))
+
+
+def inverse_mass(prob):
+    """Diagonal M^-1 of eq:M_ab: (per real part of each mode, per distance, s)."""
+    var = mode_variance(prob)
+    minv_modes = 0.5 * var
+    minv_d = (prob.sigma_v / H0) ** 2 if prob.sample_distances else 0.0
+    minv_s = 1.0 if prob.sample_sigma_nl else 0.0
+    return minv_modes, minv_d, minv_s
+
+
+def draw_momenta(prob, seed, iteration):
+    """p ~ N(0, M): variance 2/sigma_k^2 per real part of a mode, etc."""
+    n = prob.n_grid
+    var = mode_variance(prob)
+    nh = n // 2 + 1
+    flat_idx = np.arange(n * n * nh)
+    canon = partner_flat_index(n).reshape(-1)
+    mm = mirror_mask(n).reshape(-1)
+    src = np.where(mm, canon, flat_idx)            # draw at the canonical index
+    z0, z1 = philox.normal_pair(philox.draw_words(seed, iteration, philox.PURPOSE_MODES, src))
+    scale = np.sqrt(2.0 / np.where(var > 0, var, 1.0)).reshape(-1)
+    pm = scale * (z0 + 1j * z1)
+    pm = np.where(mm, np.conj(pm), pm)
+    pm = np.where(retained_mask(n).reshape(-1), pm, 0.0).reshape(n, n, nh)
+    if prob.sample_distances:
+        zd, _ = philox.normal_pair(philox.draw_words(seed, iteration, philox.PURPOSE_DIST,
+                                                     np.arange(prob.n_gal)))
+        pd = (H0 / prob.sigma_v) * zd
+    else:
+        pd = np.zeros(prob.n_gal)
+    if prob.sample_sigma_nl:
+        zs, _ = philox.normal_pair(philox.draw_words(seed, iteration, philox.PURPOSE_SNL, [0]))
+        ps = float(zs[0])
+    else:
+        ps = 0.0
+    return State(pm, pd, ps)
+
+
+def kinetic(prob, p):
+    """K = (1/2) p^T M^-1 p over independent real coordinates (eq:Hamiltonian).
+
+    Per stored mode entry: (w_k / 8) sigma_k^2 |p_k|^2.
+    """
+    var = mode_variance(prob)
+    w = pair_weight(prob.n_grid)
+    k_modes = float(np.sum(w * var * np.abs(p.modes) ** 2)) / 8.0
+    _, minv_d, minv_s = inverse_mass(prob)
+    return k_modes + 0.5 * minv_d * float(np.sum(p.dist ** 2)) + 0.5 * minv_s * p.s * p.s
+
+
+def gradient(prob, q):
+    return logpost_grad(prob, q.modes, q.dist, q.s)
+
+
+def leapfrog(prob, q, p, eps, n_steps, cached=None):
+    """Kick-drift-kick integration of eq:hamilton.
+
+    cached: (psi, g_modes, g_d, g_s) at q, else computed.  Returns
+    (q, p, (psi, g_modes, g_d, g_s)) at the end point.
+    """
+    q = q.copy()
+    p = p.copy()
+    if cached is None:
+        cached = gradient(prob, q)
+    psi, gm, gd, gs = cached
+    minv_m, minv_d, minv_s = inverse_mass(prob)
+    for _ in range(n_steps):
+        p.modes = p.modes - 0.5 * eps * gm
+        p.dist = p.dist - 0.5 * eps * gd if prob.sample_distances else p.dist
+        p.s = p.s - 0.5 * eps * gs if prob.sample_sigma_nl else p.s
+        q.modes = q.modes + eps * minv_m * p.modes
+        q.dist = q.dist + eps * minv_d * p.dist
+        q.s = q.s + eps * minv_s * p.s
+        psi, gm, gd, gs = gradient(prob, q)
+        p.modes = p.modes - 0.5 * eps * gm
+        p.dist = p.dist - 0.5 * eps * gd if prob.sample_distances else p.dist
+        p.s = p.s - 0.5 * eps * gs if prob.sample_sigma_nl else p.s
+    return q, p, (psi, gm, gd, gs)
+
+
+# ----------------------------------------------------------------------------
+# Dual averaging of the step size (Hoffman & Gelman, NUTS paper, Sec. 3.2.1)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class DualAveraging:
+    eps0: float
+    target: float = 0.65
+    gamma: float = 0.05
+    t0: float = 10.0
+    kappa: float = 0.75
+
+    def __post_init__(self):
+        self.mu = math.log(10.0 * self.eps0)
+        self.hbar = 0.0
+        self.log_eps_bar = 0.0
+        self.m = 0
+
+    def update(self, accept_prob):
+        """One adaptation step; returns the step size for the next iteration."""
+        self.m += 1
+        m = float(self.m)
+        eta = 1.0 / (m + self.t0)
+        self.hbar = (1.0 - eta) * self.hbar + eta * (self.target - accept_prob)
+        log_eps = self.mu - math.sqrt(m) / self.gamma * self.hbar
+        wgt = m ** (-self.kappa)
+        self.log_eps_bar = wgt * log_eps + (1.0 - wgt) * self.log_eps_bar
+        return math.exp(log_eps)
+
+    def final(self):
+        return math.exp(self.log_eps_bar)
+
+
+def accept_probability(dh):
+    """min(1, exp(-dH)); 0 for a non-finite dH."""
+    if not math.isfinite(dh):
+        return 0.0
+    return 1.0 if dh <= 0.0 else math.exp(-dh)
+
+
+# ----------------------------------------------------------------------------
+# The chain (Section 3.2, eq:int_mc)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class ChainResult:
+    state: State
+    dh: np.ndarray
+    accepted: np.ndarray
+    eps: float
+    mode_sum: np.ndarray
+    n_mean: int
+
+
+def hmc_run(prob, q0, n_iter, n_leapfrog, eps0, seed, warmup=0, target=0.65,
+            jitter=False, callback=None):
+    """Run n_iter HMC iterations from q0.
+
+    Iterations < warmup adapt the step size by dual averaging; from then on it
+    is frozen at the averaged value.  Post-warm-up chain states (repeats
+    included) are summed into mode_sum.  With jitter the step of an iteration
+    is eps * (0.9 + 0.2 u), u uniform from the Philox stream.
+    """
+    q = q0.copy()
+    cached = gradient(prob, q)
+    eps = float(eps0)
+    da = DualAveraging(eps0, target) if warmup > 0 else None
+    dh_rec = np.zeros(n_iter)
+    acc_rec = np.zeros(n_iter, dtype=np.int32)
+    mode_sum = np.zeros_like(q.modes)
+    n_mean = 0
+    for it in range(n_iter):
+        eps_it = eps
+        if jitter:
+            w = philox.draw_words(seed, it, philox.PURPOSE_JITTER, [0])
+            eps_it = eps * (0.9 + 0.2 * float(philox.uniform53(w[0, 0], w[0, 1])))
+        p = draw_momenta(prob, seed, it)
+        h_start = kinetic(prob, p) + cached[0]
+        q1, p1, cached1 = leapfrog(prob, q, p, eps_it, n_leapfrog, cached)
+        h_end = kinetic(prob, p1) + cached1[0]
+        dh = h_end - h_start
+        if not math.isfinite(dh):
+            dh = math.inf
+        w = philox.draw_words(seed, it, philox.PURPOSE_ACCEPT, [0])
+        u = float(philox.uniform53(w[0, 0], w[0, 1]))
+        accept = math.log(u) < -dh
+        if accept:
+            q, cached = q1, cached1
+        dh_rec[it] = dh
+        acc_rec[it] = int(accept)
+        if it < warmup:
+            eps = da.update(accept_probability(dh))
+            if it == warmup - 1:
+                eps = da.final()
+        else:
+            mode_sum += q.modes
+            n_mean += 1
+        if callback is not None:
+            callback(it, q, dh, accept, eps_it)
+    return ChainResult(q, dh_rec, acc_rec, eps, mode_sum, n_mean)
