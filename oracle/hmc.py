@@ -111,10 +111,14 @@ def draw_momenta(prob, seed, iteration):
     n = prob.n_grid
     var = mode_variance(prob)
     nh = n // 2 + 1
-    flat_idx = np.arange(n * n * nh)
-    canon = partner_flat_index(n).reshape(-1)
+    # Stream index of entry (kx, ky, kz): its flat position in the layout
+    # without the kz = N/2 plane (which holds only excluded modes),
+    # (kx N + ky) N/2 + kz; a mirror entry draws at its canonical partner.
+    kx, ky, kz = np.meshgrid(np.arange(n), np.arange(n), np.arange(nh), indexing="ij")
+    stream_idx = ((kx * n + ky) * (n // 2) + kz).reshape(-1)
+    partner_idx = ((((-kx) % n) * n + ((-ky) % n)) * (n // 2)).reshape(-1)
     mm = mirror_mask(n).reshape(-1)
-    src = np.where(mm, canon, flat_idx)            # draw at the canonical index
+    src = np.where(mm, partner_idx, stream_idx)
     z0, z1 = philox.normal_pair(philox.draw_words(seed, iteration, philox.PURPOSE_MODES, src))
     scale = np.sqrt(2.0 / np.where(var > 0, var, 1.0)).reshape(-1)
     pm = scale * (z0 + 1j * z1)

@@ -15,6 +15,8 @@ rounds; ten rounds in all.  Pinned by the published known-answer vectors.
 Stream layout shared with the GPU path (a reading: the paper states none):
     key     = (seed & 0xffffffff, seed >> 32)
     counter = (index & 0xffffffff, index >> 32, iteration, purpose)
+    index of a mode: (kx N + ky) N/2 + kz; of a distance: its catalogue
+    position; of sigma_NL and of the accept/jitter draws: 0.
 Uniforms: u = ((x >> 11) + 1) * 2^-53 in (0, 1], x = (w1 << 32) | w0 built
 from two 32-bit output words.  Normals: Box-Muller on two such uniforms.
 """
