@@ -1,0 +1,168 @@
+/*
+ * hamlet.h - C ABI of the HAMLET log-posterior / gradient / HMC library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the posterior of the peculiar-velocity
+ * reconstruction of Valade, Hoffman, Libeskind & Graziani, "Hamiltonian
+ * Monte Carlo reconstruction from peculiar velocities" (HAMLET), and runs
+ * its Hamiltonian Monte Carlo sampler, on one GPU.
+ *
+ * Parameters q (eq:q): the Fourier modes of the linear density contrast on
+ * a periodic N^3 grid, the true distances d_i of the n catalogue points and
+ * s = sigma_NL / (100 km/s).  Psi(q) = -ln Pi(q) (eq:Psi) is the sum of
+ *   - the Gaussian prior of the modes (eq:prior-k),
+ *   - per point: (mu_i - mu(d_i))^2 / 2 sigma_mu,i^2 (eqn:lmu, Section 2.2),
+ *     r_i^2 / 2 kappa_i^2 + ln kappa_i with r_i = v_obs,i(d_i) - rhat_i . v(d_i rhat_i)
+ *     (eq:vrobs, eqn:lvr, eq:kappa), and -ln N_dz(d_i) (eq:D),
+ * without pure constants.  The velocity field v is the linear-theory field of
+ * the modes (eq:vel-field), interpolated cloud-in-cell (trilinear, periodic)
+ * at d_i rhat_i with the observer at the box centre (Section 5.1).
+ *
+ * Units: distances Mpc/h, velocities km/s, H0 = 100 km/s per Mpc/h.
+ *
+ * Mode layout ("half spectrum"): double complex, interleaved (re, im),
+ * index [kx][ky][kz] row-major with kx, ky in [0, N) and kz in [0, N/2)
+ * (kz fastest): N * N * N/2 entries.  Fourier convention
+ *   delta(x) = N^-3 sum_k dhat_k exp(+i k.x),  k = 2 pi n / L.
+ * Retained modes exclude k = 0 and every mode with a Nyquist component
+ * (|n_c| = N/2); those entries must be zero and stay zero.  On the kz = 0
+ * plane both members of a Hermitian pair are stored and must be conjugate
+ * (dhat(-kx, -ky, 0) = conj dhat(kx, ky, 0)); every routine preserves this.
+ * Mode gradients use the convention G = dPsi/dRe + i dPsi/dIm with respect
+ * to the independent coordinates of each mode; momenta use the same layout.
+ *
+ * Streams: every call is asynchronous on the plan's HIP stream (the stream
+ * given at creation); only hamlet_plan_create and hamlet_plan_destroy
+ * synchronise.  Calls on plans that share a stream run in call order.
+ *
+ * Errors: every entry point returns a hamlet_status; the message of the last
+ * non-OK status of the calling thread is hamlet_last_error().  A parameter
+ * state outside the domain of the posterior (a distance <= 0, beyond
+ * c / (3 Omega0 H0), or outside the distance histogram) is not an error:
+ * Psi is +inf there and the sampler rejects such a trajectory.
+ */
+#ifndef HAMLET_H
+#define HAMLET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HAMLET_OK = 0,
+  HAMLET_EINVAL = -1,       /* invalid argument (message says which) */
+  HAMLET_ENOMEM = -2,       /* device allocation failed */
+  HAMLET_EDEVICE = -3,      /* a HIP call failed */
+  HAMLET_EUNSUPPORTED = -4  /* grid size or option not built */
+} hamlet_status;
+
+typedef enum {
+  HAMLET_FP64 = 0,          /* every transform, gather and scatter in FP64 */
+  HAMLET_FP32_FP64E = 1     /* transforms, gather, scatter in FP32; Hamiltonian,
+                               likelihood, dH, Metropolis test, momenta in FP64 */
+} hamlet_precision;
+
+/* Problem statement (Section 2; the grid and box of Section 5.1).  All
+ * pointers are host memory, read during hamlet_plan_create only. */
+typedef struct {
+  int32_t n_grid;           /* N: 16, 32, 64, 128 or 256 */
+  int32_t precision;        /* hamlet_precision */
+  double box;               /* L, Mpc/h */
+  double omega_m;           /* Omega0 of zbar(d) (Section 2.2) */
+  double h;                 /* little h in mu(d) = 5 log10(d (1 + zbar) / h) + 25 */
+  double f_growth;          /* f(Omega0) of eq:vel-field */
+  double sigma_v;           /* km/s; mass of a distance is sigma_v^2 / H0^2 (eq:M_ab) */
+  const double* pk_n2;      /* P(|k|) in (Mpc/h)^3 at |k| = (2 pi / L) sqrt(j),
+                               j = 0 .. 3 (N/2)^2; mode variance is N^6 P / L^3 */
+  int32_t n_pk;             /* must be 3 (N/2)^2 + 1 */
+  double hist_width;        /* bin width of the distance prior (eq:D), Mpc/h; <= 0: 5 */
+  int32_t sample_distances; /* 0: distances frozen (no momentum) */
+  int32_t sample_sigma_nl;  /* 0: s frozen */
+} hamlet_plan_desc;
+
+/* Catalogue (Section 2, Section 5.1): n points, host arrays of length n.
+ * rhat is 3 n doubles (x, y, z per point), the unit vector
+ * (cos SGB cos SGL, cos SGB sin SGL, sin SGB).  cz = c z (km/s). */
+typedef struct {
+  int64_t n;
+  const double* rhat;
+  const double* mu;
+  const double* sigma_mu;
+  const double* cz;
+  const double* sigma_cz;
+} hamlet_catalog;
+
+typedef struct hamlet_plan hamlet_plan;
+
+/* Creates a plan on the current HIP device: uploads tables and catalogue and
+ * allocates the workspace (hamlet_plan_footprint_bytes).  The distance prior
+ * (eq:D) is built here from the catalogue: redshift distances by the
+ * integral of eq:e:dz (composite Simpson, 2000 intervals), a histogram of
+ * bin width hist_width over [0, max d_z + 15 Mpc/h) with one pseudo-count per
+ * bin, normalised to a density.  `stream` is a hipStream_t (NULL: default
+ * stream).  On error *out is NULL. */
+hamlet_status hamlet_plan_create(const hamlet_plan_desc* desc, const hamlet_catalog* cat, void* stream,
+                                 hamlet_plan** out);
+hamlet_status hamlet_plan_destroy(hamlet_plan* plan);
+
+/* Device bytes a plan of this description with n_gal points would own. */
+hamlet_status hamlet_plan_footprint_bytes(const hamlet_plan_desc* desc, int64_t n_gal, size_t* bytes);
+
+/* Psi(q) and its gradient for n_plans plans (batch of independent chains).
+ * All array arguments are device pointers owned by the caller, one per plan:
+ *   q_modes[j], g_modes[j]: N*N*N/2 double complex (layout above)
+ *   q_dist[j],  g_dist[j]:  n doubles
+ *   q_snl[j], g_snl[j]:     1 double each (s and dPsi/ds)
+ *   psi[j]:                 1 double (Psi, +inf outside the domain)
+ * Inputs and outputs must not overlap. */
+hamlet_status hamlet_logpost_grad(hamlet_plan* const* plans, int32_t n_plans,
+                                  const void* const* q_modes, const double* const* q_dist,
+                                  const double* const* q_snl,
+                                  void* const* g_modes, double* const* g_dist, double* const* g_snl,
+                                  double* const* psi);
+
+/* n_steps[j] kick-drift-kick leapfrog steps of size eps[j] (host arrays) of
+ * Hamilton's equations (eq:hamilton) with the mass matrix of eq:M_ab, from
+ * (q, p) in place (device pointers as above; p_* have the layout of q_*).
+ * psi[j] receives Psi at the end point.  Frozen coordinates do not move. */
+hamlet_status hamlet_leapfrog(hamlet_plan* const* plans, int32_t n_plans, const double* eps,
+                              const int32_t* n_steps,
+                              void* const* q_modes, double* const* q_dist, double* const* q_snl,
+                              void* const* p_modes, double* const* p_dist, double* const* p_snl,
+                              double* const* psi);
+
+typedef struct {
+  int32_t n_iter;           /* HMC iterations (trajectories) */
+  int32_t n_leapfrog;       /* leapfrog steps per trajectory */
+  int32_t warmup;           /* first `warmup` iterations adapt eps by dual averaging */
+  int32_t jitter_eps;       /* 1: step of iteration t is eps (0.9 + 0.2 u_t) */
+  double eps0;              /* initial step */
+  double target_accept;     /* dual-averaging target (Section 3.3: 0.65) */
+  uint64_t seed;            /* Philox4x32-10 key */
+} hamlet_hmc_opts;
+
+/* Runs the chain of Section 3.2 for each plan: fresh momenta p ~ N(0, M)
+ * per trajectory (Philox4x32-10, counter (index, 0, iteration, purpose)),
+ * n_leapfrog steps, Metropolis-Hastings test ln u < -dH (a rejected
+ * trajectory repeats the state), dual averaging of eps during warm-up.
+ * q_* (device, in/out): start state in, last state out.
+ * mode_sum[j] (device, may be NULL): sum over post-warm-up iterations of the
+ *   chain's mode state (eq:int_mc numerator); accumulated onto its contents.
+ * dh[j], accepted[j] (device, may be NULL): n_iter per plan.
+ * eps_out (host, may be NULL): n_plans, the step after warm-up (synchronises). */
+hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_plans, const hamlet_hmc_opts* opts,
+                             void* const* q_modes, double* const* q_dist, double* const* q_snl,
+                             void* const* mode_sum, double* const* dh, int32_t* const* accepted,
+                             double* eps_out);
+
+/* Message of the last non-OK status on this thread ("" if none). */
+const char* hamlet_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HAMLET_H */

@@ -1,0 +1,169 @@
+// LDS-staged Stockham FFT building blocks for gfx950 (wave64).
+//
+// The velocity field of eq:vel-field is three inverse 3-D transforms of the
+// modes, and the gradient needs three forward transforms of the scattered
+// galaxy weights (the hand-built inverse-transform gradient of Section 4).
+// Each 3-D transform is done as three batched 1-D passes; this header holds
+// the 1-D part: a batch of B transforms of length N held in LDS is
+// transformed in place by self-sorting (Stockham) radix-R stages, each
+// butterfly's R points kept in registers.
+//
+// Stage with sub-transform length L (product of the earlier radices): for
+// butterfly j in [0, N/R), k = j mod L,
+//     x_r = in[j + r N/R] * w^(r k),  w = exp(sign 2 pi i / (L R)),
+//     y   = DFT_R(x),
+//     out[(j / L) L R + k + s L] = y_s.
+// Twiddles come from a table tw[m] = exp(-2 pi i m / N) staged in LDS.
+#pragma once
+
+#include "common.hpp"
+
+namespace hamlet {
+
+// exp(SIGN 2 pi i j / 16) for j in [0, 8): cos and sin of multiples of pi/8.
+template <typename T> __device__ __forceinline__ T cos16(int j) {
+  // j in [0, 8)
+  constexpr double c[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                           0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613};
+  return static_cast<T>(c[j]);
+}
+template <typename T> __device__ __forceinline__ T sin16(int j) {
+  constexpr double s[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                           1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
+  return static_cast<T>(s[j]);
+}
+
+// b * exp(SIGN 2 pi i j / 16), j in [0, 8) known after unrolling.
+template <typename T, int SIGN>
+__device__ __forceinline__ cplx_t<T> rot16(cplx_t<T> b, int j) {
+  using C = cplx_t<T>;
+  if (j == 0) return b;
+  if (j == 4) return SIGN > 0 ? cmake<C>(-b.y, b.x) : cmake<C>(b.y, -b.x);
+  const T c = cos16<T>(j);
+  const T s = SIGN > 0 ? sin16<T>(j) : -sin16<T>(j);
+  return cmake<C>(b.x * c - b.y * s, b.x * s + b.y * c);
+}
+
+__host__ __device__ constexpr int bitrev_c(int i, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+__host__ __device__ constexpr int log2_c(int n) { return n <= 1 ? 0 : 1 + log2_c(n / 2); }
+
+// In-register DFT of R = 2, 4, 8 or 16 points, natural order in and out:
+// bit-reversal permutation, then radix-2 butterflies.
+template <typename T, int R, int SIGN>
+__device__ __forceinline__ void dft_reg(cplx_t<T> (&v)[R]) {
+  using C = cplx_t<T>;
+  constexpr int BITS = log2_c(R);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int j = bitrev_c(i, BITS);
+    if (j > i) { C t = v[i]; v[i] = v[j]; v[j] = t; }
+  }
+#pragma unroll
+  for (int half = 1; half < R; half *= 2) {
+#pragma unroll
+    for (int g = 0; g < R; g += 2 * half) {
+#pragma unroll
+      for (int k = 0; k < half; ++k) {
+        const C a = v[g + k];
+        const C b = rot16<T, SIGN>(v[g + k + half], k * (16 / (2 * half)));
+        v[g + k] = cadd(a, b);
+        v[g + k + half] = csub(a, b);
+      }
+    }
+  }
+}
+
+// One Stockham stage on a batch held in LDS.  Element n of transform b is at
+// buf[n * SN + b * SB].  NFAST selects the thread mapping: butterflies of a
+// transform on consecutive threads (for SN = 1 layouts) or transforms on
+// consecutive threads (for SB = 1 layouts), so LDS accesses stay unit-stride.
+template <typename T, int N, int R, int L, int B, int SN, int SB, bool NFAST, int NT, int SIGN>
+__device__ __forceinline__ void lds_stage(cplx_t<T>* buf, const cplx_t<T>* tw) {
+  using C = cplx_t<T>;
+  constexpr int NB = N / R;
+  constexpr int TOT = NB * B;
+  constexpr int PER = (TOT + NT - 1) / NT;
+  constexpr int TSTEP = N / (L * R);
+  C v[PER][R];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int idx = tid + p * NT;
+    if (TOT % NT == 0 || idx < TOT) {
+      const int b = NFAST ? idx / NB : idx % B;
+      const int j = NFAST ? idx % NB : idx / B;
+      const int k = j % L;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        C x = buf[(j + r * NB) * SN + b * SB];
+        if (L > 1 && r > 0) {
+          C w = tw[r * k * TSTEP];
+          if (SIGN > 0) w.y = -w.y;
+          x = cmul(x, w);
+        }
+        v[p][r] = x;
+      }
+      dft_reg<T, R, SIGN>(v[p]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int idx = tid + p * NT;
+    if (TOT % NT == 0 || idx < TOT) {
+      const int b = NFAST ? idx / NB : idx % B;
+      const int j = NFAST ? idx % NB : idx / B;
+      const int k = j % L;
+      const int base = (j / L) * L * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(base + r * L) * SN + b * SB] = v[p][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Radix plan per length; the whole transform of a batch in LDS.
+// Callers must have synchronised the LDS contents before the call; on
+// return the result is in place and synchronised.
+template <typename T, int N, int B, int SN, int SB, bool NFAST, int NT, int SIGN>
+__device__ __forceinline__ void lds_fft(cplx_t<T>* buf, const cplx_t<T>* tw) {
+  static_assert(N >= 8 && N <= 1024 && (N & (N - 1)) == 0, "FFT length must be 8..1024, power of two");
+  if constexpr (N == 8) {
+    lds_stage<T, N, 8, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+  } else if constexpr (N == 16) {
+    lds_stage<T, N, 4, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 4, 4, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+  } else if constexpr (N == 32) {
+    lds_stage<T, N, 8, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 4, 8, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+  } else if constexpr (N == 64) {
+    lds_stage<T, N, 8, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 8, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+  } else if constexpr (N == 128) {
+    lds_stage<T, N, 16, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 16, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+  } else if constexpr (N == 256) {
+    lds_stage<T, N, 16, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 16, 16, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+  } else if constexpr (N == 512) {
+    lds_stage<T, N, 8, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 8, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 64, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+  } else {
+    lds_stage<T, N, 16, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 16, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 128, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+  }
+}
+
+// Stage the N-entry twiddle table into LDS (caller synchronises).
+template <typename T, int N, int NT>
+__device__ __forceinline__ void load_twiddles(cplx_t<T>* tw_lds, const cplx_t<T>* __restrict__ tw) {
+  for (int i = threadIdx.x; i < N; i += NT) tw_lds[i] = tw[i];
+}
+
+}  // namespace hamlet

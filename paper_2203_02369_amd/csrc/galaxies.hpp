@@ -1,0 +1,239 @@
+// Per-galaxy kernels: CIC binning and the likelihood of Section 2.
+#pragma once
+
+#include "common.hpp"
+#include "passes.hpp"
+
+namespace hamlet {
+
+constexpr int kGalThreads = 256;
+
+// Catalogue and distance-prior data on the device (by galaxy id).
+struct Catalogue {
+  int n;
+  const double* rhat;      // 3 n, (x, y, z) per galaxy
+  const double* mu;        // observed distance modulus
+  const double* sigma_mu;
+  const double* cz;        // observed redshift times c, km/s
+  const double* sigma_cz;  // km/s
+  const double* hist;      // distance-prior density per bin (eq:D)
+  int n_hist;
+  double hist_w;           // bin width, Mpc/h
+};
+
+struct Cosmo {
+  double om, h;            // Omega_0, little h (for mu)
+  double box, spacing;     // L, L / N
+  double dmax;             // c / (3 Omega_0 H0): domain of zbar(d)
+};
+
+// A distance in the domain of the posterior: zbar(d) real and d > 0.
+__device__ __forceinline__ bool dist_ok(double d, const Cosmo& cm) { return d > 0.0 && d < cm.dmax; }
+
+// ---------------------------------------------------------------------------
+// Binning.  Positions x = o + d rhat with o = (L/2)(1,1,1) in FP64 without
+// contraction, so the lower CIC node floor(x / Delta) is bit-identical to a
+// plain FP64 evaluation.  Invalid distances are replaced by 1 Mpc/h for the
+// geometry (their Psi is +inf anyway), which keeps every index in range.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kGalThreads)
+k_bin_count(const double* __restrict__ dist, Catalogue cat, Cosmo cm, int n_grid,
+            int* __restrict__ count, int* __restrict__ key, int* __restrict__ cell_z, double* __restrict__ frac) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cat.n) return;
+  double d = dist[i];
+  if (!dist_ok(d, cm)) d = 1.0;
+  const double half = 0.5 * cm.box;
+  int cell[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double prod = d * cat.rhat[3 * i + a];
+    const double xa = half + prod;
+    const double s = xa / cm.spacing;
+    const double fl = floor(s);
+    frac[3 * i + a] = s - fl;
+    long long c = (long long)fl % n_grid;
+    if (c < 0) c += n_grid;
+    cell[a] = (int)c;
+  }
+  const int k = cell[0] * n_grid + cell[1];
+  key[i] = k;
+  cell_z[i] = cell[2];
+  atomicAdd(&count[k], 1);
+}
+
+// Exclusive scan of the N^2 bucket counts in one block; clears the counts
+// for the next evaluation and primes the placement cursors.
+__global__ void __launch_bounds__(1024)
+k_bin_scan(int* __restrict__ count, int* __restrict__ off, int* __restrict__ cursor, int nkeys) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int per = (nkeys + 1023) / 1024;
+  const int b0 = t * per, b1 = min(b0 + per, nkeys);
+  int s = 0;
+  for (int k = b0; k < b1; ++k) s += count[k];
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int k = b0; k < b1; ++k) {
+    const int c = count[k];
+    off[k] = run;
+    cursor[k] = run;
+    count[k] = 0;
+    run += c;
+  }
+  if (t == 1023) off[nkeys] = part[1023];
+}
+
+__global__ void __launch_bounds__(kGalThreads)
+k_bin_place(const int* __restrict__ key, int* __restrict__ cursor, int* __restrict__ slot_gid, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int s = atomicAdd(&cursor[key[i]], 1);
+  slot_gid[s] = i;
+}
+
+// Per bucket: order members by galaxy id (placement order is racy), then
+// write the sorted per-galaxy records used by the z passes.
+template <typename T>
+__global__ void __launch_bounds__(kGalThreads)
+k_bin_sort(const int* __restrict__ off, int* __restrict__ slot_gid, const int* __restrict__ cell_z,
+           const double* __restrict__ frac, Catalogue cat, int nkeys,
+           T* rx, T* ry, T* rz, T* tx, T* ty, T* tz, int* iz, int* gid) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nkeys) return;
+  const int s0 = off[k], s1 = off[k + 1];
+  for (int a = s0 + 1; a < s1; ++a) {
+    const int v = slot_gid[a];
+    int b = a - 1;
+    while (b >= s0 && slot_gid[b] > v) { slot_gid[b + 1] = slot_gid[b]; --b; }
+    slot_gid[b + 1] = v;
+  }
+  for (int s = s0; s < s1; ++s) {
+    const int i = slot_gid[s];
+    gid[s] = i;
+    rx[s] = (T)cat.rhat[3 * i + 0];
+    ry[s] = (T)cat.rhat[3 * i + 1];
+    rz[s] = (T)cat.rhat[3 * i + 2];
+    tx[s] = (T)frac[3 * i + 0];
+    ty[s] = (T)frac[3 * i + 1];
+    tz[s] = (T)frac[3 * i + 2];
+    iz[s] = cell_z[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Likelihood (eqn:lmu, eq:vrobs, eqn:lvr, eq:kappa, eq:D) per galaxy, in
+// sorted order.  Combines the four column partials of the gather into
+//   u  = sum_col wx wy Pc
+//   u' = sum_col (dwx wy rx + wx dwy ry) Pc + wx wy rz Qc / Delta,
+// then, in FP64,
+//   Psi_i = (mu_i - mu(d))^2 / 2 sigma_mu^2 + r^2 / 2 kappa^2 + ln kappa - ln N(d),
+//   g_i = dPsi/du = -r / kappa^2,  dPsi/dd_i,  dPsi_i/ds,
+// with r = v_obs(d) - u.  Block partials (Psi, dPsi/ds, invalid count) are
+// written for a deterministic final sum.
+// ---------------------------------------------------------------------------
+struct LikeOut {
+  double* g_dist;     // dPsi/dd by galaxy id (n)
+  double* part;       // 3 per block: Psi, dPsi/ds, invalid
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kGalThreads)
+k_like(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const double* __restrict__ frac,
+       const double* __restrict__ dist, const double* __restrict__ snl_q, Catalogue cat, Cosmo cm,
+       T* __restrict__ gsort, LikeOut out) {
+  __shared__ double red[kGalThreads / 64];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double psi = 0.0, dps = 0.0, bad = 0.0;
+  if (s < cat.n) {
+    const int i = gid[s];
+    const double tx = frac[3 * i], ty = frac[3 * i + 1];
+    const double rx = cat.rhat[3 * i], ry = cat.rhat[3 * i + 1], rz = cat.rhat[3 * i + 2];
+    const double inv_d = 1.0 / cm.spacing;
+    double u = 0.0, du = 0.0;
+#pragma unroll
+    for (int corner = 0; corner < 4; ++corner) {
+      const int ox = corner >> 1, oy = corner & 1;
+      const double wx = ox ? tx : 1.0 - tx, wy = oy ? ty : 1.0 - ty;
+      const double dwx = ox ? inv_d : -inv_d, dwy = oy ? inv_d : -inv_d;
+      const cplx_t<T> pq = part[4 * (size_t)s + corner];
+      const double pc = (double)pq.x, qc = (double)pq.y;
+      u += wx * wy * pc;
+      du += (dwx * wy * rx + wx * dwy * ry) * pc + wx * wy * rz * qc * inv_d;
+    }
+    double d = dist[i];
+    const bool ok_d = dist_ok(d, cm);
+    if (!ok_d) d = 1.0;
+    const double sv = snl_q[0];
+    const double a3 = 3.0 * cm.om * kH0 / kC;
+    const double root = sqrt(1.0 - a3 * d);
+    const double zb = (2.0 / (3.0 * cm.om)) * (1.0 - root);
+    const double zbp = (kH0 / kC) / root;
+    const double opz = 1.0 + zb;
+    const double scz = cat.sigma_cz[i];
+    const double snl = kSigmaNlUnit * sv;
+    const double kappa2 = snl * snl + scz * scz / (opz * opz);
+    const double mu_d = 5.0 * log10(d * opz / cm.h) + 25.0;
+    const double mup = (5.0 / log(10.0)) * (opz + d * zbp) / (d * opz);
+    const double smu = cat.sigma_mu[i];
+    const double dmu = cat.mu[i] - mu_d;
+    const double czi = cat.cz[i];
+    const double vobs = kC * (czi / kC - zb) / opz;
+    const double vobsp = -kC * zbp * (1.0 + czi / kC) / (opz * opz);
+    const double r = vobs - u;
+    // distance prior: histogram bin of d
+    const double bf = floor(d / cat.hist_w);
+    const bool ok_h = bf >= 0.0 && bf < (double)cat.n_hist;
+    const double lnN = ok_h ? log(cat.hist[(int)bf]) : 0.0;
+    psi = dmu * dmu / (2.0 * smu * smu) + r * r / (2.0 * kappa2) + 0.5 * log(kappa2) - lnN;
+    const double dk2 = 0.5 / kappa2 - 0.5 * r * r / (kappa2 * kappa2);
+    const double dkappa2_dd = -2.0 * scz * scz * zbp / (opz * opz * opz);
+    const double gd = -dmu * mup / (smu * smu) + (r / kappa2) * (vobsp - du) + dk2 * dkappa2_dd;
+    dps = dk2 * 2.0 * kSigmaNlUnit * kSigmaNlUnit * sv;
+    out.g_dist[i] = gd;
+    gsort[s] = (T)(-r / kappa2);
+    bad = (ok_d && ok_h) ? 0.0 : 1.0;
+  }
+  const double a = block_sum(psi, red);
+  const double b = block_sum(dps, red);
+  const double c = block_sum(bad, red);
+  if (threadIdx.x == 0) {
+    out.part[3 * blockIdx.x + 0] = a;
+    out.part[3 * blockIdx.x + 1] = b;
+    out.part[3 * blockIdx.x + 2] = c;
+  }
+}
+
+// Final deterministic sums: Psi = prior + sum of galaxy terms (+inf when a
+// distance left the domain or Psi is not finite); dPsi/ds.
+__global__ void __launch_bounds__(256)
+k_finalize(const double* __restrict__ prior_part, int n_prior, const double* __restrict__ like_part, int n_like,
+           double* __restrict__ psi_out, double* __restrict__ gs_out) {
+  __shared__ double red[4];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < n_prior; i += blockDim.x) a += prior_part[i];
+  for (int i = threadIdx.x; i < n_like; i += blockDim.x) {
+    a += like_part[3 * i];
+    b += like_part[3 * i + 1];
+    c += like_part[3 * i + 2];
+  }
+  a = block_sum(a, red);
+  b = block_sum(b, red);
+  c = block_sum(c, red);
+  if (threadIdx.x == 0) {
+    const bool ok = c == 0.0 && isfinite(a);
+    psi_out[0] = ok ? a : __builtin_inf();
+    if (gs_out) gs_out[0] = b;
+  }
+}
+
+}  // namespace hamlet

@@ -1,0 +1,217 @@
+"""Python binding of libhamlet: plans and the four entry points.
+
+Argument marshalling only.  Device buffers are torch tensors (PyTorch
+provides device memory and streams); every step of the computation runs in
+the library's HIP kernels.  Shapes and dtypes:
+    modes, gradients, momenta   complex128 (N, N, N/2)   [kx][ky][kz < N/2]
+    distances                   float64 (n,)
+    s = sigma_NL / 100 km/s     float64 (1,)
+    Psi                         float64 (1,)
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _capi
+from ._capi import HmcOpts, c_double_p
+
+PRECISIONS = {"fp64": _capi.HAMLET_FP64, "fp32": _capi.HAMLET_FP32_FP64E}
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(c_double_p)
+
+
+def _stream_handle(stream, device):
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A reconstruction problem resident on one GPU (hamlet_plan_create)."""
+
+    def __init__(self, *, n_grid, box, omega_m, h, f_growth, sigma_v, pk_n2, rhat, mu, sigma_mu, cz, sigma_cz,
+                 hist_width=5.0, precision="fp32", sample_distances=True, sample_sigma_nl=True,
+                 stream=None, device=None):
+        lib = _capi.load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.n_grid = int(n_grid)
+        self.precision = precision
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        pk = _f64(pk_n2)
+        rh = _f64(rhat).reshape(-1)
+        arrays = [_f64(mu), _f64(sigma_mu), _f64(cz), _f64(sigma_cz)]
+        n = len(arrays[0])
+        if rh.size != 3 * n or any(len(a) != n for a in arrays):
+            raise ValueError("catalogue arrays must all have length n (rhat: n x 3)")
+        desc = _capi.PlanDesc(n_grid=self.n_grid, precision=PRECISIONS[precision], box=float(box),
+                              omega_m=float(omega_m), h=float(h), f_growth=float(f_growth),
+                              sigma_v=float(sigma_v), pk_n2=_dptr(pk), n_pk=len(pk),
+                              hist_width=float(hist_width), sample_distances=int(bool(sample_distances)),
+                              sample_sigma_nl=int(bool(sample_sigma_nl)))
+        cat = _capi.Catalog(n=n, rhat=_dptr(rh), mu=_dptr(arrays[0]), sigma_mu=_dptr(arrays[1]),
+                            cz=_dptr(arrays[2]), sigma_cz=_dptr(arrays[3]))
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _capi.check(lib.hamlet_plan_create(ctypes.byref(desc), ctypes.byref(cat),
+                                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)))
+        self._handle = handle
+        self.n_gal = n
+        self.mode_shape = (self.n_grid, self.n_grid, self.n_grid // 2)
+
+    @classmethod
+    def from_mock(cls, mock, **kw):
+        args = mock.problem_kwargs()
+        args.update(kw)
+        return cls(**args)
+
+    @property
+    def handle(self):
+        if self._handle is None:
+            raise RuntimeError("plan is closed")
+        return self._handle.value
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            _capi.check(_capi.load().hamlet_plan_destroy(self._handle))
+        self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- buffers ---------------------------------------------------------------
+    def zeros_modes(self):
+        return torch.zeros(self.mode_shape, dtype=torch.complex128, device=self.device)
+
+    def zeros_dist(self):
+        return torch.zeros(max(self.n_gal, 0), dtype=torch.float64, device=self.device)
+
+    def scalar(self, value=0.0):
+        return torch.full((1,), float(value), dtype=torch.float64, device=self.device)
+
+
+def footprint_bytes(n_grid, n_gal, precision="fp32", pk_len=None):
+    """Device bytes a plan of this size would own (hamlet_plan_footprint_bytes)."""
+    lib = _capi.load()
+    npk = 3 * (n_grid // 2) ** 2 + 1 if pk_len is None else pk_len
+    pk = np.ones(npk)
+    desc = _capi.PlanDesc(n_grid=int(n_grid), precision=PRECISIONS[precision], box=500.0, omega_m=0.3, h=0.7,
+                          f_growth=0.5, sigma_v=300.0, pk_n2=_dptr(pk), n_pk=npk, hist_width=5.0,
+                          sample_distances=1, sample_sigma_nl=1)
+    out = ctypes.c_size_t()
+    _capi.check(lib.hamlet_plan_footprint_bytes(ctypes.byref(desc), int(n_gal), ctypes.byref(out)))
+    return out.value
+
+
+# -- checks and pointer arrays -------------------------------------------------
+
+def _check(t, plan, kind, name):
+    if t is None:
+        return 0
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if kind == "modes":
+        if t.dtype != torch.complex128 or tuple(t.shape) != plan.mode_shape:
+            raise ValueError("%s must be complex128 %s" % (name, plan.mode_shape))
+    elif kind == "dist":
+        if t.dtype != torch.float64 or t.numel() != plan.n_gal:
+            raise ValueError("%s must be float64 (%d,)" % (name, plan.n_gal))
+    elif kind == "scalar":
+        if t.dtype != torch.float64 or t.numel() < 1:
+            raise ValueError("%s must be float64 (1,)" % name)
+    elif kind == "iter_f64":
+        if t.dtype != torch.float64:
+            raise ValueError("%s must be float64" % name)
+    elif kind == "iter_i32":
+        if t.dtype != torch.int32:
+            raise ValueError("%s must be int32" % name)
+    return t.data_ptr()
+
+
+def _vp(addrs):
+    return (ctypes.c_void_p * len(addrs))(*[a or None for a in addrs])
+
+
+def _dpp(addrs):
+    arr = (c_double_p * len(addrs))()
+    for i, a in enumerate(addrs):
+        arr[i] = ctypes.cast(ctypes.c_void_p(a), c_double_p) if a else c_double_p()
+    return arr
+
+
+def _ipp(addrs):
+    arr = (_capi.c_int32_p * len(addrs))()
+    for i, a in enumerate(addrs):
+        arr[i] = ctypes.cast(ctypes.c_void_p(a), _capi.c_int32_p) if a else _capi.c_int32_p()
+    return arr
+
+
+def _plans(plans):
+    plans = list(plans)
+    return plans, _vp([p.handle for p in plans])
+
+
+def logpost_grad(plans, q_modes, q_dist, q_snl, g_modes, g_dist, g_snl, psi):
+    """Psi and its gradient for a batch of plans (hamlet_logpost_grad)."""
+    plans, hp = _plans(plans)
+    args = []
+    for kind, name, ts in (("modes", "q_modes", q_modes), ("dist", "q_dist", q_dist), ("scalar", "q_snl", q_snl),
+                           ("modes", "g_modes", g_modes), ("dist", "g_dist", g_dist), ("scalar", "g_snl", g_snl),
+                           ("scalar", "psi", psi)):
+        args.append([_check(t, p, kind, name) for t, p in zip(ts, plans)])
+    lib = _capi.load()
+    _capi.check(lib.hamlet_logpost_grad(hp, len(plans), _vp(args[0]), _dpp(args[1]), _dpp(args[2]),
+                                        _vp(args[3]), _dpp(args[4]), _dpp(args[5]), _dpp(args[6])))
+
+
+def leapfrog(plans, eps, n_steps, q_modes, q_dist, q_snl, p_modes, p_dist, p_snl, psi):
+    """n_steps kick-drift-kick steps in place (hamlet_leapfrog)."""
+    plans, hp = _plans(plans)
+    args = []
+    for kind, name, ts in (("modes", "q_modes", q_modes), ("dist", "q_dist", q_dist), ("scalar", "q_snl", q_snl),
+                           ("modes", "p_modes", p_modes), ("dist", "p_dist", p_dist), ("scalar", "p_snl", p_snl),
+                           ("scalar", "psi", psi)):
+        args.append([_check(t, p, kind, name) for t, p in zip(ts, plans)])
+    e = (ctypes.c_double * len(plans))(*[float(x) for x in eps])
+    s = (ctypes.c_int32 * len(plans))(*[int(x) for x in n_steps])
+    lib = _capi.load()
+    _capi.check(lib.hamlet_leapfrog(hp, len(plans), e, s, _vp(args[0]), _dpp(args[1]), _dpp(args[2]),
+                                    _vp(args[3]), _dpp(args[4]), _dpp(args[5]), _dpp(args[6])))
+
+
+def hmc_run(plans, q_modes, q_dist, q_snl, *, n_iter, n_leapfrog, eps0, seed, warmup=0, jitter=False,
+            target_accept=0.65, mode_sum=None, dh=None, accepted=None, want_eps=True):
+    """Runs the HMC chains (hamlet_hmc_run); returns the post-warm-up steps."""
+    plans, hp = _plans(plans)
+    nplan = len(plans)
+    qm = [_check(t, p, "modes", "q_modes") for t, p in zip(q_modes, plans)]
+    qd = [_check(t, p, "dist", "q_dist") for t, p in zip(q_dist, plans)]
+    qs = [_check(t, p, "scalar", "q_snl") for t, p in zip(q_snl, plans)]
+    ms = [_check(t, p, "modes", "mode_sum") for t, p in zip(mode_sum, plans)] if mode_sum else None
+    dd = [_check(t, p, "iter_f64", "dh") for t, p in zip(dh, plans)] if dh else None
+    aa = [_check(t, p, "iter_i32", "accepted") for t, p in zip(accepted, plans)] if accepted else None
+    for lst, what in ((dh, "dh"), (accepted, "accepted")):
+        if lst:
+            for t in lst:
+                if t.numel() < n_iter:
+                    raise ValueError("%s needs n_iter entries" % what)
+    opts = HmcOpts(n_iter=int(n_iter), n_leapfrog=int(n_leapfrog), warmup=int(warmup), jitter_eps=int(bool(jitter)),
+                   eps0=float(eps0), target_accept=float(target_accept), seed=int(seed) & 0xFFFFFFFFFFFFFFFF)
+    eps_out = (ctypes.c_double * nplan)() if want_eps else None
+    lib = _capi.load()
+    _capi.check(lib.hamlet_hmc_run(hp, nplan, ctypes.byref(opts), _vp(qm), _dpp(qd), _dpp(qs),
+                                   _vp(ms) if ms else None, _dpp(dd) if dd else None,
+                                   _ipp(aa) if aa else None,
+                                   ctypes.cast(eps_out, c_double_p) if want_eps else None))
+    return list(eps_out) if want_eps else None

@@ -1,0 +1,64 @@
+"""The C ABI library loads, exports every declared entry point, and validates
+arguments on the host (no GPU needed for any of this)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "hamlet.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hamlet_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for required in ("hamlet_plan_create", "hamlet_logpost_grad", "hamlet_leapfrog", "hamlet_hmc_run",
+                     "hamlet_plan_destroy", "hamlet_plan_footprint_bytes", "hamlet_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2203_02369_amd import _capi
+    lib = _capi.load()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert set(_declared_functions()) == set(_capi.SIGNATURES)
+
+
+def test_footprint_query_is_host_only():
+    from paper_2203_02369_amd import hamlet
+    small = hamlet.footprint_bytes(32, 1000, "fp64")
+    big = hamlet.footprint_bytes(256, 30000, "fp32")
+    assert 0 < small < big
+    # five FP32 spectral arrays and four FP64 mode arrays dominate at 256^3
+    nm = 256 * 256 * 128
+    assert big > nm * (5 * 8 + 4 * 16)
+    assert hamlet.footprint_bytes(256, 30000, "fp64") > big
+
+
+def test_invalid_arguments_are_rejected_on_the_host():
+    from paper_2203_02369_amd import _capi, hamlet
+    lib = _capi.load()
+    out = ctypes.c_size_t()
+    pk = np.ones(3 * 16 * 16 + 1)
+    desc = _capi.PlanDesc(n_grid=24, precision=0, box=100.0, omega_m=0.3, h=0.7, f_growth=0.5, sigma_v=300.0,
+                          pk_n2=pk.ctypes.data_as(_capi.c_double_p), n_pk=len(pk), hist_width=5.0,
+                          sample_distances=1, sample_sigma_nl=1)
+    assert lib.hamlet_plan_footprint_bytes(ctypes.byref(desc), 10, ctypes.byref(out)) == -4
+    assert b"n_grid" in lib.hamlet_last_error()
+    desc.n_grid = 32
+    assert lib.hamlet_plan_footprint_bytes(ctypes.byref(desc), 10, ctypes.byref(out)) == 0
+    desc.n_pk = 5
+    assert lib.hamlet_plan_footprint_bytes(ctypes.byref(desc), 10, ctypes.byref(out)) == -1
+    desc.n_pk = len(pk)
+    desc.sigma_v = -1.0
+    assert lib.hamlet_plan_footprint_bytes(ctypes.byref(desc), 10, ctypes.byref(out)) == -1
+    assert lib.hamlet_plan_create(None, None, None, ctypes.byref(ctypes.c_void_p())) == -1
+    with pytest.raises(_capi.HamletError):
+        _capi.check(-1)
