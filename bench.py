@@ -1,0 +1,195 @@
+"""Throughput of the HAMLET hot path on one MI355X.
+
+A step is one HMC iteration of the paper-scale problem (256^3 grid, box
+500 Mpc/h, 30 000 points with number density ~ 1/r to 250 Mpc/h and a zone
+of avoidance |b| < 10 deg, lognormal distance errors 15-25 %): momentum
+refresh, 20 leapfrog steps (each one log-posterior-and-gradient evaluation:
+binning, three inverse FFTs with the CIC gather, likelihood, CIC scatter,
+three forward FFTs, adjoint multiply), kinetic energies and the
+Metropolis-Hastings test, all on the device.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  value = gradient evaluations per second of the
+FP32-field / FP64-Hamiltonian path; the plain FP64 path is timed beside it
+with the same step size and seed ("fp64_path"), and the FP64 oracle is
+timed on the host cores ("cpu_baseline").
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--leapfrog", type=int, default=20)
+    ap.add_argument("--fp64-steps", type=int, default=20)
+    ap.add_argument("--n-grid", type=int, default=256)
+    ap.add_argument("--n-gal", type=int, default=30000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(independent chains shard across GPUs with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2203_02369_amd import hamlet, mocks
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    mock = mocks.paper_scale_256(n_gal=args.n_gal, n_grid=args.n_grid)
+    log("mock %d^3, %d points in %.1fs" % (mock.n_grid, mock.n_gal, time.time() - t0))
+    n = mock.n_grid
+    # start at a posterior-typical point: the mock field, Hermitian on kz = 0
+    dhat0 = mock.dhat_true[:, :, : n // 2]
+    d0 = mock.d_true.copy()
+    s0 = 1.5
+    L = args.leapfrog
+    seed = mocks.config_seed(3) + 3
+
+    def state(plan):
+        q = torch.from_numpy(np.ascontiguousarray(dhat0)).to(dev)
+        qd = torch.from_numpy(d0.copy()).to(dev)
+        return q, qd, plan.scalar(s0)
+
+    # ---- warm-up: dual averaging of the step on the FP32 path (untimed) -------
+    plan = hamlet.Plan.from_mock(mock, precision="fp32", device=dev)
+    q, qd, qs = state(plan)
+    eps = 0.002
+    if args.warmup > 0:
+        eps = hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=args.warmup, n_leapfrog=L, eps0=eps, seed=seed,
+                             warmup=args.warmup, jitter=True)[0]
+    log("warm-up: %d iterations, eps = %.4g" % (args.warmup, eps))
+    start = (q.clone(), qd.clone(), qs.clone())     # both paths start here
+
+    # ---- timed: FP32 fields + FP64 Hamiltonian --------------------------------
+    acc = torch.zeros(args.steps, dtype=torch.int32, device=dev)
+    dh32 = torch.zeros(args.steps, dtype=torch.float64, device=dev)
+    q, qd, qs = (t.clone() for t in start)
+    prof = hamlet.KernelTimer(plan, hamlet.PROFILE_KERNELS["fwd_x"])
+    torch.cuda.synchronize()
+    prof.start()
+    t1 = time.perf_counter()
+    hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=args.steps, n_leapfrog=L, eps0=eps, seed=seed + 1,
+                   jitter=True, accepted=[acc], dh=[dh32], want_eps=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    kern_ms, kern_launches = prof.stop()
+    dt = t2 - t1
+    grads = args.steps * L + 1
+    value = grads / dt
+    acc32 = acc.cpu().numpy()
+    log("fp32: %d iterations x %d steps in %.3fs: %.1f grad/s, acceptance %.2f"
+        % (args.steps, L, dt, value, acc32.mean()))
+    plan.close()
+    del q, qd, qs
+
+    # ---- plain FP64 path, same start, step and seed ------------------------------
+    fp64 = None
+    if not args.no_fp64 and args.fp64_steps > 0:
+        plan = hamlet.Plan.from_mock(mock, precision="fp64", device=dev)
+        acc64 = torch.zeros(args.fp64_steps, dtype=torch.int32, device=dev)
+        q, qd, qs = (t.clone() for t in start)
+        hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=1, n_leapfrog=2, eps0=eps, seed=seed, want_eps=False)
+        q, qd, qs = (t.clone() for t in start)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=args.fp64_steps, n_leapfrog=L, eps0=eps, seed=seed + 1,
+                       jitter=True, accepted=[acc64], want_eps=False)
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t3
+        v64 = (args.fp64_steps * L + 1) / dt64
+        a64 = acc64.cpu().numpy()
+        m = min(len(a64), len(acc32))
+        fp64 = {"value": round(v64, 2), "unit": "grad evals/s", "ms_per_step": round(1e3 * dt64 / args.fp64_steps, 3),
+                "steps": args.fp64_steps, "acceptance": float(a64.mean()),
+                "same_decisions_as_fp32": "%d of %d" % (int((a64[:m] == acc32[:m]).sum()), m),
+                "speedup_fp32_vs_fp64": round(value / v64, 3)}
+        log("fp64: %.1f grad/s, acceptance %.2f" % (v64, a64.mean()))
+        plan.close()
+        del q, qd, qs
+
+    # ---- roofline of the dominant kernel ------------------------------------
+    # k_x_pass: the x pass of every evaluation, fused with the leapfrog update
+    # and the next inverse pass 1.  Algorithmic bytes in units of one complex64
+    # spectral array c (8 N^2 N/2 bytes; complex128 arrays count 2c):
+    #   plain gradient (1 per run):        S1, S2, q in; G out          =  6c
+    #   first step of a trajectory:        G, p, q in; p, q, A, B out   = 12c
+    #   middle steps (L - 1 per traj.):    S1, S2, p, q in; p, q, A, B  = 12c
+    #   last step:                         S1, S2, p, q in; p, G out    = 10c
+    nm = n * n * (n // 2)
+    c32 = 8 * nm
+    x_bytes = c32 * (6 + args.steps * (12 + 12 * (L - 1) + 10))
+    x_launches = 1 + args.steps * (L + 1)
+    assert kern_launches == x_launches, (kern_launches, x_launches)
+    avg_ms = kern_ms / kern_launches
+    per_launch = x_bytes / x_launches
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_x_pass (x FFT + gradient + leapfrog update + next inverse x FFT)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(per_launch), "avg_launch_ms": round(avg_ms, 4), "launches": kern_launches}
+
+    # ---- CPU baseline: the oracle on the host cores --------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import hmc, model
+        prob = model.Problem(**mock.problem_kwargs())
+        dh = hmc.symmetrise(n, mock.dhat_true)
+        tc = time.perf_counter()
+        model.logpost_grad(prob, dh, d0, s0)
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": round(1.0 / tcpu, 5), "unit": "grad evals/s", "cores": 1, "kind": "oracle",
+               "sample": "one oracle log-posterior-and-gradient evaluation at %d^3 with %d points "
+                         "(numpy FP64, own radix-2 FFT, single thread): %.1f s" % (n, mock.n_gal, tcpu)}
+        log("cpu oracle: %.1f s per gradient" % tcpu)
+
+    out = {
+        "metric": "grad evals/s (fwd+adjoint) at 256^3, N=3e4 vs plain FP64",
+        "value": round(value, 2),
+        "unit": "grad evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 fields, f64 Hamiltonian",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale single chain: %d^3 grid, box 500 Mpc/h, %d points, "
+                               "HMC iteration of %d leapfrog steps" % (n, mock.n_gal, L),
+                   "n_grid": n, "n_gal": mock.n_gal, "leapfrog_steps": L, "eps": round(eps, 6),
+                   "acceptance": float(acc32.mean()), "grad_evals_timed": grads},
+        "fp64_path": fp64,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

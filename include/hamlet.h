@@ -158,6 +158,29 @@ hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_plans, const h
                              void* const* mode_sum, double* const* dh, int32_t* const* accepted,
                              double* eps_out);
 
+/* Measurement aid.  Kernel kinds that can be timed with HIP events: */
+typedef enum {
+  HAMLET_K_BIN = 0,         /* binning of the points into CIC columns (4 kernels, timed as one) */
+  HAMLET_K_INV_X = 1,       /* inverse pass 1: multiplier, prior energy, FFT along x */
+  HAMLET_K_INV_Y = 2,       /* inverse pass 2: FFT along y */
+  HAMLET_K_INV_Z = 3,       /* inverse pass 3: complex-to-real FFT along z + CIC gather */
+  HAMLET_K_LIKE = 4,        /* per-point likelihood and its gradient */
+  HAMLET_K_FWD_Z = 5,       /* forward pass 1: CIC scatter + real-to-complex FFT along z */
+  HAMLET_K_FWD_Y = 6,       /* forward pass 2: FFT along y */
+  HAMLET_K_FWD_X = 7,       /* forward pass 3: FFT along x, adjoint multiply, prior gradient; inside a
+                               leapfrog trajectory also the mode kick and drift and inverse pass 1 of
+                               the next evaluation (then HAMLET_K_INV_X is not launched) */
+  HAMLET_K_COUNT = 8
+} hamlet_kernel;
+
+/* While armed, every launch of that kernel kind on the plan's stream is
+ * bracketed by a pair of HIP events (host objects created on demand).
+ * hamlet_profile_stop synchronises the plan's stream, returns the summed
+ * event-measured duration (ms) and the number of launches since
+ * hamlet_profile_start, and disarms. */
+hamlet_status hamlet_profile_start(hamlet_plan* plan, int32_t kernel);
+hamlet_status hamlet_profile_stop(hamlet_plan* plan, double* total_ms, int64_t* launches);
+
 /* Message of the last non-OK status on this thread ("" if none). */
 const char* hamlet_last_error(void);
 

@@ -75,6 +75,8 @@ SIGNATURES = {
                                        c_double_pp, c_void_pp, c_double_pp, c_double_pp, c_double_pp]),
     "hamlet_hmc_run": (ctypes.c_int, [c_void_pp, ctypes.c_int32, ctypes.POINTER(HmcOpts), c_void_pp, c_double_pp,
                                       c_double_pp, c_void_pp, c_double_pp, ctypes.POINTER(c_int32_p), c_double_p]),
+    "hamlet_profile_start": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "hamlet_profile_stop": (ctypes.c_int, [ctypes.c_void_p, c_double_p, ctypes.POINTER(ctypes.c_int64)]),
     "hamlet_last_error": (ctypes.c_char_p, []),
 }
 

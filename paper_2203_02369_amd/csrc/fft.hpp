@@ -77,17 +77,43 @@ __device__ __forceinline__ void dft_reg(cplx_t<T> (&v)[R]) {
   }
 }
 
-// One Stockham stage on a batch held in LDS.  Element n of transform b is at
-// buf[n * SN + b * SB].  NFAST selects the thread mapping: butterflies of a
-// transform on consecutive threads (for SN = 1 layouts) or transforms on
-// consecutive threads (for SB = 1 layouts), so LDS accesses stay unit-stride.
-template <typename T, int N, int R, int L, int B, int SN, int SB, bool NFAST, int NT, int SIGN>
+// LDS layouts of a batch of transforms.  idx(n, b) is the slot of element n
+// of transform b.  Both pad so that the store phase of a radix-16 stage
+// (writes R*L apart) spreads over the 64 banks as evenly as 64-bit or
+// 128-bit accesses allow.
+//
+// RowLayout: W transforms side by side (element n of all transforms is one
+// row of W); used for passes along a strided axis, transforms on consecutive
+// threads.  8-byte elements get one pad slot per row, 16-byte elements two
+// pad slots every 16 rows.
+template <typename C, int W> struct RowLayout {
+  static constexpr int P1 = sizeof(C) == 8 ? 1 : 0;
+  static constexpr int P16 = sizeof(C) == 8 ? 0 : 2;
+  static constexpr bool kNFast = false;
+  __device__ __forceinline__ static int idx(int n, int b) { return n * (W + P1) + (n >> 4) * P16 + b; }
+  static constexpr int size(int n) { return n * (W + P1) + (n >> 4) * P16; }
+};
+
+// PencilLayout: each transform contiguous with one pad slot per 16 elements;
+// used for passes along the contiguous axis, butterflies on consecutive threads.
+template <int N> struct PencilLayout {
+  static constexpr int SB = N + N / 16;
+  static constexpr bool kNFast = true;
+  __device__ __forceinline__ static int idx(int n, int b) { return b * SB + n + (n >> 4); }
+  static constexpr int size(int f) { return f * SB; }
+};
+
+// One Stockham stage on a batch of B transforms held in LDS (layout L).
+// Thread mapping follows the layout: butterflies of a transform on
+// consecutive threads (pencils) or transforms on consecutive threads (rows).
+template <typename T, int N, int R, int LEN, int B, typename LAY, int NT, int SIGN>
 __device__ __forceinline__ void lds_stage(cplx_t<T>* buf, const cplx_t<T>* tw) {
   using C = cplx_t<T>;
   constexpr int NB = N / R;
   constexpr int TOT = NB * B;
   constexpr int PER = (TOT + NT - 1) / NT;
-  constexpr int TSTEP = N / (L * R);
+  constexpr int TSTEP = N / (LEN * R);
+  constexpr bool NFAST = LAY::kNFast;
   C v[PER][R];
   const int tid = threadIdx.x;
 #pragma unroll
@@ -96,11 +122,11 @@ __device__ __forceinline__ void lds_stage(cplx_t<T>* buf, const cplx_t<T>* tw) {
     if (TOT % NT == 0 || idx < TOT) {
       const int b = NFAST ? idx / NB : idx % B;
       const int j = NFAST ? idx % NB : idx / B;
-      const int k = j % L;
+      const int k = j % LEN;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        C x = buf[(j + r * NB) * SN + b * SB];
-        if (L > 1 && r > 0) {
+        C x = buf[LAY::idx(j + r * NB, b)];
+        if (LEN > 1 && r > 0) {
           C w = tw[r * k * TSTEP];
           if (SIGN > 0) w.y = -w.y;
           x = cmul(x, w);
@@ -117,10 +143,10 @@ __device__ __forceinline__ void lds_stage(cplx_t<T>* buf, const cplx_t<T>* tw) {
     if (TOT % NT == 0 || idx < TOT) {
       const int b = NFAST ? idx / NB : idx % B;
       const int j = NFAST ? idx % NB : idx / B;
-      const int k = j % L;
-      const int base = (j / L) * L * R + k;
+      const int k = j % LEN;
+      const int base = (j / LEN) * LEN * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(base + r * L) * SN + b * SB] = v[p][r];
+      for (int r = 0; r < R; ++r) buf[LAY::idx(base + r * LEN, b)] = v[p][r];
     }
   }
   __syncthreads();
@@ -129,34 +155,34 @@ __device__ __forceinline__ void lds_stage(cplx_t<T>* buf, const cplx_t<T>* tw) {
 // Radix plan per length; the whole transform of a batch in LDS.
 // Callers must have synchronised the LDS contents before the call; on
 // return the result is in place and synchronised.
-template <typename T, int N, int B, int SN, int SB, bool NFAST, int NT, int SIGN>
+template <typename T, int N, int B, typename LAY, int NT, int SIGN>
 __device__ __forceinline__ void lds_fft(cplx_t<T>* buf, const cplx_t<T>* tw) {
   static_assert(N >= 8 && N <= 1024 && (N & (N - 1)) == 0, "FFT length must be 8..1024, power of two");
   if constexpr (N == 8) {
-    lds_stage<T, N, 8, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN>(buf, tw);
   } else if constexpr (N == 16) {
-    lds_stage<T, N, 4, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 4, 4, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 4, 1, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 4, 4, B, LAY, NT, SIGN>(buf, tw);
   } else if constexpr (N == 32) {
-    lds_stage<T, N, 8, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 4, 8, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 4, 8, B, LAY, NT, SIGN>(buf, tw);
   } else if constexpr (N == 64) {
-    lds_stage<T, N, 8, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 8, 8, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 8, B, LAY, NT, SIGN>(buf, tw);
   } else if constexpr (N == 128) {
-    lds_stage<T, N, 16, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 8, 16, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 16, 1, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 16, B, LAY, NT, SIGN>(buf, tw);
   } else if constexpr (N == 256) {
-    lds_stage<T, N, 16, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 16, 16, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 16, 1, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 16, 16, B, LAY, NT, SIGN>(buf, tw);
   } else if constexpr (N == 512) {
-    lds_stage<T, N, 8, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 8, 8, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 8, 64, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 8, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 64, B, LAY, NT, SIGN>(buf, tw);
   } else {
-    lds_stage<T, N, 16, 1, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 8, 16, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 8, 128, B, SN, SB, NFAST, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 16, 1, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 16, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 128, B, LAY, NT, SIGN>(buf, tw);
   }
 }
 

@@ -64,33 +64,64 @@ k_bin_count(const double* __restrict__ dist, Catalogue cat, Cosmo cm, int n_grid
   atomicAdd(&count[k], 1);
 }
 
-// Exclusive scan of the N^2 bucket counts in one block; clears the counts
-// for the next evaluation and primes the placement cursors.
-__global__ void __launch_bounds__(1024)
-k_bin_scan(int* __restrict__ count, int* __restrict__ off, int* __restrict__ cursor, int nkeys) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x;
-  const int per = (nkeys + 1023) / 1024;
-  const int b0 = t * per, b1 = min(b0 + per, nkeys);
-  int s = 0;
-  for (int k = b0; k < b1; ++k) s += count[k];
-  part[t] = s;
+// Exclusive scan of the N^2 bucket counts, in two coalesced passes over
+// tiles of 1024 counts: (1) scan within each tile, tile totals to bsum;
+// (2) add the sum of the preceding tiles, prime the placement cursors and
+// clear the counts for the next evaluation.
+constexpr int kScanTile = 1024;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* wsum, int* total) {
+  // inclusive scan within the wave
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wid] = x;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    int v = t >= o ? part[t - o] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      const int t = wsum[w];
+      wsum[w] = run;
+      run += t;
+    }
+    *total = run;
   }
-  int run = part[t] - s;
-  for (int k = b0; k < b1; ++k) {
-    const int c = count[k];
-    off[k] = run;
-    cursor[k] = run;
+  __syncthreads();
+  return x - v + wsum[wid];
+}
+
+__global__ void __launch_bounds__(kScanTile)
+k_bin_scan_tiles(const int* __restrict__ count, int* __restrict__ off, int* __restrict__ bsum, int nkeys) {
+  __shared__ int wsum[kScanTile / 64];
+  __shared__ int total;
+  const int k = blockIdx.x * kScanTile + threadIdx.x;
+  const int c = k < nkeys ? count[k] : 0;
+  const int ex = block_exclusive_scan(c, wsum, &total);
+  if (k < nkeys) off[k] = ex;
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanTile)
+k_bin_scan_add(int* __restrict__ count, int* __restrict__ off, int* __restrict__ cursor,
+               const int* __restrict__ bsum, int nkeys) {
+  __shared__ int base;
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int b = 0; b < (int)blockIdx.x; ++b) s += bsum[b];
+    base = s;
+    if (blockIdx.x == gridDim.x - 1) off[nkeys] = s + bsum[blockIdx.x];
+  }
+  __syncthreads();
+  const int k = blockIdx.x * kScanTile + threadIdx.x;
+  if (k < nkeys) {
+    const int o = off[k] + base;
+    off[k] = o;
+    cursor[k] = o;
     count[k] = 0;
-    run += c;
   }
-  if (t == 1023) off[nkeys] = part[1023];
 }
 
 __global__ void __launch_bounds__(kGalThreads)
@@ -146,11 +177,21 @@ struct LikeOut {
   double* part;       // 3 per block: Psi, dPsi/ds, invalid
 };
 
+// Optional leapfrog update of a block of coordinates right after their
+// gradient is known: p -= kick * eps * g, then (drift) q += eps * minv * p.
+struct LeapUpdate {
+  double* p = nullptr;       // momenta (nullptr: no update)
+  const double* eps = nullptr;
+  double kick = 0.0;         // 1 for merged half kicks, 0.5 for the last half kick
+  int drift = 0;
+  double minv = 0.0;         // inverse mass
+};
+
 template <typename T>
 __global__ void __launch_bounds__(kGalThreads)
 k_like(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const double* __restrict__ frac,
-       const double* __restrict__ dist, const double* __restrict__ snl_q, Catalogue cat, Cosmo cm,
-       T* __restrict__ gsort, LikeOut out) {
+       double* __restrict__ dist, const double* __restrict__ snl_q, Catalogue cat, Cosmo cm,
+       T* __restrict__ gsort, LikeOut out, LeapUpdate lf) {
   __shared__ double red[kGalThreads / 64];
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double psi = 0.0, dps = 0.0, bad = 0.0;
@@ -201,6 +242,12 @@ k_like(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const do
     dps = dk2 * 2.0 * kSigmaNlUnit * kSigmaNlUnit * sv;
     out.g_dist[i] = gd;
     gsort[s] = (T)(-r / kappa2);
+    if (lf.p) {
+      const double e = lf.eps[0];
+      const double pv = lf.p[i] - lf.kick * e * gd;
+      lf.p[i] = pv;
+      if (lf.drift) dist[i] = dist[i] + e * lf.minv * pv;
+    }
     bad = (ok_d && ok_h) ? 0.0 : 1.0;
   }
   const double a = block_sum(psi, red);
@@ -217,7 +264,7 @@ k_like(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const do
 // distance left the domain or Psi is not finite); dPsi/ds.
 __global__ void __launch_bounds__(256)
 k_finalize(const double* __restrict__ prior_part, int n_prior, const double* __restrict__ like_part, int n_like,
-           double* __restrict__ psi_out, double* __restrict__ gs_out) {
+           double* __restrict__ psi_out, double* __restrict__ gs_out, double* __restrict__ snl_q, LeapUpdate lf) {
   __shared__ double red[4];
   double a = 0.0, b = 0.0, c = 0.0;
   for (int i = threadIdx.x; i < n_prior; i += blockDim.x) a += prior_part[i];
@@ -233,6 +280,12 @@ k_finalize(const double* __restrict__ prior_part, int n_prior, const double* __r
     const bool ok = c == 0.0 && isfinite(a);
     psi_out[0] = ok ? a : __builtin_inf();
     if (gs_out) gs_out[0] = b;
+    if (lf.p) {
+      const double e = lf.eps[0];
+      const double pv = lf.p[0] - lf.kick * e * b;
+      lf.p[0] = pv;
+      if (lf.drift) snl_q[0] = snl_q[0] + e * lf.minv * pv;
+    }
   }
 }
 

@@ -61,8 +61,23 @@ struct Workspace {
 };
 
 struct hamlet_plan;
-typedef hamlet_status (*grad_fn)(hamlet_plan*, const double2*, const double*, const double*, double2*, double*,
-                                 double*, double*);
+
+// What one evaluation does besides Psi and the gradient.  Plain gradient:
+// x_mode = kXGrad, the gradient goes to g.  Inside a leapfrog trajectory the
+// inverse pass 1 was already done by the previous evaluation's x pass, and
+// the leapfrog update of every coordinate is fused in (x_mode kXMid or
+// kXLast; the gradient of a kXLast evaluation goes to g as the cache).
+struct EvalMode {
+  int x_mode = kXGrad;
+  double2* p_modes = nullptr;
+  double* p_dist = nullptr;
+  double* p_snl = nullptr;
+  const double* eps = nullptr;
+};
+
+typedef hamlet_status (*eval_fn)(hamlet_plan*, double2*, double*, double*, double2*, double*, double*, double*,
+                                 const EvalMode&);
+typedef hamlet_status (*first_fn)(hamlet_plan*, double2*, double2*, const double*);
 
 struct hamlet_plan {
   int n = 0, prec = 0, n_gal = 0, sample_d = 1, sample_s = 1, n_hist = 0;
@@ -76,7 +91,7 @@ struct hamlet_plan {
   double *rhat = nullptr, *mu = nullptr, *smu = nullptr, *cz = nullptr, *scz = nullptr;
   // binning
   int *count = nullptr, *off = nullptr, *cursor = nullptr, *key = nullptr, *cellz = nullptr, *slot = nullptr,
-      *iz = nullptr;
+      *iz = nullptr, *bsum = nullptr;
   double* frac = nullptr;
   void *rx = nullptr, *ry = nullptr, *rz = nullptr, *tx = nullptr, *ty = nullptr, *tz = nullptr;
   // spectral intermediates and galaxy partials (precision T)
@@ -88,9 +103,41 @@ struct hamlet_plan {
   double2 *gcache = nullptr, *q0 = nullptr, *g0 = nullptr, *pm = nullptr;
   double *gd = nullptr, *gd0 = nullptr, *qd0 = nullptr, *pd = nullptr, *qs0 = nullptr, *ps = nullptr;
   double* eps_slot = nullptr;
-  grad_fn grad = nullptr;
+  eval_fn eval = nullptr;
+  first_fn first = nullptr;
+  // event timing of one kernel kind (hamlet_profile_start / stop)
+  int prof_kind = -1;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pool;
+  size_t prof_used = 0;
+  bool prof_failed = false;
   size_t modes_count() const { return (size_t)n * n * (n / 2); }
 };
+
+// Bracket one launch of kernel kind `kind` with events when it is armed.
+static void prof_before(hamlet_plan* pl, int kind) {
+  if (pl->prof_kind != kind) return;
+  if (pl->prof_used == pl->prof_pool.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      pl->prof_failed = true;
+      pl->prof_kind = -1;
+      return;
+    }
+    pl->prof_pool.emplace_back(a, b);
+  }
+  if (hipEventRecord(pl->prof_pool[pl->prof_used].first, pl->stream) != hipSuccess) pl->prof_failed = true;
+}
+static void prof_after(hamlet_plan* pl, int kind) {
+  if (pl->prof_kind != kind) return;
+  if (hipEventRecord(pl->prof_pool[pl->prof_used].second, pl->stream) != hipSuccess) pl->prof_failed = true;
+  ++pl->prof_used;
+}
+#define TIMED(pl, kind, ...)   \
+  do {                         \
+    prof_before(pl, kind);     \
+    __VA_ARGS__;               \
+    prof_after(pl, kind);      \
+  } while (0)
 
 template <typename T> static Binned<T> binned_view(hamlet_plan* pl) {
   Binned<T> b;
@@ -123,11 +170,13 @@ static ModeTables tables_view(hamlet_plan* pl) {
 
 static inline unsigned blocks_for(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// One log-posterior-and-gradient evaluation (bin, 3 inverse passes with the
-// gather, likelihood, 3 forward passes with the scatter, final sums).
+// One log-posterior-and-gradient evaluation: bin, inverse passes with the
+// gather, likelihood, final sums (Psi, dPsi/ds), forward passes with the
+// scatter, and the x pass (gradient, or the fused leapfrog update and the
+// next evaluation's inverse pass 1).
 template <typename T, int N>
-static hamlet_status grad_impl(hamlet_plan* pl, const double2* q, const double* qd, const double* qs, double2* g,
-                               double* gd, double* gs, double* psi) {
+static hamlet_status eval_impl(hamlet_plan* pl, double2* q, double* qd, double* qs, double2* g, double* gd,
+                               double* gs, double* psi, const EvalMode& em) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   hipStream_t st = pl->stream;
@@ -137,49 +186,116 @@ static hamlet_status grad_impl(hamlet_plan* pl, const double2* q, const double* 
   const ModeTables tab = tables_view(pl);
   const C* tw = (const C*)pl->tw;
   const Binned<T> bins = binned_view<T>(pl);
+  const bool leap = em.x_mode != kXGrad;
+  LeapUpdate lf_d, lf_s;
+  if (leap) {
+    const double kick = em.x_mode == kXMid ? 1.0 : 0.5;
+    const int drift = em.x_mode == kXMid ? 1 : 0;
+    if (pl->sample_d) {
+      lf_d.p = em.p_dist; lf_d.eps = em.eps; lf_d.kick = kick; lf_d.drift = drift; lf_d.minv = pl->minv_d;
+    }
+    if (pl->sample_s) {
+      lf_s.p = em.p_snl; lf_s.eps = em.eps; lf_s.kick = kick; lf_s.drift = drift; lf_s.minv = 1.0;
+    }
+  }
   if (n > 0) {
+    prof_before(pl, HAMLET_K_BIN);
     k_bin_count<T><<<blocks_for(n, kGalThreads), kGalThreads, 0, st>>>(qd, cat, cm, N, pl->count, pl->key,
                                                                         pl->cellz, pl->frac);
-    k_bin_scan<<<1, 1024, 0, st>>>(pl->count, pl->off, pl->cursor, N * N);
+    constexpr int tiles = (N * N + kScanTile - 1) / kScanTile;
+    k_bin_scan_tiles<<<tiles, kScanTile, 0, st>>>(pl->count, pl->off, pl->bsum, N * N);
+    k_bin_scan_add<<<tiles, kScanTile, 0, st>>>(pl->count, pl->off, pl->cursor, pl->bsum, N * N);
     k_bin_place<<<blocks_for(n, kGalThreads), kGalThreads, 0, st>>>(pl->key, pl->cursor, pl->slot, n);
     k_bin_sort<T><<<blocks_for((size_t)N * N, kGalThreads), kGalThreads, 0, st>>>(
         pl->off, pl->slot, pl->cellz, pl->frac, cat, N * N, (T*)pl->rx, (T*)pl->ry, (T*)pl->rz, (T*)pl->tx,
         (T*)pl->ty, (T*)pl->tz, pl->iz, pl->slot);
+    prof_after(pl, HAMLET_K_BIN);
     LAUNCH_CHECK();
   }
-  const dim3 gs_xy(N, S::CHUNKS), gs_z(N, N / S::P);
-  k_inv_x<T, N><<<gs_xy, kPassThreads, 0, st>>>(q, tab, tw, (C*)pl->a, (C*)pl->b, pl->prior_part);
-  k_inv_y<T, N><<<gs_xy, kPassThreads, 0, st>>>((const C*)pl->a, (const C*)pl->b, tw, (C*)pl->v0, (C*)pl->v1,
-                                                 (C*)pl->v2);
-  k_inv_z_gather<T, N><<<gs_z, kPassThreads, 0, st>>>((const C*)pl->v0, (const C*)pl->v1, (const C*)pl->v2, tw,
-                                                       bins, (C*)pl->part);
+  const dim3 gs_xy(S::CHUNKS, N), gs_z(N / S::P, N);
+  if (!leap)
+    TIMED(pl, HAMLET_K_INV_X,
+          k_inv_x<T, N><<<gs_xy, kPassThreads, 0, st>>>(q, tab, tw, (C*)pl->a, (C*)pl->b, pl->prior_part));
+  TIMED(pl, HAMLET_K_INV_Y,
+        k_inv_y<T, N><<<gs_xy, kPassThreads, 0, st>>>((const C*)pl->a, (const C*)pl->b, tw, (C*)pl->v0,
+                                                       (C*)pl->v1, (C*)pl->v2));
+  TIMED(pl, HAMLET_K_INV_Z,
+        k_inv_z_gather<T, N><<<gs_z, kPassThreads, 0, st>>>((const C*)pl->v0, (const C*)pl->v1,
+                                                             (const C*)pl->v2, tw, bins, (C*)pl->part));
   LAUNCH_CHECK();
   if (n > 0) {
     LikeOut lo;
     lo.g_dist = gd;
     lo.part = pl->like_part;
-    k_like<T><<<blocks_for(n, kGalThreads), kGalThreads, 0, st>>>((const C*)pl->part, pl->slot, pl->frac, qd, qs,
-                                                                   cat, cm, (T*)pl->gsort, lo);
+    TIMED(pl, HAMLET_K_LIKE,
+          k_like<T><<<blocks_for(n, kGalThreads), kGalThreads, 0, st>>>((const C*)pl->part, pl->slot, pl->frac,
+                                                                         qd, qs, cat, cm, (T*)pl->gsort, lo, lf_d));
     LAUNCH_CHECK();
   }
-  k_fwd_z_scatter<T, N><<<gs_z, kPassThreads, 0, st>>>((const T*)pl->gsort, bins, tw, (C*)pl->v0, (C*)pl->v1,
-                                                        (C*)pl->v2);
-  k_fwd_y<T, N><<<gs_xy, kPassThreads, 0, st>>>((const C*)pl->v0, (const C*)pl->v1, (const C*)pl->v2, tw,
-                                                 (C*)pl->a, (C*)pl->b);
-  k_fwd_x_grad<T, N><<<gs_xy, kPassThreads, 0, st>>>((const C*)pl->a, (const C*)pl->b, q, tab, tw, g);
   k_finalize<<<1, 256, 0, st>>>(pl->prior_part, pl->n_prior_part, pl->like_part, n > 0 ? pl->n_like_part : 0, psi,
-                                gs);
+                                gs, qs, lf_s);
+  TIMED(pl, HAMLET_K_FWD_Z,
+        k_fwd_z_scatter<T, N><<<gs_z, kPassThreads, 0, st>>>((const T*)pl->gsort, bins, tw, (C*)pl->v0,
+                                                              (C*)pl->v1, (C*)pl->v2));
+  TIMED(pl, HAMLET_K_FWD_Y,
+        k_fwd_y<T, N><<<gs_xy, kPassThreads, 0, st>>>((const C*)pl->v0, (const C*)pl->v1, (const C*)pl->v2, tw,
+                                                       (C*)pl->a, (C*)pl->b));
+  const C* s1 = (const C*)pl->a;
+  const C* s2 = (const C*)pl->b;
+  if (em.x_mode == kXGrad) {
+    TIMED(pl, HAMLET_K_FWD_X,
+          (k_x_pass<T, N, kXGrad><<<gs_xy, kPassThreads, 0, st>>>(s1, s2, q, nullptr, g, tab, tw, nullptr, nullptr,
+                                                                    nullptr, nullptr)));
+  } else if (em.x_mode == kXMid) {
+    // S1, S2 live in a, b and are read by the same tile that writes the next
+    // A, B: the x pass writes them to v0, v1 and the plan swaps the roles.
+    TIMED(pl, HAMLET_K_FWD_X,
+          (k_x_pass<T, N, kXMid><<<gs_xy, kPassThreads, 0, st>>>(s1, s2, q, em.p_modes, nullptr, tab, tw, em.eps,
+                                                                   (C*)pl->v0, (C*)pl->v1, pl->prior_part)));
+    std::swap(pl->a, pl->v0);
+    std::swap(pl->b, pl->v1);
+  } else {
+    TIMED(pl, HAMLET_K_FWD_X,
+          (k_x_pass<T, N, kXLast><<<gs_xy, kPassThreads, 0, st>>>(s1, s2, q, em.p_modes, g, tab, tw, em.eps, nullptr,
+                                                                    nullptr, nullptr)));
+  }
   LAUNCH_CHECK();
   return HAMLET_OK;
 }
 
-template <typename T> static grad_fn pick_grad(int n) {
+// First step of a trajectory: half kick from the cached gradient and drift
+// of every coordinate, then inverse pass 1 of the new modes.
+template <typename T, int N>
+static hamlet_status first_impl(hamlet_plan* pl, double2* q, double2* p_modes, const double* eps) {
+  using C = cplx_t<T>;
+  using S = PassShape<T, N>;
+  const dim3 gs_xy(S::CHUNKS, N);
+  TIMED(pl, HAMLET_K_FWD_X,
+        (k_x_pass<T, N, kXFirst><<<gs_xy, kPassThreads, 0, pl->stream>>>(
+            nullptr, nullptr, q, p_modes, pl->gcache, tables_view(pl), (const C*)pl->tw, eps, (C*)pl->a, (C*)pl->b,
+            pl->prior_part)));
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
+template <typename T> static eval_fn pick_eval(int n) {
   switch (n) {
-    case 16: return grad_impl<T, 16>;
-    case 32: return grad_impl<T, 32>;
-    case 64: return grad_impl<T, 64>;
-    case 128: return grad_impl<T, 128>;
-    case 256: return grad_impl<T, 256>;
+    case 16: return eval_impl<T, 16>;
+    case 32: return eval_impl<T, 32>;
+    case 64: return eval_impl<T, 64>;
+    case 128: return eval_impl<T, 128>;
+    case 256: return eval_impl<T, 256>;
+    default: return nullptr;
+  }
+}
+
+template <typename T> static first_fn pick_first(int n) {
+  switch (n) {
+    case 16: return first_impl<T, 16>;
+    case 32: return first_impl<T, 32>;
+    case 64: return first_impl<T, 64>;
+    case 128: return first_impl<T, 128>;
+    case 256: return first_impl<T, 256>;
     default: return nullptr;
   }
 }
@@ -206,6 +322,7 @@ static void carve(hamlet_plan* pl) {
   pl->count = ws.take<int>((size_t)n * n);
   pl->off = ws.take<int>((size_t)n * n + 1);
   pl->cursor = ws.take<int>((size_t)n * n);
+  pl->bsum = ws.take<int>(((size_t)n * n + kScanTile - 1) / kScanTile);
   pl->key = ws.take<int>(ng);
   pl->cellz = ws.take<int>(ng);
   pl->slot = ws.take<int>(ng);
@@ -406,7 +523,8 @@ extern "C" hamlet_status hamlet_plan_create(const hamlet_plan_desc* desc, const 
   hamlet_plan* pl = new hamlet_plan();
   fill_plan_scalars(pl, desc, cat->n, (int)hist.size());
   pl->stream = (hipStream_t)stream;
-  pl->grad = pl->prec == HAMLET_FP64 ? pick_grad<double>(pl->n) : pick_grad<float>(pl->n);
+  pl->eval = pl->prec == HAMLET_FP64 ? pick_eval<double>(pl->n) : pick_eval<float>(pl->n);
+  pl->first = pl->prec == HAMLET_FP64 ? pick_first<double>(pl->n) : pick_first<float>(pl->n);
   carve(pl);
   const size_t bytes = pl->ws.used;
   if (hipMalloc((void**)&pl->ws.base, bytes) != hipSuccess) {
@@ -428,6 +546,10 @@ extern "C" hamlet_status hamlet_plan_create(const hamlet_plan_desc* desc, const 
 extern "C" hamlet_status hamlet_plan_destroy(hamlet_plan* pl) {
   if (!pl) return HAMLET_OK;
   hipError_t e1 = hipStreamSynchronize(pl->stream);
+  for (auto& ev : pl->prof_pool) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
   hipError_t e2 = hipFree(pl->ws.base);
   delete pl;
   if (e1 != hipSuccess || e2 != hipSuccess) return fail(HAMLET_EDEVICE, "plan destroy: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
@@ -437,41 +559,28 @@ extern "C" hamlet_status hamlet_plan_destroy(hamlet_plan* pl) {
 // ---------------------------------------------------------------------------
 // Leapfrog and chain orchestration
 // ---------------------------------------------------------------------------
-static hamlet_status kick(hamlet_plan* pl, double2* pmodes, double* pd, double* ps, const double2* g,
-                          const double* gd, const double* gs, const double* eps, double mult) {
-  const size_t nm = pl->modes_count();
-  k_kick_modes<<<blocks_for(nm, kEltThreads), kEltThreads, 0, pl->stream>>>(pmodes, g, nm, eps, mult);
-  k_small_update<<<blocks_for(std::max(pl->n_gal, 1), kEltThreads), kEltThreads, 0, pl->stream>>>(
-      nullptr, pd, gd, nullptr, ps, gs, pl->n_gal, pl->sample_d, pl->sample_s, pl->minv_d, eps, mult, 0);
-  LAUNCH_CHECK();
-  return HAMLET_OK;
-}
-
-static hamlet_status drift(hamlet_plan* pl, double2* q, double* qd, double* qs, const double2* pmodes,
-                           double* pd, double* ps, const double* eps) {
-  const size_t nm = pl->modes_count();
-  k_drift_modes<<<blocks_for(nm, kEltThreads), kEltThreads, 0, pl->stream>>>(q, pmodes, tables_view(pl), pl->n,
-                                                                              eps);
-  k_small_update<<<blocks_for(std::max(pl->n_gal, 1), kEltThreads), kEltThreads, 0, pl->stream>>>(
-      qd, pd, nullptr, qs, ps, nullptr, pl->n_gal, pl->sample_d, pl->sample_s, pl->minv_d, eps, 1.0, 1);
-  LAUNCH_CHECK();
-  return HAMLET_OK;
-}
-
-// Kick-drift-kick trajectory from a state whose gradient is cached in
-// (pl->gcache, pl->gd, cs->gs); leaves the end point's gradient and Psi there.
+// Kick-drift-kick trajectory (eq:hamilton, Section 3.3) of `steps` steps from
+// a state whose gradient is cached in (pl->gcache, pl->gd, cs->gs); leaves
+// the end point's gradient there and its Psi in cs->psi.  Consecutive half
+// kicks are merged and every update is fused into the evaluation kernels.
 static hamlet_status trajectory(hamlet_plan* pl, int steps, const double* eps, double2* q, double* qd, double* qs,
                                 double2* pmodes, double* pd, double* ps) {
+  if (steps <= 0) return HAMLET_OK;
   double* psi = &pl->cs->psi;
   double* gs = &pl->cs->gs;
-  for (int s = 0; s < steps; ++s) {
-    hamlet_status st = kick(pl, pmodes, pd, ps, pl->gcache, pl->gd, gs, eps, 0.5);
-    if (st != HAMLET_OK) return st;
-    st = drift(pl, q, qd, qs, pmodes, pd, ps, eps);
-    if (st != HAMLET_OK) return st;
-    st = pl->grad(pl, q, qd, qs, pl->gcache, pl->gd, gs, psi);
-    if (st != HAMLET_OK) return st;
-    st = kick(pl, pmodes, pd, ps, pl->gcache, pl->gd, gs, eps, 0.5);
+  k_small_kick_drift<<<blocks_for(std::max(pl->n_gal, 1), kEltThreads), kEltThreads, 0, pl->stream>>>(
+      qd, pd, pl->gd, qs, ps, gs, pl->n_gal, pl->sample_d, pl->sample_s, pl->minv_d, eps);
+  LAUNCH_CHECK();
+  hamlet_status st = pl->first(pl, q, pmodes, eps);
+  if (st != HAMLET_OK) return st;
+  EvalMode em;
+  em.p_modes = pmodes;
+  em.p_dist = pd;
+  em.p_snl = ps;
+  em.eps = eps;
+  for (int k = 1; k <= steps; ++k) {
+    em.x_mode = k < steps ? kXMid : kXLast;
+    st = pl->eval(pl, q, qd, qs, pl->gcache, pl->gd, gs, psi, em);
     if (st != HAMLET_OK) return st;
   }
   return HAMLET_OK;
@@ -506,8 +615,8 @@ extern "C" hamlet_status hamlet_logpost_grad(hamlet_plan* const* plans, int32_t 
       return fail(HAMLET_EINVAL, "plan %d: NULL buffer", j);
     if (pl->n_gal > 0 && (!q_dist || !g_dist || !q_dist[j] || !g_dist[j]))
       return fail(HAMLET_EINVAL, "plan %d: NULL distance buffer", j);
-    st = pl->grad(pl, (const double2*)q_modes[j], pl->n_gal ? q_dist[j] : nullptr, q_snl[j],
-                  (double2*)g_modes[j], pl->n_gal ? g_dist[j] : nullptr, g_snl[j], psi[j]);
+    st = pl->eval(pl, (double2*)q_modes[j], pl->n_gal ? (double*)q_dist[j] : nullptr, (double*)q_snl[j],
+                  (double2*)g_modes[j], pl->n_gal ? g_dist[j] : nullptr, g_snl[j], psi[j], EvalMode());
     if (st != HAMLET_OK) return st;
   }
   return HAMLET_OK;
@@ -532,7 +641,7 @@ extern "C" hamlet_status hamlet_leapfrog(hamlet_plan* const* plans, int32_t n_pl
     double* qd = pl->n_gal ? q_dist[j] : pl->qd0;
     double* pd = pl->n_gal ? p_dist[j] : pl->pd;
     k_set_scalar<<<1, 1, 0, pl->stream>>>(pl->eps_slot, eps[j]);
-    st = pl->grad(pl, (const double2*)q_modes[j], qd, q_snl[j], pl->gcache, pl->gd, &pl->cs->gs, &pl->cs->psi);
+    st = pl->eval(pl, (double2*)q_modes[j], qd, q_snl[j], pl->gcache, pl->gd, &pl->cs->gs, &pl->cs->psi, EvalMode());
     if (st != HAMLET_OK) return st;
     st = trajectory(pl, n_steps[j], pl->eps_slot, (double2*)q_modes[j], qd, q_snl[j], (double2*)p_modes[j], pd,
                     p_snl[j]);
@@ -564,7 +673,7 @@ extern "C" hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_pla
     hamlet_plan* pl = plans[j];
     double* qd = pl->n_gal ? q_dist[j] : pl->qd0;
     k_chain_init<<<1, 1, 0, pl->stream>>>(pl->cs, o->eps0, o->target_accept);
-    st = pl->grad(pl, (const double2*)q_modes[j], qd, q_snl[j], pl->gcache, pl->gd, &pl->cs->gs, &pl->cs->psi);
+    st = pl->eval(pl, (double2*)q_modes[j], qd, q_snl[j], pl->gcache, pl->gd, &pl->cs->gs, &pl->cs->psi, EvalMode());
     if (st != HAMLET_OK) return st;
   }
   for (int it = 0; it < o->n_iter; ++it) {
@@ -612,6 +721,32 @@ extern "C" hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_pla
       HIP_TRY(hipStreamSynchronize(pl->stream));
     }
   }
+  return HAMLET_OK;
+}
+
+extern "C" hamlet_status hamlet_profile_start(hamlet_plan* pl, int32_t kernel) {
+  if (!pl) return fail(HAMLET_EINVAL, "plan is NULL");
+  if (kernel < 0 || kernel >= HAMLET_K_COUNT) return fail(HAMLET_EINVAL, "kernel kind %d", kernel);
+  pl->prof_kind = kernel;
+  pl->prof_used = 0;
+  pl->prof_failed = false;
+  return HAMLET_OK;
+}
+
+extern "C" hamlet_status hamlet_profile_stop(hamlet_plan* pl, double* total_ms, int64_t* launches) {
+  if (!pl || !total_ms || !launches) return fail(HAMLET_EINVAL, "NULL argument");
+  pl->prof_kind = -1;
+  HIP_TRY(hipStreamSynchronize(pl->stream));
+  double sum = 0.0;
+  for (size_t i = 0; i < pl->prof_used; ++i) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, pl->prof_pool[i].first, pl->prof_pool[i].second));
+    sum += ms;
+  }
+  *total_ms = sum;
+  *launches = (int64_t)pl->prof_used;
+  pl->prof_used = 0;
+  if (pl->prof_failed) return fail(HAMLET_EDEVICE, "event creation or record failed while profiling");
   return HAMLET_OK;
 }
 

@@ -143,54 +143,23 @@ k_kinetic_final(const double* __restrict__ part, int n_part, const double* __res
   if (threadIdx.x == 0) out[0] = a + 0.5 * minv_d * b + 0.5 * minv_s * p_snl[0] * p_snl[0];
 }
 
-// ---------------------------------------------------------------------------
-// Leapfrog pieces (kick-drift-kick), step read from device memory.
-// ---------------------------------------------------------------------------
+// First half kick (from the cached gradient) and drift of the distances and
+// of s: p -= (eps/2) g, q += eps M^-1 p.
 __global__ void __launch_bounds__(kEltThreads)
-k_kick_modes(double2* __restrict__ p, const double2* __restrict__ grad, size_t total,
-             const double* __restrict__ eps, double mult) {
-  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const double h = mult * eps[0];
-  double2 v = p[g];
-  const double2 f = grad[g];
-  v.x -= h * f.x;
-  v.y -= h * f.y;
-  p[g] = v;
-}
-
-__global__ void __launch_bounds__(kEltThreads)
-k_drift_modes(double2* __restrict__ q, const double2* __restrict__ p, ModeTables tab, int n,
-              const double* __restrict__ eps) {
-  const size_t total = (size_t)n * n * (n / 2);
-  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const ModeIdx m = mode_idx(g, n);
-  if (!retained(m.sx, m.sy, m.kz, n)) return;
-  const int n2 = m.sx * m.sx + m.sy * m.sy + m.kz * m.kz;
-  const double c = eps[0] * (0.5 * tab.var[n2]);
-  double2 v = q[g];
-  const double2 pv = p[g];
-  v.x += c * pv.x;
-  v.y += c * pv.y;
-  q[g] = v;
-}
-
-// Kick (mode 0) or drift (mode 1) of the distances and of s.
-__global__ void __launch_bounds__(kEltThreads)
-k_small_update(double* __restrict__ q_dist, double* __restrict__ p_dist, const double* __restrict__ g_dist,
-               double* __restrict__ q_snl, double* __restrict__ p_snl, const double* __restrict__ g_snl,
-               int n_gal, int sample_d, int sample_s, double minv_d, const double* __restrict__ eps,
-               double mult, int drift) {
+k_small_kick_drift(double* __restrict__ q_dist, double* __restrict__ p_dist, const double* __restrict__ g_dist,
+                   double* __restrict__ q_snl, double* __restrict__ p_snl, const double* __restrict__ g_snl,
+                   int n_gal, int sample_d, int sample_s, double minv_d, const double* __restrict__ eps) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const double h = mult * eps[0];
+  const double e = eps[0];
   if (i < n_gal && sample_d) {
-    if (drift) q_dist[i] += h * minv_d * p_dist[i];
-    else p_dist[i] -= h * g_dist[i];
+    const double pv = p_dist[i] - 0.5 * e * g_dist[i];
+    p_dist[i] = pv;
+    q_dist[i] += e * minv_d * pv;
   }
   if (i == 0 && sample_s) {
-    if (drift) q_snl[0] += h * p_snl[0];
-    else p_snl[0] -= h * g_snl[0];
+    const double pv = p_snl[0] - 0.5 * e * g_snl[0];
+    p_snl[0] = pv;
+    q_snl[0] += e * pv;
   }
 }
 

@@ -18,6 +18,11 @@
 //   sum_c n_c Ghat_c = FFT_x(S1) + n_x FFT_x(S2),
 // and the mode gradient (complex convention dPsi/dRe + i dPsi/dIm) is
 //   G = 2 dhat / sigma_k^2 - 2 i kfac sum_c n_c Ghat_c      (eq:prior-k + adjoint).
+//
+// Strided passes (x, y) work on tiles of W consecutive kz columns times all
+// N entries along the axis; the grid is (N/2 / W chunks, N rows) with the
+// chunk index fastest, so the blocks that run together read whole 1 KB
+// (FP32) rows of the array.  z passes work on P consecutive pencils.
 #pragma once
 
 #include "common.hpp"
@@ -27,14 +32,18 @@ namespace hamlet {
 
 constexpr int kPassThreads = 256;
 
-// Chunk of contiguous kz columns per strided-pass tile, pencils per z tile.
 template <typename T, int N> struct PassShape {
-  static constexpr int W = (sizeof(T) == 4 ? 16 : 8) < N / 2 ? (sizeof(T) == 4 ? 16 : 8) : N / 2;
-  static constexpr int P = (sizeof(T) == 4 ? 16 : 8) < N ? (sizeof(T) == 4 ? 16 : 8) : N;
+  using C = cplx_t<T>;
+  static constexpr int WMAX = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int W = WMAX < N / 2 ? WMAX : N / 2;     // kz columns per strided tile
+  static constexpr int P = WMAX < N ? WMAX : N;             // pencils per z tile
   static constexpr int H = N / 2;
   static constexpr int CHUNKS = H / W;
   static constexpr int ELEMS = N * W;
   static constexpr int EPT = (ELEMS + kPassThreads - 1) / kPassThreads;
+  static constexpr int F = 3 * P / 2;                       // complex transforms per z tile
+  using Row = RowLayout<C, W>;
+  using Pen = PencilLayout<N>;
 };
 
 // Tables indexed by n^2 = nx^2 + ny^2 + nz^2 (0 .. 3 (N/2)^2).
@@ -59,9 +68,26 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;   // valid in thread 0
 }
 
+// Visit this thread's elements (a = index along the FFT axis, w = column)
+// of a strided tile.
+template <typename T, int N, typename Fn>
+__device__ __forceinline__ void tile_elems(Fn&& fn) {
+  using S = PassShape<T, N>;
+#pragma unroll
+  for (int e = 0; e < S::EPT; ++e) {
+    const int idx = threadIdx.x + e * kPassThreads;
+    if (S::ELEMS % kPassThreads == 0 || idx < S::ELEMS) fn(e, idx / S::W, idx % S::W);
+  }
+}
+
+// Global offset of (i, j, kz) in an [N][N][N/2] array.
+template <int N> __device__ __forceinline__ size_t gofs(int i, int j, int kz) {
+  return ((size_t)i * N + j) * (N / 2) + kz;
+}
+
 // ---------------------------------------------------------------------------
 // Inverse pass 1 (along x): multiplier, prior energy, two spectral outputs.
-// Tile: fixed ky, kz chunk [z0, z0 + W), all kx.  Grid (N, CHUNKS).
+// Tile: fixed ky, kz chunk, all kx.
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ void __launch_bounds__(kPassThreads)
@@ -69,69 +95,44 @@ k_inv_x(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* __re
         cplx_t<T>* __restrict__ outA, cplx_t<T>* __restrict__ outB, double* __restrict__ prior_part) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
-  constexpr int W = S::W, H = S::H;
-  __shared__ C tile[S::ELEMS];
+  using LAY = typename S::Row;
+  __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
   __shared__ double red[kPassThreads / 64];
   load_twiddles<T, N, kPassThreads>(twl, tw);
-  const int y = blockIdx.x, z0 = blockIdx.y * W;
+  const int y = blockIdx.y, z0 = blockIdx.x * S::W;
   const int sy = signed_freq(y, N);
-  double2 ain[S::EPT];
   double prior = 0.0;
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    ain[e] = make_double2(0.0, 0.0);
-    if (idx < S::ELEMS) {
-      const int w = idx % W, x = idx / W, kz = z0 + w;
-      const int sx = signed_freq(x, N);
-      const double2 q = modes[((size_t)x * N + y) * H + kz];
-      if (retained(sx, sy, kz, N)) {
-        const int n2 = sx * sx + sy * sy + kz * kz;
-        const double wk = kz == 0 ? 0.5 : 1.0;
-        prior += wk * (q.x * q.x + q.y * q.y) * tab.inv_var[n2];
-        const double kf = tab.kfac[n2];
-        ain[e] = make_double2(-kf * q.y, kf * q.x);   // i kfac q
-      }
-      tile[x * W + w] = cconvert<C>(ain[e]);
+  // i kfac q (and n_x times it), zero on excluded modes
+  auto ain = [&](int x, int w, double scale_x) {
+    const int kz = z0 + w, sx = signed_freq(x, N);
+    if (!retained(sx, sy, kz, N)) return make_double2(0.0, 0.0);
+    const double2 q = modes[gofs<N>(x, y, kz)];
+    const double kf = tab.kfac[sx * sx + sy * sy + kz * kz] * (scale_x != 0.0 ? scale_x * sx : 1.0);
+    return make_double2(-kf * q.y, kf * q.x);
+  };
+  tile_elems<T, N>([&](int, int x, int w) {
+    const int kz = z0 + w, sx = signed_freq(x, N);
+    if (retained(sx, sy, kz, N)) {
+      const double2 q = modes[gofs<N>(x, y, kz)];
+      prior += (kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * tab.inv_var[sx * sx + sy * sy + kz * kz];
     }
-  }
+    tile[LAY::idx(x, w)] = cconvert<C>(ain(x, w, 0.0));
+  });
   const double ps = block_sum(prior, red);
   if (threadIdx.x == 0) prior_part[blockIdx.y * gridDim.x + blockIdx.x] = ps;
   __syncthreads();
-  lds_fft<T, N, W, W, 1, false, kPassThreads, +1>(tile, twl);
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, x = idx / W;
-      outA[((size_t)x * N + y) * H + z0 + w] = tile[x * W + w];
-    }
-  }
+  lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
+  tile_elems<T, N>([&](int, int x, int w) { outA[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
   __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, x = idx / W;
-      const double sx = (double)signed_freq(x, N);
-      tile[x * W + w] = cconvert<C>(make_double2(sx * ain[e].x, sx * ain[e].y));
-    }
-  }
+  tile_elems<T, N>([&](int, int x, int w) { tile[LAY::idx(x, w)] = cconvert<C>(ain(x, w, 1.0)); });
   __syncthreads();
-  lds_fft<T, N, W, W, 1, false, kPassThreads, +1>(tile, twl);
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, x = idx / W;
-      outB[((size_t)x * N + y) * H + z0 + w] = tile[x * W + w];
-    }
-  }
+  lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
+  tile_elems<T, N>([&](int, int x, int w) { outB[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
 }
 
 // ---------------------------------------------------------------------------
-// Inverse pass 2 (along y).  Tile: fixed x, kz chunk, all ky.  Grid (N, CHUNKS).
+// Inverse pass 2 (along y).  Tile: fixed x, kz chunk, all ky.
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ void __launch_bounds__(kPassThreads)
@@ -139,70 +140,27 @@ k_inv_y(const cplx_t<T>* __restrict__ inA, const cplx_t<T>* __restrict__ inB, co
         cplx_t<T>* __restrict__ vx, cplx_t<T>* __restrict__ vy, cplx_t<T>* __restrict__ vz) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
-  constexpr int W = S::W, H = S::H;
-  __shared__ C tile[S::ELEMS];
+  using LAY = typename S::Row;
+  __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
   load_twiddles<T, N, kPassThreads>(twl, tw);
-  const int x = blockIdx.x, z0 = blockIdx.y * W;
-  C a[S::EPT];
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, y = idx / W;
-      const size_t g = ((size_t)x * N + y) * H + z0 + w;
-      a[e] = inA[g];
-      tile[y * W + w] = inB[g];
-    }
-  }
+  const int x = blockIdx.y, z0 = blockIdx.x * S::W;
+  tile_elems<T, N>([&](int, int y, int w) { tile[LAY::idx(y, w)] = inB[gofs<N>(x, y, z0 + w)]; });
   __syncthreads();
-  lds_fft<T, N, W, W, 1, false, kPassThreads, +1>(tile, twl);
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, y = idx / W;
-      vx[((size_t)x * N + y) * H + z0 + w] = tile[y * W + w];
-    }
-  }
+  lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
+  tile_elems<T, N>([&](int, int y, int w) { vx[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
   __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, y = idx / W;
-      tile[y * W + w] = cscale(a[e], (T)signed_freq(y, N));
-    }
-  }
+  tile_elems<T, N>([&](int, int y, int w) {
+    tile[LAY::idx(y, w)] = cscale(inA[gofs<N>(x, y, z0 + w)], (T)signed_freq(y, N));
+  });
   __syncthreads();
-  lds_fft<T, N, W, W, 1, false, kPassThreads, +1>(tile, twl);
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, y = idx / W;
-      vy[((size_t)x * N + y) * H + z0 + w] = tile[y * W + w];
-    }
-  }
+  lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
+  tile_elems<T, N>([&](int, int y, int w) { vy[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
   __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, y = idx / W;
-      tile[y * W + w] = a[e];
-    }
-  }
+  tile_elems<T, N>([&](int, int y, int w) { tile[LAY::idx(y, w)] = inA[gofs<N>(x, y, z0 + w)]; });
   __syncthreads();
-  lds_fft<T, N, W, W, 1, false, kPassThreads, +1>(tile, twl);
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, y = idx / W;
-      vz[((size_t)x * N + y) * H + z0 + w] = tile[y * W + w];
-    }
-  }
+  lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
+  tile_elems<T, N>([&](int, int y, int w) { vz[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
 }
 
 // Galaxies binned by CIC column (ix, iy) of their lower corner, in sorted
@@ -217,7 +175,7 @@ template <typename T> struct Binned {
 // Transform slot of the real pencil of component c of pencil p in a z tile:
 // pairs of pencils (2m, 2m+1) fill three complex transforms
 //   3m   : (vx_2m,   vy_2m)      3m+1 : (vz_2m, vz_2m+1)      3m+2 : (vx_2m+1, vy_2m+1)
-// and the real pencil is the real (slot 0) or imaginary (slot 1) part.
+// and the real pencil is the real (part 0) or imaginary (part 1) part.
 __device__ __forceinline__ int zslot_f(int p, int c) {
   const int m = p >> 1, odd = p & 1;
   return c == 2 ? 3 * m + 1 : 3 * m + (odd ? 2 : 0);
@@ -225,11 +183,10 @@ __device__ __forceinline__ int zslot_f(int p, int c) {
 __device__ __forceinline__ int zslot_part(int p, int c) {
   return c == 0 ? 0 : (c == 1 ? 1 : (p & 1));
 }
-template <typename C> __device__ __forceinline__ decltype(C{}.x) part_of(C v, int slot) { return slot ? v.y : v.x; }
 
 // ---------------------------------------------------------------------------
 // Inverse pass 3 (along z, complex-to-real) fused with the CIC gather.
-// Tile: fixed x, pencils y0 .. y0 + P.  Grid (N, N / P).
+// Tile: fixed x, pencils y0 .. y0 + P.  Grid (N / P, N).
 // Writes, for every galaxy whose CIC stencil touches a pencil of the tile,
 // the column partials of its projected velocity (eqn:lvr):
 //   Pc = sum_c rhat_c [(1 - tz) v_c(z0) + tz v_c(z1)],  Qc = sum_c rhat_c [v_c(z1) - v_c(z0)]
@@ -241,11 +198,12 @@ k_inv_z_gather(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ v
                const cplx_t<T>* __restrict__ tw, Binned<T> bins, cplx_t<T>* __restrict__ part) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
-  constexpr int P = S::P, H = S::H, F = 3 * P / 2;
-  __shared__ C buf[F * N];
+  using LAY = typename S::Pen;
+  constexpr int P = S::P, H = S::H, F = S::F;
+  __shared__ C buf[LAY::size(F)];
   __shared__ C twl[N];
   load_twiddles<T, N, kPassThreads>(twl, tw);
-  const int x = blockIdx.x, y0 = blockIdx.y * P;
+  const int x = blockIdx.y, y0 = blockIdx.x * P;
   // Build Z = A + i B with A, B the Hermitian half spectra of the two real
   // pencils of each transform (Nyquist entry zero, DC entries real).
   for (int idx = threadIdx.x; idx < F * H; idx += kPassThreads) {
@@ -253,58 +211,58 @@ k_inv_z_gather(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ v
     const int m = f / 3, r = f % 3;
     C av, bv;
     if (r == 1) {
-      const size_t g0 = ((size_t)x * N + y0 + 2 * m) * H + k;
+      const size_t g0 = gofs<N>(x, y0 + 2 * m, k);
       av = cscale(vz[g0], (T)k);
       bv = cscale(vz[g0 + H], (T)k);
     } else {
-      const size_t g = ((size_t)x * N + y0 + 2 * m + (r == 2 ? 1 : 0)) * H + k;
+      const size_t g = gofs<N>(x, y0 + 2 * m + (r == 2 ? 1 : 0), k);
       av = vx[g];
       bv = vy[g];
     }
-    C* row = buf + f * N;
     if (k == 0) {
-      row[0] = cmake<C>(av.x, bv.x);
-      row[H] = cmake<C>((T)0, (T)0);
+      buf[LAY::idx(0, f)] = cmake<C>(av.x, bv.x);
+      buf[LAY::idx(H, f)] = cmake<C>((T)0, (T)0);
     } else {
-      row[k] = cmake<C>(av.x - bv.y, av.y + bv.x);          // A + i B
-      row[N - k] = cmake<C>(av.x + bv.y, bv.x - av.y);      // conj(A) + i conj(B)
+      buf[LAY::idx(k, f)] = cmake<C>(av.x - bv.y, av.y + bv.x);          // A + i B
+      buf[LAY::idx(N - k, f)] = cmake<C>(av.x + bv.y, bv.x - av.y);      // conj(A) + i conj(B)
     }
   }
   __syncthreads();
-  lds_fft<T, N, F, 1, N, true, kPassThreads, +1>(buf, twl);
-  // Gather: one thread per (pencil, corner), bucket members in sorted order.
-  if (threadIdx.x < 4 * P) {
-    const int p = threadIdx.x >> 2, corner = threadIdx.x & 3;
+  lds_fft<T, N, F, LAY, kPassThreads, +1>(buf, twl);
+  // Gather: (pencil, corner, lane) per thread; lane strides the bucket.
+  constexpr int LANES = kPassThreads / (4 * P);
+  {
+    const int t = threadIdx.x;
+    const int pc = t % (4 * P), lane = t / (4 * P);
+    const int p = pc >> 2, corner = pc & 3;
     const int ox = corner >> 1, oy = corner & 1;
     const int y = y0 + p;
     const int key = ((x - ox + N) & (N - 1)) * N + ((y - oy + N) & (N - 1));
     const int s0 = bins.off[key], s1 = bins.off[key + 1];
-    const C* fx = buf + zslot_f(p, 0) * N;
-    const C* fy = buf + zslot_f(p, 1) * N;
-    const C* fz = buf + zslot_f(p, 2) * N;
-    const int sz = zslot_part(p, 2);
-    for (int s = s0; s < s1; ++s) {
+    const int fxy = zslot_f(p, 0), fz = zslot_f(p, 2), sz = zslot_part(p, 2);
+    for (int s = s0 + lane; s < s1; s += LANES) {
       const int z0 = bins.iz[s], z1 = (z0 + 1) & (N - 1);
       const T tz = bins.tz[s];
       const T rx = bins.rx[s], ry = bins.ry[s], rz = bins.rz[s];
-      const T ax0 = fx[z0].x, ax1 = fx[z1].x;
-      const T ay0 = fy[z0].y, ay1 = fy[z1].y;
-      const T az0 = part_of(fz[z0], sz), az1 = part_of(fz[z1], sz);
+      const C a0 = buf[LAY::idx(z0, fxy)], a1 = buf[LAY::idx(z1, fxy)];
+      const C c0 = buf[LAY::idx(z0, fz)], c1 = buf[LAY::idx(z1, fz)];
+      const T az0 = sz ? c0.y : c0.x, az1 = sz ? c1.y : c1.x;
       const T omt = (T)1 - tz;
-      const T pc = rx * (omt * ax0 + tz * ax1) + ry * (omt * ay0 + tz * ay1) + rz * (omt * az0 + tz * az1);
-      const T qc = rx * (ax1 - ax0) + ry * (ay1 - ay0) + rz * (az1 - az0);
-      part[4 * (size_t)s + corner] = cmake<C>(pc, qc);
+      const T pcv = rx * (omt * a0.x + tz * a1.x) + ry * (omt * a0.y + tz * a1.y) + rz * (omt * az0 + tz * az1);
+      const T qcv = rx * (a1.x - a0.x) + ry * (a1.y - a0.y) + rz * (az1 - az0);
+      part[4 * (size_t)s + corner] = cmake<C>(pcv, qcv);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Forward pass 1 (along z, real-to-complex) fused with the CIC scatter-add:
-// each pencil of the tile is built in LDS from the galaxies whose stencil
-// touches it, one thread per pencil adding contributions in a fixed order
-// (corner, then sorted index), so the result is deterministic.
+// each real pencil of the tile is built in LDS from the galaxies whose
+// stencil touches it, one thread per (pencil, component) adding
+// contributions in a fixed order (corner, then sorted index), so the result
+// is deterministic.
 //   G_c(x_j) = sum_i g_i rhat_ic W_i(x_j)  (adjoint of the gather)
-// Outputs Gx, Gy and n_z Gz on kz in [0, N/2).  Grid (N, N / P).
+// Outputs Gx, Gy and n_z Gz on kz in [0, N/2).  Grid (N / P, N).
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ void __launch_bounds__(kPassThreads)
@@ -312,18 +270,18 @@ k_fwd_z_scatter(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>* __
                 cplx_t<T>* __restrict__ gx, cplx_t<T>* __restrict__ gy, cplx_t<T>* __restrict__ gz) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
-  constexpr int P = S::P, H = S::H, F = 3 * P / 2;
-  __shared__ C buf[F * N];
+  using LAY = typename S::Pen;
+  constexpr int P = S::P, H = S::H, F = S::F;
+  __shared__ C buf[LAY::size(F)];
   __shared__ C twl[N];
   load_twiddles<T, N, kPassThreads>(twl, tw);
-  for (int i = threadIdx.x; i < F * N; i += kPassThreads) buf[i] = cmake<C>((T)0, (T)0);
+  for (int i = threadIdx.x; i < LAY::size(F); i += kPassThreads) buf[i] = cmake<C>((T)0, (T)0);
   __syncthreads();
-  const int x = blockIdx.x, y0 = blockIdx.y * P;
-  if (threadIdx.x < P) {
-    const int p = threadIdx.x, y = y0 + p;
-    T* rowx = reinterpret_cast<T*>(buf + zslot_f(p, 0) * N) + zslot_part(p, 0);
-    T* rowy = reinterpret_cast<T*>(buf + zslot_f(p, 1) * N) + zslot_part(p, 1);
-    T* rowz = reinterpret_cast<T*>(buf + zslot_f(p, 2) * N) + zslot_part(p, 2);
+  const int x = blockIdx.y, y0 = blockIdx.x * P;
+  if (threadIdx.x < 3 * P) {
+    const int p = threadIdx.x / 3, c = threadIdx.x % 3, y = y0 + p;
+    const int f = zslot_f(p, c), part = zslot_part(p, c);
+    T* row = reinterpret_cast<T*>(buf);
     for (int corner = 0; corner < 4; ++corner) {
       const int ox = corner >> 1, oy = corner & 1;
       const int key = ((x - ox + N) & (N - 1)) * N + ((y - oy + N) & (N - 1));
@@ -331,35 +289,32 @@ k_fwd_z_scatter(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>* __
       for (int s = s0; s < s1; ++s) {
         const T tx = bins.tx[s], ty = bins.ty[s], tz = bins.tz[s];
         const T wxy = (ox ? tx : (T)1 - tx) * (oy ? ty : (T)1 - ty);
-        const T gw = gsort[s] * wxy;
+        const T rc = c == 0 ? bins.rx[s] : (c == 1 ? bins.ry[s] : bins.rz[s]);
+        const T val = gsort[s] * wxy * rc;
         const int z0 = bins.iz[s], z1 = (z0 + 1) & (N - 1);
-        const T w0 = (T)1 - tz, w1 = tz;
-        const T cx = gw * bins.rx[s], cy = gw * bins.ry[s], cz = gw * bins.rz[s];
-        rowx[2 * z0] += cx * w0; rowx[2 * z1] += cx * w1;
-        rowy[2 * z0] += cy * w0; rowy[2 * z1] += cy * w1;
-        rowz[2 * z0] += cz * w0; rowz[2 * z1] += cz * w1;
+        row[2 * LAY::idx(z0, f) + part] += val * ((T)1 - tz);
+        row[2 * LAY::idx(z1, f) + part] += val * tz;
       }
     }
   }
   __syncthreads();
-  lds_fft<T, N, F, 1, N, true, kPassThreads, -1>(buf, twl);
+  lds_fft<T, N, F, LAY, kPassThreads, -1>(buf, twl);
   // Split each transform Z of a + i b into the half spectra
   //   A_k = (Z_k + conj Z_{N-k}) / 2,   B_k = (Z_k - conj Z_{N-k}) / (2 i).
   for (int idx = threadIdx.x; idx < F * H; idx += kPassThreads) {
     const int k = idx % H, f = idx / H;
     const int m = f / 3, r = f % 3;
-    const C* row = buf + f * N;
-    const C zk = row[k];
-    const C zm = row[(N - k) & (N - 1)];
+    const C zk = buf[LAY::idx(k, f)];
+    const C zm = buf[LAY::idx((N - k) & (N - 1), f)];
     const T half = (T)0.5;
     const C av = cmake<C>(half * (zk.x + zm.x), half * (zk.y - zm.y));
     const C bv = cmake<C>(half * (zk.y + zm.y), half * (zm.x - zk.x));
     if (r == 1) {
-      const size_t g0 = ((size_t)x * N + y0 + 2 * m) * H + k;
+      const size_t g0 = gofs<N>(x, y0 + 2 * m, k);
       gz[g0] = cscale(av, (T)k);
       gz[g0 + H] = cscale(bv, (T)k);
     } else {
-      const size_t g = ((size_t)x * N + y0 + 2 * m + (r == 2 ? 1 : 0)) * H + k;
+      const size_t g = gofs<N>(x, y0 + 2 * m + (r == 2 ? 1 : 0), k);
       gx[g] = av;
       gy[g] = bv;
     }
@@ -368,7 +323,7 @@ k_fwd_z_scatter(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>* __
 
 // ---------------------------------------------------------------------------
 // Forward pass 2 (along y): S1 = n_y FFT_y(Gy) + FFT_y(n_z Gz), S2 = FFT_y(Gx).
-// Tile: fixed x, kz chunk, all ky.  Grid (N, CHUNKS).
+// Tile: fixed x, kz chunk, all ky.
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ void __launch_bounds__(kPassThreads)
@@ -376,135 +331,141 @@ k_fwd_y(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, cons
         const cplx_t<T>* __restrict__ tw, cplx_t<T>* __restrict__ s1, cplx_t<T>* __restrict__ s2) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
-  constexpr int W = S::W, H = S::H;
-  __shared__ C tile[S::ELEMS];
+  using LAY = typename S::Row;
+  __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
   load_twiddles<T, N, kPassThreads>(twl, tw);
-  const int x = blockIdx.x, z0 = blockIdx.y * W;
+  const int x = blockIdx.y, z0 = blockIdx.x * S::W;
   C acc[S::EPT];
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, y = idx / W;
-      tile[y * W + w] = gy[((size_t)x * N + y) * H + z0 + w];
-    }
-  }
+  tile_elems<T, N>([&](int, int y, int w) { tile[LAY::idx(y, w)] = gy[gofs<N>(x, y, z0 + w)]; });
   __syncthreads();
-  lds_fft<T, N, W, W, 1, false, kPassThreads, -1>(tile, twl);
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, y = idx / W;
-      acc[e] = cscale(tile[y * W + w], (T)signed_freq(y, N));
-    }
-  }
+  lds_fft<T, N, S::W, LAY, kPassThreads, -1>(tile, twl);
+  tile_elems<T, N>([&](int e, int y, int w) { acc[e] = cscale(tile[LAY::idx(y, w)], (T)signed_freq(y, N)); });
   __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, y = idx / W;
-      tile[y * W + w] = gz[((size_t)x * N + y) * H + z0 + w];
-    }
-  }
+  tile_elems<T, N>([&](int, int y, int w) { tile[LAY::idx(y, w)] = gz[gofs<N>(x, y, z0 + w)]; });
   __syncthreads();
-  lds_fft<T, N, W, W, 1, false, kPassThreads, -1>(tile, twl);
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, y = idx / W;
-      s1[((size_t)x * N + y) * H + z0 + w] = cadd(acc[e], tile[y * W + w]);
-    }
-  }
+  lds_fft<T, N, S::W, LAY, kPassThreads, -1>(tile, twl);
+  tile_elems<T, N>([&](int e, int y, int w) { s1[gofs<N>(x, y, z0 + w)] = cadd(acc[e], tile[LAY::idx(y, w)]); });
   __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, y = idx / W;
-      tile[y * W + w] = gx[((size_t)x * N + y) * H + z0 + w];
-    }
-  }
+  tile_elems<T, N>([&](int, int y, int w) { tile[LAY::idx(y, w)] = gx[gofs<N>(x, y, z0 + w)]; });
   __syncthreads();
-  lds_fft<T, N, W, W, 1, false, kPassThreads, -1>(tile, twl);
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, y = idx / W;
-      s2[((size_t)x * N + y) * H + z0 + w] = tile[y * W + w];
-    }
-  }
+  lds_fft<T, N, S::W, LAY, kPassThreads, -1>(tile, twl);
+  tile_elems<T, N>([&](int, int y, int w) { s2[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
 }
 
 // ---------------------------------------------------------------------------
-// Forward pass 3 (along x) with the adjoint multiply and the prior gradient:
-//   G = 2 dhat / sigma^2 - 2 i kfac (FFT_x(S1) + n_x FFT_x(S2)),  0 on
-//   excluded modes.  Tile: fixed ky, kz chunk, all kx.  Grid (N, CHUNKS).
+// Pass along x at the end of a gradient evaluation, optionally fused with the
+// leapfrog update of the modes and the first inverse pass of the next
+// evaluation (the tile is the same: fixed ky, kz chunk, all kx).
+//
+// Gradient (complex convention, 0 on excluded modes):
+//   G = 2 dhat / sigma^2 - 2 i kfac (FFT_x(S1) + n_x FFT_x(S2))
+// Modes:
+//   kXGrad  : write G.
+//   kXFirst : G read from `gcache` (gradient at the current point); kick
+//             p -= (eps/2) G, drift q += eps (sigma^2/2) p, then inverse pass 1
+//             of the new q (A, B, prior energy).
+//   kXMid   : G from S1, S2; kick p -= eps G (two half kicks merged), drift,
+//             inverse pass 1 of the new q.
+//   kXLast  : G from S1, S2; kick p -= (eps/2) G; write G to `gcache`.
+// (eq:hamilton integrated by kick-drift-kick leapfrog, mass matrix eq:M_ab.)
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+enum XMode { kXGrad = 0, kXFirst = 1, kXMid = 2, kXLast = 3 };
+
+template <typename T, int N, int MODE>
 __global__ void __launch_bounds__(kPassThreads)
-k_fwd_x_grad(const cplx_t<T>* __restrict__ s1, const cplx_t<T>* __restrict__ s2, const double2* __restrict__ modes,
-             ModeTables tab, const cplx_t<T>* __restrict__ tw, double2* __restrict__ grad) {
+k_x_pass(const cplx_t<T>* __restrict__ s1, const cplx_t<T>* __restrict__ s2, double2* __restrict__ modes,
+         double2* __restrict__ mom, double2* __restrict__ gcache, ModeTables tab, const cplx_t<T>* __restrict__ tw,
+         const double* __restrict__ eps_ptr, cplx_t<T>* __restrict__ outA, cplx_t<T>* __restrict__ outB,
+         double* __restrict__ prior_part) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
-  constexpr int W = S::W, H = S::H;
-  __shared__ C tile[S::ELEMS];
+  using LAY = typename S::Row;
+  constexpr bool kFromSpectra = MODE != kXFirst;
+  constexpr bool kDrift = MODE == kXFirst || MODE == kXMid;
+  __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
+  __shared__ double red[kPassThreads / 64];
   load_twiddles<T, N, kPassThreads>(twl, tw);
-  const int y = blockIdx.x, z0 = blockIdx.y * W;
+  const int y = blockIdx.y, z0 = blockIdx.x * S::W;
   const int sy = signed_freq(y, N);
   C acc[S::EPT];
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, x = idx / W;
-      tile[x * W + w] = s2[((size_t)x * N + y) * H + z0 + w];
-    }
+  if constexpr (kFromSpectra) {
+    tile_elems<T, N>([&](int, int x, int w) { tile[LAY::idx(x, w)] = s2[gofs<N>(x, y, z0 + w)]; });
+    __syncthreads();
+    lds_fft<T, N, S::W, LAY, kPassThreads, -1>(tile, twl);
+    tile_elems<T, N>([&](int e, int x, int w) { acc[e] = cscale(tile[LAY::idx(x, w)], (T)signed_freq(x, N)); });
+    __syncthreads();
+    tile_elems<T, N>([&](int, int x, int w) { tile[LAY::idx(x, w)] = s1[gofs<N>(x, y, z0 + w)]; });
+    __syncthreads();
+    lds_fft<T, N, S::W, LAY, kPassThreads, -1>(tile, twl);
+  } else {
+    (void)s1;
+    (void)s2;
   }
-  __syncthreads();
-  lds_fft<T, N, W, W, 1, false, kPassThreads, -1>(tile, twl);
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, x = idx / W;
-      acc[e] = cscale(tile[x * W + w], (T)signed_freq(x, N));
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, x = idx / W;
-      tile[x * W + w] = s1[((size_t)x * N + y) * H + z0 + w];
-    }
-  }
-  __syncthreads();
-  lds_fft<T, N, W, W, 1, false, kPassThreads, -1>(tile, twl);
-#pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (idx < S::ELEMS) {
-      const int w = idx % W, x = idx / W, kz = z0 + w;
-      const int sx = signed_freq(x, N);
-      const size_t g = ((size_t)x * N + y) * H + kz;
-      double2 out = make_double2(0.0, 0.0);
-      if (retained(sx, sy, kz, N)) {
-        const int n2 = sx * sx + sy * sy + kz * kz;
-        const C tv = cadd(acc[e], tile[x * W + w]);
+  const double eps = MODE == kXGrad ? 0.0 : eps_ptr[0];
+  const double hk = MODE == kXMid ? eps : 0.5 * eps;
+  double prior = 0.0;
+  // B-input of the next inverse pass (n_x times the A-input), kept in registers
+  C bin[S::EPT];
+  tile_elems<T, N>([&](int e, int x, int w) {
+    const int kz = z0 + w, sx = signed_freq(x, N);
+    const size_t g = gofs<N>(x, y, kz);
+    const bool keep = retained(sx, sy, kz, N);
+    const int n2 = sx * sx + sy * sy + kz * kz;
+    double2 G = make_double2(0.0, 0.0);
+    if constexpr (kFromSpectra) {
+      if (keep) {
+        const C tv = cadd(acc[e], tile[LAY::idx(x, w)]);
         const double2 q = modes[g];
         const double iv2 = 2.0 * tab.inv_var[n2], kf2 = 2.0 * tab.kfac[n2];
         // -2 i kfac t = (2 kfac t.y, -2 kfac t.x)
-        out = make_double2(iv2 * q.x + kf2 * (double)tv.y, iv2 * q.y - kf2 * (double)tv.x);
+        G = make_double2(iv2 * q.x + kf2 * (double)tv.y, iv2 * q.y - kf2 * (double)tv.x);
       }
-      grad[g] = out;
+    } else {
+      G = gcache[g];
     }
+    if constexpr (MODE == kXGrad || MODE == kXLast) gcache[g] = G;
+    if constexpr (MODE != kXGrad) {
+      double2 p = mom[g];
+      p.x -= hk * G.x;
+      p.y -= hk * G.y;
+      mom[g] = p;
+      if constexpr (kDrift) {
+        double2 a = make_double2(0.0, 0.0);
+        if (keep) {
+          double2 q = modes[g];
+          const double c = eps * (0.5 * tab.var[n2]);
+          q.x += c * p.x;
+          q.y += c * p.y;
+          modes[g] = q;
+          prior += (kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * tab.inv_var[n2];
+          const double kf = tab.kfac[n2];
+          a = make_double2(-kf * q.y, kf * q.x);      // i kfac q
+        }
+        acc[e] = cconvert<C>(a);                       // A-input (acc is free now)
+        bin[e] = cconvert<C>(make_double2((double)sx * a.x, (double)sx * a.y));
+      }
+    }
+  });
+  if constexpr (kDrift) {
+    const double ps = block_sum(prior, red);
+    if (threadIdx.x == 0) prior_part[blockIdx.y * gridDim.x + blockIdx.x] = ps;
+    __syncthreads();
+    tile_elems<T, N>([&](int e, int x, int w) { tile[LAY::idx(x, w)] = acc[e]; });
+    __syncthreads();
+    lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
+    tile_elems<T, N>([&](int, int x, int w) { outA[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
+    __syncthreads();
+    tile_elems<T, N>([&](int e, int x, int w) { tile[LAY::idx(x, w)] = bin[e]; });
+    __syncthreads();
+    lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
+    tile_elems<T, N>([&](int, int x, int w) { outB[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
+  } else {
+    (void)outA;
+    (void)outB;
+    (void)prior_part;
+    (void)bin;
   }
 }
 

@@ -215,3 +215,27 @@ def hmc_run(plans, q_modes, q_dist, q_snl, *, n_iter, n_leapfrog, eps0, seed, wa
                                    _ipp(aa) if aa else None,
                                    ctypes.cast(eps_out, c_double_p) if want_eps else None))
     return list(eps_out) if want_eps else None
+
+
+# -- measurement ---------------------------------------------------------------
+
+PROFILE_KERNELS = {"bin": 0, "inv_x": 1, "inv_y": 2, "inv_z_gather": 3, "like": 4, "fwd_z_scatter": 5,
+                   "fwd_y": 6, "fwd_x": 7}
+
+
+class KernelTimer:
+    """HIP-event timing of one kernel kind of a plan (hamlet_profile_*)."""
+
+    def __init__(self, plan, kind):
+        self.plan = plan
+        self.kind = int(kind)
+
+    def start(self):
+        _capi.check(_capi.load().hamlet_profile_start(ctypes.c_void_p(self.plan.handle), self.kind))
+
+    def stop(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _capi.check(_capi.load().hamlet_profile_stop(ctypes.c_void_p(self.plan.handle), ctypes.byref(ms),
+                                                     ctypes.byref(n)))
+        return ms.value, n.value

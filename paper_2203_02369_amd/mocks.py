@@ -139,7 +139,25 @@ def _gaussian_field(rng, n_grid, box, pk):
     half = n_grid // 2
     bad = (np.abs(kx) == half) | (np.abs(ky) == half) | (kz == half) | (kmag == 0)
     dhat[bad] = 0.0
-    return dhat, (kx, ky, kz)
+    return hermitian_half(dhat), (kx, ky, kz)
+
+
+def hermitian_half(dhat):
+    """Make the kz = 0 plane of a half spectrum exactly Hermitian.
+
+    The entry (kx, ky, 0) with ky < N/2 taken as signed ky < 0, or ky = 0 and
+    kx past N/2, is set to the conjugate of its partner (-kx, -ky, 0).
+    """
+    out = np.array(dhat, dtype=np.complex128, copy=True)
+    n = out.shape[0]
+    f = np.fft.fftfreq(n, d=1.0 / n).astype(np.int64)
+    plane = out[:, :, 0]
+    neg = (-np.arange(n)) % n
+    partner = np.conj(plane[np.ix_(neg, neg)])
+    mirror = (f[None, :] < 0) | ((f[None, :] == 0) & (f[:, None] < 0))
+    plane[mirror] = partner[mirror]
+    out[:, :, 0] = plane
+    return out
 
 
 def _linear_velocity(dhat, kvec, n_grid, box, f_growth):
