@@ -135,14 +135,15 @@ def main():
     # ---- roofline of the dominant kernel ------------------------------------
     # k_x_pass: the x pass of every evaluation, fused with the leapfrog update
     # and the next inverse pass 1.  Algorithmic bytes in units of one complex64
-    # spectral array c (8 N^2 N/2 bytes; complex128 arrays count 2c):
-    #   plain gradient (1 per run):        S1, S2, q in; G out          =  6c
-    #   first step of a trajectory:        G, p, q in; p, q, A, B out   = 12c
-    #   middle steps (L - 1 per traj.):    S1, S2, p, q in; p, q, A, B  = 12c
-    #   last step:                         S1, S2, p, q in; p, G out    = 10c
+    # spectral array c (8 N^2 N/2 bytes; complex128 arrays count 2c; the FP64
+    # per-mode prior variance sigma_k^2 counts 1c):
+    #   plain gradient (1 per run):        S1, S2, q, var in; G out           =  7c
+    #   first step of a trajectory:        G, p, q, var in; p, q, A, B out    = 13c
+    #   middle steps (L - 1 per traj.):    S1, S2, p, q, var in; p, q, A, B   = 13c
+    #   last step:                         S1, S2, p, q, var in; p, G out     = 11c
     nm = n * n * (n // 2)
     c32 = 8 * nm
-    x_bytes = c32 * (6 + args.steps * (12 + 12 * (L - 1) + 10))
+    x_bytes = c32 * (7 + args.steps * (13 + 13 * (L - 1) + 11))
     x_launches = 1 + args.steps * (L + 1)
     assert kern_launches == x_launches, (kern_launches, x_launches)
     avg_ms = kern_ms / kern_launches

@@ -85,7 +85,7 @@ struct hamlet_plan {
   hipStream_t stream = nullptr;
   Workspace ws;
   // tables
-  double *kfac = nullptr, *inv_var = nullptr, *var = nullptr, *hist = nullptr;
+  double *var = nullptr, *mvar = nullptr, *hist = nullptr;
   void* tw = nullptr;
   // catalogue
   double *rhat = nullptr, *mu = nullptr, *smu = nullptr, *cz = nullptr, *scz = nullptr;
@@ -164,7 +164,8 @@ static Cosmo cosmo_view(hamlet_plan* pl) {
 
 static ModeTables tables_view(hamlet_plan* pl) {
   ModeTables t;
-  t.kfac = pl->kfac; t.inv_var = pl->inv_var; t.var = pl->var;
+  t.var = pl->mvar;
+  t.kfac0 = kH0 * pl->f / ((double)pl->n * pl->n * pl->n * (2.0 * M_PI / pl->box));
   return t;
 }
 
@@ -309,9 +310,8 @@ static void carve(hamlet_plan* pl) {
   const size_t npk = 3 * (size_t)(n / 2) * (n / 2) + 1;
   const size_t real = pl->prec == HAMLET_FP64 ? 8 : 4;
   const size_t ng = std::max(pl->n_gal, 1);
-  pl->kfac = ws.take<double>(npk);
-  pl->inv_var = ws.take<double>(npk);
   pl->var = ws.take<double>(npk);
+  pl->mvar = ws.take<double>(nm);
   pl->hist = ws.take<double>(std::max(pl->n_hist, 1));
   pl->tw = ws.take<char>(2 * real * n);
   pl->rhat = ws.take<double>(3 * ng);
@@ -439,12 +439,9 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
   const double kf = 2.0 * M_PI / pl->box;
   const double n3 = (double)n * n * n;
   const double vol = pl->box * pl->box * pl->box;
-  std::vector<double> kfac(npk), var(npk), ivar(npk);
-  for (size_t j = 0; j < npk; ++j) {
-    kfac[j] = j == 0 ? 0.0 : kH0 * pl->f / (n3 * kf * (double)j);
-    var[j] = n3 * n3 / vol * d->pk_n2[j];
-    ivar[j] = var[j] > 0 ? 1.0 / var[j] : 0.0;
-  }
+  std::vector<double> var(npk);
+  for (size_t j = 0; j < npk; ++j) var[j] = n3 * n3 / vol * d->pk_n2[j];
+  (void)kf;
   // Twiddles exp(-2 pi i m / N), computed in long double and rounded once.
   std::vector<double> twd(2 * n);
   std::vector<float> twf(2 * n);
@@ -456,9 +453,9 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
     twf[2 * m + 1] = (float)sinl(ang);
   }
   hipStream_t st = pl->stream;
-  HIP_TRY(hipMemcpyAsync(pl->kfac, kfac.data(), npk * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(pl->var, var.data(), npk * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(pl->inv_var, ivar.data(), npk * 8, hipMemcpyHostToDevice, st));
+  k_fill_mode_var<<<blocks_for(pl->modes_count(), kEltThreads), kEltThreads, 0, st>>>(pl->mvar, pl->var, n);
+  LAUNCH_CHECK();
   if (pl->prec == HAMLET_FP64)
     HIP_TRY(hipMemcpyAsync(pl->tw, twd.data(), twd.size() * 8, hipMemcpyHostToDevice, st));
   else

@@ -77,6 +77,16 @@ __device__ __forceinline__ bool is_mirror(const ModeIdx& m) {
   return m.kz == 0 && (m.sy < 0 || (m.sy == 0 && m.sx < 0));
 }
 
+// sigma_k^2 per mode from the n^2-indexed table (plan set-up only).
+__global__ void __launch_bounds__(kEltThreads)
+k_fill_mode_var(double* __restrict__ mvar, const double* __restrict__ var_n2, int n) {
+  const size_t total = (size_t)n * n * (n / 2);
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const ModeIdx m = mode_idx(g, n);
+  mvar[g] = retained(m.sx, m.sy, m.kz, n) ? var_n2[m.sx * m.sx + m.sy * m.sy + m.kz * m.kz] : 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // Momentum refresh p ~ N(0, M).
 // ---------------------------------------------------------------------------
@@ -92,8 +102,7 @@ k_momenta_modes(double2* __restrict__ p, ModeTables tab, int n, uint64_t seed, u
     size_t src = g;
     if (mir) src = ((size_t)((n - m.x) & (n - 1)) * n + ((n - m.y) & (n - 1))) * (n / 2);
     const double2 z = normal_pair(draw_words(seed, iteration, kPurposeModes, src));
-    const int n2 = m.sx * m.sx + m.sy * m.sy + m.kz * m.kz;
-    const double sc = sqrt(2.0 * tab.inv_var[n2]);
+    const double sc = sqrt(2.0 * inv_or_zero(tab.var[g]));
     out = make_double2(sc * z.x, mir ? -sc * z.y : sc * z.y);
   }
   p[g] = out;
@@ -121,9 +130,8 @@ k_kinetic_modes(const double2* __restrict__ p, ModeTables tab, int n, double* __
   for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (size_t)gridDim.x * blockDim.x) {
     const ModeIdx m = mode_idx(g, n);
     if (retained(m.sx, m.sy, m.kz, n)) {
-      const int n2 = m.sx * m.sx + m.sy * m.sy + m.kz * m.kz;
       const double2 v = p[g];
-      acc += (m.kz == 0 ? 0.125 : 0.25) * tab.var[n2] * (v.x * v.x + v.y * v.y);
+      acc += (m.kz == 0 ? 0.125 : 0.25) * tab.var[g] * (v.x * v.x + v.y * v.y);
     }
   }
   const double s = block_sum(acc, red);

@@ -35,8 +35,9 @@ constexpr int kPassThreads = 256;
 template <typename T, int N> struct PassShape {
   using C = cplx_t<T>;
   static constexpr int WMAX = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int PMAX = sizeof(T) == 4 ? 8 : 4;
   static constexpr int W = WMAX < N / 2 ? WMAX : N / 2;     // kz columns per strided tile
-  static constexpr int P = WMAX < N ? WMAX : N;             // pencils per z tile
+  static constexpr int P = PMAX < N ? PMAX : N;             // pencils per z tile
   static constexpr int H = N / 2;
   static constexpr int CHUNKS = H / W;
   static constexpr int ELEMS = N * W;
@@ -46,12 +47,16 @@ template <typename T, int N> struct PassShape {
   using Pen = PencilLayout<N>;
 };
 
-// Tables indexed by n^2 = nx^2 + ny^2 + nz^2 (0 .. 3 (N/2)^2).
+// Per-mode constants.  sigma_k^2 = N^6 P(|k|) / V is stored per mode in the
+// mode layout (0 on excluded modes), so every pass reads it coalesced
+// instead of gathering from a table indexed by n^2; the multiplier factor
+// kfac = H0 f / (N^3 k_f n^2) is computed from n^2.
 struct ModeTables {
-  const double* kfac;      // H0 f / (N^3 k_f n^2), 0 at n^2 = 0
-  const double* inv_var;   // 1 / sigma_k^2, 0 where P = 0
-  const double* var;       // sigma_k^2 = N^6 P / V
+  const double* var;       // sigma_k^2 per mode, [kx][ky][kz < N/2]
+  double kfac0;            // H0 f / (N^3 k_f)
 };
+__device__ __forceinline__ double mode_kfac(const ModeTables& t, int n2) { return n2 > 0 ? t.kfac0 / (double)n2 : 0.0; }
+__device__ __forceinline__ double inv_or_zero(double v) { return v > 0.0 ? 1.0 / v : 0.0; }
 
 // Deterministic block sum of a double (wave64 shuffles, then LDS).
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -108,14 +113,15 @@ k_inv_x(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* __re
     const int kz = z0 + w, sx = signed_freq(x, N);
     if (!retained(sx, sy, kz, N)) return make_double2(0.0, 0.0);
     const double2 q = modes[gofs<N>(x, y, kz)];
-    const double kf = tab.kfac[sx * sx + sy * sy + kz * kz] * (scale_x != 0.0 ? scale_x * sx : 1.0);
+    const double kf = mode_kfac(tab, sx * sx + sy * sy + kz * kz) * (scale_x != 0.0 ? scale_x * sx : 1.0);
     return make_double2(-kf * q.y, kf * q.x);
   };
   tile_elems<T, N>([&](int, int x, int w) {
     const int kz = z0 + w, sx = signed_freq(x, N);
     if (retained(sx, sy, kz, N)) {
-      const double2 q = modes[gofs<N>(x, y, kz)];
-      prior += (kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * tab.inv_var[sx * sx + sy * sy + kz * kz];
+      const size_t g = gofs<N>(x, y, kz);
+      const double2 q = modes[g];
+      prior += (kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(tab.var[g]);
     }
     tile[LAY::idx(x, w)] = cconvert<C>(ain(x, w, 0.0));
   });
@@ -413,12 +419,13 @@ k_x_pass(const cplx_t<T>* __restrict__ s1, const cplx_t<T>* __restrict__ s2, dou
     const size_t g = gofs<N>(x, y, kz);
     const bool keep = retained(sx, sy, kz, N);
     const int n2 = sx * sx + sy * sy + kz * kz;
+    const double var = keep ? tab.var[g] : 0.0;
     double2 G = make_double2(0.0, 0.0);
     if constexpr (kFromSpectra) {
       if (keep) {
         const C tv = cadd(acc[e], tile[LAY::idx(x, w)]);
         const double2 q = modes[g];
-        const double iv2 = 2.0 * tab.inv_var[n2], kf2 = 2.0 * tab.kfac[n2];
+        const double iv2 = 2.0 * inv_or_zero(var), kf2 = 2.0 * mode_kfac(tab, n2);
         // -2 i kfac t = (2 kfac t.y, -2 kfac t.x)
         G = make_double2(iv2 * q.x + kf2 * (double)tv.y, iv2 * q.y - kf2 * (double)tv.x);
       }
@@ -435,12 +442,12 @@ k_x_pass(const cplx_t<T>* __restrict__ s1, const cplx_t<T>* __restrict__ s2, dou
         double2 a = make_double2(0.0, 0.0);
         if (keep) {
           double2 q = modes[g];
-          const double c = eps * (0.5 * tab.var[n2]);
+          const double c = eps * (0.5 * var);
           q.x += c * p.x;
           q.y += c * p.y;
           modes[g] = q;
-          prior += (kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * tab.inv_var[n2];
-          const double kf = tab.kfac[n2];
+          prior += (kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(var);
+          const double kf = mode_kfac(tab, n2);
           a = make_double2(-kf * q.y, kf * q.x);      // i kfac q
         }
         acc[e] = cconvert<C>(a);                       // A-input (acc is free now)
