@@ -180,6 +180,7 @@ static hamlet_status eval_impl(hamlet_plan* pl, double2* q, double* qd, double* 
                                double* gs, double* psi, const EvalMode& em) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
+  using TH = PassThreads<T, N>;
   hipStream_t st = pl->stream;
   const int n = pl->n_gal;
   const Catalogue cat = catalogue_view(pl);
@@ -213,16 +214,21 @@ static hamlet_status eval_impl(hamlet_plan* pl, double2* q, double* qd, double* 
     prof_after(pl, HAMLET_K_BIN);
     LAUNCH_CHECK();
   }
-  const dim3 gs_xy(S::CHUNKS, N), gs_z(N / S::P, N);
+  const dim3 gs_xy(S::CHUNKS, N);
   if (!leap)
     TIMED(pl, HAMLET_K_INV_X,
-          k_inv_x<T, N><<<gs_xy, kPassThreads, 0, st>>>(q, tab, tw, (C*)pl->a, (C*)pl->b, pl->prior_part));
-  TIMED(pl, HAMLET_K_INV_Y,
-        k_inv_y<T, N><<<gs_xy, kPassThreads, 0, st>>>((const C*)pl->a, (const C*)pl->b, tw, (C*)pl->v0,
-                                                       (C*)pl->v1, (C*)pl->v2));
-  TIMED(pl, HAMLET_K_INV_Z,
-        k_inv_z_gather<T, N><<<gs_z, kPassThreads, 0, st>>>((const C*)pl->v0, (const C*)pl->v1,
-                                                             (const C*)pl->v2, tw, bins, (C*)pl->part));
+          k_inv_x<T, N, TH::XY><<<gs_xy, TH::XY, 0, st>>>(q, tab, tw, (C*)pl->a, (C*)pl->b, pl->prior_part));
+  using SL = XSlabs<N>;
+  const dim3 gs_xy_slab(S::CHUNKS, SL::SIZE), gs_z_slab(N / S::P, SL::SIZE);
+  for (int sl = 0; sl < SL::COUNT; ++sl) {
+    const int x0 = sl * SL::SIZE;
+    TIMED(pl, HAMLET_K_INV_Y,
+          k_inv_y<T, N, TH::XY><<<gs_xy_slab, TH::XY, 0, st>>>((const C*)pl->a, (const C*)pl->b, tw, (C*)pl->v0,
+                                                                (C*)pl->v1, (C*)pl->v2, x0));
+    TIMED(pl, HAMLET_K_INV_Z,
+          k_inv_z_gather<T, N, TH::Z><<<gs_z_slab, TH::Z, 0, st>>>((const C*)pl->v0, (const C*)pl->v1,
+                                                                    (const C*)pl->v2, tw, bins, (C*)pl->part, x0));
+  }
   LAUNCH_CHECK();
   if (n > 0) {
     LikeOut lo;
@@ -235,29 +241,32 @@ static hamlet_status eval_impl(hamlet_plan* pl, double2* q, double* qd, double* 
   }
   k_finalize<<<1, 256, 0, st>>>(pl->prior_part, pl->n_prior_part, pl->like_part, n > 0 ? pl->n_like_part : 0, psi,
                                 gs, qs, lf_s);
-  TIMED(pl, HAMLET_K_FWD_Z,
-        k_fwd_z_scatter<T, N><<<gs_z, kPassThreads, 0, st>>>((const T*)pl->gsort, bins, tw, (C*)pl->v0,
-                                                              (C*)pl->v1, (C*)pl->v2));
-  TIMED(pl, HAMLET_K_FWD_Y,
-        k_fwd_y<T, N><<<gs_xy, kPassThreads, 0, st>>>((const C*)pl->v0, (const C*)pl->v1, (const C*)pl->v2, tw,
-                                                       (C*)pl->a, (C*)pl->b));
+  for (int sl = 0; sl < SL::COUNT; ++sl) {
+    const int x0 = sl * SL::SIZE;
+    TIMED(pl, HAMLET_K_FWD_Z,
+          k_fwd_z_scatter<T, N, TH::Z><<<gs_z_slab, TH::Z, 0, st>>>((const T*)pl->gsort, bins, tw, (C*)pl->v0,
+                                                                     (C*)pl->v1, (C*)pl->v2, x0));
+    TIMED(pl, HAMLET_K_FWD_Y,
+          k_fwd_y<T, N, TH::XY><<<gs_xy_slab, TH::XY, 0, st>>>((const C*)pl->v0, (const C*)pl->v1,
+                                                                (const C*)pl->v2, tw, (C*)pl->a, (C*)pl->b, x0));
+  }
   const C* s1 = (const C*)pl->a;
   const C* s2 = (const C*)pl->b;
   if (em.x_mode == kXGrad) {
     TIMED(pl, HAMLET_K_FWD_X,
-          (k_x_pass<T, N, kXGrad><<<gs_xy, kPassThreads, 0, st>>>(s1, s2, q, nullptr, g, tab, tw, nullptr, nullptr,
+          (k_x_pass<T, N, kXGrad, TH::X><<<gs_xy, TH::X, 0, st>>>(s1, s2, q, nullptr, g, tab, tw, nullptr, nullptr,
                                                                     nullptr, nullptr)));
   } else if (em.x_mode == kXMid) {
     // S1, S2 live in a, b and are read by the same tile that writes the next
     // A, B: the x pass writes them to v0, v1 and the plan swaps the roles.
     TIMED(pl, HAMLET_K_FWD_X,
-          (k_x_pass<T, N, kXMid><<<gs_xy, kPassThreads, 0, st>>>(s1, s2, q, em.p_modes, nullptr, tab, tw, em.eps,
+          (k_x_pass<T, N, kXMid, TH::X><<<gs_xy, TH::X, 0, st>>>(s1, s2, q, em.p_modes, nullptr, tab, tw, em.eps,
                                                                    (C*)pl->v0, (C*)pl->v1, pl->prior_part)));
     std::swap(pl->a, pl->v0);
     std::swap(pl->b, pl->v1);
   } else {
     TIMED(pl, HAMLET_K_FWD_X,
-          (k_x_pass<T, N, kXLast><<<gs_xy, kPassThreads, 0, st>>>(s1, s2, q, em.p_modes, g, tab, tw, em.eps, nullptr,
+          (k_x_pass<T, N, kXLast, TH::X><<<gs_xy, TH::X, 0, st>>>(s1, s2, q, em.p_modes, g, tab, tw, em.eps, nullptr,
                                                                     nullptr, nullptr)));
   }
   LAUNCH_CHECK();
@@ -270,9 +279,10 @@ template <typename T, int N>
 static hamlet_status first_impl(hamlet_plan* pl, double2* q, double2* p_modes, const double* eps) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
+  using TH = PassThreads<T, N>;
   const dim3 gs_xy(S::CHUNKS, N);
   TIMED(pl, HAMLET_K_FWD_X,
-        (k_x_pass<T, N, kXFirst><<<gs_xy, kPassThreads, 0, pl->stream>>>(
+        (k_x_pass<T, N, kXFirst, TH::X><<<gs_xy, TH::X, 0, pl->stream>>>(
             nullptr, nullptr, q, p_modes, pl->gcache, tables_view(pl), (const C*)pl->tw, eps, (C*)pl->a, (C*)pl->b,
             pl->prior_part)));
   LAUNCH_CHECK();

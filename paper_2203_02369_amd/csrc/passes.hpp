@@ -32,6 +32,21 @@ namespace hamlet {
 
 constexpr int kPassThreads = 256;
 
+// Threads per block of each pass kind (tuned on the MI355X).
+template <typename T, int N> struct PassThreads {
+  static constexpr int XY = 256;                        // k_inv_x, k_inv_y, k_fwd_y
+  static constexpr int X = sizeof(T) == 4 ? 512 : 256;   // k_x_pass
+  static constexpr int Z = sizeof(T) == 4 ? 512 : 256;   // k_inv_z_gather, k_fwd_z_scatter
+};
+
+// The y and z passes of each direction may run slab by slab in x so that the
+// arrays handed from one to the other stay in the memory-side cache; at
+// 256^3 smaller launches cost more than that saves, so one slab is used.
+template <int N> struct XSlabs {
+  static constexpr int COUNT = 1;
+  static constexpr int SIZE = N / COUNT;
+};
+
 template <typename T, int N> struct PassShape {
   using C = cplx_t<T>;
   static constexpr int WMAX = sizeof(T) == 4 ? 16 : 8;
@@ -41,7 +56,6 @@ template <typename T, int N> struct PassShape {
   static constexpr int H = N / 2;
   static constexpr int CHUNKS = H / W;
   static constexpr int ELEMS = N * W;
-  static constexpr int EPT = (ELEMS + kPassThreads - 1) / kPassThreads;
   static constexpr int F = 3 * P / 2;                       // complex transforms per z tile
   using Row = RowLayout<C, W>;
   using Pen = PencilLayout<N>;
@@ -75,15 +89,17 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 // Visit this thread's elements (a = index along the FFT axis, w = column)
 // of a strided tile.
-template <typename T, int N, typename Fn>
+template <typename T, int N, int NT, typename Fn>
 __device__ __forceinline__ void tile_elems(Fn&& fn) {
   using S = PassShape<T, N>;
+  constexpr int EPT = (S::ELEMS + NT - 1) / NT;
 #pragma unroll
-  for (int e = 0; e < S::EPT; ++e) {
-    const int idx = threadIdx.x + e * kPassThreads;
-    if (S::ELEMS % kPassThreads == 0 || idx < S::ELEMS) fn(e, idx / S::W, idx % S::W);
+  for (int e = 0; e < EPT; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (S::ELEMS % NT == 0 || idx < S::ELEMS) fn(e, idx / S::W, idx % S::W);
   }
 }
+template <typename T, int N, int NT> constexpr int elems_per_thread() { return (PassShape<T, N>::ELEMS + NT - 1) / NT; }
 
 // Global offset of (i, j, kz) in an [N][N][N/2] array.
 template <int N> __device__ __forceinline__ size_t gofs(int i, int j, int kz) {
@@ -94,8 +110,8 @@ template <int N> __device__ __forceinline__ size_t gofs(int i, int j, int kz) {
 // Inverse pass 1 (along x): multiplier, prior energy, two spectral outputs.
 // Tile: fixed ky, kz chunk, all kx.
 // ---------------------------------------------------------------------------
-template <typename T, int N>
-__global__ void __launch_bounds__(kPassThreads)
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT)
 k_inv_x(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* __restrict__ tw,
         cplx_t<T>* __restrict__ outA, cplx_t<T>* __restrict__ outB, double* __restrict__ prior_part) {
   using C = cplx_t<T>;
@@ -103,8 +119,8 @@ k_inv_x(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* __re
   using LAY = typename S::Row;
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
-  __shared__ double red[kPassThreads / 64];
-  load_twiddles<T, N, kPassThreads>(twl, tw);
+  __shared__ double red[NT / 64];
+  load_twiddles<T, N, NT>(twl, tw);
   const int y = blockIdx.y, z0 = blockIdx.x * S::W;
   const int sy = signed_freq(y, N);
   double prior = 0.0;
@@ -116,7 +132,7 @@ k_inv_x(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* __re
     const double kf = mode_kfac(tab, sx * sx + sy * sy + kz * kz) * (scale_x != 0.0 ? scale_x * sx : 1.0);
     return make_double2(-kf * q.y, kf * q.x);
   };
-  tile_elems<T, N>([&](int, int x, int w) {
+  tile_elems<T, N, NT>([&](int, int x, int w) {
     const int kz = z0 + w, sx = signed_freq(x, N);
     if (retained(sx, sy, kz, N)) {
       const size_t g = gofs<N>(x, y, kz);
@@ -128,45 +144,45 @@ k_inv_x(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* __re
   const double ps = block_sum(prior, red);
   if (threadIdx.x == 0) prior_part[blockIdx.y * gridDim.x + blockIdx.x] = ps;
   __syncthreads();
-  lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
-  tile_elems<T, N>([&](int, int x, int w) { outA[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
+  lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
+  tile_elems<T, N, NT>([&](int, int x, int w) { outA[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
   __syncthreads();
-  tile_elems<T, N>([&](int, int x, int w) { tile[LAY::idx(x, w)] = cconvert<C>(ain(x, w, 1.0)); });
+  tile_elems<T, N, NT>([&](int, int x, int w) { tile[LAY::idx(x, w)] = cconvert<C>(ain(x, w, 1.0)); });
   __syncthreads();
-  lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
-  tile_elems<T, N>([&](int, int x, int w) { outB[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
+  lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
+  tile_elems<T, N, NT>([&](int, int x, int w) { outB[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
 }
 
 // ---------------------------------------------------------------------------
 // Inverse pass 2 (along y).  Tile: fixed x, kz chunk, all ky.
 // ---------------------------------------------------------------------------
-template <typename T, int N>
-__global__ void __launch_bounds__(kPassThreads)
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT)
 k_inv_y(const cplx_t<T>* __restrict__ inA, const cplx_t<T>* __restrict__ inB, const cplx_t<T>* __restrict__ tw,
-        cplx_t<T>* __restrict__ vx, cplx_t<T>* __restrict__ vy, cplx_t<T>* __restrict__ vz) {
+        cplx_t<T>* __restrict__ vx, cplx_t<T>* __restrict__ vy, cplx_t<T>* __restrict__ vz, int x0) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Row;
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
-  load_twiddles<T, N, kPassThreads>(twl, tw);
-  const int x = blockIdx.y, z0 = blockIdx.x * S::W;
-  tile_elems<T, N>([&](int, int y, int w) { tile[LAY::idx(y, w)] = inB[gofs<N>(x, y, z0 + w)]; });
+  load_twiddles<T, N, NT>(twl, tw);
+  const int x = x0 + blockIdx.y, z0 = blockIdx.x * S::W;
+  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = inB[gofs<N>(x, y, z0 + w)]; });
   __syncthreads();
-  lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
-  tile_elems<T, N>([&](int, int y, int w) { vx[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
+  lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
+  tile_elems<T, N, NT>([&](int, int y, int w) { vx[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
   __syncthreads();
-  tile_elems<T, N>([&](int, int y, int w) {
+  tile_elems<T, N, NT>([&](int, int y, int w) {
     tile[LAY::idx(y, w)] = cscale(inA[gofs<N>(x, y, z0 + w)], (T)signed_freq(y, N));
   });
   __syncthreads();
-  lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
-  tile_elems<T, N>([&](int, int y, int w) { vy[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
+  lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
+  tile_elems<T, N, NT>([&](int, int y, int w) { vy[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
   __syncthreads();
-  tile_elems<T, N>([&](int, int y, int w) { tile[LAY::idx(y, w)] = inA[gofs<N>(x, y, z0 + w)]; });
+  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = inA[gofs<N>(x, y, z0 + w)]; });
   __syncthreads();
-  lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
-  tile_elems<T, N>([&](int, int y, int w) { vz[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
+  lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
+  tile_elems<T, N, NT>([&](int, int y, int w) { vz[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
 }
 
 // Galaxies binned by CIC column (ix, iy) of their lower corner, in sorted
@@ -198,21 +214,21 @@ __device__ __forceinline__ int zslot_part(int p, int c) {
 //   Pc = sum_c rhat_c [(1 - tz) v_c(z0) + tz v_c(z1)],  Qc = sum_c rhat_c [v_c(z1) - v_c(z0)]
 // into part[4 s + corner], corner = 2 (x - ix) + (y - iy).
 // ---------------------------------------------------------------------------
-template <typename T, int N>
-__global__ void __launch_bounds__(kPassThreads)
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT)
 k_inv_z_gather(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ vy, const cplx_t<T>* __restrict__ vz,
-               const cplx_t<T>* __restrict__ tw, Binned<T> bins, cplx_t<T>* __restrict__ part) {
+               const cplx_t<T>* __restrict__ tw, Binned<T> bins, cplx_t<T>* __restrict__ part, int x0) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Pen;
   constexpr int P = S::P, H = S::H, F = S::F;
   __shared__ C buf[LAY::size(F)];
   __shared__ C twl[N];
-  load_twiddles<T, N, kPassThreads>(twl, tw);
-  const int x = blockIdx.y, y0 = blockIdx.x * P;
+  load_twiddles<T, N, NT>(twl, tw);
+  const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
   // Build Z = A + i B with A, B the Hermitian half spectra of the two real
   // pencils of each transform (Nyquist entry zero, DC entries real).
-  for (int idx = threadIdx.x; idx < F * H; idx += kPassThreads) {
+  for (int idx = threadIdx.x; idx < F * H; idx += NT) {
     const int k = idx % H, f = idx / H;
     const int m = f / 3, r = f % 3;
     C av, bv;
@@ -234,9 +250,9 @@ k_inv_z_gather(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ v
     }
   }
   __syncthreads();
-  lds_fft<T, N, F, LAY, kPassThreads, +1>(buf, twl);
+  lds_fft<T, N, F, LAY, NT, +1>(buf, twl);
   // Gather: (pencil, corner, lane) per thread; lane strides the bucket.
-  constexpr int LANES = kPassThreads / (4 * P);
+  constexpr int LANES = NT / (4 * P);
   {
     const int t = threadIdx.x;
     const int pc = t % (4 * P), lane = t / (4 * P);
@@ -270,20 +286,20 @@ k_inv_z_gather(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ v
 //   G_c(x_j) = sum_i g_i rhat_ic W_i(x_j)  (adjoint of the gather)
 // Outputs Gx, Gy and n_z Gz on kz in [0, N/2).  Grid (N / P, N).
 // ---------------------------------------------------------------------------
-template <typename T, int N>
-__global__ void __launch_bounds__(kPassThreads)
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT)
 k_fwd_z_scatter(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>* __restrict__ tw,
-                cplx_t<T>* __restrict__ gx, cplx_t<T>* __restrict__ gy, cplx_t<T>* __restrict__ gz) {
+                cplx_t<T>* __restrict__ gx, cplx_t<T>* __restrict__ gy, cplx_t<T>* __restrict__ gz, int x0) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Pen;
   constexpr int P = S::P, H = S::H, F = S::F;
   __shared__ C buf[LAY::size(F)];
   __shared__ C twl[N];
-  load_twiddles<T, N, kPassThreads>(twl, tw);
-  for (int i = threadIdx.x; i < LAY::size(F); i += kPassThreads) buf[i] = cmake<C>((T)0, (T)0);
+  load_twiddles<T, N, NT>(twl, tw);
+  for (int i = threadIdx.x; i < LAY::size(F); i += NT) buf[i] = cmake<C>((T)0, (T)0);
   __syncthreads();
-  const int x = blockIdx.y, y0 = blockIdx.x * P;
+  const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
   if (threadIdx.x < 3 * P) {
     const int p = threadIdx.x / 3, c = threadIdx.x % 3, y = y0 + p;
     const int f = zslot_f(p, c), part = zslot_part(p, c);
@@ -304,10 +320,10 @@ k_fwd_z_scatter(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>* __
     }
   }
   __syncthreads();
-  lds_fft<T, N, F, LAY, kPassThreads, -1>(buf, twl);
+  lds_fft<T, N, F, LAY, NT, -1>(buf, twl);
   // Split each transform Z of a + i b into the half spectra
   //   A_k = (Z_k + conj Z_{N-k}) / 2,   B_k = (Z_k - conj Z_{N-k}) / (2 i).
-  for (int idx = threadIdx.x; idx < F * H; idx += kPassThreads) {
+  for (int idx = threadIdx.x; idx < F * H; idx += NT) {
     const int k = idx % H, f = idx / H;
     const int m = f / 3, r = f % 3;
     const C zk = buf[LAY::idx(k, f)];
@@ -331,32 +347,33 @@ k_fwd_z_scatter(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>* __
 // Forward pass 2 (along y): S1 = n_y FFT_y(Gy) + FFT_y(n_z Gz), S2 = FFT_y(Gx).
 // Tile: fixed x, kz chunk, all ky.
 // ---------------------------------------------------------------------------
-template <typename T, int N>
-__global__ void __launch_bounds__(kPassThreads)
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT)
 k_fwd_y(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, const cplx_t<T>* __restrict__ gz,
-        const cplx_t<T>* __restrict__ tw, cplx_t<T>* __restrict__ s1, cplx_t<T>* __restrict__ s2) {
+        const cplx_t<T>* __restrict__ tw, cplx_t<T>* __restrict__ s1, cplx_t<T>* __restrict__ s2, int x0) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Row;
+  constexpr int EPT = elems_per_thread<T, N, NT>();
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
-  load_twiddles<T, N, kPassThreads>(twl, tw);
-  const int x = blockIdx.y, z0 = blockIdx.x * S::W;
-  C acc[S::EPT];
-  tile_elems<T, N>([&](int, int y, int w) { tile[LAY::idx(y, w)] = gy[gofs<N>(x, y, z0 + w)]; });
+  load_twiddles<T, N, NT>(twl, tw);
+  const int x = x0 + blockIdx.y, z0 = blockIdx.x * S::W;
+  C acc[EPT];
+  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = gy[gofs<N>(x, y, z0 + w)]; });
   __syncthreads();
-  lds_fft<T, N, S::W, LAY, kPassThreads, -1>(tile, twl);
-  tile_elems<T, N>([&](int e, int y, int w) { acc[e] = cscale(tile[LAY::idx(y, w)], (T)signed_freq(y, N)); });
+  lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
+  tile_elems<T, N, NT>([&](int e, int y, int w) { acc[e] = cscale(tile[LAY::idx(y, w)], (T)signed_freq(y, N)); });
   __syncthreads();
-  tile_elems<T, N>([&](int, int y, int w) { tile[LAY::idx(y, w)] = gz[gofs<N>(x, y, z0 + w)]; });
+  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = gz[gofs<N>(x, y, z0 + w)]; });
   __syncthreads();
-  lds_fft<T, N, S::W, LAY, kPassThreads, -1>(tile, twl);
-  tile_elems<T, N>([&](int e, int y, int w) { s1[gofs<N>(x, y, z0 + w)] = cadd(acc[e], tile[LAY::idx(y, w)]); });
+  lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
+  tile_elems<T, N, NT>([&](int e, int y, int w) { s1[gofs<N>(x, y, z0 + w)] = cadd(acc[e], tile[LAY::idx(y, w)]); });
   __syncthreads();
-  tile_elems<T, N>([&](int, int y, int w) { tile[LAY::idx(y, w)] = gx[gofs<N>(x, y, z0 + w)]; });
+  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = gx[gofs<N>(x, y, z0 + w)]; });
   __syncthreads();
-  lds_fft<T, N, S::W, LAY, kPassThreads, -1>(tile, twl);
-  tile_elems<T, N>([&](int, int y, int w) { s2[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
+  lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
+  tile_elems<T, N, NT>([&](int, int y, int w) { s2[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -378,8 +395,8 @@ k_fwd_y(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, cons
 // ---------------------------------------------------------------------------
 enum XMode { kXGrad = 0, kXFirst = 1, kXMid = 2, kXLast = 3 };
 
-template <typename T, int N, int MODE>
-__global__ void __launch_bounds__(kPassThreads)
+template <typename T, int N, int MODE, int NT>
+__global__ void __launch_bounds__(NT)
 k_x_pass(const cplx_t<T>* __restrict__ s1, const cplx_t<T>* __restrict__ s2, double2* __restrict__ modes,
          double2* __restrict__ mom, double2* __restrict__ gcache, ModeTables tab, const cplx_t<T>* __restrict__ tw,
          const double* __restrict__ eps_ptr, cplx_t<T>* __restrict__ outA, cplx_t<T>* __restrict__ outB,
@@ -391,20 +408,20 @@ k_x_pass(const cplx_t<T>* __restrict__ s1, const cplx_t<T>* __restrict__ s2, dou
   constexpr bool kDrift = MODE == kXFirst || MODE == kXMid;
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
-  __shared__ double red[kPassThreads / 64];
-  load_twiddles<T, N, kPassThreads>(twl, tw);
+  __shared__ double red[NT / 64];
+  load_twiddles<T, N, NT>(twl, tw);
   const int y = blockIdx.y, z0 = blockIdx.x * S::W;
   const int sy = signed_freq(y, N);
-  C acc[S::EPT];
+  C acc[elems_per_thread<T, N, NT>()];
   if constexpr (kFromSpectra) {
-    tile_elems<T, N>([&](int, int x, int w) { tile[LAY::idx(x, w)] = s2[gofs<N>(x, y, z0 + w)]; });
+    tile_elems<T, N, NT>([&](int, int x, int w) { tile[LAY::idx(x, w)] = s2[gofs<N>(x, y, z0 + w)]; });
     __syncthreads();
-    lds_fft<T, N, S::W, LAY, kPassThreads, -1>(tile, twl);
-    tile_elems<T, N>([&](int e, int x, int w) { acc[e] = cscale(tile[LAY::idx(x, w)], (T)signed_freq(x, N)); });
+    lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
+    tile_elems<T, N, NT>([&](int e, int x, int w) { acc[e] = cscale(tile[LAY::idx(x, w)], (T)signed_freq(x, N)); });
     __syncthreads();
-    tile_elems<T, N>([&](int, int x, int w) { tile[LAY::idx(x, w)] = s1[gofs<N>(x, y, z0 + w)]; });
+    tile_elems<T, N, NT>([&](int, int x, int w) { tile[LAY::idx(x, w)] = s1[gofs<N>(x, y, z0 + w)]; });
     __syncthreads();
-    lds_fft<T, N, S::W, LAY, kPassThreads, -1>(tile, twl);
+    lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
   } else {
     (void)s1;
     (void)s2;
@@ -413,8 +430,8 @@ k_x_pass(const cplx_t<T>* __restrict__ s1, const cplx_t<T>* __restrict__ s2, dou
   const double hk = MODE == kXMid ? eps : 0.5 * eps;
   double prior = 0.0;
   // B-input of the next inverse pass (n_x times the A-input), kept in registers
-  C bin[S::EPT];
-  tile_elems<T, N>([&](int e, int x, int w) {
+  C bin[elems_per_thread<T, N, NT>()];
+  tile_elems<T, N, NT>([&](int e, int x, int w) {
     const int kz = z0 + w, sx = signed_freq(x, N);
     const size_t g = gofs<N>(x, y, kz);
     const bool keep = retained(sx, sy, kz, N);
@@ -459,15 +476,15 @@ k_x_pass(const cplx_t<T>* __restrict__ s1, const cplx_t<T>* __restrict__ s2, dou
     const double ps = block_sum(prior, red);
     if (threadIdx.x == 0) prior_part[blockIdx.y * gridDim.x + blockIdx.x] = ps;
     __syncthreads();
-    tile_elems<T, N>([&](int e, int x, int w) { tile[LAY::idx(x, w)] = acc[e]; });
+    tile_elems<T, N, NT>([&](int e, int x, int w) { tile[LAY::idx(x, w)] = acc[e]; });
     __syncthreads();
-    lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
-    tile_elems<T, N>([&](int, int x, int w) { outA[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
+    lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
+    tile_elems<T, N, NT>([&](int, int x, int w) { outA[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
     __syncthreads();
-    tile_elems<T, N>([&](int e, int x, int w) { tile[LAY::idx(x, w)] = bin[e]; });
+    tile_elems<T, N, NT>([&](int e, int x, int w) { tile[LAY::idx(x, w)] = bin[e]; });
     __syncthreads();
-    lds_fft<T, N, S::W, LAY, kPassThreads, +1>(tile, twl);
-    tile_elems<T, N>([&](int, int x, int w) { outB[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
+    lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
+    tile_elems<T, N, NT>([&](int, int x, int w) { outB[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
   } else {
     (void)outA;
     (void)outB;
