@@ -26,6 +26,25 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of k_x_pass<float, 256> per launch, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, then WRITE_SIZE) of this script at 256^3 with 30 000
+# points, each scaled by what the counter reads for a plain 1 GiB device copy
+# (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Bytes read and
+# written per launch for the plain-gradient, first, middle and last variants.
+# Valid only for the kernel sources they were taken on (hash below).
+X_TRAFFIC_SOURCES_SHA1 = "c9c21d198864a969f83a20944df204a62f37b4a1"
+X_TRAFFIC = {"grad": (334203820, 134217728), "first": (468463685, 401674965),
+             "mid": (468598666, 401676500), "last": (468428700, 268435456)}
+
+
+def kernel_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("passes.hpp", "fft.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2203_02369_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -42,6 +61,8 @@ def parse():
     ap.add_argument("--n-gal", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 1 GiB device-to-device copy (reference for traffic counters)")
     return ap.parse_args()
 
 
@@ -59,6 +80,13 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+        del src, dst
     t0 = time.time()
     mock = mocks.paper_scale_256(n_gal=args.n_gal, n_grid=args.n_grid)
     log("mock %d^3, %d points in %.1fs" % (mock.n_grid, mock.n_gal, time.time() - t0))
@@ -149,9 +177,14 @@ def main():
     avg_ms = kern_ms / kern_launches
     per_launch = x_bytes / x_launches
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if n == 256 and kernel_sources_sha1() == X_TRAFFIC_SOURCES_SHA1:
+        t = X_TRAFFIC
+        tot = sum(t["grad"]) + args.steps * (sum(t["first"]) + (L - 1) * sum(t["mid"]) + sum(t["last"]))
+        traffic = int(tot / x_launches)
     roofline = {"bound": "hbm", "kernel": "k_x_pass (x FFT + gradient + leapfrog update + next inverse x FFT)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": int(per_launch), "avg_launch_ms": round(avg_ms, 4), "launches": kern_launches}
 
     # ---- CPU baseline: the oracle on the host cores --------------------------
