@@ -124,6 +124,17 @@ hamlet_status hamlet_logpost_grad(hamlet_plan* const* plans, int32_t n_plans,
                                   void* const* g_modes, double* const* g_dist, double* const* g_snl,
                                   double* const* psi);
 
+/* As hamlet_logpost_grad, but the mode gradient is taken with respect to the
+ * stored entries one by one (the convention of automatic differentiation,
+ * where both members of a Hermitian pair on the kz = 0 plane are separate
+ * variables): equal to the hamlet_logpost_grad gradient except on the kz = 0
+ * plane, where it is half of it.  Ψ and the other outputs are the same. */
+hamlet_status hamlet_logpost_grad_entries(hamlet_plan* const* plans, int32_t n_plans,
+                                          const void* const* q_modes, const double* const* q_dist,
+                                          const double* const* q_snl,
+                                          void* const* g_modes, double* const* g_dist, double* const* g_snl,
+                                          double* const* psi);
+
 /* n_steps[j] kick-drift-kick leapfrog steps of size eps[j] (host arrays) of
  * Hamilton's equations (eq:hamilton) with the mass matrix of eq:M_ab, from
  * (q, p) in place (device pointers as above; p_* have the layout of q_*).

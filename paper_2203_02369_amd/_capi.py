@@ -71,6 +71,8 @@ SIGNATURES = {
                                                    ctypes.POINTER(ctypes.c_size_t)]),
     "hamlet_logpost_grad": (ctypes.c_int, [c_void_pp, ctypes.c_int32, c_void_pp, c_double_pp, c_double_pp,
                                            c_void_pp, c_double_pp, c_double_pp, c_double_pp]),
+    "hamlet_logpost_grad_entries": (ctypes.c_int, [c_void_pp, ctypes.c_int32, c_void_pp, c_double_pp, c_double_pp,
+                                                   c_void_pp, c_double_pp, c_double_pp, c_double_pp]),
     "hamlet_leapfrog": (ctypes.c_int, [c_void_pp, ctypes.c_int32, c_double_p, c_int32_p, c_void_pp, c_double_pp,
                                        c_double_pp, c_void_pp, c_double_pp, c_double_pp, c_double_pp]),
     "hamlet_hmc_run": (ctypes.c_int, [c_void_pp, ctypes.c_int32, ctypes.POINTER(HmcOpts), c_void_pp, c_double_pp,

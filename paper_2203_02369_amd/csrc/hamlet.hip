@@ -69,6 +69,7 @@ struct hamlet_plan;
 // kXLast; the gradient of a kXLast evaluation goes to g as the cache).
 struct EvalMode {
   int x_mode = kXGrad;
+  double plane_scale = 1.0;   // kXGrad: factor on the kz = 0 plane of the gradient
   double2* p_modes = nullptr;
   double* p_dist = nullptr;
   double* p_snl = nullptr;
@@ -255,19 +256,19 @@ static hamlet_status eval_impl(hamlet_plan* pl, double2* q, double* qd, double* 
   if (em.x_mode == kXGrad) {
     TIMED(pl, HAMLET_K_FWD_X,
           (k_x_pass<T, N, kXGrad, TH::X><<<gs_xy, TH::X, 0, st>>>(s1, s2, q, nullptr, g, tab, tw, nullptr, nullptr,
-                                                                    nullptr, nullptr)));
+                                                                    nullptr, nullptr, em.plane_scale)));
   } else if (em.x_mode == kXMid) {
     // S1, S2 live in a, b and are read by the same tile that writes the next
     // A, B: the x pass writes them to v0, v1 and the plan swaps the roles.
     TIMED(pl, HAMLET_K_FWD_X,
           (k_x_pass<T, N, kXMid, TH::X><<<gs_xy, TH::X, 0, st>>>(s1, s2, q, em.p_modes, nullptr, tab, tw, em.eps,
-                                                                   (C*)pl->v0, (C*)pl->v1, pl->prior_part)));
+                                                                   (C*)pl->v0, (C*)pl->v1, pl->prior_part, 1.0)));
     std::swap(pl->a, pl->v0);
     std::swap(pl->b, pl->v1);
   } else {
     TIMED(pl, HAMLET_K_FWD_X,
           (k_x_pass<T, N, kXLast, TH::X><<<gs_xy, TH::X, 0, st>>>(s1, s2, q, em.p_modes, g, tab, tw, em.eps, nullptr,
-                                                                    nullptr, nullptr)));
+                                                                    nullptr, nullptr, 1.0)));
   }
   LAUNCH_CHECK();
   return HAMLET_OK;
@@ -284,7 +285,7 @@ static hamlet_status first_impl(hamlet_plan* pl, double2* q, double2* p_modes, c
   TIMED(pl, HAMLET_K_FWD_X,
         (k_x_pass<T, N, kXFirst, TH::X><<<gs_xy, TH::X, 0, pl->stream>>>(
             nullptr, nullptr, q, p_modes, pl->gcache, tables_view(pl), (const C*)pl->tw, eps, (C*)pl->a, (C*)pl->b,
-            pl->prior_part)));
+            pl->prior_part, 1.0)));
   LAUNCH_CHECK();
   return HAMLET_OK;
 }
@@ -609,10 +610,12 @@ static hamlet_status check_plans(hamlet_plan* const* plans, int32_t n_plans) {
   return HAMLET_OK;
 }
 
-extern "C" hamlet_status hamlet_logpost_grad(hamlet_plan* const* plans, int32_t n_plans,
-                                             const void* const* q_modes, const double* const* q_dist,
-                                             const double* const* q_snl, void* const* g_modes,
-                                             double* const* g_dist, double* const* g_snl, double* const* psi) {
+static hamlet_status logpost_grad_impl(hamlet_plan* const* plans, int32_t n_plans, const void* const* q_modes,
+                                       const double* const* q_dist, const double* const* q_snl,
+                                       void* const* g_modes, double* const* g_dist, double* const* g_snl,
+                                       double* const* psi, double plane_scale) {
+  EvalMode em;
+  em.plane_scale = plane_scale;
   hamlet_status st = check_plans(plans, n_plans);
   if (st != HAMLET_OK) return st;
   if (!q_modes || !q_snl || !g_modes || !g_snl || !psi) return fail(HAMLET_EINVAL, "NULL argument array");
@@ -623,10 +626,25 @@ extern "C" hamlet_status hamlet_logpost_grad(hamlet_plan* const* plans, int32_t 
     if (pl->n_gal > 0 && (!q_dist || !g_dist || !q_dist[j] || !g_dist[j]))
       return fail(HAMLET_EINVAL, "plan %d: NULL distance buffer", j);
     st = pl->eval(pl, (double2*)q_modes[j], pl->n_gal ? (double*)q_dist[j] : nullptr, (double*)q_snl[j],
-                  (double2*)g_modes[j], pl->n_gal ? g_dist[j] : nullptr, g_snl[j], psi[j], EvalMode());
+                  (double2*)g_modes[j], pl->n_gal ? g_dist[j] : nullptr, g_snl[j], psi[j], em);
     if (st != HAMLET_OK) return st;
   }
   return HAMLET_OK;
+}
+
+extern "C" hamlet_status hamlet_logpost_grad(hamlet_plan* const* plans, int32_t n_plans,
+                                             const void* const* q_modes, const double* const* q_dist,
+                                             const double* const* q_snl, void* const* g_modes,
+                                             double* const* g_dist, double* const* g_snl, double* const* psi) {
+  return logpost_grad_impl(plans, n_plans, q_modes, q_dist, q_snl, g_modes, g_dist, g_snl, psi, 1.0);
+}
+
+extern "C" hamlet_status hamlet_logpost_grad_entries(hamlet_plan* const* plans, int32_t n_plans,
+                                                     const void* const* q_modes, const double* const* q_dist,
+                                                     const double* const* q_snl, void* const* g_modes,
+                                                     double* const* g_dist, double* const* g_snl,
+                                                     double* const* psi) {
+  return logpost_grad_impl(plans, n_plans, q_modes, q_dist, q_snl, g_modes, g_dist, g_snl, psi, 0.5);
 }
 
 extern "C" hamlet_status hamlet_leapfrog(hamlet_plan* const* plans, int32_t n_plans, const double* eps,

@@ -384,7 +384,7 @@ k_fwd_y(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, cons
 // Gradient (complex convention, 0 on excluded modes):
 //   G = 2 dhat / sigma^2 - 2 i kfac (FFT_x(S1) + n_x FFT_x(S2))
 // Modes:
-//   kXGrad  : write G.
+//   kXGrad  : write G (times plane_scale on the kz = 0 plane).
 //   kXFirst : G read from `gcache` (gradient at the current point); kick
 //             p -= (eps/2) G, drift q += eps (sigma^2/2) p, then inverse pass 1
 //             of the new q (A, B, prior energy).
@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(NT)
 k_x_pass(const cplx_t<T>* __restrict__ s1, const cplx_t<T>* __restrict__ s2, double2* __restrict__ modes,
          double2* __restrict__ mom, double2* __restrict__ gcache, ModeTables tab, const cplx_t<T>* __restrict__ tw,
          const double* __restrict__ eps_ptr, cplx_t<T>* __restrict__ outA, cplx_t<T>* __restrict__ outB,
-         double* __restrict__ prior_part) {
+         double* __restrict__ prior_part, double plane_scale) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Row;
@@ -449,7 +449,12 @@ k_x_pass(const cplx_t<T>* __restrict__ s1, const cplx_t<T>* __restrict__ s2, dou
     } else {
       G = gcache[g];
     }
-    if constexpr (MODE == kXGrad || MODE == kXLast) gcache[g] = G;
+    if constexpr (MODE == kXGrad) {
+      // plane_scale 0.5: gradient per stored entry (each Hermitian partner of
+      // the kz = 0 plane taken as its own variable carries half)
+      gcache[g] = kz == 0 ? make_double2(plane_scale * G.x, plane_scale * G.y) : G;
+    }
+    if constexpr (MODE == kXLast) gcache[g] = G;
     if constexpr (MODE != kXGrad) {
       double2 p = mom[g];
       p.x -= hk * G.x;

@@ -162,8 +162,9 @@ def _plans(plans):
     return plans, _vp([p.handle for p in plans])
 
 
-def logpost_grad(plans, q_modes, q_dist, q_snl, g_modes, g_dist, g_snl, psi):
-    """Psi and its gradient for a batch of plans (hamlet_logpost_grad)."""
+def logpost_grad(plans, q_modes, q_dist, q_snl, g_modes, g_dist, g_snl, psi, per_entry=False):
+    """Psi and its gradient for a batch of plans (hamlet_logpost_grad, or
+    hamlet_logpost_grad_entries with per_entry=True)."""
     plans, hp = _plans(plans)
     args = []
     for kind, name, ts in (("modes", "q_modes", q_modes), ("dist", "q_dist", q_dist), ("scalar", "q_snl", q_snl),
@@ -171,8 +172,9 @@ def logpost_grad(plans, q_modes, q_dist, q_snl, g_modes, g_dist, g_snl, psi):
                            ("scalar", "psi", psi)):
         args.append([_check(t, p, kind, name) for t, p in zip(ts, plans)])
     lib = _capi.load()
-    _capi.check(lib.hamlet_logpost_grad(hp, len(plans), _vp(args[0]), _dpp(args[1]), _dpp(args[2]),
-                                        _vp(args[3]), _dpp(args[4]), _dpp(args[5]), _dpp(args[6])))
+    fn = lib.hamlet_logpost_grad_entries if per_entry else lib.hamlet_logpost_grad
+    _capi.check(fn(hp, len(plans), _vp(args[0]), _dpp(args[1]), _dpp(args[2]),
+                   _vp(args[3]), _dpp(args[4]), _dpp(args[5]), _dpp(args[6])))
 
 
 def leapfrog(plans, eps, n_steps, q_modes, q_dist, q_snl, p_modes, p_dist, p_snl, psi):
