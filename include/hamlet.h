@@ -34,6 +34,10 @@
  * Streams: every call is asynchronous on the plan's HIP stream (the stream
  * given at creation); only hamlet_plan_create and hamlet_plan_destroy
  * synchronise.  Calls on plans that share a stream run in call order.
+ * Plans of one call with the same N and precision are batched: their
+ * kernels run as shared launches on the stream of the first of them, ordered
+ * after and before the other plans' streams with events.  A plan may appear
+ * once per call.
  *
  * Errors: every entry point returns a hamlet_status; the message of the last
  * non-OK status of the calling thread is hamlet_last_error().  A parameter
@@ -148,22 +152,33 @@ hamlet_status hamlet_leapfrog(hamlet_plan* const* plans, int32_t n_plans, const 
 typedef struct {
   int32_t n_iter;           /* HMC iterations (trajectories) */
   int32_t n_leapfrog;       /* leapfrog steps per trajectory */
-  int32_t warmup;           /* first `warmup` iterations adapt eps by dual averaging */
+  int32_t warmup;           /* the chain's first `warmup` iterations adapt eps by dual averaging
+                               (the adapted step is fixed after iteration warmup - 1) */
   int32_t jitter_eps;       /* 1: step of iteration t is eps (0.9 + 0.2 u_t) */
   double eps0;              /* initial step */
   double target_accept;     /* dual-averaging target (Section 3.3: 0.65) */
-  uint64_t seed;            /* Philox4x32-10 key */
+  uint64_t seed;            /* Philox4x32-10 key of plan j's chain: seed + j (or seeds[j]) */
+  int32_t resume;           /* 1: continue each plan's chain (step, adaptation, iteration count,
+                               cached gradient) from its last hamlet_hmc_run; q_* must still
+                               hold that chain's state.  A chain with no such run (or after
+                               hamlet_leapfrog on its plan) starts fresh. */
+  const uint64_t* seeds;    /* host, n_plans keys, or NULL */
 } hamlet_hmc_opts;
 
 /* Runs the chain of Section 3.2 for each plan: fresh momenta p ~ N(0, M)
- * per trajectory (Philox4x32-10, counter (index, 0, iteration, purpose)),
- * n_leapfrog steps, Metropolis-Hastings test ln u < -dH (a rejected
- * trajectory repeats the state), dual averaging of eps during warm-up.
+ * per trajectory (Philox4x32-10, counter (index, 0, iteration, purpose),
+ * iteration = the chain's own count), n_leapfrog steps, Metropolis-Hastings
+ * test ln u < -dH (a rejected trajectory repeats the state), dual averaging
+ * of eps during the chain's first `warmup` iterations.
  * q_* (device, in/out): start state in, last state out.
  * mode_sum[j] (device, may be NULL): sum over post-warm-up iterations of the
  *   chain's mode state (eq:int_mc numerator); accumulated onto its contents.
- * dh[j], accepted[j] (device, may be NULL): n_iter per plan.
- * eps_out (host, may be NULL): n_plans, the step after warm-up (synchronises). */
+ * dh[j], accepted[j] (device, may be NULL): indexed by the chain's iteration
+ *   count, so n_iter entries for a fresh chain (more when resumed).
+ * eps_out (host, may be NULL): n_plans, the step after warm-up (synchronises).
+ * Batches: the plans of one call with the same N and precision share every
+ * kernel launch (up to 32 plans per launch); each chain's numbers do not
+ * depend on which other chains share its launches. */
 hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_plans, const hamlet_hmc_opts* opts,
                              void* const* q_modes, double* const* q_dist, double* const* q_snl,
                              void* const* mode_sum, double* const* dh, int32_t* const* accepted,

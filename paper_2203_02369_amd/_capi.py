@@ -59,6 +59,8 @@ class HmcOpts(ctypes.Structure):
         ("eps0", ctypes.c_double),
         ("target_accept", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("resume", ctypes.c_int32),
+        ("seeds", ctypes.POINTER(ctypes.c_uint64)),
     ]
 
 

@@ -27,6 +27,16 @@ struct Cosmo {
   double dmax;             // c / (3 Omega_0 H0): domain of zbar(d)
 };
 
+// Optional leapfrog update of a block of coordinates right after their
+// gradient is known: p -= kick * eps * g, then (drift) q += eps * minv * p.
+struct LeapUpdate {
+  double* p = nullptr;       // momenta (nullptr: no update)
+  const double* eps = nullptr;
+  double kick = 0.0;         // 1 for merged half kicks, 0.5 for the last half kick
+  int drift = 0;
+  double minv = 0.0;         // inverse mass
+};
+
 // A distance in the domain of the posterior: zbar(d) real and d > 0.
 __device__ __forceinline__ bool dist_ok(double d, const Cosmo& cm) { return d > 0.0 && d < cm.dmax; }
 
@@ -36,9 +46,8 @@ __device__ __forceinline__ bool dist_ok(double d, const Cosmo& cm) { return d > 
 // plain FP64 evaluation.  Invalid distances are replaced by 1 Mpc/h for the
 // geometry (their Psi is +inf anyway), which keeps every index in range.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kGalThreads)
-k_bin_count(const double* __restrict__ dist, Catalogue cat, Cosmo cm, int n_grid,
+__device__ __forceinline__ void
+bin_count_body(const double* __restrict__ dist, Catalogue cat, Cosmo cm, int n_grid,
             int* __restrict__ count, int* __restrict__ key, int* __restrict__ cell_z, double* __restrict__ frac) {
 #pragma clang fp contract(off)
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -93,8 +102,8 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* wsum, int* total
   return x - v + wsum[wid];
 }
 
-__global__ void __launch_bounds__(kScanTile)
-k_bin_scan_tiles(const int* __restrict__ count, int* __restrict__ off, int* __restrict__ bsum, int nkeys) {
+__device__ __forceinline__ void
+bin_scan_tiles_body(const int* __restrict__ count, int* __restrict__ off, int* __restrict__ bsum, int nkeys) {
   __shared__ int wsum[kScanTile / 64];
   __shared__ int total;
   const int k = blockIdx.x * kScanTile + threadIdx.x;
@@ -104,8 +113,8 @@ k_bin_scan_tiles(const int* __restrict__ count, int* __restrict__ off, int* __re
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(kScanTile)
-k_bin_scan_add(int* __restrict__ count, int* __restrict__ off, int* __restrict__ cursor,
+__device__ __forceinline__ void
+bin_scan_add_body(int* __restrict__ count, int* __restrict__ off, int* __restrict__ cursor,
                const int* __restrict__ bsum, int nkeys) {
   __shared__ int base;
   if (threadIdx.x == 0) {
@@ -124,8 +133,8 @@ k_bin_scan_add(int* __restrict__ count, int* __restrict__ off, int* __restrict__
   }
 }
 
-__global__ void __launch_bounds__(kGalThreads)
-k_bin_place(const int* __restrict__ key, int* __restrict__ cursor, int* __restrict__ slot_gid, int n) {
+__device__ __forceinline__ void
+bin_place_body(const int* __restrict__ key, int* __restrict__ cursor, int* __restrict__ slot_gid, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int s = atomicAdd(&cursor[key[i]], 1);
@@ -135,10 +144,11 @@ k_bin_place(const int* __restrict__ key, int* __restrict__ cursor, int* __restri
 // Per bucket: order members by galaxy id (placement order is racy), then
 // write the sorted per-galaxy records used by the z passes.
 template <typename T>
-__global__ void __launch_bounds__(kGalThreads)
-k_bin_sort(const int* __restrict__ off, int* __restrict__ slot_gid, const int* __restrict__ cell_z,
-           const double* __restrict__ frac, Catalogue cat, int nkeys,
-           T* rx, T* ry, T* rz, T* tx, T* ty, T* tz, int* iz, int* gid) {
+__device__ __forceinline__ void
+bin_sort_body(const int* __restrict__ off, int* __restrict__ slot_gid, const int* __restrict__ cell_z,
+              const double* __restrict__ frac, Catalogue cat, int nkeys, T* __restrict__ rx, T* __restrict__ ry,
+              T* __restrict__ rz, T* __restrict__ tx, T* __restrict__ ty, T* __restrict__ tz,
+              int* __restrict__ iz) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nkeys) return;
   const int s0 = off[k], s1 = off[k + 1];
@@ -150,7 +160,6 @@ k_bin_sort(const int* __restrict__ off, int* __restrict__ slot_gid, const int* _
   }
   for (int s = s0; s < s1; ++s) {
     const int i = slot_gid[s];
-    gid[s] = i;
     rx[s] = (T)cat.rhat[3 * i + 0];
     ry[s] = (T)cat.rhat[3 * i + 1];
     rz[s] = (T)cat.rhat[3 * i + 2];
@@ -177,19 +186,9 @@ struct LikeOut {
   double* part;       // 3 per block: Psi, dPsi/ds, invalid
 };
 
-// Optional leapfrog update of a block of coordinates right after their
-// gradient is known: p -= kick * eps * g, then (drift) q += eps * minv * p.
-struct LeapUpdate {
-  double* p = nullptr;       // momenta (nullptr: no update)
-  const double* eps = nullptr;
-  double kick = 0.0;         // 1 for merged half kicks, 0.5 for the last half kick
-  int drift = 0;
-  double minv = 0.0;         // inverse mass
-};
-
 template <typename T>
-__global__ void __launch_bounds__(kGalThreads)
-k_like(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const double* __restrict__ frac,
+__device__ __forceinline__ void
+like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const double* __restrict__ frac,
        double* __restrict__ dist, const double* __restrict__ snl_q, Catalogue cat, Cosmo cm,
        T* __restrict__ gsort, LikeOut out, LeapUpdate lf) {
   __shared__ double red[kGalThreads / 64];
@@ -262,8 +261,8 @@ k_like(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const do
 
 // Final deterministic sums: Psi = prior + sum of galaxy terms (+inf when a
 // distance left the domain or Psi is not finite); dPsi/ds.
-__global__ void __launch_bounds__(256)
-k_finalize(const double* __restrict__ prior_part, int n_prior, const double* __restrict__ like_part, int n_like,
+__device__ __forceinline__ void
+finalize_body(const double* __restrict__ prior_part, int n_prior, const double* __restrict__ like_part, int n_like,
            double* __restrict__ psi_out, double* __restrict__ gs_out, double* __restrict__ snl_q, LeapUpdate lf) {
   __shared__ double red[4];
   double a = 0.0, b = 0.0, c = 0.0;
@@ -287,6 +286,100 @@ k_finalize(const double* __restrict__ prior_part, int n_prior, const double* __r
       if (lf.drift) snl_q[0] = snl_q[0] + e * lf.minv * pv;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Shared launches: blockIdx.z selects the plan; galaxy grids cover the
+// largest catalogue of the batch and each plan ignores blocks past its own.
+// ---------------------------------------------------------------------------
+template <typename T, int N> __device__ __forceinline__ Catalogue catalogue(const Ws<T, N>& w, int n_gal) {
+  const PlanConst& pc = w.pc();
+  Catalogue c;
+  c.n = n_gal;
+  c.rhat = w.rhat(); c.mu = w.mu(); c.sigma_mu = w.smu(); c.cz = w.cz(); c.sigma_cz = w.scz();
+  c.hist = w.hist(n_gal);
+  c.n_hist = pc.n_hist;
+  c.hist_w = pc.hist_w;
+  return c;
+}
+
+template <typename T, int N> __device__ __forceinline__ Cosmo cosmo(const Ws<T, N>& w) {
+  const PlanConst& pc = w.pc();
+  Cosmo c;
+  c.om = pc.om; c.h = pc.h; c.box = pc.box; c.spacing = pc.spacing; c.dmax = pc.dmax;
+  return c;
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(kGalThreads) k_bin_count(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  bin_count_body(k.st.qd, catalogue(k.w, k.n_gal), cosmo(k.w), N, k.w.count(), k.w.key(), k.w.cellz(), k.w.frac());
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(kScanTile) k_bin_scan_tiles(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  bin_scan_tiles_body(k.w.count(), k.w.off(), k.w.bsum(), N * N);
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(kScanTile) k_bin_scan_add(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  bin_scan_add_body(k.w.count(), k.w.off(), k.w.cursor(), k.w.bsum(), N * N);
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(kGalThreads) k_bin_place(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  bin_place_body(k.w.key(), k.w.cursor(), k.w.slot(), k.n_gal);
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(kGalThreads) k_bin_sort(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  bin_sort_body<T>(k.w.off(), k.w.slot(), k.w.cellz(), k.w.frac(), catalogue(k.w, k.n_gal), N * N, k.w.rx(),
+                   k.w.ry(), k.w.rz(), k.w.tx(), k.w.ty(), k.w.tz(), k.w.iz());
+}
+
+// Leapfrog update fused into the galaxy kernels: merged kicks with a drift
+// inside a trajectory (kXMid), a last half kick (kXLast), none for a plain
+// gradient (kXGrad).
+__device__ __forceinline__ LeapUpdate leap_update(int x_mode, int sample, double* p, const double* eps, double minv) {
+  LeapUpdate lf;
+  if (x_mode == kXGrad || !sample) return lf;
+  lf.p = p;
+  lf.eps = eps;
+  lf.kick = x_mode == kXMid ? 1.0 : 0.5;
+  lf.drift = x_mode == kXMid ? 1 : 0;
+  lf.minv = minv;
+  return lf;
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(kGalThreads) k_like(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  if ((int)(blockIdx.x * blockDim.x) >= k.n_gal) return;   // whole block past this catalogue
+  const PlanConst& pc = k.w.pc();
+  LikeOut lo;
+  lo.g_dist = k.st.gd;
+  lo.part = k.w.like_part();
+  like_body<T>(k.w.part(), k.w.slot(), k.w.frac(), k.st.qd, k.st.qs, catalogue(k.w, k.n_gal), cosmo(k.w),
+               k.w.gsort(), lo, leap_update(k.mode, pc.sample_d, k.st.pd, k.st.eps, pc.minv_d));
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_finalize(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  const PlanConst& pc = k.w.pc();
+  finalize_body(k.w.prior_part(), pc.n_prior_part, k.w.like_part(), pc.n_like_part, k.st.psi, k.st.gs, k.st.qs,
+                leap_update(k.mode, pc.sample_s, k.st.ps, k.st.eps, 1.0));
 }
 
 }  // namespace hamlet

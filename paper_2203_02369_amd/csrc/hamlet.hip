@@ -15,6 +15,7 @@
 #include "passes.hpp"
 #include "galaxies.hpp"
 #include "hmc.hpp"
+#include "workspace.hpp"
 
 using namespace hamlet;
 
@@ -48,64 +49,50 @@ static hamlet_status fail(hamlet_status st, const char* fmt, ...) {
 // ---------------------------------------------------------------------------
 // The plan
 // ---------------------------------------------------------------------------
-struct Workspace {
-  char* base = nullptr;
-  size_t used = 0;
-  size_t cap = 0;
-  template <typename X> X* take(size_t count) {
-    const size_t bytes = ((count * sizeof(X)) + 255) & ~size_t(255);
-    X* p = base ? reinterpret_cast<X*>(base + used) : nullptr;
-    used += bytes;
-    return p;
-  }
-};
-
 struct hamlet_plan;
 
-// What one evaluation does besides Psi and the gradient.  Plain gradient:
-// x_mode = kXGrad, the gradient goes to g.  Inside a leapfrog trajectory the
-// inverse pass 1 was already done by the previous evaluation's x pass, and
-// the leapfrog update of every coordinate is fused in (x_mode kXMid or
-// kXLast; the gradient of a kXLast evaluation goes to g as the cache).
-struct EvalMode {
-  int x_mode = kXGrad;
+// A shared launch: up to kMaxBatch plans of one grid size and precision,
+// each with its mode for this launch, on the stream of the first plan.
+struct Batch {
+  hipStream_t stream = nullptr;
+  int count = 0;
+  hamlet_plan* plan[kMaxBatch] = {};
+  int8_t mode[kMaxBatch] = {};
   double plane_scale = 1.0;   // kXGrad: factor on the kz = 0 plane of the gradient
-  double2* p_modes = nullptr;
-  double* p_dist = nullptr;
-  double* p_snl = nullptr;
-  const double* eps = nullptr;
 };
 
-typedef hamlet_status (*eval_fn)(hamlet_plan*, double2*, double*, double*, double2*, double*, double*, double*,
-                                 const EvalMode&);
-typedef hamlet_status (*first_fn)(hamlet_plan*, double2*, double2*, const double*);
+// Launch sequences and workspace layout, one instantiation per (precision, N).
+struct Ops {
+  hamlet_status (*eval)(const Batch&);       // one evaluation, per-plan modes
+  hamlet_status (*start)(const Batch&);      // trajectory start: step, momenta, K0, saved state
+  hamlet_status (*first)(const Batch&);      // first half kick and drift, inverse pass 1
+  hamlet_status (*end)(const Batch&);        // trajectory end: K1, Metropolis test, restore, sum
+  hamlet_status (*leap_out)(const Batch&);   // Psi of a leapfrog end point to the caller
+  size_t (*bytes)(int n_gal, int n_hist);    // workspace size
+  void (*locate)(hamlet_plan*);              // host copies of the workspace addresses it needs
+};
 
 struct hamlet_plan {
   int n = 0, prec = 0, n_gal = 0, sample_d = 1, sample_s = 1, n_hist = 0;
   double box = 0, om = 0, h = 0, f = 0, sigma_v = 0, hist_w = 5.0, minv_d = 0;
   hipStream_t stream = nullptr;
-  Workspace ws;
-  // tables
+  hipEvent_t order_ev = nullptr;   // orders shared launches against this plan's stream
+  char* base = nullptr;            // the workspace (one allocation)
+  size_t bytes = 0;
+  StateDev st{};                   // what the current call works on
+  // workspace addresses used by the host
+  PlanConst* consts = nullptr;
+  ChainScalars* cs = nullptr;
   double *var = nullptr, *mvar = nullptr, *hist = nullptr;
   void* tw = nullptr;
-  // catalogue
   double *rhat = nullptr, *mu = nullptr, *smu = nullptr, *cz = nullptr, *scz = nullptr;
-  // binning
-  int *count = nullptr, *off = nullptr, *cursor = nullptr, *key = nullptr, *cellz = nullptr, *slot = nullptr,
-      *iz = nullptr, *bsum = nullptr;
-  double* frac = nullptr;
-  void *rx = nullptr, *ry = nullptr, *rz = nullptr, *tx = nullptr, *ty = nullptr, *tz = nullptr;
-  // spectral intermediates and galaxy partials (precision T)
-  void *a = nullptr, *b = nullptr, *v0 = nullptr, *v1 = nullptr, *v2 = nullptr, *part = nullptr, *gsort = nullptr;
-  double *prior_part = nullptr, *like_part = nullptr, *kin_part = nullptr;
+  int *count = nullptr, *off = nullptr;
+  double2* gcache = nullptr;
+  double2* pm = nullptr;
+  double *gd = nullptr, *qd0 = nullptr, *pd = nullptr, *ps = nullptr, *eps_slot = nullptr;
   int n_prior_part = 0, n_like_part = 0, n_kin_part = 0;
-  // chain state
-  ChainScalars* cs = nullptr;
-  double2 *gcache = nullptr, *q0 = nullptr, *g0 = nullptr, *pm = nullptr;
-  double *gd = nullptr, *gd0 = nullptr, *qd0 = nullptr, *pd = nullptr, *qs0 = nullptr, *ps = nullptr;
-  double* eps_slot = nullptr;
-  eval_fn eval = nullptr;
-  first_fn first = nullptr;
+  bool chain_ready = false;        // chain state and cached gradient valid (resume)
+  const Ops* ops = nullptr;
   // event timing of one kernel kind (hamlet_profile_start / stop)
   int prof_kind = -1;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pool;
@@ -114,162 +101,154 @@ struct hamlet_plan {
   size_t modes_count() const { return (size_t)n * n * (n / 2); }
 };
 
-// Bracket one launch of kernel kind `kind` with events when it is armed.
-static void prof_before(hamlet_plan* pl, int kind) {
+// Bracket one launch of kernel kind `kind` with events when it is armed on
+// the first plan of the batch (events go to the batch's stream).
+static void prof_before(const Batch& b, int kind) {
+  hamlet_plan* pl = b.plan[0];
   if (pl->prof_kind != kind) return;
   if (pl->prof_used == pl->prof_pool.size()) {
-    hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
       pl->prof_failed = true;
       pl->prof_kind = -1;
       return;
     }
-    pl->prof_pool.emplace_back(a, b);
+    pl->prof_pool.emplace_back(e0, e1);
   }
-  if (hipEventRecord(pl->prof_pool[pl->prof_used].first, pl->stream) != hipSuccess) pl->prof_failed = true;
+  if (hipEventRecord(pl->prof_pool[pl->prof_used].first, b.stream) != hipSuccess) pl->prof_failed = true;
 }
-static void prof_after(hamlet_plan* pl, int kind) {
+static void prof_after(const Batch& b, int kind) {
+  hamlet_plan* pl = b.plan[0];
   if (pl->prof_kind != kind) return;
-  if (hipEventRecord(pl->prof_pool[pl->prof_used].second, pl->stream) != hipSuccess) pl->prof_failed = true;
+  if (hipEventRecord(pl->prof_pool[pl->prof_used].second, b.stream) != hipSuccess) pl->prof_failed = true;
   ++pl->prof_used;
 }
-#define TIMED(pl, kind, ...)   \
-  do {                         \
-    prof_before(pl, kind);     \
-    __VA_ARGS__;               \
-    prof_after(pl, kind);      \
+#define TIMED(b, kind, ...)   \
+  do {                        \
+    prof_before(b, kind);     \
+    __VA_ARGS__;              \
+    prof_after(b, kind);      \
   } while (0)
-
-template <typename T> static Binned<T> binned_view(hamlet_plan* pl) {
-  Binned<T> b;
-  b.off = pl->off;
-  b.rx = (const T*)pl->rx; b.ry = (const T*)pl->ry; b.rz = (const T*)pl->rz;
-  b.tx = (const T*)pl->tx; b.ty = (const T*)pl->ty; b.tz = (const T*)pl->tz;
-  b.iz = pl->iz;
-  return b;
-}
-
-static Catalogue catalogue_view(hamlet_plan* pl) {
-  Catalogue c;
-  c.n = pl->n_gal; c.rhat = pl->rhat; c.mu = pl->mu; c.sigma_mu = pl->smu; c.cz = pl->cz; c.sigma_cz = pl->scz;
-  c.hist = pl->hist; c.n_hist = pl->n_hist; c.hist_w = pl->hist_w;
-  return c;
-}
-
-static Cosmo cosmo_view(hamlet_plan* pl) {
-  Cosmo c;
-  c.om = pl->om; c.h = pl->h; c.box = pl->box; c.spacing = pl->box / pl->n;
-  c.dmax = kC / (3.0 * pl->om * kH0);
-  return c;
-}
-
-static ModeTables tables_view(hamlet_plan* pl) {
-  ModeTables t;
-  t.var = pl->mvar;
-  t.kfac0 = kH0 * pl->f / ((double)pl->n * pl->n * pl->n * (2.0 * M_PI / pl->box));
-  return t;
-}
 
 static inline unsigned blocks_for(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// One log-posterior-and-gradient evaluation: bin, inverse passes with the
-// gather, likelihood, final sums (Psi, dPsi/ds), forward passes with the
-// scatter, and the x pass (gradient, or the fused leapfrog update and the
-// next evaluation's inverse pass 1).
+// Argument table of a batch; `force` >= kXSkip replaces every plan's mode.
+constexpr int kOwnModes = -100;
+static Launch launch_table(const Batch& b, int force = kOwnModes) {
+  Launch L;
+  for (int i = 0; i < kMaxBatch; ++i) {
+    const bool in = i < b.count;
+    const hamlet_plan* p = b.plan[in ? i : 0];
+    L.base[i] = p->base;
+    L.n_gal[i] = p->n_gal;
+    L.mode[i] = in ? (force == kOwnModes ? b.mode[i] : force) : kXSkip;
+    L.st[i] = p->st;
+  }
+  return L;
+}
+
+// Largest catalogue among the plans of a batch that take part.
+static int batch_max_gal(const Batch& b) {
+  int m = 0;
+  for (int i = 0; i < b.count; ++i)
+    if (b.mode[i] != kXSkip) m = std::max(m, b.plan[i]->n_gal);
+  return m;
+}
+
+static bool batch_has(const Batch& b, int mode) {
+  for (int i = 0; i < b.count; ++i)
+    if (b.mode[i] == mode) return true;
+  return false;
+}
+
+// One log-posterior-and-gradient evaluation of every plan of the batch:
+// bin, inverse passes with the gather, likelihood, final sums (Psi,
+// dPsi/ds), forward passes with the scatter, and the x pass (gradient, or
+// the fused leapfrog update and the next evaluation's inverse pass 1).
 template <typename T, int N>
-static hamlet_status eval_impl(hamlet_plan* pl, double2* q, double* qd, double* qs, double2* g, double* gd,
-                               double* gs, double* psi, const EvalMode& em) {
-  using C = cplx_t<T>;
+static hamlet_status eval_impl(const Batch& b) {
   using S = PassShape<T, N>;
   using TH = PassThreads<T, N>;
-  hipStream_t st = pl->stream;
-  const int n = pl->n_gal;
-  const Catalogue cat = catalogue_view(pl);
-  const Cosmo cm = cosmo_view(pl);
-  const ModeTables tab = tables_view(pl);
-  const C* tw = (const C*)pl->tw;
-  const Binned<T> bins = binned_view<T>(pl);
-  const bool leap = em.x_mode != kXGrad;
-  LeapUpdate lf_d, lf_s;
-  if (leap) {
-    const double kick = em.x_mode == kXMid ? 1.0 : 0.5;
-    const int drift = em.x_mode == kXMid ? 1 : 0;
-    if (pl->sample_d) {
-      lf_d.p = em.p_dist; lf_d.eps = em.eps; lf_d.kick = kick; lf_d.drift = drift; lf_d.minv = pl->minv_d;
-    }
-    if (pl->sample_s) {
-      lf_s.p = em.p_snl; lf_s.eps = em.eps; lf_s.kick = kick; lf_s.drift = drift; lf_s.minv = 1.0;
-    }
-  }
-  if (n > 0) {
-    prof_before(pl, HAMLET_K_BIN);
-    k_bin_count<T><<<blocks_for(n, kGalThreads), kGalThreads, 0, st>>>(qd, cat, cm, N, pl->count, pl->key,
-                                                                        pl->cellz, pl->frac);
-    constexpr int tiles = (N * N + kScanTile - 1) / kScanTile;
-    k_bin_scan_tiles<<<tiles, kScanTile, 0, st>>>(pl->count, pl->off, pl->bsum, N * N);
-    k_bin_scan_add<<<tiles, kScanTile, 0, st>>>(pl->count, pl->off, pl->cursor, pl->bsum, N * N);
-    k_bin_place<<<blocks_for(n, kGalThreads), kGalThreads, 0, st>>>(pl->key, pl->cursor, pl->slot, n);
-    k_bin_sort<T><<<blocks_for((size_t)N * N, kGalThreads), kGalThreads, 0, st>>>(
-        pl->off, pl->slot, pl->cellz, pl->frac, cat, N * N, (T*)pl->rx, (T*)pl->ry, (T*)pl->rz, (T*)pl->tx,
-        (T*)pl->ty, (T*)pl->tz, pl->iz, pl->slot);
-    prof_after(pl, HAMLET_K_BIN);
+  using SL = XSlabs<N>;
+  if (b.count <= 0) return HAMLET_OK;
+  hipStream_t st = b.stream;
+  const Launch sel = launch_table(b);
+  const unsigned nb = (unsigned)b.count;
+  const int ng = batch_max_gal(b);
+  if (ng > 0) {
+    constexpr unsigned tiles = (N * N + kScanTile - 1) / kScanTile;
+    const dim3 g_gal(blocks_for(ng, kGalThreads), 1, nb);
+    prof_before(b, HAMLET_K_BIN);
+    k_bin_count<T, N><<<g_gal, kGalThreads, 0, st>>>(sel);
+    k_bin_scan_tiles<T, N><<<dim3(tiles, 1, nb), kScanTile, 0, st>>>(sel);
+    k_bin_scan_add<T, N><<<dim3(tiles, 1, nb), kScanTile, 0, st>>>(sel);
+    k_bin_place<T, N><<<g_gal, kGalThreads, 0, st>>>(sel);
+    k_bin_sort<T, N><<<dim3(blocks_for((size_t)N * N, kGalThreads), 1, nb), kGalThreads, 0, st>>>(sel);
+    prof_after(b, HAMLET_K_BIN);
     LAUNCH_CHECK();
   }
-  const dim3 gs_xy(S::CHUNKS, N);
-  if (!leap)
-    TIMED(pl, HAMLET_K_INV_X,
-          k_inv_x<T, N, TH::XY><<<gs_xy, TH::XY, 0, st>>>(q, tab, tw, (C*)pl->a, (C*)pl->b, pl->prior_part));
-  using SL = XSlabs<N>;
-  const dim3 gs_xy_slab(S::CHUNKS, SL::SIZE), gs_z_slab(N / S::P, SL::SIZE);
+  const dim3 g_xy(S::CHUNKS, N, nb);
+  const dim3 g_xy_slab(S::CHUNKS, SL::SIZE, nb), g_z_slab(N / S::P, SL::SIZE, nb);
+  if (batch_has(b, kXGrad)) TIMED(b, HAMLET_K_INV_X, (k_inv_x<T, N, TH::XY><<<g_xy, TH::XY, 0, st>>>(sel)));
   for (int sl = 0; sl < SL::COUNT; ++sl) {
     const int x0 = sl * SL::SIZE;
-    TIMED(pl, HAMLET_K_INV_Y,
-          k_inv_y<T, N, TH::XY><<<gs_xy_slab, TH::XY, 0, st>>>((const C*)pl->a, (const C*)pl->b, tw, (C*)pl->v0,
-                                                                (C*)pl->v1, (C*)pl->v2, x0));
-    TIMED(pl, HAMLET_K_INV_Z,
-          k_inv_z_gather<T, N, TH::Z><<<gs_z_slab, TH::Z, 0, st>>>((const C*)pl->v0, (const C*)pl->v1,
-                                                                    (const C*)pl->v2, tw, bins, (C*)pl->part, x0));
+    TIMED(b, HAMLET_K_INV_Y, (k_inv_y<T, N, TH::XY><<<g_xy_slab, TH::XY, 0, st>>>(sel, x0)));
+    TIMED(b, HAMLET_K_INV_Z, (k_inv_z_gather<T, N, TH::Z><<<g_z_slab, TH::Z, 0, st>>>(sel, x0)));
   }
   LAUNCH_CHECK();
-  if (n > 0) {
-    LikeOut lo;
-    lo.g_dist = gd;
-    lo.part = pl->like_part;
-    TIMED(pl, HAMLET_K_LIKE,
-          k_like<T><<<blocks_for(n, kGalThreads), kGalThreads, 0, st>>>((const C*)pl->part, pl->slot, pl->frac,
-                                                                         qd, qs, cat, cm, (T*)pl->gsort, lo, lf_d));
+  if (ng > 0) {
+    TIMED(b, HAMLET_K_LIKE, (k_like<T, N><<<dim3(blocks_for(ng, kGalThreads), 1, nb), kGalThreads, 0, st>>>(sel)));
     LAUNCH_CHECK();
   }
-  k_finalize<<<1, 256, 0, st>>>(pl->prior_part, pl->n_prior_part, pl->like_part, n > 0 ? pl->n_like_part : 0, psi,
-                                gs, qs, lf_s);
+  k_finalize<T, N><<<dim3(1, 1, nb), 256, 0, st>>>(sel);
   for (int sl = 0; sl < SL::COUNT; ++sl) {
     const int x0 = sl * SL::SIZE;
-    TIMED(pl, HAMLET_K_FWD_Z,
-          k_fwd_z_scatter<T, N, TH::Z><<<gs_z_slab, TH::Z, 0, st>>>((const T*)pl->gsort, bins, tw, (C*)pl->v0,
-                                                                     (C*)pl->v1, (C*)pl->v2, x0));
-    TIMED(pl, HAMLET_K_FWD_Y,
-          k_fwd_y<T, N, TH::XY><<<gs_xy_slab, TH::XY, 0, st>>>((const C*)pl->v0, (const C*)pl->v1,
-                                                                (const C*)pl->v2, tw, (C*)pl->a, (C*)pl->b, x0));
+    TIMED(b, HAMLET_K_FWD_Z, (k_fwd_z_scatter<T, N, TH::Z><<<g_z_slab, TH::Z, 0, st>>>(sel, x0)));
+    TIMED(b, HAMLET_K_FWD_Y, (k_fwd_y<T, N, TH::XY><<<g_xy_slab, TH::XY, 0, st>>>(sel, x0)));
   }
-  const C* s1 = (const C*)pl->a;
-  const C* s2 = (const C*)pl->b;
-  if (em.x_mode == kXGrad) {
-    TIMED(pl, HAMLET_K_FWD_X,
-          (k_x_pass<T, N, kXGrad, TH::X><<<gs_xy, TH::X, 0, st>>>(s1, s2, q, nullptr, g, tab, tw, nullptr, nullptr,
-                                                                    nullptr, nullptr, em.plane_scale)));
-  } else if (em.x_mode == kXMid) {
-    // S1, S2 live in a, b and are read by the same tile that writes the next
-    // A, B: the x pass writes them to v0, v1 and the plan swaps the roles.
-    TIMED(pl, HAMLET_K_FWD_X,
-          (k_x_pass<T, N, kXMid, TH::X><<<gs_xy, TH::X, 0, st>>>(s1, s2, q, em.p_modes, nullptr, tab, tw, em.eps,
-                                                                   (C*)pl->v0, (C*)pl->v1, pl->prior_part, 1.0)));
-    std::swap(pl->a, pl->v0);
-    std::swap(pl->b, pl->v1);
-  } else {
-    TIMED(pl, HAMLET_K_FWD_X,
-          (k_x_pass<T, N, kXLast, TH::X><<<gs_xy, TH::X, 0, st>>>(s1, s2, q, em.p_modes, g, tab, tw, em.eps, nullptr,
-                                                                    nullptr, nullptr, 1.0)));
-  }
+  if (batch_has(b, kXGrad))
+    TIMED(b, HAMLET_K_FWD_X, (k_x_pass<T, N, kXGrad, TH::X><<<g_xy, TH::X, 0, st>>>(sel, b.plane_scale)));
+  if (batch_has(b, kXMid))
+    TIMED(b, HAMLET_K_FWD_X, (k_x_pass<T, N, kXMid, TH::X><<<g_xy, TH::X, 0, st>>>(sel, 1.0)));
+  if (batch_has(b, kXLast))
+    TIMED(b, HAMLET_K_FWD_X, (k_x_pass<T, N, kXLast, TH::X><<<g_xy, TH::X, 0, st>>>(sel, 1.0)));
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
+// Kinetic energy of every plan of the batch into kin0 (which = 0) or kin1.
+template <typename T, int N>
+static hamlet_status kinetic_impl(const Batch& b, const Launch& sel, int which) {
+  const unsigned nb = (unsigned)b.count;
+  k_kinetic_modes<T, N><<<dim3(FixedLayout<N, sizeof(T)>::N_KIN, 1, nb), kEltThreads, 0, b.stream>>>(sel);
+  k_kinetic_final<T, N><<<dim3(1, 1, nb), 256, 0, b.stream>>>(sel, which);
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
+static int batch_gal_or_one(const Batch& b) {
+  int m = 1;
+  for (int i = 0; i < b.count; ++i) m = std::max(m, b.plan[i]->n_gal);
+  return m;
+}
+
+// Start of a trajectory of every plan of the batch: the iteration's step,
+// fresh momenta, K0, and the saved state for a possible rejection.
+template <typename T, int N>
+static hamlet_status start_impl(const Batch& b) {
+  if (b.count <= 0) return HAMLET_OK;
+  const Launch sel = launch_table(b, 0);
+  const unsigned nb = (unsigned)b.count;
+  const size_t nm = (size_t)N * N * (N / 2);
+  const int ng = batch_gal_or_one(b);
+  k_iter_begin<T, N><<<dim3(1, 1, nb), 64, 0, b.stream>>>(sel);
+  k_momenta_modes<T, N><<<dim3(blocks_for(nm, kEltThreads), 1, nb), kEltThreads, 0, b.stream>>>(sel);
+  k_momenta_small<T, N><<<dim3(blocks_for(ng, kEltThreads), 1, nb), kEltThreads, 0, b.stream>>>(sel);
+  LAUNCH_CHECK();
+  hamlet_status s = kinetic_impl<T, N>(b, sel, 0);
+  if (s != HAMLET_OK) return s;
+  k_save_state<T, N><<<dim3(blocks_for(std::max(nm, (size_t)ng), kEltThreads), 1, nb), kEltThreads, 0, b.stream>>>(
+      sel);
   LAUNCH_CHECK();
   return HAMLET_OK;
 }
@@ -277,100 +256,82 @@ static hamlet_status eval_impl(hamlet_plan* pl, double2* q, double* qd, double* 
 // First step of a trajectory: half kick from the cached gradient and drift
 // of every coordinate, then inverse pass 1 of the new modes.
 template <typename T, int N>
-static hamlet_status first_impl(hamlet_plan* pl, double2* q, double2* p_modes, const double* eps) {
-  using C = cplx_t<T>;
+static hamlet_status first_impl(const Batch& b) {
   using S = PassShape<T, N>;
   using TH = PassThreads<T, N>;
-  const dim3 gs_xy(S::CHUNKS, N);
-  TIMED(pl, HAMLET_K_FWD_X,
-        (k_x_pass<T, N, kXFirst, TH::X><<<gs_xy, TH::X, 0, pl->stream>>>(
-            nullptr, nullptr, q, p_modes, pl->gcache, tables_view(pl), (const C*)pl->tw, eps, (C*)pl->a, (C*)pl->b,
-            pl->prior_part, 1.0)));
+  if (b.count <= 0) return HAMLET_OK;
+  const Launch sel = launch_table(b, kXFirst);
+  const unsigned nb = (unsigned)b.count;
+  k_small_kick_drift<T, N><<<dim3(blocks_for(batch_gal_or_one(b), kEltThreads), 1, nb), kEltThreads, 0, b.stream>>>(
+      sel);
+  TIMED(b, HAMLET_K_FWD_X, (k_x_pass<T, N, kXFirst, TH::X><<<dim3(S::CHUNKS, N, nb), TH::X, 0, b.stream>>>(sel, 1.0)));
   LAUNCH_CHECK();
   return HAMLET_OK;
 }
 
-template <typename T> static eval_fn pick_eval(int n) {
-  switch (n) {
-    case 16: return eval_impl<T, 16>;
-    case 32: return eval_impl<T, 32>;
-    case 64: return eval_impl<T, 64>;
-    case 128: return eval_impl<T, 128>;
-    case 256: return eval_impl<T, 256>;
-    default: return nullptr;
-  }
+// End of a trajectory: K1, Metropolis-Hastings test and step adaptation,
+// restore on rejection, running sum of the post-warm-up samples.
+template <typename T, int N>
+static hamlet_status end_impl(const Batch& b) {
+  if (b.count <= 0) return HAMLET_OK;
+  const Launch sel = launch_table(b, 0);
+  const unsigned nb = (unsigned)b.count;
+  const size_t nm = (size_t)N * N * (N / 2);
+  hamlet_status s = kinetic_impl<T, N>(b, sel, 1);
+  if (s != HAMLET_OK) return s;
+  k_accept<T, N><<<dim3(1, 1, nb), 64, 0, b.stream>>>(sel);
+  k_restore_accumulate<T, N><<<dim3(blocks_for(std::max(nm, (size_t)batch_gal_or_one(b)), kEltThreads), 1, nb),
+                               kEltThreads, 0, b.stream>>>(sel);
+  LAUNCH_CHECK();
+  return HAMLET_OK;
 }
 
-template <typename T> static first_fn pick_first(int n) {
-  switch (n) {
-    case 16: return first_impl<T, 16>;
-    case 32: return first_impl<T, 32>;
-    case 64: return first_impl<T, 64>;
-    case 128: return first_impl<T, 128>;
-    case 256: return first_impl<T, 256>;
-    default: return nullptr;
-  }
+template <typename T, int N>
+static hamlet_status leap_out_impl(const Batch& b) {
+  if (b.count <= 0) return HAMLET_OK;
+  k_leap_out<T, N><<<dim3(1, 1, (unsigned)b.count), 64, 0, b.stream>>>(launch_table(b, 0));
+  LAUNCH_CHECK();
+  return HAMLET_OK;
 }
 
-// Workspace layout; with ws.base == nullptr only the size is computed.
-static void carve(hamlet_plan* pl) {
-  Workspace& ws = pl->ws;
-  ws.used = 0;
-  const int n = pl->n;
-  const size_t nm = pl->modes_count();
-  const size_t npk = 3 * (size_t)(n / 2) * (n / 2) + 1;
-  const size_t real = pl->prec == HAMLET_FP64 ? 8 : 4;
-  const size_t ng = std::max(pl->n_gal, 1);
-  pl->var = ws.take<double>(npk);
-  pl->mvar = ws.take<double>(nm);
-  pl->hist = ws.take<double>(std::max(pl->n_hist, 1));
-  pl->tw = ws.take<char>(2 * real * n);
-  pl->rhat = ws.take<double>(3 * ng);
-  pl->mu = ws.take<double>(ng);
-  pl->smu = ws.take<double>(ng);
-  pl->cz = ws.take<double>(ng);
-  pl->scz = ws.take<double>(ng);
-  pl->count = ws.take<int>((size_t)n * n);
-  pl->off = ws.take<int>((size_t)n * n + 1);
-  pl->cursor = ws.take<int>((size_t)n * n);
-  pl->bsum = ws.take<int>(((size_t)n * n + kScanTile - 1) / kScanTile);
-  pl->key = ws.take<int>(ng);
-  pl->cellz = ws.take<int>(ng);
-  pl->slot = ws.take<int>(ng);
-  pl->iz = ws.take<int>(ng);
-  pl->frac = ws.take<double>(3 * ng);
-  pl->rx = ws.take<char>(real * ng);
-  pl->ry = ws.take<char>(real * ng);
-  pl->rz = ws.take<char>(real * ng);
-  pl->tx = ws.take<char>(real * ng);
-  pl->ty = ws.take<char>(real * ng);
-  pl->tz = ws.take<char>(real * ng);
-  pl->gsort = ws.take<char>(real * ng);
-  pl->part = ws.take<char>(2 * real * 4 * ng);
-  pl->a = ws.take<char>(2 * real * nm);
-  pl->b = ws.take<char>(2 * real * nm);
-  pl->v0 = ws.take<char>(2 * real * nm);
-  pl->v1 = ws.take<char>(2 * real * nm);
-  pl->v2 = ws.take<char>(2 * real * nm);
-  const int chunks = (n / 2) / (pl->prec == HAMLET_FP64 ? std::min(8, n / 2) : std::min(16, n / 2));
-  pl->n_prior_part = n * chunks;
-  pl->prior_part = ws.take<double>(pl->n_prior_part);
-  pl->n_like_part = (int)blocks_for(ng, kGalThreads);
-  pl->like_part = ws.take<double>(3 * (size_t)pl->n_like_part);
-  pl->n_kin_part = 1024;
-  pl->kin_part = ws.take<double>(pl->n_kin_part);
-  pl->cs = ws.take<ChainScalars>(1);
-  pl->gcache = ws.take<double2>(nm);
-  pl->q0 = ws.take<double2>(nm);
-  pl->g0 = ws.take<double2>(nm);
-  pl->pm = ws.take<double2>(nm);
-  pl->gd = ws.take<double>(ng);
-  pl->gd0 = ws.take<double>(ng);
-  pl->qd0 = ws.take<double>(ng);
-  pl->pd = ws.take<double>(ng);
-  pl->qs0 = ws.take<double>(1);
-  pl->ps = ws.take<double>(1);
-  pl->eps_slot = ws.take<double>(1);
+template <typename T, int N> static size_t bytes_impl(int n_gal, int n_hist) {
+  return workspace_bytes<N, sizeof(T)>(n_gal, n_hist);
+}
+
+template <typename T, int N> static void locate_impl(hamlet_plan* pl) {
+  using F = FixedLayout<N, sizeof(T)>;
+  const Ws<T, N> w(pl->base, pl->n_gal);
+  pl->consts = w.template at<PlanConst>(F::consts);
+  pl->cs = w.template at<ChainScalars>(F::chain);
+  pl->var = w.var_n2();
+  pl->mvar = w.mvar();
+  pl->hist = w.hist(pl->n_gal);
+  pl->tw = w.tw();
+  pl->rhat = w.rhat(); pl->mu = w.mu(); pl->smu = w.smu(); pl->cz = w.cz(); pl->scz = w.scz();
+  pl->count = w.count();
+  pl->off = w.off();
+  pl->gcache = w.gcache();
+  pl->pm = w.pm();
+  pl->gd = w.gd(); pl->qd0 = w.qd0(); pl->pd = w.pd(); pl->ps = w.ps(); pl->eps_slot = w.eps_slot();
+  pl->n_prior_part = F::N_PRIOR;
+  pl->n_like_part = pl->n_gal > 0 ? (int)blocks_for(pl->n_gal, kGalThreads) : 0;
+  pl->n_kin_part = F::N_KIN;
+}
+
+template <typename T, int N> struct OpsFor {
+  static constexpr Ops ops{eval_impl<T, N>, start_impl<T, N>, first_impl<T, N>, end_impl<T, N>,
+                           leap_out_impl<T, N>, bytes_impl<T, N>, locate_impl<T, N>};
+};
+
+template <typename T> static const Ops* pick_ops(int n) {
+  switch (n) {
+    case 16: return &OpsFor<T, 16>::ops;
+    case 32: return &OpsFor<T, 32>::ops;
+    case 64: return &OpsFor<T, 64>::ops;
+    case 128: return &OpsFor<T, 128>::ops;
+    case 256: return &OpsFor<T, 256>::ops;
+    default: return nullptr;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -452,7 +413,6 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
   const double vol = pl->box * pl->box * pl->box;
   std::vector<double> var(npk);
   for (size_t j = 0; j < npk; ++j) var[j] = n3 * n3 / vol * d->pk_n2[j];
-  (void)kf;
   // Twiddles exp(-2 pi i m / N), computed in long double and rounded once.
   std::vector<double> twd(2 * n);
   std::vector<float> twf(2 * n);
@@ -481,6 +441,24 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
   }
   HIP_TRY(hipMemsetAsync(pl->count, 0, (size_t)n * n * sizeof(int), st));
   HIP_TRY(hipMemsetAsync(pl->off, 0, ((size_t)n * n + 1) * sizeof(int), st));
+  PlanConst pc{};
+  pc.n_gal = pl->n_gal;
+  pc.n_hist = pl->n_hist;
+  pc.sample_d = pl->sample_d;
+  pc.sample_s = pl->sample_s;
+  pc.n_prior_part = pl->n_prior_part;
+  pc.n_like_part = pl->n_like_part;
+  pc.n_kin_part = pl->n_kin_part;
+  pc.om = pl->om;
+  pc.h = pl->h;
+  pc.box = pl->box;
+  pc.spacing = pl->box / pl->n;
+  pc.dmax = kC / (3.0 * pl->om * kH0);
+  pc.hist_w = pl->hist_w;
+  pc.minv_d = pl->minv_d;
+  pc.psd = kH0 / pl->sigma_v;
+  pc.kfac0 = kH0 * pl->f / ((double)pl->n * pl->n * pl->n * kf);
+  HIP_TRY(hipMemcpyAsync(pl->consts, &pc, sizeof(pc), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   return HAMLET_OK;
 }
@@ -511,10 +489,9 @@ extern "C" hamlet_status hamlet_plan_footprint_bytes(const hamlet_plan_desc* des
   if (st != HAMLET_OK) return st;
   if (!bytes) return fail(HAMLET_EINVAL, "bytes is NULL");
   if (n_gal < 0) return fail(HAMLET_EINVAL, "n_gal < 0");
-  hamlet_plan tmp;
-  fill_plan_scalars(&tmp, desc, n_gal, kFootprintHistBins);
-  carve(&tmp);
-  *bytes = tmp.ws.used;
+  if (n_gal > (int64_t)(1 << 28)) return fail(HAMLET_EINVAL, "n_gal %lld", (long long)n_gal);
+  const Ops* ops = desc->precision == HAMLET_FP64 ? pick_ops<double>(desc->n_grid) : pick_ops<float>(desc->n_grid);
+  *bytes = ops->bytes((int)n_gal, kFootprintHistBins);
   return HAMLET_OK;
 }
 
@@ -531,19 +508,23 @@ extern "C" hamlet_status hamlet_plan_create(const hamlet_plan_desc* desc, const 
   hamlet_plan* pl = new hamlet_plan();
   fill_plan_scalars(pl, desc, cat->n, (int)hist.size());
   pl->stream = (hipStream_t)stream;
-  pl->eval = pl->prec == HAMLET_FP64 ? pick_eval<double>(pl->n) : pick_eval<float>(pl->n);
-  pl->first = pl->prec == HAMLET_FP64 ? pick_first<double>(pl->n) : pick_first<float>(pl->n);
-  carve(pl);
-  const size_t bytes = pl->ws.used;
-  if (hipMalloc((void**)&pl->ws.base, bytes) != hipSuccess) {
+  pl->ops = pl->prec == HAMLET_FP64 ? pick_ops<double>(pl->n) : pick_ops<float>(pl->n);
+  if (hipEventCreateWithFlags(&pl->order_ev, hipEventDisableTiming) != hipSuccess) {
+    delete pl;
+    return fail(HAMLET_EDEVICE, "hipEventCreateWithFlags failed");
+  }
+  pl->bytes = pl->ops->bytes(pl->n_gal, pl->n_hist);
+  if (hipMalloc((void**)&pl->base, pl->bytes) != hipSuccess) {
+    (void)hipEventDestroy(pl->order_ev);
+    const size_t bytes = pl->bytes;
     delete pl;
     return fail(HAMLET_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
   }
-  pl->ws.cap = bytes;
-  carve(pl);
+  pl->ops->locate(pl);
   st = upload(pl, desc, cat, hist);
   if (st != HAMLET_OK) {
-    (void)hipFree(pl->ws.base);
+    (void)hipFree(pl->base);
+    (void)hipEventDestroy(pl->order_ev);
     delete pl;
     return st;
   }
@@ -558,64 +539,167 @@ extern "C" hamlet_status hamlet_plan_destroy(hamlet_plan* pl) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
   }
-  hipError_t e2 = hipFree(pl->ws.base);
+  hipError_t e2 = hipFree(pl->base);
+  (void)hipEventDestroy(pl->order_ev);
   delete pl;
   if (e1 != hipSuccess || e2 != hipSuccess) return fail(HAMLET_EDEVICE, "plan destroy: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
   return HAMLET_OK;
 }
 
+
 // ---------------------------------------------------------------------------
-// Leapfrog and chain orchestration
+// Batching: plans of one grid size and precision share launches
 // ---------------------------------------------------------------------------
-// Kick-drift-kick trajectory (eq:hamilton, Section 3.3) of `steps` steps from
-// a state whose gradient is cached in (pl->gcache, pl->gd, cs->gs); leaves
-// the end point's gradient there and its Psi in cs->psi.  Consecutive half
-// kicks are merged and every update is fused into the evaluation kernels.
-static hamlet_status trajectory(hamlet_plan* pl, int steps, const double* eps, double2* q, double* qd, double* qs,
-                                double2* pmodes, double* pd, double* ps) {
-  if (steps <= 0) return HAMLET_OK;
-  double* psi = &pl->cs->psi;
-  double* gs = &pl->cs->gs;
-  k_small_kick_drift<<<blocks_for(std::max(pl->n_gal, 1), kEltThreads), kEltThreads, 0, pl->stream>>>(
-      qd, pd, pl->gd, qs, ps, gs, pl->n_gal, pl->sample_d, pl->sample_s, pl->minv_d, eps);
-  LAUNCH_CHECK();
-  hamlet_status st = pl->first(pl, q, pmodes, eps);
-  if (st != HAMLET_OK) return st;
-  EvalMode em;
-  em.p_modes = pmodes;
-  em.p_dist = pd;
-  em.p_snl = ps;
-  em.eps = eps;
-  for (int k = 1; k <= steps; ++k) {
-    em.x_mode = k < steps ? kXMid : kXLast;
-    st = pl->eval(pl, q, qd, qs, pl->gcache, pl->gd, gs, psi, em);
-    if (st != HAMLET_OK) return st;
+static hamlet_status check_plans(hamlet_plan* const* plans, int32_t n_plans) {
+  if (!plans || n_plans <= 0) return fail(HAMLET_EINVAL, "need at least one plan");
+  for (int j = 0; j < n_plans; ++j) {
+    if (!plans[j]) return fail(HAMLET_EINVAL, "plans[%d] is NULL", j);
+    for (int k = 0; k < j; ++k)
+      if (plans[k] == plans[j]) return fail(HAMLET_EINVAL, "plans[%d] and plans[%d] are the same plan", k, j);
   }
   return HAMLET_OK;
 }
 
-static hamlet_status kinetic(hamlet_plan* pl, const double2* pmodes, const double* pd, const double* ps,
-                             double* out) {
-  k_kinetic_modes<<<pl->n_kin_part, kEltThreads, 0, pl->stream>>>(pmodes, tables_view(pl), pl->n, pl->kin_part);
-  k_kinetic_final<<<1, 256, 0, pl->stream>>>(pl->kin_part, pl->n_kin_part, pd, pl->n_gal, ps, pl->minv_d,
-                                              pl->sample_s ? 1.0 : 0.0, out);
-  LAUNCH_CHECK();
+// Plan indices grouped by (N, precision, extra key) in call order, at most
+// kMaxBatch per group.
+static std::vector<std::vector<int>> group_plans(hamlet_plan* const* plans, int32_t n_plans,
+                                                 const int32_t* extra = nullptr) {
+  std::vector<std::vector<int>> groups;
+  for (int j = 0; j < n_plans; ++j) {
+    const hamlet_plan* p = plans[j];
+    int found = -1;
+    for (int g = (int)groups.size() - 1; g >= 0; --g) {
+      const int k = groups[g][0];
+      const hamlet_plan* q = plans[k];
+      if (q->n == p->n && q->prec == p->prec && (!extra || extra[k] == extra[j])) {
+        if ((int)groups[g].size() < kMaxBatch) found = g;
+        break;
+      }
+    }
+    if (found < 0) {
+      groups.emplace_back();
+      found = (int)groups.size() - 1;
+    }
+    groups[found].push_back(j);
+  }
+  return groups;
+}
+
+// A group's launches go to the stream of its first plan; the other plans'
+// streams are ordered before (join) and after (release) them with events.
+static hamlet_status streams_join(hamlet_plan* const* plans, const std::vector<int>& g) {
+  hipStream_t s0 = plans[g[0]]->stream;
+  for (int j : g) {
+    hamlet_plan* p = plans[j];
+    if (p->stream == s0) continue;
+    HIP_TRY(hipEventRecord(p->order_ev, p->stream));
+    HIP_TRY(hipStreamWaitEvent(s0, p->order_ev, 0));
+  }
   return HAMLET_OK;
 }
 
-static hamlet_status check_plans(hamlet_plan* const* plans, int32_t n_plans) {
-  if (!plans || n_plans <= 0) return fail(HAMLET_EINVAL, "need at least one plan");
-  for (int j = 0; j < n_plans; ++j)
-    if (!plans[j]) return fail(HAMLET_EINVAL, "plans[%d] is NULL", j);
+static hamlet_status streams_release(hamlet_plan* const* plans, const std::vector<int>& g) {
+  hamlet_plan* p0 = plans[g[0]];
+  bool recorded = false;
+  for (int j : g) {
+    hamlet_plan* p = plans[j];
+    if (p->stream == p0->stream) continue;
+    if (!recorded) {
+      HIP_TRY(hipEventRecord(p0->order_ev, p0->stream));
+      recorded = true;
+    }
+    HIP_TRY(hipStreamWaitEvent(p->stream, p0->order_ev, 0));
+  }
   return HAMLET_OK;
 }
 
+static Batch make_batch(hamlet_plan* const* plans, const std::vector<int>& g, int mode) {
+  Batch b;
+  b.stream = plans[g[0]]->stream;
+  b.count = (int)g.size();
+  for (int i = 0; i < b.count; ++i) {
+    b.plan[i] = plans[g[i]];
+    b.mode[i] = (int8_t)mode;
+  }
+  return b;
+}
+
+static void batch_add(Batch& b, hamlet_plan* pl, int mode) {
+  b.plan[b.count] = pl;
+  b.mode[b.count] = (int8_t)mode;
+  ++b.count;
+}
+
+static void batch_set_modes(Batch& b, int mode) {
+  for (int i = 0; i < b.count; ++i) b.mode[i] = (int8_t)mode;
+}
+
+// ---------------------------------------------------------------------------
+// Chains advanced one leapfrog step (one evaluation) per tick
+// ---------------------------------------------------------------------------
+// A chain's schedule: one plain gradient at the start point (unless resumed
+// with a valid cached gradient), then per iteration a trajectory of L
+// evaluations (eq:hamilton, kick-drift-kick): the tick of its first step
+// also refreshes the momenta and does the first half kick and drift; the
+// tick of its last step ends with the Metropolis-Hastings test (Section
+// 3.2).  Chains of one group at different points of their schedules share
+// the tick's launches.
+struct ChainRun {
+  hamlet_plan* pl = nullptr;
+  int L = 0;             // leapfrog steps per trajectory
+  int todo = 0;          // iterations to run
+  int iter = 0;          // iterations done
+  int step = 0;          // evaluations done in the current trajectory
+  bool need_grad = false;
+  bool active() const { return need_grad || iter < todo; }
+};
+
+static hamlet_status tick_group(hipStream_t stream, const std::vector<ChainRun*>& runs) {
+  Batch start, first, eval, end;
+  start.stream = first.stream = eval.stream = end.stream = stream;
+  const Ops* ops = nullptr;
+  for (ChainRun* r : runs) {
+    if (!r->active()) continue;
+    ops = r->pl->ops;
+    if (r->need_grad) {
+      batch_add(eval, r->pl, kXGrad);
+      continue;
+    }
+    const bool ending = r->L == 0 || r->step + 1 == r->L;
+    if (r->step == 0) {
+      batch_add(start, r->pl, 0);
+      if (r->L > 0) batch_add(first, r->pl, kXFirst);
+    }
+    if (r->L > 0) batch_add(eval, r->pl, ending ? kXLast : kXMid);
+    if (ending) batch_add(end, r->pl, 0);
+  }
+  if (!ops) return HAMLET_OK;
+  hamlet_status s = ops->start(start);
+  if (s == HAMLET_OK) s = ops->first(first);
+  if (s == HAMLET_OK) s = ops->eval(eval);
+  if (s == HAMLET_OK) s = ops->end(end);
+  if (s != HAMLET_OK) return s;
+  for (ChainRun* r : runs) {
+    if (!r->active()) continue;
+    if (r->need_grad) {
+      r->need_grad = false;
+    } else if (r->L == 0 || r->step + 1 == r->L) {
+      r->step = 0;
+      ++r->iter;
+    } else {
+      ++r->step;
+    }
+  }
+  return HAMLET_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Entry points
+// ---------------------------------------------------------------------------
 static hamlet_status logpost_grad_impl(hamlet_plan* const* plans, int32_t n_plans, const void* const* q_modes,
                                        const double* const* q_dist, const double* const* q_snl,
                                        void* const* g_modes, double* const* g_dist, double* const* g_snl,
                                        double* const* psi, double plane_scale) {
-  EvalMode em;
-  em.plane_scale = plane_scale;
   hamlet_status st = check_plans(plans, n_plans);
   if (st != HAMLET_OK) return st;
   if (!q_modes || !q_snl || !g_modes || !g_snl || !psi) return fail(HAMLET_EINVAL, "NULL argument array");
@@ -625,9 +709,25 @@ static hamlet_status logpost_grad_impl(hamlet_plan* const* plans, int32_t n_plan
       return fail(HAMLET_EINVAL, "plan %d: NULL buffer", j);
     if (pl->n_gal > 0 && (!q_dist || !g_dist || !q_dist[j] || !g_dist[j]))
       return fail(HAMLET_EINVAL, "plan %d: NULL distance buffer", j);
-    st = pl->eval(pl, (double2*)q_modes[j], pl->n_gal ? (double*)q_dist[j] : nullptr, (double*)q_snl[j],
-                  (double2*)g_modes[j], pl->n_gal ? g_dist[j] : nullptr, g_snl[j], psi[j], em);
-    if (st != HAMLET_OK) return st;
+  }
+  for (const std::vector<int>& g : group_plans(plans, n_plans)) {
+    if ((st = streams_join(plans, g)) != HAMLET_OK) return st;
+    Batch b = make_batch(plans, g, kXGrad);
+    b.plane_scale = plane_scale;
+    for (int j : g) {
+      hamlet_plan* pl = plans[j];
+      StateDev sd{};
+      sd.q = (double2*)q_modes[j];
+      sd.qd = pl->n_gal ? (double*)q_dist[j] : pl->qd0;
+      sd.qs = (double*)q_snl[j];
+      sd.g = (double2*)g_modes[j];
+      sd.gd = pl->n_gal ? g_dist[j] : pl->gd;
+      sd.gs = g_snl[j];
+      sd.psi = psi[j];
+      pl->st = sd;
+    }
+    if ((st = b.plan[0]->ops->eval(b)) != HAMLET_OK) return st;
+    if ((st = streams_release(plans, g)) != HAMLET_OK) return st;
   }
   return HAMLET_OK;
 }
@@ -663,15 +763,42 @@ extern "C" hamlet_status hamlet_leapfrog(hamlet_plan* const* plans, int32_t n_pl
       return fail(HAMLET_EINVAL, "plan %d: NULL buffer", j);
     if (pl->n_gal > 0 && (!q_dist || !p_dist || !q_dist[j] || !p_dist[j]))
       return fail(HAMLET_EINVAL, "plan %d: NULL distance buffer", j);
-    double* qd = pl->n_gal ? q_dist[j] : pl->qd0;
-    double* pd = pl->n_gal ? p_dist[j] : pl->pd;
-    k_set_scalar<<<1, 1, 0, pl->stream>>>(pl->eps_slot, eps[j]);
-    st = pl->eval(pl, (double2*)q_modes[j], qd, q_snl[j], pl->gcache, pl->gd, &pl->cs->gs, &pl->cs->psi, EvalMode());
-    if (st != HAMLET_OK) return st;
-    st = trajectory(pl, n_steps[j], pl->eps_slot, (double2*)q_modes[j], qd, q_snl[j], (double2*)p_modes[j], pd,
-                    p_snl[j]);
-    if (st != HAMLET_OK) return st;
-    HIP_TRY(hipMemcpyAsync(psi[j], &pl->cs->psi, sizeof(double), hipMemcpyDeviceToDevice, pl->stream));
+  }
+  for (const std::vector<int>& g : group_plans(plans, n_plans, n_steps)) {
+    if ((st = streams_join(plans, g)) != HAMLET_OK) return st;
+    Batch b = make_batch(plans, g, kXGrad);
+    for (int j : g) {
+      hamlet_plan* pl = plans[j];
+      StateDev sd{};
+      sd.q = (double2*)q_modes[j];
+      sd.qd = pl->n_gal ? q_dist[j] : pl->qd0;
+      sd.qs = q_snl[j];
+      sd.p = (double2*)p_modes[j];
+      sd.pd = pl->n_gal ? p_dist[j] : pl->pd;
+      sd.ps = p_snl[j];
+      sd.g = pl->gcache;
+      sd.gd = pl->gd;
+      sd.gs = &pl->cs->gs;
+      sd.psi = &pl->cs->psi;
+      sd.eps = pl->eps_slot;
+      sd.psi_out = psi[j];
+      pl->st = sd;
+      k_set_scalar<<<1, 64, 0, b.stream>>>(pl->eps_slot, eps[j]);
+      LAUNCH_CHECK();
+      pl->chain_ready = false;   // the cached gradient now belongs to this call
+    }
+    const Ops* ops = b.plan[0]->ops;
+    const int steps = n_steps[g[0]];
+    if ((st = ops->eval(b)) != HAMLET_OK) return st;   // gradient at the start point
+    if (steps > 0) {
+      if ((st = ops->first(b)) != HAMLET_OK) return st;
+      for (int k = 1; k <= steps; ++k) {
+        batch_set_modes(b, k < steps ? kXMid : kXLast);
+        if ((st = ops->eval(b)) != HAMLET_OK) return st;
+      }
+    }
+    if ((st = ops->leap_out(b)) != HAMLET_OK) return st;
+    if ((st = streams_release(plans, g)) != HAMLET_OK) return st;
   }
   return HAMLET_OK;
 }
@@ -683,7 +810,7 @@ extern "C" hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_pla
   hamlet_status st = check_plans(plans, n_plans);
   if (st != HAMLET_OK) return st;
   if (!o) return fail(HAMLET_EINVAL, "opts is NULL");
-  if (o->n_iter < 0 || o->n_leapfrog < 0 || o->warmup < 0 || o->warmup > o->n_iter)
+  if (o->n_iter < 0 || o->n_leapfrog < 0 || o->warmup < 0)
     return fail(HAMLET_EINVAL, "n_iter/n_leapfrog/warmup out of range");
   if (!(o->eps0 > 0) || !std::isfinite(o->eps0)) return fail(HAMLET_EINVAL, "eps0 must be positive");
   if (!(o->target_accept > 0 && o->target_accept < 1)) return fail(HAMLET_EINVAL, "target_accept must be in (0,1)");
@@ -693,58 +820,63 @@ extern "C" hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_pla
     if (!q_modes[j] || !q_snl[j]) return fail(HAMLET_EINVAL, "plan %d: NULL buffer", j);
     if (pl->n_gal > 0 && (!q_dist || !q_dist[j])) return fail(HAMLET_EINVAL, "plan %d: NULL distance buffer", j);
   }
-  // Initial gradient of every chain.
-  for (int j = 0; j < n_plans; ++j) {
-    hamlet_plan* pl = plans[j];
-    double* qd = pl->n_gal ? q_dist[j] : pl->qd0;
-    k_chain_init<<<1, 1, 0, pl->stream>>>(pl->cs, o->eps0, o->target_accept);
-    st = pl->eval(pl, (double2*)q_modes[j], qd, q_snl[j], pl->gcache, pl->gd, &pl->cs->gs, &pl->cs->psi, EvalMode());
-    if (st != HAMLET_OK) return st;
-  }
-  for (int it = 0; it < o->n_iter; ++it) {
-    for (int j = 0; j < n_plans; ++j) {
+  const std::vector<std::vector<int>> groups = group_plans(plans, n_plans);
+  std::vector<ChainRun> runs(n_plans);
+  for (const std::vector<int>& g : groups) {
+    if ((st = streams_join(plans, g)) != HAMLET_OK) return st;
+    hipStream_t s0 = plans[g[0]]->stream;
+    for (int j : g) {
       hamlet_plan* pl = plans[j];
-      hipStream_t s = pl->stream;
-      const size_t nm = pl->modes_count();
-      double2* q = (double2*)q_modes[j];
-      double* qd = pl->n_gal ? q_dist[j] : pl->qd0;
-      const int ng1 = std::max(pl->n_gal, 1);
-      k_iter_begin<<<1, 1, 0, s>>>(pl->cs, o->seed, (uint32_t)it, o->jitter_eps);
-      k_momenta_modes<<<blocks_for(nm, kEltThreads), kEltThreads, 0, s>>>(pl->pm, tables_view(pl), pl->n, o->seed,
-                                                                           (uint32_t)it);
-      k_momenta_small<<<blocks_for(ng1, kEltThreads), kEltThreads, 0, s>>>(
-          pl->pd, pl->ps, pl->n_gal, kH0 / pl->sigma_v, pl->sample_d, pl->sample_s, o->seed, (uint32_t)it);
-      LAUNCH_CHECK();
-      st = kinetic(pl, pl->pm, pl->pd, pl->ps, &pl->cs->kin0);
-      if (st != HAMLET_OK) return st;
-      HIP_TRY(hipMemcpyAsync(pl->q0, q, nm * sizeof(double2), hipMemcpyDeviceToDevice, s));
-      HIP_TRY(hipMemcpyAsync(pl->g0, pl->gcache, nm * sizeof(double2), hipMemcpyDeviceToDevice, s));
-      if (pl->n_gal > 0) {
-        HIP_TRY(hipMemcpyAsync(pl->qd0, qd, pl->n_gal * sizeof(double), hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(pl->gd0, pl->gd, pl->n_gal * sizeof(double), hipMemcpyDeviceToDevice, s));
+      StateDev sd{};
+      sd.q = (double2*)q_modes[j];
+      sd.qd = pl->n_gal ? q_dist[j] : pl->qd0;
+      sd.qs = q_snl[j];
+      sd.p = pl->pm;
+      sd.pd = pl->pd;
+      sd.ps = pl->ps;
+      sd.g = pl->gcache;
+      sd.gd = pl->gd;
+      sd.gs = &pl->cs->gs;
+      sd.psi = &pl->cs->psi;
+      sd.eps = &pl->cs->eps_it;
+      sd.dh = dh ? dh[j] : nullptr;
+      sd.acc = accepted ? accepted[j] : nullptr;
+      sd.msum = mode_sum ? (double2*)mode_sum[j] : nullptr;
+      pl->st = sd;
+      ChainRun& r = runs[j];
+      r.pl = pl;
+      r.L = o->n_leapfrog;
+      r.todo = o->n_iter;
+      r.need_grad = !(o->resume && pl->chain_ready);
+      if (r.need_grad) {
+        const uint64_t seed = o->seeds ? o->seeds[j] : o->seed + (uint64_t)j;
+        k_chain_init<<<1, 1, 0, s0>>>(pl->cs, o->eps0, o->target_accept, seed, o->warmup, o->jitter_eps);
+        LAUNCH_CHECK();
       }
-      HIP_TRY(hipMemcpyAsync(pl->qs0, q_snl[j], sizeof(double), hipMemcpyDeviceToDevice, s));
-      st = trajectory(pl, o->n_leapfrog, &pl->cs->eps_it, q, qd, q_snl[j], pl->pm, pl->pd, pl->ps);
-      if (st != HAMLET_OK) return st;
-      st = kinetic(pl, pl->pm, pl->pd, pl->ps, &pl->cs->kin1);
-      if (st != HAMLET_OK) return st;
-      k_accept<<<1, 1, 0, s>>>(pl->cs, o->seed, (uint32_t)it, o->warmup, dh ? dh[j] : nullptr,
-                               accepted ? accepted[j] : nullptr);
-      k_restore_modes<<<blocks_for(nm, kEltThreads), kEltThreads, 0, s>>>(pl->cs, q, pl->q0, pl->gcache, pl->g0,
-                                                                           nm);
-      k_restore_small<<<blocks_for(ng1, kEltThreads), kEltThreads, 0, s>>>(pl->cs, qd, pl->qd0, pl->gd, pl->gd0,
-                                                                           q_snl[j], pl->qs0, pl->n_gal);
-      if (it >= o->warmup && mode_sum && mode_sum[j])
-        k_accumulate<<<blocks_for(nm, kEltThreads), kEltThreads, 0, s>>>((double2*)mode_sum[j], q, nm);
-      LAUNCH_CHECK();
     }
   }
-  if (eps_out) {
-    for (int j = 0; j < n_plans; ++j) {
-      hamlet_plan* pl = plans[j];
-      HIP_TRY(hipMemcpyAsync(&eps_out[j], &pl->cs->eps, sizeof(double), hipMemcpyDeviceToHost, pl->stream));
-      HIP_TRY(hipStreamSynchronize(pl->stream));
+  std::vector<std::vector<ChainRun*>> group_runs(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi)
+    for (int j : groups[gi]) group_runs[gi].push_back(&runs[j]);
+  for (;;) {
+    bool any = false;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      bool act = false;
+      for (ChainRun* r : group_runs[gi]) act = act || r->active();
+      if (!act) continue;
+      any = true;
+      if ((st = tick_group(plans[groups[gi][0]]->stream, group_runs[gi])) != HAMLET_OK) return st;
     }
+    if (!any) break;
+  }
+  for (int j = 0; j < n_plans; ++j) plans[j]->chain_ready = true;
+  for (const std::vector<int>& g : groups) {
+    if (eps_out) {
+      hipStream_t s0 = plans[g[0]]->stream;
+      for (int j : g) HIP_TRY(hipMemcpyAsync(&eps_out[j], &plans[j]->cs->eps, sizeof(double), hipMemcpyDeviceToHost, s0));
+      HIP_TRY(hipStreamSynchronize(s0));
+    }
+    if ((st = streams_release(plans, g)) != HAMLET_OK) return st;
   }
   return HAMLET_OK;
 }

@@ -8,6 +8,7 @@
 
 #include "common.hpp"
 #include "passes.hpp"
+#include "workspace.hpp"
 
 namespace hamlet {
 
@@ -88,92 +89,9 @@ k_fill_mode_var(double* __restrict__ mvar, const double* __restrict__ var_n2, in
 }
 
 // ---------------------------------------------------------------------------
-// Momentum refresh p ~ N(0, M).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kEltThreads)
-k_momenta_modes(double2* __restrict__ p, ModeTables tab, int n, uint64_t seed, uint32_t iteration) {
-  const size_t total = (size_t)n * n * (n / 2);
-  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const ModeIdx m = mode_idx(g, n);
-  double2 out = make_double2(0.0, 0.0);
-  if (retained(m.sx, m.sy, m.kz, n)) {
-    const bool mir = is_mirror(m);
-    size_t src = g;
-    if (mir) src = ((size_t)((n - m.x) & (n - 1)) * n + ((n - m.y) & (n - 1))) * (n / 2);
-    const double2 z = normal_pair(draw_words(seed, iteration, kPurposeModes, src));
-    const double sc = sqrt(2.0 * inv_or_zero(tab.var[g]));
-    out = make_double2(sc * z.x, mir ? -sc * z.y : sc * z.y);
-  }
-  p[g] = out;
-}
-
-__global__ void __launch_bounds__(kEltThreads)
-k_momenta_small(double* __restrict__ p_dist, double* __restrict__ p_snl, int n_gal, double inv_sqrt_minv_d,
-                int sample_d, int sample_s, uint64_t seed, uint32_t iteration) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_gal) {
-    p_dist[i] = sample_d ? inv_sqrt_minv_d * normal_pair(draw_words(seed, iteration, kPurposeDist, i)).x : 0.0;
-  }
-  if (i == 0) p_snl[0] = sample_s ? normal_pair(draw_words(seed, iteration, kPurposeSnl, 0)).x : 0.0;
-}
-
-// ---------------------------------------------------------------------------
-// Kinetic energy K = (1/2) p^T M^-1 p: per stored mode (w_k / 8) sigma^2 |p|^2
-// (w_k = 1 on kz = 0 where both Hermitian partners are stored, else 2).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kEltThreads)
-k_kinetic_modes(const double2* __restrict__ p, ModeTables tab, int n, double* __restrict__ part) {
-  __shared__ double red[kEltThreads / 64];
-  const size_t total = (size_t)n * n * (n / 2);
-  double acc = 0.0;
-  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (size_t)gridDim.x * blockDim.x) {
-    const ModeIdx m = mode_idx(g, n);
-    if (retained(m.sx, m.sy, m.kz, n)) {
-      const double2 v = p[g];
-      acc += (m.kz == 0 ? 0.125 : 0.25) * tab.var[g] * (v.x * v.x + v.y * v.y);
-    }
-  }
-  const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// Sums the mode partials and adds (1/2) M_d^-1 sum p_d^2 + (1/2) M_s^-1 p_s^2.
-__global__ void __launch_bounds__(256)
-k_kinetic_final(const double* __restrict__ part, int n_part, const double* __restrict__ p_dist, int n_gal,
-                const double* __restrict__ p_snl, double minv_d, double minv_s, double* __restrict__ out) {
-  __shared__ double red[4];
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < n_part; i += blockDim.x) a += part[i];
-  for (int i = threadIdx.x; i < n_gal; i += blockDim.x) b += p_dist[i] * p_dist[i];
-  a = block_sum(a, red);
-  b = block_sum(b, red);
-  if (threadIdx.x == 0) out[0] = a + 0.5 * minv_d * b + 0.5 * minv_s * p_snl[0] * p_snl[0];
-}
-
-// First half kick (from the cached gradient) and drift of the distances and
-// of s: p -= (eps/2) g, q += eps M^-1 p.
-__global__ void __launch_bounds__(kEltThreads)
-k_small_kick_drift(double* __restrict__ q_dist, double* __restrict__ p_dist, const double* __restrict__ g_dist,
-                   double* __restrict__ q_snl, double* __restrict__ p_snl, const double* __restrict__ g_snl,
-                   int n_gal, int sample_d, int sample_s, double minv_d, const double* __restrict__ eps) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const double e = eps[0];
-  if (i < n_gal && sample_d) {
-    const double pv = p_dist[i] - 0.5 * e * g_dist[i];
-    p_dist[i] = pv;
-    q_dist[i] += e * minv_d * pv;
-  }
-  if (i == 0 && sample_s) {
-    const double pv = p_snl[0] - 0.5 * e * g_snl[0];
-    p_snl[0] = pv;
-    q_snl[0] += e * pv;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Chain scalars kept on the device so a whole run is enqueued without a
-// host round trip.
+// host round trip.  Each chain has its own seed and iteration counter, so a
+// chain draws the same numbers whichever other chains share its launches.
 // ---------------------------------------------------------------------------
 struct ChainScalars {
   double eps;          // step size of the chain (adapted during warm-up)
@@ -183,12 +101,24 @@ struct ChainScalars {
   double psi_saved, gs_saved;  // at the start of the trajectory
   double kin0, kin1;
   double target;
-  int accept;
+  uint64_t seed;
+  int iter;            // iterations done by this chain
+  int warmup;          // adaptation iterations
+  int jitter;          // jitter the step by U(0.9, 1.1)
+  int accept;          // last iteration accepted
+  int post;            // last iteration was past warm-up
 };
+static_assert(sizeof(ChainScalars) <= FixedLayout<16, 8>::chain_bytes, "chain scalars block");
 
-__global__ void k_set_scalar(double* dst, double v) { dst[0] = v; }
+template <typename T, int N> __device__ __forceinline__ ChainScalars* chain(const Ws<T, N>& w) {
+  return w.template at<ChainScalars>(Ws<T, N>::F::chain);
+}
 
-__global__ void k_chain_init(ChainScalars* cs, double eps0, double target) {
+__global__ void k_set_scalar(double* dst, double v) {
+  if (threadIdx.x == 0) dst[0] = v;
+}
+
+__global__ void k_chain_init(ChainScalars* cs, double eps0, double target, uint64_t seed, int warmup, int jitter) {
   cs->eps = eps0;
   cs->eps_it = eps0;
   cs->da_mu = log(10.0 * eps0);
@@ -196,15 +126,136 @@ __global__ void k_chain_init(ChainScalars* cs, double eps0, double target) {
   cs->da_log_eps_bar = 0.0;
   cs->da_m = 0.0;
   cs->target = target;
+  cs->seed = seed;
+  cs->iter = 0;
+  cs->warmup = warmup;
+  cs->jitter = jitter;
   cs->accept = 0;
+  cs->post = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Momentum refresh p ~ N(0, M).
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__(kEltThreads) k_momenta_modes(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  const size_t total = (size_t)N * N * (N / 2);
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const ChainScalars* cs = chain(k.w);
+  const uint64_t seed = cs->seed;
+  const uint32_t iteration = (uint32_t)cs->iter;
+  const ModeIdx m = mode_idx(g, N);
+  double2 out = make_double2(0.0, 0.0);
+  if (retained(m.sx, m.sy, m.kz, N)) {
+    const bool mir = is_mirror(m);
+    size_t src = g;
+    if (mir) src = ((size_t)((N - m.x) & (N - 1)) * N + ((N - m.y) & (N - 1))) * (N / 2);
+    const double2 z = normal_pair(draw_words(seed, iteration, kPurposeModes, src));
+    const double sc = sqrt(2.0 * inv_or_zero(k.w.mvar()[g]));
+    out = make_double2(sc * z.x, mir ? -sc * z.y : sc * z.y);
+  }
+  k.w.pm()[g] = out;
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(kEltThreads) k_momenta_small(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const PlanConst& pc = k.w.pc();
+  const ChainScalars* cs = chain(k.w);
+  const uint64_t seed = cs->seed;
+  const uint32_t iteration = (uint32_t)cs->iter;
+  if (i < k.n_gal) {
+    k.w.pd()[i] = pc.sample_d ? pc.psd * normal_pair(draw_words(seed, iteration, kPurposeDist, i)).x : 0.0;
+  }
+  if (i == 0) k.w.ps()[0] = pc.sample_s ? normal_pair(draw_words(seed, iteration, kPurposeSnl, 0)).x : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Kinetic energy K = (1/2) p^T M^-1 p: per stored mode (w_k / 8) sigma^2 |p|^2
+// (w_k = 1 on kz = 0 where both Hermitian partners are stored, else 2).
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__(kEltThreads) k_kinetic_modes(Launch L) {
+  __shared__ double red[kEltThreads / 64];
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  const double2* __restrict__ p = k.w.pm();
+  const double* __restrict__ var = k.w.mvar();
+  const size_t total = (size_t)N * N * (N / 2);
+  double acc = 0.0;
+  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (size_t)gridDim.x * blockDim.x) {
+    const ModeIdx m = mode_idx(g, N);
+    if (retained(m.sx, m.sy, m.kz, N)) {
+      const double2 v = p[g];
+      acc += (m.kz == 0 ? 0.125 : 0.25) * var[g] * (v.x * v.x + v.y * v.y);
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) k.w.kin_part()[blockIdx.x] = s;
+}
+
+// Sums the mode partials and adds (1/2) M_d^-1 sum p_d^2 + (1/2) M_s^-1 p_s^2
+// into kin0 (which = 0, before the trajectory) or kin1 (after).
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_kinetic_final(Launch L, int which) {
+  __shared__ double red[4];
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  const PlanConst& pc = k.w.pc();
+  const double* __restrict__ kin = k.w.kin_part();
+  const double* __restrict__ pd = k.w.pd();
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < pc.n_kin_part; i += blockDim.x) a += kin[i];
+  for (int i = threadIdx.x; i < k.n_gal; i += blockDim.x) b += pd[i] * pd[i];
+  a = block_sum(a, red);
+  b = block_sum(b, red);
+  if (threadIdx.x == 0) {
+    const double minv_s = pc.sample_s ? 1.0 : 0.0;
+    const double ps = k.w.ps()[0];
+    const double e = a + 0.5 * pc.minv_d * b + 0.5 * minv_s * ps * ps;
+    ChainScalars* cs = chain(k.w);
+    if (which) cs->kin1 = e;
+    else cs->kin0 = e;
+  }
+}
+
+// First half kick (from the cached gradient) and drift of the distances and
+// of s: p -= (eps/2) g, q += eps M^-1 p.
+template <typename T, int N>
+__global__ void __launch_bounds__(kEltThreads) k_small_kick_drift(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  const StateDev& st = k.st;
+  const PlanConst& pc = k.w.pc();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double e = st.eps[0];
+  if (i < k.n_gal && pc.sample_d) {
+    const double pv = st.pd[i] - 0.5 * e * st.gd[i];
+    st.pd[i] = pv;
+    st.qd[i] += e * pc.minv_d * pv;
+  }
+  if (i == 0 && pc.sample_s) {
+    const double pv = st.ps[0] - 0.5 * e * st.gs[0];
+    st.ps[0] = pv;
+    st.qs[0] += e * pv;
+  }
 }
 
 // Start of an iteration: the (optionally jittered) step, and the state's
 // Psi / dPsi/ds saved for a possible rejection.
-__global__ void k_iter_begin(ChainScalars* cs, uint64_t seed, uint32_t iteration, int jitter) {
+template <typename T, int N>
+__global__ void k_iter_begin(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip || threadIdx.x != 0) return;
+  ChainScalars* cs = chain(k.w);
   double e = cs->eps;
-  if (jitter) {
-    const Philox4 w = draw_words(seed, iteration, kPurposeJitter, 0);
+  if (cs->jitter) {
+    const Philox4 w = draw_words(cs->seed, (uint32_t)cs->iter, kPurposeJitter, 0);
     e = e * (0.9 + 0.2 * uniform53(w.v[0], w.v[1]));
   }
   cs->eps_it = e;
@@ -212,19 +263,44 @@ __global__ void k_iter_begin(ChainScalars* cs, uint64_t seed, uint32_t iteration
   cs->gs_saved = cs->gs;
 }
 
+// Copies of the start of the trajectory (modes, cached gradient, distances,
+// their gradient, s) for a possible rejection.
+template <typename T, int N>
+__global__ void __launch_bounds__(kEltThreads) k_save_state(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  const size_t total = (size_t)N * N * (N / 2);
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < total) {
+    k.w.q0()[i] = k.st.q[i];
+    k.w.g0()[i] = k.w.gcache()[i];
+  }
+  if (i < (size_t)k.n_gal) {
+    k.w.qd0()[i] = k.st.qd[i];
+    k.w.gd0()[i] = k.w.gd()[i];
+  }
+  if (i == 0) k.w.qs0()[0] = k.st.qs[0];
+}
+
 // Metropolis-Hastings test of the end point (Section 3.2) and dual
-// averaging of the step (Hoffman & Gelman) during warm-up.
-__global__ void k_accept(ChainScalars* cs, uint64_t seed, uint32_t iteration, int warmup,
-                         double* __restrict__ dh_out, int32_t* __restrict__ acc_out) {
+// averaging of the step (Hoffman & Gelman) during warm-up; advances the
+// chain's iteration counter.
+template <typename T, int N>
+__global__ void k_accept(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip || threadIdx.x != 0) return;
+  ChainScalars* cs = chain(k.w);
+  const int it = cs->iter;
   double dh = (cs->kin1 + cs->psi) - (cs->kin0 + cs->psi_saved);
   if (!isfinite(dh)) dh = __builtin_inf();
-  const Philox4 w = draw_words(seed, iteration, kPurposeAccept, 0);
+  const Philox4 w = draw_words(cs->seed, (uint32_t)it, kPurposeAccept, 0);
   const double u = uniform53(w.v[0], w.v[1]);
   const int acc = log(u) < -dh ? 1 : 0;
   cs->accept = acc;
-  if (dh_out) dh_out[iteration] = dh;
-  if (acc_out) acc_out[iteration] = acc;
-  if ((int)iteration < warmup) {
+  cs->post = it >= cs->warmup ? 1 : 0;
+  if (k.st.dh) k.st.dh[it] = dh;
+  if (k.st.acc) k.st.acc[it] = acc;
+  if (it < cs->warmup) {
     const double alpha = !isfinite(dh) ? 0.0 : (dh <= 0.0 ? 1.0 : exp(-dh));
     cs->da_m += 1.0;
     const double m = cs->da_m;
@@ -233,46 +309,57 @@ __global__ void k_accept(ChainScalars* cs, uint64_t seed, uint32_t iteration, in
     const double log_eps = cs->da_mu - sqrt(m) / 0.05 * cs->da_hbar;
     const double wgt = pow(m, -0.75);
     cs->da_log_eps_bar = wgt * log_eps + (1.0 - wgt) * cs->da_log_eps_bar;
-    cs->eps = ((int)iteration == warmup - 1) ? exp(cs->da_log_eps_bar) : exp(log_eps);
+    cs->eps = (it == cs->warmup - 1) ? exp(cs->da_log_eps_bar) : exp(log_eps);
   }
   if (!acc) {
     cs->psi = cs->psi_saved;
     cs->gs = cs->gs_saved;
   }
+  cs->iter = it + 1;
 }
 
-// On rejection restore the saved state and its cached gradient.
-__global__ void __launch_bounds__(kEltThreads)
-k_restore_modes(const ChainScalars* __restrict__ cs, double2* __restrict__ q, const double2* __restrict__ q0,
-                double2* __restrict__ g, const double2* __restrict__ g0, size_t total) {
-  if (cs->accept) return;
+// After the test: on rejection restore the saved state and its cached
+// gradient; past warm-up add the (possibly restored) modes to the running
+// sum of samples.
+template <typename T, int N>
+__global__ void __launch_bounds__(kEltThreads) k_restore_accumulate(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  const size_t total = (size_t)N * N * (N / 2);
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  q[i] = q0[i];
-  g[i] = g0[i];
+  const ChainScalars* cs = chain(k.w);
+  const int rejected = !cs->accept;
+  if (i < total) {
+    double2 q;
+    if (rejected) {
+      q = k.w.q0()[i];
+      k.st.q[i] = q;
+      k.w.gcache()[i] = k.w.g0()[i];
+    } else {
+      q = k.st.q[i];
+    }
+    if (cs->post && k.st.msum) {
+      double2 a = k.st.msum[i];
+      a.x += q.x;
+      a.y += q.y;
+      k.st.msum[i] = a;
+    }
+  }
+  if (rejected) {
+    if (i < (size_t)k.n_gal) {
+      k.st.qd[i] = k.w.qd0()[i];
+      k.w.gd()[i] = k.w.gd0()[i];
+    }
+    if (i == 0) k.st.qs[0] = k.w.qs0()[0];
+  }
 }
 
-__global__ void __launch_bounds__(kEltThreads)
-k_restore_small(const ChainScalars* __restrict__ cs, double* __restrict__ qd, const double* __restrict__ qd0,
-                double* __restrict__ gd, const double* __restrict__ gd0, double* __restrict__ qs,
-                const double* __restrict__ qs0, int n_gal) {
-  if (cs->accept) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_gal) { qd[i] = qd0[i]; gd[i] = gd0[i]; }
-  if (i == 0) qs[0] = qs0[0];
+// End of a leapfrog call: Psi of the end point to the caller's slot.
+template <typename T, int N>
+__global__ void k_leap_out(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip || threadIdx.x != 0) return;
+  k.st.psi_out[0] = chain(k.w)->psi;
 }
-
-__global__ void __launch_bounds__(kEltThreads)
-k_accumulate(double2* __restrict__ sum, const double2* __restrict__ q, size_t total) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  double2 a = sum[i];
-  const double2 b = q[i];
-  a.x += b.x;
-  a.y += b.y;
-  sum[i] = a;
-}
-
-__global__ void k_copy_gs(const ChainScalars* cs, double* out_eps) { out_eps[0] = cs->eps; }
 
 }  // namespace hamlet

@@ -27,6 +27,7 @@
 
 #include "common.hpp"
 #include "fft.hpp"
+#include "workspace.hpp"
 
 namespace hamlet {
 
@@ -111,8 +112,8 @@ template <int N> __device__ __forceinline__ size_t gofs(int i, int j, int kz) {
 // Tile: fixed ky, kz chunk, all kx.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int NT>
-__global__ void __launch_bounds__(NT)
-k_inv_x(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* __restrict__ tw,
+__device__ __forceinline__ void
+inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* __restrict__ tw,
         cplx_t<T>* __restrict__ outA, cplx_t<T>* __restrict__ outB, double* __restrict__ prior_part) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
@@ -157,8 +158,8 @@ k_inv_x(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* __re
 // Inverse pass 2 (along y).  Tile: fixed x, kz chunk, all ky.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int NT>
-__global__ void __launch_bounds__(NT)
-k_inv_y(const cplx_t<T>* __restrict__ inA, const cplx_t<T>* __restrict__ inB, const cplx_t<T>* __restrict__ tw,
+__device__ __forceinline__ void
+inv_y_body(const cplx_t<T>* __restrict__ inA, const cplx_t<T>* __restrict__ inB, const cplx_t<T>* __restrict__ tw,
         cplx_t<T>* __restrict__ vx, cplx_t<T>* __restrict__ vy, cplx_t<T>* __restrict__ vz, int x0) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
@@ -215,8 +216,8 @@ __device__ __forceinline__ int zslot_part(int p, int c) {
 // into part[4 s + corner], corner = 2 (x - ix) + (y - iy).
 // ---------------------------------------------------------------------------
 template <typename T, int N, int NT>
-__global__ void __launch_bounds__(NT)
-k_inv_z_gather(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ vy, const cplx_t<T>* __restrict__ vz,
+__device__ __forceinline__ void
+inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ vy, const cplx_t<T>* __restrict__ vz,
                const cplx_t<T>* __restrict__ tw, Binned<T> bins, cplx_t<T>* __restrict__ part, int x0) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
@@ -287,8 +288,8 @@ k_inv_z_gather(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ v
 // Outputs Gx, Gy and n_z Gz on kz in [0, N/2).  Grid (N / P, N).
 // ---------------------------------------------------------------------------
 template <typename T, int N, int NT>
-__global__ void __launch_bounds__(NT)
-k_fwd_z_scatter(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>* __restrict__ tw,
+__device__ __forceinline__ void
+fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>* __restrict__ tw,
                 cplx_t<T>* __restrict__ gx, cplx_t<T>* __restrict__ gy, cplx_t<T>* __restrict__ gz, int x0) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
@@ -348,8 +349,8 @@ k_fwd_z_scatter(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>* __
 // Tile: fixed x, kz chunk, all ky.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int NT>
-__global__ void __launch_bounds__(NT)
-k_fwd_y(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, const cplx_t<T>* __restrict__ gz,
+__device__ __forceinline__ void
+fwd_y_body(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, const cplx_t<T>* __restrict__ gz,
         const cplx_t<T>* __restrict__ tw, cplx_t<T>* __restrict__ s1, cplx_t<T>* __restrict__ s2, int x0) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
@@ -393,14 +394,12 @@ k_fwd_y(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, cons
 //   kXLast  : G from S1, S2; kick p -= (eps/2) G; write G to `gcache`.
 // (eq:hamilton integrated by kick-drift-kick leapfrog, mass matrix eq:M_ab.)
 // ---------------------------------------------------------------------------
-enum XMode { kXGrad = 0, kXFirst = 1, kXMid = 2, kXLast = 3 };
-
 template <typename T, int N, int MODE, int NT>
-__global__ void __launch_bounds__(NT)
-k_x_pass(const cplx_t<T>* __restrict__ s1, const cplx_t<T>* __restrict__ s2, double2* __restrict__ modes,
-         double2* __restrict__ mom, double2* __restrict__ gcache, ModeTables tab, const cplx_t<T>* __restrict__ tw,
-         const double* __restrict__ eps_ptr, cplx_t<T>* __restrict__ outA, cplx_t<T>* __restrict__ outB,
-         double* __restrict__ prior_part, double plane_scale) {
+__device__ __forceinline__ void
+x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ modes, double2* __restrict__ mom,
+            double2* __restrict__ gcache, ModeTables tab, const cplx_t<T>* __restrict__ tw,
+            const double* __restrict__ eps_ptr, cplx_t<T>* outA, cplx_t<T>* outB, double* __restrict__ prior_part,
+            double plane_scale) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Row;
@@ -496,6 +495,68 @@ k_x_pass(const cplx_t<T>* __restrict__ s1, const cplx_t<T>* __restrict__ s2, dou
     (void)prior_part;
     (void)bin;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Shared launches: blockIdx.z selects the plan.  The x pass reads S1, S2
+// from a, b and, in the leapfrog modes, writes the next A, B over them
+// (every tile reads its own entries before it writes them).
+// ---------------------------------------------------------------------------
+template <typename T, int N> __device__ __forceinline__ ModeTables tables(const Ws<T, N>& w) {
+  return ModeTables{w.mvar(), w.pc().kfac0};
+}
+
+template <typename T, int N> __device__ __forceinline__ Binned<T> binned(const Ws<T, N>& w) {
+  Binned<T> b;
+  b.off = w.off();
+  b.rx = w.rx(); b.ry = w.ry(); b.rz = w.rz();
+  b.tx = w.tx(); b.ty = w.ty(); b.tz = w.tz();
+  b.iz = w.iz();
+  return b;
+}
+
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT) k_inv_x(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode != kXGrad) return;
+  inv_x_body<T, N, NT>(k.st.q, tables(k.w), k.w.tw(), k.w.a(), k.w.b(), k.w.prior_part());
+}
+
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT) k_inv_y(Launch L, int x0) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  inv_y_body<T, N, NT>(k.w.a(), k.w.b(), k.w.tw(), k.w.v0(), k.w.v1(), k.w.v2(), x0);
+}
+
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT) k_inv_z_gather(Launch L, int x0) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  inv_z_gather_body<T, N, NT>(k.w.v0(), k.w.v1(), k.w.v2(), k.w.tw(), binned(k.w), k.w.part(), x0);
+}
+
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT) k_fwd_z_scatter(Launch L, int x0) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  fwd_z_scatter_body<T, N, NT>(k.w.gsort(), binned(k.w), k.w.tw(), k.w.v0(), k.w.v1(), k.w.v2(), x0);
+}
+
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT) k_fwd_y(Launch L, int x0) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  fwd_y_body<T, N, NT>(k.w.v0(), k.w.v1(), k.w.v2(), k.w.tw(), k.w.a(), k.w.b(), x0);
+}
+
+// One launch per mode present in a batch; plans in another mode return.
+template <typename T, int N, int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_x_pass(Launch L, double plane_scale) {
+  const Pick<T, N> k(L);
+  if (k.mode != MODE) return;
+  x_pass_body<T, N, MODE, NT>(k.w.a(), k.w.b(), k.st.q, k.st.p, k.st.g, tables(k.w), k.w.tw(), k.st.eps, k.w.a(),
+                              k.w.b(), k.w.prior_part(), plane_scale);
 }
 
 }  // namespace hamlet

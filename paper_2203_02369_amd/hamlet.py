@@ -193,8 +193,12 @@ def leapfrog(plans, eps, n_steps, q_modes, q_dist, q_snl, p_modes, p_dist, p_snl
 
 
 def hmc_run(plans, q_modes, q_dist, q_snl, *, n_iter, n_leapfrog, eps0, seed, warmup=0, jitter=False,
-            target_accept=0.65, mode_sum=None, dh=None, accepted=None, want_eps=True):
-    """Runs the HMC chains (hamlet_hmc_run); returns the post-warm-up steps."""
+            target_accept=0.65, mode_sum=None, dh=None, accepted=None, want_eps=True, seeds=None, resume=False):
+    """Runs the HMC chains (hamlet_hmc_run); returns the post-warm-up steps.
+
+    Chain j's key is seeds[j] when given, else seed + j.  resume=True
+    continues each plan's chain from its previous run (then dh/accepted are
+    indexed by the chain's own iteration count)."""
     plans, hp = _plans(plans)
     nplan = len(plans)
     qm = [_check(t, p, "modes", "q_modes") for t, p in zip(q_modes, plans)]
@@ -209,7 +213,13 @@ def hmc_run(plans, q_modes, q_dist, q_snl, *, n_iter, n_leapfrog, eps0, seed, wa
                 if t.numel() < n_iter:
                     raise ValueError("%s needs n_iter entries" % what)
     opts = HmcOpts(n_iter=int(n_iter), n_leapfrog=int(n_leapfrog), warmup=int(warmup), jitter_eps=int(bool(jitter)),
-                   eps0=float(eps0), target_accept=float(target_accept), seed=int(seed) & 0xFFFFFFFFFFFFFFFF)
+                   eps0=float(eps0), target_accept=float(target_accept), seed=int(seed) & 0xFFFFFFFFFFFFFFFF,
+                   resume=int(bool(resume)))
+    if seeds is not None:
+        if len(seeds) != nplan:
+            raise ValueError("seeds needs one key per plan")
+        keys = (ctypes.c_uint64 * nplan)(*[int(k) & 0xFFFFFFFFFFFFFFFF for k in seeds])
+        opts.seeds = ctypes.cast(keys, ctypes.POINTER(ctypes.c_uint64))
     eps_out = (ctypes.c_double * nplan)() if want_eps else None
     lib = _capi.load()
     _capi.check(lib.hamlet_hmc_run(hp, nplan, ctypes.byref(opts), _vp(qm), _dpp(qd), _dpp(qs),
