@@ -14,6 +14,13 @@ Prints one JSON line.  value = gradient evaluations per second of the
 FP32-field / FP64-Hamiltonian path; the plain FP64 path is timed beside it
 with the same step size and seed ("fp64_path"), and the FP64 oracle is
 timed on the host cores ("cpu_baseline").
+
+    python bench.py --workload batched
+
+16 independent chains of uneven size (grids 64^3, 128^3, 256^3 in turn,
+2000 to 30 000 points) advanced together: chains of one grid size share
+every kernel launch.  value = gradient evaluations per second summed over
+the chains; the same chains advanced one at a time are timed beside it.
 """
 import argparse
 import json
@@ -61,6 +68,7 @@ def parse():
     ap.add_argument("--n-gal", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", choices=("paper", "batched"), default="paper")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (reference for traffic counters)")
     return ap.parse_args()
@@ -80,6 +88,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload == "batched":
+        return run_batched(args, dev)
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -223,6 +233,98 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def run_batched(args, dev):
+    import numpy as np
+    import torch
+
+    from paper_2203_02369_amd import hamlet, mocks
+
+    L = args.leapfrog
+    t0 = time.time()
+    ms = []
+    for j, (ng, n) in enumerate(mocks.batched_16_sizes()):
+        ms.append(mocks.make_mock(ng, 500.0, n, 200.0, "inv_r", (0.20, 0.25), seed=mocks.config_seed(4) + j))
+        log("mock %d: %d^3, %d points (%.0fs)" % (j, ng, n, time.time() - t0))
+    plans = [hamlet.Plan.from_mock(m, precision="fp32", device=dev) for m in ms]
+    qm = [torch.from_numpy(np.ascontiguousarray(m.dhat_true[:, :, : m.n_grid // 2])).to(dev) for m in ms]
+    qd = [torch.from_numpy(m.d_true.copy()).to(dev) for m in ms]
+    qs = [p.scalar(1.5) for p in plans]
+    seeds = [mocks.config_seed(4) + 100 + j for j in range(len(plans))]
+
+    # warm-up: every chain adapts its own step (dual averaging), all together
+    eps = hamlet.hmc_run(plans, qm, qd, qs, n_iter=args.warmup, n_leapfrog=L, eps0=0.002, seed=0, seeds=seeds,
+                         warmup=args.warmup, jitter=True)
+    log("warm-up: %d iterations, eps %s" % (args.warmup, " ".join("%.3g" % e for e in eps)))
+
+    # timed: shared launches, every chain continuing from its warm-up
+    lead = plans[[p.n_grid for p in plans].index(256)]
+    prof = hamlet.KernelTimer(lead, hamlet.PROFILE_KERNELS["fwd_x"])
+    acc = [torch.zeros(args.warmup + 2 * args.steps, dtype=torch.int32, device=dev) for _ in plans]
+    torch.cuda.synchronize()
+    prof.start()
+    t1 = time.perf_counter()
+    hamlet.hmc_run(plans, qm, qd, qs, n_iter=args.steps, n_leapfrog=L, eps0=0.002, seed=0, seeds=seeds,
+                   jitter=True, accepted=acc, resume=True, want_eps=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    kern_ms, kern_launches = prof.stop()
+    grads = len(plans) * args.steps * L
+    value = grads / dt
+    log("batched: %d chains x %d iterations x %d steps in %.3fs: %.1f grad/s" % (len(plans), args.steps, L, dt, value))
+
+    # the same chains one at a time
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for j, p in enumerate(plans):
+        hamlet.hmc_run([p], [qm[j]], [qd[j]], [qs[j]], n_iter=args.steps, n_leapfrog=L, eps0=0.002, seed=0,
+                       seeds=[seeds[j]], jitter=True, accepted=[acc[j]], resume=True, want_eps=False)
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t2
+    v_seq = grads / dt_seq
+    log("one at a time: %.3fs: %.1f grad/s" % (dt_seq, v_seq))
+    rate = float(np.mean([a.cpu().numpy()[args.warmup:].mean() for a in acc]))
+
+    # roofline of the x pass of the 256^3 group (5 chains per launch):
+    # per chain and iteration first 13c, L - 1 middle 13c, last 11c.
+    n256 = [p for p in plans if p.n_grid == 256]
+    c32 = 8 * 256 * 256 * 128
+    per_iter = len(n256) * c32 * (13 + 13 * (L - 1) + 11)
+    assert kern_launches == args.steps * (L + 1), (kern_launches, args.steps * (L + 1))
+    avg_ms = kern_ms / kern_launches
+    per_launch = per_iter * args.steps / kern_launches
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": "grad evals/s summed over 16 independent chains (64^3/128^3/256^3, 2000-30000 points)",
+        "value": round(value, 2),
+        "unit": "grad evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 fields, f64 Hamiltonian",
+        "data": "synthetic",
+        "config": {"workload": "batched: 16 chains, grids 64^3/128^3/256^3 in turn, n_j = 2000 + 28000 j / 15, "
+                               "box 500 Mpc/h, HMC iterations of %d leapfrog steps; chains of one grid size "
+                               "share every launch" % L,
+                   "chains": [[p.n_grid, p.n_gal] for p in plans], "leapfrog_steps": L,
+                   "acceptance": round(rate, 3), "grad_evals_timed": grads},
+        "one_at_a_time": {"value": round(v_seq, 2), "unit": "grad evals/s",
+                          "speedup_shared_vs_one_at_a_time": round(value / v_seq, 3)},
+        "roofline": {"bound": "hbm", "kernel": "k_x_pass<float, 256> over the five 256^3 chains of one launch",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": int(per_launch), "avg_launch_ms": round(avg_ms, 4),
+                     "launches": kern_launches},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    for p in plans:
+        p.close()
 
 
 if __name__ == "__main__":

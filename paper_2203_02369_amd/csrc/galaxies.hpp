@@ -103,25 +103,40 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* wsum, int* total
 }
 
 __device__ __forceinline__ void
-bin_scan_tiles_body(const int* __restrict__ count, int* __restrict__ off, int* __restrict__ bsum, int nkeys) {
+bin_scan_tiles_body(const int* __restrict__ count, int* __restrict__ off, int* __restrict__ bsum,
+                    int* __restrict__ bmax, int nkeys) {
   __shared__ int wsum[kScanTile / 64];
+  __shared__ int wmax[kScanTile / 64];
   __shared__ int total;
   const int k = blockIdx.x * kScanTile + threadIdx.x;
   const int c = k < nkeys ? count[k] : 0;
+  int m = c;
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
   const int ex = block_exclusive_scan(c, wsum, &total);
   if (k < nkeys) off[k] = ex;
-  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+  if (threadIdx.x == 0) {
+    bsum[blockIdx.x] = total;
+    int mb = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mb = max(mb, wmax[w]);
+    bmax[blockIdx.x] = mb;
+  }
 }
 
 __device__ __forceinline__ void
 bin_scan_add_body(int* __restrict__ count, int* __restrict__ off, int* __restrict__ cursor,
-               const int* __restrict__ bsum, int nkeys) {
+                  const int* __restrict__ bsum, const int* __restrict__ bmax, int* __restrict__ most, int nkeys) {
   __shared__ int base;
   if (threadIdx.x == 0) {
     int s = 0;
     for (int b = 0; b < (int)blockIdx.x; ++b) s += bsum[b];
     base = s;
-    if (blockIdx.x == gridDim.x - 1) off[nkeys] = s + bsum[blockIdx.x];
+    if (blockIdx.x == gridDim.x - 1) {
+      off[nkeys] = s + bsum[blockIdx.x];
+      int m = 0;
+      for (int b = 0; b < (int)gridDim.x; ++b) m = max(m, bmax[b]);
+      most[0] = m;
+    }
   }
   __syncthreads();
   const int k = blockIdx.x * kScanTile + threadIdx.x;
@@ -141,33 +156,36 @@ bin_place_body(const int* __restrict__ key, int* __restrict__ cursor, int* __res
   slot_gid[s] = i;
 }
 
-// Per bucket: order members by galaxy id (placement order is racy), then
-// write the sorted per-galaxy records used by the z passes.
+// Final position of each point in its column: the members of a column are
+// ordered by (z cell, galaxy id), so the z passes find the points of one z
+// cell as a contiguous run, and the order does not depend on the racy
+// placement.  One thread per point: its rank is a count over its column.
+// Writes the binned records used by the z passes and the likelihood.
 template <typename T>
 __device__ __forceinline__ void
-bin_sort_body(const int* __restrict__ off, int* __restrict__ slot_gid, const int* __restrict__ cell_z,
-              const double* __restrict__ frac, Catalogue cat, int nkeys, T* __restrict__ rx, T* __restrict__ ry,
-              T* __restrict__ rz, T* __restrict__ tx, T* __restrict__ ty, T* __restrict__ tz,
-              int* __restrict__ iz) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nkeys) return;
+bin_rank_body(const int* __restrict__ off, const int* __restrict__ key, const int* __restrict__ placed,
+              const int* __restrict__ cell_z, const double* __restrict__ frac, Catalogue cat, int* __restrict__ gid,
+              T* __restrict__ rx, T* __restrict__ ry, T* __restrict__ rz, T* __restrict__ tx, T* __restrict__ ty,
+              T* __restrict__ tz, int* __restrict__ iz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cat.n) return;
+  const int k = key[i], z = cell_z[i];
   const int s0 = off[k], s1 = off[k + 1];
-  for (int a = s0 + 1; a < s1; ++a) {
-    const int v = slot_gid[a];
-    int b = a - 1;
-    while (b >= s0 && slot_gid[b] > v) { slot_gid[b + 1] = slot_gid[b]; --b; }
-    slot_gid[b + 1] = v;
-  }
+  int rank = 0;
   for (int s = s0; s < s1; ++s) {
-    const int i = slot_gid[s];
-    rx[s] = (T)cat.rhat[3 * i + 0];
-    ry[s] = (T)cat.rhat[3 * i + 1];
-    rz[s] = (T)cat.rhat[3 * i + 2];
-    tx[s] = (T)frac[3 * i + 0];
-    ty[s] = (T)frac[3 * i + 1];
-    tz[s] = (T)frac[3 * i + 2];
-    iz[s] = cell_z[i];
+    const int j = placed[s];
+    const int zj = cell_z[j];
+    rank += (zj < z || (zj == z && j < i)) ? 1 : 0;
   }
+  const int pos = s0 + rank;
+  gid[pos] = i;
+  rx[pos] = (T)cat.rhat[3 * i + 0];
+  ry[pos] = (T)cat.rhat[3 * i + 1];
+  rz[pos] = (T)cat.rhat[3 * i + 2];
+  tx[pos] = (T)frac[3 * i + 0];
+  ty[pos] = (T)frac[3 * i + 1];
+  tz[pos] = (T)frac[3 * i + 2];
+  iz[pos] = z;
 }
 
 // ---------------------------------------------------------------------------
@@ -321,14 +339,14 @@ template <typename T, int N>
 __global__ void __launch_bounds__(kScanTile) k_bin_scan_tiles(Launch L) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
-  bin_scan_tiles_body(k.w.count(), k.w.off(), k.w.bsum(), N * N);
+  bin_scan_tiles_body(k.w.count(), k.w.off(), k.w.bsum(), k.w.bmax(), N * N);
 }
 
 template <typename T, int N>
 __global__ void __launch_bounds__(kScanTile) k_bin_scan_add(Launch L) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
-  bin_scan_add_body(k.w.count(), k.w.off(), k.w.cursor(), k.w.bsum(), N * N);
+  bin_scan_add_body(k.w.count(), k.w.off(), k.w.cursor(), k.w.bsum(), k.w.bmax(), k.w.most(), N * N);
 }
 
 template <typename T, int N>
@@ -339,11 +357,11 @@ __global__ void __launch_bounds__(kGalThreads) k_bin_place(Launch L) {
 }
 
 template <typename T, int N>
-__global__ void __launch_bounds__(kGalThreads) k_bin_sort(Launch L) {
+__global__ void __launch_bounds__(kGalThreads) k_bin_rank(Launch L) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
-  bin_sort_body<T>(k.w.off(), k.w.slot(), k.w.cellz(), k.w.frac(), catalogue(k.w, k.n_gal), N * N, k.w.rx(),
-                   k.w.ry(), k.w.rz(), k.w.tx(), k.w.ty(), k.w.tz(), k.w.iz());
+  bin_rank_body<T>(k.w.off(), k.w.key(), k.w.slot(), k.w.cellz(), k.w.frac(), catalogue(k.w, k.n_gal), k.w.gid(),
+                   k.w.rx(), k.w.ry(), k.w.rz(), k.w.tx(), k.w.ty(), k.w.tz(), k.w.iz());
 }
 
 // Leapfrog update fused into the galaxy kernels: merged kicks with a drift
@@ -369,7 +387,7 @@ __global__ void __launch_bounds__(kGalThreads) k_like(Launch L) {
   LikeOut lo;
   lo.g_dist = k.st.gd;
   lo.part = k.w.like_part();
-  like_body<T>(k.w.part(), k.w.slot(), k.w.frac(), k.st.qd, k.st.qs, catalogue(k.w, k.n_gal), cosmo(k.w),
+  like_body<T>(k.w.part(), k.w.gid(), k.w.frac(), k.st.qd, k.st.qs, catalogue(k.w, k.n_gal), cosmo(k.w),
                k.w.gsort(), lo, leap_update(k.mode, pc.sample_d, k.st.pd, k.st.eps, pc.minv_d));
 }
 

@@ -86,7 +86,7 @@ struct hamlet_plan {
   double *var = nullptr, *mvar = nullptr, *hist = nullptr;
   void* tw = nullptr;
   double *rhat = nullptr, *mu = nullptr, *smu = nullptr, *cz = nullptr, *scz = nullptr;
-  int *count = nullptr, *off = nullptr;
+  int *count = nullptr, *off = nullptr, *most = nullptr;
   double2* gcache = nullptr;
   double2* pm = nullptr;
   double *gd = nullptr, *qd0 = nullptr, *pd = nullptr, *ps = nullptr, *eps_slot = nullptr;
@@ -183,7 +183,7 @@ static hamlet_status eval_impl(const Batch& b) {
     k_bin_scan_tiles<T, N><<<dim3(tiles, 1, nb), kScanTile, 0, st>>>(sel);
     k_bin_scan_add<T, N><<<dim3(tiles, 1, nb), kScanTile, 0, st>>>(sel);
     k_bin_place<T, N><<<g_gal, kGalThreads, 0, st>>>(sel);
-    k_bin_sort<T, N><<<dim3(blocks_for((size_t)N * N, kGalThreads), 1, nb), kGalThreads, 0, st>>>(sel);
+    k_bin_rank<T, N><<<g_gal, kGalThreads, 0, st>>>(sel);
     prof_after(b, HAMLET_K_BIN);
     LAUNCH_CHECK();
   }
@@ -310,6 +310,7 @@ template <typename T, int N> static void locate_impl(hamlet_plan* pl) {
   pl->rhat = w.rhat(); pl->mu = w.mu(); pl->smu = w.smu(); pl->cz = w.cz(); pl->scz = w.scz();
   pl->count = w.count();
   pl->off = w.off();
+  pl->most = w.most();
   pl->gcache = w.gcache();
   pl->pm = w.pm();
   pl->gd = w.gd(); pl->qd0 = w.qd0(); pl->pd = w.pd(); pl->ps = w.ps(); pl->eps_slot = w.eps_slot();
@@ -441,6 +442,7 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
   }
   HIP_TRY(hipMemsetAsync(pl->count, 0, (size_t)n * n * sizeof(int), st));
   HIP_TRY(hipMemsetAsync(pl->off, 0, ((size_t)n * n + 1) * sizeof(int), st));
+  HIP_TRY(hipMemsetAsync(pl->most, 0, sizeof(int), st));
   PlanConst pc{};
   pc.n_gal = pl->n_gal;
   pc.n_hist = pl->n_hist;

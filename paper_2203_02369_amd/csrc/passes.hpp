@@ -193,6 +193,7 @@ template <typename T> struct Binned {
   const T* rx; const T* ry; const T* rz;   // rhat
   const T* tx; const T* ty; const T* tz;   // fractional offsets in the cell
   const int* iz;           // lower z node
+  const int* most;         // most points in one column
 };
 
 // Transform slot of the real pencil of component c of pencil p in a z tile:
@@ -278,45 +279,186 @@ inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict_
   }
 }
 
+// First index in [lo, hi) of the ascending z cells `iz` with iz[s] >= v.
+template <typename I>
+__device__ __forceinline__ int lower_bound_cell(const I* iz, int lo, int hi, int v) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((int)iz[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// The binned points of the stencil columns of a z tile (columns x and x - 1,
+// rows y0 - 1 .. y0 + P - 1) are at most four contiguous ranges of the
+// binned arrays: rows max(y0 - 1, 0) .. y0 + P - 1 of each column index, and
+// row N - 1 when y0 = 0.  Crowded tiles stage them in LDS when they fit.
+template <typename T, int CAP> struct ZStage {
+  T g[CAP], tx[CAP], ty[CAP], tz[CAP], r[3][CAP];
+  int16_t iz[CAP];
+  int start[4], at[4], count;   // range start in the binned arrays, its index in the stage
+};
+
+// Index in the stage of binned index s of the column (x - ox, y).
+__device__ __forceinline__ int stage_index(const int* start, const int* at, int s, int ox, bool wrap_row) {
+  const int r = 2 * ox + (wrap_row ? 1 : 0);
+  return s - start[r] + at[r];
+}
+
 // ---------------------------------------------------------------------------
 // Forward pass 1 (along z, real-to-complex) fused with the CIC scatter-add:
-// each real pencil of the tile is built in LDS from the galaxies whose
-// stencil touches it, one thread per (pencil, component) adding
-// contributions in a fixed order (corner, then sorted index), so the result
-// is deterministic.
 //   G_c(x_j) = sum_i g_i rhat_ic W_i(x_j)  (adjoint of the gather)
+// Each real pencil of the tile is built in LDS, every node summing its
+// contributions in a fixed order, so the result is deterministic.
+//  * Sparse grids (no column holds more than 8 points): one thread per
+//    (pencil, component) adds the points of its four stencil columns,
+//    corner by corner in binned order.
+//  * Crowded grids: the points of a column are sorted by z cell, so the
+//    points that reach node j are two runs per stencil column (z cell j - 1
+//    with weight tz, then z cell j with weight 1 - tz); G lanes share each
+//    (pencil, component) row, lane l owning the nodes of one z segment, and
+//    node j sums in the order (corner, run, binned index) whatever G is.  The
+//    tile's points are staged in LDS when they fit.
+// G follows the most crowded column of the grid (found by the binning scan).
 // Outputs Gx, Gy and n_z Gz on kz in [0, N/2).  Grid (N / P, N).
 // ---------------------------------------------------------------------------
 template <typename T, int N, int NT>
 __device__ __forceinline__ void
 fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>* __restrict__ tw,
-                cplx_t<T>* __restrict__ gx, cplx_t<T>* __restrict__ gy, cplx_t<T>* __restrict__ gz, int x0) {
+                   cplx_t<T>* __restrict__ gx, cplx_t<T>* __restrict__ gy, cplx_t<T>* __restrict__ gz, int x0) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Pen;
   constexpr int P = S::P, H = S::H, F = S::F;
+  constexpr int GMAX_T = NT / (3 * P) >= 16 ? 16 : (NT / (3 * P) >= 8 ? 8 : (NT / (3 * P) >= 4 ? 4 : 1));
+  constexpr int GMAX = GMAX_T < N ? GMAX_T : N;
+  // stage capacity (points); the FP64 path keeps its LDS for occupancy and
+  // reads crowded columns from the binned arrays
+  constexpr int CAP = sizeof(T) == 4 ? 256 : 1;
   __shared__ C buf[LAY::size(F)];
   __shared__ C twl[N];
+  __shared__ int col[4 * P][2];     // binned range of the 4 stencil columns of each pencil
+  __shared__ ZStage<T, CAP> stg;
   load_twiddles<T, N, NT>(twl, tw);
   for (int i = threadIdx.x; i < LAY::size(F); i += NT) buf[i] = cmake<C>((T)0, (T)0);
-  __syncthreads();
   const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
-  if (threadIdx.x < 3 * P) {
-    const int p = threadIdx.x / 3, c = threadIdx.x % 3, y = y0 + p;
-    const int f = zslot_f(p, c), part = zslot_part(p, c);
-    T* row = reinterpret_cast<T*>(buf);
-    for (int corner = 0; corner < 4; ++corner) {
-      const int ox = corner >> 1, oy = corner & 1;
-      const int key = ((x - ox + N) & (N - 1)) * N + ((y - oy + N) & (N - 1));
-      const int s0 = bins.off[key], s1 = bins.off[key + 1];
-      for (int s = s0; s < s1; ++s) {
-        const T tx = bins.tx[s], ty = bins.ty[s], tz = bins.tz[s];
-        const T wxy = (ox ? tx : (T)1 - tx) * (oy ? ty : (T)1 - ty);
-        const T rc = c == 0 ? bins.rx[s] : (c == 1 ? bins.ry[s] : bins.rz[s]);
-        const T val = gsort[s] * wxy * rc;
-        const int z0 = bins.iz[s], z1 = (z0 + 1) & (N - 1);
-        row[2 * LAY::idx(z0, f) + part] += val * ((T)1 - tz);
-        row[2 * LAY::idx(z1, f) + part] += val * tz;
+  const int most = bins.most[0];
+  int G = 1;
+  while (G < GMAX && 8 * G < most) G <<= 1;
+  T* row = reinterpret_cast<T*>(buf);
+  if (G == 1) {
+    __syncthreads();
+    if (threadIdx.x < 3 * P) {
+      const int p = threadIdx.x / 3, c = threadIdx.x % 3, y = y0 + p;
+      const int f = zslot_f(p, c), part = zslot_part(p, c);
+      for (int corner = 0; corner < 4; ++corner) {
+        const int ox = corner >> 1, oy = corner & 1;
+        const int key = ((x - ox + N) & (N - 1)) * N + ((y - oy + N) & (N - 1));
+        const int s0 = bins.off[key], s1 = bins.off[key + 1];
+        for (int s = s0; s < s1; ++s) {
+          const T tx = bins.tx[s], ty = bins.ty[s], tz = bins.tz[s];
+          const T wxy = (ox ? tx : (T)1 - tx) * (oy ? ty : (T)1 - ty);
+          const T rc = c == 0 ? bins.rx[s] : (c == 1 ? bins.ry[s] : bins.rz[s]);
+          const T val = gsort[s] * wxy * rc;
+          const int z0 = bins.iz[s], z1 = (z0 + 1) & (N - 1);
+          row[2 * LAY::idx(z0, f) + part] += val * ((T)1 - tz);
+          row[2 * LAY::idx(z1, f) + part] += val * tz;
+        }
+      }
+    }
+  } else {
+    static_assert(4 * P + 4 <= 64, "tile set-up runs in the first wave");
+    if (threadIdx.x < 64) {
+      // lanes 0 .. 4P-1: the stencil columns; lanes 4P .. 4P+3: the four ranges
+      const int t = threadIdx.x;
+      int a = 0, b = 0;
+      if (t < 4 * P) {
+        const int p = t >> 2, corner = t & 3;
+        const int ox = corner >> 1, oy = corner & 1;
+        const int key = ((x - ox + N) & (N - 1)) * N + ((y0 + p - oy + N) & (N - 1));
+        a = bins.off[key];
+        b = bins.off[key + 1];
+        col[t][0] = a;
+        col[t][1] = b;
+      } else if (t < 4 * P + 4) {
+        const int r = t - 4 * P, ox = r >> 1, wrap = r & 1;
+        const int kx = ((x - ox + N) & (N - 1)) * N;
+        if (!wrap) {
+          a = bins.off[kx + (y0 > 0 ? y0 - 1 : 0)];
+          b = bins.off[kx + y0 + P];
+        } else if (y0 == 0) {
+          a = bins.off[kx + N - 1];
+          b = bins.off[kx + N];
+        }
+        stg.start[r] = a;
+      }
+      // stage offsets of the four ranges
+      const int len = (t >= 4 * P && t < 4 * P + 4) ? b - a : 0;
+      const int l0 = __shfl(len, 4 * P, 64), l1 = __shfl(len, 4 * P + 1, 64);
+      const int l2 = __shfl(len, 4 * P + 2, 64), l3 = __shfl(len, 4 * P + 3, 64);
+      if (t == 0) {
+        stg.at[0] = 0;
+        stg.at[1] = l0;
+        stg.at[2] = l0 + l1;
+        stg.at[3] = l0 + l1 + l2;
+        stg.count = l0 + l1 + l2 + l3;
+      }
+    }
+    __syncthreads();
+    const bool staged = CAP > 1 && stg.count <= CAP;   // block-uniform
+    if (staged) {
+      for (int i = threadIdx.x; i < stg.count; i += NT) {
+        int r = 0;
+        while (r < 3 && i >= stg.at[r + 1]) ++r;
+        const int s = stg.start[r] + (i - stg.at[r]);
+        stg.g[i] = gsort[s];
+        stg.tx[i] = bins.tx[s];
+        stg.ty[i] = bins.ty[s];
+        stg.tz[i] = bins.tz[s];
+        stg.r[0][i] = bins.rx[s];
+        stg.r[1][i] = bins.ry[s];
+        stg.r[2][i] = bins.rz[s];
+        stg.iz[i] = (int16_t)bins.iz[s];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x < 3 * P * G) {
+      const int lane = threadIdx.x % G, pc = threadIdx.x / G;
+      const int p = pc / 3, c = pc % 3;
+      const int seg = N / G, za = lane * seg, zb = za + seg;
+      const int zl = (za - 1) & (N - 1);
+      const int f = zslot_f(p, c), part = zslot_part(p, c);
+      const T* rcs = c == 0 ? bins.rx : (c == 1 ? bins.ry : bins.rz);
+      for (int corner = 0; corner < 4; ++corner) {
+        const int s0 = col[4 * p + corner][0], s1 = col[4 * p + corner][1];
+        if (s0 == s1) continue;
+        const int ox = corner >> 1, oy = corner & 1;
+        // the run of z cell za - 1 puts its upper weight on node za; cells
+        // za .. zb - 1 put their lower weight on node z and their upper weight
+        // on node z + 1 inside the segment
+        auto scatter = [&](auto g_, auto tx_, auto ty_, auto tz_, auto r_, auto iz_, int lo, int hi) {
+          auto value = [&](int s) {
+            const T tx = tx_[s], ty = ty_[s];
+            const T wxy = (ox ? tx : (T)1 - tx) * (oy ? ty : (T)1 - ty);
+            return g_[s] * wxy * r_[s];
+          };
+          for (int s = lower_bound_cell(iz_, lo, hi, zl); s < hi && (int)iz_[s] == zl; ++s)
+            row[2 * LAY::idx(za, f) + part] += value(s) * tz_[s];
+          for (int s = lower_bound_cell(iz_, lo, hi, za); s < hi && (int)iz_[s] < zb; ++s) {
+            const int z = iz_[s];
+            const T v = value(s), tz = tz_[s];
+            row[2 * LAY::idx(z, f) + part] += v * ((T)1 - tz);
+            if (z + 1 < zb) row[2 * LAY::idx(z + 1, f) + part] += v * tz;
+          }
+        };
+        if (staged) {
+          const bool wrap_row = y0 == 0 && p - oy < 0;
+          const int lo = stage_index(stg.start, stg.at, s0, ox, wrap_row);
+          scatter(stg.g, stg.tx, stg.ty, stg.tz, stg.r[c], stg.iz, lo, lo + (s1 - s0));
+        } else {
+          scatter(gsort, bins.tx, bins.ty, bins.tz, rcs, bins.iz, s0, s1);
+        }
       }
     }
   }
@@ -512,6 +654,7 @@ template <typename T, int N> __device__ __forceinline__ Binned<T> binned(const W
   b.rx = w.rx(); b.ry = w.ry(); b.rz = w.rz();
   b.tx = w.tx(); b.ty = w.ty(); b.tz = w.tz();
   b.iz = w.iz();
+  b.most = w.most();
   return b;
 }
 

@@ -84,9 +84,10 @@ template <int N, int R> struct FixedLayout {
   static constexpr size_t off = align256(count + 4 * size_t(N) * N);
   static constexpr size_t cursor = align256(off + 4 * (size_t(N) * N + 1));
   static constexpr size_t bsum = align256(cursor + 4 * size_t(N) * N);
-  static constexpr size_t prior_part = align256(bsum + 4 * ((size_t(N) * N + 1023) / 1024));
+  static constexpr size_t bmax = align256(bsum + 4 * ((size_t(N) * N + 1023) / 1024));
+  static constexpr size_t prior_part = align256(bmax + 4 * ((size_t(N) * N + 1023) / 1024));
   static constexpr size_t kin_part = align256(prior_part + 8 * size_t(N_PRIOR));
-  static constexpr size_t small = align256(kin_part + 8 * size_t(N_KIN));   // qs0, ps, eps_slot
+  static constexpr size_t small = align256(kin_part + 8 * size_t(N_KIN));   // qs0, ps, eps_slot, most
   static constexpr size_t mvar = align256(small + 256);
   static constexpr size_t a = align256(mvar + 8 * NM);
   static constexpr size_t b = a + 2 * R * NM;
@@ -110,7 +111,8 @@ template <int R> struct GalaxyUnits {
   static constexpr size_t like_part = 14;  // 3 doubles per block of 256 galaxies
   static constexpr size_t key = 15, cellz = 16, slot = 17, iz = 18;   // ints
   static constexpr size_t rx = 19, ry = 20, rz = 21, tx = 22, ty = 23, tz = 24, gsort = 25;   // reals
-  static constexpr size_t part = 26;       // 4 complex reals per galaxy
+  static constexpr size_t gid = 26;        // galaxy id in binned order
+  static constexpr size_t part = 27;       // 4 complex reals per galaxy
   static constexpr size_t count = part + (R == 4 ? 4 : 8);
 };
 
@@ -146,6 +148,8 @@ template <typename T, int N> struct Ws {
   __host__ __device__ double* qs0() const { return at<double>(F::small); }
   __host__ __device__ double* ps() const { return at<double>(F::small + 8); }
   __host__ __device__ double* eps_slot() const { return at<double>(F::small + 16); }
+  __host__ __device__ int* most() const { return at<int>(F::small + 24); }   // most points in one column
+  __host__ __device__ int* bmax() const { return at<int>(F::bmax); }
   __host__ __device__ double* mvar() const { return at<double>(F::mvar); }
   __host__ __device__ C* a() const { return at<C>(F::a); }
   __host__ __device__ C* b() const { return at<C>(F::b); }
@@ -170,6 +174,7 @@ template <typename T, int N> struct Ws {
   __host__ __device__ int* key() const { return gal<int>(G::key); }
   __host__ __device__ int* cellz() const { return gal<int>(G::cellz); }
   __host__ __device__ int* slot() const { return gal<int>(G::slot); }
+  __host__ __device__ int* gid() const { return gal<int>(G::gid); }
   __host__ __device__ int* iz() const { return gal<int>(G::iz); }
   __host__ __device__ T* rx() const { return gal<T>(G::rx); }
   __host__ __device__ T* ry() const { return gal<T>(G::ry); }

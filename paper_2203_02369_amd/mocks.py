@@ -269,6 +269,20 @@ def paper_scale_256(n_gal=30000, n_grid=256, seed=None):
                      seed=config_seed(3) if seed is None else seed)
 
 
+def batched_16_sizes():
+    """(N, n) of the 16 independent chains of the batched workload: grids
+    64^3, 128^3, 256^3 in turn, catalogues from 2000 to 30 000 points."""
+    grids = (64, 128, 256)
+    return [(grids[j % 3], 2000 + (28000 * j) // 15) for j in range(16)]
+
+
+def batched_16():
+    """16 mock problems of uneven size (box 500 Mpc/h, n ~ 1/r to 200 Mpc/h,
+    20-25 % distance errors, one seed each)."""
+    return [make_mock(ng, 500.0, n, 200.0, "inv_r", (0.20, 0.25), seed=config_seed(4) + j)
+            for j, (ng, n) in enumerate(batched_16_sizes())]
+
+
 def small_case(n_grid=16, box=200.0, n_gal=300, radius=80.0, seed=7):
     """A tiny problem for oracle-only pins."""
     return make_mock(n_grid, box, n_gal, radius, "sphere", (0.2, 0.2), seed=seed)
