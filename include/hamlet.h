@@ -184,6 +184,61 @@ hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_plans, const h
                              void* const* mode_sum, double* const* dh, int32_t* const* accepted,
                              double* eps_out);
 
+/* ---- Serving: continuous batching of independent reconstruction jobs ----
+ *
+ * A server runs many chains (jobs) on one device.  Jobs are queued with
+ * their problem; on each tick the server admits queued jobs in arrival
+ * order while the next one's device footprint (plan workspace and chain
+ * state) fits its budget, and advances every running job by one leapfrog
+ * step: jobs of one grid size and precision share every kernel launch, a
+ * newly admitted job joins at its first tick, each job runs its own
+ * Metropolis-Hastings test at the end of each of its trajectories (Section
+ * 3.2), and a job leaves after its last iteration.  Each job's numbers do not
+ * depend on which other jobs run beside it.  Ticks are enqueued on the
+ * server's stream at most `ticks_ahead` ahead of the device. */
+typedef struct hamlet_server hamlet_server;
+
+typedef struct {
+  size_t hbm_budget;        /* device bytes the running jobs may hold */
+  int32_t max_running;      /* at most this many running jobs (<= 0: no limit) */
+  int32_t ticks_ahead;      /* <= 0: 2 */
+} hamlet_server_desc;
+
+typedef struct {
+  int32_t queued, running, finished;   /* finished: done on the device, not yet taken */
+  int64_t ticks;
+  size_t bytes_in_use;
+} hamlet_server_stats;
+
+/* `stream`: a hipStream_t for all of the server's work (NULL: default stream). */
+hamlet_status hamlet_server_create(const hamlet_server_desc* desc, void* stream, hamlet_server** out);
+/* Waits for the device and releases every job, taken or not. */
+hamlet_status hamlet_server_destroy(hamlet_server* server);
+
+/* Queues a job.  desc, cat: as for hamlet_plan_create (copied).  opts: the
+ * chain (n_iter iterations of n_leapfrog steps, warmup, step; opts->seed is
+ * the job's Philox key; resume and seeds are ignored).  Start state (host,
+ * copied): q_modes N*N*N/2 double complex or NULL (all modes zero), q_dist n
+ * doubles or NULL (the redshift distances d_z of eq:e:dz), q_snl.  A job that
+ * could never fit the budget is rejected (HAMLET_ENOMEM). */
+hamlet_status hamlet_server_submit(hamlet_server* server, const hamlet_plan_desc* desc, const hamlet_catalog* cat,
+                                   const hamlet_hmc_opts* opts, const double* q_modes, const double* q_dist,
+                                   double q_snl, int64_t* job_id);
+
+/* One tick (see above).  stats may be NULL. */
+hamlet_status hamlet_server_tick(hamlet_server* server, hamlet_server_stats* stats);
+
+/* state: 0 queued, 1 running, 2 finished (all its work done on the device),
+ * -1 failed at admission (the tick that tried reported why). */
+hamlet_status hamlet_server_job_state(hamlet_server* server, int64_t job_id, int32_t* state);
+
+/* Copies a finished job's results to host memory and releases it; each
+ * pointer may be NULL.  mode_sum: N*N*N/2 double complex, the sum of the
+ * post-warm-up states (eq:int_mc numerator); q_modes, q_dist, q_snl: the last
+ * state; dh, accepted: n_iter; eps: the step after warm-up. */
+hamlet_status hamlet_server_take(hamlet_server* server, int64_t job_id, double* mode_sum, double* q_modes,
+                                 double* q_dist, double* q_snl, double* dh, int32_t* accepted, double* eps);
+
 /* Measurement aid.  Kernel kinds that can be timed with HIP events: */
 typedef enum {
   HAMLET_K_BIN = 0,         /* binning of the points into CIC columns (4 kernels, timed as one) */

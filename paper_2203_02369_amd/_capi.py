@@ -64,6 +64,24 @@ class HmcOpts(ctypes.Structure):
     ]
 
 
+class ServerDesc(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_size_t),
+        ("max_running", ctypes.c_int32),
+        ("ticks_ahead", ctypes.c_int32),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("queued", ctypes.c_int32),
+        ("running", ctypes.c_int32),
+        ("finished", ctypes.c_int32),
+        ("ticks", ctypes.c_int64),
+        ("bytes_in_use", ctypes.c_size_t),
+    ]
+
+
 # Every function the header declares, with its ctypes signature.
 SIGNATURES = {
     "hamlet_plan_create": (ctypes.c_int, [ctypes.POINTER(PlanDesc), ctypes.POINTER(Catalog), ctypes.c_void_p,
@@ -79,6 +97,16 @@ SIGNATURES = {
                                        c_double_pp, c_void_pp, c_double_pp, c_double_pp, c_double_pp]),
     "hamlet_hmc_run": (ctypes.c_int, [c_void_pp, ctypes.c_int32, ctypes.POINTER(HmcOpts), c_void_pp, c_double_pp,
                                       c_double_pp, c_void_pp, c_double_pp, ctypes.POINTER(c_int32_p), c_double_p]),
+    "hamlet_server_create": (ctypes.c_int, [ctypes.POINTER(ServerDesc), ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_void_p)]),
+    "hamlet_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "hamlet_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanDesc), ctypes.POINTER(Catalog),
+                                            ctypes.POINTER(HmcOpts), c_double_p, c_double_p, ctypes.c_double,
+                                            ctypes.POINTER(ctypes.c_int64)]),
+    "hamlet_server_tick": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    "hamlet_server_job_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, c_int32_p]),
+    "hamlet_server_take": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, c_double_p, c_double_p, c_double_p,
+                                          c_double_p, c_double_p, c_int32_p, c_double_p]),
     "hamlet_profile_start": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "hamlet_profile_stop": (ctypes.c_int, [ctypes.c_void_p, c_double_p, ctypes.POINTER(ctypes.c_int64)]),
     "hamlet_last_error": (ctypes.c_char_p, []),

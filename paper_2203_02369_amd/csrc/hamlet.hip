@@ -6,6 +6,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -89,7 +92,8 @@ struct hamlet_plan {
   int *count = nullptr, *off = nullptr, *most = nullptr;
   double2* gcache = nullptr;
   double2* pm = nullptr;
-  double *gd = nullptr, *qd0 = nullptr, *pd = nullptr, *ps = nullptr, *eps_slot = nullptr;
+  double *gd = nullptr, *qd0 = nullptr, *pd = nullptr, *ps = nullptr, *eps_slot = nullptr, *dz = nullptr;
+  bool pooled = false;             // workspace from the stream-ordered pool
   int n_prior_part = 0, n_like_part = 0, n_kin_part = 0;
   bool chain_ready = false;        // chain state and cached gradient valid (resume)
   const Ops* ops = nullptr;
@@ -314,6 +318,7 @@ template <typename T, int N> static void locate_impl(hamlet_plan* pl) {
   pl->gcache = w.gcache();
   pl->pm = w.pm();
   pl->gd = w.gd(); pl->qd0 = w.qd0(); pl->pd = w.pd(); pl->ps = w.ps(); pl->eps_slot = w.eps_slot();
+  pl->dz = w.dz();
   pl->n_prior_part = F::N_PRIOR;
   pl->n_like_part = pl->n_gal > 0 ? (int)blocks_for(pl->n_gal, kGalThreads) : 0;
   pl->n_kin_part = F::N_KIN;
@@ -385,38 +390,44 @@ static double redshift_distance(double z, double om) {
   return (kC / kH0) * (hstep / 3.0) * acc;
 }
 
-// Distance prior (eq:D): density histogram of the redshift distances, bins
-// of width w on [0, max d_z + 15), one pseudo-count per bin.
-static std::vector<double> distance_histogram(const hamlet_catalog* c, double om, double w) {
-  std::vector<double> dz(c->n);
+// Number of distance-prior bins (eq:D): width w on [0, max d_z + 15).  d_z
+// grows with z, so the largest redshift distance is that of the largest cz.
+static int distance_prior_bins(const hamlet_catalog* c, double om, double w) {
   double top = 0.0;
-  for (int64_t i = 0; i < c->n; ++i) {
-    dz[i] = redshift_distance(c->cz[i] / kC, om);
-    top = std::max(top, dz[i]);
+  if (c->n > 0) {
+    double zmax = c->cz[0];
+    for (int64_t i = 1; i < c->n; ++i) zmax = std::max(zmax, c->cz[i]);
+    top = std::max(0.0, redshift_distance(zmax / kC, om));
   }
-  const int nb = (int)std::ceil((top + 15.0) / w);
-  std::vector<double> cnt(nb, 0.0);
-  for (int64_t i = 0; i < c->n; ++i) {
-    long long b = (long long)std::floor(dz[i] / w);
-    b = std::min<long long>(std::max<long long>(b, 0), nb - 1);
-    cnt[b] += 1.0;
-  }
-  for (int b = 0; b < nb; ++b) cnt[b] = (cnt[b] + 1.0) / ((double)(c->n + nb) * w);
-  return cnt;
+  return (int)std::ceil((top + 15.0) / w);
 }
 
-static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const hamlet_catalog* c,
-                            const std::vector<double>& hist) {
+// Host values an upload reads from; they must outlive the upload (the
+// caller synchronises, or keeps them until the plan is done).
+struct Staging {
+  std::vector<double> var;
+  std::vector<double> twd;
+  std::vector<float> twf;
+  PlanConst pc{};
+};
+
+// Enqueues the plan's set-up on its stream: tables, twiddles, catalogue,
+// distance prior, constants.  Reads the catalogue arrays and `sg` until the
+// stream reaches the end of the set-up.
+static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const hamlet_catalog* c, Staging& sg) {
   const int n = pl->n;
   const size_t npk = 3 * (size_t)(n / 2) * (n / 2) + 1;
   const double kf = 2.0 * M_PI / pl->box;
   const double n3 = (double)n * n * n;
   const double vol = pl->box * pl->box * pl->box;
-  std::vector<double> var(npk);
+  std::vector<double>& var = sg.var;
+  var.resize(npk);
   for (size_t j = 0; j < npk; ++j) var[j] = n3 * n3 / vol * d->pk_n2[j];
   // Twiddles exp(-2 pi i m / N), computed in long double and rounded once.
-  std::vector<double> twd(2 * n);
-  std::vector<float> twf(2 * n);
+  std::vector<double>& twd = sg.twd;
+  std::vector<float>& twf = sg.twf;
+  twd.resize(2 * n);
+  twf.resize(2 * n);
   for (int m = 0; m < n; ++m) {
     const long double ang = -2.0L * 3.141592653589793238462643383279502884L * m / n;
     twd[2 * m] = (double)cosl(ang);
@@ -432,18 +443,24 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
     HIP_TRY(hipMemcpyAsync(pl->tw, twd.data(), twd.size() * 8, hipMemcpyHostToDevice, st));
   else
     HIP_TRY(hipMemcpyAsync(pl->tw, twf.data(), twf.size() * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(pl->hist, hist.data(), hist.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(pl->hist, 0, (size_t)pl->n_hist * 8, st));
   if (c->n > 0) {
     HIP_TRY(hipMemcpyAsync(pl->rhat, c->rhat, 3 * c->n * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(pl->mu, c->mu, c->n * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(pl->smu, c->sigma_mu, c->n * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(pl->cz, c->cz, c->n * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(pl->scz, c->sigma_cz, c->n * 8, hipMemcpyHostToDevice, st));
+    k_dist_prior_count<<<blocks_for(c->n, kGalThreads), kGalThreads, 0, st>>>(pl->cz, pl->n_gal, pl->om, pl->hist_w,
+                                                                               pl->n_hist, pl->dz, pl->hist);
+    LAUNCH_CHECK();
   }
+  k_dist_prior_norm<<<blocks_for(pl->n_hist, kGalThreads), kGalThreads, 0, st>>>(pl->hist, pl->n_hist, pl->n_gal,
+                                                                                 pl->hist_w);
+  LAUNCH_CHECK();
   HIP_TRY(hipMemsetAsync(pl->count, 0, (size_t)n * n * sizeof(int), st));
   HIP_TRY(hipMemsetAsync(pl->off, 0, ((size_t)n * n + 1) * sizeof(int), st));
   HIP_TRY(hipMemsetAsync(pl->most, 0, sizeof(int), st));
-  PlanConst pc{};
+  PlanConst& pc = sg.pc;
   pc.n_gal = pl->n_gal;
   pc.n_hist = pl->n_hist;
   pc.sample_d = pl->sample_d;
@@ -461,7 +478,6 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
   pc.psd = kH0 / pl->sigma_v;
   pc.kfac0 = kH0 * pl->f / ((double)pl->n * pl->n * pl->n * kf);
   HIP_TRY(hipMemcpyAsync(pl->consts, &pc, sizeof(pc), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipStreamSynchronize(st));
   return HAMLET_OK;
 }
 
@@ -497,8 +513,10 @@ extern "C" hamlet_status hamlet_plan_footprint_bytes(const hamlet_plan_desc* des
   return HAMLET_OK;
 }
 
-extern "C" hamlet_status hamlet_plan_create(const hamlet_plan_desc* desc, const hamlet_catalog* cat, void* stream,
-                                            hamlet_plan** out) {
+// Validates, allocates (from the stream-ordered pool when `pooled`) and
+// enqueues the set-up of a plan on `stream`, without waiting for it.
+static hamlet_status plan_make(const hamlet_plan_desc* desc, const hamlet_catalog* cat, hipStream_t stream,
+                               bool pooled, Staging& sg, hamlet_plan** out) {
   if (!out) return fail(HAMLET_EINVAL, "out is NULL");
   *out = nullptr;
   hamlet_status st = check_desc(desc);
@@ -506,31 +524,50 @@ extern "C" hamlet_status hamlet_plan_create(const hamlet_plan_desc* desc, const 
   st = check_catalog(cat);
   if (st != HAMLET_OK) return st;
   const double w = desc->hist_width > 0 ? desc->hist_width : 5.0;
-  std::vector<double> hist = distance_histogram(cat, desc->omega_m, w);
   hamlet_plan* pl = new hamlet_plan();
-  fill_plan_scalars(pl, desc, cat->n, (int)hist.size());
-  pl->stream = (hipStream_t)stream;
+  fill_plan_scalars(pl, desc, cat->n, distance_prior_bins(cat, desc->omega_m, w));
+  pl->stream = stream;
+  pl->pooled = pooled;
   pl->ops = pl->prec == HAMLET_FP64 ? pick_ops<double>(pl->n) : pick_ops<float>(pl->n);
   if (hipEventCreateWithFlags(&pl->order_ev, hipEventDisableTiming) != hipSuccess) {
     delete pl;
     return fail(HAMLET_EDEVICE, "hipEventCreateWithFlags failed");
   }
   pl->bytes = pl->ops->bytes(pl->n_gal, pl->n_hist);
-  if (hipMalloc((void**)&pl->base, pl->bytes) != hipSuccess) {
+  const hipError_t e = pooled ? hipMallocAsync((void**)&pl->base, pl->bytes, stream)
+                              : hipMalloc((void**)&pl->base, pl->bytes);
+  if (e != hipSuccess) {
     (void)hipEventDestroy(pl->order_ev);
     const size_t bytes = pl->bytes;
     delete pl;
-    return fail(HAMLET_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    return fail(HAMLET_ENOMEM, "allocation of %zu bytes failed", bytes);
   }
   pl->ops->locate(pl);
-  st = upload(pl, desc, cat, hist);
+  st = upload(pl, desc, cat, sg);
   if (st != HAMLET_OK) {
-    (void)hipFree(pl->base);
+    (void)hipStreamSynchronize(stream);
+    (void)(pooled ? hipFreeAsync(pl->base, stream) : hipFree(pl->base));
     (void)hipEventDestroy(pl->order_ev);
     delete pl;
     return st;
   }
   *out = pl;
+  return HAMLET_OK;
+}
+
+extern "C" hamlet_status hamlet_plan_create(const hamlet_plan_desc* desc, const hamlet_catalog* cat, void* stream,
+                                            hamlet_plan** out) {
+  Staging sg;
+  hamlet_status st = plan_make(desc, cat, (hipStream_t)stream, false, sg, out);
+  if (st != HAMLET_OK) return st;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+    hamlet_plan* pl = *out;
+    *out = nullptr;
+    (void)hipFree(pl->base);
+    (void)hipEventDestroy(pl->order_ev);
+    delete pl;
+    return fail(HAMLET_EDEVICE, "plan set-up failed on the device");
+  }
   return HAMLET_OK;
 }
 
@@ -541,7 +578,7 @@ extern "C" hamlet_status hamlet_plan_destroy(hamlet_plan* pl) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
   }
-  hipError_t e2 = hipFree(pl->base);
+  hipError_t e2 = pl->pooled ? hipFreeAsync(pl->base, pl->stream) : hipFree(pl->base);
   (void)hipEventDestroy(pl->order_ev);
   delete pl;
   if (e1 != hipSuccess || e2 != hipSuccess) return fail(HAMLET_EDEVICE, "plan destroy: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
@@ -880,6 +917,323 @@ extern "C" hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_pla
     }
     if ((st = streams_release(plans, g)) != HAMLET_OK) return st;
   }
+  return HAMLET_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching of independent jobs
+// ---------------------------------------------------------------------------
+struct Job {
+  int64_t id = 0;
+  int state = 0;                   // 0 queued, 1 running, 2 last tick enqueued, 3 done on the device,
+                                   // -1 failed at admission
+  // the request; uploads read from it, so it lives as long as the job
+  hamlet_plan_desc desc{};
+  std::vector<double> pk, rhat, mu, smu, cz, scz, q_modes, q_dist;
+  double q_snl = 1.0;
+  hamlet_hmc_opts opts{};
+  Staging sg;
+  size_t state_bytes = 0, bytes = 0;
+  // once admitted
+  hamlet_plan* plan = nullptr;
+  char* mem = nullptr;             // chain state: q, mode sum, distances, s, dH, accept flags
+  double2 *q = nullptr, *msum = nullptr;
+  double *qd = nullptr, *qs = nullptr, *dh = nullptr;
+  int32_t* acc = nullptr;
+  ChainRun run;
+  hipEvent_t done = nullptr;
+  hamlet_catalog catalog() const {
+    hamlet_catalog c;
+    c.n = (int64_t)mu.size();
+    c.rhat = rhat.data(); c.mu = mu.data(); c.sigma_mu = smu.data(); c.cz = cz.data(); c.sigma_cz = scz.data();
+    return c;
+  }
+};
+
+struct hamlet_server {
+  size_t budget = 0, in_use = 0;
+  int max_running = 0, ahead = 2;
+  hipStream_t stream = nullptr;
+  hipStream_t copy = nullptr;      // result copies, off the tick stream
+  std::vector<hipEvent_t> tick_ev;
+  int64_t ticks = 0, next_id = 1;
+  std::map<int64_t, std::unique_ptr<Job>> jobs;
+  std::deque<Job*> queue;
+  std::vector<Job*> running;       // state 1
+};
+
+// Chain state of a job: q and the mode sum (N^3 / 2 complex each), distances,
+// s, dH and accept flags (n_iter each).
+static size_t job_state_bytes(int n, int64_t n_gal, int n_iter) {
+  const size_t nm = (size_t)n * n * (n / 2);
+  return 2 * align256(16 * nm) + align256(8 * (size_t)std::max<int64_t>(n_gal, 1)) + 256 +
+         align256(8 * (size_t)std::max(n_iter, 1)) + align256(4 * (size_t)std::max(n_iter, 1));
+}
+
+static hamlet_status check_opts(const hamlet_hmc_opts* o) {
+  if (!o) return fail(HAMLET_EINVAL, "opts is NULL");
+  if (o->n_iter < 0 || o->n_leapfrog < 0 || o->warmup < 0)
+    return fail(HAMLET_EINVAL, "n_iter/n_leapfrog/warmup out of range");
+  if (!(o->eps0 > 0) || !std::isfinite(o->eps0)) return fail(HAMLET_EINVAL, "eps0 must be positive");
+  if (!(o->target_accept > 0 && o->target_accept < 1)) return fail(HAMLET_EINVAL, "target_accept must be in (0,1)");
+  return HAMLET_OK;
+}
+
+static void job_release(hamlet_server* sv, Job* j) {
+  if (j->plan) {
+    hamlet_plan* pl = j->plan;
+    (void)hipFreeAsync(pl->base, sv->stream);
+    for (auto& ev : pl->prof_pool) {
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+    (void)hipEventDestroy(pl->order_ev);
+    delete pl;
+    j->plan = nullptr;
+  }
+  if (j->mem) (void)hipFreeAsync(j->mem, sv->stream);
+  j->mem = nullptr;
+  if (j->done) (void)hipEventDestroy(j->done);
+  j->done = nullptr;
+  if (j->state >= 1) sv->in_use -= j->bytes;
+  j->state = j->state >= 1 ? 4 : j->state;   // released
+}
+
+extern "C" hamlet_status hamlet_server_create(const hamlet_server_desc* desc, void* stream, hamlet_server** out) {
+  if (!out) return fail(HAMLET_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(HAMLET_EINVAL, "desc is NULL");
+  if (desc->hbm_budget == 0) return fail(HAMLET_EINVAL, "hbm_budget is 0");
+  std::unique_ptr<hamlet_server> sv(new hamlet_server());
+  sv->budget = desc->hbm_budget;
+  sv->max_running = desc->max_running;
+  sv->ahead = desc->ticks_ahead > 0 ? desc->ticks_ahead : 2;
+  sv->stream = (hipStream_t)stream;
+  HIP_TRY(hipStreamCreateWithFlags(&sv->copy, hipStreamNonBlocking));
+  sv->tick_ev.resize(sv->ahead, nullptr);
+  for (hipEvent_t& e : sv->tick_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  *out = sv.release();
+  return HAMLET_OK;
+}
+
+extern "C" hamlet_status hamlet_server_destroy(hamlet_server* sv) {
+  if (!sv) return HAMLET_OK;
+  hipError_t e = hipStreamSynchronize(sv->stream);
+  for (auto& kv : sv->jobs) job_release(sv, kv.second.get());
+  if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+  for (hipEvent_t ev : sv->tick_ev) (void)hipEventDestroy(ev);
+  (void)hipStreamDestroy(sv->copy);
+  delete sv;
+  if (e != hipSuccess) return fail(HAMLET_EDEVICE, "server destroy: %s", hipGetErrorString(e));
+  return HAMLET_OK;
+}
+
+extern "C" hamlet_status hamlet_server_submit(hamlet_server* sv, const hamlet_plan_desc* desc,
+                                              const hamlet_catalog* cat, const hamlet_hmc_opts* opts,
+                                              const double* q_modes, const double* q_dist, double q_snl,
+                                              int64_t* job_id) {
+  if (!sv || !job_id) return fail(HAMLET_EINVAL, "NULL argument");
+  hamlet_status st = check_desc(desc);
+  if (st == HAMLET_OK) st = check_catalog(cat);
+  if (st == HAMLET_OK) st = check_opts(opts);
+  if (st != HAMLET_OK) return st;
+  if (!std::isfinite(q_snl)) return fail(HAMLET_EINVAL, "q_snl not finite");
+  std::unique_ptr<Job> j(new Job());
+  j->desc = *desc;
+  j->pk.assign(desc->pk_n2, desc->pk_n2 + desc->n_pk);
+  j->desc.pk_n2 = j->pk.data();
+  const int64_t n = cat->n;
+  if (n > 0) {
+    j->rhat.assign(cat->rhat, cat->rhat + 3 * n);
+    j->mu.assign(cat->mu, cat->mu + n);
+    j->smu.assign(cat->sigma_mu, cat->sigma_mu + n);
+    j->cz.assign(cat->cz, cat->cz + n);
+    j->scz.assign(cat->sigma_cz, cat->sigma_cz + n);
+  }
+  const size_t nm = (size_t)desc->n_grid * desc->n_grid * (desc->n_grid / 2);
+  if (q_modes) j->q_modes.assign(q_modes, q_modes + 2 * nm);
+  if (q_dist && n > 0) j->q_dist.assign(q_dist, q_dist + n);
+  j->q_snl = q_snl;
+  j->opts = *opts;
+  const Ops* ops = desc->precision == HAMLET_FP64 ? pick_ops<double>(desc->n_grid) : pick_ops<float>(desc->n_grid);
+  const double w = desc->hist_width > 0 ? desc->hist_width : 5.0;
+  const hamlet_catalog c = j->catalog();
+  j->state_bytes = job_state_bytes(desc->n_grid, n, opts->n_iter);
+  j->bytes = ops->bytes((int)n, distance_prior_bins(&c, desc->omega_m, w)) + j->state_bytes;
+  if (j->bytes > sv->budget)
+    return fail(HAMLET_ENOMEM, "job needs %zu device bytes, budget %zu", j->bytes, sv->budget);
+  j->id = sv->next_id++;
+  *job_id = j->id;
+  sv->queue.push_back(j.get());
+  sv->jobs[j->id] = std::move(j);
+  return HAMLET_OK;
+}
+
+// Creates the job's plan and chain state on the server's stream and
+// initialises its chain; it runs from the next tick on.
+static hamlet_status job_admit(hamlet_server* sv, Job* j) {
+  const hamlet_catalog c = j->catalog();
+  hamlet_status st = plan_make(&j->desc, &c, sv->stream, true, j->sg, &j->plan);
+  if (st != HAMLET_OK) return st;
+  hamlet_plan* pl = j->plan;
+  const size_t nm = pl->modes_count();
+  if (hipMallocAsync((void**)&j->mem, j->state_bytes, sv->stream) != hipSuccess) {
+    j->mem = nullptr;
+    return fail(HAMLET_ENOMEM, "allocation of %zu bytes failed", j->state_bytes);
+  }
+  char* m = j->mem;
+  j->q = (double2*)m;                 m += align256(16 * nm);
+  j->msum = (double2*)m;              m += align256(16 * nm);
+  j->qd = (double*)m;                 m += align256(8 * (size_t)std::max(pl->n_gal, 1));
+  j->qs = (double*)m;                 m += 256;
+  j->dh = (double*)m;                 m += align256(8 * (size_t)std::max(j->opts.n_iter, 1));
+  j->acc = (int32_t*)m;
+  hipStream_t s = sv->stream;
+  if (!j->q_modes.empty())
+    HIP_TRY(hipMemcpyAsync(j->q, j->q_modes.data(), 16 * nm, hipMemcpyHostToDevice, s));
+  else
+    HIP_TRY(hipMemsetAsync(j->q, 0, 16 * nm, s));
+  HIP_TRY(hipMemsetAsync(j->msum, 0, 16 * nm, s));
+  if (pl->n_gal > 0) {
+    if (!j->q_dist.empty())
+      HIP_TRY(hipMemcpyAsync(j->qd, j->q_dist.data(), 8 * (size_t)pl->n_gal, hipMemcpyHostToDevice, s));
+    else
+      HIP_TRY(hipMemcpyAsync(j->qd, pl->dz, 8 * (size_t)pl->n_gal, hipMemcpyDeviceToDevice, s));
+  }
+  k_set_scalar<<<1, 64, 0, s>>>(j->qs, j->q_snl);
+  k_chain_init<<<1, 1, 0, s>>>(pl->cs, j->opts.eps0, j->opts.target_accept, j->opts.seed, j->opts.warmup,
+                               j->opts.jitter_eps);
+  LAUNCH_CHECK();
+  StateDev sd{};
+  sd.q = j->q;
+  sd.qd = pl->n_gal ? j->qd : pl->qd0;
+  sd.qs = j->qs;
+  sd.p = pl->pm;
+  sd.pd = pl->pd;
+  sd.ps = pl->ps;
+  sd.g = pl->gcache;
+  sd.gd = pl->gd;
+  sd.gs = &pl->cs->gs;
+  sd.psi = &pl->cs->psi;
+  sd.eps = &pl->cs->eps_it;
+  sd.dh = j->dh;
+  sd.acc = j->acc;
+  sd.msum = j->msum;
+  pl->st = sd;
+  j->run.pl = pl;
+  j->run.L = j->opts.n_leapfrog;
+  j->run.todo = j->opts.n_iter;
+  j->run.need_grad = true;
+  HIP_TRY(hipEventCreateWithFlags(&j->done, hipEventDisableTiming));
+  return HAMLET_OK;
+}
+
+static int job_poll(Job* j) {
+  if (j->state == 2 && hipEventQuery(j->done) == hipSuccess) j->state = 3;
+  return j->state;
+}
+
+static void server_stats(hamlet_server* sv, hamlet_server_stats* out) {
+  if (!out) return;
+  out->queued = (int32_t)sv->queue.size();
+  out->running = 0;
+  out->finished = 0;
+  for (auto& kv : sv->jobs) {
+    const int s = job_poll(kv.second.get());
+    if (s == 1 || s == 2) ++out->running;
+    if (s == 3) ++out->finished;
+  }
+  out->ticks = sv->ticks;
+  out->bytes_in_use = sv->in_use;
+}
+
+extern "C" hamlet_status hamlet_server_tick(hamlet_server* sv, hamlet_server_stats* stats) {
+  if (!sv) return fail(HAMLET_EINVAL, "server is NULL");
+  hamlet_status st;
+  // keep at most `ahead` ticks queued on the device
+  if (sv->ticks >= sv->ahead) HIP_TRY(hipEventSynchronize(sv->tick_ev[sv->ticks % sv->ahead]));
+  // admission in arrival order, by device footprint
+  while (!sv->queue.empty()) {
+    Job* j = sv->queue.front();
+    if (sv->max_running > 0 && (int)sv->running.size() >= sv->max_running) break;
+    if (sv->in_use + j->bytes > sv->budget) break;
+    sv->queue.pop_front();
+    j->state = 1;
+    sv->in_use += j->bytes;
+    if ((st = job_admit(sv, j)) != HAMLET_OK) {
+      const std::string msg = g_last_error;
+      job_release(sv, j);
+      j->state = -1;
+      return fail(st, "job %lld not admitted: %s", (long long)j->id, msg.c_str());
+    }
+    sv->running.push_back(j);
+  }
+  // one leapfrog step of every running job; jobs of one grid size and
+  // precision share launches, up to kMaxBatch per launch
+  std::vector<bool> taken(sv->running.size(), false);
+  for (size_t a = 0; a < sv->running.size(); ++a) {
+    if (taken[a]) continue;
+    std::vector<ChainRun*> group;
+    const hamlet_plan* p0 = sv->running[a]->plan;
+    for (size_t b = a; b < sv->running.size() && (int)group.size() < kMaxBatch; ++b) {
+      const hamlet_plan* pb = sv->running[b]->plan;
+      if (taken[b] || pb->n != p0->n || pb->prec != p0->prec) continue;
+      taken[b] = true;
+      group.push_back(&sv->running[b]->run);
+    }
+    if ((st = tick_group(sv->stream, group)) != HAMLET_OK) return st;
+  }
+  // jobs whose last iteration was in this tick leave
+  std::vector<Job*> still;
+  for (Job* j : sv->running) {
+    if (j->run.active()) {
+      still.push_back(j);
+      continue;
+    }
+    HIP_TRY(hipEventRecord(j->done, sv->stream));
+    j->state = 2;
+  }
+  sv->running.swap(still);
+  HIP_TRY(hipEventRecord(sv->tick_ev[sv->ticks % sv->ahead], sv->stream));
+  ++sv->ticks;
+  server_stats(sv, stats);
+  return HAMLET_OK;
+}
+
+extern "C" hamlet_status hamlet_server_job_state(hamlet_server* sv, int64_t job_id, int32_t* state) {
+  if (!sv || !state) return fail(HAMLET_EINVAL, "NULL argument");
+  auto it = sv->jobs.find(job_id);
+  if (it == sv->jobs.end()) return fail(HAMLET_EINVAL, "no job %lld", (long long)job_id);
+  const int s = job_poll(it->second.get());
+  *state = s < 0 ? -1 : (s == 3 ? 2 : (s == 0 ? 0 : 1));
+  return HAMLET_OK;
+}
+
+extern "C" hamlet_status hamlet_server_take(hamlet_server* sv, int64_t job_id, double* mode_sum, double* q_modes,
+                                            double* q_dist, double* q_snl, double* dh, int32_t* accepted,
+                                            double* eps) {
+  if (!sv) return fail(HAMLET_EINVAL, "server is NULL");
+  auto it = sv->jobs.find(job_id);
+  if (it == sv->jobs.end()) return fail(HAMLET_EINVAL, "no job %lld", (long long)job_id);
+  Job* j = it->second.get();
+  if (j->state < 2) return fail(HAMLET_EINVAL, "job %lld has not finished", (long long)job_id);
+  HIP_TRY(hipEventSynchronize(j->done));
+  const hamlet_plan* pl = j->plan;
+  const size_t nm = pl->modes_count();
+  hipStream_t c = sv->copy;
+  if (mode_sum) HIP_TRY(hipMemcpyAsync(mode_sum, j->msum, 16 * nm, hipMemcpyDeviceToHost, c));
+  if (q_modes) HIP_TRY(hipMemcpyAsync(q_modes, j->q, 16 * nm, hipMemcpyDeviceToHost, c));
+  if (q_dist && pl->n_gal > 0)
+    HIP_TRY(hipMemcpyAsync(q_dist, j->qd, 8 * (size_t)pl->n_gal, hipMemcpyDeviceToHost, c));
+  if (q_snl) HIP_TRY(hipMemcpyAsync(q_snl, j->qs, 8, hipMemcpyDeviceToHost, c));
+  if (dh && j->opts.n_iter > 0)
+    HIP_TRY(hipMemcpyAsync(dh, j->dh, 8 * (size_t)j->opts.n_iter, hipMemcpyDeviceToHost, c));
+  if (accepted && j->opts.n_iter > 0)
+    HIP_TRY(hipMemcpyAsync(accepted, j->acc, 4 * (size_t)j->opts.n_iter, hipMemcpyDeviceToHost, c));
+  if (eps) HIP_TRY(hipMemcpyAsync(eps, &pl->cs->eps, 8, hipMemcpyDeviceToHost, c));
+  HIP_TRY(hipStreamSynchronize(c));
+  job_release(sv, j);
+  sv->jobs.erase(it);
   return HAMLET_OK;
 }
 

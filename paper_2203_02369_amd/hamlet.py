@@ -33,6 +33,25 @@ def _stream_handle(stream, device):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _problem(n_grid, box, omega_m, h, f_growth, sigma_v, pk_n2, rhat, mu, sigma_mu, cz, sigma_cz, hist_width,
+             precision, sample_distances, sample_sigma_nl):
+    """hamlet_plan_desc and hamlet_catalog of a problem, and the arrays they point into."""
+    pk = _f64(pk_n2)
+    rh = _f64(rhat).reshape(-1)
+    arrays = [_f64(mu), _f64(sigma_mu), _f64(cz), _f64(sigma_cz)]
+    n = len(arrays[0])
+    if rh.size != 3 * n or any(len(a) != n for a in arrays):
+        raise ValueError("catalogue arrays must all have length n (rhat: n x 3)")
+    desc = _capi.PlanDesc(n_grid=int(n_grid), precision=PRECISIONS[precision], box=float(box),
+                          omega_m=float(omega_m), h=float(h), f_growth=float(f_growth),
+                          sigma_v=float(sigma_v), pk_n2=_dptr(pk), n_pk=len(pk),
+                          hist_width=float(hist_width), sample_distances=int(bool(sample_distances)),
+                          sample_sigma_nl=int(bool(sample_sigma_nl)))
+    cat = _capi.Catalog(n=n, rhat=_dptr(rh), mu=_dptr(arrays[0]), sigma_mu=_dptr(arrays[1]),
+                        cz=_dptr(arrays[2]), sigma_cz=_dptr(arrays[3]))
+    return desc, cat, n, (pk, rh, arrays)
+
+
 class Plan:
     """A reconstruction problem resident on one GPU (hamlet_plan_create)."""
 
@@ -44,19 +63,8 @@ class Plan:
         self.n_grid = int(n_grid)
         self.precision = precision
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        pk = _f64(pk_n2)
-        rh = _f64(rhat).reshape(-1)
-        arrays = [_f64(mu), _f64(sigma_mu), _f64(cz), _f64(sigma_cz)]
-        n = len(arrays[0])
-        if rh.size != 3 * n or any(len(a) != n for a in arrays):
-            raise ValueError("catalogue arrays must all have length n (rhat: n x 3)")
-        desc = _capi.PlanDesc(n_grid=self.n_grid, precision=PRECISIONS[precision], box=float(box),
-                              omega_m=float(omega_m), h=float(h), f_growth=float(f_growth),
-                              sigma_v=float(sigma_v), pk_n2=_dptr(pk), n_pk=len(pk),
-                              hist_width=float(hist_width), sample_distances=int(bool(sample_distances)),
-                              sample_sigma_nl=int(bool(sample_sigma_nl)))
-        cat = _capi.Catalog(n=n, rhat=_dptr(rh), mu=_dptr(arrays[0]), sigma_mu=_dptr(arrays[1]),
-                            cz=_dptr(arrays[2]), sigma_cz=_dptr(arrays[3]))
+        desc, cat, n, _keep = _problem(n_grid, box, omega_m, h, f_growth, sigma_v, pk_n2, rhat, mu, sigma_mu, cz,
+                                       sigma_cz, hist_width, precision, sample_distances, sample_sigma_nl)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _capi.check(lib.hamlet_plan_create(ctypes.byref(desc), ctypes.byref(cat),
@@ -227,6 +235,104 @@ def hmc_run(plans, q_modes, q_dist, q_snl, *, n_iter, n_leapfrog, eps0, seed, wa
                                    _ipp(aa) if aa else None,
                                    ctypes.cast(eps_out, c_double_p) if want_eps else None))
     return list(eps_out) if want_eps else None
+
+
+# -- serving ---------------------------------------------------------------------
+
+SERVER_STATES = {-1: "failed", 0: "queued", 1: "running", 2: "finished"}
+
+
+class Server:
+    """Continuous batching of independent reconstruction jobs on one GPU
+    (hamlet_server_*): submit() queues a job, tick() admits what fits the
+    device budget and advances every running job by one leapfrog step,
+    take() returns a finished job's results as numpy arrays."""
+
+    def __init__(self, hbm_budget, *, max_running=0, ticks_ahead=2, stream=None, device=None):
+        lib = _capi.load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        desc = _capi.ServerDesc(hbm_budget=int(hbm_budget), max_running=int(max_running),
+                                ticks_ahead=int(ticks_ahead))
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _capi.check(lib.hamlet_server_create(ctypes.byref(desc), ctypes.c_void_p(self.stream.cuda_stream),
+                                                 ctypes.byref(handle)))
+        self._handle = handle
+        self._jobs = {}
+
+    @property
+    def handle(self):
+        if self._handle is None:
+            raise RuntimeError("server is closed")
+        return self._handle.value
+
+    def submit(self, *, n_iter, n_leapfrog, eps0, seed, warmup=0, jitter=False, target_accept=0.65,
+               q_modes=None, q_dist=None, q_snl=1.0, precision="fp32", hist_width=5.0, sample_distances=True,
+               sample_sigma_nl=True, **problem):
+        """Queue a job; `problem` holds the Plan keywords (n_grid, box, ...,
+        sigma_cz).  q_modes: complex (N, N, N/2) or None (zero field); q_dist:
+        (n,) or None (redshift distances)."""
+        desc, cat, n, _keep = _problem(hist_width=hist_width, precision=precision,
+                                       sample_distances=sample_distances, sample_sigma_nl=sample_sigma_nl,
+                                       **problem)
+        ng = int(problem["n_grid"])
+        opts = HmcOpts(n_iter=int(n_iter), n_leapfrog=int(n_leapfrog), warmup=int(warmup),
+                       jitter_eps=int(bool(jitter)), eps0=float(eps0), target_accept=float(target_accept),
+                       seed=int(seed) & 0xFFFFFFFFFFFFFFFF)
+        qm = None
+        if q_modes is not None:
+            qm = np.ascontiguousarray(np.asarray(q_modes, dtype=np.complex128))
+            if qm.shape != (ng, ng, ng // 2):
+                raise ValueError("q_modes must be complex (N, N, N/2)")
+        qd = None
+        if q_dist is not None:
+            qd = _f64(q_dist)
+            if qd.shape != (n,):
+                raise ValueError("q_dist must have n entries")
+        job = ctypes.c_int64()
+        _capi.check(_capi.load().hamlet_server_submit(
+            self.handle, ctypes.byref(desc), ctypes.byref(cat), ctypes.byref(opts),
+            qm.ctypes.data_as(c_double_p) if qm is not None else None,
+            _dptr(qd) if qd is not None else None, float(q_snl), ctypes.byref(job)))
+        self._jobs[job.value] = (ng, n, int(n_iter))
+        return job.value
+
+    def tick(self):
+        st = _capi.ServerStats()
+        _capi.check(_capi.load().hamlet_server_tick(self.handle, ctypes.byref(st)))
+        return {"queued": st.queued, "running": st.running, "finished": st.finished, "ticks": st.ticks,
+                "bytes_in_use": st.bytes_in_use}
+
+    def state(self, job):
+        out = ctypes.c_int32()
+        _capi.check(_capi.load().hamlet_server_job_state(self.handle, int(job), ctypes.byref(out)))
+        return SERVER_STATES[out.value]
+
+    def take(self, job):
+        ng, n, n_iter = self._jobs.pop(job)
+        res = {"mode_sum": np.zeros((ng, ng, ng // 2), np.complex128),
+               "q_modes": np.zeros((ng, ng, ng // 2), np.complex128),
+               "q_dist": np.zeros(n), "q_snl": np.zeros(1), "dh": np.zeros(n_iter),
+               "accepted": np.zeros(n_iter, np.int32), "eps": np.zeros(1)}
+        dp = {k: v.ctypes.data_as(c_double_p) for k, v in res.items() if k != "accepted"}
+        _capi.check(_capi.load().hamlet_server_take(
+            self.handle, int(job), dp["mode_sum"], dp["q_modes"], dp["q_dist"], dp["q_snl"], dp["dh"],
+            res["accepted"].ctypes.data_as(_capi.c_int32_p), dp["eps"]))
+        res["q_snl"] = float(res["q_snl"][0])
+        res["eps"] = float(res["eps"][0])
+        return res
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            _capi.check(_capi.load().hamlet_server_destroy(self._handle))
+        self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # -- measurement ---------------------------------------------------------------

@@ -1,0 +1,169 @@
+"""Served execution through the C ABI (hamlet_server_*): continuous batching
+of independent jobs with admission by device footprint.
+
+A job's results must not depend on the other jobs of the server: a served
+job is compared bit for bit with the same chain run by hamlet_hmc_run, and
+with itself served alone versus joining a running mix of other grid sizes
+and precisions.  Admission keeps the device bytes of the running jobs within
+the budget, in arrival order.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import model
+from paper_2203_02369_amd import _capi, mocks
+
+from helpers import start_modes, to_lib_layout
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_02369_amd import hamlet
+    return hamlet
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+GIB = 1 << 30
+CHAIN = dict(n_iter=6, n_leapfrog=4, eps0=2e-3, warmup=3, jitter=True)
+
+
+def _start(m, k):
+    rng = np.random.default_rng(300 + k)
+    return to_lib_layout(start_modes(m)), m.d_true * (1.0 + 0.02 * rng.standard_normal(m.n_gal)), 1.2 + 0.05 * k
+
+
+def _submit(sv, m, prec, seed, start, **chain):
+    qm, qd, qs = start
+    args = dict(CHAIN)
+    args.update(chain)
+    return sv.submit(q_modes=qm, q_dist=qd, q_snl=qs, precision=prec, seed=seed, **args, **m.problem_kwargs())
+
+
+def _drain(sv, jobs, limit=10000):
+    for _ in range(limit):
+        if all(sv.state(j) == "finished" for j in jobs):
+            return
+        sv.tick()
+    raise AssertionError("jobs did not finish")
+
+
+def _same(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in ("mode_sum", "q_modes", "q_dist", "q_snl", "dh", "accepted",
+                                                     "eps"))
+
+
+def test_served_job_equals_hmc_run(hl):
+    m = mocks.make_mock(16, 200.0, 300, 80.0, "sphere", (0.2, 0.2), seed=31)
+    start = _start(m, 0)
+    sv = hl.Server(4 * GIB)
+    say("served job")
+    job = _submit(sv, m, "fp64", 77, start)
+    _drain(sv, [job])
+    got = sv.take(job)
+    sv.close()
+    say("hmc_run")
+    plan = hl.Plan.from_mock(m, precision="fp64")
+    dev = plan.device
+    q = torch.from_numpy(start[0].copy()).to(dev)
+    qd = torch.from_numpy(start[1].copy()).to(dev)
+    qs = plan.scalar(start[2])
+    msum = plan.zeros_modes()
+    dh = torch.zeros(CHAIN["n_iter"], dtype=torch.float64, device=dev)
+    acc = torch.zeros(CHAIN["n_iter"], dtype=torch.int32, device=dev)
+    eps = hl.hmc_run([plan], [q], [qd], [qs], seed=77, mode_sum=[msum], dh=[dh], accepted=[acc], **CHAIN)
+    torch.cuda.synchronize()
+    ref = {"mode_sum": msum.cpu().numpy(), "q_modes": q.cpu().numpy(), "q_dist": qd.cpu().numpy(),
+           "q_snl": qs.item(), "dh": dh.cpu().numpy(), "accepted": acc.cpu().numpy(), "eps": eps[0]}
+    plan.close()
+    assert _same(got, ref)
+    assert 0 < got["accepted"].sum()
+
+
+def test_job_alone_equals_job_in_a_mix(hl):
+    x = mocks.make_mock(32, 400.0, 400, 120.0, "sphere", (0.2, 0.2), seed=41)
+    sx = _start(x, 1)
+    sv = hl.Server(4 * GIB)
+    say("alone")
+    j = _submit(sv, x, "fp32", 5, sx)
+    _drain(sv, [j])
+    alone = sv.take(j)
+    sv.close()
+    # the same job joining a running mix (another 32^3 FP32 job shares its
+    # launches; a 16^3 FP64 job runs beside them) two ticks late
+    others = [(mocks.make_mock(32, 400.0, 700, 120.0, "inv_r", (0.2, 0.2), seed=44), "fp32", 6),
+              (mocks.make_mock(16, 200.0, 300, 80.0, "sphere", (0.2, 0.2), seed=36), "fp64", 7)]
+    sv = hl.Server(4 * GIB)
+    say("in a mix")
+    ids = [_submit(sv, m, prec, seed, _start(m, 2 + k), n_iter=5, n_leapfrog=3)
+           for k, (m, prec, seed) in enumerate(others)]
+    sv.tick()
+    sv.tick()
+    j = _submit(sv, x, "fp32", 5, sx)
+    _drain(sv, ids + [j])
+    mixed = sv.take(j)
+    for i in ids:
+        sv.take(i)
+    sv.close()
+    assert _same(alone, mixed)
+
+
+def test_admission_keeps_within_budget(hl):
+    ms = [mocks.make_mock(32, 400.0, 300 + 50 * k, 120.0, "sphere", (0.2, 0.2), seed=60 + k) for k in range(4)]
+    # a served 32^3 job holds its plan (footprint_bytes) and its chain state
+    # (two mode arrays, 0.5 MiB): three plan footprints fit two jobs, not three
+    per_job = [hl.footprint_bytes(32, m.n_gal, "fp32") for m in ms]
+    budget = 3 * max(per_job)
+    sv = hl.Server(budget)
+    ids = [_submit(sv, m, "fp32", 10 + k, _start(m, k), n_iter=3, n_leapfrog=2) for k, m in enumerate(ms)]
+    say("admission")
+    most = 0
+    seen_queue = False
+    left = set(ids)
+    for _ in range(200):
+        st = sv.tick()
+        assert st["bytes_in_use"] <= budget
+        most = max(most, st["running"] + st["finished"])
+        seen_queue = seen_queue or st["queued"] > 0
+        for j in sorted(left):
+            if sv.state(j) == "finished":      # a finished job holds its memory until taken
+                res = sv.take(j)
+                assert np.isfinite(res["dh"]).any()
+                left.discard(j)
+        if not left:
+            break
+    assert not left
+    assert most == 2 and seen_queue
+    sv.close()
+
+
+def test_job_over_the_budget_is_rejected(hl):
+    m = mocks.make_mock(32, 400.0, 300, 120.0, "sphere", (0.2, 0.2), seed=61)
+    sv = hl.Server(1 << 20)
+    with pytest.raises(_capi.HamletError, match="budget"):
+        _submit(sv, m, "fp32", 1, _start(m, 0))
+    sv.close()
+
+
+def test_default_start_state(hl):
+    # no start state: zero field, the redshift distances d_z, and s as given
+    m = mocks.make_mock(16, 200.0, 300, 80.0, "sphere", (0.2, 0.2), seed=31)
+    sv = hl.Server(GIB)
+    job = sv.submit(n_iter=0, n_leapfrog=1, eps0=1e-3, seed=1, q_snl=1.1, precision="fp64", **m.problem_kwargs())
+    _drain(sv, [job])
+    res = sv.take(job)
+    sv.close()
+    dz = model.redshift_distance(m.cz / model.C_KMS, m.omega_m)
+    assert np.all(res["q_modes"] == 0)
+    assert np.max(np.abs(res["q_dist"] - dz) / dz) <= 1e-12
+    assert res["q_snl"] == 1.1
