@@ -21,6 +21,15 @@ timed on the host cores ("cpu_baseline").
 2000 to 30 000 points) advanced together: chains of one grid size share
 every kernel launch.  value = gradient evaluations per second summed over
 the chains; the same chains advanced one at a time are timed beside it.
+
+    python bench.py --workload served [--jobs J] [--rate R]
+
+A seeded Poisson stream of J reconstruction requests at R per second (grid
+64^3, 128^3 or 256^3, 1000 to 30 000 points, 100 HMC iterations of 20
+leapfrog steps each) served by continuous batching with admission by device
+footprint.  value = gradient evaluations per second over the run; p50 and
+p99 job latency (arrival to results) are reported beside those of the same
+stream served by the plain FP64 path one job at a time.
 """
 import argparse
 import json
@@ -68,7 +77,10 @@ def parse():
     ap.add_argument("--n-gal", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", choices=("paper", "batched"), default="paper")
+    ap.add_argument("--workload", choices=("paper", "batched", "served"), default="paper")
+    ap.add_argument("--jobs", type=int, default=24, help="served: number of requests")
+    ap.add_argument("--rate", type=float, default=1.5, help="served: requests per second")
+    ap.add_argument("--iters", type=int, default=100, help="served: HMC iterations per request")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (reference for traffic counters)")
     return ap.parse_args()
@@ -90,6 +102,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "batched":
         return run_batched(args, dev)
+    if args.workload == "served":
+        return run_served(args, dev)
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -325,6 +339,109 @@ def run_batched(args, dev):
     print(json.dumps(out), flush=True)
     for p in plans:
         p.close()
+
+
+def served_trace(args, mocks, np):
+    """Seeded request stream: arrival time, grid, pool universe, catalogue size, seed."""
+    rng = np.random.default_rng(mocks.config_seed(5))
+    t = np.cumsum(rng.exponential(1.0 / args.rate, args.jobs))
+    grids = rng.choice([64, 128, 256], args.jobs)
+    pool = rng.integers(0, 2, args.jobs)
+    sizes = rng.integers(1000, 30001, args.jobs)
+    return [dict(t=float(t[k]), n_grid=int(grids[k]), pool=int(pool[k]), n_gal=int(sizes[k]),
+                 seed=mocks.config_seed(5) + 1000 + k) for k in range(args.jobs)]
+
+
+def serve_trace(hamlet, trace, universes, precision, max_running, L, n_iter, budget, dev, label):
+    """Replays the request stream in real time through a server; returns per-job latencies (s) and the makespan."""
+    import numpy as np
+    sv = hamlet.Server(budget, max_running=max_running, ticks_ahead=2, device=dev)
+    t0 = time.perf_counter()
+    pending = list(range(len(trace)))
+    live = {}
+    lat = {}
+    last_log = t0
+    while len(lat) < len(trace):
+        now = time.perf_counter() - t0
+        while pending and trace[pending[0]]["t"] <= now:
+            k = pending.pop(0)
+            r = trace[k]
+            u = universes[(r["n_grid"], r["pool"])]
+            n = r["n_gal"]
+            prob = u.problem_kwargs()
+            for key in ("rhat", "mu", "sigma_mu", "cz", "sigma_cz"):
+                prob[key] = prob[key][:n]
+            live[sv.submit(n_iter=n_iter, n_leapfrog=L, eps0=2e-3, warmup=n_iter // 5, jitter=True,
+                           seed=r["seed"], precision=precision, **prob)] = k
+        if live:
+            sv.tick()
+            for j in list(live):
+                if sv.state(j) == "finished":
+                    k = live.pop(j)
+                    sv.take(j, outputs=("dh", "accepted"))
+                    lat[k] = time.perf_counter() - t0 - trace[k]["t"]
+        elif pending:
+            time.sleep(max(0.0, min(0.05, trace[pending[0]]["t"] - now)))
+        if time.perf_counter() - last_log > 5.0:
+            last_log = time.perf_counter()
+            log("%s: %.0fs, %d done, %d running or queued" % (label, last_log - t0, len(lat), len(live)))
+    makespan = time.perf_counter() - t0 - trace[0]["t"]
+    sv.close()
+    return np.array([lat[k] for k in range(len(trace))]), makespan
+
+
+def run_served(args, dev):
+    import numpy as np
+
+    from paper_2203_02369_amd import hamlet, mocks
+
+    L = args.leapfrog
+    n_iter = args.iters
+    trace = served_trace(args, mocks, np)
+    t0 = time.time()
+    universes = {}
+    for ng in (64, 128, 256):
+        for p in range(2):
+            universes[(ng, p)] = mocks.paper_scale_256(n_gal=30000, n_grid=ng, seed=mocks.config_seed(5) + 10 * p + ng)
+            log("universe %d^3 #%d (%.0fs)" % (ng, p, time.time() - t0))
+    budget = 96 << 30
+    grads = sum(1 + n_iter * L for _ in trace)
+    lat32, span32 = serve_trace(hamlet, trace, universes, "fp32", 0, L, n_iter, budget, dev, "served fp32")
+    log("served fp32: %d jobs in %.1fs, p50 %.2fs, p99 %.2fs" % (len(trace), span32, np.percentile(lat32, 50),
+                                                                 np.percentile(lat32, 99)))
+    lat64, span64 = serve_trace(hamlet, trace, universes, "fp64", 1, L, n_iter, budget, dev, "fp64 one at a time")
+    log("fp64 one job at a time: %.1fs, p50 %.2fs, p99 %.2fs" % (span64, np.percentile(lat64, 50),
+                                                                 np.percentile(lat64, 99)))
+    value = grads / span32
+    out = {
+        "metric": "grad evals/s serving a Poisson stream of reconstructions (64^3/128^3/256^3, 1000-30000 points)",
+        "value": round(value, 2),
+        "unit": "grad evals/s",
+        "n_gpus": 1,
+        "steps": len(trace),
+        "warmup": 0,
+        "ms_per_step": round(1e3 * span32 / len(trace), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 fields, f64 Hamiltonian",
+        "data": "synthetic",
+        "config": {"workload": "served: %d requests, Poisson arrivals at %.2f/s, grid uniform in 64^3/128^3/256^3, "
+                               "1000-30000 points (paper-scale catalogue generator), %d HMC iterations of %d "
+                               "leapfrog steps each, continuous batching, admission by device footprint"
+                               % (len(trace), args.rate, n_iter, L),
+                   "jobs_per_s": round(len(trace) / span32, 3), "latency_p50_s": round(float(np.percentile(lat32, 50)), 3),
+                   "latency_p99_s": round(float(np.percentile(lat32, 99)), 3), "makespan_s": round(span32, 2),
+                   "grad_evals": grads},
+        "fp64_one_job_at_a_time": {"value": round(grads / span64, 2), "unit": "grad evals/s",
+                                   "jobs_per_s": round(len(trace) / span64, 3),
+                                   "latency_p50_s": round(float(np.percentile(lat64, 50)), 3),
+                                   "latency_p99_s": round(float(np.percentile(lat64, 99)), 3),
+                                   "makespan_s": round(span64, 2)},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

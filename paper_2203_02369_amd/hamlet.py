@@ -309,18 +309,24 @@ class Server:
         _capi.check(_capi.load().hamlet_server_job_state(self.handle, int(job), ctypes.byref(out)))
         return SERVER_STATES[out.value]
 
-    def take(self, job):
+    TAKE_ALL = ("mode_sum", "q_modes", "q_dist", "q_snl", "dh", "accepted", "eps")
+
+    def take(self, job, outputs=TAKE_ALL):
+        """Results of a finished job (the listed ones) as numpy arrays; releases the job."""
         ng, n, n_iter = self._jobs.pop(job)
-        res = {"mode_sum": np.zeros((ng, ng, ng // 2), np.complex128),
-               "q_modes": np.zeros((ng, ng, ng // 2), np.complex128),
-               "q_dist": np.zeros(n), "q_snl": np.zeros(1), "dh": np.zeros(n_iter),
-               "accepted": np.zeros(n_iter, np.int32), "eps": np.zeros(1)}
-        dp = {k: v.ctypes.data_as(c_double_p) for k, v in res.items() if k != "accepted"}
+        shapes = {"mode_sum": ((ng, ng, ng // 2), np.complex128), "q_modes": ((ng, ng, ng // 2), np.complex128),
+                  "q_dist": ((n,), np.float64), "q_snl": ((1,), np.float64), "dh": ((n_iter,), np.float64),
+                  "accepted": ((n_iter,), np.int32), "eps": ((1,), np.float64)}
+        res = {k: np.zeros(*shapes[k]) for k in outputs}
+
+        def ptr(k, typ=c_double_p):
+            return res[k].ctypes.data_as(typ) if k in res else None
         _capi.check(_capi.load().hamlet_server_take(
-            self.handle, int(job), dp["mode_sum"], dp["q_modes"], dp["q_dist"], dp["q_snl"], dp["dh"],
-            res["accepted"].ctypes.data_as(_capi.c_int32_p), dp["eps"]))
-        res["q_snl"] = float(res["q_snl"][0])
-        res["eps"] = float(res["eps"][0])
+            self.handle, int(job), ptr("mode_sum"), ptr("q_modes"), ptr("q_dist"), ptr("q_snl"), ptr("dh"),
+            ptr("accepted", _capi.c_int32_p), ptr("eps")))
+        for k in ("q_snl", "eps"):
+            if k in res:
+                res[k] = float(res[k][0])
         return res
 
     def close(self):
