@@ -48,15 +48,15 @@ HBM_PEAK_GBS = 8000.0
 # (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Bytes read and
 # written per launch for the plain-gradient, first, middle and last variants.
 # Valid only for the kernel sources they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "c9c21d198864a969f83a20944df204a62f37b4a1"
-X_TRAFFIC = {"grad": (334203820, 134217728), "first": (468463685, 401674965),
-             "mid": (468598666, 401676500), "last": (468428700, 268435456)}
+X_TRAFFIC_SOURCES_SHA1 = "6eb09f9dd89332467399c0ddd95358b775de24c2"
+X_TRAFFIC = {"grad": (334216882, 134217728), "first": (468473367, 401674240),
+             "mid": (468610783, 401675878), "last": (468441419, 268435456)}
 
 
 def kernel_sources_sha1():
     import hashlib
     h = hashlib.sha1()
-    for f in ("passes.hpp", "fft.hpp", "common.hpp"):
+    for f in ("passes.hpp", "fft.hpp", "common.hpp", "workspace.hpp"):
         with open(os.path.join(ROOT, "paper_2203_02369_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

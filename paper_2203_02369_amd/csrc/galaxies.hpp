@@ -127,15 +127,24 @@ __device__ __forceinline__ void
 bin_scan_add_body(int* __restrict__ count, int* __restrict__ off, int* __restrict__ cursor,
                   const int* __restrict__ bsum, const int* __restrict__ bmax, int* __restrict__ most, int nkeys) {
   __shared__ int base;
-  if (threadIdx.x == 0) {
-    int s = 0;
-    for (int b = 0; b < (int)blockIdx.x; ++b) s += bsum[b];
-    base = s;
-    if (blockIdx.x == gridDim.x - 1) {
-      off[nkeys] = s + bsum[blockIdx.x];
-      int m = 0;
-      for (int b = 0; b < (int)gridDim.x; ++b) m = max(m, bmax[b]);
-      most[0] = m;
+  if (threadIdx.x < 64) {
+    // the first wave sums the preceding tiles (and, in the last block, takes
+    // the largest count of any column)
+    const bool last = blockIdx.x == gridDim.x - 1;
+    int s = 0, m = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 64) s += bsum[b];
+    if (last)
+      for (int b = threadIdx.x; b < (int)gridDim.x; b += 64) m = max(m, bmax[b]);
+    for (int o = 32; o > 0; o >>= 1) {
+      s += __shfl_xor(s, o, 64);
+      m = max(m, __shfl_xor(m, o, 64));
+    }
+    if (threadIdx.x == 0) {
+      base = s;
+      if (last) {
+        off[nkeys] = s + bsum[blockIdx.x];
+        most[0] = m;
+      }
     }
   }
   __syncthreads();
