@@ -245,7 +245,7 @@ typedef enum {
   HAMLET_K_INV_X = 1,       /* inverse pass 1: multiplier, prior energy, FFT along x */
   HAMLET_K_INV_Y = 2,       /* inverse pass 2: FFT along y */
   HAMLET_K_INV_Z = 3,       /* inverse pass 3: complex-to-real FFT along z + CIC gather */
-  HAMLET_K_LIKE = 4,        /* per-point likelihood and its gradient */
+  HAMLET_K_LIKE = 4,        /* per-point likelihood and its gradient, and the final sums */
   HAMLET_K_FWD_Z = 5,       /* forward pass 1: CIC scatter + real-to-complex FFT along z */
   HAMLET_K_FWD_Y = 6,       /* forward pass 2: FFT along y */
   HAMLET_K_FWD_X = 7,       /* forward pass 3: FFT along x, adjoint multiply, prior gradient; inside a

@@ -210,14 +210,17 @@ bin_rank_body(const int* __restrict__ off, const int* __restrict__ key, const in
 // ---------------------------------------------------------------------------
 struct LikeOut {
   double* g_dist;     // dPsi/dd by galaxy id (n)
-  double* part;       // 3 per block: Psi, dPsi/ds, invalid
+  double* part;       // 4 per block: Psi, dPsi/ds, invalid, a slice of the prior partials
+  const double* prior_part;   // prior partials of the x pass
+  int n_prior;
+  int n_blocks;               // this plan's blocks (ceil(n / block size)); block b sums slice b
 };
 
 template <typename T>
 __device__ __forceinline__ void
 like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const double* __restrict__ frac,
-       double* __restrict__ dist, const double* __restrict__ snl_q, Catalogue cat, Cosmo cm,
-       T* __restrict__ gsort, LikeOut out, LeapUpdate lf) {
+          double* __restrict__ dist, const double* snl_q, Catalogue cat, Cosmo cm, T* __restrict__ gsort,
+          LikeOut out, LeapUpdate lf) {
   __shared__ double red[kGalThreads / 64];
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double psi = 0.0, dps = 0.0, bad = 0.0;
@@ -279,10 +282,17 @@ like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const
   const double a = block_sum(psi, red);
   const double b = block_sum(dps, red);
   const double c = block_sum(bad, red);
+  // this block's slice of the prior partials
+  const int per = (out.n_prior + out.n_blocks - 1) / out.n_blocks;
+  const int lo = blockIdx.x * per, hi = min(out.n_prior, lo + per);
+  double pr = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) pr += out.prior_part[i];
+  const double d = block_sum(pr, red);
   if (threadIdx.x == 0) {
-    out.part[3 * blockIdx.x + 0] = a;
-    out.part[3 * blockIdx.x + 1] = b;
-    out.part[3 * blockIdx.x + 2] = c;
+    out.part[4 * blockIdx.x + 0] = a;
+    out.part[4 * blockIdx.x + 1] = b;
+    out.part[4 * blockIdx.x + 2] = c;
+    out.part[4 * blockIdx.x + 3] = d;
   }
 }
 
@@ -290,14 +300,14 @@ like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const
 // distance left the domain or Psi is not finite); dPsi/ds.
 __device__ __forceinline__ void
 finalize_body(const double* __restrict__ prior_part, int n_prior, const double* __restrict__ like_part, int n_like,
-           double* __restrict__ psi_out, double* __restrict__ gs_out, double* __restrict__ snl_q, LeapUpdate lf) {
+              double* __restrict__ psi_out, double* __restrict__ gs_out, double* snl_q, LeapUpdate lf) {
   __shared__ double red[4];
   double a = 0.0, b = 0.0, c = 0.0;
   for (int i = threadIdx.x; i < n_prior; i += blockDim.x) a += prior_part[i];
   for (int i = threadIdx.x; i < n_like; i += blockDim.x) {
-    a += like_part[3 * i];
-    b += like_part[3 * i + 1];
-    c += like_part[3 * i + 2];
+    a += like_part[4 * i] + like_part[4 * i + 3];
+    b += like_part[4 * i + 1];
+    c += like_part[4 * i + 2];
   }
   a = block_sum(a, red);
   b = block_sum(b, red);
@@ -438,10 +448,28 @@ __global__ void __launch_bounds__(kGalThreads) k_like(Launch L) {
   LikeOut lo;
   lo.g_dist = k.st.gd;
   lo.part = k.w.like_part();
+  lo.prior_part = k.w.prior_part();
+  lo.n_prior = pc.n_prior_part;
+  lo.n_blocks = pc.n_like_part;
   like_body<T>(k.w.part(), k.w.gid(), k.w.frac(), k.st.qd, k.st.qs, catalogue(k.w, k.n_gal), cosmo(k.w),
                k.w.gsort(), lo, leap_update(k.mode, pc.sample_d, k.st.pd, k.st.eps, pc.minv_d));
+  // The plan's last block to finish completes the evaluation: it sums every
+  // block's partials in block order (the final sums) and resets the ticket.
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(k.w.ticket(), 1) == pc.n_like_part - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  finalize_body(k.w.prior_part(), 0, k.w.like_part(), pc.n_like_part, k.st.psi, k.st.gs, k.st.qs,
+                leap_update(k.mode, pc.sample_s, k.st.ps, k.st.eps, 1.0));
+  if (threadIdx.x == 0) *k.w.ticket() = 0;
 }
 
+// The final sums of a plan with no points (the likelihood kernel does them
+// for the others).
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_finalize(Launch L) {
   const Pick<T, N> k(L);

@@ -204,7 +204,14 @@ static hamlet_status eval_impl(const Batch& b) {
     TIMED(b, HAMLET_K_LIKE, (k_like<T, N><<<dim3(blocks_for(ng, kGalThreads), 1, nb), kGalThreads, 0, st>>>(sel)));
     LAUNCH_CHECK();
   }
-  k_finalize<T, N><<<dim3(1, 1, nb), 256, 0, st>>>(sel);
+  // plans without points still need their final sums (prior only)
+  Batch empty = b;
+  bool any_empty = false;
+  for (int i = 0; i < b.count; ++i) {
+    if (b.plan[i]->n_gal > 0) empty.mode[i] = kXSkip;
+    any_empty = any_empty || empty.mode[i] != kXSkip;
+  }
+  if (any_empty) k_finalize<T, N><<<dim3(1, 1, nb), 256, 0, st>>>(launch_table(empty));
   for (int sl = 0; sl < SL::COUNT; ++sl) {
     const int x0 = sl * SL::SIZE;
     TIMED(b, HAMLET_K_FWD_Z, (k_fwd_z_scatter<T, N, TH::Z><<<g_z_slab, TH::Z, 0, st>>>(sel, x0)));
@@ -459,7 +466,7 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
   LAUNCH_CHECK();
   HIP_TRY(hipMemsetAsync(pl->count, 0, (size_t)n * n * sizeof(int), st));
   HIP_TRY(hipMemsetAsync(pl->off, 0, ((size_t)n * n + 1) * sizeof(int), st));
-  HIP_TRY(hipMemsetAsync(pl->most, 0, sizeof(int), st));
+  HIP_TRY(hipMemsetAsync(pl->most, 0, 2 * sizeof(int), st));   // most crowded column, likelihood ticket
   PlanConst& pc = sg.pc;
   pc.n_gal = pl->n_gal;
   pc.n_hist = pl->n_hist;

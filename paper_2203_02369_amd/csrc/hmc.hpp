@@ -177,30 +177,41 @@ __global__ void __launch_bounds__(kEltThreads) k_momenta_small(Launch L) {
 
 // ---------------------------------------------------------------------------
 // Kinetic energy K = (1/2) p^T M^-1 p: per stored mode (w_k / 8) sigma^2 |p|^2
-// (w_k = 1 on kz = 0 where both Hermitian partners are stored, else 2).
+// (w_k = 1 on kz = 0 where both Hermitian partners are stored, else 2), per
+// distance (1/2) M_d^-1 p_d^2, and (1/2) M_s^-1 p_s^2; block partials, then
+// one block sums them in order into kin0 (which = 0, before the trajectory)
+// or kin1 (after).
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ void __launch_bounds__(kEltThreads) k_kinetic_modes(Launch L) {
   __shared__ double red[kEltThreads / 64];
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
+  const PlanConst& pc = k.w.pc();
   const double2* __restrict__ p = k.w.pm();
   const double* __restrict__ var = k.w.mvar();
+  const double* __restrict__ pd = k.w.pd();
   const size_t total = (size_t)N * N * (N / 2);
+  const size_t stop = total > (size_t)k.n_gal ? total : (size_t)k.n_gal;
   double acc = 0.0;
-  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (size_t)gridDim.x * blockDim.x) {
-    const ModeIdx m = mode_idx(g, N);
-    if (retained(m.sx, m.sy, m.kz, N)) {
-      const double2 v = p[g];
-      acc += (m.kz == 0 ? 0.125 : 0.25) * var[g] * (v.x * v.x + v.y * v.y);
+  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < stop; g += (size_t)gridDim.x * blockDim.x) {
+    if (g < total) {
+      const ModeIdx m = mode_idx(g, N);
+      if (retained(m.sx, m.sy, m.kz, N)) {
+        const double2 v = p[g];
+        acc += (m.kz == 0 ? 0.125 : 0.25) * var[g] * (v.x * v.x + v.y * v.y);
+      }
     }
+    if (g < (size_t)k.n_gal) acc += 0.5 * pc.minv_d * pd[g] * pd[g];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && pc.sample_s) {
+    const double ps = k.w.ps()[0];
+    acc += 0.5 * ps * ps;
   }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) k.w.kin_part()[blockIdx.x] = s;
 }
 
-// Sums the mode partials and adds (1/2) M_d^-1 sum p_d^2 + (1/2) M_s^-1 p_s^2
-// into kin0 (which = 0, before the trajectory) or kin1 (after).
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_kinetic_final(Launch L, int which) {
   __shared__ double red[4];
@@ -208,19 +219,13 @@ __global__ void __launch_bounds__(256) k_kinetic_final(Launch L, int which) {
   if (k.mode == kXSkip) return;
   const PlanConst& pc = k.w.pc();
   const double* __restrict__ kin = k.w.kin_part();
-  const double* __restrict__ pd = k.w.pd();
-  double a = 0.0, b = 0.0;
+  double a = 0.0;
   for (int i = threadIdx.x; i < pc.n_kin_part; i += blockDim.x) a += kin[i];
-  for (int i = threadIdx.x; i < k.n_gal; i += blockDim.x) b += pd[i] * pd[i];
   a = block_sum(a, red);
-  b = block_sum(b, red);
   if (threadIdx.x == 0) {
-    const double minv_s = pc.sample_s ? 1.0 : 0.0;
-    const double ps = k.w.ps()[0];
-    const double e = a + 0.5 * pc.minv_d * b + 0.5 * minv_s * ps * ps;
     ChainScalars* cs = chain(k.w);
-    if (which) cs->kin1 = e;
-    else cs->kin0 = e;
+    if (which) cs->kin1 = a;
+    else cs->kin0 = a;
   }
 }
 

@@ -87,7 +87,7 @@ template <int N, int R> struct FixedLayout {
   static constexpr size_t bmax = align256(bsum + 4 * ((size_t(N) * N + 1023) / 1024));
   static constexpr size_t prior_part = align256(bmax + 4 * ((size_t(N) * N + 1023) / 1024));
   static constexpr size_t kin_part = align256(prior_part + 8 * size_t(N_PRIOR));
-  static constexpr size_t small = align256(kin_part + 8 * size_t(N_KIN));   // qs0, ps, eps_slot, most
+  static constexpr size_t small = align256(kin_part + 8 * size_t(N_KIN));   // qs0, ps, eps_slot, most, ticket
   static constexpr size_t mvar = align256(small + 256);
   static constexpr size_t a = align256(mvar + 8 * NM);
   static constexpr size_t b = a + 2 * R * NM;
@@ -150,6 +150,7 @@ template <typename T, int N> struct Ws {
   __host__ __device__ double* ps() const { return at<double>(F::small + 8); }
   __host__ __device__ double* eps_slot() const { return at<double>(F::small + 16); }
   __host__ __device__ int* most() const { return at<int>(F::small + 24); }   // most points in one column
+  __host__ __device__ int* ticket() const { return at<int>(F::small + 28); } // likelihood blocks done
   __host__ __device__ int* bmax() const { return at<int>(F::bmax); }
   __host__ __device__ double* mvar() const { return at<double>(F::mvar); }
   __host__ __device__ C* a() const { return at<C>(F::a); }
