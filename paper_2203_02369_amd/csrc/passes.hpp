@@ -168,19 +168,22 @@ inv_y_body(const cplx_t<T>* __restrict__ inA, const cplx_t<T>* __restrict__ inB,
   __shared__ C twl[N];
   load_twiddles<T, N, NT>(twl, tw);
   const int x = x0 + blockIdx.y, z0 = blockIdx.x * S::W;
-  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = inB[gofs<N>(x, y, z0 + w)]; });
+  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = ld_stream(&inB[gofs<N>(x, y, z0 + w)]); });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
   tile_elems<T, N, NT>([&](int, int y, int w) { vx[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
   __syncthreads();
-  tile_elems<T, N, NT>([&](int, int y, int w) {
-    tile[LAY::idx(y, w)] = cscale(inA[gofs<N>(x, y, z0 + w)], (T)signed_freq(y, N));
+  // A is read once and kept in registers for its second transform
+  C ra[elems_per_thread<T, N, NT>()];
+  tile_elems<T, N, NT>([&](int e, int y, int w) {
+    ra[e] = ld_stream(&inA[gofs<N>(x, y, z0 + w)]);
+    tile[LAY::idx(y, w)] = cscale(ra[e], (T)signed_freq(y, N));
   });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
   tile_elems<T, N, NT>([&](int, int y, int w) { vy[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
   __syncthreads();
-  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = inA[gofs<N>(x, y, z0 + w)]; });
+  tile_elems<T, N, NT>([&](int e, int y, int w) { tile[LAY::idx(y, w)] = ra[e]; });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
   tile_elems<T, N, NT>([&](int, int y, int w) { vz[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
@@ -236,12 +239,12 @@ inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict_
     C av, bv;
     if (r == 1) {
       const size_t g0 = gofs<N>(x, y0 + 2 * m, k);
-      av = cscale(vz[g0], (T)k);
-      bv = cscale(vz[g0 + H], (T)k);
+      av = cscale(ld_stream(&vz[g0]), (T)k);
+      bv = cscale(ld_stream(&vz[g0 + H]), (T)k);
     } else {
       const size_t g = gofs<N>(x, y0 + 2 * m + (r == 2 ? 1 : 0), k);
-      av = vx[g];
-      bv = vy[g];
+      av = ld_stream(&vx[g]);
+      bv = ld_stream(&vy[g]);
     }
     if (k == 0) {
       buf[LAY::idx(0, f)] = cmake<C>(av.x, bv.x);
@@ -503,17 +506,19 @@ fwd_y_body(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, c
   load_twiddles<T, N, NT>(twl, tw);
   const int x = x0 + blockIdx.y, z0 = blockIdx.x * S::W;
   C acc[EPT];
-  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = gy[gofs<N>(x, y, z0 + w)]; });
+  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = ld_stream(&gy[gofs<N>(x, y, z0 + w)]); });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
   tile_elems<T, N, NT>([&](int e, int y, int w) { acc[e] = cscale(tile[LAY::idx(y, w)], (T)signed_freq(y, N)); });
   __syncthreads();
-  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = gz[gofs<N>(x, y, z0 + w)]; });
+  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = ld_stream(&gz[gofs<N>(x, y, z0 + w)]); });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
-  tile_elems<T, N, NT>([&](int e, int y, int w) { s1[gofs<N>(x, y, z0 + w)] = cadd(acc[e], tile[LAY::idx(y, w)]); });
+  tile_elems<T, N, NT>([&](int e, int y, int w) {
+    s1[gofs<N>(x, y, z0 + w)] = cadd(acc[e], tile[LAY::idx(y, w)]);
+  });
   __syncthreads();
-  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = gx[gofs<N>(x, y, z0 + w)]; });
+  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = ld_stream(&gx[gofs<N>(x, y, z0 + w)]); });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
   tile_elems<T, N, NT>([&](int, int y, int w) { s2[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
@@ -555,12 +560,12 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
   const int sy = signed_freq(y, N);
   C acc[elems_per_thread<T, N, NT>()];
   if constexpr (kFromSpectra) {
-    tile_elems<T, N, NT>([&](int, int x, int w) { tile[LAY::idx(x, w)] = s2[gofs<N>(x, y, z0 + w)]; });
+    tile_elems<T, N, NT>([&](int, int x, int w) { tile[LAY::idx(x, w)] = ld_stream(&s2[gofs<N>(x, y, z0 + w)]); });
     __syncthreads();
     lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
     tile_elems<T, N, NT>([&](int e, int x, int w) { acc[e] = cscale(tile[LAY::idx(x, w)], (T)signed_freq(x, N)); });
     __syncthreads();
-    tile_elems<T, N, NT>([&](int, int x, int w) { tile[LAY::idx(x, w)] = s1[gofs<N>(x, y, z0 + w)]; });
+    tile_elems<T, N, NT>([&](int, int x, int w) { tile[LAY::idx(x, w)] = ld_stream(&s1[gofs<N>(x, y, z0 + w)]); });
     __syncthreads();
     lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
   } else {
@@ -577,38 +582,39 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
     const size_t g = gofs<N>(x, y, kz);
     const bool keep = retained(sx, sy, kz, N);
     const int n2 = sx * sx + sy * sy + kz * kz;
-    const double var = keep ? tab.var[g] : 0.0;
+    const double var = keep ? ld_stream(&tab.var[g]) : 0.0;
+    // the mode, read once (gradient and drift)
+    double2 q = make_double2(0.0, 0.0);
+    if (keep && (kFromSpectra || kDrift)) q = ld_stream(&modes[g]);
     double2 G = make_double2(0.0, 0.0);
     if constexpr (kFromSpectra) {
       if (keep) {
         const C tv = cadd(acc[e], tile[LAY::idx(x, w)]);
-        const double2 q = modes[g];
         const double iv2 = 2.0 * inv_or_zero(var), kf2 = 2.0 * mode_kfac(tab, n2);
         // -2 i kfac t = (2 kfac t.y, -2 kfac t.x)
         G = make_double2(iv2 * q.x + kf2 * (double)tv.y, iv2 * q.y - kf2 * (double)tv.x);
       }
     } else {
-      G = gcache[g];
+      G = ld_stream(&gcache[g]);
     }
     if constexpr (MODE == kXGrad) {
       // plane_scale 0.5: gradient per stored entry (each Hermitian partner of
       // the kz = 0 plane taken as its own variable carries half)
-      gcache[g] = kz == 0 ? make_double2(plane_scale * G.x, plane_scale * G.y) : G;
+      st_stream(&gcache[g], kz == 0 ? make_double2(plane_scale * G.x, plane_scale * G.y) : G);
     }
-    if constexpr (MODE == kXLast) gcache[g] = G;
+    if constexpr (MODE == kXLast) st_stream(&gcache[g], G);
     if constexpr (MODE != kXGrad) {
-      double2 p = mom[g];
+      double2 p = ld_stream(&mom[g]);
       p.x -= hk * G.x;
       p.y -= hk * G.y;
-      mom[g] = p;
+      st_stream(&mom[g], p);
       if constexpr (kDrift) {
         double2 a = make_double2(0.0, 0.0);
         if (keep) {
-          double2 q = modes[g];
           const double c = eps * (0.5 * var);
           q.x += c * p.x;
           q.y += c * p.y;
-          modes[g] = q;
+          st_stream(&modes[g], q);
           prior += (kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(var);
           const double kf = mode_kfac(tab, n2);
           a = make_double2(-kf * q.y, kf * q.x);      // i kfac q
