@@ -45,12 +45,12 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of k_x_pass<float, 256> per launch, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, then WRITE_SIZE) of this script at 256^3 with 30 000
 # points, each scaled by what the counter reads for a plain 1 GiB device copy
-# (--copy-calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Bytes read and
+# (--copy-calibration: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  Bytes read and
 # written per launch for the plain-gradient, first, middle and last variants.
 # Valid only for the kernel sources they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "6eb09f9dd89332467399c0ddd95358b775de24c2"
-X_TRAFFIC = {"grad": (334216882, 134217728), "first": (468473367, 401674240),
-             "mid": (468610783, 401675878), "last": (468441419, 268435456)}
+X_TRAFFIC_SOURCES_SHA1 = "297dc74ba2fc7cf8d37c2f88ac3e337417507017"
+X_TRAFFIC = {"grad": (334167781, 134217856), "first": (468408004, 401693867),
+             "mid": (468537360, 401674337), "last": (468379077, 268437504)}
 
 
 def kernel_sources_sha1():

@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(kEltThreads) k_momenta_modes(Launch L) {
     size_t src = g;
     if (mir) src = ((size_t)((N - m.x) & (N - 1)) * N + ((N - m.y) & (N - 1))) * (N / 2);
     const double2 z = normal_pair(draw_words(seed, iteration, kPurposeModes, src));
-    const double sc = sqrt(2.0 * inv_or_zero(k.w.mvar()[g]));
+    const double sc = sqrt(2.0 * inv_or_zero(ld_stream(&k.w.mvar()[g])));
     out = make_double2(sc * z.x, mir ? -sc * z.y : sc * z.y);
   }
   k.w.pm()[g] = out;
@@ -198,8 +198,8 @@ __global__ void __launch_bounds__(kEltThreads) k_kinetic_modes(Launch L) {
     if (g < total) {
       const ModeIdx m = mode_idx(g, N);
       if (retained(m.sx, m.sy, m.kz, N)) {
-        const double2 v = p[g];
-        acc += (m.kz == 0 ? 0.125 : 0.25) * var[g] * (v.x * v.x + v.y * v.y);
+        const double2 v = ld_stream(&p[g]);
+        acc += (m.kz == 0 ? 0.125 : 0.25) * ld_stream(&var[g]) * (v.x * v.x + v.y * v.y);
       }
     }
     if (g < (size_t)k.n_gal) acc += 0.5 * pc.minv_d * pd[g] * pd[g];
@@ -277,8 +277,8 @@ __global__ void __launch_bounds__(kEltThreads) k_save_state(Launch L) {
   const size_t total = (size_t)N * N * (N / 2);
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < total) {
-    k.w.q0()[i] = k.st.q[i];
-    k.w.g0()[i] = k.w.gcache()[i];
+    st_stream(&k.w.q0()[i], ld_stream(&k.st.q[i]));
+    st_stream(&k.w.g0()[i], ld_stream(&k.w.gcache()[i]));
   }
   if (i < (size_t)k.n_gal) {
     k.w.qd0()[i] = k.st.qd[i];
@@ -335,19 +335,19 @@ __global__ void __launch_bounds__(kEltThreads) k_restore_accumulate(Launch L) {
   const ChainScalars* cs = chain(k.w);
   const int rejected = !cs->accept;
   if (i < total) {
-    double2 q;
+    double2 q = make_double2(0.0, 0.0);
     if (rejected) {
-      q = k.w.q0()[i];
-      k.st.q[i] = q;
-      k.w.gcache()[i] = k.w.g0()[i];
-    } else {
-      q = k.st.q[i];
+      q = ld_stream(&k.w.q0()[i]);
+      st_stream(&k.st.q[i], q);
+      st_stream(&k.w.gcache()[i], ld_stream(&k.w.g0()[i]));
+    } else if (cs->post && k.st.msum) {
+      q = ld_stream(&k.st.q[i]);
     }
     if (cs->post && k.st.msum) {
-      double2 a = k.st.msum[i];
+      double2 a = ld_stream(&k.st.msum[i]);
       a.x += q.x;
       a.y += q.y;
-      k.st.msum[i] = a;
+      st_stream(&k.st.msum[i], a);
     }
   }
   if (rejected) {
