@@ -62,3 +62,34 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert lib.hamlet_plan_create(None, None, None, ctypes.byref(ctypes.c_void_p())) == -1
     with pytest.raises(_capi.HamletError):
         _capi.check(-1)
+
+
+def test_batch_entry_points_reject_bad_plan_lists_on_the_host():
+    from paper_2203_02369_amd import _capi
+    lib = _capi.load()
+    fake = ctypes.c_void_p(0x1000)     # never dereferenced: the list check comes first
+    plans = (ctypes.c_void_p * 2)(fake, fake)
+    null_ptrs = (ctypes.c_void_p * 2)()
+    dnull = (_capi.c_double_p * 2)()
+    assert lib.hamlet_logpost_grad(plans, 0, null_ptrs, dnull, dnull, null_ptrs, dnull, dnull, dnull) == -1
+    assert b"at least one plan" in lib.hamlet_last_error()
+    assert lib.hamlet_logpost_grad(plans, 2, null_ptrs, dnull, dnull, null_ptrs, dnull, dnull, dnull) == -1
+    assert b"same plan" in lib.hamlet_last_error()
+    one = (ctypes.c_void_p * 1)(None)
+    assert lib.hamlet_hmc_run(one, 1, None, null_ptrs, dnull, dnull, None, None, None, None) == -1
+    assert b"NULL" in lib.hamlet_last_error()
+
+
+def test_server_entry_points_validate_on_the_host():
+    from paper_2203_02369_amd import _capi
+    lib = _capi.load()
+    out = ctypes.c_void_p()
+    desc = _capi.ServerDesc(hbm_budget=0, max_running=0, ticks_ahead=0)
+    assert lib.hamlet_server_create(ctypes.byref(desc), None, ctypes.byref(out)) == -1
+    assert b"hbm_budget" in lib.hamlet_last_error()
+    assert lib.hamlet_server_create(None, None, ctypes.byref(out)) == -1
+    assert lib.hamlet_server_tick(None, None) == -1
+    state = ctypes.c_int32()
+    assert lib.hamlet_server_job_state(None, 1, ctypes.byref(state)) == -1
+    assert lib.hamlet_server_take(None, 1, None, None, None, None, None, None, None) == -1
+    assert lib.hamlet_server_destroy(None) == 0
