@@ -241,7 +241,7 @@ hamlet_status hamlet_server_take(hamlet_server* server, int64_t job_id, double* 
 
 /* Measurement aid.  Kernel kinds that can be timed with HIP events: */
 typedef enum {
-  HAMLET_K_BIN = 0,         /* binning of the points into CIC columns (4 kernels, timed as one) */
+  HAMLET_K_BIN = 0,         /* binning of the points into CIC columns (its kernels timed as one) */
   HAMLET_K_INV_X = 1,       /* inverse pass 1: multiplier, prior energy, FFT along x */
   HAMLET_K_INV_Y = 2,       /* inverse pass 2: FFT along y */
   HAMLET_K_INV_Z = 3,       /* inverse pass 3: complex-to-real FFT along z + CIC gather */

@@ -46,13 +46,22 @@ __device__ __forceinline__ bool dist_ok(double d, const Cosmo& cm) { return d > 
 // plain FP64 evaluation.  Invalid distances are replaced by 1 Mpc/h for the
 // geometry (their Psi is +inf anyway), which keeps every index in range.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void
-bin_count_body(const double* __restrict__ dist, Catalogue cat, Cosmo cm, int n_grid,
-            int* __restrict__ count, int* __restrict__ key, int* __restrict__ cell_z, double* __restrict__ frac) {
+// Where binning writes: the bucket counts and, per point, its bucket,
+// lower z node and fractional offsets.
+struct BinOut {
+  int* count;
+  int* key;
+  int* cell_z;
+  double* frac;
+};
+
+// Bins point i at distance d.  The next evaluation's binning is known as soon
+// as a drift has moved the distances, so the drifting kernels (the
+// likelihood inside a trajectory, the first kick and drift) bin their points
+// right away and the counting kernel runs only before a plain gradient.
+__device__ __forceinline__ void bin_point(int i, double d, const Catalogue& cat, const Cosmo& cm, int n_grid,
+                                          const BinOut& bo) {
 #pragma clang fp contract(off)
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cat.n) return;
-  double d = dist[i];
   if (!dist_ok(d, cm)) d = 1.0;
   const double half = 0.5 * cm.box;
   int cell[3];
@@ -62,15 +71,22 @@ bin_count_body(const double* __restrict__ dist, Catalogue cat, Cosmo cm, int n_g
     const double xa = half + prod;
     const double s = xa / cm.spacing;
     const double fl = floor(s);
-    frac[3 * i + a] = s - fl;
+    bo.frac[3 * i + a] = s - fl;
     long long c = (long long)fl % n_grid;
     if (c < 0) c += n_grid;
     cell[a] = (int)c;
   }
   const int k = cell[0] * n_grid + cell[1];
-  key[i] = k;
-  cell_z[i] = cell[2];
-  atomicAdd(&count[k], 1);
+  bo.key[i] = k;
+  bo.cell_z[i] = cell[2];
+  atomicAdd(&bo.count[k], 1);
+}
+
+__device__ __forceinline__ void bin_count_body(const double* __restrict__ dist, Catalogue cat, Cosmo cm, int n_grid,
+                                               BinOut bo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cat.n) return;
+  bin_point(i, dist[i], cat, cm, n_grid, bo);
 }
 
 // Exclusive scan of the N^2 bucket counts, in two coalesced passes over
@@ -208,6 +224,13 @@ bin_rank_body(const int* __restrict__ off, const int* __restrict__ key, const in
 // with r = v_obs(d) - u.  Block partials (Psi, dPsi/ds, invalid count) are
 // written for a deterministic final sum.
 // ---------------------------------------------------------------------------
+// Binning of the next evaluation, done by the likelihood kernel inside a
+// trajectory (after the drift of the distances).
+struct BinNext {
+  BinOut out;
+  int n_grid;
+};
+
 struct LikeOut {
   double* g_dist;     // dPsi/dd by galaxy id (n)
   double* part;       // 4 per block: Psi, dPsi/ds, invalid, a slice of the prior partials
@@ -220,7 +243,7 @@ template <typename T>
 __device__ __forceinline__ void
 like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const double* __restrict__ frac,
           double* __restrict__ dist, const double* snl_q, Catalogue cat, Cosmo cm, T* __restrict__ gsort,
-          LikeOut out, LeapUpdate lf) {
+          LikeOut out, LeapUpdate lf, const BinNext* next) {
   __shared__ double red[kGalThreads / 64];
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double psi = 0.0, dps = 0.0, bad = 0.0;
@@ -277,6 +300,7 @@ like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const
       lf.p[i] = pv;
       if (lf.drift) dist[i] = dist[i] + e * lf.minv * pv;
     }
+    if (next) bin_point(i, dist[i], cat, cm, next->n_grid, next->out);
     bad = (ok_d && ok_h) ? 0.0 : 1.0;
   }
   const double a = block_sum(psi, red);
@@ -389,11 +413,15 @@ template <typename T, int N> __device__ __forceinline__ Cosmo cosmo(const Ws<T, 
   return c;
 }
 
+template <typename T, int N> __device__ __forceinline__ BinOut bin_out(const Ws<T, N>& w) {
+  return BinOut{w.count(), w.key(), w.cellz(), w.frac()};
+}
+
 template <typename T, int N>
 __global__ void __launch_bounds__(kGalThreads) k_bin_count(Launch L) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
-  bin_count_body(k.st.qd, catalogue(k.w, k.n_gal), cosmo(k.w), N, k.w.count(), k.w.key(), k.w.cellz(), k.w.frac());
+  bin_count_body(k.st.qd, catalogue(k.w, k.n_gal), cosmo(k.w), N, bin_out(k.w));
 }
 
 template <typename T, int N>
@@ -451,8 +479,10 @@ __global__ void __launch_bounds__(kGalThreads) k_like(Launch L) {
   lo.prior_part = k.w.prior_part();
   lo.n_prior = pc.n_prior_part;
   lo.n_blocks = pc.n_like_part;
+  const BinNext next{bin_out(k.w), N};
   like_body<T>(k.w.part(), k.w.gid(), k.w.frac(), k.st.qd, k.st.qs, catalogue(k.w, k.n_gal), cosmo(k.w),
-               k.w.gsort(), lo, leap_update(k.mode, pc.sample_d, k.st.pd, k.st.eps, pc.minv_d));
+               k.w.gsort(), lo, leap_update(k.mode, pc.sample_d, k.st.pd, k.st.eps, pc.minv_d),
+               k.mode == kXMid ? &next : nullptr);
   // The plan's last block to finish completes the evaluation: it sums every
   // block's partials in block order (the final sums) and resets the ticket.
   __shared__ int last;

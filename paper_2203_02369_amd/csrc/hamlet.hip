@@ -183,7 +183,14 @@ static hamlet_status eval_impl(const Batch& b) {
     constexpr unsigned tiles = (N * N + kScanTile - 1) / kScanTile;
     const dim3 g_gal(blocks_for(ng, kGalThreads), 1, nb);
     prof_before(b, HAMLET_K_BIN);
-    k_bin_count<T, N><<<g_gal, kGalThreads, 0, st>>>(sel);
+    // points are counted here only before a plain gradient; inside a
+    // trajectory the drifting kernels binned them already
+    if (batch_has(b, kXGrad)) {
+      Batch grad = b;
+      for (int i = 0; i < b.count; ++i)
+        if (grad.mode[i] != kXGrad) grad.mode[i] = kXSkip;
+      k_bin_count<T, N><<<g_gal, kGalThreads, 0, st>>>(launch_table(grad));
+    }
     k_bin_scan_tiles<T, N><<<dim3(tiles, 1, nb), kScanTile, 0, st>>>(sel);
     k_bin_scan_add<T, N><<<dim3(tiles, 1, nb), kScanTile, 0, st>>>(sel);
     k_bin_place<T, N><<<g_gal, kGalThreads, 0, st>>>(sel);

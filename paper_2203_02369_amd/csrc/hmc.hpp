@@ -7,6 +7,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "galaxies.hpp"
 #include "passes.hpp"
 #include "workspace.hpp"
 
@@ -230,7 +231,8 @@ __global__ void __launch_bounds__(256) k_kinetic_final(Launch L, int which) {
 }
 
 // First half kick (from the cached gradient) and drift of the distances and
-// of s: p -= (eps/2) g, q += eps M^-1 p.
+// of s: p -= (eps/2) g, q += eps M^-1 p; then the binning of the drifted
+// points for the next evaluation.
 template <typename T, int N>
 __global__ void __launch_bounds__(kEltThreads) k_small_kick_drift(Launch L) {
   const Pick<T, N> k(L);
@@ -239,10 +241,13 @@ __global__ void __launch_bounds__(kEltThreads) k_small_kick_drift(Launch L) {
   const PlanConst& pc = k.w.pc();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const double e = st.eps[0];
-  if (i < k.n_gal && pc.sample_d) {
-    const double pv = st.pd[i] - 0.5 * e * st.gd[i];
-    st.pd[i] = pv;
-    st.qd[i] += e * pc.minv_d * pv;
+  if (i < k.n_gal) {
+    if (pc.sample_d) {
+      const double pv = st.pd[i] - 0.5 * e * st.gd[i];
+      st.pd[i] = pv;
+      st.qd[i] += e * pc.minv_d * pv;
+    }
+    bin_point(i, st.qd[i], catalogue(k.w, k.n_gal), cosmo(k.w), N, bin_out(k.w));
   }
   if (i == 0 && pc.sample_s) {
     const double pv = st.ps[0] - 0.5 * e * st.gs[0];

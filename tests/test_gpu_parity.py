@@ -243,6 +243,30 @@ def test_leapfrog_matches_oracle(hl, precision):
     plan.close()
 
 
+@pytest.mark.parametrize("steps", [1, 3])
+def test_gradient_after_a_trajectory_is_unchanged(hl, steps):
+    # Inside a trajectory the drifting kernels bin the points of the next
+    # evaluation ahead of it; a plain gradient after a finished trajectory
+    # must find the plan's binning state as a fresh plan has it.
+    m, prob, dhat, d, s, ref = case("64^3 L500 n2000 inv_r ZoA")
+    say("gradient after a trajectory of", steps)
+    plan = hl.Plan.from_mock(m, precision="fp32")
+    before = gpu_grad(hl, plan, dhat, d, s)
+    dev = plan.device
+    p0 = _random_momenta(prob, 9)
+    tq = torch.from_numpy(to_lib_layout(dhat)).to(dev)
+    tqd = torch.from_numpy(d.copy()).to(dev)
+    tqs = plan.scalar(s)
+    tp = torch.from_numpy(to_lib_layout(p0.modes)).to(dev)
+    tpd = torch.from_numpy(p0.dist.copy()).to(dev)
+    tps = plan.scalar(p0.s)
+    hl.leapfrog([plan], [0.01], [steps], [tq], [tqd], [tqs], [tp], [tpd], [tps], [plan.scalar()])
+    after = gpu_grad(hl, plan, dhat, d, s)
+    assert before[0] == after[0] and before[3] == after[3]
+    assert np.array_equal(before[1], after[1]) and np.array_equal(before[2], after[2])
+    plan.close()
+
+
 # ----------------------------------------------------------------------- HMC --
 
 def test_hmc_chain_matches_oracle_fp64(hl):
