@@ -229,8 +229,21 @@ inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict_
   constexpr int P = S::P, H = S::H, F = S::F;
   __shared__ C buf[LAY::size(F)];
   __shared__ C twl[N];
-  load_twiddles<T, N, NT>(twl, tw);
   const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
+  // Gather: (pencil, corner, lane) per thread; lane strides the bucket.  The
+  // column range is loaded first, and (FP32) the first point before the
+  // transform, so that their latency overlaps the field loads and the FFT;
+  // the FP64 path loads its points after the transform, which keeps its
+  // registers, and occupancy, where they were.
+  constexpr int LANES = NT / (4 * P);
+  const int t = threadIdx.x;
+  const int pc = t % (4 * P), lane = t / (4 * P);
+  const int p = pc >> 2, corner = pc & 3;
+  const int ox = corner >> 1, oy = corner & 1;
+  const int y = y0 + p;
+  const int key = ((x - ox + N) & (N - 1)) * N + ((y - oy + N) & (N - 1));
+  const int s0 = bins.off[key], s1 = bins.off[key + 1];
+  load_twiddles<T, N, NT>(twl, tw);
   // Build Z = A + i B with A, B the Hermitian half spectra of the two real
   // pencils of each transform (Nyquist entry zero, DC entries real).
   for (int idx = threadIdx.x; idx < F * H; idx += NT) {
@@ -255,30 +268,32 @@ inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict_
     }
   }
   __syncthreads();
+  constexpr bool kEarly = sizeof(T) == 4;
+  int s = s0 + lane;
+  int pz = 0;
+  T ptz = 0, prx = 0, pry = 0, prz = 0;
+  auto load_point = [&](int i) {
+    pz = bins.iz[i];
+    ptz = bins.tz[i];
+    prx = bins.rx[i];
+    pry = bins.ry[i];
+    prz = bins.rz[i];
+  };
+  if (kEarly && s < s1) load_point(s);
   lds_fft<T, N, F, LAY, NT, +1>(buf, twl);
-  // Gather: (pencil, corner, lane) per thread; lane strides the bucket.
-  constexpr int LANES = NT / (4 * P);
-  {
-    const int t = threadIdx.x;
-    const int pc = t % (4 * P), lane = t / (4 * P);
-    const int p = pc >> 2, corner = pc & 3;
-    const int ox = corner >> 1, oy = corner & 1;
-    const int y = y0 + p;
-    const int key = ((x - ox + N) & (N - 1)) * N + ((y - oy + N) & (N - 1));
-    const int s0 = bins.off[key], s1 = bins.off[key + 1];
-    const int fxy = zslot_f(p, 0), fz = zslot_f(p, 2), sz = zslot_part(p, 2);
-    for (int s = s0 + lane; s < s1; s += LANES) {
-      const int z0 = bins.iz[s], z1 = (z0 + 1) & (N - 1);
-      const T tz = bins.tz[s];
-      const T rx = bins.rx[s], ry = bins.ry[s], rz = bins.rz[s];
-      const C a0 = buf[LAY::idx(z0, fxy)], a1 = buf[LAY::idx(z1, fxy)];
-      const C c0 = buf[LAY::idx(z0, fz)], c1 = buf[LAY::idx(z1, fz)];
-      const T az0 = sz ? c0.y : c0.x, az1 = sz ? c1.y : c1.x;
-      const T omt = (T)1 - tz;
-      const T pcv = rx * (omt * a0.x + tz * a1.x) + ry * (omt * a0.y + tz * a1.y) + rz * (omt * az0 + tz * az1);
-      const T qcv = rx * (a1.x - a0.x) + ry * (a1.y - a0.y) + rz * (az1 - az0);
-      part[4 * (size_t)s + corner] = cmake<C>(pcv, qcv);
-    }
+  const int fxy = zslot_f(p, 0), fz = zslot_f(p, 2), sz = zslot_part(p, 2);
+  for (; s < s1; s += LANES) {
+    if (!kEarly) load_point(s);
+    const int z0 = pz, z1 = (z0 + 1) & (N - 1);
+    const T tz = ptz, rx = prx, ry = pry, rz = prz;
+    const C a0 = buf[LAY::idx(z0, fxy)], a1 = buf[LAY::idx(z1, fxy)];
+    const C c0 = buf[LAY::idx(z0, fz)], c1 = buf[LAY::idx(z1, fz)];
+    const T az0 = sz ? c0.y : c0.x, az1 = sz ? c1.y : c1.x;
+    const T omt = (T)1 - tz;
+    const T pcv = rx * (omt * a0.x + tz * a1.x) + ry * (omt * a0.y + tz * a1.y) + rz * (omt * az0 + tz * az1);
+    const T qcv = rx * (a1.x - a0.x) + ry * (a1.y - a0.y) + rz * (az1 - az0);
+    part[4 * (size_t)s + corner] = cmake<C>(pcv, qcv);
+    if (kEarly && s + LANES < s1) load_point(s + LANES);
   }
 }
 
@@ -296,7 +311,7 @@ __device__ __forceinline__ int lower_bound_cell(const I* iz, int lo, int hi, int
 // The binned points of the stencil columns of a z tile (columns x and x - 1,
 // rows y0 - 1 .. y0 + P - 1) are at most four contiguous ranges of the
 // binned arrays: rows max(y0 - 1, 0) .. y0 + P - 1 of each column index, and
-// row N - 1 when y0 = 0.  Crowded tiles stage them in LDS when they fit.
+// row N - 1 when y0 = 0.  A tile stages them in LDS when they fit.
 template <typename T, int CAP> struct ZStage {
   T g[CAP], tx[CAP], ty[CAP], tz[CAP], r[3][CAP];
   int16_t iz[CAP];
@@ -312,12 +327,15 @@ __device__ __forceinline__ int stage_index(const int* start, const int* at, int 
 // ---------------------------------------------------------------------------
 // Forward pass 1 (along z, real-to-complex) fused with the CIC scatter-add:
 //   G_c(x_j) = sum_i g_i rhat_ic W_i(x_j)  (adjoint of the gather)
-// Each real pencil of the tile is built in LDS, every node summing its
-// contributions in a fixed order, so the result is deterministic.
-//  * Sparse grids (no column holds more than 8 points): one thread per
-//    (pencil, component) adds the points of its four stencil columns,
-//    corner by corner in binned order.
-//  * Crowded grids: the points of a column are sorted by z cell, so the
+// Every output sums its contributions in a fixed order, so the result is
+// deterministic.  The tile's points (at most four contiguous ranges of the
+// binned arrays) are staged in LDS when they fit.
+//  * Sparse grids (no column holds more than 8 points): a pencil has only a
+//    few nonzero nodes, so each output coefficient is summed directly over
+//    the points of the pencil's four stencil columns (corner by corner, in
+//    binned order) instead of building the pencil and transforming it.
+//  * Crowded grids: each real pencil is built in LDS and transformed.  The
+//    points of a column are sorted by z cell, so the
 //    points that reach node j are two runs per stencil column (z cell j - 1
 //    with weight tz, then z cell j with weight 1 - tz); G lanes share each
 //    (pencil, component) row, lane l owning the nodes of one z segment, and
@@ -336,132 +354,148 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
   constexpr int P = S::P, H = S::H, F = S::F;
   constexpr int GMAX_T = NT / (3 * P) >= 16 ? 16 : (NT / (3 * P) >= 8 ? 8 : (NT / (3 * P) >= 4 ? 4 : 1));
   constexpr int GMAX = GMAX_T < N ? GMAX_T : N;
-  // stage capacity (points); the FP64 path keeps its LDS for occupancy and
-  // reads crowded columns from the binned arrays
-  constexpr int CAP = sizeof(T) == 4 ? 256 : 1;
+  // stage capacity (points); the FP64 path keeps its LDS small for occupancy
+  constexpr int CAP = sizeof(T) == 4 ? 256 : 32;
   __shared__ C buf[LAY::size(F)];
   __shared__ C twl[N];
   __shared__ int col[4 * P][2];     // binned range of the 4 stencil columns of each pencil
   __shared__ ZStage<T, CAP> stg;
-  load_twiddles<T, N, NT>(twl, tw);
-  for (int i = threadIdx.x; i < LAY::size(F); i += NT) buf[i] = cmake<C>((T)0, (T)0);
   const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
+  static_assert(4 * P + 4 <= 64, "tile set-up runs in the first wave");
+  // Tile set-up, issued first so that its loads overlap the twiddle load:
+  // lanes 0 .. 4P-1 load the stencil columns, lanes 4P .. 4P+3 the four
+  // ranges of the binned arrays that hold them.
+  if (threadIdx.x < 64) {
+    const int t = threadIdx.x;
+    int a = 0, b = 0;
+    if (t < 4 * P) {
+      const int p = t >> 2, corner = t & 3;
+      const int ox = corner >> 1, oy = corner & 1;
+      const int key = ((x - ox + N) & (N - 1)) * N + ((y0 + p - oy + N) & (N - 1));
+      a = bins.off[key];
+      b = bins.off[key + 1];
+      col[t][0] = a;
+      col[t][1] = b;
+    } else if (t < 4 * P + 4) {
+      const int r = t - 4 * P, ox = r >> 1, wrap = r & 1;
+      const int kx = ((x - ox + N) & (N - 1)) * N;
+      if (!wrap) {
+        a = bins.off[kx + (y0 > 0 ? y0 - 1 : 0)];
+        b = bins.off[kx + y0 + P];
+      } else if (y0 == 0) {
+        a = bins.off[kx + N - 1];
+        b = bins.off[kx + N];
+      }
+      stg.start[r] = a;
+    }
+    const int len = (t >= 4 * P && t < 4 * P + 4) ? b - a : 0;
+    const int l0 = __shfl(len, 4 * P, 64), l1 = __shfl(len, 4 * P + 1, 64);
+    const int l2 = __shfl(len, 4 * P + 2, 64), l3 = __shfl(len, 4 * P + 3, 64);
+    if (t == 0) {
+      stg.at[0] = 0;
+      stg.at[1] = l0;
+      stg.at[2] = l0 + l1;
+      stg.at[3] = l0 + l1 + l2;
+      stg.count = l0 + l1 + l2 + l3;
+    }
+  }
+  load_twiddles<T, N, NT>(twl, tw);
   const int most = bins.most[0];
   int G = 1;
   while (G < GMAX && 8 * G < most) G <<= 1;
-  T* row = reinterpret_cast<T*>(buf);
-  if (G == 1) {
+  __syncthreads();
+  const bool staged = stg.count <= CAP;   // block-uniform
+  if (staged) {
+    for (int i = threadIdx.x; i < stg.count; i += NT) {
+      int r = 0;
+      while (r < 3 && i >= stg.at[r + 1]) ++r;
+      const int s = stg.start[r] + (i - stg.at[r]);
+      stg.g[i] = gsort[s];
+      stg.tx[i] = bins.tx[s];
+      stg.ty[i] = bins.ty[s];
+      stg.tz[i] = bins.tz[s];
+      stg.r[0][i] = bins.rx[s];
+      stg.r[1][i] = bins.ry[s];
+      stg.r[2][i] = bins.rz[s];
+      stg.iz[i] = (int16_t)bins.iz[s];
+    }
+  }
+  if (G == 1 && staged) {
+    // Sparse tile: a pencil holds a few nonzero nodes, so each output is the
+    // direct sum  X_c(k) = sum_points v_c [(1 - tz) w^(z0 k) + tz w^((z0+1) k)],
+    // w = exp(-2 pi i / N), over the pencil's stencil columns (corner by
+    // corner, binned order); the bracket is shared by the three components.
     __syncthreads();
-    if (threadIdx.x < 3 * P) {
-      const int p = threadIdx.x / 3, c = threadIdx.x % 3, y = y0 + p;
-      const int f = zslot_f(p, c), part = zslot_part(p, c);
-      for (int corner = 0; corner < 4; ++corner) {
-        const int ox = corner >> 1, oy = corner & 1;
-        const int key = ((x - ox + N) & (N - 1)) * N + ((y - oy + N) & (N - 1));
-        const int s0 = bins.off[key], s1 = bins.off[key + 1];
-        for (int s = s0; s < s1; ++s) {
-          const T tx = bins.tx[s], ty = bins.ty[s], tz = bins.tz[s];
-          const T wxy = (ox ? tx : (T)1 - tx) * (oy ? ty : (T)1 - ty);
-          const T rc = c == 0 ? bins.rx[s] : (c == 1 ? bins.ry[s] : bins.rz[s]);
-          const T val = gsort[s] * wxy * rc;
-          const int z0 = bins.iz[s], z1 = (z0 + 1) & (N - 1);
-          row[2 * LAY::idx(z0, f) + part] += val * ((T)1 - tz);
-          row[2 * LAY::idx(z1, f) + part] += val * tz;
-        }
-      }
-    }
-  } else {
-    static_assert(4 * P + 4 <= 64, "tile set-up runs in the first wave");
-    if (threadIdx.x < 64) {
-      // lanes 0 .. 4P-1: the stencil columns; lanes 4P .. 4P+3: the four ranges
-      const int t = threadIdx.x;
-      int a = 0, b = 0;
-      if (t < 4 * P) {
-        const int p = t >> 2, corner = t & 3;
-        const int ox = corner >> 1, oy = corner & 1;
-        const int key = ((x - ox + N) & (N - 1)) * N + ((y0 + p - oy + N) & (N - 1));
-        a = bins.off[key];
-        b = bins.off[key + 1];
-        col[t][0] = a;
-        col[t][1] = b;
-      } else if (t < 4 * P + 4) {
-        const int r = t - 4 * P, ox = r >> 1, wrap = r & 1;
-        const int kx = ((x - ox + N) & (N - 1)) * N;
-        if (!wrap) {
-          a = bins.off[kx + (y0 > 0 ? y0 - 1 : 0)];
-          b = bins.off[kx + y0 + P];
-        } else if (y0 == 0) {
-          a = bins.off[kx + N - 1];
-          b = bins.off[kx + N];
-        }
-        stg.start[r] = a;
-      }
-      // stage offsets of the four ranges
-      const int len = (t >= 4 * P && t < 4 * P + 4) ? b - a : 0;
-      const int l0 = __shfl(len, 4 * P, 64), l1 = __shfl(len, 4 * P + 1, 64);
-      const int l2 = __shfl(len, 4 * P + 2, 64), l3 = __shfl(len, 4 * P + 3, 64);
-      if (t == 0) {
-        stg.at[0] = 0;
-        stg.at[1] = l0;
-        stg.at[2] = l0 + l1;
-        stg.at[3] = l0 + l1 + l2;
-        stg.count = l0 + l1 + l2 + l3;
-      }
-    }
-    __syncthreads();
-    const bool staged = CAP > 1 && stg.count <= CAP;   // block-uniform
-    if (staged) {
-      for (int i = threadIdx.x; i < stg.count; i += NT) {
-        int r = 0;
-        while (r < 3 && i >= stg.at[r + 1]) ++r;
-        const int s = stg.start[r] + (i - stg.at[r]);
-        stg.g[i] = gsort[s];
-        stg.tx[i] = bins.tx[s];
-        stg.ty[i] = bins.ty[s];
-        stg.tz[i] = bins.tz[s];
-        stg.r[0][i] = bins.rx[s];
-        stg.r[1][i] = bins.ry[s];
-        stg.r[2][i] = bins.rz[s];
-        stg.iz[i] = (int16_t)bins.iz[s];
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x < 3 * P * G) {
-      const int lane = threadIdx.x % G, pc = threadIdx.x / G;
-      const int p = pc / 3, c = pc % 3;
-      const int seg = N / G, za = lane * seg, zb = za + seg;
-      const int zl = (za - 1) & (N - 1);
-      const int f = zslot_f(p, c), part = zslot_part(p, c);
-      const T* rcs = c == 0 ? bins.rx : (c == 1 ? bins.ry : bins.rz);
+    for (int idx = threadIdx.x; idx < P * H; idx += NT) {
+      const int k = idx % H, p = idx / H;
+      const C wk = twl[k];
+      T ax = 0, ay = 0, bx = 0, by = 0, cx = 0, cy = 0;
       for (int corner = 0; corner < 4; ++corner) {
         const int s0 = col[4 * p + corner][0], s1 = col[4 * p + corner][1];
-        if (s0 == s1) continue;
         const int ox = corner >> 1, oy = corner & 1;
-        // the run of z cell za - 1 puts its upper weight on node za; cells
-        // za .. zb - 1 put their lower weight on node z and their upper weight
-        // on node z + 1 inside the segment
-        auto scatter = [&](auto g_, auto tx_, auto ty_, auto tz_, auto r_, auto iz_, int lo, int hi) {
-          auto value = [&](int s) {
-            const T tx = tx_[s], ty = ty_[s];
-            const T wxy = (ox ? tx : (T)1 - tx) * (oy ? ty : (T)1 - ty);
-            return g_[s] * wxy * r_[s];
-          };
-          for (int s = lower_bound_cell(iz_, lo, hi, zl); s < hi && (int)iz_[s] == zl; ++s)
-            row[2 * LAY::idx(za, f) + part] += value(s) * tz_[s];
-          for (int s = lower_bound_cell(iz_, lo, hi, za); s < hi && (int)iz_[s] < zb; ++s) {
-            const int z = iz_[s];
-            const T v = value(s), tz = tz_[s];
-            row[2 * LAY::idx(z, f) + part] += v * ((T)1 - tz);
-            if (z + 1 < zb) row[2 * LAY::idx(z + 1, f) + part] += v * tz;
-          }
-        };
-        if (staged) {
-          const bool wrap_row = y0 == 0 && p - oy < 0;
-          const int lo = stage_index(stg.start, stg.at, s0, ox, wrap_row);
-          scatter(stg.g, stg.tx, stg.ty, stg.tz, stg.r[c], stg.iz, lo, lo + (s1 - s0));
-        } else {
-          scatter(gsort, bins.tx, bins.ty, bins.tz, rcs, bins.iz, s0, s1);
+        const bool wrap_row = y0 == 0 && p - oy < 0;
+        const int lo = stage_index(stg.start, stg.at, s0, ox, wrap_row);
+        for (int i = lo; i < lo + (s1 - s0); ++i) {
+          const T tx = stg.tx[i], ty = stg.ty[i], tz = stg.tz[i];
+          const T v = stg.g[i] * ((ox ? tx : (T)1 - tx) * (oy ? ty : (T)1 - ty));
+          const C w0 = twl[((int)stg.iz[i] * k) & (N - 1)];
+          const T ux = ((T)1 - tz) + tz * wk.x, uy = tz * wk.y;
+          const T wx = w0.x * ux - w0.y * uy, wy = w0.x * uy + w0.y * ux;
+          const T vx = v * stg.r[0][i], vy = v * stg.r[1][i], vz = v * stg.r[2][i];
+          ax += vx * wx;
+          ay += vx * wy;
+          bx += vy * wx;
+          by += vy * wy;
+          cx += vz * wx;
+          cy += vz * wy;
         }
+      }
+      const size_t g = gofs<N>(x, y0 + p, k);
+      gx[g] = cmake<C>(ax, ay);
+      gy[g] = cmake<C>(bx, by);
+      gz[g] = cmake<C>((T)k * cx, (T)k * cy);
+    }
+    return;
+  }
+  // Dense tiles: pencils built in LDS and transformed.
+  for (int i = threadIdx.x; i < LAY::size(F); i += NT) buf[i] = cmake<C>((T)0, (T)0);
+  __syncthreads();
+  T* row = reinterpret_cast<T*>(buf);
+  if (threadIdx.x < 3 * P * G) {
+    const int lane = threadIdx.x % G, pc = threadIdx.x / G;
+    const int p = pc / 3, c = pc % 3;
+    const int seg = N / G, za = lane * seg, zb = za + seg;
+    const int zl = (za - 1) & (N - 1);
+    const int f = zslot_f(p, c), part = zslot_part(p, c);
+    const T* rcs = c == 0 ? bins.rx : (c == 1 ? bins.ry : bins.rz);
+    for (int corner = 0; corner < 4; ++corner) {
+      const int s0 = col[4 * p + corner][0], s1 = col[4 * p + corner][1];
+      if (s0 == s1) continue;
+      const int ox = corner >> 1, oy = corner & 1;
+      // the run of z cell za - 1 puts its upper weight on node za; cells
+      // za .. zb - 1 put their lower weight on node z and their upper weight
+      // on node z + 1 inside the segment
+      auto scatter = [&](auto g_, auto tx_, auto ty_, auto tz_, auto r_, auto iz_, int lo, int hi) {
+        auto value = [&](int s) {
+          const T tx = tx_[s], ty = ty_[s];
+          const T wxy = (ox ? tx : (T)1 - tx) * (oy ? ty : (T)1 - ty);
+          return g_[s] * wxy * r_[s];
+        };
+        for (int s = lower_bound_cell(iz_, lo, hi, zl); s < hi && (int)iz_[s] == zl; ++s)
+          row[2 * LAY::idx(za, f) + part] += value(s) * tz_[s];
+        for (int s = lower_bound_cell(iz_, lo, hi, za); s < hi && (int)iz_[s] < zb; ++s) {
+          const int z = iz_[s];
+          const T v = value(s), tz = tz_[s];
+          row[2 * LAY::idx(z, f) + part] += v * ((T)1 - tz);
+          if (z + 1 < zb) row[2 * LAY::idx(z + 1, f) + part] += v * tz;
+        }
+      };
+      if (staged) {
+        const bool wrap_row = y0 == 0 && p - oy < 0;
+        const int lo = stage_index(stg.start, stg.at, s0, ox, wrap_row);
+        scatter(stg.g, stg.tx, stg.ty, stg.tz, stg.r[c], stg.iz, lo, lo + (s1 - s0));
+      } else {
+        scatter(gsort, bins.tx, bins.ty, bins.tz, rcs, bins.iz, s0, s1);
       }
     }
   }
