@@ -190,12 +190,13 @@ def main():
     # spectral array c (8 N^2 N/2 bytes; complex128 arrays count 2c; the FP64
     # per-mode prior variance sigma_k^2 counts 1c):
     #   plain gradient (1 per run):        S1, S2, q, var in; G out           =  7c
-    #   first step of a trajectory:        G, p, q, var in; p, q, A, B out    = 13c
+    #   first step of a chain's trajectory: G, p, q, var in; p, q, A, B and
+    #                                       the kept start q0, G0 out       = 17c
     #   middle steps (L - 1 per traj.):    S1, S2, p, q, var in; p, q, A, B   = 13c
     #   last step:                         S1, S2, p, q, var in; p, G out     = 11c
     nm = n * n * (n // 2)
     c32 = 8 * nm
-    x_bytes = c32 * (7 + args.steps * (13 + 13 * (L - 1) + 11))
+    x_bytes = c32 * (7 + args.steps * (17 + 13 * (L - 1) + 11))
     x_launches = 1 + args.steps * (L + 1)
     assert kern_launches == x_launches, (kern_launches, x_launches)
     avg_ms = kern_ms / kern_launches
@@ -301,10 +302,10 @@ def run_batched(args, dev):
     rate = float(np.mean([a.cpu().numpy()[args.warmup:].mean() for a in acc]))
 
     # roofline of the x pass of the 256^3 group (5 chains per launch):
-    # per chain and iteration first 13c, L - 1 middle 13c, last 11c.
+    # per chain and iteration first 17c, L - 1 middle 13c, last 11c.
     n256 = [p for p in plans if p.n_grid == 256]
     c32 = 8 * 256 * 256 * 128
-    per_iter = len(n256) * c32 * (13 + 13 * (L - 1) + 11)
+    per_iter = len(n256) * c32 * (17 + 13 * (L - 1) + 11)
     assert kern_launches == args.steps * (L + 1), (kern_launches, args.steps * (L + 1))
     avg_ms = kern_ms / kern_launches
     per_launch = per_iter * args.steps / kern_launches

@@ -62,6 +62,7 @@ struct Batch {
   hamlet_plan* plan[kMaxBatch] = {};
   int8_t mode[kMaxBatch] = {};
   double plane_scale = 1.0;   // kXGrad: factor on the kz = 0 plane of the gradient
+  bool chain = false;         // first steps: trajectories of chains (momenta drawn here, start kept)
 };
 
 // Launch sequences and workspace layout, one instantiation per (precision, N).
@@ -234,16 +235,6 @@ static hamlet_status eval_impl(const Batch& b) {
   return HAMLET_OK;
 }
 
-// Kinetic energy of every plan of the batch into kin0 (which = 0) or kin1.
-template <typename T, int N>
-static hamlet_status kinetic_impl(const Batch& b, const Launch& sel, int which) {
-  const unsigned nb = (unsigned)b.count;
-  k_kinetic_modes<T, N><<<dim3(FixedLayout<N, sizeof(T)>::N_KIN, 1, nb), kEltThreads, 0, b.stream>>>(sel);
-  k_kinetic_final<T, N><<<dim3(1, 1, nb), 256, 0, b.stream>>>(sel, which);
-  LAUNCH_CHECK();
-  return HAMLET_OK;
-}
-
 static int batch_gal_or_one(const Batch& b) {
   int m = 1;
   for (int i = 0; i < b.count; ++i) m = std::max(m, b.plan[i]->n_gal);
@@ -251,22 +242,17 @@ static int batch_gal_or_one(const Batch& b) {
 }
 
 // Start of a trajectory of every plan of the batch: the iteration's step,
-// fresh momenta, K0, and the saved state for a possible rejection.
+// fresh momenta, the saved distances and s, and their part of K0 (the mode
+// part, and the saved modes, come with the first step).
 template <typename T, int N>
 static hamlet_status start_impl(const Batch& b) {
   if (b.count <= 0) return HAMLET_OK;
   const Launch sel = launch_table(b, 0);
   const unsigned nb = (unsigned)b.count;
   const size_t nm = (size_t)N * N * (N / 2);
-  const int ng = batch_gal_or_one(b);
   k_iter_begin<T, N><<<dim3(1, 1, nb), 64, 0, b.stream>>>(sel);
   k_momenta_modes<T, N><<<dim3(blocks_for(nm, kEltThreads), 1, nb), kEltThreads, 0, b.stream>>>(sel);
-  k_momenta_small<T, N><<<dim3(blocks_for(ng, kEltThreads), 1, nb), kEltThreads, 0, b.stream>>>(sel);
-  LAUNCH_CHECK();
-  hamlet_status s = kinetic_impl<T, N>(b, sel, 0);
-  if (s != HAMLET_OK) return s;
-  k_save_state<T, N><<<dim3(blocks_for(std::max(nm, (size_t)ng), kEltThreads), 1, nb), kEltThreads, 0, b.stream>>>(
-      sel);
+  k_momenta_small<T, N><<<dim3(FixedLayout<N, sizeof(T)>::N_KIN_SMALL, 1, nb), kEltThreads, 0, b.stream>>>(sel);
   LAUNCH_CHECK();
   return HAMLET_OK;
 }
@@ -282,7 +268,16 @@ static hamlet_status first_impl(const Batch& b) {
   const unsigned nb = (unsigned)b.count;
   k_small_kick_drift<T, N><<<dim3(blocks_for(batch_gal_or_one(b), kEltThreads), 1, nb), kEltThreads, 0, b.stream>>>(
       sel);
-  TIMED(b, HAMLET_K_FWD_X, (k_x_pass<T, N, kXFirst, TH::X><<<dim3(S::CHUNKS, N, nb), TH::X, 0, b.stream>>>(sel, 1.0)));
+  if (b.chain) {
+    // a chain's trajectory: the pass also keeps the start point and sums the
+    // mode part of K0, which is completed here
+    TIMED(b, HAMLET_K_FWD_X,
+          (k_x_pass<T, N, kXFirst, TH::X, true><<<dim3(S::CHUNKS, N, nb), TH::X, 0, b.stream>>>(sel, 1.0)));
+    k_kinetic_final<T, N><<<dim3(1, 1, nb), 256, 0, b.stream>>>(sel, 0);
+  } else {
+    TIMED(b, HAMLET_K_FWD_X,
+          (k_x_pass<T, N, kXFirst, TH::X><<<dim3(S::CHUNKS, N, nb), TH::X, 0, b.stream>>>(sel, 1.0)));
+  }
   LAUNCH_CHECK();
   return HAMLET_OK;
 }
@@ -295,8 +290,16 @@ static hamlet_status end_impl(const Batch& b) {
   const Launch sel = launch_table(b, 0);
   const unsigned nb = (unsigned)b.count;
   const size_t nm = (size_t)N * N * (N / 2);
-  hamlet_status s = kinetic_impl<T, N>(b, sel, 1);
-  if (s != HAMLET_OK) return s;
+  // K1 of the plans whose trajectory had steps (its last x pass summed the
+  // mode part); a trajectory without steps keeps K1 = K0
+  if (batch_has(b, kXLast)) {
+    Batch moved = b;
+    for (int i = 0; i < b.count; ++i)
+      if (moved.mode[i] != kXLast) moved.mode[i] = kXSkip;
+    const Launch kin = launch_table(moved);
+    k_kinetic_small<T, N><<<dim3(FixedLayout<N, sizeof(T)>::N_KIN_SMALL, 1, nb), kEltThreads, 0, b.stream>>>(kin);
+    k_kinetic_final<T, N><<<dim3(1, 1, nb), 256, 0, b.stream>>>(kin, 1);
+  }
   k_accept<T, N><<<dim3(1, 1, nb), 64, 0, b.stream>>>(sel);
   k_restore_accumulate<T, N><<<dim3(blocks_for(std::max(nm, (size_t)batch_gal_or_one(b)), kEltThreads), 1, nb),
                                kEltThreads, 0, b.stream>>>(sel);
@@ -710,6 +713,7 @@ struct ChainRun {
 static hamlet_status tick_group(hipStream_t stream, const std::vector<ChainRun*>& runs) {
   Batch start, first, eval, end;
   start.stream = first.stream = eval.stream = end.stream = stream;
+  first.chain = true;
   const Ops* ops = nullptr;
   for (ChainRun* r : runs) {
     if (!r->active()) continue;
@@ -724,7 +728,7 @@ static hamlet_status tick_group(hipStream_t stream, const std::vector<ChainRun*>
       if (r->L > 0) batch_add(first, r->pl, kXFirst);
     }
     if (r->L > 0) batch_add(eval, r->pl, ending ? kXLast : kXMid);
-    if (ending) batch_add(end, r->pl, 0);
+    if (ending) batch_add(end, r->pl, r->L > 0 ? kXLast : kXGrad);
   }
   if (!ops) return HAMLET_OK;
   hamlet_status s = ops->start(start);

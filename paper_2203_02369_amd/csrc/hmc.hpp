@@ -161,56 +161,67 @@ __global__ void __launch_bounds__(kEltThreads) k_momenta_modes(Launch L) {
   k.w.pm()[g] = out;
 }
 
-template <typename T, int N>
-__global__ void __launch_bounds__(kEltThreads) k_momenta_small(Launch L) {
-  const Pick<T, N> k(L);
-  if (k.mode == kXSkip) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const PlanConst& pc = k.w.pc();
-  const ChainScalars* cs = chain(k.w);
-  const uint64_t seed = cs->seed;
-  const uint32_t iteration = (uint32_t)cs->iter;
-  if (i < k.n_gal) {
-    k.w.pd()[i] = pc.sample_d ? pc.psd * normal_pair(draw_words(seed, iteration, kPurposeDist, i)).x : 0.0;
-  }
-  if (i == 0) k.w.ps()[0] = pc.sample_s ? normal_pair(draw_words(seed, iteration, kPurposeSnl, 0)).x : 0.0;
-}
-
 // ---------------------------------------------------------------------------
 // Kinetic energy K = (1/2) p^T M^-1 p: per stored mode (w_k / 8) sigma^2 |p|^2
 // (w_k = 1 on kz = 0 where both Hermitian partners are stored, else 2), per
-// distance (1/2) M_d^-1 p_d^2, and (1/2) M_s^-1 p_s^2; block partials, then
-// one block sums them in order into kin0 (which = 0, before the trajectory)
-// or kin1 (after).
+// distance (1/2) M_d^-1 p_d^2, and (1/2) M_s^-1 p_s^2.  The mode terms are
+// block partials of the x pass that starts (K0) or ends (K1) a trajectory;
+// the distance and s terms are N_KIN_SMALL block partials after them; one
+// block sums all of them in order into kin0 or kin1.
 // ---------------------------------------------------------------------------
+template <typename T, int N> __device__ __forceinline__ double* kin_small(const Ws<T, N>& w) {
+  return w.kin_part() + Ws<T, N>::F::N_PRIOR;
+}
+
+// Distance and s terms of the kinetic energy, one partial per block.
 template <typename T, int N>
-__global__ void __launch_bounds__(kEltThreads) k_kinetic_modes(Launch L) {
-  __shared__ double red[kEltThreads / 64];
-  const Pick<T, N> k(L);
-  if (k.mode == kXSkip) return;
-  const PlanConst& pc = k.w.pc();
-  const double2* __restrict__ p = k.w.pm();
-  const double* __restrict__ var = k.w.mvar();
-  const double* __restrict__ pd = k.w.pd();
-  const size_t total = (size_t)N * N * (N / 2);
-  const size_t stop = total > (size_t)k.n_gal ? total : (size_t)k.n_gal;
-  double acc = 0.0;
-  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < stop; g += (size_t)gridDim.x * blockDim.x) {
-    if (g < total) {
-      const ModeIdx m = mode_idx(g, N);
-      if (retained(m.sx, m.sy, m.kz, N)) {
-        const double2 v = ld_stream(&p[g]);
-        acc += (m.kz == 0 ? 0.125 : 0.25) * ld_stream(&var[g]) * (v.x * v.x + v.y * v.y);
-      }
-    }
-    if (g < (size_t)k.n_gal) acc += 0.5 * pc.minv_d * pd[g] * pd[g];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && pc.sample_s) {
+__device__ __forceinline__ void kinetic_small_part(const Pick<T, N>& k, double acc, double* red) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && k.w.pc().sample_s) {
     const double ps = k.w.ps()[0];
     acc += 0.5 * ps * ps;
   }
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) k.w.kin_part()[blockIdx.x] = s;
+  if (threadIdx.x == 0) kin_small(k.w)[blockIdx.x] = s;
+}
+
+// Momentum refresh of the distances and s (grid: N_KIN_SMALL blocks), the
+// saved start point of the small variables, and their part of K0.
+template <typename T, int N>
+__global__ void __launch_bounds__(kEltThreads) k_momenta_small(Launch L) {
+  __shared__ double red[kEltThreads / 64];
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  const PlanConst& pc = k.w.pc();
+  const ChainScalars* cs = chain(k.w);
+  const uint64_t seed = cs->seed;
+  const uint32_t iteration = (uint32_t)cs->iter;
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k.n_gal; i += gridDim.x * blockDim.x) {
+    const double pv = pc.sample_d ? pc.psd * normal_pair(draw_words(seed, iteration, kPurposeDist, i)).x : 0.0;
+    k.w.pd()[i] = pv;
+    k.w.qd0()[i] = k.st.qd[i];
+    k.w.gd0()[i] = k.w.gd()[i];
+    acc += 0.5 * pc.minv_d * pv * pv;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    k.w.ps()[0] = pc.sample_s ? normal_pair(draw_words(seed, iteration, kPurposeSnl, 0)).x : 0.0;
+    k.w.qs0()[0] = k.st.qs[0];
+  }
+  kinetic_small_part(k, acc, red);
+}
+
+// Distance and s terms of K1 (grid: N_KIN_SMALL blocks).
+template <typename T, int N>
+__global__ void __launch_bounds__(kEltThreads) k_kinetic_small(Launch L) {
+  __shared__ double red[kEltThreads / 64];
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  const double minv = k.w.pc().minv_d;
+  const double* __restrict__ pd = k.w.pd();
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k.n_gal; i += gridDim.x * blockDim.x)
+    acc += 0.5 * minv * pd[i] * pd[i];
+  kinetic_small_part(k, acc, red);
 }
 
 template <typename T, int N>
@@ -271,25 +282,9 @@ __global__ void k_iter_begin(Launch L) {
   cs->eps_it = e;
   cs->psi_saved = cs->psi;
   cs->gs_saved = cs->gs;
-}
-
-// Copies of the start of the trajectory (modes, cached gradient, distances,
-// their gradient, s) for a possible rejection.
-template <typename T, int N>
-__global__ void __launch_bounds__(kEltThreads) k_save_state(Launch L) {
-  const Pick<T, N> k(L);
-  if (k.mode == kXSkip) return;
-  const size_t total = (size_t)N * N * (N / 2);
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < total) {
-    st_stream(&k.w.q0()[i], ld_stream(&k.st.q[i]));
-    st_stream(&k.w.g0()[i], ld_stream(&k.w.gcache()[i]));
-  }
-  if (i < (size_t)k.n_gal) {
-    k.w.qd0()[i] = k.st.qd[i];
-    k.w.gd0()[i] = k.w.gd()[i];
-  }
-  if (i == 0) k.w.qs0()[0] = k.st.qs[0];
+  // set by the trajectory; equal (no change of H) when it has no steps
+  cs->kin0 = 0.0;
+  cs->kin1 = 0.0;
 }
 
 // Metropolis-Hastings test of the end point (Section 3.2) and dual

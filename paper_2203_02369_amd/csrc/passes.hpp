@@ -558,6 +558,15 @@ fwd_y_body(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, c
   tile_elems<T, N, NT>([&](int, int y, int w) { s2[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
 }
 
+// Where a pass that starts or ends a trajectory leaves its by-products: the
+// saved start point (modes, cached gradient) and the kinetic-energy partial
+// of each block (one per x-pass block, in block order).
+struct ChainSave {
+  double2* q0;
+  double2* g0;
+  double* kin_part;
+};
+
 // ---------------------------------------------------------------------------
 // Pass along x at the end of a gradient evaluation, optionally fused with the
 // leapfrog update of the modes and the first inverse pass of the next
@@ -575,17 +584,21 @@ fwd_y_body(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, c
 //   kXLast  : G from S1, S2; kick p -= (eps/2) G; write G to `gcache`.
 // (eq:hamilton integrated by kick-drift-kick leapfrog, mass matrix eq:M_ab.)
 // ---------------------------------------------------------------------------
-template <typename T, int N, int MODE, int NT>
+template <typename T, int N, int MODE, int NT, bool CHAIN>
 __device__ __forceinline__ void
 x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ modes, double2* __restrict__ mom,
             double2* __restrict__ gcache, ModeTables tab, const cplx_t<T>* __restrict__ tw,
             const double* __restrict__ eps_ptr, cplx_t<T>* outA, cplx_t<T>* outB, double* __restrict__ prior_part,
-            double plane_scale) {
+            double plane_scale, ChainSave save) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Row;
   constexpr bool kFromSpectra = MODE != kXFirst;
   constexpr bool kDrift = MODE == kXFirst || MODE == kXMid;
+  // kinetic energy of the momenta: before the first kick of a chain's
+  // trajectory (K0), after the last kick (K1)
+  constexpr bool kStartOfChain = CHAIN && MODE == kXFirst;
+  constexpr bool kKinetic = kStartOfChain || MODE == kXLast;
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
   __shared__ double red[NT / 64];
@@ -608,7 +621,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
   }
   const double eps = MODE == kXGrad ? 0.0 : eps_ptr[0];
   const double hk = MODE == kXMid ? eps : 0.5 * eps;
-  double prior = 0.0;
+  double prior = 0.0, kin = 0.0;
   // B-input of the next inverse pass (n_x times the A-input), kept in registers
   C bin[elems_per_thread<T, N, NT>()];
   tile_elems<T, N, NT>([&](int e, int x, int w) {
@@ -619,7 +632,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
     const double var = keep ? ld_stream(&tab.var[g]) : 0.0;
     // the mode, read once (gradient and drift)
     double2 q = make_double2(0.0, 0.0);
-    if (keep && (kFromSpectra || kDrift)) q = ld_stream(&modes[g]);
+    if (kStartOfChain || (keep && (kFromSpectra || kDrift))) q = ld_stream(&modes[g]);
     double2 G = make_double2(0.0, 0.0);
     if constexpr (kFromSpectra) {
       if (keep) {
@@ -637,10 +650,20 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
       st_stream(&gcache[g], kz == 0 ? make_double2(plane_scale * G.x, plane_scale * G.y) : G);
     }
     if constexpr (MODE == kXLast) st_stream(&gcache[g], G);
+    if constexpr (kStartOfChain) {
+      // the start of the trajectory, kept for a rejection
+      st_stream(&save.q0[g], q);
+      st_stream(&save.g0[g], G);
+    }
     if constexpr (MODE != kXGrad) {
       double2 p = ld_stream(&mom[g]);
+      // per stored mode (w / 8) sigma^2 |p|^2, w = 1 on kz = 0 (both
+      // Hermitian partners stored), else 2
+      const double wk = kz == 0 ? 0.125 : 0.25;
+      if (kStartOfChain && keep) kin += wk * var * (p.x * p.x + p.y * p.y);
       p.x -= hk * G.x;
       p.y -= hk * G.y;
+      if (MODE == kXLast && keep) kin += wk * var * (p.x * p.x + p.y * p.y);
       st_stream(&mom[g], p);
       if constexpr (kDrift) {
         double2 a = make_double2(0.0, 0.0);
@@ -658,6 +681,12 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
       }
     }
   });
+  if constexpr (kKinetic) {
+    const double ks = block_sum(kin, red);
+    if (threadIdx.x == 0) save.kin_part[blockIdx.y * gridDim.x + blockIdx.x] = ks;
+  } else {
+    (void)kin;
+  }
   if constexpr (kDrift) {
     const double ps = block_sum(prior, red);
     if (threadIdx.x == 0) prior_part[blockIdx.y * gridDim.x + blockIdx.x] = ps;
@@ -734,12 +763,15 @@ __global__ void __launch_bounds__(NT) k_fwd_y(Launch L, int x0) {
 }
 
 // One launch per mode present in a batch; plans in another mode return.
-template <typename T, int N, int MODE, int NT>
+// CHAIN: the first step of a chain's trajectory, which also keeps the start
+// point and sums K0.
+template <typename T, int N, int MODE, int NT, bool CHAIN = false>
 __global__ void __launch_bounds__(NT) k_x_pass(Launch L, double plane_scale) {
   const Pick<T, N> k(L);
   if (k.mode != MODE) return;
-  x_pass_body<T, N, MODE, NT>(k.w.a(), k.w.b(), k.st.q, k.st.p, k.st.g, tables(k.w), k.w.tw(), k.st.eps, k.w.a(),
-                              k.w.b(), k.w.prior_part(), plane_scale);
+  const ChainSave save{k.w.q0(), k.w.g0(), k.w.kin_part()};
+  x_pass_body<T, N, MODE, NT, CHAIN>(k.w.a(), k.w.b(), k.st.q, k.st.p, k.st.g, tables(k.w), k.w.tw(), k.st.eps,
+                                     k.w.a(), k.w.b(), k.w.prior_part(), plane_scale, save);
 }
 
 }  // namespace hamlet

@@ -74,7 +74,8 @@ template <int N, int R> struct FixedLayout {
   static constexpr size_t NPK = 3 * size_t(N / 2) * (N / 2) + 1; // |n|^2 table
   static constexpr int W = (R == 4 ? 16 : 8) < N / 2 ? (R == 4 ? 16 : 8) : N / 2;
   static constexpr int N_PRIOR = N * ((N / 2) / W);              // x-pass blocks
-  static constexpr int N_KIN = 1024;                             // kinetic-energy blocks
+  static constexpr int N_KIN_SMALL = 64;                         // blocks of the distance and s terms
+  static constexpr int N_KIN = N_PRIOR + N_KIN_SMALL;            // kinetic-energy partials
   static constexpr size_t consts = 0;
   static constexpr size_t chain = align256(consts + sizeof(PlanConst));
   static constexpr size_t chain_bytes = 256;                     // ChainScalars
