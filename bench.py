@@ -56,7 +56,7 @@ X_TRAFFIC = {"grad": (334167781, 134217856), "first": (468408004, 401693867),
 def kernel_sources_sha1():
     import hashlib
     h = hashlib.sha1()
-    for f in ("passes.hpp", "fft.hpp", "common.hpp", "workspace.hpp"):
+    for f in ("passes.hpp", "fft.hpp", "common.hpp", "workspace.hpp", "random.hpp"):
         with open(os.path.join(ROOT, "paper_2203_02369_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -190,13 +190,14 @@ def main():
     # spectral array c (8 N^2 N/2 bytes; complex128 arrays count 2c; the FP64
     # per-mode prior variance sigma_k^2 counts 1c):
     #   plain gradient (1 per run):        S1, S2, q, var in; G out           =  7c
-    #   first step of a chain's trajectory: G, p, q, var in; p, q, A, B and
-    #                                       the kept start q0, G0 out       = 17c
+    #   first step of a chain's trajectory (momenta drawn in the pass):
+    #                                       G, q, var in; p, q, A, B and the
+    #                                       kept start q0, G0 out           = 15c
     #   middle steps (L - 1 per traj.):    S1, S2, p, q, var in; p, q, A, B   = 13c
     #   last step:                         S1, S2, p, q, var in; p, G out     = 11c
     nm = n * n * (n // 2)
     c32 = 8 * nm
-    x_bytes = c32 * (7 + args.steps * (17 + 13 * (L - 1) + 11))
+    x_bytes = c32 * (7 + args.steps * (15 + 13 * (L - 1) + 11))
     x_launches = 1 + args.steps * (L + 1)
     assert kern_launches == x_launches, (kern_launches, x_launches)
     avg_ms = kern_ms / kern_launches
@@ -302,10 +303,10 @@ def run_batched(args, dev):
     rate = float(np.mean([a.cpu().numpy()[args.warmup:].mean() for a in acc]))
 
     # roofline of the x pass of the 256^3 group (5 chains per launch):
-    # per chain and iteration first 17c, L - 1 middle 13c, last 11c.
+    # per chain and iteration first 15c, L - 1 middle 13c, last 11c.
     n256 = [p for p in plans if p.n_grid == 256]
     c32 = 8 * 256 * 256 * 128
-    per_iter = len(n256) * c32 * (17 + 13 * (L - 1) + 11)
+    per_iter = len(n256) * c32 * (15 + 13 * (L - 1) + 11)
     assert kern_launches == args.steps * (L + 1), (kern_launches, args.steps * (L + 1))
     avg_ms = kern_ms / kern_launches
     per_launch = per_iter * args.steps / kern_launches

@@ -242,16 +242,15 @@ static int batch_gal_or_one(const Batch& b) {
 }
 
 // Start of a trajectory of every plan of the batch: the iteration's step,
-// fresh momenta, the saved distances and s, and their part of K0 (the mode
-// part, and the saved modes, come with the first step).
+// fresh momenta of the distances and s, their saved values and their part of
+// K0 (the mode momenta, their part of K0 and the saved modes come with the
+// first step).
 template <typename T, int N>
 static hamlet_status start_impl(const Batch& b) {
   if (b.count <= 0) return HAMLET_OK;
   const Launch sel = launch_table(b, 0);
   const unsigned nb = (unsigned)b.count;
-  const size_t nm = (size_t)N * N * (N / 2);
   k_iter_begin<T, N><<<dim3(1, 1, nb), 64, 0, b.stream>>>(sel);
-  k_momenta_modes<T, N><<<dim3(blocks_for(nm, kEltThreads), 1, nb), kEltThreads, 0, b.stream>>>(sel);
   k_momenta_small<T, N><<<dim3(FixedLayout<N, sizeof(T)>::N_KIN_SMALL, 1, nb), kEltThreads, 0, b.stream>>>(sel);
   LAUNCH_CHECK();
   return HAMLET_OK;
@@ -269,8 +268,8 @@ static hamlet_status first_impl(const Batch& b) {
   k_small_kick_drift<T, N><<<dim3(blocks_for(batch_gal_or_one(b), kEltThreads), 1, nb), kEltThreads, 0, b.stream>>>(
       sel);
   if (b.chain) {
-    // a chain's trajectory: the pass also keeps the start point and sums the
-    // mode part of K0, which is completed here
+    // a chain's trajectory: the pass also draws the mode momenta, keeps the
+    // start point and sums the mode part of K0, which is completed here
     TIMED(b, HAMLET_K_FWD_X,
           (k_x_pass<T, N, kXFirst, TH::X, true><<<dim3(S::CHUNKS, N, nb), TH::X, 0, b.stream>>>(sel, 1.0)));
     k_kinetic_final<T, N><<<dim3(1, 1, nb), 256, 0, b.stream>>>(sel, 0);

@@ -9,55 +9,12 @@
 #include "common.hpp"
 #include "galaxies.hpp"
 #include "passes.hpp"
+#include "random.hpp"
 #include "workspace.hpp"
 
 namespace hamlet {
 
 constexpr int kEltThreads = 256;
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11), counter (idx lo, idx hi, iteration,
-// purpose), key (seed lo, seed hi).
-// ---------------------------------------------------------------------------
-struct Philox4 { uint32_t v[4]; };
-
-__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                                 uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-    c0 = hi1 ^ c1 ^ k0; c1 = lo1; c2 = hi0 ^ c3 ^ k1; c3 = lo0;
-  }
-  Philox4 o; o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3; return o;
-}
-
-enum Purpose : uint32_t { kPurposeModes = 0, kPurposeDist = 1, kPurposeSnl = 2, kPurposeAccept = 3, kPurposeJitter = 4 };
-
-__device__ __forceinline__ Philox4 draw_words(uint64_t seed, uint32_t iteration, uint32_t purpose, uint64_t index) {
-  return philox4x32_10((uint32_t)index, (uint32_t)(index >> 32), iteration, purpose,
-                       (uint32_t)seed, (uint32_t)(seed >> 32));
-}
-
-// ((x >> 11) + 1) 2^-53 in (0, 1], x = (hi << 32) | lo.
-__device__ __forceinline__ double uniform53(uint32_t lo, uint32_t hi) {
-  const uint64_t x = ((uint64_t)hi << 32) | lo;
-  return ((double)(x >> 11) + 1.0) * 0x1.0p-53;
-}
-
-// Box-Muller on the two uniforms of one Philox output.
-__device__ __forceinline__ double2 normal_pair(const Philox4& w) {
-  const double u1 = uniform53(w.v[0], w.v[1]);
-  const double u2 = uniform53(w.v[2], w.v[3]);
-  const double rad = sqrt(-2.0 * log(u1));
-  const double ang = 2.0 * M_PI * u2;
-  double sn, cs;
-  sincos(ang, &sn, &cs);
-  return make_double2(rad * cs, rad * sn);
-}
 
 // Mode coordinates of flat index g of the [kx][ky][kz < N/2] layout.
 struct ModeIdx { int x, y, kz, sx, sy; };
@@ -73,12 +30,6 @@ __device__ __forceinline__ ModeIdx mode_idx(size_t g, int n) {
   return m;
 }
 
-// kz = 0 entries whose canonical Hermitian partner is (-kx, -ky, 0):
-// canonical half = ny > 0, or ny = 0 and nx > 0.
-__device__ __forceinline__ bool is_mirror(const ModeIdx& m) {
-  return m.kz == 0 && (m.sy < 0 || (m.sy == 0 && m.sx < 0));
-}
-
 // sigma_k^2 per mode from the n^2-indexed table (plan set-up only).
 __global__ void __launch_bounds__(kEltThreads)
 k_fill_mode_var(double* __restrict__ mvar, const double* __restrict__ var_n2, int n) {
@@ -89,31 +40,8 @@ k_fill_mode_var(double* __restrict__ mvar, const double* __restrict__ var_n2, in
   mvar[g] = retained(m.sx, m.sy, m.kz, n) ? var_n2[m.sx * m.sx + m.sy * m.sy + m.kz * m.kz] : 0.0;
 }
 
-// ---------------------------------------------------------------------------
-// Chain scalars kept on the device so a whole run is enqueued without a
-// host round trip.  Each chain has its own seed and iteration counter, so a
-// chain draws the same numbers whichever other chains share its launches.
-// ---------------------------------------------------------------------------
-struct ChainScalars {
-  double eps;          // step size of the chain (adapted during warm-up)
-  double eps_it;       // step of the current iteration (jittered)
-  double da_mu, da_hbar, da_log_eps_bar, da_m;
-  double psi, gs;              // Psi and dPsi/ds at the current state
-  double psi_saved, gs_saved;  // at the start of the trajectory
-  double kin0, kin1;
-  double target;
-  uint64_t seed;
-  int iter;            // iterations done by this chain
-  int warmup;          // adaptation iterations
-  int jitter;          // jitter the step by U(0.9, 1.1)
-  int accept;          // last iteration accepted
-  int post;            // last iteration was past warm-up
-};
-static_assert(sizeof(ChainScalars) <= FixedLayout<16, 8>::chain_bytes, "chain scalars block");
 
-template <typename T, int N> __device__ __forceinline__ ChainScalars* chain(const Ws<T, N>& w) {
-  return w.template at<ChainScalars>(Ws<T, N>::F::chain);
-}
+template <typename T, int N> __device__ __forceinline__ ChainScalars* chain(const Ws<T, N>& w) { return w.chain(); }
 
 __global__ void k_set_scalar(double* dst, double v) {
   if (threadIdx.x == 0) dst[0] = v;
@@ -133,32 +61,6 @@ __global__ void k_chain_init(ChainScalars* cs, double eps0, double target, uint6
   cs->jitter = jitter;
   cs->accept = 0;
   cs->post = 0;
-}
-
-// ---------------------------------------------------------------------------
-// Momentum refresh p ~ N(0, M).
-// ---------------------------------------------------------------------------
-template <typename T, int N>
-__global__ void __launch_bounds__(kEltThreads) k_momenta_modes(Launch L) {
-  const Pick<T, N> k(L);
-  if (k.mode == kXSkip) return;
-  const size_t total = (size_t)N * N * (N / 2);
-  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const ChainScalars* cs = chain(k.w);
-  const uint64_t seed = cs->seed;
-  const uint32_t iteration = (uint32_t)cs->iter;
-  const ModeIdx m = mode_idx(g, N);
-  double2 out = make_double2(0.0, 0.0);
-  if (retained(m.sx, m.sy, m.kz, N)) {
-    const bool mir = is_mirror(m);
-    size_t src = g;
-    if (mir) src = ((size_t)((N - m.x) & (N - 1)) * N + ((N - m.y) & (N - 1))) * (N / 2);
-    const double2 z = normal_pair(draw_words(seed, iteration, kPurposeModes, src));
-    const double sc = sqrt(2.0 * inv_or_zero(ld_stream(&k.w.mvar()[g])));
-    out = make_double2(sc * z.x, mir ? -sc * z.y : sc * z.y);
-  }
-  k.w.pm()[g] = out;
 }
 
 // ---------------------------------------------------------------------------

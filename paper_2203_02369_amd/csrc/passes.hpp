@@ -27,6 +27,7 @@
 
 #include "common.hpp"
 #include "fft.hpp"
+#include "random.hpp"
 #include "workspace.hpp"
 
 namespace hamlet {
@@ -558,13 +559,17 @@ fwd_y_body(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, c
   tile_elems<T, N, NT>([&](int, int y, int w) { s2[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
 }
 
-// Where a pass that starts or ends a trajectory leaves its by-products: the
-// saved start point (modes, cached gradient) and the kinetic-energy partial
-// of each block (one per x-pass block, in block order).
+// What a pass that starts or ends a trajectory needs besides the state: the
+// chain's key and iteration (the first pass of a chain's trajectory draws
+// the momenta), where the start point is kept (modes, cached gradient), and
+// the kinetic-energy partial of each block (one per x-pass block, in block
+// order).
 struct ChainSave {
   double2* q0;
   double2* g0;
   double* kin_part;
+  uint64_t seed;
+  uint32_t iteration;
 };
 
 // ---------------------------------------------------------------------------
@@ -656,7 +661,22 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
       st_stream(&save.g0[g], G);
     }
     if constexpr (MODE != kXGrad) {
-      double2 p = ld_stream(&mom[g]);
+      double2 p = make_double2(0.0, 0.0);
+      if constexpr (kStartOfChain) {
+        // momentum refresh p ~ N(0, M): Re and Im of a retained mode each
+        // with variance 2 / sigma_k^2; an entry of the kz = 0 plane whose
+        // Hermitian partner (-kx, -ky, 0) is canonical (ny > 0, or ny = 0 and
+        // nx > 0) takes the conjugate of the partner's draw
+        if (keep) {
+          const bool mirror = kz == 0 && (sy < 0 || (sy == 0 && sx < 0));
+          const size_t src = mirror ? gofs<N>((N - x) & (N - 1), (N - y) & (N - 1), 0) : g;
+          const double2 z = normal_pair(draw_words(save.seed, save.iteration, kPurposeModes, src));
+          const double sc = sqrt(2.0 * inv_or_zero(var));
+          p = make_double2(sc * z.x, mirror ? -sc * z.y : sc * z.y);
+        }
+      } else {
+        p = ld_stream(&mom[g]);
+      }
       // per stored mode (w / 8) sigma^2 |p|^2, w = 1 on kz = 0 (both
       // Hermitian partners stored), else 2
       const double wk = kz == 0 ? 0.125 : 0.25;
@@ -763,13 +783,18 @@ __global__ void __launch_bounds__(NT) k_fwd_y(Launch L, int x0) {
 }
 
 // One launch per mode present in a batch; plans in another mode return.
-// CHAIN: the first step of a chain's trajectory, which also keeps the start
-// point and sums K0.
+// CHAIN: the first step of a chain's trajectory, which also draws the
+// momenta, keeps the start point and sums K0.
 template <typename T, int N, int MODE, int NT, bool CHAIN = false>
 __global__ void __launch_bounds__(NT) k_x_pass(Launch L, double plane_scale) {
   const Pick<T, N> k(L);
   if (k.mode != MODE) return;
-  const ChainSave save{k.w.q0(), k.w.g0(), k.w.kin_part()};
+  ChainSave save{k.w.q0(), k.w.g0(), k.w.kin_part(), 0, 0};
+  if constexpr (CHAIN) {
+    const ChainScalars* cs = k.w.chain();
+    save.seed = cs->seed;
+    save.iteration = (uint32_t)cs->iter;
+  }
   x_pass_body<T, N, MODE, NT, CHAIN>(k.w.a(), k.w.b(), k.st.q, k.st.p, k.st.g, tables(k.w), k.w.tw(), k.st.eps,
                                      k.w.a(), k.w.b(), k.w.prior_part(), plane_scale, save);
 }

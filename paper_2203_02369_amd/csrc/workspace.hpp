@@ -128,6 +128,28 @@ template <int N, int R> __host__ __device__ inline size_t workspace_bytes(int n_
   return align256(hist_offset<N, R>(n_gal) + 8 * size_t(n_hist > 0 ? n_hist : 1));
 }
 
+// ---------------------------------------------------------------------------
+// Chain scalars kept on the device so a whole run is enqueued without a
+// host round trip.  Each chain has its own seed and iteration counter, so a
+// chain draws the same numbers whichever other chains share its launches.
+// ---------------------------------------------------------------------------
+struct ChainScalars {
+  double eps;          // step size of the chain (adapted during warm-up)
+  double eps_it;       // step of the current iteration (jittered)
+  double da_mu, da_hbar, da_log_eps_bar, da_m;
+  double psi, gs;              // Psi and dPsi/ds at the current state
+  double psi_saved, gs_saved;  // at the start of the trajectory
+  double kin0, kin1;
+  double target;
+  uint64_t seed;
+  int iter;            // iterations done by this chain
+  int warmup;          // adaptation iterations
+  int jitter;          // jitter the step by U(0.9, 1.1)
+  int accept;          // last iteration accepted
+  int post;            // last iteration was past warm-up
+};
+static_assert(sizeof(ChainScalars) <= FixedLayout<16, 8>::chain_bytes, "chain scalars block");
+
 // Typed view of a plan's workspace.
 template <typename T, int N> struct Ws {
   using C = cplx_t<T>;
@@ -139,6 +161,7 @@ template <typename T, int N> struct Ws {
   template <typename X> __host__ __device__ X* at(size_t o) const { return reinterpret_cast<X*>(base + o); }
   template <typename X> __host__ __device__ X* gal(size_t u) const { return at<X>(F::end + u * unit); }
   __host__ __device__ const PlanConst& pc() const { return *at<const PlanConst>(F::consts); }
+  __host__ __device__ ChainScalars* chain() const { return at<ChainScalars>(F::chain); }
   __host__ __device__ double* var_n2() const { return at<double>(F::var_n2); }
   __host__ __device__ C* tw() const { return at<C>(F::tw); }
   __host__ __device__ int* count() const { return at<int>(F::count); }
