@@ -103,6 +103,50 @@ __device__ __forceinline__ void tile_elems(Fn&& fn) {
 }
 template <typename T, int N, int NT> constexpr int elems_per_thread() { return (PassShape<T, N>::ELEMS + NT - 1) / NT; }
 
+// K consecutive columns of a strided tile moved as one 16-byte access (K = 2
+// for 8-byte complex elements, 1 for 16-byte ones).
+template <typename T> struct ColVec {
+  using C = cplx_t<T>;
+  static constexpr int K = sizeof(C) == 8 ? 2 : 1;
+  struct alignas(16) V { C v[K]; };
+};
+
+// Visit this thread's groups of K columns (w a multiple of K).
+template <typename T, int N, int NT, typename Fn>
+__device__ __forceinline__ void tile_vecs(Fn&& fn) {
+  using S = PassShape<T, N>;
+  constexpr int K = ColVec<T>::K, WK = S::W / K, NV = S::ELEMS / K;
+  constexpr int VPT = (NV + NT - 1) / NT;
+#pragma unroll
+  for (int e = 0; e < VPT; ++e) {
+    const int idx = threadIdx.x + e * NT;
+    if (NV % NT == 0 || idx < NV) fn(e, idx / WK, K * (idx % WK));
+  }
+}
+template <typename T, int N, int NT> constexpr int vecs_per_thread() {
+  return (PassShape<T, N>::ELEMS / ColVec<T>::K + NT - 1) / NT;
+}
+
+// Global <-> LDS moves of one group of K columns of row a.
+template <typename T, typename LAY>
+__device__ __forceinline__ void vec_to_lds(cplx_t<T>* tile, int a, int w, const typename ColVec<T>::V& v) {
+#pragma unroll
+  for (int j = 0; j < ColVec<T>::K; ++j) tile[LAY::idx(a, w + j)] = v.v[j];
+}
+template <typename T, typename LAY>
+__device__ __forceinline__ typename ColVec<T>::V vec_from_lds(const cplx_t<T>* tile, int a, int w) {
+  typename ColVec<T>::V v;
+#pragma unroll
+  for (int j = 0; j < ColVec<T>::K; ++j) v.v[j] = tile[LAY::idx(a, w + j)];
+  return v;
+}
+template <typename T> __device__ __forceinline__ typename ColVec<T>::V vec_load(const cplx_t<T>* p) {
+  return ld_stream(reinterpret_cast<const typename ColVec<T>::V*>(p));
+}
+template <typename T> __device__ __forceinline__ void vec_store(cplx_t<T>* p, const typename ColVec<T>::V& v) {
+  *reinterpret_cast<typename ColVec<T>::V*>(p) = v;
+}
+
 // Global offset of (i, j, kz) in an [N][N][N/2] array.
 template <int N> __device__ __forceinline__ size_t gofs(int i, int j, int kz) {
   return ((size_t)i * N + j) * (N / 2) + kz;
@@ -165,29 +209,32 @@ inv_y_body(const cplx_t<T>* __restrict__ inA, const cplx_t<T>* __restrict__ inB,
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Row;
+  using CV = ColVec<T>;
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
   load_twiddles<T, N, NT>(twl, tw);
   const int x = x0 + blockIdx.y, z0 = blockIdx.x * S::W;
-  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = ld_stream(&inB[gofs<N>(x, y, z0 + w)]); });
+  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, vec_load<T>(&inB[gofs<N>(x, y, z0 + w)])); });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
-  tile_elems<T, N, NT>([&](int, int y, int w) { vx[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
+  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_store<T>(&vx[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, y, w)); });
   __syncthreads();
   // A is read once and kept in registers for its second transform
-  C ra[elems_per_thread<T, N, NT>()];
-  tile_elems<T, N, NT>([&](int e, int y, int w) {
-    ra[e] = ld_stream(&inA[gofs<N>(x, y, z0 + w)]);
-    tile[LAY::idx(y, w)] = cscale(ra[e], (T)signed_freq(y, N));
+  typename CV::V ra[vecs_per_thread<T, N, NT>()];
+  tile_vecs<T, N, NT>([&](int e, int y, int w) {
+    ra[e] = vec_load<T>(&inA[gofs<N>(x, y, z0 + w)]);
+    const T ny = (T)signed_freq(y, N);
+#pragma unroll
+    for (int j = 0; j < CV::K; ++j) tile[LAY::idx(y, w + j)] = cscale(ra[e].v[j], ny);
   });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
-  tile_elems<T, N, NT>([&](int, int y, int w) { vy[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
+  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_store<T>(&vy[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, y, w)); });
   __syncthreads();
-  tile_elems<T, N, NT>([&](int e, int y, int w) { tile[LAY::idx(y, w)] = ra[e]; });
+  tile_vecs<T, N, NT>([&](int e, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, ra[e]); });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
-  tile_elems<T, N, NT>([&](int, int y, int w) { vz[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
+  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_store<T>(&vz[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, y, w)); });
 }
 
 // Galaxies binned by CIC column (ix, iy) of their lower corner, in sorted
@@ -247,25 +294,54 @@ inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict_
   load_twiddles<T, N, NT>(twl, tw);
   // Build Z = A + i B with A, B the Hermitian half spectra of the two real
   // pencils of each transform (Nyquist entry zero, DC entries real).
-  for (int idx = threadIdx.x; idx < F * H; idx += NT) {
-    const int k = idx % H, f = idx / H;
-    const int m = f / 3, r = f % 3;
-    C av, bv;
-    if (r == 1) {
-      const size_t g0 = gofs<N>(x, y0 + 2 * m, k);
-      av = cscale(ld_stream(&vz[g0]), (T)k);
-      bv = cscale(ld_stream(&vz[g0 + H]), (T)k);
-    } else {
-      const size_t g = gofs<N>(x, y0 + 2 * m + (r == 2 ? 1 : 0), k);
-      av = ld_stream(&vx[g]);
-      bv = ld_stream(&vy[g]);
-    }
+  auto put = [&](int k, int f, C av, C bv) {
     if (k == 0) {
       buf[LAY::idx(0, f)] = cmake<C>(av.x, bv.x);
       buf[LAY::idx(H, f)] = cmake<C>((T)0, (T)0);
     } else {
       buf[LAY::idx(k, f)] = cmake<C>(av.x - bv.y, av.y + bv.x);          // A + i B
       buf[LAY::idx(N - k, f)] = cmake<C>(av.x + bv.y, bv.x - av.y);      // conj(A) + i conj(B)
+    }
+  };
+  if constexpr (sizeof(C) == 8) {
+    // FP32: two consecutive kz per thread, 16-byte loads
+    struct C2 { C a, b; };
+    constexpr int H2 = H / 2;
+    for (int idx = threadIdx.x; idx < F * H2; idx += NT) {
+      const int k = 2 * (idx % H2), f = idx / H2;
+      const int m = f / 3, r = f % 3;
+      C2 av, bv;
+      if (r == 1) {
+        const size_t g0 = gofs<N>(x, y0 + 2 * m, k);
+        av = ld_stream(reinterpret_cast<const C2*>(&vz[g0]));
+        bv = ld_stream(reinterpret_cast<const C2*>(&vz[g0 + H]));
+        av.a = cscale(av.a, (T)k);
+        av.b = cscale(av.b, (T)(k + 1));
+        bv.a = cscale(bv.a, (T)k);
+        bv.b = cscale(bv.b, (T)(k + 1));
+      } else {
+        const size_t g = gofs<N>(x, y0 + 2 * m + (r == 2 ? 1 : 0), k);
+        av = ld_stream(reinterpret_cast<const C2*>(&vx[g]));
+        bv = ld_stream(reinterpret_cast<const C2*>(&vy[g]));
+      }
+      put(k, f, av.a, bv.a);
+      put(k + 1, f, av.b, bv.b);
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < F * H; idx += NT) {
+      const int k = idx % H, f = idx / H;
+      const int m = f / 3, r = f % 3;
+      C av, bv;
+      if (r == 1) {
+        const size_t g0 = gofs<N>(x, y0 + 2 * m, k);
+        av = cscale(ld_stream(&vz[g0]), (T)k);
+        bv = cscale(ld_stream(&vz[g0 + H]), (T)k);
+      } else {
+        const size_t g = gofs<N>(x, y0 + 2 * m + (r == 2 ? 1 : 0), k);
+        av = ld_stream(&vx[g]);
+        bv = ld_stream(&vy[g]);
+      }
+      put(k, f, av, bv);
     }
   }
   __syncthreads();
@@ -427,10 +503,19 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
     // w = exp(-2 pi i / N), over the pencil's stencil columns (corner by
     // corner, binned order); the bracket is shared by the three components.
     __syncthreads();
-    for (int idx = threadIdx.x; idx < P * H; idx += NT) {
-      const int k = idx % H, p = idx / H;
-      const C wk = twl[k];
-      T ax = 0, ay = 0, bx = 0, by = 0, cx = 0, cy = 0;
+    // two consecutive kz per thread (16-byte stores in FP32)
+    constexpr int KT = sizeof(C) == 8 ? 2 : 1;
+    constexpr int HK = H / KT;
+    struct alignas(16) CK { C v[KT]; };
+    for (int idx = threadIdx.x; idx < P * HK; idx += NT) {
+      const int k0 = KT * (idx % HK), p = idx / HK;
+      C wk[KT];
+      T ax[KT], ay[KT], bx[KT], by[KT], cx[KT], cy[KT];
+#pragma unroll
+      for (int j = 0; j < KT; ++j) {
+        wk[j] = twl[k0 + j];
+        ax[j] = ay[j] = bx[j] = by[j] = cx[j] = cy[j] = (T)0;
+      }
       for (int corner = 0; corner < 4; ++corner) {
         const int s0 = col[4 * p + corner][0], s1 = col[4 * p + corner][1];
         const int ox = corner >> 1, oy = corner & 1;
@@ -439,22 +524,33 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
         for (int i = lo; i < lo + (s1 - s0); ++i) {
           const T tx = stg.tx[i], ty = stg.ty[i], tz = stg.tz[i];
           const T v = stg.g[i] * ((ox ? tx : (T)1 - tx) * (oy ? ty : (T)1 - ty));
-          const C w0 = twl[((int)stg.iz[i] * k) & (N - 1)];
-          const T ux = ((T)1 - tz) + tz * wk.x, uy = tz * wk.y;
-          const T wx = w0.x * ux - w0.y * uy, wy = w0.x * uy + w0.y * ux;
           const T vx = v * stg.r[0][i], vy = v * stg.r[1][i], vz = v * stg.r[2][i];
-          ax += vx * wx;
-          ay += vx * wy;
-          bx += vy * wx;
-          by += vy * wy;
-          cx += vz * wx;
-          cy += vz * wy;
+          const int iz = stg.iz[i];
+#pragma unroll
+          for (int j = 0; j < KT; ++j) {
+            const C w0 = twl[(iz * (k0 + j)) & (N - 1)];
+            const T ux = ((T)1 - tz) + tz * wk[j].x, uy = tz * wk[j].y;
+            const T wx = w0.x * ux - w0.y * uy, wy = w0.x * uy + w0.y * ux;
+            ax[j] += vx * wx;
+            ay[j] += vx * wy;
+            bx[j] += vy * wx;
+            by[j] += vy * wy;
+            cx[j] += vz * wx;
+            cy[j] += vz * wy;
+          }
         }
       }
-      const size_t g = gofs<N>(x, y0 + p, k);
-      gx[g] = cmake<C>(ax, ay);
-      gy[g] = cmake<C>(bx, by);
-      gz[g] = cmake<C>((T)k * cx, (T)k * cy);
+      const size_t g = gofs<N>(x, y0 + p, k0);
+      CK ox_, oy_, oz_;
+#pragma unroll
+      for (int j = 0; j < KT; ++j) {
+        ox_.v[j] = cmake<C>(ax[j], ay[j]);
+        oy_.v[j] = cmake<C>(bx[j], by[j]);
+        oz_.v[j] = cmake<C>((T)(k0 + j) * cx[j], (T)(k0 + j) * cy[j]);
+      }
+      *reinterpret_cast<CK*>(&gx[g]) = ox_;
+      *reinterpret_cast<CK*>(&gy[g]) = oy_;
+      *reinterpret_cast<CK*>(&gz[g]) = oz_;
     }
     return;
   }
@@ -535,28 +631,35 @@ fwd_y_body(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, c
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Row;
-  constexpr int EPT = elems_per_thread<T, N, NT>();
+  using CV = ColVec<T>;
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
   load_twiddles<T, N, NT>(twl, tw);
   const int x = x0 + blockIdx.y, z0 = blockIdx.x * S::W;
-  C acc[EPT];
-  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = ld_stream(&gy[gofs<N>(x, y, z0 + w)]); });
+  typename CV::V acc[vecs_per_thread<T, N, NT>()];
+  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, vec_load<T>(&gy[gofs<N>(x, y, z0 + w)])); });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
-  tile_elems<T, N, NT>([&](int e, int y, int w) { acc[e] = cscale(tile[LAY::idx(y, w)], (T)signed_freq(y, N)); });
-  __syncthreads();
-  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = ld_stream(&gz[gofs<N>(x, y, z0 + w)]); });
-  __syncthreads();
-  lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
-  tile_elems<T, N, NT>([&](int e, int y, int w) {
-    s1[gofs<N>(x, y, z0 + w)] = cadd(acc[e], tile[LAY::idx(y, w)]);
+  tile_vecs<T, N, NT>([&](int e, int y, int w) {
+    const T ny = (T)signed_freq(y, N);
+#pragma unroll
+    for (int j = 0; j < CV::K; ++j) acc[e].v[j] = cscale(tile[LAY::idx(y, w + j)], ny);
   });
   __syncthreads();
-  tile_elems<T, N, NT>([&](int, int y, int w) { tile[LAY::idx(y, w)] = ld_stream(&gx[gofs<N>(x, y, z0 + w)]); });
+  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, vec_load<T>(&gz[gofs<N>(x, y, z0 + w)])); });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
-  tile_elems<T, N, NT>([&](int, int y, int w) { s2[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(y, w)]; });
+  tile_vecs<T, N, NT>([&](int e, int y, int w) {
+    typename CV::V o;
+#pragma unroll
+    for (int j = 0; j < CV::K; ++j) o.v[j] = cadd(acc[e].v[j], tile[LAY::idx(y, w + j)]);
+    vec_store<T>(&s1[gofs<N>(x, y, z0 + w)], o);
+  });
+  __syncthreads();
+  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, vec_load<T>(&gx[gofs<N>(x, y, z0 + w)])); });
+  __syncthreads();
+  lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
+  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_store<T>(&s2[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, y, w)); });
 }
 
 // What a pass that starts or ends a trajectory needs besides the state: the
@@ -612,12 +715,12 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
   const int sy = signed_freq(y, N);
   C acc[elems_per_thread<T, N, NT>()];
   if constexpr (kFromSpectra) {
-    tile_elems<T, N, NT>([&](int, int x, int w) { tile[LAY::idx(x, w)] = ld_stream(&s2[gofs<N>(x, y, z0 + w)]); });
+    tile_vecs<T, N, NT>([&](int, int x, int w) { vec_to_lds<T, LAY>(tile, x, w, vec_load<T>(&s2[gofs<N>(x, y, z0 + w)])); });
     __syncthreads();
     lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
     tile_elems<T, N, NT>([&](int e, int x, int w) { acc[e] = cscale(tile[LAY::idx(x, w)], (T)signed_freq(x, N)); });
     __syncthreads();
-    tile_elems<T, N, NT>([&](int, int x, int w) { tile[LAY::idx(x, w)] = ld_stream(&s1[gofs<N>(x, y, z0 + w)]); });
+    tile_vecs<T, N, NT>([&](int, int x, int w) { vec_to_lds<T, LAY>(tile, x, w, vec_load<T>(&s1[gofs<N>(x, y, z0 + w)])); });
     __syncthreads();
     lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
   } else {
@@ -714,12 +817,12 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
     tile_elems<T, N, NT>([&](int e, int x, int w) { tile[LAY::idx(x, w)] = acc[e]; });
     __syncthreads();
     lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
-    tile_elems<T, N, NT>([&](int, int x, int w) { outA[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
+    tile_vecs<T, N, NT>([&](int, int x, int w) { vec_store<T>(&outA[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, x, w)); });
     __syncthreads();
     tile_elems<T, N, NT>([&](int e, int x, int w) { tile[LAY::idx(x, w)] = bin[e]; });
     __syncthreads();
     lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
-    tile_elems<T, N, NT>([&](int, int x, int w) { outB[gofs<N>(x, y, z0 + w)] = tile[LAY::idx(x, w)]; });
+    tile_vecs<T, N, NT>([&](int, int x, int w) { vec_store<T>(&outB[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, x, w)); });
   } else {
     (void)outA;
     (void)outB;
