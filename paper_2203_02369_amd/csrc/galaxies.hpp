@@ -189,7 +189,7 @@ bin_place_body(const int* __restrict__ key, int* __restrict__ cursor, int* __res
 template <typename T>
 __device__ __forceinline__ void
 bin_rank_body(const int* __restrict__ off, const int* __restrict__ key, const int* __restrict__ placed,
-              const int* __restrict__ cell_z, const double* __restrict__ frac, Catalogue cat, int* __restrict__ gid,
+              const int* __restrict__ cell_z, const double* __restrict__ frac, Catalogue cat, int* __restrict__ bpos,
               T* __restrict__ rx, T* __restrict__ ry, T* __restrict__ rz, T* __restrict__ tx, T* __restrict__ ty,
               T* __restrict__ tz, int* __restrict__ iz) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -203,7 +203,7 @@ bin_rank_body(const int* __restrict__ off, const int* __restrict__ key, const in
     rank += (zj < z || (zj == z && j < i)) ? 1 : 0;
   }
   const int pos = s0 + rank;
-  gid[pos] = i;
+  bpos[i] = pos;
   rx[pos] = (T)cat.rhat[3 * i + 0];
   ry[pos] = (T)cat.rhat[3 * i + 1];
   rz[pos] = (T)cat.rhat[3 * i + 2];
@@ -215,7 +215,10 @@ bin_rank_body(const int* __restrict__ off, const int* __restrict__ key, const in
 
 // ---------------------------------------------------------------------------
 // Likelihood (eqn:lmu, eq:vrobs, eqn:lvr, eq:kappa, eq:D) per galaxy, in
-// sorted order.  Combines the four column partials of the gather into
+// galaxy order (so the per-galaxy arrays are read coalesced and the block
+// partials do not depend on the binning); the gather's partials and the
+// scatter's input sit at the galaxy's binned index.  Combines the four
+// column partials of the gather into
 //   u  = sum_col wx wy Pc
 //   u' = sum_col (dwx wy rx + wx dwy ry) Pc + wx wy rz Qc / Delta,
 // then, in FP64,
@@ -241,14 +244,14 @@ struct LikeOut {
 
 template <typename T>
 __device__ __forceinline__ void
-like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ gid, const double* __restrict__ frac,
+like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, const double* __restrict__ frac,
           double* __restrict__ dist, const double* snl_q, Catalogue cat, Cosmo cm, T* __restrict__ gsort,
           LikeOut out, LeapUpdate lf, const BinNext* next) {
   __shared__ double red[kGalThreads / 64];
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double psi = 0.0, dps = 0.0, bad = 0.0;
-  if (s < cat.n) {
-    const int i = gid[s];
+  if (i < cat.n) {
+    const int s = bpos[i];
     const double tx = frac[3 * i], ty = frac[3 * i + 1];
     const double rx = cat.rhat[3 * i], ry = cat.rhat[3 * i + 1], rz = cat.rhat[3 * i + 2];
     const double inv_d = 1.0 / cm.spacing;
@@ -449,7 +452,7 @@ template <typename T, int N>
 __global__ void __launch_bounds__(kGalThreads) k_bin_rank(Launch L) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
-  bin_rank_body<T>(k.w.off(), k.w.key(), k.w.slot(), k.w.cellz(), k.w.frac(), catalogue(k.w, k.n_gal), k.w.gid(),
+  bin_rank_body<T>(k.w.off(), k.w.key(), k.w.slot(), k.w.cellz(), k.w.frac(), catalogue(k.w, k.n_gal), k.w.bpos(),
                    k.w.rx(), k.w.ry(), k.w.rz(), k.w.tx(), k.w.ty(), k.w.tz(), k.w.iz());
 }
 
@@ -480,7 +483,7 @@ __global__ void __launch_bounds__(kGalThreads) k_like(Launch L) {
   lo.n_prior = pc.n_prior_part;
   lo.n_blocks = pc.n_like_part;
   const BinNext next{bin_out(k.w), N};
-  like_body<T>(k.w.part(), k.w.gid(), k.w.frac(), k.st.qd, k.st.qs, catalogue(k.w, k.n_gal), cosmo(k.w),
+  like_body<T>(k.w.part(), k.w.bpos(), k.w.frac(), k.st.qd, k.st.qs, catalogue(k.w, k.n_gal), cosmo(k.w),
                k.w.gsort(), lo, leap_update(k.mode, pc.sample_d, k.st.pd, k.st.eps, pc.minv_d),
                k.mode == kXMid ? &next : nullptr);
   // The plan's last block to finish completes the evaluation: it sums every

@@ -112,7 +112,7 @@ template <int R> struct GalaxyUnits {
   static constexpr size_t like_part = 14;  // 3 doubles per block of 256 galaxies
   static constexpr size_t key = 15, cellz = 16, slot = 17, iz = 18;   // ints
   static constexpr size_t rx = 19, ry = 20, rz = 21, tx = 22, ty = 23, tz = 24, gsort = 25;   // reals
-  static constexpr size_t gid = 26;        // galaxy id in binned order
+  static constexpr size_t bpos = 26;       // binned index of each galaxy
   static constexpr size_t dz = 27;         // redshift distance of each galaxy
   static constexpr size_t part = 28;       // 4 complex reals per galaxy
   static constexpr size_t count = part + (R == 4 ? 4 : 8);
@@ -200,7 +200,7 @@ template <typename T, int N> struct Ws {
   __host__ __device__ int* key() const { return gal<int>(G::key); }
   __host__ __device__ int* cellz() const { return gal<int>(G::cellz); }
   __host__ __device__ int* slot() const { return gal<int>(G::slot); }
-  __host__ __device__ int* gid() const { return gal<int>(G::gid); }
+  __host__ __device__ int* bpos() const { return gal<int>(G::bpos); }
   __host__ __device__ double* dz() const { return gal<double>(G::dz); }
   __host__ __device__ int* iz() const { return gal<int>(G::iz); }
   __host__ __device__ T* rx() const { return gal<T>(G::rx); }
