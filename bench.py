@@ -48,9 +48,9 @@ HBM_PEAK_GBS = 8000.0
 # (--copy-calibration: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  Bytes read and
 # written per launch for the plain-gradient, first, middle and last variants.
 # Valid only for the kernel sources they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "297dc74ba2fc7cf8d37c2f88ac3e337417507017"
-X_TRAFFIC = {"grad": (334167781, 134217856), "first": (468408004, 401693867),
-             "mid": (468537360, 401674337), "last": (468379077, 268437504)}
+X_TRAFFIC_SOURCES_SHA1 = "56bd36b7f44c2803d396e7ae0f29e01f23e3c196"
+X_TRAFFIC = {"grad": (334153181, 134217920), "first": (335656996, 670191701),
+             "mid": (468530995, 401675000), "last": (468399724, 268502912)}
 
 
 def kernel_sources_sha1():
