@@ -453,7 +453,9 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
   }
   hipStream_t st = pl->stream;
   HIP_TRY(hipMemcpyAsync(pl->var, var.data(), npk * 8, hipMemcpyHostToDevice, st));
-  k_fill_mode_var<<<blocks_for(pl->modes_count(), kEltThreads), kEltThreads, 0, st>>>(pl->mvar, pl->var, n);
+  // tile width of the x pass: 16 (FP32) or 8 (FP64) kz columns, at most N/2
+  const int wmax = pl->prec == HAMLET_FP64 ? 8 : 16, w = std::min(wmax, n / 2);
+  k_fill_mode_var<<<blocks_for(pl->modes_count(), kEltThreads), kEltThreads, 0, st>>>(pl->mvar, pl->var, n, w);
   LAUNCH_CHECK();
   if (pl->prec == HAMLET_FP64)
     HIP_TRY(hipMemcpyAsync(pl->tw, twd.data(), twd.size() * 8, hipMemcpyHostToDevice, st));

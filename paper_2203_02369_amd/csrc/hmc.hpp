@@ -30,14 +30,16 @@ __device__ __forceinline__ ModeIdx mode_idx(size_t g, int n) {
   return m;
 }
 
-// sigma_k^2 per mode from the n^2-indexed table (plan set-up only).
+// sigma_k^2 per mode from the n^2-indexed table (plan set-up only), in the
+// x-pass tile order (var_ofs, tile width w).
 __global__ void __launch_bounds__(kEltThreads)
-k_fill_mode_var(double* __restrict__ mvar, const double* __restrict__ var_n2, int n) {
+k_fill_mode_var(double* __restrict__ mvar, const double* __restrict__ var_n2, int n, int w) {
   const size_t total = (size_t)n * n * (n / 2);
   const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const ModeIdx m = mode_idx(g, n);
-  mvar[g] = retained(m.sx, m.sy, m.kz, n) ? var_n2[m.sx * m.sx + m.sy * m.sy + m.kz * m.kz] : 0.0;
+  mvar[var_ofs(n, w, m.x, m.y, m.kz)] =
+      retained(m.sx, m.sy, m.kz, n) ? var_n2[m.sx * m.sx + m.sy * m.sy + m.kz * m.kz] : 0.0;
 }
 
 

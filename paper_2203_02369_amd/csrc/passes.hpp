@@ -63,15 +63,16 @@ template <typename T, int N> struct PassShape {
   using Pen = PencilLayout<N>;
 };
 
-// Per-mode constants.  sigma_k^2 = N^6 P(|k|) / V is stored per mode in the
-// mode layout (0 on excluded modes), so every pass reads it coalesced
-// instead of gathering from a table indexed by n^2; the multiplier factor
+// Per-mode constants.  sigma_k^2 = N^6 P(|k|) / V is stored per mode in
+// FP64 (0 on excluded modes), so every pass reads it coalesced instead of
+// gathering from a table indexed by n^2, in the order of the x-pass tiles
+// (see var_ofs): a tile's values are contiguous.  The multiplier factor
 // kfac = H0 f / (N^3 k_f n^2) is computed from n^2.
 struct ModeTables {
-  const double* var;       // sigma_k^2 per mode, [kx][ky][kz < N/2]
+  const double* var;       // sigma_k^2 per mode, [ky][kz / W][kx][kz % W]
   double kfac0;            // H0 f / (N^3 k_f)
 };
-__device__ __forceinline__ double mode_kfac(const ModeTables& t, int n2) { return n2 > 0 ? t.kfac0 / (double)n2 : 0.0; }
+__device__ __forceinline__ double mode_kfac(double kfac0, int n2) { return n2 > 0 ? kfac0 / (double)n2 : 0.0; }
 __device__ __forceinline__ double inv_or_zero(double v) { return v > 0.0 ? 1.0 / v : 0.0; }
 
 // Deterministic block sum of a double (wave64 shuffles, then LDS).
@@ -152,6 +153,14 @@ template <int N> __device__ __forceinline__ size_t gofs(int i, int j, int kz) {
   return ((size_t)i * N + j) * (N / 2) + kz;
 }
 
+// Offset of mode (kx, ky, kz) in the per-mode sigma_k^2 array, laid out as
+// the x-pass tiles [ky][kz / W][kx][kz % W]: element e of a tile is at
+// tile * N W + e, so a wave reads whole cache lines (a row of W values
+// alone is half a line in the FP64 path, whose tiles are 8 columns wide).
+__host__ __device__ inline size_t var_ofs(int n, int w, int kx, int ky, int kz) {
+  return (((size_t)ky * (n / 2 / w) + kz / w) * n + kx) * w + kz % w;
+}
+
 // ---------------------------------------------------------------------------
 // Inverse pass 1 (along x): multiplier, prior energy, two spectral outputs.
 // Tile: fixed ky, kz chunk, all kx.
@@ -175,7 +184,7 @@ inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* _
     const int kz = z0 + w, sx = signed_freq(x, N);
     if (!retained(sx, sy, kz, N)) return make_double2(0.0, 0.0);
     const double2 q = modes[gofs<N>(x, y, kz)];
-    const double kf = mode_kfac(tab, sx * sx + sy * sy + kz * kz) * (scale_x != 0.0 ? scale_x * sx : 1.0);
+    const double kf = mode_kfac(tab.kfac0, sx * sx + sy * sy + kz * kz) * (scale_x != 0.0 ? scale_x * sx : 1.0);
     return make_double2(-kf * q.y, kf * q.x);
   };
   tile_elems<T, N, NT>([&](int, int x, int w) {
@@ -183,7 +192,7 @@ inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* _
     if (retained(sx, sy, kz, N)) {
       const size_t g = gofs<N>(x, y, kz);
       const double2 q = modes[g];
-      prior += (kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(tab.var[g]);
+      prior += (kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(tab.var[var_ofs(N, S::W, x, y, kz)]);
     }
     tile[LAY::idx(x, w)] = cconvert<C>(ain(x, w, 0.0));
   });
@@ -737,7 +746,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
     const size_t g = gofs<N>(x, y, kz);
     const bool keep = retained(sx, sy, kz, N);
     const int n2 = sx * sx + sy * sy + kz * kz;
-    const double var = keep ? ld_stream(&tab.var[g]) : 0.0;
+    const double var = keep ? ld_stream(&tab.var[var_ofs(N, S::W, x, y, kz)]) : 0.0;
     // the mode, read once (gradient and drift)
     double2 q = make_double2(0.0, 0.0);
     if (kStartOfChain || (keep && (kFromSpectra || kDrift))) q = ld_stream(&modes[g]);
@@ -745,7 +754,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
     if constexpr (kFromSpectra) {
       if (keep) {
         const C tv = cadd(acc[e], tile[LAY::idx(x, w)]);
-        const double iv2 = 2.0 * inv_or_zero(var), kf2 = 2.0 * mode_kfac(tab, n2);
+        const double iv2 = 2.0 * inv_or_zero(var), kf2 = 2.0 * mode_kfac(tab.kfac0, n2);
         // -2 i kfac t = (2 kfac t.y, -2 kfac t.x)
         G = make_double2(iv2 * q.x + kf2 * (double)tv.y, iv2 * q.y - kf2 * (double)tv.x);
       }
@@ -796,7 +805,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
           q.y += c * p.y;
           st_stream(&modes[g], q);
           prior += (kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(var);
-          const double kf = mode_kfac(tab, n2);
+          const double kf = mode_kfac(tab.kfac0, n2);
           a = make_double2(-kf * q.y, kf * q.x);      // i kfac q
         }
         acc[e] = cconvert<C>(a);                       // A-input (acc is free now)
