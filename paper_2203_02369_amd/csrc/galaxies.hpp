@@ -247,7 +247,7 @@ __device__ __forceinline__ void
 like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, const double* __restrict__ frac,
           double* __restrict__ dist, const double* snl_q, Catalogue cat, Cosmo cm, T* __restrict__ gsort,
           LikeOut out, LeapUpdate lf, const BinNext* next) {
-  __shared__ double red[kGalThreads / 64];
+  __shared__ double red[4 * (kGalThreads / 64)];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double psi = 0.0, dps = 0.0, bad = 0.0;
   if (i < cat.n) {
@@ -306,20 +306,18 @@ like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, cons
     if (next) bin_point(i, dist[i], cat, cm, next->n_grid, next->out);
     bad = (ok_d && ok_h) ? 0.0 : 1.0;
   }
-  const double a = block_sum(psi, red);
-  const double b = block_sum(dps, red);
-  const double c = block_sum(bad, red);
   // this block's slice of the prior partials
   const int per = (out.n_prior + out.n_blocks - 1) / out.n_blocks;
   const int lo = blockIdx.x * per, hi = min(out.n_prior, lo + per);
   double pr = 0.0;
-  for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) pr += out.prior_part[i];
-  const double d = block_sum(pr, red);
+  for (int j = lo + threadIdx.x; j < hi; j += blockDim.x) pr += out.prior_part[j];
+  double sums[4] = {psi, dps, bad, pr};
+  block_sums(sums, red);
   if (threadIdx.x == 0) {
-    out.part[4 * blockIdx.x + 0] = a;
-    out.part[4 * blockIdx.x + 1] = b;
-    out.part[4 * blockIdx.x + 2] = c;
-    out.part[4 * blockIdx.x + 3] = d;
+    out.part[4 * blockIdx.x + 0] = sums[0];
+    out.part[4 * blockIdx.x + 1] = sums[1];
+    out.part[4 * blockIdx.x + 2] = sums[2];
+    out.part[4 * blockIdx.x + 3] = sums[3];
   }
 }
 
@@ -328,7 +326,7 @@ like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, cons
 __device__ __forceinline__ void
 finalize_body(const double* __restrict__ prior_part, int n_prior, const double* __restrict__ like_part, int n_like,
               double* __restrict__ psi_out, double* __restrict__ gs_out, double* snl_q, LeapUpdate lf) {
-  __shared__ double red[4];
+  __shared__ double red[3 * 4];   // blocks of up to 256 threads
   double a = 0.0, b = 0.0, c = 0.0;
   for (int i = threadIdx.x; i < n_prior; i += blockDim.x) a += prior_part[i];
   for (int i = threadIdx.x; i < n_like; i += blockDim.x) {
@@ -336,9 +334,11 @@ finalize_body(const double* __restrict__ prior_part, int n_prior, const double* 
     b += like_part[4 * i + 1];
     c += like_part[4 * i + 2];
   }
-  a = block_sum(a, red);
-  b = block_sum(b, red);
-  c = block_sum(c, red);
+  double sums[3] = {a, b, c};
+  block_sums(sums, red);
+  a = sums[0];
+  b = sums[1];
+  c = sums[2];
   if (threadIdx.x == 0) {
     const bool ok = c == 0.0 && isfinite(a);
     psi_out[0] = ok ? a : __builtin_inf();

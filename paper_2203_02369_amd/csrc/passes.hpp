@@ -90,6 +90,30 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;   // valid in thread 0
 }
 
+// K block sums at once, each in the same order as block_sum (so with the
+// same result) but with one pair of barriers; red holds K * (waves per
+// block) doubles.  Results valid in thread 0.
+template <int K> __device__ __forceinline__ void block_sums(double (&v)[K], double* red) {
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_down(v[j], off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) red[j * nw + wid] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < nw; ++i) s += red[j * nw + i];
+      v[j] = s;
+    }
+  }
+}
+
 // Visit this thread's elements (a = index along the FFT axis, w = column)
 // of a strided tile.
 template <typename T, int N, int NT, typename Fn>
