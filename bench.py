@@ -300,7 +300,7 @@ def run_batched(args, dev):
     for j, p in enumerate(plans):
         hamlet.hmc_run([p], [qm[j]], [qd[j]], [qs[j]], n_iter=args.steps, n_leapfrog=L, eps0=0.002, seed=0,
                        seeds=[seeds[j]], jitter=True, accepted=[acc[j]], resume=True, want_eps=False)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()   # one chain after the other, whatever the streams
     dt_seq = time.perf_counter() - t2
     v_seq = grads / dt_seq
     log("one at a time: %.3fs: %.1f grad/s" % (dt_seq, v_seq))
@@ -330,7 +330,7 @@ def run_batched(args, dev):
         "data": "synthetic",
         "config": {"workload": "batched: 16 chains, grids 64^3/128^3/256^3 in turn, n_j = 2000 + 28000 j / 15, "
                                "box 500 Mpc/h, HMC iterations of %d leapfrog steps; chains of one grid size "
-                               "share every launch" % L,
+                               "share every launch, the grid sizes run side by side" % L,
                    "chains": [[p.n_grid, p.n_gal] for p in plans], "leapfrog_steps": L,
                    "acceptance": round(rate, 3), "grad_evals_timed": grads},
         "one_at_a_time": {"value": round(v_seq, 2), "unit": "grad evals/s",

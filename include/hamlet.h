@@ -36,8 +36,11 @@
  * synchronise.  Calls on plans that share a stream run in call order.
  * Plans of one call with the same N and precision are batched: their
  * kernels run as shared launches on the stream of the first of them, ordered
- * after and before the other plans' streams with events.  A plan may appear
- * once per call.
+ * after and before the other plans' streams with events.  When several such
+ * groups of one call would use the same stream, every group after the first
+ * runs on a side stream of it (owned by the library, created on first use
+ * and kept until the process ends), ordered the same way, so independent
+ * groups may run concurrently.  A plan may appear once per call.
  *
  * Errors: every entry point returns a hamlet_status; the message of the last
  * non-OK status of the calling thread is hamlet_last_error().  A parameter

@@ -9,7 +9,9 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "hamlet.h"
@@ -642,27 +644,63 @@ static std::vector<std::vector<int>> group_plans(hamlet_plan* const* plans, int3
   return groups;
 }
 
-// A group's launches go to the stream of its first plan; the other plans'
-// streams are ordered before (join) and after (release) them with events.
-static hamlet_status streams_join(hamlet_plan* const* plans, const std::vector<int>& g) {
-  hipStream_t s0 = plans[g[0]]->stream;
+// Side streams of a stream (per device): created on first use and kept for
+// the life of the process, so that no call waits for a stream to drain
+// before destroying it.  Default priority, non-blocking.
+static hipStream_t side_stream(hipStream_t main, int k) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, hipStream_t, int>, hipStream_t> sides;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_tuple(dev, main, k);
+  auto it = sides.find(key);
+  if (it != sides.end()) return it->second;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  sides.emplace(key, s);
+  return s;
+}
+
+// The stream each group of one call runs on.  Groups are independent (no
+// plan is in two of them), so when several groups share their first plan's
+// stream, every group after the first on it runs on a side stream of that
+// stream, and the groups' launches can run side by side (a bandwidth-bound
+// 256^3 group leaves room for the small launches of a 64^3 one).  Without a
+// side stream the group runs on the shared stream, in call order.
+static std::vector<hipStream_t> group_streams(hamlet_plan* const* plans, const std::vector<std::vector<int>>& groups) {
+  std::vector<hipStream_t> out;
+  std::map<hipStream_t, int> used;
+  for (const std::vector<int>& g : groups) {
+    hipStream_t s = plans[g[0]]->stream;
+    const int k = used[s]++;
+    hipStream_t side = k > 0 ? side_stream(s, k) : nullptr;
+    out.push_back(side ? side : s);
+  }
+  return out;
+}
+
+// A group's launches go to its stream `run` (see group_streams); every
+// plan's stream is ordered before (join) and after (release) them with
+// events.
+static hamlet_status streams_join(hamlet_plan* const* plans, const std::vector<int>& g, hipStream_t run) {
   for (int j : g) {
     hamlet_plan* p = plans[j];
-    if (p->stream == s0) continue;
+    if (p->stream == run) continue;
     HIP_TRY(hipEventRecord(p->order_ev, p->stream));
-    HIP_TRY(hipStreamWaitEvent(s0, p->order_ev, 0));
+    HIP_TRY(hipStreamWaitEvent(run, p->order_ev, 0));
   }
   return HAMLET_OK;
 }
 
-static hamlet_status streams_release(hamlet_plan* const* plans, const std::vector<int>& g) {
+static hamlet_status streams_release(hamlet_plan* const* plans, const std::vector<int>& g, hipStream_t run) {
   hamlet_plan* p0 = plans[g[0]];
   bool recorded = false;
   for (int j : g) {
     hamlet_plan* p = plans[j];
-    if (p->stream == p0->stream) continue;
+    if (p->stream == run) continue;
     if (!recorded) {
-      HIP_TRY(hipEventRecord(p0->order_ev, p0->stream));
+      HIP_TRY(hipEventRecord(p0->order_ev, run));
       recorded = true;
     }
     HIP_TRY(hipStreamWaitEvent(p->stream, p0->order_ev, 0));
@@ -670,9 +708,9 @@ static hamlet_status streams_release(hamlet_plan* const* plans, const std::vecto
   return HAMLET_OK;
 }
 
-static Batch make_batch(hamlet_plan* const* plans, const std::vector<int>& g, int mode) {
+static Batch make_batch(hamlet_plan* const* plans, const std::vector<int>& g, int mode, hipStream_t run) {
   Batch b;
-  b.stream = plans[g[0]]->stream;
+  b.stream = run;
   b.count = (int)g.size();
   for (int i = 0; i < b.count; ++i) {
     b.plan[i] = plans[g[i]];
@@ -768,9 +806,12 @@ static hamlet_status logpost_grad_impl(hamlet_plan* const* plans, int32_t n_plan
     if (pl->n_gal > 0 && (!q_dist || !g_dist || !q_dist[j] || !g_dist[j]))
       return fail(HAMLET_EINVAL, "plan %d: NULL distance buffer", j);
   }
-  for (const std::vector<int>& g : group_plans(plans, n_plans)) {
-    if ((st = streams_join(plans, g)) != HAMLET_OK) return st;
-    Batch b = make_batch(plans, g, kXGrad);
+  const std::vector<std::vector<int>> groups = group_plans(plans, n_plans);
+  const std::vector<hipStream_t> runs = group_streams(plans, groups);
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const std::vector<int>& g = groups[gi];
+    if ((st = streams_join(plans, g, runs[gi])) != HAMLET_OK) return st;
+    Batch b = make_batch(plans, g, kXGrad, runs[gi]);
     b.plane_scale = plane_scale;
     for (int j : g) {
       hamlet_plan* pl = plans[j];
@@ -785,7 +826,7 @@ static hamlet_status logpost_grad_impl(hamlet_plan* const* plans, int32_t n_plan
       pl->st = sd;
     }
     if ((st = b.plan[0]->ops->eval(b)) != HAMLET_OK) return st;
-    if ((st = streams_release(plans, g)) != HAMLET_OK) return st;
+    if ((st = streams_release(plans, g, runs[gi])) != HAMLET_OK) return st;
   }
   return HAMLET_OK;
 }
@@ -822,9 +863,12 @@ extern "C" hamlet_status hamlet_leapfrog(hamlet_plan* const* plans, int32_t n_pl
     if (pl->n_gal > 0 && (!q_dist || !p_dist || !q_dist[j] || !p_dist[j]))
       return fail(HAMLET_EINVAL, "plan %d: NULL distance buffer", j);
   }
-  for (const std::vector<int>& g : group_plans(plans, n_plans, n_steps)) {
-    if ((st = streams_join(plans, g)) != HAMLET_OK) return st;
-    Batch b = make_batch(plans, g, kXGrad);
+  const std::vector<std::vector<int>> groups = group_plans(plans, n_plans, n_steps);
+  const std::vector<hipStream_t> runs = group_streams(plans, groups);
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const std::vector<int>& g = groups[gi];
+    if ((st = streams_join(plans, g, runs[gi])) != HAMLET_OK) return st;
+    Batch b = make_batch(plans, g, kXGrad, runs[gi]);
     for (int j : g) {
       hamlet_plan* pl = plans[j];
       StateDev sd{};
@@ -856,7 +900,7 @@ extern "C" hamlet_status hamlet_leapfrog(hamlet_plan* const* plans, int32_t n_pl
       }
     }
     if ((st = ops->leap_out(b)) != HAMLET_OK) return st;
-    if ((st = streams_release(plans, g)) != HAMLET_OK) return st;
+    if ((st = streams_release(plans, g, runs[gi])) != HAMLET_OK) return st;
   }
   return HAMLET_OK;
 }
@@ -879,10 +923,12 @@ extern "C" hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_pla
     if (pl->n_gal > 0 && (!q_dist || !q_dist[j])) return fail(HAMLET_EINVAL, "plan %d: NULL distance buffer", j);
   }
   const std::vector<std::vector<int>> groups = group_plans(plans, n_plans);
+  const std::vector<hipStream_t> gstream = group_streams(plans, groups);
   std::vector<ChainRun> runs(n_plans);
-  for (const std::vector<int>& g : groups) {
-    if ((st = streams_join(plans, g)) != HAMLET_OK) return st;
-    hipStream_t s0 = plans[g[0]]->stream;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const std::vector<int>& g = groups[gi];
+    if ((st = streams_join(plans, g, gstream[gi])) != HAMLET_OK) return st;
+    hipStream_t s0 = gstream[gi];
     for (int j : g) {
       hamlet_plan* pl = plans[j];
       StateDev sd{};
@@ -923,18 +969,19 @@ extern "C" hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_pla
       for (ChainRun* r : group_runs[gi]) act = act || r->active();
       if (!act) continue;
       any = true;
-      if ((st = tick_group(plans[groups[gi][0]]->stream, group_runs[gi])) != HAMLET_OK) return st;
+      if ((st = tick_group(gstream[gi], group_runs[gi])) != HAMLET_OK) return st;
     }
     if (!any) break;
   }
   for (int j = 0; j < n_plans; ++j) plans[j]->chain_ready = true;
-  for (const std::vector<int>& g : groups) {
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const std::vector<int>& g = groups[gi];
     if (eps_out) {
-      hipStream_t s0 = plans[g[0]]->stream;
+      hipStream_t s0 = gstream[gi];
       for (int j : g) HIP_TRY(hipMemcpyAsync(&eps_out[j], &plans[j]->cs->eps, sizeof(double), hipMemcpyDeviceToHost, s0));
       HIP_TRY(hipStreamSynchronize(s0));
     }
-    if ((st = streams_release(plans, g)) != HAMLET_OK) return st;
+    if ((st = streams_release(plans, g, gstream[gi])) != HAMLET_OK) return st;
   }
   return HAMLET_OK;
 }
