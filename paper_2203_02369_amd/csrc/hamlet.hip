@@ -1016,12 +1016,18 @@ struct Job {
   }
 };
 
+constexpr int kServerSides = 4;   // side streams a server tick uses at most
+
 struct hamlet_server {
   size_t budget = 0, in_use = 0;
   int max_running = 0, ahead = 2;
   hipStream_t stream = nullptr;
   hipStream_t copy = nullptr;      // result copies, off the tick stream
   std::vector<hipEvent_t> tick_ev;
+  // the groups of a tick after the first run on side streams of `stream`
+  // (see group_streams), forked and joined with these events
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;   // one per side stream
   int64_t ticks = 0, next_id = 1;
   std::map<int64_t, std::unique_ptr<Job>> jobs;
   std::deque<Job*> queue;
@@ -1078,6 +1084,9 @@ extern "C" hamlet_status hamlet_server_create(const hamlet_server_desc* desc, vo
   HIP_TRY(hipStreamCreateWithFlags(&sv->copy, hipStreamNonBlocking));
   sv->tick_ev.resize(sv->ahead, nullptr);
   for (hipEvent_t& e : sv->tick_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&sv->fork_ev, hipEventDisableTiming));
+  sv->join_ev.resize(kServerSides, nullptr);
+  for (hipEvent_t& e : sv->join_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   *out = sv.release();
   return HAMLET_OK;
 }
@@ -1088,6 +1097,8 @@ extern "C" hamlet_status hamlet_server_destroy(hamlet_server* sv) {
   for (auto& kv : sv->jobs) job_release(sv, kv.second.get());
   if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
   for (hipEvent_t ev : sv->tick_ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : sv->join_ev) (void)hipEventDestroy(ev);
+  if (sv->fork_ev) (void)hipEventDestroy(sv->fork_ev);
   (void)hipStreamDestroy(sv->copy);
   delete sv;
   if (e != hipSuccess) return fail(HAMLET_EDEVICE, "server destroy: %s", hipGetErrorString(e));
@@ -1235,8 +1246,10 @@ extern "C" hamlet_status hamlet_server_tick(hamlet_server* sv, hamlet_server_sta
     sv->running.push_back(j);
   }
   // one leapfrog step of every running job; jobs of one grid size and
-  // precision share launches, up to kMaxBatch per launch
+  // precision share launches, up to kMaxBatch per launch, and the groups
+  // after the first run side by side on side streams of the server's stream
   std::vector<bool> taken(sv->running.size(), false);
+  std::vector<std::vector<ChainRun*>> groups;
   for (size_t a = 0; a < sv->running.size(); ++a) {
     if (taken[a]) continue;
     std::vector<ChainRun*> group;
@@ -1247,7 +1260,26 @@ extern "C" hamlet_status hamlet_server_tick(hamlet_server* sv, hamlet_server_sta
       taken[b] = true;
       group.push_back(&sv->running[b]->run);
     }
-    if ((st = tick_group(sv->stream, group)) != HAMLET_OK) return st;
+    groups.push_back(std::move(group));
+  }
+  hipStream_t side[kServerSides] = {};
+  if (groups.size() > 1) HIP_TRY(hipEventRecord(sv->fork_ev, sv->stream));
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    hipStream_t run = sv->stream;
+    if (gi > 0) {
+      const int k = (int)((gi - 1) % kServerSides);
+      if (!side[k]) {
+        side[k] = side_stream(sv->stream, k + 1);
+        if (side[k]) HIP_TRY(hipStreamWaitEvent(side[k], sv->fork_ev, 0));
+      }
+      if (side[k]) run = side[k];
+    }
+    if ((st = tick_group(run, groups[gi])) != HAMLET_OK) return st;
+  }
+  for (int k = 0; k < kServerSides; ++k) {
+    if (!side[k]) continue;
+    HIP_TRY(hipEventRecord(sv->join_ev[k], side[k]));
+    HIP_TRY(hipStreamWaitEvent(sv->stream, sv->join_ev[k], 0));
   }
   // jobs whose last iteration was in this tick leave
   std::vector<Job*> still;
