@@ -48,9 +48,9 @@ HBM_PEAK_GBS = 8000.0
 # (--copy-calibration: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  Bytes read and
 # written per launch for the plain-gradient, first, middle and last variants.
 # Valid only for the kernel sources they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "56bd36b7f44c2803d396e7ae0f29e01f23e3c196"
-X_TRAFFIC = {"grad": (334153181, 134217920), "first": (335656996, 670191701),
-             "mid": (468530995, 401675000), "last": (468399724, 268502912)}
+X_TRAFFIC_SOURCES_SHA1 = "8930a12d5b86f6eb757ee66d4023ea6c0cd10ac5"
+X_TRAFFIC = {"grad": (334171872, 134217856), "first": (335669347, 670194091),
+             "mid": (468540936, 401674851), "last": (468406575, 268503947)}
 
 
 def kernel_sources_sha1():

@@ -253,7 +253,10 @@ typedef enum {
   HAMLET_K_FWD_Y = 6,       /* forward pass 2: FFT along y */
   HAMLET_K_FWD_X = 7,       /* forward pass 3: FFT along x, adjoint multiply, prior gradient; inside a
                                leapfrog trajectory also the mode kick and drift and inverse pass 1 of
-                               the next evaluation (then HAMLET_K_INV_X is not launched) */
+                               the next evaluation (then HAMLET_K_INV_X is not launched); the first
+                               pass of a chain's trajectory also draws the mode momenta, sums their
+                               kinetic energy and keeps the start point, the last sums the kinetic
+                               energy after its half kick */
   HAMLET_K_COUNT = 8
 } hamlet_kernel;
 
