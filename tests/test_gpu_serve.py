@@ -167,3 +167,27 @@ def test_default_start_state(hl):
     assert np.all(res["q_modes"] == 0)
     assert np.max(np.abs(res["q_dist"] - dz) / dz) <= 1e-12
     assert res["q_snl"] == 1.1
+
+
+def test_more_groups_than_side_streams(hl):
+    # six groups in every tick (three grid sizes x two precisions): the groups
+    # after the first run on the server's side streams, two of them sharing
+    # one; each job must equal itself served alone
+    cfgs = [(16, "fp64"), (16, "fp32"), (32, "fp64"), (32, "fp32"), (64, "fp64"), (64, "fp32")]
+    ms = [mocks.make_mock(n, 200.0 if n == 16 else 400.0, 200 + 50 * k, 80.0, "sphere", (0.2, 0.2), seed=70 + k)
+          for k, (n, _) in enumerate(cfgs)]
+    chain = dict(n_iter=3, n_leapfrog=2)
+    sv = hl.Server(8 * GIB)
+    say("six groups together")
+    ids = [_submit(sv, m, prec, 20 + k, _start(m, k), **chain) for k, (m, (_, prec)) in enumerate(zip(ms, cfgs))]
+    _drain(sv, ids)
+    together = [sv.take(j) for j in ids]
+    sv.close()
+    for k, (m, (n, prec)) in enumerate(zip(ms, cfgs)):
+        say("alone", n, prec)
+        sv = hl.Server(8 * GIB)
+        j = _submit(sv, m, prec, 20 + k, _start(m, k), **chain)
+        _drain(sv, [j])
+        alone = sv.take(j)
+        sv.close()
+        assert _same(alone, together[k])
