@@ -180,12 +180,40 @@ typedef struct {
  *   count, so n_iter entries for a fresh chain (more when resumed).
  * eps_out (host, may be NULL): n_plans, the step after warm-up (synchronises).
  * Batches: the plans of one call with the same N and precision share every
- * kernel launch (up to 32 plans per launch); each chain's numbers do not
+ * kernel launch (up to 16 plans per launch); each chain's numbers do not
  * depend on which other chains share its launches. */
 hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_plans, const hamlet_hmc_opts* opts,
                              void* const* q_modes, double* const* q_dist, double* const* q_snl,
                              void* const* mode_sum, double* const* dh, int32_t* const* accepted,
                              double* eps_out);
+
+/* ---- The paper's flat parameter vector ----
+ *
+ * Section 3.1 orders the parameters of the posterior as one real vector:
+ * the real parts of the independent Fourier modes, then their imaginary
+ * parts, the n distances and sigma_NL (here s = sigma_NL / 100 km/s, the
+ * sampled coordinate).  The independent modes are the retained entries of
+ * the stored layout (no k = 0, no Nyquist component) with kz > 0, and on
+ * the kz = 0 plane the canonical member of each Hermitian pair (ny > 0, or
+ * ny = 0 and nx > 0), taken in row-major (kx, ky, kz) order: m = ((N-1)^3 - 1)
+ * / 2 of them, so the vector has 2m + n + 1 entries.  Applied to a gradient
+ * (G = dPsi/dRe + i dPsi/dIm per independent coordinate, dPsi/dd, dPsi/ds)
+ * packing gives dPsi/dq in the same order. */
+
+/* Length 2m + n + 1 of the plan's flat vector (host only). */
+hamlet_status hamlet_flat_size(const hamlet_plan* plan, int64_t* n_flat);
+
+/* flat (device, n_flat doubles) <- modes (device, N x N x N/2 complex128),
+ * dist (device, n doubles; may be NULL when n = 0), snl (device, 1 double).
+ * Reads only the independent entries.  Asynchronous on the plan's stream. */
+hamlet_status hamlet_pack_flat(hamlet_plan* plan, const void* modes, const double* dist, const double* snl,
+                               double* flat);
+
+/* modes, dist, snl (device) <- flat (device).  Writes every stored entry:
+ * the independent ones from flat, each mirror entry of the kz = 0 plane as
+ * the conjugate of its partner, excluded entries 0.  Asynchronous on the
+ * plan's stream. */
+hamlet_status hamlet_unpack_flat(hamlet_plan* plan, const double* flat, void* modes, double* dist, double* snl);
 
 /* ---- Serving: continuous batching of independent reconstruction jobs ----
  *

@@ -83,6 +83,20 @@ def unpack_modes(n, vec):
     return symmetrise(n, out.reshape(n, n, n // 2 + 1))
 
 
+def pack_state(n, modes, dist, s):
+    """The whole flat parameter vector of Section 3.1 (eq:q): Re and Im of
+    the independent modes, then the n distances, then s = sigma_NL/100."""
+    return np.concatenate([pack_modes(n, modes), np.asarray(dist, dtype=float), [float(s)]])
+
+
+def unpack_state(n, vec, n_gal):
+    """Inverse of pack_state: (modes with mirror entries filled, dist, s)."""
+    m2 = (n - 1) ** 3 - 1
+    vec = np.asarray(vec, dtype=float)
+    assert vec.size == m2 + n_gal + 1
+    return unpack_modes(n, vec[:m2]), vec[m2:m2 + n_gal].copy(), float(vec[m2 + n_gal])
+
+
 # ----------------------------------------------------------------------------
 # Phase-space state
 # ----------------------------------------------------------------------------

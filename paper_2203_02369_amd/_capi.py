@@ -97,6 +97,9 @@ SIGNATURES = {
                                        c_double_pp, c_void_pp, c_double_pp, c_double_pp, c_double_pp]),
     "hamlet_hmc_run": (ctypes.c_int, [c_void_pp, ctypes.c_int32, ctypes.POINTER(HmcOpts), c_void_pp, c_double_pp,
                                       c_double_pp, c_void_pp, c_double_pp, ctypes.POINTER(c_int32_p), c_double_p]),
+    "hamlet_flat_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "hamlet_pack_flat": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, c_double_p, c_double_p]),
+    "hamlet_unpack_flat": (ctypes.c_int, [ctypes.c_void_p, c_double_p, ctypes.c_void_p, c_double_p, c_double_p]),
     "hamlet_server_create": (ctypes.c_int, [ctypes.POINTER(ServerDesc), ctypes.c_void_p,
                                             ctypes.POINTER(ctypes.c_void_p)]),
     "hamlet_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),

@@ -17,6 +17,7 @@
 #include "hamlet.h"
 #include "common.hpp"
 #include "fft.hpp"
+#include "flat.hpp"
 #include "passes.hpp"
 #include "galaxies.hpp"
 #include "hmc.hpp"
@@ -983,6 +984,39 @@ extern "C" hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_pla
     }
     if ((st = streams_release(plans, g, gstream[gi])) != HAMLET_OK) return st;
   }
+  return HAMLET_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The paper's flat parameter vector
+// ---------------------------------------------------------------------------
+extern "C" hamlet_status hamlet_flat_size(const hamlet_plan* plan, int64_t* n_flat) {
+  if (!plan || !n_flat) return fail(HAMLET_EINVAL, "NULL argument");
+  *n_flat = 2 * flat_modes(plan->n) + plan->n_gal + 1;
+  return HAMLET_OK;
+}
+
+static unsigned flat_blocks(const hamlet_plan* pl) {
+  return blocks_for(std::max(pl->modes_count(), (size_t)pl->n_gal + 1), 256);
+}
+
+extern "C" hamlet_status hamlet_pack_flat(hamlet_plan* plan, const void* modes, const double* dist,
+                                          const double* snl, double* flat) {
+  if (!plan || !modes || !snl || !flat) return fail(HAMLET_EINVAL, "NULL argument");
+  if (plan->n_gal > 0 && !dist) return fail(HAMLET_EINVAL, "NULL distance buffer");
+  k_pack_flat<<<flat_blocks(plan), 256, 0, plan->stream>>>((const double2*)modes, dist, snl, flat, plan->n,
+                                                           plan->n_gal);
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
+extern "C" hamlet_status hamlet_unpack_flat(hamlet_plan* plan, const double* flat, void* modes, double* dist,
+                                            double* snl) {
+  if (!plan || !flat || !modes || !snl) return fail(HAMLET_EINVAL, "NULL argument");
+  if (plan->n_gal > 0 && !dist) return fail(HAMLET_EINVAL, "NULL distance buffer");
+  k_unpack_flat<<<flat_blocks(plan), 256, 0, plan->stream>>>(flat, (double2*)modes, dist, snl, plan->n,
+                                                             plan->n_gal);
+  LAUNCH_CHECK();
   return HAMLET_OK;
 }
 

@@ -185,6 +185,40 @@ def logpost_grad(plans, q_modes, q_dist, q_snl, g_modes, g_dist, g_snl, psi, per
                    _vp(args[3]), _dpp(args[4]), _dpp(args[5]), _dpp(args[6])))
 
 
+def _ptr(addr):
+    return ctypes.cast(ctypes.c_void_p(addr), c_double_p) if addr else c_double_p()
+
+
+def flat_size(plan):
+    """Length 2m + n + 1 of the plan's flat parameter vector (hamlet_flat_size)."""
+    out = ctypes.c_int64()
+    _capi.check(_capi.load().hamlet_flat_size(plan.handle, ctypes.byref(out)))
+    return out.value
+
+
+def pack_flat(plan, modes, dist, snl, flat=None):
+    """The paper's flat vector (Re, Im of the independent modes, distances, s)
+    of a state or a gradient, on the plan's stream (hamlet_pack_flat)."""
+    if flat is None:
+        flat = torch.empty(flat_size(plan), dtype=torch.float64, device=plan.device)
+    elif flat.dtype != torch.float64 or flat.numel() != flat_size(plan) or not flat.is_contiguous():
+        raise ValueError("flat must be contiguous float64 (%d,)" % flat_size(plan))
+    m, d, s = _check(modes, plan, "modes", "modes"), _check(dist, plan, "dist", "dist"), _check(snl, plan, "scalar", "snl")
+    _capi.check(_capi.load().hamlet_pack_flat(plan.handle, ctypes.c_void_p(m), _ptr(d), _ptr(s),
+                                              _ptr(_check(flat, plan, "iter_f64", "flat"))))
+    return flat
+
+
+def unpack_flat(plan, flat, modes, dist, snl):
+    """Writes the state (modes with mirror entries and excluded modes filled,
+    distances, s) of a flat vector, on the plan's stream (hamlet_unpack_flat)."""
+    if flat.dtype != torch.float64 or flat.numel() != flat_size(plan) or not flat.is_contiguous():
+        raise ValueError("flat must be contiguous float64 (%d,)" % flat_size(plan))
+    m, d, s = _check(modes, plan, "modes", "modes"), _check(dist, plan, "dist", "dist"), _check(snl, plan, "scalar", "snl")
+    _capi.check(_capi.load().hamlet_unpack_flat(plan.handle, _ptr(_check(flat, plan, "iter_f64", "flat")),
+                                                ctypes.c_void_p(m), _ptr(d), _ptr(s)))
+
+
 def leapfrog(plans, eps, n_steps, q_modes, q_dist, q_snl, p_modes, p_dist, p_snl, psi):
     """n_steps kick-drift-kick steps in place (hamlet_leapfrog)."""
     plans, hp = _plans(plans)
