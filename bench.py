@@ -160,6 +160,30 @@ def main():
     acc32 = acc.cpu().numpy()
     log("fp32: %d iterations x %d steps in %.3fs: %.1f grad/s, acceptance %.2f"
         % (args.steps, L, dt, value, acc32.mean()))
+
+    # ---- the other passes, each timed over two more iterations -----------------
+    # algorithmic bytes per launch in c (the z passes also move the points'
+    # records, a few MB); the galaxy kernels are latency-bound (time only)
+    passes = {}
+    c_bytes = 8 * n * n * (n // 2)
+    for kind, name, cs in (("inv_y", "k_inv_y", 5), ("inv_z_gather", "k_inv_z_gather", 3),
+                           ("fwd_z_scatter", "k_fwd_z_scatter", 3), ("fwd_y", "k_fwd_y", 5),
+                           ("like", "k_like", None), ("bin", "binning (4 kernels)", None)):
+        timer = hamlet.KernelTimer(plan, hamlet.PROFILE_KERNELS[kind])
+        q2, qd2, qs2 = (t.clone() for t in start)
+        torch.cuda.synchronize()
+        timer.start()
+        hamlet.hmc_run([plan], [q2], [qd2], [qs2], n_iter=2, n_leapfrog=L, eps0=eps, seed=seed + 1, jitter=True,
+                       want_eps=False)
+        ms, launches = timer.stop()
+        entry = {"avg_launch_ms": round(ms / launches, 4), "launches": launches}
+        if cs is not None:
+            gbs = cs * c_bytes / (ms / launches * 1e-3) / 1e9
+            entry.update({"bytes_per_launch": cs * c_bytes, "achieved": round(gbs, 1), "unit": "GB/s",
+                          "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        passes[name] = entry
+        del q2, qd2, qs2
+    log("passes: " + ", ".join("%s %.4f ms" % (k, v["avg_launch_ms"]) for k, v in passes.items()))
     plan.close()
     del q, qd, qs
 
@@ -250,6 +274,7 @@ def main():
                    "acceptance": float(acc32.mean()), "grad_evals_timed": grads},
         "fp64_path": fp64,
         "roofline": roofline,
+        "passes": passes,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
