@@ -243,6 +243,40 @@ def test_leapfrog_matches_oracle(hl, precision):
     plan.close()
 
 
+def test_paper_scale_leapfrog_matches_oracle_fp32(hl):
+    # 256^3, 30 000 points, one leapfrog step with the step size the
+    # benchmark adapts to: the fused first- and last-step x passes and the
+    # likelihood's kicks at full size.  The state moves little in one step,
+    # so the displacements are compared.
+    m = mocks.paper_scale_256()
+    prob = oracle_problem(m)
+    q0 = hmc.State(hmc.symmetrise(256, m.dhat_true), m.d_true.copy(), 1.5)
+    p0 = _random_momenta(prob, 12)
+    eps = 1e-4
+    say("oracle 256^3 leapfrog (two evaluations on the host)")
+    q1, p1, c1 = hmc.leapfrog(prob, q0, p0, eps, 1)
+    say("gpu 256^3 fp32 leapfrog")
+    plan = hl.Plan.from_mock(m, precision="fp32")
+    dev = plan.device
+    tq = torch.from_numpy(to_lib_layout(q0.modes)).to(dev)
+    tqd = torch.from_numpy(q0.dist.copy()).to(dev)
+    tqs = plan.scalar(q0.s)
+    tp = torch.from_numpy(to_lib_layout(p0.modes)).to(dev)
+    tpd = torch.from_numpy(p0.dist.copy()).to(dev)
+    tps = plan.scalar(p0.s)
+    psi = plan.scalar()
+    hl.leapfrog([plan], [eps], [1], [tq], [tqd], [tqs], [tp], [tpd], [tps], [psi])
+    torch.cuda.synchronize()
+    dq = from_lib_layout(tq.cpu().numpy()) - q0.modes
+    dp = from_lib_layout(tp.cpu().numpy()) - p0.modes
+    assert rel_inf(dq, q1.modes - q0.modes) <= 1e-4
+    assert rel_inf(dp, p1.modes - p0.modes) <= 1e-3
+    assert rel_inf(tqd.cpu().numpy() - q0.dist, q1.dist - q0.dist) <= 1e-3
+    assert rel_inf(tpd.cpu().numpy() - p0.dist, p1.dist - p0.dist) <= 1e-3
+    assert abs(psi.item() - c1[0]) <= TOL32_PSI * abs(c1[0])
+    plan.close()
+
+
 @pytest.mark.parametrize("steps", [1, 3])
 def test_gradient_after_a_trajectory_is_unchanged(hl, steps):
     # Inside a trajectory the drifting kernels bin the points of the next
