@@ -93,3 +93,13 @@ def test_server_entry_points_validate_on_the_host():
     assert lib.hamlet_server_job_state(None, 1, ctypes.byref(state)) == -1
     assert lib.hamlet_server_take(None, 1, None, None, None, None, None, None, None) == -1
     assert lib.hamlet_server_destroy(None) == 0
+
+
+def test_flat_vector_entry_points_validate_on_the_host():
+    from paper_2203_02369_amd import _capi
+    lib = _capi.load()
+    n = ctypes.c_int64()
+    assert lib.hamlet_flat_size(None, ctypes.byref(n)) == -1
+    assert b"NULL" in lib.hamlet_last_error()
+    assert lib.hamlet_pack_flat(None, None, None, None, None) == -1
+    assert lib.hamlet_unpack_flat(None, None, None, None, None) == -1
