@@ -93,7 +93,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(independent chains shard across GPUs with no exchange; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
