@@ -357,3 +357,38 @@ def test_hmc_dual_averaging_matches_oracle_fp64(hl):
     assert abs(eps_out[0] - res.eps) <= 1e-9 * res.eps
     assert rel_inf(from_lib_layout(tq.cpu().numpy()), res.state.modes) <= 1e-9
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_leapfrog_is_reversible(hl, precision):
+    # The force is a deterministic function of the state (no float atomics),
+    # so kick-drift-kick run back with negated momenta returns to the start up
+    # to the rounding of the FP64 coordinates (the property that keeps the
+    # Metropolis-Hastings test exact).
+    m, prob, dhat, d, s, ref = case("32^3 L400 n1000 sphere")
+    p0 = _random_momenta(prob, 21)
+    plan = hl.Plan.from_mock(m, precision=precision)
+    dev = plan.device
+    say("reversibility", precision)
+    tq = torch.from_numpy(to_lib_layout(dhat)).to(dev)
+    tqd = torch.from_numpy(d.copy()).to(dev)
+    tqs = plan.scalar(s)
+    tp = torch.from_numpy(to_lib_layout(p0.modes)).to(dev)
+    tpd = torch.from_numpy(p0.dist.copy()).to(dev)
+    tps = plan.scalar(p0.s)
+    psi = plan.scalar()
+    eps, steps = 0.02, 20
+    hl.leapfrog([plan], [eps], [steps], [tq], [tqd], [tqs], [tp], [tpd], [tps], [psi])
+    moved = rel_inf(from_lib_layout(tq.cpu().numpy()), dhat)
+    for t in (tp, tpd, tps):
+        t.neg_()
+    hl.leapfrog([plan], [eps], [steps], [tq], [tqd], [tqs], [tp], [tpd], [tps], [psi])
+    torch.cuda.synchronize()
+    tol = 1e-10 if precision == "fp64" else 1e-7
+    assert moved > 1e-3                       # the trajectory went somewhere
+    assert rel_inf(from_lib_layout(tq.cpu().numpy()), dhat) <= tol
+    assert rel_inf(tqd.cpu().numpy(), d) <= tol
+    assert abs(tqs.item() - s) <= tol * abs(s)
+    assert rel_inf(from_lib_layout(-tp.cpu().numpy()), p0.modes) <= 100 * tol
+    assert abs(psi.item() - ref[0]) <= (1e-10 if precision == "fp64" else TOL32_PSI) * abs(ref[0])
+    plan.close()
