@@ -192,4 +192,25 @@ __device__ __forceinline__ void load_twiddles(cplx_t<T>* tw_lds, const cplx_t<T>
   for (int i = threadIdx.x; i < N; i += NT) tw_lds[i] = tw[i];
 }
 
+// The same in two steps: load() into registers, store() into LDS, so that a
+// pass can issue its tile loads in between and wait once for both.
+template <typename T, int N, int NT> struct TwiddleStage {
+  static constexpr int R = (N + NT - 1) / NT;
+  cplx_t<T> v[R];
+  __device__ __forceinline__ void load(const cplx_t<T>* __restrict__ tw) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = threadIdx.x + r * NT;
+      if (i < N) v[r] = tw[i];
+    }
+  }
+  __device__ __forceinline__ void store(cplx_t<T>* tw_lds) const {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = threadIdx.x + r * NT;
+      if (i < N) tw_lds[i] = v[r];
+    }
+  }
+};
+
 }  // namespace hamlet

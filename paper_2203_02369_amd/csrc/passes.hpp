@@ -177,6 +177,54 @@ template <int N> __device__ __forceinline__ size_t gofs(int i, int j, int kz) {
   return ((size_t)i * N + j) * (N / 2) + kz;
 }
 
+// Pencils in reach of the points.  A real-space pencil (x, y) (after the x
+// and y transforms) takes part in the gather and the scatter only when a
+// point's CIC stencil reaches it: one of the columns (x - ox, y - oy),
+// ox, oy in {0, 1}, holds a point.  Elsewhere the velocity pencils are never
+// read and the scattered field is zero, so the passes on either side skip
+// those pencils' rows: the inverse y pass does not store them, the gather
+// does not load them, the scatter does not store them and the forward y
+// pass reads them as zero.  Every pass derives the flag from the same bucket
+// offsets (off, N^2 + 1 entries) of the evaluation.
+//
+// PencilProbe loads the bucket bounds of the four stencil columns of pencil
+// (x, y) together; the flag is taken later, so the loads can overlap other
+// work.
+template <int N> struct PencilProbe {
+  int b[8];
+  __device__ __forceinline__ void load(const int* off, int x, int y) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = ((x - (c >> 1) + N) & (N - 1)) * N + ((y - (c & 1) + N) & (N - 1));
+      b[2 * c] = off[k];
+      b[2 * c + 1] = off[k + 1];
+    }
+  }
+  __device__ __forceinline__ bool touched() const {
+    return (b[1] > b[0]) | (b[3] > b[2]) | (b[5] > b[4]) | (b[7] > b[6]);
+  }
+};
+
+// The flags of the pencils (x, y), y in [0, N), into LDS (visible after the
+// caller's next barrier): one pencil per thread.
+template <int N, int NT> __device__ __forceinline__ void plane_flags(const int* off, int x, bool* touched) {
+  static_assert(N <= NT, "one pencil per thread");
+  if (threadIdx.x < N) {
+    PencilProbe<N> pr;
+    pr.load(off, x, threadIdx.x);
+    touched[threadIdx.x] = pr.touched();
+  }
+}
+
+// Bit e: the row of this thread's e-th column group (tile_vecs order) is
+// flagged.
+template <typename T, int N, int NT> __device__ __forceinline__ unsigned row_bits(const bool* touched) {
+  static_assert(vecs_per_thread<T, N, NT>() <= 32, "one bit per column group");
+  unsigned m = 0;
+  tile_vecs<T, N, NT>([&](int e, int y, int) { m |= touched[y] ? 1u << e : 0u; });
+  return m;
+}
+
 // Offset of mode (kx, ky, kz) in the per-mode sigma_k^2 array, laid out as
 // the x-pass tiles [ky][kz / W][kx][kz % W]: element e of a tile is at
 // tile * N W + e, so a wave reads whole cache lines (a row of W values
@@ -238,19 +286,32 @@ inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* _
 template <typename T, int N, int NT>
 __device__ __forceinline__ void
 inv_y_body(const cplx_t<T>* __restrict__ inA, const cplx_t<T>* __restrict__ inB, const cplx_t<T>* __restrict__ tw,
-        cplx_t<T>* __restrict__ vx, cplx_t<T>* __restrict__ vy, cplx_t<T>* __restrict__ vz, int x0) {
+        cplx_t<T>* __restrict__ vx, cplx_t<T>* __restrict__ vy, cplx_t<T>* __restrict__ vz, const int* __restrict__ off,
+        int x0) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Row;
   using CV = ColVec<T>;
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
-  load_twiddles<T, N, NT>(twl, tw);
+  __shared__ bool touched[N];   // rows stored (see PencilProbe)
   const int x = x0 + blockIdx.y, z0 = blockIdx.x * S::W;
+  // the flags are needed only at the first store: their loads go first,
+  // and they are taken once the tile is in
+  static_assert(N <= NT, "one pencil per thread");
+  PencilProbe<N> probe;
+  if (threadIdx.x < N) probe.load(off, x, threadIdx.x);
+  TwiddleStage<T, N, NT> tws;
+  tws.load(tw);
   tile_vecs<T, N, NT>([&](int, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, vec_load<T>(&inB[gofs<N>(x, y, z0 + w)])); });
+  tws.store(twl);
+  if (threadIdx.x < N) touched[threadIdx.x] = probe.touched();
   __syncthreads();
+  const unsigned rows = row_bits<T, N, NT>(touched);
   lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
-  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_store<T>(&vx[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, y, w)); });
+  tile_vecs<T, N, NT>([&](int e, int y, int w) {
+    if ((rows >> e) & 1u) vec_store<T>(&vx[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, y, w));
+  });
   __syncthreads();
   // A is read once and kept in registers for its second transform
   typename CV::V ra[vecs_per_thread<T, N, NT>()];
@@ -262,12 +323,16 @@ inv_y_body(const cplx_t<T>* __restrict__ inA, const cplx_t<T>* __restrict__ inB,
   });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
-  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_store<T>(&vy[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, y, w)); });
+  tile_vecs<T, N, NT>([&](int e, int y, int w) {
+    if ((rows >> e) & 1u) vec_store<T>(&vy[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, y, w));
+  });
   __syncthreads();
   tile_vecs<T, N, NT>([&](int e, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, ra[e]); });
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
-  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_store<T>(&vz[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, y, w)); });
+  tile_vecs<T, N, NT>([&](int e, int y, int w) {
+    if ((rows >> e) & 1u) vec_store<T>(&vz[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, y, w));
+  });
 }
 
 // Galaxies binned by CIC column (ix, iy) of their lower corner, in sorted
@@ -325,6 +390,17 @@ inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict_
   const int key = ((x - ox + N) & (N - 1)) * N + ((y - oy + N) & (N - 1));
   const int s0 = bins.off[key], s1 = bins.off[key + 1];
   load_twiddles<T, N, NT>(twl, tw);
+  // Pencils of the tile in reach of a point (see PencilProbe).  Every
+  // wave holds every (pencil, corner) in its lanes, so a ballot gives each
+  // wave the whole tile's flags.  The inverse y pass stored only these
+  // pencils; the others are transformed as zero and never read.
+  static_assert(64 % (4 * P) == 0 && NT % 64 == 0, "a wave covers the tile's stencil columns");
+  const unsigned long long occ = __ballot(s1 > s0);
+  unsigned tp = 0;
+#pragma unroll
+  for (int q = 0; q < P; ++q) tp |= ((occ >> (4 * q)) & 0xFull) ? 1u << q : 0u;
+  if (tp == 0) return;   // block-uniform: no point reaches the tile
+  auto touched = [&](int q) { return ((tp >> q) & 1u) != 0; };
   // Build Z = A + i B with A, B the Hermitian half spectra of the two real
   // pencils of each transform (Nyquist entry zero, DC entries real).
   auto put = [&](int k, int f, C av, C bv) {
@@ -336,45 +412,77 @@ inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict_
       buf[LAY::idx(N - k, f)] = cmake<C>(av.x + bv.y, bv.x - av.y);      // conj(A) + i conj(B)
     }
   };
+  // Real pencils of transform f: pa in the real part, pb in the imaginary
+  // part, from vx / vy (f = 3m, 3m + 2) or n_z vz (f = 3m + 1).
+  auto sources = [&](int f, int& pa, int& pb) {
+    const int m = f / 3, r = f % 3;
+    pa = 2 * m + (r == 2 ? 1 : 0);
+    pb = r == 1 ? 2 * m + 1 : pa;
+    return r == 1;
+  };
+  // Every load of a thread is issued before the first wait: loads into
+  // registers, then the spectra into LDS.
   if constexpr (sizeof(C) == 8) {
     // FP32: two consecutive kz per thread, 16-byte loads
     struct C2 { C a, b; };
-    constexpr int H2 = H / 2;
-    for (int idx = threadIdx.x; idx < F * H2; idx += NT) {
-      const int k = 2 * (idx % H2), f = idx / H2;
-      const int m = f / 3, r = f % 3;
-      C2 av, bv;
-      if (r == 1) {
-        const size_t g0 = gofs<N>(x, y0 + 2 * m, k);
-        av = ld_stream(reinterpret_cast<const C2*>(&vz[g0]));
-        bv = ld_stream(reinterpret_cast<const C2*>(&vz[g0 + H]));
-        av.a = cscale(av.a, (T)k);
-        av.b = cscale(av.b, (T)(k + 1));
-        bv.a = cscale(bv.a, (T)k);
-        bv.b = cscale(bv.b, (T)(k + 1));
-      } else {
-        const size_t g = gofs<N>(x, y0 + 2 * m + (r == 2 ? 1 : 0), k);
-        av = ld_stream(reinterpret_cast<const C2*>(&vx[g]));
-        bv = ld_stream(reinterpret_cast<const C2*>(&vy[g]));
+    constexpr int H2 = H / 2, IT = (F * H2 + NT - 1) / NT;
+    C2 av[IT], bv[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      const C zero = cmake<C>((T)0, (T)0);
+      av[it] = bv[it] = C2{zero, zero};
+      if (idx < F * H2) {
+        const int k = 2 * (idx % H2), f = idx / H2;
+        int pa, pb;
+        const bool zc = sources(f, pa, pb);
+        if (touched(pa)) av[it] = ld_stream(reinterpret_cast<const C2*>(&(zc ? vz : vx)[gofs<N>(x, y0 + pa, k)]));
+        if (touched(pb)) bv[it] = ld_stream(reinterpret_cast<const C2*>(&(zc ? vz : vy)[gofs<N>(x, y0 + pb, k)]));
       }
-      put(k, f, av.a, bv.a);
-      put(k + 1, f, av.b, bv.b);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < F * H2) {
+        const int k = 2 * (idx % H2), f = idx / H2;
+        int pa, pb;
+        if (sources(f, pa, pb)) {
+          av[it].a = cscale(av[it].a, (T)k);
+          av[it].b = cscale(av[it].b, (T)(k + 1));
+          bv[it].a = cscale(bv[it].a, (T)k);
+          bv[it].b = cscale(bv[it].b, (T)(k + 1));
+        }
+        put(k, f, av[it].a, bv[it].a);
+        put(k + 1, f, av[it].b, bv[it].b);
+      }
     }
   } else {
-    for (int idx = threadIdx.x; idx < F * H; idx += NT) {
-      const int k = idx % H, f = idx / H;
-      const int m = f / 3, r = f % 3;
-      C av, bv;
-      if (r == 1) {
-        const size_t g0 = gofs<N>(x, y0 + 2 * m, k);
-        av = cscale(ld_stream(&vz[g0]), (T)k);
-        bv = cscale(ld_stream(&vz[g0 + H]), (T)k);
-      } else {
-        const size_t g = gofs<N>(x, y0 + 2 * m + (r == 2 ? 1 : 0), k);
-        av = ld_stream(&vx[g]);
-        bv = ld_stream(&vy[g]);
+    constexpr int IT = (F * H + NT - 1) / NT;
+    C av[IT], bv[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      av[it] = bv[it] = cmake<C>((T)0, (T)0);
+      if (idx < F * H) {
+        const int k = idx % H, f = idx / H;
+        int pa, pb;
+        const bool zc = sources(f, pa, pb);
+        if (touched(pa)) av[it] = ld_stream(&(zc ? vz : vx)[gofs<N>(x, y0 + pa, k)]);
+        if (touched(pb)) bv[it] = ld_stream(&(zc ? vz : vy)[gofs<N>(x, y0 + pb, k)]);
       }
-      put(k, f, av, bv);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < F * H) {
+        const int k = idx % H, f = idx / H;
+        int pa, pb;
+        if (sources(f, pa, pb)) {
+          av[it] = cscale(av[it], (T)k);
+          bv[it] = cscale(bv[it], (T)k);
+        }
+        put(k, f, av[it], bv[it]);
+      }
     }
   }
   __syncthreads();
@@ -470,6 +578,7 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
   __shared__ C twl[N];
   __shared__ int col[4 * P][2];     // binned range of the 4 stencil columns of each pencil
   __shared__ ZStage<T, CAP> stg;
+  __shared__ unsigned tile_touch;   // bit p: pencil p in reach of a point (see PencilProbe)
   const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
   static_assert(4 * P + 4 <= 64, "tile set-up runs in the first wave");
   // Tile set-up, issued first so that its loads overlap the twiddle load:
@@ -498,6 +607,7 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
       }
       stg.start[r] = a;
     }
+    const unsigned long long occ = __ballot(t < 4 * P && b > a);
     const int len = (t >= 4 * P && t < 4 * P + 4) ? b - a : 0;
     const int l0 = __shfl(len, 4 * P, 64), l1 = __shfl(len, 4 * P + 1, 64);
     const int l2 = __shfl(len, 4 * P + 2, 64), l3 = __shfl(len, 4 * P + 3, 64);
@@ -507,6 +617,9 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
       stg.at[2] = l0 + l1;
       stg.at[3] = l0 + l1 + l2;
       stg.count = l0 + l1 + l2 + l3;
+      unsigned tp = 0;
+      for (int q = 0; q < P; ++q) tp |= ((occ >> (4 * q)) & 0xFull) ? 1u << q : 0u;
+      tile_touch = tp;
     }
   }
   load_twiddles<T, N, NT>(twl, tw);
@@ -514,6 +627,11 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
   int G = 1;
   while (G < GMAX && 8 * G < most) G <<= 1;
   __syncthreads();
+  // Only pencils in reach of a point are stored: the forward y pass reads
+  // the others as zero.
+  const unsigned tp = tile_touch;
+  if (tp == 0) return;   // block-uniform
+  auto touched = [&](int q) { return ((tp >> q) & 1u) != 0; };
   const bool staged = stg.count <= CAP;   // block-uniform
   if (staged) {
     for (int i = threadIdx.x; i < stg.count; i += NT) {
@@ -542,6 +660,7 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
     struct alignas(16) CK { C v[KT]; };
     for (int idx = threadIdx.x; idx < P * HK; idx += NT) {
       const int k0 = KT * (idx % HK), p = idx / HK;
+      if (!touched(p)) continue;
       C wk[KT];
       T ax[KT], ay[KT], bx[KT], by[KT], cx[KT], cy[KT];
 #pragma unroll
@@ -643,9 +762,9 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
     const C bv = cmake<C>(half * (zk.y + zm.y), half * (zm.x - zk.x));
     if (r == 1) {
       const size_t g0 = gofs<N>(x, y0 + 2 * m, k);
-      gz[g0] = cscale(av, (T)k);
-      gz[g0 + H] = cscale(bv, (T)k);
-    } else {
+      if (touched(2 * m)) gz[g0] = cscale(av, (T)k);
+      if (touched(2 * m + 1)) gz[g0 + H] = cscale(bv, (T)k);
+    } else if (touched(2 * m + (r == 2 ? 1 : 0))) {
       const size_t g = gofs<N>(x, y0 + 2 * m + (r == 2 ? 1 : 0), k);
       gx[g] = av;
       gy[g] = bv;
@@ -660,17 +779,35 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
 template <typename T, int N, int NT>
 __device__ __forceinline__ void
 fwd_y_body(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, const cplx_t<T>* __restrict__ gz,
-        const cplx_t<T>* __restrict__ tw, cplx_t<T>* __restrict__ s1, cplx_t<T>* __restrict__ s2, int x0) {
+        const cplx_t<T>* __restrict__ tw, const int* __restrict__ off, cplx_t<T>* __restrict__ s1,
+        cplx_t<T>* __restrict__ s2, int x0) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Row;
   using CV = ColVec<T>;
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
-  load_twiddles<T, N, NT>(twl, tw);
+  __shared__ bool touched[N];   // rows the scatter stored; the others are zero
   const int x = x0 + blockIdx.y, z0 = blockIdx.x * S::W;
+  plane_flags<N, NT>(off, x, touched);
+  load_twiddles<T, N, NT>(twl, tw);
+  __syncthreads();
+  const unsigned rows = row_bits<T, N, NT>(touched);
+  // flagged rows into LDS, zeros for the others; every load is issued
+  // before the first wait
+  typename CV::V ld[vecs_per_thread<T, N, NT>()];
+  auto load = [&](const C* g) {
+    tile_vecs<T, N, NT>([&](int e, int, int) {
+#pragma unroll
+      for (int j = 0; j < CV::K; ++j) ld[e].v[j] = cmake<C>((T)0, (T)0);
+    });
+    tile_vecs<T, N, NT>([&](int e, int y, int w) {
+      if ((rows >> e) & 1u) ld[e] = vec_load<T>(&g[gofs<N>(x, y, z0 + w)]);
+    });
+    tile_vecs<T, N, NT>([&](int e, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, ld[e]); });
+  };
   typename CV::V acc[vecs_per_thread<T, N, NT>()];
-  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, vec_load<T>(&gy[gofs<N>(x, y, z0 + w)])); });
+  load(gy);
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
   tile_vecs<T, N, NT>([&](int e, int y, int w) {
@@ -679,7 +816,7 @@ fwd_y_body(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, c
     for (int j = 0; j < CV::K; ++j) acc[e].v[j] = cscale(tile[LAY::idx(y, w + j)], ny);
   });
   __syncthreads();
-  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, vec_load<T>(&gz[gofs<N>(x, y, z0 + w)])); });
+  load(gz);
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
   tile_vecs<T, N, NT>([&](int e, int y, int w) {
@@ -689,7 +826,7 @@ fwd_y_body(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, c
     vec_store<T>(&s1[gofs<N>(x, y, z0 + w)], o);
   });
   __syncthreads();
-  tile_vecs<T, N, NT>([&](int, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, vec_load<T>(&gx[gofs<N>(x, y, z0 + w)])); });
+  load(gx);
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
   tile_vecs<T, N, NT>([&](int, int y, int w) { vec_store<T>(&s2[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, y, w)); });
@@ -743,12 +880,15 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
   __shared__ double red[NT / 64];
-  load_twiddles<T, N, NT>(twl, tw);
+  // twiddles into LDS once the first tile loads are issued
+  TwiddleStage<T, N, NT> tws;
+  tws.load(tw);
   const int y = blockIdx.y, z0 = blockIdx.x * S::W;
   const int sy = signed_freq(y, N);
   C acc[elems_per_thread<T, N, NT>()];
   if constexpr (kFromSpectra) {
     tile_vecs<T, N, NT>([&](int, int x, int w) { vec_to_lds<T, LAY>(tile, x, w, vec_load<T>(&s2[gofs<N>(x, y, z0 + w)])); });
+    tws.store(twl);
     __syncthreads();
     lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
     tile_elems<T, N, NT>([&](int e, int x, int w) { acc[e] = cscale(tile[LAY::idx(x, w)], (T)signed_freq(x, N)); });
@@ -759,6 +899,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
   } else {
     (void)s1;
     (void)s2;
+    tws.store(twl);
   }
   const double eps = MODE == kXGrad ? 0.0 : eps_ptr[0];
   const double hk = MODE == kXMid ? eps : 0.5 * eps;
@@ -894,7 +1035,7 @@ template <typename T, int N, int NT>
 __global__ void __launch_bounds__(NT) k_inv_y(Launch L, int x0) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
-  inv_y_body<T, N, NT>(k.w.a(), k.w.b(), k.w.tw(), k.w.v0(), k.w.v1(), k.w.v2(), x0);
+  inv_y_body<T, N, NT>(k.w.a(), k.w.b(), k.w.tw(), k.w.v0(), k.w.v1(), k.w.v2(), k.w.off(), x0);
 }
 
 template <typename T, int N, int NT>
@@ -915,7 +1056,7 @@ template <typename T, int N, int NT>
 __global__ void __launch_bounds__(NT) k_fwd_y(Launch L, int x0) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
-  fwd_y_body<T, N, NT>(k.w.v0(), k.w.v1(), k.w.v2(), k.w.tw(), k.w.a(), k.w.b(), x0);
+  fwd_y_body<T, N, NT>(k.w.v0(), k.w.v1(), k.w.v2(), k.w.tw(), k.w.off(), k.w.a(), k.w.b(), x0);
 }
 
 // One launch per mode present in a batch; plans in another mode return.

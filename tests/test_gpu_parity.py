@@ -141,20 +141,53 @@ def test_points_on_cell_faces_match_oracle(hl):
     plan.close()
 
 
-def test_empty_catalogue_is_prior_only(hl):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_empty_catalogue_is_prior_only(hl, precision):
     m = mocks.make_mock(16, 200.0, 5, 50.0, seed=3)
     for key in ("mu", "sigma_mu", "cz", "sigma_cz", "d_init", "d_true"):
         setattr(m, key, np.zeros(0))
     m.rhat = np.zeros((0, 3))
     prob = oracle_problem(m)
     dhat = start_modes(m)
-    say("empty fp64")
+    say("empty", precision)
     ref = model.logpost_grad(prob, dhat, np.zeros(0), 1.0)
-    plan = hl.Plan.from_mock(m, precision="fp64")
+    plan = hl.Plan.from_mock(m, precision=precision)
     psi, g, gd, gs = gpu_grad(hl, plan, dhat, np.zeros(0), 1.0)
-    assert abs(psi - ref[0]) <= TOL64 * abs(ref[0])
-    assert rel_inf(g, ref[1]) <= TOL64
+    tol_psi, tol_g = (TOL64, TOL64) if precision == "fp64" else (TOL32_PSI, TOL32_GRAD)
+    assert abs(psi - ref[0]) <= tol_psi * abs(ref[0])
+    assert rel_inf(g, ref[1]) <= tol_g
     assert gs == 0.0
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_points_in_two_cones_through_the_box_corners(hl, precision):
+    # All points in two narrow cones towards opposite corners of the box,
+    # reaching past the faces: most pencils lie outside every CIC stencil
+    # (the passes skip them), and the stencils that remain wrap across the
+    # periodic boundary in x and y.
+    m = mocks.make_mock(32, 400.0, 400, 300.0, "sphere", (0.2, 0.2), seed=47)
+    rng = np.random.default_rng(5)
+    axis = np.array([1.0, 1.0, 0.05])
+    axis /= np.linalg.norm(axis)
+    rhat = axis + 0.03 * rng.standard_normal((m.n_gal, 3))
+    rhat[1::2] *= -1.0
+    m.rhat = rhat / np.linalg.norm(rhat, axis=1)[:, None]
+    prob = oracle_problem(m)
+    dhat = start_modes(m)
+    d = m.d_true.copy()
+    pos = 0.5 * m.box + d[:, None] * m.rhat
+    assert np.any(pos[:, :2] >= m.box) and np.any(pos[:, :2] < 0.0)   # both wraps happen
+    ref = model.logpost_grad(prob, dhat, d, 1.3)
+    assert np.isfinite(ref[0])
+    say("cones", precision)
+    plan = hl.Plan.from_mock(m, precision=precision)
+    psi, g, gd, gs = gpu_grad(hl, plan, dhat, d, 1.3)
+    tol_psi, tol_g = (TOL64, TOL64) if precision == "fp64" else (TOL32_PSI, TOL32_GRAD)
+    assert abs(psi - ref[0]) <= tol_psi * abs(ref[0]), (psi, ref[0])
+    assert rel_inf(g, ref[1]) <= tol_g, rel_inf(g, ref[1])
+    assert rel_inf(gd, ref[2]) <= tol_g, rel_inf(gd, ref[2])
+    assert abs(gs - ref[3]) <= tol_g * abs(ref[3]), (gs, ref[3])
     plan.close()
 
 
