@@ -48,9 +48,9 @@ HBM_PEAK_GBS = 8000.0
 # (--copy-calibration: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  Bytes read and
 # written per launch for the plain-gradient, first, middle and last variants.
 # Valid only for the kernel sources they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "8930a12d5b86f6eb757ee66d4023ea6c0cd10ac5"
-X_TRAFFIC = {"grad": (334171872, 134217856), "first": (335669347, 670194091),
-             "mid": (468540936, 401674851), "last": (468406575, 268503947)}
+X_TRAFFIC_SOURCES_SHA1 = "2ec44c789b5a9ba24b62f9aa388338f0a9077bcb"
+X_TRAFFIC = {"grad": (334160060, 134217856), "first": (335666522, 670191294),
+             "mid": (468531066, 401674667), "last": (468399835, 268503285)}
 
 
 def kernel_sources_sha1():
@@ -90,6 +90,20 @@ def parse():
     return ap.parse_args()
 
 
+def touched_pencil_fraction(mock, d):
+    """Fraction of the real-space pencils (x, y) that some point's CIC
+    stencil reaches (columns x - ox, y - oy, ox, oy in {0, 1}, hold a point);
+    the y and z passes move only their rows."""
+    import numpy as np
+    n = mock.n_grid
+    pos = np.mod(0.5 * mock.box + d[:, None] * mock.rhat, mock.box)
+    cell = np.floor(pos[:, :2] * (n / mock.box)).astype(np.int64) % n
+    occ = np.zeros((n, n), dtype=bool)
+    occ[cell[:, 0], cell[:, 1]] = True
+    reach = occ | np.roll(occ, 1, axis=0) | np.roll(occ, 1, axis=1) | np.roll(occ, (1, 1), axis=(0, 1))
+    return float(reach.mean())
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -122,6 +136,7 @@ def main():
     # start at a posterior-typical point: the mock field, Hermitian on kz = 0
     dhat0 = mock.dhat_true[:, :, : n // 2]
     d0 = mock.d_true.copy()
+    ft = touched_pencil_fraction(mock, d0)
     s0 = 1.5
     L = args.leapfrog
     seed = mocks.config_seed(3) + 3
@@ -163,11 +178,13 @@ def main():
 
     # ---- the other passes, each timed over two more iterations -----------------
     # algorithmic bytes per launch in c (the z passes also move the points'
-    # records, a few MB); the galaxy kernels are latency-bound (time only)
-    passes = {}
+    # records, a few MB); the y and z passes move only the rows of pencils in
+    # reach of a point (fraction ft, taken at the start positions); the galaxy
+    # kernels are latency-bound (time only)
+    passes = {"touched_pencil_fraction": round(ft, 4)}
     c_bytes = 8 * n * n * (n // 2)
-    for kind, name, cs in (("inv_y", "k_inv_y", 5), ("inv_z_gather", "k_inv_z_gather", 3),
-                           ("fwd_z_scatter", "k_fwd_z_scatter", 3), ("fwd_y", "k_fwd_y", 5),
+    for kind, name, cs in (("inv_y", "k_inv_y", 2 + 3 * ft), ("inv_z_gather", "k_inv_z_gather", 3 * ft),
+                           ("fwd_z_scatter", "k_fwd_z_scatter", 3 * ft), ("fwd_y", "k_fwd_y", 3 * ft + 2),
                            ("like", "k_like", None), ("bin", "binning (4 kernels)", None)):
         timer = hamlet.KernelTimer(plan, hamlet.PROFILE_KERNELS[kind])
         q2, qd2, qs2 = (t.clone() for t in start)
@@ -179,11 +196,12 @@ def main():
         entry = {"avg_launch_ms": round(ms / launches, 4), "launches": launches}
         if cs is not None:
             gbs = cs * c_bytes / (ms / launches * 1e-3) / 1e9
-            entry.update({"bytes_per_launch": cs * c_bytes, "achieved": round(gbs, 1), "unit": "GB/s",
+            entry.update({"bytes_per_launch": int(cs * c_bytes), "achieved": round(gbs, 1), "unit": "GB/s",
                           "frac": round(gbs / HBM_PEAK_GBS, 4)})
         passes[name] = entry
         del q2, qd2, qs2
-    log("passes: " + ", ".join("%s %.4f ms" % (k, v["avg_launch_ms"]) for k, v in passes.items()))
+    log("passes: " + ", ".join("%s %.4f ms" % (k, v["avg_launch_ms"]) for k, v in passes.items()
+                               if isinstance(v, dict)))
     plan.close()
     del q, qd, qs
 

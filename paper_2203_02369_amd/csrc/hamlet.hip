@@ -208,7 +208,7 @@ static hamlet_status eval_impl(const Batch& b) {
   for (int sl = 0; sl < SL::COUNT; ++sl) {
     const int x0 = sl * SL::SIZE;
     TIMED(b, HAMLET_K_INV_Y, (k_inv_y<T, N, TH::XY><<<g_xy_slab, TH::XY, 0, st>>>(sel, x0)));
-    TIMED(b, HAMLET_K_INV_Z, (k_inv_z_gather<T, N, TH::Z><<<g_z_slab, TH::Z, 0, st>>>(sel, x0)));
+    TIMED(b, HAMLET_K_INV_Z, (k_inv_z_gather<T, N, TH::ZG><<<g_z_slab, TH::ZG, 0, st>>>(sel, x0)));
   }
   LAUNCH_CHECK();
   if (ng > 0) {
@@ -225,7 +225,7 @@ static hamlet_status eval_impl(const Batch& b) {
   if (any_empty) k_finalize<T, N><<<dim3(1, 1, nb), 256, 0, st>>>(launch_table(empty));
   for (int sl = 0; sl < SL::COUNT; ++sl) {
     const int x0 = sl * SL::SIZE;
-    TIMED(b, HAMLET_K_FWD_Z, (k_fwd_z_scatter<T, N, TH::Z><<<g_z_slab, TH::Z, 0, st>>>(sel, x0)));
+    TIMED(b, HAMLET_K_FWD_Z, (k_fwd_z_scatter<T, N, TH::ZS><<<g_z_slab, TH::ZS, 0, st>>>(sel, x0)));
     TIMED(b, HAMLET_K_FWD_Y, (k_fwd_y<T, N, TH::XY><<<g_xy_slab, TH::XY, 0, st>>>(sel, x0)));
   }
   if (batch_has(b, kXGrad))

@@ -38,7 +38,8 @@ constexpr int kPassThreads = 256;
 template <typename T, int N> struct PassThreads {
   static constexpr int XY = 256;                        // k_inv_x, k_inv_y, k_fwd_y
   static constexpr int X = sizeof(T) == 4 ? 512 : 256;   // k_x_pass
-  static constexpr int Z = sizeof(T) == 4 ? 512 : 256;   // k_inv_z_gather, k_fwd_z_scatter
+  static constexpr int ZG = 256;                         // k_inv_z_gather
+  static constexpr int ZS = 256;                         // k_fwd_z_scatter
 };
 
 // The y and z passes of each direction may run slab by slab in x so that the
@@ -59,6 +60,10 @@ template <typename T, int N> struct PassShape {
   static constexpr int CHUNKS = H / W;
   static constexpr int ELEMS = N * W;
   static constexpr int F = 3 * P / 2;                       // complex transforms per z tile
+  // pencils per round of the scatter's dense path (its LDS buffer holds
+  // 3 PC / 2 transforms)
+  static constexpr int PCMAX = 4;
+  static constexpr int PC = PCMAX < P ? PCMAX : P;
   using Row = RowLayout<C, W>;
   using Pen = PencilLayout<N>;
 };
@@ -552,8 +557,10 @@ __device__ __forceinline__ int stage_index(const int* start, const int* at, int 
 //    few nonzero nodes, so each output coefficient is summed directly over
 //    the points of the pencil's four stencil columns (corner by corner, in
 //    binned order) instead of building the pencil and transforming it.
-//  * Crowded grids: each real pencil is built in LDS and transformed.  The
-//    points of a column are sorted by z cell, so the
+//  * Crowded grids: each real pencil is built in LDS and transformed, a few
+//    pencil pairs a round (a small buffer keeps more tiles resident on a
+//    compute unit for the sparse case).  The points of a column are sorted
+//    by z cell, so the
 //    points that reach node j are two runs per stencil column (z cell j - 1
 //    with weight tz, then z cell j with weight 1 - tz); G lanes share each
 //    (pencil, component) row, lane l owning the nodes of one z segment, and
@@ -569,12 +576,13 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Pen;
-  constexpr int P = S::P, H = S::H, F = S::F;
-  constexpr int GMAX_T = NT / (3 * P) >= 16 ? 16 : (NT / (3 * P) >= 8 ? 8 : (NT / (3 * P) >= 4 ? 4 : 1));
+  constexpr int P = S::P, H = S::H, PC = S::PC, FC = 3 * PC / 2;
+  static_assert(P % PC == 0 && PC % 2 == 0, "rounds of whole pencil pairs");
+  constexpr int GMAX_T = NT / (3 * PC) >= 16 ? 16 : (NT / (3 * PC) >= 8 ? 8 : (NT / (3 * PC) >= 4 ? 4 : 1));
   constexpr int GMAX = GMAX_T < N ? GMAX_T : N;
   // stage capacity (points); the FP64 path keeps its LDS small for occupancy
   constexpr int CAP = sizeof(T) == 4 ? 256 : 32;
-  __shared__ C buf[LAY::size(F)];
+  __shared__ C buf[LAY::size(FC)];
   __shared__ C twl[N];
   __shared__ int col[4 * P][2];     // binned range of the 4 stencil columns of each pencil
   __shared__ ZStage<T, CAP> stg;
@@ -706,69 +714,75 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
     }
     return;
   }
-  // Dense tiles: pencils built in LDS and transformed.
-  for (int i = threadIdx.x; i < LAY::size(F); i += NT) buf[i] = cmake<C>((T)0, (T)0);
-  __syncthreads();
+  // Dense tiles: pencils built in LDS and transformed, PC pencils (FC
+  // transforms) a round; rounds with no pencil in reach are skipped.
   T* row = reinterpret_cast<T*>(buf);
-  if (threadIdx.x < 3 * P * G) {
-    const int lane = threadIdx.x % G, pc = threadIdx.x / G;
-    const int p = pc / 3, c = pc % 3;
-    const int seg = N / G, za = lane * seg, zb = za + seg;
-    const int zl = (za - 1) & (N - 1);
-    const int f = zslot_f(p, c), part = zslot_part(p, c);
-    const T* rcs = c == 0 ? bins.rx : (c == 1 ? bins.ry : bins.rz);
-    for (int corner = 0; corner < 4; ++corner) {
-      const int s0 = col[4 * p + corner][0], s1 = col[4 * p + corner][1];
-      if (s0 == s1) continue;
-      const int ox = corner >> 1, oy = corner & 1;
-      // the run of z cell za - 1 puts its upper weight on node za; cells
-      // za .. zb - 1 put their lower weight on node z and their upper weight
-      // on node z + 1 inside the segment
-      auto scatter = [&](auto g_, auto tx_, auto ty_, auto tz_, auto r_, auto iz_, int lo, int hi) {
-        auto value = [&](int s) {
-          const T tx = tx_[s], ty = ty_[s];
-          const T wxy = (ox ? tx : (T)1 - tx) * (oy ? ty : (T)1 - ty);
-          return g_[s] * wxy * r_[s];
+  for (int p0 = 0; p0 < P; p0 += PC) {
+    if (((tp >> p0) & ((1u << PC) - 1u)) == 0u) continue;   // block-uniform
+    const int f0 = 3 * p0 / 2;
+    for (int i = threadIdx.x; i < LAY::size(FC); i += NT) buf[i] = cmake<C>((T)0, (T)0);
+    __syncthreads();
+    if (threadIdx.x < 3 * PC * G) {
+      const int lane = threadIdx.x % G, pc = threadIdx.x / G;
+      const int p = p0 + pc / 3, c = pc % 3;
+      const int seg = N / G, za = lane * seg, zb = za + seg;
+      const int zl = (za - 1) & (N - 1);
+      const int f = zslot_f(p, c) - f0, part = zslot_part(p, c);
+      const T* rcs = c == 0 ? bins.rx : (c == 1 ? bins.ry : bins.rz);
+      for (int corner = 0; corner < 4; ++corner) {
+        const int s0 = col[4 * p + corner][0], s1 = col[4 * p + corner][1];
+        if (s0 == s1) continue;
+        const int ox = corner >> 1, oy = corner & 1;
+        // the run of z cell za - 1 puts its upper weight on node za; cells
+        // za .. zb - 1 put their lower weight on node z and their upper
+        // weight on node z + 1 inside the segment
+        auto scatter = [&](auto g_, auto tx_, auto ty_, auto tz_, auto r_, auto iz_, int lo, int hi) {
+          auto value = [&](int s) {
+            const T tx = tx_[s], ty = ty_[s];
+            const T wxy = (ox ? tx : (T)1 - tx) * (oy ? ty : (T)1 - ty);
+            return g_[s] * wxy * r_[s];
+          };
+          for (int s = lower_bound_cell(iz_, lo, hi, zl); s < hi && (int)iz_[s] == zl; ++s)
+            row[2 * LAY::idx(za, f) + part] += value(s) * tz_[s];
+          for (int s = lower_bound_cell(iz_, lo, hi, za); s < hi && (int)iz_[s] < zb; ++s) {
+            const int z = iz_[s];
+            const T v = value(s), tz = tz_[s];
+            row[2 * LAY::idx(z, f) + part] += v * ((T)1 - tz);
+            if (z + 1 < zb) row[2 * LAY::idx(z + 1, f) + part] += v * tz;
+          }
         };
-        for (int s = lower_bound_cell(iz_, lo, hi, zl); s < hi && (int)iz_[s] == zl; ++s)
-          row[2 * LAY::idx(za, f) + part] += value(s) * tz_[s];
-        for (int s = lower_bound_cell(iz_, lo, hi, za); s < hi && (int)iz_[s] < zb; ++s) {
-          const int z = iz_[s];
-          const T v = value(s), tz = tz_[s];
-          row[2 * LAY::idx(z, f) + part] += v * ((T)1 - tz);
-          if (z + 1 < zb) row[2 * LAY::idx(z + 1, f) + part] += v * tz;
+        if (staged) {
+          const bool wrap_row = y0 == 0 && p - oy < 0;
+          const int lo = stage_index(stg.start, stg.at, s0, ox, wrap_row);
+          scatter(stg.g, stg.tx, stg.ty, stg.tz, stg.r[c], stg.iz, lo, lo + (s1 - s0));
+        } else {
+          scatter(gsort, bins.tx, bins.ty, bins.tz, rcs, bins.iz, s0, s1);
         }
-      };
-      if (staged) {
-        const bool wrap_row = y0 == 0 && p - oy < 0;
-        const int lo = stage_index(stg.start, stg.at, s0, ox, wrap_row);
-        scatter(stg.g, stg.tx, stg.ty, stg.tz, stg.r[c], stg.iz, lo, lo + (s1 - s0));
-      } else {
-        scatter(gsort, bins.tx, bins.ty, bins.tz, rcs, bins.iz, s0, s1);
       }
     }
-  }
-  __syncthreads();
-  lds_fft<T, N, F, LAY, NT, -1>(buf, twl);
-  // Split each transform Z of a + i b into the half spectra
-  //   A_k = (Z_k + conj Z_{N-k}) / 2,   B_k = (Z_k - conj Z_{N-k}) / (2 i).
-  for (int idx = threadIdx.x; idx < F * H; idx += NT) {
-    const int k = idx % H, f = idx / H;
-    const int m = f / 3, r = f % 3;
-    const C zk = buf[LAY::idx(k, f)];
-    const C zm = buf[LAY::idx((N - k) & (N - 1), f)];
-    const T half = (T)0.5;
-    const C av = cmake<C>(half * (zk.x + zm.x), half * (zk.y - zm.y));
-    const C bv = cmake<C>(half * (zk.y + zm.y), half * (zm.x - zk.x));
-    if (r == 1) {
-      const size_t g0 = gofs<N>(x, y0 + 2 * m, k);
-      if (touched(2 * m)) gz[g0] = cscale(av, (T)k);
-      if (touched(2 * m + 1)) gz[g0 + H] = cscale(bv, (T)k);
-    } else if (touched(2 * m + (r == 2 ? 1 : 0))) {
-      const size_t g = gofs<N>(x, y0 + 2 * m + (r == 2 ? 1 : 0), k);
-      gx[g] = av;
-      gy[g] = bv;
+    __syncthreads();
+    lds_fft<T, N, FC, LAY, NT, -1>(buf, twl);
+    // Split each transform Z of a + i b into the half spectra
+    //   A_k = (Z_k + conj Z_{N-k}) / 2,   B_k = (Z_k - conj Z_{N-k}) / (2 i).
+    for (int idx = threadIdx.x; idx < FC * H; idx += NT) {
+      const int k = idx % H, fl = idx / H;
+      const int m = (f0 + fl) / 3, r = (f0 + fl) % 3;
+      const C zk = buf[LAY::idx(k, fl)];
+      const C zm = buf[LAY::idx((N - k) & (N - 1), fl)];
+      const T half = (T)0.5;
+      const C av = cmake<C>(half * (zk.x + zm.x), half * (zk.y - zm.y));
+      const C bv = cmake<C>(half * (zk.y + zm.y), half * (zm.x - zk.x));
+      if (r == 1) {
+        const size_t g0 = gofs<N>(x, y0 + 2 * m, k);
+        if (touched(2 * m)) gz[g0] = cscale(av, (T)k);
+        if (touched(2 * m + 1)) gz[g0 + H] = cscale(bv, (T)k);
+      } else if (touched(2 * m + (r == 2 ? 1 : 0))) {
+        const size_t g = gofs<N>(x, y0 + 2 * m + (r == 2 ? 1 : 0), k);
+        gx[g] = av;
+        gy[g] = bv;
+      }
     }
+    __syncthreads();   // the next round reuses the buffer
   }
 }
 
