@@ -1,0 +1,105 @@
+"""Oracle of the monopole and dipole moments of the velocity field in spheres
+about the observer (Section 5, "Monopole and dipole").
+
+TEST INFRASTRUCTURE ONLY.  Plain FP64 numpy written from the definitions;
+only the test suite, the smoke check and the CPU baseline leg of the
+benchmark may import it.
+
+For a sphere of radius R centred on the observer o = (L/2)(1, 1, 1):
+  * the monopole M(R) is the volume mean of -div v / H0 over the ball
+    (the paper scales by H0 so that it follows the mean linear overdensity:
+    with the velocity operator of model.velocity_multiplier, -div v / H0 is
+    f delta);
+  * the dipole D(R) is the volume mean of v over the ball: the bulk velocity
+    of the sphere, in km/s.
+
+Readings (also in the design notes):
+  * The field between grid nodes is the band-limited (trigonometric)
+    interpolant of the retained modes, v_c(x) = N^-3 sum_k m_c(k) dhat_k
+    exp(i k.x) over all N^3 modes; on the nodes it is model.velocity_grids.
+    The paper averages over grid cells; the continuous mean of the
+    interpolant is the limit of that average for fine cells and has no
+    dependence on how cells straddle the sphere.
+  * The ball mean of a plane wave exp(i k.x) is exp(i k.o) W(|k| R) with the
+    top-hat window W(y) = 3 (sin y - y cos y) / y^3, W(0) = 1.  Hence
+        M(R)   = N^-3 sum_k (-i k.m(k) / H0) dhat_k exp(i k.o) W(|k| R),
+        D_c(R) = N^-3 sum_k m_c(k) dhat_k exp(i k.o) W(|k| R),
+    summed over the full spectrum (model.full_spectrum), real by Hermitian
+    symmetry.
+"""
+import math
+
+import numpy as np
+
+from . import model
+
+
+def tophat_window(y):
+    """W(y) = 3 (sin y - y cos y) / y^3.  Below |y| = 1/2, where the closed
+    form cancels, its Taylor series sum_m (-1)^m 3 (2m + 2) y^(2m) / (2m + 3)!
+    to m = 7 (next term below 1e-17)."""
+    y = np.asarray(y, dtype=np.float64)
+    small = np.abs(y) < 0.5
+    ys = np.where(small, 1.0, y)
+    exact = 3.0 * (np.sin(ys) - ys * np.cos(ys)) / ys ** 3
+    y2 = y * y
+    series = np.zeros_like(y)
+    for m in range(7, -1, -1):
+        series = series * y2 + (-1) ** m * 3.0 * (2 * m + 2) / math.factorial(2 * m + 3)
+    return np.where(small, series, exact)
+
+
+def _full_grid_modes(prob):
+    """Signed wave vectors and the retained mask over all N^3 modes."""
+    n = prob.n_grid
+    s = model.signed_index(n)
+    nx, ny, nz = np.meshgrid(s, s, s, indexing="ij")
+    half = n // 2
+    keep = ~((np.abs(nx) == half) | (np.abs(ny) == half) | (np.abs(nz) == half) | ((nx == 0) & (ny == 0) & (nz == 0)))
+    kf = 2.0 * math.pi / prob.box
+    return (kf * nx, kf * ny, kf * nz), keep
+
+
+def sphere_moments(prob, dhat, radii):
+    """(M, D) for each radius: arrays (n_R,) and (n_R, 3).
+
+    dhat: half spectrum (N, N, N/2 + 1) complex, as everywhere in the oracle.
+    """
+    n = prob.n_grid
+    kvec, keep = _full_grid_modes(prob)
+    k2 = kvec[0] ** 2 + kvec[1] ** 2 + kvec[2] ** 2
+    safe = np.where(keep, k2, 1.0)
+    amp = model.H0 * prob.f_growth
+    m = [np.where(keep, 1j * amp * kc / safe, 0.0) for kc in kvec]       # m_c(k), eq:vel-field
+    div = -1j * (kvec[0] * m[0] + kvec[1] * m[1] + kvec[2] * m[2]) / model.H0
+    full = model.full_spectrum(dhat)
+    o = 0.5 * prob.box
+    phase = np.exp(1j * (kvec[0] * o + kvec[1] * o + kvec[2] * o))
+    kmag = np.sqrt(k2)
+    norm = 1.0 / float(n) ** 3
+    mono, dip = [], []
+    for r in radii:
+        w = tophat_window(kmag * r)
+        base = full * phase * w
+        mono.append(norm * np.sum(div * base).real)
+        dip.append([norm * np.sum(mc * base).real for mc in m])
+    return np.array(mono), np.array(dip)
+
+
+def sphere_moments_abs(prob, dhat, radii):
+    """Sum of the absolute values of the terms of sphere_moments, per
+    quantity: the scale of its rounding error (shape (n_R, 4))."""
+    n = prob.n_grid
+    kvec, keep = _full_grid_modes(prob)
+    k2 = kvec[0] ** 2 + kvec[1] ** 2 + kvec[2] ** 2
+    safe = np.where(keep, k2, 1.0)
+    amp = model.H0 * prob.f_growth
+    m = [np.where(keep, amp * np.abs(kc) / safe, 0.0) for kc in kvec]
+    full = np.abs(model.full_spectrum(dhat))
+    kmag = np.sqrt(k2)
+    norm = 1.0 / float(n) ** 3
+    out = []
+    for r in radii:
+        w = np.abs(tophat_window(kmag * r))
+        out.append([norm * np.sum(prob.f_growth * keep * full * w)] + [norm * np.sum(mc * full * w) for mc in m])
+    return np.array(out)

@@ -1,0 +1,125 @@
+"""Pins of the oracle's sphere moments (Section 5, "Monopole and dipole")
+against values fixed independently of its k-space sums: the field at the
+observer node, quadrature of the band-limited field over the ball, the
+window's own integral, and a single mode in closed form."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import analysis, hmc, model
+from paper_2203_02369_amd import mocks
+
+from helpers import oracle_problem
+
+
+def _problem(n, box, seed):
+    m = mocks.make_mock(n, box, 20, 0.3 * box, "sphere", (0.2, 0.2), seed=seed)
+    prob = oracle_problem(m)
+    rng = np.random.default_rng(seed)
+    shape = model.half_shape(n)
+    dhat = hmc.symmetrise(n, rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+    return prob, dhat
+
+
+def test_window_is_the_ball_mean_of_a_plane_wave():
+    # (3 / R^3) int_0^R j0(k r) r^2 dr by Gauss-Legendre, against W(kR)
+    x, w = np.polynomial.legendre.leggauss(40)
+    for kr in (1e-6, 5e-3, 0.02, 0.7, 3.0, 9.5, 21.0):
+        r = 0.5 * (x + 1.0)                     # R = 1
+        j0 = np.sin(kr * r) / (kr * r)
+        quad = 3.0 * np.sum(0.5 * w * j0 * r * r)
+        assert abs(analysis.tophat_window(kr) - quad) <= 1e-13, kr
+    assert analysis.tophat_window(0.0) == 1.0
+
+
+def test_vanishing_radius_gives_the_field_at_the_observer():
+    n = 8
+    prob, dhat = _problem(n, 100.0, 3)
+    mono, dip = analysis.sphere_moments(prob, dhat, [1e-9])
+    v = model.velocity_grids(prob, dhat)
+    c = n // 2                                     # o = (L/2)(1,1,1) is node N/2
+    assert np.allclose(dip[0], v[:, c, c, c], rtol=1e-12, atol=1e-12 * np.abs(v).max())
+    delta = np.fft.ifftn(model.full_spectrum(dhat)).real   # N^-3 sum_k dhat e^{ik.x}
+    assert abs(mono[0] - prob.f_growth * delta[c, c, c]) <= 1e-12 * np.abs(delta).max()
+
+
+def _ball_quadrature(prob, full, mult, radius):
+    """Ball means of N^-3 sum_k a_k e^{ik.x} by a product rule in (r, mu, phi)."""
+    n = prob.n_grid
+    s = model.signed_index(n)
+    nx, ny, nz = np.meshgrid(s, s, s, indexing="ij")
+    kf = 2.0 * math.pi / prob.box
+    kx, ky, kz = (kf * a.reshape(-1) for a in (nx, ny, nz))
+    xr, wr = np.polynomial.legendre.leggauss(24)
+    r = 0.5 * radius * (xr + 1.0)
+    wr = 0.5 * radius * wr * r * r
+    mu, wmu = np.polynomial.legendre.leggauss(24)
+    nphi = 48
+    phi = 2.0 * math.pi * np.arange(nphi) / nphi
+    R, MU, PHI = np.meshgrid(r, mu, phi, indexing="ij")
+    W = (wr[:, None, None] * wmu[None, :, None] * np.full(nphi, 2.0 * math.pi / nphi)[None, None, :]).reshape(-1)
+    st = np.sqrt(1.0 - MU * MU)
+    o = 0.5 * prob.box
+    px = (o + R * st * np.cos(PHI)).reshape(-1)
+    py = (o + R * st * np.sin(PHI)).reshape(-1)
+    pz = (o + R * MU).reshape(-1)
+    vol = 4.0 / 3.0 * math.pi * radius ** 3
+    out = []
+    for a in mult:
+        coef = (a * full).reshape(-1) / float(n) ** 3
+        acc = 0.0
+        for i0 in range(0, len(px), 4096):
+            ph = np.exp(1j * (np.outer(px[i0:i0 + 4096], kx) + np.outer(py[i0:i0 + 4096], ky)
+                              + np.outer(pz[i0:i0 + 4096], kz)))
+            acc += np.sum(W[i0:i0 + 4096] * (ph @ coef).real)
+        out.append(acc / vol)
+    return np.array(out)
+
+
+def test_ball_means_match_quadrature_of_the_band_limited_field():
+    n = 8
+    prob, dhat = _problem(n, 100.0, 5)
+    full = model.full_spectrum(dhat)
+    # m_c(k) on the full grid from the half-spectrum multiplier's own formula
+    s = model.signed_index(n)
+    nx, ny, nz = np.meshgrid(s, s, s, indexing="ij")
+    kf = 2.0 * math.pi / prob.box
+    k2 = (kf * kf) * (nx * nx + ny * ny + nz * nz)
+    half = n // 2
+    keep = ~((np.abs(nx) == half) | (np.abs(ny) == half) | (np.abs(nz) == half) | (k2 == 0))
+    amp = model.H0 * prob.f_growth
+    mult = [np.where(keep, 1j * amp * kf * a / np.where(keep, k2, 1.0), 0.0) for a in (nx, ny, nz)]
+    radii = [6.0, 17.0, 33.0]
+    mono, dip = analysis.sphere_moments(prob, dhat, radii)
+    for j, r in enumerate(radii):
+        qv = _ball_quadrature(prob, full, mult, r)
+        qd = _ball_quadrature(prob, full, [np.ones_like(full)], r)[0]   # mean density contrast
+        scale = np.abs(qv).max()
+        assert np.abs(dip[j] - qv).max() <= 1e-10 * scale, (r, dip[j], qv)
+        # -div v / H0 = f delta for the linear velocity field
+        assert abs(mono[j] - prob.f_growth * qd) <= 1e-10 * max(abs(qd), 1e-3), (r, mono[j], qd)
+
+
+@pytest.mark.parametrize("mode", [(1, 0, 0), (0, 0, 2)])
+def test_single_mode_in_closed_form(mode):
+    n = 16
+    prob, _ = _problem(n, 200.0, 7)
+    dhat = np.zeros(model.half_shape(n), dtype=np.complex128)
+    a = 0.3 - 1.7j
+    dhat[mode[0] % n, mode[1] % n, mode[2]] = a
+    if mode[2] == 0:
+        dhat[(-mode[0]) % n, (-mode[1]) % n, 0] = np.conj(a)
+    kf = 2.0 * math.pi / prob.box
+    kvec = kf * np.array(mode, dtype=float)
+    k = np.linalg.norm(kvec)
+    sign = (-1.0) ** sum(mode)                      # e^{i k.o}, o = (L/2)(1,1,1)
+    radii = [5.0, 40.0]
+    mono, dip = analysis.sphere_moments(prob, dhat, radii)
+    for j, r in enumerate(radii):
+        w = analysis.tophat_window(k * r)
+        # the pair k, -k: N^-3 (a e^{ik.o} + conj(a) e^{-ik.o}) times each factor
+        m_ref = 2.0 * sign * prob.f_growth * a.real * w / n ** 3
+        d_ref = -2.0 * sign * model.H0 * prob.f_growth * a.imag * w * kvec / (k * k) / n ** 3
+        assert abs(mono[j] - m_ref) <= 1e-13 * abs(m_ref)
+        assert np.allclose(dip[j], d_ref, rtol=1e-13, atol=1e-13 * np.abs(d_ref).max())
