@@ -202,6 +202,24 @@ def main():
         del q2, qd2, qs2
     log("passes: " + ", ".join("%s %.4f ms" % (k, v["avg_launch_ms"]) for k, v in passes.items()
                                if isinstance(v, dict)))
+
+    # ---- analysis of a state: sphere moments of the velocity field --------------
+    # (monopole and dipole in 16 spheres, four passes over the FP64 modes; the
+    # FP64 window per mode and radius bounds it, not the mode reads)
+    radii = [5.0 + 15.0 * j for j in range(16)]
+    hamlet.sphere_moments(plan, q, radii)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(plan.stream)
+    for _ in range(5):
+        hamlet.sphere_moments(plan, q, radii)
+    ev1.record(plan.stream)
+    ev1.synchronize()
+    mom_ms = ev0.elapsed_time(ev1) / 5
+    mom_bytes = 4 * 16 * n * n * (n // 2)
+    analysis = {"sphere_moments": {"radii": len(radii), "avg_call_ms": round(mom_ms, 4), "mode_passes": 4,
+                                   "mode_bytes_per_call": mom_bytes,
+                                   "mode_read_GBs": round(mom_bytes / (mom_ms * 1e-3) / 1e9, 1)}}
+    log("sphere moments (16 radii): %.3f ms per call" % mom_ms)
     plan.close()
     del q, qd, qs
 
@@ -293,6 +311,7 @@ def main():
         "fp64_path": fp64,
         "roofline": roofline,
         "passes": passes,
+        "analysis": analysis,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -215,6 +215,32 @@ hamlet_status hamlet_pack_flat(hamlet_plan* plan, const void* modes, const doubl
  * plan's stream. */
 hamlet_status hamlet_unpack_flat(hamlet_plan* plan, const double* flat, void* modes, double* dist, double* snl);
 
+/* ---- Sphere moments of the velocity field ----
+ *
+ * Section 5 (monopole and dipole) follows the reconstruction by the moments
+ * of the linear velocity field in spheres of radius R about the observer
+ * o = (L/2)(1, 1, 1): the monopole M(R), the mean of -div v / H0 over the
+ * ball (f times the mean density contrast within R), and the dipole D(R),
+ * the mean of v over the ball (the bulk velocity of the sphere, km/s).  The
+ * field between grid nodes is the band-limited field of the modes (on the
+ * nodes it is the velocity field of the evaluation); each mode contributes
+ * through the top-hat window W(|k| R) = 3 (sin y - y cos y) / y^3, y = |k| R.
+ *
+ * modes (device): N x N x N/2 complex128, a state of the chain (e.g. a
+ *   sample, or the mode sum of hamlet_hmc_run divided by its count).
+ * radii (host): n_radii radii in Mpc/h, each positive and finite;
+ *   0 <= n_radii <= 16.
+ * out (device): 4 n_radii doubles (may be NULL when n_radii = 0);
+ *   out[4 j] = M(R_j), out[4 j + 1 + c] the component c (x, y, z) of D(R_j).
+ * Computed in FP64 for both precisions; the sums run in a fixed order, so a
+ * rerun gives the same bits.  Uses the plan's scratch for its partial sums:
+ * calls on one plan are ordered by its stream like every other call.
+ * Errors: HAMLET_EINVAL for NULL buffers, a count outside [0, 16] or a radius
+ * that is not positive and finite (nothing is enqueued).  Asynchronous on the
+ * plan's stream. */
+hamlet_status hamlet_sphere_moments(hamlet_plan* plan, const void* modes, const double* radii, int32_t n_radii,
+                                    double* out);
+
 /* ---- Serving: continuous batching of independent reconstruction jobs ----
  *
  * A server runs many chains (jobs) on one device.  Jobs are queued with

@@ -11,7 +11,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libhamlet.so")
 SOURCES = [os.path.join(PKG, "csrc", "hamlet.hip")]
-HEADERS = ["common.hpp", "fft.hpp", "workspace.hpp", "random.hpp", "flat.hpp", "passes.hpp", "galaxies.hpp", "hmc.hpp"]
+HEADERS = ["common.hpp", "fft.hpp", "workspace.hpp", "random.hpp", "flat.hpp", "passes.hpp", "galaxies.hpp", "hmc.hpp",
+           "analysis.hpp"]
 
 ARCH = "gfx950"
 FLAGS = [

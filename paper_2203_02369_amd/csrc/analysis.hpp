@@ -1,0 +1,106 @@
+// Monopole and dipole moments of the linear velocity field in spheres about
+// the observer (Section 5, monopole and dipole): for a ball of radius R
+// centred on o = (L/2)(1, 1, 1),
+//   M(R) = ball mean of -div v / H0   (= f times the mean density contrast),
+//   D(R) = ball mean of v             (the bulk velocity, km/s),
+// of the band-limited field of the modes.  A plane wave exp(i k.x) averages
+// to exp(i k.o) W(|k| R) over the ball, W(y) = 3 (sin y - y cos y) / y^3, and
+// exp(i k.o) = (-1)^(nx + ny + nz) at this observer, so with the velocity
+// multiplier i H0 f k / k^2 and the pair weight w (1 on the kz = 0 plane,
+// whose Hermitian partners are both stored, 2 elsewhere):
+//   M(R)   = sum_stored w (-1)^(n) (f / N^3) Re q_k W(|k| R),
+//   D_c(R) = sum_stored w (-1)^(n) (-H0 f / (N^3 k_f)) (n_c / n^2) Im q_k W(|k| R).
+// One pass over the stored modes handles kMomentsRadiiPerPass radii (their
+// sums stay in registers); every block writes its partial sums, and a second
+// kernel adds them in block order, so the result does not depend on timing.
+// FP64 throughout: the modes are the FP64 masters in both precisions.
+#pragma once
+
+#include "common.hpp"
+#include "passes.hpp"
+#include "workspace.hpp"
+
+namespace hamlet {
+
+struct MomentRadii {
+  double r[kMomentsRadiiPerPass];
+  int count;
+};
+
+// Coefficient m of the Taylor series of the window,
+// W(y) = sum_m (-1)^m 3 (2m + 2) y^(2m) / (2m + 3)!.
+__host__ __device__ constexpr double tophat_coefficient(int m) {
+  double fact = 1.0;
+  for (int i = 2; i <= 2 * m + 3; ++i) fact *= i;
+  return (m % 2 ? -3.0 : 3.0) * (2 * m + 2) / fact;
+}
+
+// W(y); below |y| = 1/2, where sin y - y cos y cancels, the series to m = 7
+// (the first term left out is below 1e-17 there).
+__device__ __forceinline__ double tophat_window(double y) {
+  if (fabs(y) < 0.5) {
+    const double y2 = y * y;
+    double acc = tophat_coefficient(7);
+#pragma unroll
+    for (int m = 6; m >= 0; --m) acc = acc * y2 + tophat_coefficient(m);
+    return acc;
+  }
+  double s, c;
+  sincos(y, &s, &c);
+  return 3.0 * (s - y * c) / (y * y * y);
+}
+
+// One pass: partial sums of (M, Dx, Dy, Dz) for each radius of rad, per
+// block, into part[block * kMomentsPassValues + 4 j + c].
+template <int N>
+__global__ void __launch_bounds__(256)
+k_sphere_moments(const double2* __restrict__ modes, MomentRadii rad, double kf, double mono_scale,
+                 double dip_scale, double* __restrict__ part) {
+  __shared__ double red[kMomentsPassValues * (256 / 64)];
+  constexpr int H = N / 2;
+  constexpr size_t total = (size_t)N * N * H;
+  double acc[kMomentsPassValues];
+#pragma unroll
+  for (int i = 0; i < kMomentsPassValues; ++i) acc[i] = 0.0;
+  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (size_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(g % H), y = (int)((g / H) % N), x = (int)(g / ((size_t)H * N));
+    const int sx = signed_freq(x, N), sy = signed_freq(y, N);
+    if (!retained(sx, sy, kz, N)) continue;
+    const double2 q = modes[g];
+    const int n2 = sx * sx + sy * sy + kz * kz;
+    const double w = (kz == 0 ? 1.0 : 2.0) * (((sx + sy + kz) & 1) ? -1.0 : 1.0);
+    const double a = w * mono_scale * q.x;
+    const double b = -w * dip_scale * q.y / (double)n2;
+    const double kmag = kf * sqrt((double)n2);
+#pragma unroll
+    for (int j = 0; j < kMomentsRadiiPerPass; ++j) {
+      if (j < rad.count) {
+        const double wr = tophat_window(kmag * rad.r[j]);
+        acc[4 * j + 0] += a * wr;
+        acc[4 * j + 1] += b * sx * wr;
+        acc[4 * j + 2] += b * sy * wr;
+        acc[4 * j + 3] += b * kz * wr;
+      }
+    }
+  }
+  block_sums<kMomentsPassValues>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kMomentsPassValues; ++i) part[(size_t)blockIdx.x * kMomentsPassValues + i] = acc[i];
+  }
+}
+
+// out[t] = the sum over the blocks of a pass of value t, in a fixed order:
+// one block per output value, t = 4 j + c over all radii of the call.
+__global__ void __launch_bounds__(256) k_sphere_moments_sum(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double red[256 / 64];
+  const int t = blockIdx.x;
+  const int pass = t / kMomentsPassValues, i = t % kMomentsPassValues;
+  const double* p = part + (size_t)pass * kMomentsBlocks * kMomentsPassValues + i;
+  double s[1] = {0.0};
+  for (int b = threadIdx.x; b < kMomentsBlocks; b += blockDim.x) s[0] += p[(size_t)b * kMomentsPassValues];
+  block_sums<1>(s, red);
+  if (threadIdx.x == 0) out[t] = s[0];
+}
+
+}  // namespace hamlet

@@ -17,6 +17,7 @@
 #include "hamlet.h"
 #include "common.hpp"
 #include "fft.hpp"
+#include "analysis.hpp"
 #include "flat.hpp"
 #include "passes.hpp"
 #include "galaxies.hpp"
@@ -90,7 +91,7 @@ struct hamlet_plan {
   // workspace addresses used by the host
   PlanConst* consts = nullptr;
   ChainScalars* cs = nullptr;
-  double *var = nullptr, *mvar = nullptr, *hist = nullptr;
+  double *var = nullptr, *mvar = nullptr, *hist = nullptr, *mom_part = nullptr;
   void* tw = nullptr;
   double *rhat = nullptr, *mu = nullptr, *smu = nullptr, *cz = nullptr, *scz = nullptr;
   int *count = nullptr, *off = nullptr, *most = nullptr;
@@ -328,6 +329,7 @@ template <typename T, int N> static void locate_impl(hamlet_plan* pl) {
   pl->cs = w.template at<ChainScalars>(F::chain);
   pl->var = w.var_n2();
   pl->mvar = w.mvar();
+  pl->mom_part = w.template at<double>(F::mom_part);
   pl->hist = w.hist(pl->n_gal);
   pl->tw = w.tw();
   pl->rhat = w.rhat(); pl->mu = w.mu(); pl->smu = w.smu(); pl->cz = w.cz(); pl->scz = w.scz();
@@ -1016,6 +1018,48 @@ extern "C" hamlet_status hamlet_unpack_flat(hamlet_plan* plan, const double* fla
   if (plan->n_gal > 0 && !dist) return fail(HAMLET_EINVAL, "NULL distance buffer");
   k_unpack_flat<<<flat_blocks(plan), 256, 0, plan->stream>>>(flat, (double2*)modes, dist, snl, plan->n,
                                                              plan->n_gal);
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Sphere moments of the velocity field (Section 5, monopole and dipole)
+// ---------------------------------------------------------------------------
+template <int N>
+static void moments_pass(const hamlet_plan* pl, const double2* modes, const MomentRadii& rad, double kf,
+                         double mono_scale, double dip_scale, double* part) {
+  k_sphere_moments<N><<<kMomentsBlocks, 256, 0, pl->stream>>>(modes, rad, kf, mono_scale, dip_scale, part);
+}
+
+extern "C" hamlet_status hamlet_sphere_moments(hamlet_plan* plan, const void* modes, const double* radii,
+                                               int32_t n_radii, double* out) {
+  if (!plan || !modes || (n_radii > 0 && (!radii || !out))) return fail(HAMLET_EINVAL, "NULL argument");
+  if (n_radii < 0 || n_radii > kMomentsMaxRadii)
+    return fail(HAMLET_EINVAL, "n_radii %d outside [0, %d]", (int)n_radii, kMomentsMaxRadii);
+  for (int j = 0; j < n_radii; ++j)
+    if (!(radii[j] > 0.0) || !std::isfinite(radii[j]))
+      return fail(HAMLET_EINVAL, "radius %d (%g) is not positive and finite", j, radii[j]);
+  if (n_radii == 0) return HAMLET_OK;
+  const double kf = 2.0 * M_PI / plan->box;
+  const double n3 = (double)plan->n * plan->n * plan->n;
+  const double mono_scale = plan->f / n3;             // f / N^3
+  const double dip_scale = kH0 * plan->f / (n3 * kf);  // H0 f / (N^3 k_f)
+  for (int j0 = 0; j0 < n_radii; j0 += kMomentsRadiiPerPass) {
+    MomentRadii rad{};
+    rad.count = std::min(kMomentsRadiiPerPass, n_radii - j0);
+    for (int j = 0; j < rad.count; ++j) rad.r[j] = radii[j0 + j];
+    double* part = plan->mom_part + (size_t)(j0 / kMomentsRadiiPerPass) * kMomentsBlocks * kMomentsPassValues;
+    const double2* q = (const double2*)modes;
+    switch (plan->n) {
+      case 16: moments_pass<16>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
+      case 32: moments_pass<32>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
+      case 64: moments_pass<64>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
+      case 128: moments_pass<128>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
+      case 256: moments_pass<256>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
+      default: return fail(HAMLET_EUNSUPPORTED, "grid size %d", plan->n);
+    }
+  }
+  k_sphere_moments_sum<<<4 * n_radii, 256, 0, plan->stream>>>(plan->mom_part, out);
   LAUNCH_CHECK();
   return HAMLET_OK;
 }

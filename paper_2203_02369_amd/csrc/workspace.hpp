@@ -69,6 +69,16 @@ struct Launch {
 constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Offsets of the arrays whose size depends on N and the real size R only.
+// Sphere moments of the velocity field (analysis.hpp): radii per call, radii
+// per pass over the modes, blocks of a pass (one partial sum per block and
+// value), values per pass.
+constexpr int kMomentsMaxRadii = 16;
+constexpr int kMomentsRadiiPerPass = 4;
+constexpr int kMomentsBlocks = 1024;
+constexpr int kMomentsPassValues = 4 * kMomentsRadiiPerPass;
+constexpr size_t kMomentsPartBytes =
+    8 * size_t(kMomentsBlocks) * kMomentsPassValues * (kMomentsMaxRadii / kMomentsRadiiPerPass);
+
 template <int N, int R> struct FixedLayout {
   static constexpr size_t NM = size_t(N) * N * (N / 2);          // stored modes
   static constexpr size_t NPK = 3 * size_t(N / 2) * (N / 2) + 1; // |n|^2 table
@@ -89,7 +99,8 @@ template <int N, int R> struct FixedLayout {
   static constexpr size_t prior_part = align256(bmax + 4 * ((size_t(N) * N + 1023) / 1024));
   static constexpr size_t kin_part = align256(prior_part + 8 * size_t(N_PRIOR));
   static constexpr size_t small = align256(kin_part + 8 * size_t(N_KIN));   // qs0, ps, eps_slot, most, ticket
-  static constexpr size_t mvar = align256(small + 256);
+  static constexpr size_t mom_part = align256(small + 256);       // sphere-moment partial sums
+  static constexpr size_t mvar = align256(mom_part + kMomentsPartBytes);
   static constexpr size_t a = align256(mvar + 8 * NM);
   static constexpr size_t b = a + 2 * R * NM;
   static constexpr size_t v0 = b + 2 * R * NM;

@@ -219,6 +219,22 @@ def unpack_flat(plan, flat, modes, dist, snl):
                                                 ctypes.c_void_p(m), _ptr(d), _ptr(s)))
 
 
+def sphere_moments(plan, modes, radii, out=None):
+    """Monopole and dipole of the velocity field in spheres of the given radii
+    (Mpc/h) about the observer, on the plan's stream (hamlet_sphere_moments):
+    a float64 device tensor (len(radii), 4) of (M, Dx, Dy, Dz) per radius."""
+    r = [float(x) for x in radii]
+    if out is None:
+        out = torch.empty((len(r), 4), dtype=torch.float64, device=plan.device)
+    elif out.dtype != torch.float64 or out.numel() != 4 * len(r) or not out.is_contiguous():
+        raise ValueError("out must be contiguous float64 (%d, 4)" % len(r))
+    m = _check(modes, plan, "modes", "modes")
+    rr = (ctypes.c_double * max(len(r), 1))(*r)
+    _capi.check(_capi.load().hamlet_sphere_moments(plan.handle, ctypes.c_void_p(m), rr, len(r),
+                                                   _ptr(_check(out, plan, "iter_f64", "out"))))
+    return out
+
+
 def leapfrog(plans, eps, n_steps, q_modes, q_dist, q_snl, p_modes, p_dist, p_snl, psi):
     """n_steps kick-drift-kick steps in place (hamlet_leapfrog)."""
     plans, hp = _plans(plans)

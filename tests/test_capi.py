@@ -95,6 +95,14 @@ def test_server_entry_points_validate_on_the_host():
     assert lib.hamlet_server_destroy(None) == 0
 
 
+def test_sphere_moments_validate_on_the_host():
+    from paper_2203_02369_amd import _capi
+    lib = _capi.load()
+    radii = (ctypes.c_double * 2)(10.0, 20.0)
+    assert lib.hamlet_sphere_moments(None, None, radii, 2, None) == -1
+    assert b"NULL" in lib.hamlet_last_error()
+
+
 def test_flat_vector_entry_points_validate_on_the_host():
     from paper_2203_02369_amd import _capi
     lib = _capi.load()

@@ -1,0 +1,108 @@
+"""Sphere moments of the velocity field (hamlet_sphere_moments) against the
+oracle (oracle/analysis.py), through the C ABI.
+
+Tolerance: the moments are signed sums over all modes in FP64 on both
+sides, in different orders; each value must agree within 1e-12 times the
+sum of the absolute values of its terms (the scale of the rounding error).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import analysis, hmc
+from paper_2203_02369_amd import mocks
+
+from helpers import oracle_problem, start_modes, to_lib_layout
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def hl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_02369_amd import hamlet
+    return hamlet
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _check(got, prob, dhat, radii):
+    mono, dip = analysis.sphere_moments(prob, dhat, radii)
+    ref = np.concatenate([mono[:, None], dip], axis=1)
+    scale = analysis.sphere_moments_abs(prob, dhat, radii)
+    err = np.abs(got - ref)
+    assert np.all(err <= TOL * scale + 1e-300), (np.max(err / scale), got, ref)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_moments_match_the_oracle(hl, precision):
+    m = mocks.plain_fp64_32()
+    prob = oracle_problem(m)
+    rng = np.random.default_rng(11)
+    shape = (32, 32, 17)
+    dhat = hmc.symmetrise(32, 1e3 * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)))
+    # below the series switch (|k| R < 1/2 for every mode), across it, and out to the box size
+    radii = [0.05, 3.0, 12.5, 40.0, 90.0, 150.0, 199.0, 260.0, 380.0]
+    say("moments 32^3", precision)
+    plan = hl.Plan.from_mock(m, precision=precision)
+    q = torch.from_numpy(to_lib_layout(dhat)).to(plan.device)
+    out = hl.sphere_moments(plan, q, radii)
+    torch.cuda.synchronize()
+    _check(out.cpu().numpy(), prob, dhat, radii)
+    plan.close()
+
+
+def test_moments_are_bit_identical_across_reruns_and_precisions(hl):
+    m = mocks.plain_fp64_32()
+    dhat = start_modes(m)
+    radii = [7.0, 30.0, 100.0, 150.0, 170.0]
+    say("moments determinism")
+    outs = []
+    for precision in ("fp64", "fp32", "fp64"):
+        plan = hl.Plan.from_mock(m, precision=precision)
+        q = torch.from_numpy(to_lib_layout(dhat)).to(plan.device)
+        outs.append(hl.sphere_moments(plan, q, radii).cpu().numpy())
+        plan.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_moments_at_the_paper_scale(hl):
+    # the mock field of the 256^3 benchmark, sixteen radii (four passes)
+    m = mocks.paper_scale_256()
+    prob = oracle_problem(m)
+    dhat = start_modes(m)
+    radii = [5.0 + 15.0 * j for j in range(16)]
+    say("moments 256^3")
+    plan = hl.Plan.from_mock(m, precision="fp32")
+    q = torch.from_numpy(to_lib_layout(dhat)).to(plan.device)
+    out = hl.sphere_moments(plan, q, radii).cpu().numpy()
+    plan.close()
+    say("oracle 256^3")
+    _check(out, prob, dhat, radii)
+
+
+def test_moments_validate_their_arguments(hl):
+    from paper_2203_02369_amd import _capi
+    m = mocks.make_mock(16, 200.0, 50, 80.0, seed=5)
+    plan = hl.Plan.from_mock(m, precision="fp64")
+    q = torch.zeros(plan.mode_shape, dtype=torch.complex128, device=plan.device)
+    say("moments validation")
+    for bad in ([0.0], [-3.0], [math.nan], [math.inf], [10.0] * 17):
+        with pytest.raises(Exception):
+            hl.sphere_moments(plan, q, bad)
+    assert b"radius" in _capi.load().hamlet_last_error() or b"n_radii" in _capi.load().hamlet_last_error()
+    # no radii: nothing to do
+    assert hl.sphere_moments(plan, q, []).numel() == 0
+    # a zero field has zero moments
+    out = hl.sphere_moments(plan, q, [10.0, 50.0])
+    assert torch.count_nonzero(out).item() == 0
+    plan.close()
