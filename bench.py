@@ -185,7 +185,7 @@ def main():
     c_bytes = 8 * n * n * (n // 2)
     for kind, name, cs in (("inv_y", "k_inv_y", 2 + 3 * ft), ("inv_z_gather", "k_inv_z_gather", 3 * ft),
                            ("fwd_z_scatter", "k_fwd_z_scatter", 3 * ft), ("fwd_y", "k_fwd_y", 3 * ft + 2),
-                           ("like", "k_like", None), ("bin", "binning (4 kernels)", None)):
+                           ("like", "k_like", None), ("bin", "binning (3 kernels)", None)):
         timer = hamlet.KernelTimer(plan, hamlet.PROFILE_KERNELS[kind])
         q2, qd2, qs2 = (t.clone() for t in start)
         torch.cuda.synchronize()

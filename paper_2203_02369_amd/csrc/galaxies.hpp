@@ -89,10 +89,14 @@ __device__ __forceinline__ void bin_count_body(const double* __restrict__ dist, 
   bin_point(i, dist[i], cat, cm, n_grid, bo);
 }
 
-// Exclusive scan of the N^2 bucket counts, in two coalesced passes over
-// tiles of 1024 counts: (1) scan within each tile, tile totals to bsum;
-// (2) add the sum of the preceding tiles, prime the placement cursors and
-// clear the counts for the next evaluation.
+// Exclusive scan of the N^2 bucket counts over tiles of 1024 counts, in one
+// kernel: every block adds up the counts before its tile itself (the early
+// tiles are read by many blocks: a few hundred KB in all at 256^3, from the
+// caches), scans its tile and primes the placement cursors; the last block,
+// which has read every count, writes the total and the largest count of any
+// column.  No block waits for another, and integer sums do not depend on
+// their order.  The placement clears the counts afterwards (each point its
+// own column), so nothing here changes what another block reads.
 constexpr int kScanTile = 1024;
 
 __device__ __forceinline__ int block_exclusive_scan(int v, int* wsum, int* total) {
@@ -119,66 +123,60 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* wsum, int* total
 }
 
 __device__ __forceinline__ void
-bin_scan_tiles_body(const int* __restrict__ count, int* __restrict__ off, int* __restrict__ bsum,
-                    int* __restrict__ bmax, int nkeys) {
+bin_scan_body(const int* __restrict__ count, int* __restrict__ off, int* __restrict__ cursor, int* __restrict__ most,
+              int nkeys) {
   __shared__ int wsum[kScanTile / 64];
-  __shared__ int wmax[kScanTile / 64];
+  __shared__ int wred[2][kScanTile / 64];
   __shared__ int total;
-  const int k = blockIdx.x * kScanTile + threadIdx.x;
-  const int c = k < nkeys ? count[k] : 0;
-  int m = c;
-  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
-  const int ex = block_exclusive_scan(c, wsum, &total);
-  if (k < nkeys) off[k] = ex;
-  if (threadIdx.x == 0) {
-    bsum[blockIdx.x] = total;
-    int mb = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mb = max(mb, wmax[w]);
-    bmax[blockIdx.x] = mb;
+  const int t0 = blockIdx.x * kScanTile;
+  // the counts before this tile, and the largest count up to its end
+  // (16-byte loads, eight in flight per thread: t0 is a multiple of 1024)
+  int s = 0, m = 0;
+  const int4* c4 = reinterpret_cast<const int4*>(count);
+#pragma unroll 8
+  for (int j = threadIdx.x; j < t0 / 4; j += blockDim.x) {
+    const int4 v = c4[j];
+    s += (v.x + v.y) + (v.z + v.w);
+    m = max(m, max(max(v.x, v.y), max(v.z, v.w)));
   }
-}
-
-__device__ __forceinline__ void
-bin_scan_add_body(int* __restrict__ count, int* __restrict__ off, int* __restrict__ cursor,
-                  const int* __restrict__ bsum, const int* __restrict__ bmax, int* __restrict__ most, int nkeys) {
-  __shared__ int base;
-  if (threadIdx.x < 64) {
-    // the first wave sums the preceding tiles (and, in the last block, takes
-    // the largest count of any column)
-    const bool last = blockIdx.x == gridDim.x - 1;
-    int s = 0, m = 0;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 64) s += bsum[b];
-    if (last)
-      for (int b = threadIdx.x; b < (int)gridDim.x; b += 64) m = max(m, bmax[b]);
-    for (int o = 32; o > 0; o >>= 1) {
-      s += __shfl_xor(s, o, 64);
-      m = max(m, __shfl_xor(m, o, 64));
-    }
-    if (threadIdx.x == 0) {
-      base = s;
-      if (last) {
-        off[nkeys] = s + bsum[blockIdx.x];
-        most[0] = m;
-      }
-    }
+  const int k = t0 + threadIdx.x;
+  const int c = k < nkeys ? count[k] : 0;
+  m = max(m, c);
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_xor(s, o, 64);
+    m = max(m, __shfl_xor(m, o, 64));
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  if (lane == 0) {
+    wred[0][wid] = s;
+    wred[1][wid] = m;
   }
   __syncthreads();
-  const int k = blockIdx.x * kScanTile + threadIdx.x;
+  int base = 0, mx = 0;
+  for (int w = 0; w < nw; ++w) {
+    base += wred[0][w];
+    mx = max(mx, wred[1][w]);
+  }
+  const int ex = block_exclusive_scan(c, wsum, &total);
   if (k < nkeys) {
-    const int o = off[k] + base;
-    off[k] = o;
-    cursor[k] = o;
-    count[k] = 0;
+    off[k] = base + ex;
+    cursor[k] = base + ex;
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    off[nkeys] = base + total;
+    most[0] = mx;
   }
 }
 
 __device__ __forceinline__ void
-bin_place_body(const int* __restrict__ key, int* __restrict__ cursor, int* __restrict__ slot_gid, int n) {
+bin_place_body(const int* __restrict__ key, int* __restrict__ cursor, int* __restrict__ slot_gid,
+               int* __restrict__ count, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int s = atomicAdd(&cursor[key[i]], 1);
+  const int kk = key[i];
+  const int s = atomicAdd(&cursor[kk], 1);
   slot_gid[s] = i;
+  count[kk] = 0;   // cleared for the next evaluation's counting
 }
 
 // Final position of each point in its column: the members of a column are
@@ -428,24 +426,17 @@ __global__ void __launch_bounds__(kGalThreads) k_bin_count(Launch L) {
 }
 
 template <typename T, int N>
-__global__ void __launch_bounds__(kScanTile) k_bin_scan_tiles(Launch L) {
+__global__ void __launch_bounds__(kScanTile) k_bin_scan(Launch L) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
-  bin_scan_tiles_body(k.w.count(), k.w.off(), k.w.bsum(), k.w.bmax(), N * N);
-}
-
-template <typename T, int N>
-__global__ void __launch_bounds__(kScanTile) k_bin_scan_add(Launch L) {
-  const Pick<T, N> k(L);
-  if (k.mode == kXSkip) return;
-  bin_scan_add_body(k.w.count(), k.w.off(), k.w.cursor(), k.w.bsum(), k.w.bmax(), k.w.most(), N * N);
+  bin_scan_body(k.w.count(), k.w.off(), k.w.cursor(), k.w.most(), N * N);
 }
 
 template <typename T, int N>
 __global__ void __launch_bounds__(kGalThreads) k_bin_place(Launch L) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
-  bin_place_body(k.w.key(), k.w.cursor(), k.w.slot(), k.n_gal);
+  bin_place_body(k.w.key(), k.w.cursor(), k.w.slot(), k.w.count(), k.n_gal);
 }
 
 template <typename T, int N>

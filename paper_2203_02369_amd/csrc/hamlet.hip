@@ -196,8 +196,7 @@ static hamlet_status eval_impl(const Batch& b) {
         if (grad.mode[i] != kXGrad) grad.mode[i] = kXSkip;
       k_bin_count<T, N><<<g_gal, kGalThreads, 0, st>>>(launch_table(grad));
     }
-    k_bin_scan_tiles<T, N><<<dim3(tiles, 1, nb), kScanTile, 0, st>>>(sel);
-    k_bin_scan_add<T, N><<<dim3(tiles, 1, nb), kScanTile, 0, st>>>(sel);
+    k_bin_scan<T, N><<<dim3(tiles, 1, nb), kScanTile, 0, st>>>(sel);
     k_bin_place<T, N><<<g_gal, kGalThreads, 0, st>>>(sel);
     k_bin_rank<T, N><<<g_gal, kGalThreads, 0, st>>>(sel);
     prof_after(b, HAMLET_K_BIN);

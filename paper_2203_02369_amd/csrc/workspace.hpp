@@ -94,9 +94,7 @@ template <int N, int R> struct FixedLayout {
   static constexpr size_t count = align256(tw + 2 * R * size_t(N));
   static constexpr size_t off = align256(count + 4 * size_t(N) * N);
   static constexpr size_t cursor = align256(off + 4 * (size_t(N) * N + 1));
-  static constexpr size_t bsum = align256(cursor + 4 * size_t(N) * N);
-  static constexpr size_t bmax = align256(bsum + 4 * ((size_t(N) * N + 1023) / 1024));
-  static constexpr size_t prior_part = align256(bmax + 4 * ((size_t(N) * N + 1023) / 1024));
+  static constexpr size_t prior_part = align256(cursor + 4 * size_t(N) * N);
   static constexpr size_t kin_part = align256(prior_part + 8 * size_t(N_PRIOR));
   static constexpr size_t small = align256(kin_part + 8 * size_t(N_KIN));   // qs0, ps, eps_slot, most, ticket
   static constexpr size_t mom_part = align256(small + 256);       // sphere-moment partial sums
@@ -178,7 +176,6 @@ template <typename T, int N> struct Ws {
   __host__ __device__ int* count() const { return at<int>(F::count); }
   __host__ __device__ int* off() const { return at<int>(F::off); }
   __host__ __device__ int* cursor() const { return at<int>(F::cursor); }
-  __host__ __device__ int* bsum() const { return at<int>(F::bsum); }
   __host__ __device__ double* prior_part() const { return at<double>(F::prior_part); }
   __host__ __device__ double* kin_part() const { return at<double>(F::kin_part); }
   __host__ __device__ double* qs0() const { return at<double>(F::small); }
@@ -186,7 +183,6 @@ template <typename T, int N> struct Ws {
   __host__ __device__ double* eps_slot() const { return at<double>(F::small + 16); }
   __host__ __device__ int* most() const { return at<int>(F::small + 24); }   // most points in one column
   __host__ __device__ int* ticket() const { return at<int>(F::small + 28); } // likelihood blocks done
-  __host__ __device__ int* bmax() const { return at<int>(F::bmax); }
   __host__ __device__ double* mvar() const { return at<double>(F::mvar); }
   __host__ __device__ C* a() const { return at<C>(F::a); }
   __host__ __device__ C* b() const { return at<C>(F::b); }
