@@ -48,9 +48,9 @@ HBM_PEAK_GBS = 8000.0
 # (--copy-calibration: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  Bytes read and
 # written per launch for the plain-gradient, first, middle and last variants.
 # Valid only for the kernel sources they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "2ec44c789b5a9ba24b62f9aa388338f0a9077bcb"
-X_TRAFFIC = {"grad": (334160060, 134217856), "first": (335666522, 670191294),
-             "mid": (468531066, 401674667), "last": (468399835, 268503285)}
+X_TRAFFIC_SOURCES_SHA1 = "e338f72d8568592b58b82762eda6124a416be3d0"
+X_TRAFFIC = {"grad": (334171053, 134217744), "first": (335662425, 670191582),
+             "mid": (468542057, 401674772), "last": (468407692, 268502769)}
 
 
 def kernel_sources_sha1():
