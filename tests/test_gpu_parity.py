@@ -276,6 +276,29 @@ def test_leapfrog_matches_oracle(hl, precision):
     plan.close()
 
 
+def test_paper_scale_gradient_matches_oracle_fp64(hl):
+    # 256^3, 30 000 points, the plain FP64 path at its own tolerance: every
+    # pass at full size (60 % of the pencils in reach of a point, the rest
+    # skipped), against the oracle's log-posterior and gradient.
+    m = mocks.paper_scale_256()
+    prob = oracle_problem(m)
+    dhat = start_modes(m)
+    rng = np.random.default_rng(19)
+    d = m.d_true * (1.0 + 0.02 * rng.standard_normal(m.n_gal))
+    s = 1.4
+    say("oracle 256^3 gradient")
+    psi_r, g_r, gd_r, gs_r = model.logpost_grad(prob, dhat, d, s)
+    assert np.isfinite(psi_r)
+    say("gpu 256^3 fp64 gradient")
+    plan = hl.Plan.from_mock(m, precision="fp64")
+    psi, g, gd, gs = gpu_grad(hl, plan, dhat, d, s)
+    plan.close()
+    assert abs(psi - psi_r) <= TOL64 * abs(psi_r), (psi, psi_r)
+    assert rel_inf(g, g_r) <= TOL64, rel_inf(g, g_r)
+    assert rel_inf(gd, gd_r) <= TOL64, rel_inf(gd, gd_r)
+    assert abs(gs - gs_r) <= TOL64 * abs(gs_r), (gs, gs_r)
+
+
 def test_paper_scale_leapfrog_matches_oracle_fp32(hl):
     # 256^3, 30 000 points, one leapfrog step with the step size the
     # benchmark adapts to: the fused first- and last-step x passes and the
