@@ -106,7 +106,8 @@ template <int N> struct PencilLayout {
 // One Stockham stage on a batch of B transforms held in LDS (layout L).
 // Thread mapping follows the layout: butterflies of a transform on
 // consecutive threads (pencils) or transforms on consecutive threads (rows).
-template <typename T, int N, int R, int LEN, int B, typename LAY, int NT, int SIGN>
+// TWP: form a radix-16 stage's twiddles from two table reads (below).
+template <typename T, int N, int R, int LEN, int B, typename LAY, int NT, int SIGN, bool TWP = false>
 __device__ __forceinline__ void lds_stage(cplx_t<T>* buf, const cplx_t<T>* tw) {
   using C = cplx_t<T>;
   constexpr int NB = N / R;
@@ -123,15 +124,40 @@ __device__ __forceinline__ void lds_stage(cplx_t<T>* buf, const cplx_t<T>* tw) {
       const int b = NFAST ? idx / NB : idx % B;
       const int j = NFAST ? idx % NB : idx / B;
       const int k = j % LEN;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        C x = buf[LAY::idx(j + r * NB, b)];
-        if (LEN > 1 && r > 0) {
-          C w = tw[r * k * TSTEP];
-          if (SIGN > 0) w.y = -w.y;
-          x = cmul(x, w);
+      if constexpr (TWP && R == 16 && LEN > 1) {
+        // Read w^k and w^4k and form the other powers w^rk with at most
+        // three products (a few ulp): 2 LDS reads instead of 15 and fewer
+        // live registers, which is what the scatter's dense path gains by.
+        C w1 = tw[k * TSTEP], w4 = tw[4 * k * TSTEP];
+        if (SIGN > 0) {
+          w1.y = -w1.y;
+          w4.y = -w4.y;
         }
-        v[p][r] = x;
+        C w[R];
+        w[1] = w1;
+        w[2] = cmul(w1, w1);
+        w[3] = cmul(w[2], w1);
+        w[4] = w4;
+        w[5] = cmul(w4, w1);
+        w[6] = cmul(w4, w[2]);
+        w[7] = cmul(w4, w[3]);
+        w[8] = cmul(w4, w4);
+#pragma unroll
+        for (int r = 9; r < R; ++r) w[r] = cmul(w[8], w[r - 8]);
+        v[p][0] = buf[LAY::idx(j, b)];
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[p][r] = cmul(buf[LAY::idx(j + r * NB, b)], w[r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          C x = buf[LAY::idx(j + r * NB, b)];
+          if (LEN > 1 && r > 0) {
+            C w = tw[r * k * TSTEP];
+            if (SIGN > 0) w.y = -w.y;
+            x = cmul(x, w);
+          }
+          v[p][r] = x;
+        }
       }
       dft_reg<T, R, SIGN>(v[p]);
     }
@@ -155,34 +181,34 @@ __device__ __forceinline__ void lds_stage(cplx_t<T>* buf, const cplx_t<T>* tw) {
 // Radix plan per length; the whole transform of a batch in LDS.
 // Callers must have synchronised the LDS contents before the call; on
 // return the result is in place and synchronised.
-template <typename T, int N, int B, typename LAY, int NT, int SIGN>
+template <typename T, int N, int B, typename LAY, int NT, int SIGN, bool TWP = false>
 __device__ __forceinline__ void lds_fft(cplx_t<T>* buf, const cplx_t<T>* tw) {
   static_assert(N >= 8 && N <= 1024 && (N & (N - 1)) == 0, "FFT length must be 8..1024, power of two");
   if constexpr (N == 8) {
-    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
   } else if constexpr (N == 16) {
-    lds_stage<T, N, 4, 1, B, LAY, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 4, 4, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 4, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
+    lds_stage<T, N, 4, 4, B, LAY, NT, SIGN, TWP>(buf, tw);
   } else if constexpr (N == 32) {
-    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 4, 8, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
+    lds_stage<T, N, 4, 8, B, LAY, NT, SIGN, TWP>(buf, tw);
   } else if constexpr (N == 64) {
-    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 8, 8, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
+    lds_stage<T, N, 8, 8, B, LAY, NT, SIGN, TWP>(buf, tw);
   } else if constexpr (N == 128) {
-    lds_stage<T, N, 16, 1, B, LAY, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 8, 16, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 16, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
+    lds_stage<T, N, 8, 16, B, LAY, NT, SIGN, TWP>(buf, tw);
   } else if constexpr (N == 256) {
-    lds_stage<T, N, 16, 1, B, LAY, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 16, 16, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 16, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
+    lds_stage<T, N, 16, 16, B, LAY, NT, SIGN, TWP>(buf, tw);
   } else if constexpr (N == 512) {
-    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 8, 8, B, LAY, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 8, 64, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
+    lds_stage<T, N, 8, 8, B, LAY, NT, SIGN, TWP>(buf, tw);
+    lds_stage<T, N, 8, 64, B, LAY, NT, SIGN, TWP>(buf, tw);
   } else {
-    lds_stage<T, N, 16, 1, B, LAY, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 8, 16, B, LAY, NT, SIGN>(buf, tw);
-    lds_stage<T, N, 8, 128, B, LAY, NT, SIGN>(buf, tw);
+    lds_stage<T, N, 16, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
+    lds_stage<T, N, 8, 16, B, LAY, NT, SIGN, TWP>(buf, tw);
+    lds_stage<T, N, 8, 128, B, LAY, NT, SIGN, TWP>(buf, tw);
   }
 }
 

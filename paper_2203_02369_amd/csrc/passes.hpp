@@ -761,7 +761,7 @@ fwd_z_scatter_body(const T* __restrict__ gsort, Binned<T> bins, const cplx_t<T>*
       }
     }
     __syncthreads();
-    lds_fft<T, N, FC, LAY, NT, -1>(buf, twl);
+    lds_fft<T, N, FC, LAY, NT, -1, true>(buf, twl);
     // Split each transform Z of a + i b into the half spectra
     //   A_k = (Z_k + conj Z_{N-k}) / 2,   B_k = (Z_k - conj Z_{N-k}) / (2 i).
     for (int idx = threadIdx.x; idx < FC * H; idx += NT) {

@@ -299,6 +299,37 @@ def test_paper_scale_gradient_matches_oracle_fp64(hl):
     assert abs(gs - gs_r) <= TOL64 * abs(gs_r), (gs, gs_r)
 
 
+_crowded = {}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_crowded_column_at_256_matches_oracle(hl, precision):
+    # 100 of 3000 points on the z axis through the observer: one CIC column
+    # holds all of them, so the scatter takes its dense path at 256^3 (built
+    # pencils, four a round, and the radix-16 transform) in both precisions.
+    if not _crowded:
+        m = mocks.paper_scale_256(n_gal=3000)
+        m.rhat = m.rhat.copy()
+        m.rhat[:100] = np.array([0.0, 0.0, 1.0])
+        prob = oracle_problem(m)
+        dhat = start_modes(m)
+        d = m.d_true.copy()
+        say("oracle 256^3 crowded column")
+        ref = model.logpost_grad(prob, dhat, d, 1.2)
+        assert np.isfinite(ref[0])
+        _crowded.update(m=m, dhat=dhat, d=d, ref=ref)
+    m, dhat, d, ref = _crowded["m"], _crowded["dhat"], _crowded["d"], _crowded["ref"]
+    say("gpu 256^3 crowded column", precision)
+    plan = hl.Plan.from_mock(m, precision=precision)
+    psi, g, gd, gs = gpu_grad(hl, plan, dhat, d, 1.2)
+    plan.close()
+    tol_psi, tol_g = (TOL64, TOL64) if precision == "fp64" else (TOL32_PSI, TOL32_GRAD)
+    assert abs(psi - ref[0]) <= tol_psi * abs(ref[0]), (psi, ref[0])
+    assert rel_inf(g, ref[1]) <= tol_g, rel_inf(g, ref[1])
+    assert rel_inf(gd, ref[2]) <= tol_g, rel_inf(gd, ref[2])
+    assert abs(gs - ref[3]) <= tol_g * abs(ref[3]), (gs, ref[3])
+
+
 def test_paper_scale_leapfrog_matches_oracle_fp32(hl):
     # 256^3, 30 000 points, one leapfrog step with the step size the
     # benchmark adapts to: the fused first- and last-step x passes and the
