@@ -356,6 +356,7 @@ template <typename T> static const Ops* pick_ops(int n) {
     case 64: return &OpsFor<T, 64>::ops;
     case 128: return &OpsFor<T, 128>::ops;
     case 256: return &OpsFor<T, 256>::ops;
+    case 512: return &OpsFor<T, 512>::ops;
     default: return nullptr;
   }
 }
@@ -366,8 +367,8 @@ template <typename T> static const Ops* pick_ops(int n) {
 static hamlet_status check_desc(const hamlet_plan_desc* d) {
   if (!d) return fail(HAMLET_EINVAL, "desc is NULL");
   const int n = d->n_grid;
-  if (n != 16 && n != 32 && n != 64 && n != 128 && n != 256)
-    return fail(HAMLET_EUNSUPPORTED, "n_grid %d: built for 16, 32, 64, 128, 256", n);
+  if (n != 16 && n != 32 && n != 64 && n != 128 && n != 256 && n != 512)
+    return fail(HAMLET_EUNSUPPORTED, "n_grid %d: built for 16, 32, 64, 128, 256, 512", n);
   if (d->precision != HAMLET_FP64 && d->precision != HAMLET_FP32_FP64E)
     return fail(HAMLET_EINVAL, "precision %d", d->precision);
   if (!(d->box > 0) || !std::isfinite(d->box)) return fail(HAMLET_EINVAL, "box must be positive");
@@ -457,8 +458,8 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
   }
   hipStream_t st = pl->stream;
   HIP_TRY(hipMemcpyAsync(pl->var, var.data(), npk * 8, hipMemcpyHostToDevice, st));
-  // tile width of the x pass: 16 (FP32) or 8 (FP64) kz columns, at most N/2
-  const int wmax = pl->prec == HAMLET_FP64 ? 8 : 16, w = std::min(wmax, n / 2);
+  // the x pass's tile width, in whose tiles sigma^2 is laid out
+  const int w = tile_width(pl->prec == HAMLET_FP64 ? 8 : 4, n);
   k_fill_mode_var<<<blocks_for(pl->modes_count(), kEltThreads), kEltThreads, 0, st>>>(pl->mvar, pl->var, n, w);
   LAUNCH_CHECK();
   if (pl->prec == HAMLET_FP64)
@@ -1055,6 +1056,7 @@ extern "C" hamlet_status hamlet_sphere_moments(hamlet_plan* plan, const void* mo
       case 64: moments_pass<64>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
       case 128: moments_pass<128>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
       case 256: moments_pass<256>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
+      case 512: moments_pass<512>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
       default: return fail(HAMLET_EUNSUPPORTED, "grid size %d", plan->n);
     }
   }

@@ -52,9 +52,8 @@ template <int N> struct XSlabs {
 
 template <typename T, int N> struct PassShape {
   using C = cplx_t<T>;
-  static constexpr int WMAX = sizeof(T) == 4 ? 16 : 8;
   static constexpr int PMAX = sizeof(T) == 4 ? 8 : 4;
-  static constexpr int W = WMAX < N / 2 ? WMAX : N / 2;     // kz columns per strided tile
+  static constexpr int W = tile_width(sizeof(T), N);       // kz columns per strided tile
   static constexpr int P = PMAX < N ? PMAX : N;             // pencils per z tile
   static constexpr int H = N / 2;
   static constexpr int CHUNKS = H / W;
@@ -177,6 +176,23 @@ template <typename T> __device__ __forceinline__ void vec_store(cplx_t<T>* p, co
   *reinterpret_cast<typename ColVec<T>::V*>(p) = v;
 }
 
+// The strided tile (kz chunk, row) of this block in the x and y passes.
+// Where a chunk's row is shorter than a 128-byte line (W complex values in
+// under 128 bytes: the 512^3 grid), two neighbouring chunks share every
+// line, while the hardware deals consecutive workgroups to the eight XCDs in
+// turn, each with its own L2.  The blocks are then renumbered so that the
+// two chunks of each line run on one XCD: in every group of 16 workgroups,
+// ids 8h + j (XCD j) take chunk slot 2j + h.  Identity otherwise.
+template <typename T, int N> __device__ __forceinline__ int2 strided_tile() {
+  using S = PassShape<T, N>;
+  unsigned id = blockIdx.x + S::CHUNKS * blockIdx.y;
+  if constexpr (S::W * sizeof(cplx_t<T>) < 128 && S::CHUNKS % 2 == 0) {
+    static_assert((S::CHUNKS * N) % 16 == 0, "whole groups of 16 workgroups");
+    id = (id & ~15u) | ((id & 7u) << 1) | ((id >> 3) & 1u);
+  }
+  return make_int2((int)(id % S::CHUNKS), (int)(id / S::CHUNKS));
+}
+
 // Global offset of (i, j, kz) in an [N][N][N/2] array.
 template <int N> __device__ __forceinline__ size_t gofs(int i, int j, int kz) {
   return ((size_t)i * N + j) * (N / 2) + kz;
@@ -211,13 +227,12 @@ template <int N> struct PencilProbe {
 };
 
 // The flags of the pencils (x, y), y in [0, N), into LDS (visible after the
-// caller's next barrier): one pencil per thread.
+// caller's next barrier).
 template <int N, int NT> __device__ __forceinline__ void plane_flags(const int* off, int x, bool* touched) {
-  static_assert(N <= NT, "one pencil per thread");
-  if (threadIdx.x < N) {
+  for (int y = threadIdx.x; y < N; y += NT) {
     PencilProbe<N> pr;
-    pr.load(off, x, threadIdx.x);
-    touched[threadIdx.x] = pr.touched();
+    pr.load(off, x, y);
+    touched[y] = pr.touched();
   }
 }
 
@@ -253,7 +268,8 @@ inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* _
   __shared__ C twl[N];
   __shared__ double red[NT / 64];
   load_twiddles<T, N, NT>(twl, tw);
-  const int y = blockIdx.y, z0 = blockIdx.x * S::W;
+  const int2 tl = strided_tile<T, N>();
+  const int y = tl.y, z0 = tl.x * S::W;
   const int sy = signed_freq(y, N);
   double prior = 0.0;
   // i kfac q (and n_x times it), zero on excluded modes
@@ -300,17 +316,22 @@ inv_y_body(const cplx_t<T>* __restrict__ inA, const cplx_t<T>* __restrict__ inB,
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
   __shared__ bool touched[N];   // rows stored (see PencilProbe)
-  const int x = x0 + blockIdx.y, z0 = blockIdx.x * S::W;
+  const int2 tl = strided_tile<T, N>();
+  const int x = x0 + tl.y, z0 = tl.x * S::W;
   // the flags are needed only at the first store: their loads go first,
   // and they are taken once the tile is in
-  static_assert(N <= NT, "one pencil per thread");
-  PencilProbe<N> probe;
-  if (threadIdx.x < N) probe.load(off, x, threadIdx.x);
+  constexpr int PP = (N + NT - 1) / NT;   // pencils per thread
+  PencilProbe<N> probe[PP];
+#pragma unroll
+  for (int i = 0; i < PP; ++i)
+    if (threadIdx.x + i * NT < N) probe[i].load(off, x, threadIdx.x + i * NT);
   TwiddleStage<T, N, NT> tws;
   tws.load(tw);
   tile_vecs<T, N, NT>([&](int, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, vec_load<T>(&inB[gofs<N>(x, y, z0 + w)])); });
   tws.store(twl);
-  if (threadIdx.x < N) touched[threadIdx.x] = probe.touched();
+#pragma unroll
+  for (int i = 0; i < PP; ++i)
+    if (threadIdx.x + i * NT < N) touched[threadIdx.x + i * NT] = probe[i].touched();
   __syncthreads();
   const unsigned rows = row_bits<T, N, NT>(touched);
   lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
@@ -802,7 +823,8 @@ fwd_y_body(const cplx_t<T>* __restrict__ gx, const cplx_t<T>* __restrict__ gy, c
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
   __shared__ bool touched[N];   // rows the scatter stored; the others are zero
-  const int x = x0 + blockIdx.y, z0 = blockIdx.x * S::W;
+  const int2 tl = strided_tile<T, N>();
+  const int x = x0 + tl.y, z0 = tl.x * S::W;
   plane_flags<N, NT>(off, x, touched);
   load_twiddles<T, N, NT>(twl, tw);
   __syncthreads();
@@ -897,7 +919,8 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
   // twiddles into LDS once the first tile loads are issued
   TwiddleStage<T, N, NT> tws;
   tws.load(tw);
-  const int y = blockIdx.y, z0 = blockIdx.x * S::W;
+  const int2 tl = strided_tile<T, N>();
+  const int y = tl.y, z0 = tl.x * S::W;
   const int sy = signed_freq(y, N);
   C acc[elems_per_thread<T, N, NT>()];
   if constexpr (kFromSpectra) {

@@ -23,6 +23,7 @@ are not available):
   * Observed mu = mu(d) + sigma_mu xi and cz = c zbar(d) + v (1 + zbar(d)) +
     sigma_cz xi', with v the linear radial velocity of the field at the point.
 """
+import dataclasses
 import math
 from dataclasses import dataclass
 
@@ -267,6 +268,22 @@ def paper_scale_256(n_gal=30000, n_grid=256, seed=None):
     """256^3, L = 500, 30 000 points, n ~ 1/r to 250 Mpc/h, ZoA |b| < 10 deg."""
     return make_mock(n_grid, 500.0, n_gal, 250.0, "inv_r", (0.15, 0.25), zoa_deg=10.0,
                      seed=config_seed(3) if seed is None else seed)
+
+
+def refine(mock, n_grid):
+    """The same universe and catalogue on a finer grid of n_grid^3: the
+    field's modes carried over (times (n_grid / N)^3, the unnormalised
+    transform), the modes the coarse grid cannot hold left at zero, P(k)
+    tabulated for the finer grid."""
+    n0 = mock.n_grid
+    if n_grid < n0 or n_grid % n0:
+        raise ValueError("n_grid must be a multiple of %d" % n0)
+    s = np.where(np.arange(n0) < n0 // 2, np.arange(n0), np.arange(n0) - n0)
+    fine = np.where(s < 0, s + n_grid, s)
+    dh = np.zeros((n_grid, n_grid, n_grid // 2 + 1), dtype=np.complex128)
+    dh[np.ix_(fine, fine, np.arange(n0 // 2))] = (n_grid / n0) ** 3 * mock.dhat_true[:, :, : n0 // 2]
+    pk = PowerSpectrum(omega_m=mock.omega_m, h=mock.h).table_n2(n_grid, mock.box)
+    return dataclasses.replace(mock, n_grid=n_grid, pk_n2=pk, dhat_true=dh)
 
 
 def batched_16_sizes():

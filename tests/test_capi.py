@@ -111,3 +111,15 @@ def test_flat_vector_entry_points_validate_on_the_host():
     assert b"NULL" in lib.hamlet_last_error()
     assert lib.hamlet_pack_flat(None, None, None, None, None) == -1
     assert lib.hamlet_unpack_flat(None, None, None, None, None) == -1
+
+
+def test_refined_mock_keeps_the_field_on_the_coarse_nodes():
+    # the input generator's finer-grid copy of a universe (used at 512^3)
+    import numpy as np
+    from paper_2203_02369_amd import mocks
+    m = mocks.make_mock(16, 200.0, 50, 80.0, seed=3)
+    r = mocks.refine(m, 32)
+    coarse = np.fft.irfftn(m.dhat_true, s=(16, 16, 16), axes=(0, 1, 2))
+    fine = np.fft.irfftn(r.dhat_true, s=(32, 32, 32), axes=(0, 1, 2))
+    assert np.abs(fine[::2, ::2, ::2] - coarse).max() <= 1e-12 * np.abs(coarse).max()
+    assert r.n_grid == 32 and len(r.pk_n2) == 3 * 16 ** 2 + 1 and r.n_gal == m.n_gal
