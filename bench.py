@@ -48,9 +48,9 @@ HBM_PEAK_GBS = 8000.0
 # (--copy-calibration: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  Bytes read and
 # written per launch for the plain-gradient, first, middle and last variants.
 # Valid only for the kernel sources they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "ede185114bdbea31ebe0a3533d1985ae46e658d9"
-X_TRAFFIC = {"grad": (334171308, 134217824), "first": (358922705, 703789956),
-             "mid": (468542204, 401674915), "last": (468407915, 268503334)}
+X_TRAFFIC_SOURCES_SHA1 = "5087a68b90d7636dcfe8140f5ac8af5ae1a0fced"
+X_TRAFFIC = {"grad": (334163869, 134217888), "first": (358720123, 703783290),
+             "mid": (468539130, 401674816), "last": (468405644, 268503475)}
 
 
 def kernel_sources_sha1():
