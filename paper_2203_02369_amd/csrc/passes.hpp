@@ -36,7 +36,7 @@ constexpr int kPassThreads = 256;
 
 // Threads per block of each pass kind (tuned on the MI355X).
 template <typename T, int N> struct PassThreads {
-  static constexpr int XY = 256;                        // k_inv_x, k_inv_y, k_fwd_y
+  static constexpr int XY = N >= 512 ? 512 : 256;       // k_inv_x, k_inv_y, k_fwd_y
   static constexpr int X = 512;                          // k_x_pass
   static constexpr int ZG = 256;                         // k_inv_z_gather
   static constexpr int ZS = 256;                         // k_fwd_z_scatter
