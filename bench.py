@@ -48,9 +48,9 @@ HBM_PEAK_GBS = 8000.0
 # (--copy-calibration: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  Bytes read and
 # written per launch for the plain-gradient, first, middle and last variants.
 # Valid only for the kernel sources they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "3ce4fec9af1eb925ab4f2ad68cd7d7b0a0e3b691"
-X_TRAFFIC = {"grad": (334168157, 134217840), "first": (358654845, 703784013),
-             "mid": (468539091, 401674560), "last": (468391420, 268503230)}
+X_TRAFFIC_SOURCES_SHA1 = "ee5b255ef4ba6255812eee7891f6f6d96e44ba9f"
+X_TRAFFIC = {"grad": (334159813, 134217824), "first": (358643104, 703778807),
+             "mid": (468534893, 401674745), "last": (468405588, 268503113)}
 
 
 def kernel_sources_sha1():

@@ -203,12 +203,12 @@ static hamlet_status eval_impl(const Batch& b) {
     LAUNCH_CHECK();
   }
   const dim3 g_xy(S::CHUNKS, N, nb);
-  const dim3 g_xy_slab(S::CHUNKS, SL::SIZE, nb), g_z_slab(N / S::P, SL::SIZE, nb);
+  const dim3 g_xy_slab(S::CHUNKS, SL::SIZE, nb), g_z_slab(N / S::P, SL::SIZE, nb), g_zg_slab(N / S::PG, SL::SIZE, nb);
   if (batch_has(b, kXGrad)) TIMED(b, HAMLET_K_INV_X, (k_inv_x<T, N, TH::XY><<<g_xy, TH::XY, 0, st>>>(sel)));
   for (int sl = 0; sl < SL::COUNT; ++sl) {
     const int x0 = sl * SL::SIZE;
     TIMED(b, HAMLET_K_INV_Y, (k_inv_y<T, N, TH::XY><<<g_xy_slab, TH::XY, 0, st>>>(sel, x0)));
-    TIMED(b, HAMLET_K_INV_Z, (k_inv_z_gather<T, N, TH::ZG><<<g_z_slab, TH::ZG, 0, st>>>(sel, x0)));
+    TIMED(b, HAMLET_K_INV_Z, (k_inv_z_gather<T, N, TH::ZG><<<g_zg_slab, TH::ZG, 0, st>>>(sel, x0)));
   }
   LAUNCH_CHECK();
   if (ng > 0) {

@@ -54,7 +54,11 @@ template <typename T, int N> struct PassShape {
   using C = cplx_t<T>;
   static constexpr int PMAX = sizeof(T) == 4 ? 8 : 4;
   static constexpr int W = tile_width(sizeof(T), N);       // kz columns per strided tile
-  static constexpr int P = PMAX < N ? PMAX : N;             // pencils per z tile
+  static constexpr int P = PMAX < N ? PMAX : N;             // pencils per z tile (scatter)
+  // pencils per tile of the gather: half as many at 512^3, where its LDS
+  // transform buffer would otherwise keep two tiles per compute unit
+  static constexpr int PG = N >= 512 ? P / 2 : P;
+  static constexpr int FG = 3 * PG / 2;
   static constexpr int H = N / 2;
   static constexpr int CHUNKS = H / W;
   static constexpr int ELEMS = N * W;
@@ -385,7 +389,7 @@ __device__ __forceinline__ int zslot_part(int p, int c) {
 
 // ---------------------------------------------------------------------------
 // Inverse pass 3 (along z, complex-to-real) fused with the CIC gather.
-// Tile: fixed x, pencils y0 .. y0 + P.  Grid (N / P, N).
+// Tile: fixed x, pencils y0 .. y0 + P (P = PassShape::PG).  Grid (N / P, N).
 // Writes, for every galaxy whose CIC stencil touches a pencil of the tile,
 // the column partials of its projected velocity (eqn:lvr):
 //   Pc = sum_c rhat_c [(1 - tz) v_c(z0) + tz v_c(z1)],  Qc = sum_c rhat_c [v_c(z1) - v_c(z0)]
@@ -398,7 +402,7 @@ inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict_
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Pen;
-  constexpr int P = S::P, H = S::H, F = S::F;
+  constexpr int P = S::PG, H = S::H, F = S::FG;
   __shared__ C buf[LAY::size(F)];
   __shared__ C twl[N];
   const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
