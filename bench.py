@@ -48,9 +48,9 @@ HBM_PEAK_GBS = 8000.0
 # (--copy-calibration: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  Bytes read and
 # written per launch for the plain-gradient, first, middle and last variants.
 # Valid only for the kernel sources they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "ee5b255ef4ba6255812eee7891f6f6d96e44ba9f"
-X_TRAFFIC = {"grad": (334159813, 134217824), "first": (358643104, 703778807),
-             "mid": (468534893, 401674745), "last": (468405588, 268503113)}
+X_TRAFFIC_SOURCES_SHA1 = "4a8e5ee4cd5e7b8237a30e56b9b5a79e3e016045"
+X_TRAFFIC = {"grad": (334163933, 134218192), "first": (358770877, 703788704),
+             "mid": (468539046, 401674936), "last": (468405644, 268503435)}
 
 
 def kernel_sources_sha1():
@@ -224,6 +224,21 @@ def main():
                                    "mode_bytes_per_call": mom_bytes,
                                    "mode_read_GBs": round(mom_bytes / (mom_ms * 1e-3) / 1e9, 1)}}
     log("sphere moments (16 radii): %.3f ms per call" % mom_ms)
+    # the whole velocity field of the state (three grids of N^3 reals): the
+    # inverse x pass (modes, sigma^2 in: 3c; A, B out: 2c), the y pass with
+    # every row (2c in, 3c out) and the z pass writing the field (3c in, 3c out)
+    vf = hamlet.velocity_field(plan, q)
+    ev0.record(plan.stream)
+    for _ in range(5):
+        hamlet.velocity_field(plan, q, out=vf)
+    ev1.record(plan.stream)
+    ev1.synchronize()
+    vf_ms = ev0.elapsed_time(ev1) / 5
+    vf_bytes = 16 * c_bytes
+    analysis["velocity_field"] = {"avg_call_ms": round(vf_ms, 4), "bytes_per_call": vf_bytes,
+                                  "achieved": round(vf_bytes / (vf_ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
+    log("velocity field: %.3f ms per call" % vf_ms)
+    del vf
     plan.close()
     del q, qd, qs
 

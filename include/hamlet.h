@@ -215,6 +215,21 @@ hamlet_status hamlet_pack_flat(hamlet_plan* plan, const void* modes, const doubl
  * plan's stream. */
 hamlet_status hamlet_unpack_flat(hamlet_plan* plan, const double* flat, void* modes, double* dist, double* snl);
 
+/* ---- The velocity field of a state ----
+ *
+ * eq:vel-field: v_c(x_j) = N^-3 sum_k m_c(k) dhat_k exp(i k.x_j), c = x, y, z,
+ * on every node x_j = j L / N of the grid (km/s), from the modes of a state
+ * (e.g. a sample, or the chain's mean state) for maps and statistics of the
+ * reconstructed field (Section 5).
+ *
+ * modes (device): N x N x N/2 complex128.
+ * out (device): 3 N^3 reals of the plan's precision (float for
+ *   HAMLET_FP32_FP64E, double for HAMLET_FP64), out[((c N + x) N + y) N + z].
+ * Uses the plan's workspace (the inverse passes of an evaluation); calls on
+ * one plan are ordered by its stream.  Errors: HAMLET_EINVAL for NULL
+ * buffers.  Asynchronous on the plan's stream. */
+hamlet_status hamlet_velocity_field(hamlet_plan* plan, const void* modes, void* out);
+
 /* ---- Sphere moments of the velocity field ----
  *
  * Section 5 (monopole and dipole) follows the reconstruction by the moments

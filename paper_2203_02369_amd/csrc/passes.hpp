@@ -308,7 +308,8 @@ inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* _
 // ---------------------------------------------------------------------------
 // Inverse pass 2 (along y).  Tile: fixed x, kz chunk, all ky.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int NT>
+// ALL: every row is stored (the whole field is wanted; off is not read).
+template <typename T, int N, int NT, bool ALL = false>
 __device__ __forceinline__ void
 inv_y_body(const cplx_t<T>* __restrict__ inA, const cplx_t<T>* __restrict__ inB, const cplx_t<T>* __restrict__ tw,
         cplx_t<T>* __restrict__ vx, cplx_t<T>* __restrict__ vy, cplx_t<T>* __restrict__ vz, const int* __restrict__ off,
@@ -328,16 +329,16 @@ inv_y_body(const cplx_t<T>* __restrict__ inA, const cplx_t<T>* __restrict__ inB,
   PencilProbe<N> probe[PP];
 #pragma unroll
   for (int i = 0; i < PP; ++i)
-    if (threadIdx.x + i * NT < N) probe[i].load(off, x, threadIdx.x + i * NT);
+    if (!ALL && threadIdx.x + i * NT < N) probe[i].load(off, x, threadIdx.x + i * NT);
   TwiddleStage<T, N, NT> tws;
   tws.load(tw);
   tile_vecs<T, N, NT>([&](int, int y, int w) { vec_to_lds<T, LAY>(tile, y, w, vec_load<T>(&inB[gofs<N>(x, y, z0 + w)])); });
   tws.store(twl);
 #pragma unroll
   for (int i = 0; i < PP; ++i)
-    if (threadIdx.x + i * NT < N) touched[threadIdx.x + i * NT] = probe[i].touched();
+    if (!ALL && threadIdx.x + i * NT < N) touched[threadIdx.x + i * NT] = probe[i].touched();
   __syncthreads();
-  const unsigned rows = row_bits<T, N, NT>(touched);
+  const unsigned rows = ALL ? ~0u : row_bits<T, N, NT>(touched);
   lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
   tile_vecs<T, N, NT>([&](int e, int y, int w) {
     if ((rows >> e) & 1u) vec_store<T>(&vx[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY>(tile, y, w));
@@ -387,49 +388,18 @@ __device__ __forceinline__ int zslot_part(int p, int c) {
   return c == 0 ? 0 : (c == 1 ? 1 : (p & 1));
 }
 
-// ---------------------------------------------------------------------------
-// Inverse pass 3 (along z, complex-to-real) fused with the CIC gather.
-// Tile: fixed x, pencils y0 .. y0 + P (P = PassShape::PG).  Grid (N / P, N).
-// Writes, for every galaxy whose CIC stencil touches a pencil of the tile,
-// the column partials of its projected velocity (eqn:lvr):
-//   Pc = sum_c rhat_c [(1 - tz) v_c(z0) + tz v_c(z1)],  Qc = sum_c rhat_c [v_c(z1) - v_c(z0)]
-// into part[4 s + corner], corner = 2 (x - ix) + (y - iy).
-// ---------------------------------------------------------------------------
-template <typename T, int N, int NT>
+// The spectra of a z tile into LDS (a barrier must follow): for each
+// transform f of the tile (P pencils from y0), Z = A + i B with A, B the
+// Hermitian half spectra of its two real pencils (Nyquist entry zero, DC
+// entries real).  Pencils whose bit in tp is clear are taken as zero and not
+// loaded.
+template <typename T, int N, int NT, int P>
 __device__ __forceinline__ void
-inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ vy, const cplx_t<T>* __restrict__ vz,
-               const cplx_t<T>* __restrict__ tw, Binned<T> bins, cplx_t<T>* __restrict__ part, int x0) {
+z_tile_spectra(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ vy, const cplx_t<T>* __restrict__ vz,
+               int x, int y0, unsigned tp, cplx_t<T>* buf) {
   using C = cplx_t<T>;
-  using S = PassShape<T, N>;
-  using LAY = typename S::Pen;
-  constexpr int P = S::PG, H = S::H, F = S::FG;
-  __shared__ C buf[LAY::size(F)];
-  __shared__ C twl[N];
-  const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
-  // Gather: (pencil, corner, lane) per thread; lane strides the bucket.  The
-  // column range is loaded first, and (FP32) the first point before the
-  // transform, so that their latency overlaps the field loads and the FFT;
-  // the FP64 path loads its points after the transform, which keeps its
-  // registers, and occupancy, where they were.
-  constexpr int LANES = NT / (4 * P);
-  const int t = threadIdx.x;
-  const int pc = t % (4 * P), lane = t / (4 * P);
-  const int p = pc >> 2, corner = pc & 3;
-  const int ox = corner >> 1, oy = corner & 1;
-  const int y = y0 + p;
-  const int key = ((x - ox + N) & (N - 1)) * N + ((y - oy + N) & (N - 1));
-  const int s0 = bins.off[key], s1 = bins.off[key + 1];
-  load_twiddles<T, N, NT>(twl, tw);
-  // Pencils of the tile in reach of a point (see PencilProbe).  Every
-  // wave holds every (pencil, corner) in its lanes, so a ballot gives each
-  // wave the whole tile's flags.  The inverse y pass stored only these
-  // pencils; the others are transformed as zero and never read.
-  static_assert(64 % (4 * P) == 0 && NT % 64 == 0, "a wave covers the tile's stencil columns");
-  const unsigned long long occ = __ballot(s1 > s0);
-  unsigned tp = 0;
-#pragma unroll
-  for (int q = 0; q < P; ++q) tp |= ((occ >> (4 * q)) & 0xFull) ? 1u << q : 0u;
-  if (tp == 0) return;   // block-uniform: no point reaches the tile
+  using LAY = typename PassShape<T, N>::Pen;
+  constexpr int H = N / 2, F = 3 * P / 2;
   auto touched = [&](int q) { return ((tp >> q) & 1u) != 0; };
   // Build Z = A + i B with A, B the Hermitian half spectra of the two real
   // pencils of each transform (Nyquist entry zero, DC entries real).
@@ -515,6 +485,52 @@ inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict_
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse pass 3 (along z, complex-to-real) fused with the CIC gather.
+// Tile: fixed x, pencils y0 .. y0 + P (P = PassShape::PG).  Grid (N / P, N).
+// Writes, for every galaxy whose CIC stencil touches a pencil of the tile,
+// the column partials of its projected velocity (eqn:lvr):
+//   Pc = sum_c rhat_c [(1 - tz) v_c(z0) + tz v_c(z1)],  Qc = sum_c rhat_c [v_c(z1) - v_c(z0)]
+// into part[4 s + corner], corner = 2 (x - ix) + (y - iy).
+// ---------------------------------------------------------------------------
+template <typename T, int N, int NT>
+__device__ __forceinline__ void
+inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ vy, const cplx_t<T>* __restrict__ vz,
+               const cplx_t<T>* __restrict__ tw, Binned<T> bins, cplx_t<T>* __restrict__ part, int x0) {
+  using C = cplx_t<T>;
+  using S = PassShape<T, N>;
+  using LAY = typename S::Pen;
+  constexpr int P = S::PG, H = S::H, F = S::FG;
+  __shared__ C buf[LAY::size(F)];
+  __shared__ C twl[N];
+  const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
+  // Gather: (pencil, corner, lane) per thread; lane strides the bucket.  The
+  // column range is loaded first, and (FP32) the first point before the
+  // transform, so that their latency overlaps the field loads and the FFT;
+  // the FP64 path loads its points after the transform, which keeps its
+  // registers, and occupancy, where they were.
+  constexpr int LANES = NT / (4 * P);
+  const int t = threadIdx.x;
+  const int pc = t % (4 * P), lane = t / (4 * P);
+  const int p = pc >> 2, corner = pc & 3;
+  const int ox = corner >> 1, oy = corner & 1;
+  const int y = y0 + p;
+  const int key = ((x - ox + N) & (N - 1)) * N + ((y - oy + N) & (N - 1));
+  const int s0 = bins.off[key], s1 = bins.off[key + 1];
+  load_twiddles<T, N, NT>(twl, tw);
+  // Pencils of the tile in reach of a point (see PencilProbe).  Every
+  // wave holds every (pencil, corner) in its lanes, so a ballot gives each
+  // wave the whole tile's flags.  The inverse y pass stored only these
+  // pencils; the others are transformed as zero and never read.
+  static_assert(64 % (4 * P) == 0 && NT % 64 == 0, "a wave covers the tile's stencil columns");
+  const unsigned long long occ = __ballot(s1 > s0);
+  unsigned tp = 0;
+#pragma unroll
+  for (int q = 0; q < P; ++q) tp |= ((occ >> (4 * q)) & 0xFull) ? 1u << q : 0u;
+  if (tp == 0) return;   // block-uniform: no point reaches the tile
+  z_tile_spectra<T, N, NT, P>(vx, vy, vz, x, y0, tp, buf);
   __syncthreads();
   constexpr bool kEarly = sizeof(T) == 4;
   int s = s0 + lane;
@@ -542,6 +558,37 @@ inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict_
     const T qcv = rx * (a1.x - a0.x) + ry * (a1.y - a0.y) + rz * (az1 - az0);
     part[4 * (size_t)s + corner] = cmake<C>(pcv, qcv);
     if (kEarly && s + LANES < s1) load_point(s + LANES);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse pass 3 writing the velocity field itself: the transform of the
+// gather's tile (every pencil), then out[c][x][y][z] = v_c at node (x, y, z),
+// c = x, y, z.  Used to hand a state's field to the caller, not inside an
+// evaluation.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int NT>
+__device__ __forceinline__ void
+inv_z_field_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ vy, const cplx_t<T>* __restrict__ vz,
+                 const cplx_t<T>* __restrict__ tw, T* __restrict__ out, int x0) {
+  using C = cplx_t<T>;
+  using S = PassShape<T, N>;
+  using LAY = typename S::Pen;
+  constexpr int P = S::PG, F = S::FG;
+  __shared__ C buf[LAY::size(F)];
+  __shared__ C twl[N];
+  const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
+  load_twiddles<T, N, NT>(twl, tw);
+  z_tile_spectra<T, N, NT, P>(vx, vy, vz, x, y0, (1u << P) - 1u, buf);
+  __syncthreads();
+  lds_fft<T, N, F, LAY, NT, +1>(buf, twl);
+  // (pencil, component, z) with z fastest: each row of N values is one
+  // contiguous store
+  for (int idx = threadIdx.x; idx < P * 3 * N; idx += NT) {
+    const int z = idx % N, pc = idx / N;
+    const int p = pc / 3, c = pc % 3;
+    const C v = buf[LAY::idx(z, zslot_f(p, c))];
+    out[(((size_t)c * N + x) * N + (y0 + p)) * N + z] = zslot_part(p, c) ? v.y : v.x;
   }
 }
 
@@ -1077,6 +1124,20 @@ __global__ void __launch_bounds__(NT) k_inv_y(Launch L, int x0) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
   inv_y_body<T, N, NT>(k.w.a(), k.w.b(), k.w.tw(), k.w.v0(), k.w.v1(), k.w.v2(), k.w.off(), x0);
+}
+
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT) k_inv_y_all(Launch L, int x0) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  inv_y_body<T, N, NT, true>(k.w.a(), k.w.b(), k.w.tw(), k.w.v0(), k.w.v1(), k.w.v2(), nullptr, x0);
+}
+
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT) k_inv_z_field(Launch L, int x0, T* out) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  inv_z_field_body<T, N, NT>(k.w.v0(), k.w.v1(), k.w.v2(), k.w.tw(), out, x0);
 }
 
 template <typename T, int N, int NT>

@@ -219,6 +219,21 @@ def unpack_flat(plan, flat, modes, dist, snl):
                                                 ctypes.c_void_p(m), _ptr(d), _ptr(s)))
 
 
+def velocity_field(plan, modes, out=None):
+    """The velocity field v_c (km/s) of a state's modes on every grid node, on
+    the plan's stream (hamlet_velocity_field): a device tensor (3, N, N, N) of
+    the plan's real type."""
+    n = plan.n_grid
+    dt = torch.float64 if plan.precision == "fp64" else torch.float32
+    if out is None:
+        out = torch.empty((3, n, n, n), dtype=dt, device=plan.device)
+    elif out.dtype != dt or tuple(out.shape) != (3, n, n, n) or not out.is_contiguous():
+        raise ValueError("out must be contiguous %s (3, %d, %d, %d)" % (dt, n, n, n))
+    m = _check(modes, plan, "modes", "modes")
+    _capi.check(_capi.load().hamlet_velocity_field(plan.handle, ctypes.c_void_p(m), ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
 def sphere_moments(plan, modes, radii, out=None):
     """Monopole and dipole of the velocity field in spheres of the given radii
     (Mpc/h) about the observer, on the plan's stream (hamlet_sphere_moments):

@@ -95,6 +95,13 @@ def test_server_entry_points_validate_on_the_host():
     assert lib.hamlet_server_destroy(None) == 0
 
 
+def test_velocity_field_validates_on_the_host():
+    from paper_2203_02369_amd import _capi
+    lib = _capi.load()
+    assert lib.hamlet_velocity_field(None, None, None) == -1
+    assert b"NULL" in lib.hamlet_last_error()
+
+
 def test_sphere_moments_validate_on_the_host():
     from paper_2203_02369_amd import _capi
     lib = _capi.load()
