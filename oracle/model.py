@@ -282,6 +282,13 @@ def velocity_grids(prob, dhat):
     return out
 
 
+def density_grid(prob, dhat):
+    """delta(x_j) = N^-3 sum_k dhat_k exp(+i k.x_j) on every node (the Fourier
+    convention of eq:prior-k's modes); excluded modes are zero in dhat."""
+    n = prob.n_grid
+    return (ifftn_unnormalised(full_spectrum(dhat)) / float(n) ** 3).real
+
+
 def galaxy_positions(prob, d):
     """x_i = o + d_i rhat_i with the observer at o = (L/2)(1, 1, 1)."""
     return 0.5 * prob.box + np.asarray(d)[:, None] * prob.rhat

@@ -140,6 +140,42 @@ def test_divergence_identity_per_mode():
     assert np.all(mult[:, ~keep] == 0)
 
 
+def test_density_grid_is_the_direct_mode_sum():
+    # delta(x_j) = N^-3 sum_k dhat_k e^{i k.x_j}, summed directly over all N^3
+    # modes (the half spectrum's mirror entries conjugated) on an 8^3 grid
+    m, prob = _problem(n_grid=8, box=80.0)
+    n = prob.n_grid
+    rng = np.random.default_rng(2)
+    shape = model.half_shape(n)
+    dhat = hmc.symmetrise(n, rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+    got = model.density_grid(prob, dhat)
+    s = model.signed_index(n)
+    ref = np.zeros((n, n, n))
+    j = np.arange(n)
+    for a in range(n):
+        for b in range(n):
+            for c in range(n):
+                # stored entry of (s_a, s_b, s_c) or the conjugate of (-k)'s
+                if s[c] >= 0:
+                    v = dhat[a, b, s[c]]
+                else:
+                    v = np.conj(dhat[(-s[a]) % n, (-s[b]) % n, -s[c]])
+                ph = np.exp(2j * math.pi * (s[a] * j[:, None, None] + s[b] * j[None, :, None]
+                                           + s[c] * j[None, None, :]) / n)
+                ref += (v * ph).real
+    ref /= n ** 3
+    assert np.allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    # and the linear continuity relation with the velocity grids: -div v / H0 = f delta,
+    # the divergence taken spectrally from the oracle's own velocity field
+    v = model.velocity_grids(prob, dhat)
+    kf = 2 * math.pi / prob.box
+    k = kf * np.fft.fftfreq(n, d=1.0 / n)
+    div = sum(np.fft.ifftn(1j * kk * np.fft.fftn(v[a])).real
+              for a, kk in enumerate((k[:, None, None], k[None, :, None], k[None, None, :])))
+    # Nyquist components are excluded from the modes, so the relation is exact
+    assert np.allclose(-div / model.H0, prob.f_growth * got, atol=1e-9 * np.abs(got).max() * prob.f_growth)
+
+
 # ------------------------------------------------------------------ the CIC --
 
 def test_cic_reproduces_constant_and_linear_fields():
