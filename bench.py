@@ -48,9 +48,9 @@ HBM_PEAK_GBS = 8000.0
 # (--copy-calibration: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  Bytes read and
 # written per launch for the plain-gradient, first, middle and last variants.
 # Valid only for the kernel sources they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "4a8e5ee4cd5e7b8237a30e56b9b5a79e3e016045"
-X_TRAFFIC = {"grad": (334163933, 134218192), "first": (358770877, 703788704),
-             "mid": (468539046, 401674936), "last": (468405644, 268503435)}
+X_TRAFFIC_SOURCES_SHA1 = "209d30f89a36ef917279a3cc2741d6a24eb7fccf"
+X_TRAFFIC = {"grad": (334168061, 134217776), "first": (358662209, 703777705),
+             "mid": (468539014, 401674702), "last": (468405644, 268503008)}
 
 
 def kernel_sources_sha1():
@@ -239,6 +239,20 @@ def main():
                                   "achieved": round(vf_bytes / (vf_ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
     log("velocity field: %.3f ms per call" % vf_ms)
     del vf
+    # the density contrast of the state: the velocity field's passes with one
+    # grid out move 14c; a density-only chain of passes would move 7c
+    dg = hamlet.density_field(plan, q)
+    ev0.record(plan.stream)
+    for _ in range(5):
+        hamlet.density_field(plan, q, out=dg)
+    ev1.record(plan.stream)
+    ev1.synchronize()
+    dg_ms = ev0.elapsed_time(ev1) / 5
+    analysis["density_field"] = {"avg_call_ms": round(dg_ms, 4), "bytes_per_call": 14 * c_bytes,
+                                 "density_only_minimum_bytes": 7 * c_bytes,
+                                 "achieved": round(14 * c_bytes / (dg_ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
+    log("density field: %.3f ms per call" % dg_ms)
+    del dg
     plan.close()
     del q, qd, qs
 

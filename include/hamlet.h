@@ -230,6 +230,13 @@ hamlet_status hamlet_unpack_flat(hamlet_plan* plan, const double* flat, void* mo
  * buffers.  Asynchronous on the plan's stream. */
 hamlet_status hamlet_velocity_field(hamlet_plan* plan, const void* modes, void* out);
 
+/* The density contrast delta(x_j) = N^-3 sum_k dhat_k exp(i k.x_j) of a state
+ * on every node (the modes' Fourier convention, eq:prior-k), e.g. for the
+ * maps of the mean and the scatter of delta (Section 5).  modes as above;
+ * out (device): N^3 reals of the plan's precision, out[(x N + y) N + z].
+ * Uses the plan's workspace; errors and ordering as above. */
+hamlet_status hamlet_density_field(hamlet_plan* plan, const void* modes, void* out);
+
 /* ---- Sphere moments of the velocity field ----
  *
  * Section 5 (monopole and dipole) follows the reconstruction by the moments

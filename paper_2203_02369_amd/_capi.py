@@ -103,6 +103,7 @@ SIGNATURES = {
     "hamlet_sphere_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, ctypes.c_int32,
                                              c_double_p]),
     "hamlet_velocity_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hamlet_density_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hamlet_server_create": (ctypes.c_int, [ctypes.POINTER(ServerDesc), ctypes.c_void_p,
                                             ctypes.POINTER(ctypes.c_void_p)]),
     "hamlet_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),

@@ -78,7 +78,8 @@ struct Ops {
   hamlet_status (*leap_out)(const Batch&);   // Psi of a leapfrog end point to the caller
   size_t (*bytes)(int n_gal, int n_hist);    // workspace size
   void (*locate)(hamlet_plan*);              // host copies of the workspace addresses it needs
-  hamlet_status (*field)(const Batch&, void*);  // the velocity field of the plan's modes, to the caller
+  hamlet_status (*field)(const Batch&, void*);    // the velocity field of the plan's modes, to the caller
+  hamlet_status (*density)(const Batch&, void*);  // the density contrast of the plan's modes, to the caller
 };
 
 struct hamlet_plan {
@@ -260,6 +261,26 @@ static hamlet_status field_impl(const Batch& b, void* out) {
   return HAMLET_OK;
 }
 
+// The density contrast of one plan's modes on every grid node: the same
+// passes with q / N^3 for the velocity multiplier, the third array written.
+template <typename T, int N>
+static hamlet_status density_impl(const Batch& b, void* out) {
+  using S = PassShape<T, N>;
+  using TH = PassThreads<T, N>;
+  using SL = XSlabs<N>;
+  hipStream_t st = b.stream;
+  const Launch sel = launch_table(b);
+  const unsigned nb = (unsigned)b.count;
+  k_inv_x_density<T, N, TH::XY><<<dim3(S::CHUNKS, N, nb), TH::XY, 0, st>>>(sel);
+  for (int sl = 0; sl < SL::COUNT; ++sl) {
+    const int x0 = sl * SL::SIZE;
+    k_inv_y_all<T, N, TH::XY><<<dim3(S::CHUNKS, SL::SIZE, nb), TH::XY, 0, st>>>(sel, x0);
+    k_inv_z_field<T, N, TH::ZG, true><<<dim3(N / S::PG, SL::SIZE, nb), TH::ZG, 0, st>>>(sel, x0, (T*)out);
+  }
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
 static int batch_gal_or_one(const Batch& b) {
   int m = 1;
   for (int i = 0; i < b.count; ++i) m = std::max(m, b.plan[i]->n_gal);
@@ -368,7 +389,8 @@ template <typename T, int N> static void locate_impl(hamlet_plan* pl) {
 
 template <typename T, int N> struct OpsFor {
   static constexpr Ops ops{eval_impl<T, N>,      start_impl<T, N>, first_impl<T, N>,  end_impl<T, N>,
-                           leap_out_impl<T, N>,   bytes_impl<T, N>, locate_impl<T, N>, field_impl<T, N>};
+                           leap_out_impl<T, N>,   bytes_impl<T, N>, locate_impl<T, N>, field_impl<T, N>,
+                           density_impl<T, N>};
 };
 
 template <typename T> static const Ops* pick_ops(int n) {
@@ -1058,6 +1080,19 @@ extern "C" hamlet_status hamlet_velocity_field(hamlet_plan* plan, const void* mo
   sd.q = (double2*)modes;
   plan->st = sd;
   return plan->ops->field(b, out);
+}
+
+extern "C" hamlet_status hamlet_density_field(hamlet_plan* plan, const void* modes, void* out) {
+  if (!plan || !modes || !out) return fail(HAMLET_EINVAL, "NULL argument");
+  Batch b;
+  b.stream = plan->stream;
+  b.count = 1;
+  b.plan[0] = plan;
+  b.mode[0] = kXGrad;
+  StateDev sd{};
+  sd.q = (double2*)modes;
+  plan->st = sd;
+  return plan->ops->density(b, out);
 }
 
 // ---------------------------------------------------------------------------

@@ -261,7 +261,9 @@ __host__ __device__ inline size_t var_ofs(int n, int w, int kx, int ky, int kz) 
 // Inverse pass 1 (along x): multiplier, prior energy, two spectral outputs.
 // Tile: fixed ky, kz chunk, all kx.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int NT>
+// DENSITY: A = q / N^3 (the density contrast's spectrum) instead of the
+// velocity multiplier's i kfac q.
+template <typename T, int N, int NT, bool DENSITY = false>
 __device__ __forceinline__ void
 inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* __restrict__ tw,
         cplx_t<T>* __restrict__ outA, cplx_t<T>* __restrict__ outB, double* __restrict__ prior_part) {
@@ -281,6 +283,10 @@ inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* _
     const int kz = z0 + w, sx = signed_freq(x, N);
     if (!retained(sx, sy, kz, N)) return make_double2(0.0, 0.0);
     const double2 q = modes[gofs<N>(x, y, kz)];
+    if constexpr (DENSITY) {
+      const double sc = (scale_x != 0.0 ? scale_x * sx : 1.0) / ((double)N * N * N);
+      return make_double2(sc * q.x, sc * q.y);
+    }
     const double kf = mode_kfac(tab.kfac0, sx * sx + sy * sy + kz * kz) * (scale_x != 0.0 ? scale_x * sx : 1.0);
     return make_double2(-kf * q.y, kf * q.x);
   };
@@ -393,7 +399,9 @@ __device__ __forceinline__ int zslot_part(int p, int c) {
 // Hermitian half spectra of its two real pencils (Nyquist entry zero, DC
 // entries real).  Pencils whose bit in tp is clear are taken as zero and not
 // loaded.
-template <typename T, int N, int NT, int P>
+// NZ: the third array carries n_z (velocity component z); without it the
+// third array is taken as it is (a scalar field).
+template <typename T, int N, int NT, int P, bool NZ = true>
 __device__ __forceinline__ void
 z_tile_spectra(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ vy, const cplx_t<T>* __restrict__ vz,
                int x, int y0, unsigned tp, cplx_t<T>* buf) {
@@ -446,7 +454,7 @@ z_tile_spectra(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ v
       if (idx < F * H2) {
         const int k = 2 * (idx % H2), f = idx / H2;
         int pa, pb;
-        if (sources(f, pa, pb)) {
+        if (sources(f, pa, pb) && NZ) {
           av[it].a = cscale(av[it].a, (T)k);
           av[it].b = cscale(av[it].b, (T)(k + 1));
           bv[it].a = cscale(bv[it].a, (T)k);
@@ -477,7 +485,7 @@ z_tile_spectra(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ v
       if (idx < F * H) {
         const int k = idx % H, f = idx / H;
         int pa, pb;
-        if (sources(f, pa, pb)) {
+        if (sources(f, pa, pb) && NZ) {
           av[it] = cscale(av[it], (T)k);
           bv[it] = cscale(bv[it], (T)k);
         }
@@ -567,7 +575,9 @@ inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict_
 // c = x, y, z.  Used to hand a state's field to the caller, not inside an
 // evaluation.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int NT>
+// DENSITY: the third array is the density spectrum (no n_z), and only it is
+// written: out[x][y][z].
+template <typename T, int N, int NT, bool DENSITY = false>
 __device__ __forceinline__ void
 inv_z_field_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ vy, const cplx_t<T>* __restrict__ vz,
                  const cplx_t<T>* __restrict__ tw, T* __restrict__ out, int x0) {
@@ -579,16 +589,17 @@ inv_z_field_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__
   __shared__ C twl[N];
   const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
   load_twiddles<T, N, NT>(twl, tw);
-  z_tile_spectra<T, N, NT, P>(vx, vy, vz, x, y0, (1u << P) - 1u, buf);
+  z_tile_spectra<T, N, NT, P, !DENSITY>(vx, vy, vz, x, y0, (1u << P) - 1u, buf);
   __syncthreads();
   lds_fft<T, N, F, LAY, NT, +1>(buf, twl);
   // (pencil, component, z) with z fastest: each row of N values is one
   // contiguous store
-  for (int idx = threadIdx.x; idx < P * 3 * N; idx += NT) {
+  constexpr int NC = DENSITY ? 1 : 3;
+  for (int idx = threadIdx.x; idx < P * NC * N; idx += NT) {
     const int z = idx % N, pc = idx / N;
-    const int p = pc / 3, c = pc % 3;
+    const int p = pc / NC, c = DENSITY ? 2 : pc % 3;
     const C v = buf[LAY::idx(z, zslot_f(p, c))];
-    out[(((size_t)c * N + x) * N + (y0 + p)) * N + z] = zslot_part(p, c) ? v.y : v.x;
+    out[(((size_t)(DENSITY ? 0 : c) * N + x) * N + (y0 + p)) * N + z] = zslot_part(p, c) ? v.y : v.x;
   }
 }
 
@@ -1133,11 +1144,18 @@ __global__ void __launch_bounds__(NT) k_inv_y_all(Launch L, int x0) {
   inv_y_body<T, N, NT, true>(k.w.a(), k.w.b(), k.w.tw(), k.w.v0(), k.w.v1(), k.w.v2(), nullptr, x0);
 }
 
-template <typename T, int N, int NT>
+template <typename T, int N, int NT, bool DENSITY = false>
 __global__ void __launch_bounds__(NT) k_inv_z_field(Launch L, int x0, T* out) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
-  inv_z_field_body<T, N, NT>(k.w.v0(), k.w.v1(), k.w.v2(), k.w.tw(), out, x0);
+  inv_z_field_body<T, N, NT, DENSITY>(k.w.v0(), k.w.v1(), k.w.v2(), k.w.tw(), out, x0);
+}
+
+template <typename T, int N, int NT>
+__global__ void __launch_bounds__(NT) k_inv_x_density(Launch L) {
+  const Pick<T, N> k(L);
+  if (k.mode != kXGrad) return;
+  inv_x_body<T, N, NT, true>(k.st.q, tables(k.w), k.w.tw(), k.w.a(), k.w.b(), k.w.prior_part());
 }
 
 template <typename T, int N, int NT>

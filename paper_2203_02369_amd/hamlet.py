@@ -234,6 +234,21 @@ def velocity_field(plan, modes, out=None):
     return out
 
 
+def density_field(plan, modes, out=None):
+    """The density contrast of a state's modes on every grid node, on the
+    plan's stream (hamlet_density_field): a device tensor (N, N, N) of the
+    plan's real type."""
+    n = plan.n_grid
+    dt = torch.float64 if plan.precision == "fp64" else torch.float32
+    if out is None:
+        out = torch.empty((n, n, n), dtype=dt, device=plan.device)
+    elif out.dtype != dt or tuple(out.shape) != (n, n, n) or not out.is_contiguous():
+        raise ValueError("out must be contiguous %s (%d, %d, %d)" % (dt, n, n, n))
+    m = _check(modes, plan, "modes", "modes")
+    _capi.check(_capi.load().hamlet_density_field(plan.handle, ctypes.c_void_p(m), ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
 def sphere_moments(plan, modes, radii, out=None):
     """Monopole and dipole of the velocity field in spheres of the given radii
     (Mpc/h) about the observer, on the plan's stream (hamlet_sphere_moments):

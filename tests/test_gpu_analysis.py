@@ -125,3 +125,22 @@ def test_velocity_field_matches_the_oracle(hl, precision, n):
     plan.close()
     tol = 1e-12 if precision == "fp64" else 1e-5
     assert np.abs(v - ref).max() <= tol * np.abs(ref).max(), np.abs(v - ref).max() / np.abs(ref).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [32, 64])
+def test_density_field_matches_the_oracle(hl, precision, n):
+    # the density contrast of a state on every node (hamlet_density_field)
+    # against the oracle's density grid
+    from oracle import model
+    m = mocks.plain_fp64_32() if n == 32 else mocks.make_mock(64, 500.0, 2000, 250.0, "inv_r", seed=33)
+    prob = oracle_problem(m)
+    dhat = start_modes(m)
+    ref = model.density_grid(prob, dhat)
+    say("density field", n, precision)
+    plan = hl.Plan.from_mock(m, precision=precision)
+    q = torch.from_numpy(to_lib_layout(dhat)).to(plan.device)
+    dens = hl.density_field(plan, q).double().cpu().numpy()
+    plan.close()
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert np.abs(dens - ref).max() <= tol * np.abs(ref).max(), np.abs(dens - ref).max() / np.abs(ref).max()
