@@ -144,3 +144,25 @@ def test_density_field_matches_the_oracle(hl, precision, n):
     plan.close()
     tol = 1e-12 if precision == "fp64" else 1e-5
     assert np.abs(dens - ref).max() <= tol * np.abs(ref).max(), np.abs(dens - ref).max() / np.abs(ref).max()
+
+
+def test_fields_at_the_paper_scale(hl):
+    # the velocity and density fields of a state of the 256^3 benchmark,
+    # every node, in the precision the benchmark runs (FP32 fields)
+    from oracle import model
+    m = mocks.paper_scale_256()
+    prob = oracle_problem(m)
+    dhat = start_modes(m)
+    say("fields 256^3 fp32")
+    plan = hl.Plan.from_mock(m, precision="fp32")
+    q = torch.from_numpy(to_lib_layout(dhat)).to(plan.device)
+    v = hl.velocity_field(plan, q).double().cpu().numpy()
+    dens = hl.density_field(plan, q).double().cpu().numpy()
+    plan.close()
+    say("oracle density 256^3")
+    ref = model.density_grid(prob, dhat)
+    assert np.abs(dens - ref).max() <= 1e-5 * np.abs(ref).max(), np.abs(dens - ref).max() / np.abs(ref).max()
+    del dens, ref
+    say("oracle velocity 256^3")
+    ref = model.velocity_grids(prob, dhat)
+    assert np.abs(v - ref).max() <= 1e-5 * np.abs(ref).max(), np.abs(v - ref).max() / np.abs(ref).max()
