@@ -253,6 +253,19 @@ def main():
                                  "achieved": round(14 * c_bytes / (dg_ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
     log("density field: %.3f ms per call" % dg_ms)
     del dg
+    # a state added to the running sums of delta, v_r and their squares:
+    # both chains of passes, the sums read and written in FP64 (42c)
+    acc = hamlet.field_stats_accumulate(plan, q)
+    ev0.record(plan.stream)
+    for _ in range(3):
+        hamlet.field_stats_accumulate(plan, q, acc)
+    ev1.record(plan.stream)
+    ev1.synchronize()
+    fs_ms = ev0.elapsed_time(ev1) / 3
+    analysis["field_stats_accumulate"] = {"avg_call_ms": round(fs_ms, 4), "bytes_per_call": 42 * c_bytes,
+                                          "achieved": round(42 * c_bytes / (fs_ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
+    log("field statistics: %.3f ms per state" % fs_ms)
+    del acc
     plan.close()
     del q, qd, qs
 

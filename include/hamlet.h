@@ -237,6 +237,19 @@ hamlet_status hamlet_velocity_field(hamlet_plan* plan, const void* modes, void* 
  * Uses the plan's workspace; errors and ordering as above. */
 hamlet_status hamlet_density_field(hamlet_plan* plan, const void* modes, void* out);
 
+/* Adds one state's density contrast delta and radial velocity v_r (km/s) on
+ * every node, and their squares, to running sums, for the maps of the chain's
+ * mean field and of its scatter Sigma(r) along the chain (Section 5): with
+ * n states summed, mean = S1 / n and variance = S2 / n - mean^2.  v_r is the
+ * velocity field's component along r = x - o from the observer o =
+ * (L/2)(1, 1, 1), which is node N/2 of each axis; v_r = 0 on that node.
+ * modes as above; acc (device, caller-owned): 4 N^3 doubles, the grids
+ * [sum delta, sum delta^2, sum v_r, sum v_r^2], each [(x N + y) N + z];
+ * zero it before the first state.  The values are added in the plan's
+ * precision and summed in double.  Uses the plan's workspace; errors and
+ * ordering as above. */
+hamlet_status hamlet_field_stats_accumulate(hamlet_plan* plan, const void* modes, double* acc);
+
 /* ---- Sphere moments of the velocity field ----
  *
  * Section 5 (monopole and dipole) follows the reconstruction by the moments

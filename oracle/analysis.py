@@ -1,5 +1,7 @@
-"""Oracle of the monopole and dipole moments of the velocity field in spheres
-about the observer (Section 5, "Monopole and dipole").
+"""Oracle of the chain's field statistics of Section 5: the monopole and
+dipole moments of the velocity field in spheres about the observer
+("Monopole and dipole"), and the maps of the mean and the scatter along the
+chain of the density contrast and of the radial velocity.
 
 TEST INFRASTRUCTURE ONLY.  Plain FP64 numpy written from the definitions;
 only the test suite, the smoke check and the CPU baseline leg of the
@@ -103,3 +105,34 @@ def sphere_moments_abs(prob, dhat, radii):
         w = np.abs(tophat_window(kmag * r))
         out.append([norm * np.sum(prob.f_growth * keep * full * w)] + [norm * np.sum(mc * full * w) for mc in m])
     return np.array(out)
+
+
+def radial_velocity_grid(prob, dhat):
+    """v_r(x_j) = v(x_j) . (x_j - o) / |x_j - o| on every node x_j = j L / N,
+    the observer at o = (L/2)(1, 1, 1); 0 at the observer itself.  Shape
+    (N, N, N)."""
+    n = prob.n_grid
+    v = model.velocity_grids(prob, dhat)
+    pos = np.arange(n) * (prob.box / n) - 0.5 * prob.box
+    rx, ry, rz = np.meshgrid(pos, pos, pos, indexing="ij")
+    r = np.sqrt(rx * rx + ry * ry + rz * rz)
+    dot = v[0] * rx + v[1] * ry + v[2] * rz
+    return np.where(r > 0, dot / np.where(r > 0, r, 1.0), 0.0)
+
+
+def field_sums(prob, states):
+    """Running sums over a chain's states of the density contrast and the
+    radial velocity on the grid and of their squares:
+    array (4, N, N, N) = [sum delta, sum delta^2, sum v_r, sum v_r^2].  With
+    n states, the mean map is S1 / n and the scatter map Sigma^2 is
+    S2 / n - (S1 / n)^2."""
+    n = prob.n_grid
+    out = np.zeros((4, n, n, n))
+    for dhat in states:
+        delta = model.density_grid(prob, dhat)
+        vr = radial_velocity_grid(prob, dhat)
+        out[0] += delta
+        out[1] += delta * delta
+        out[2] += vr
+        out[3] += vr * vr
+    return out

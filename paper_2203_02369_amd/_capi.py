@@ -104,6 +104,7 @@ SIGNATURES = {
                                              c_double_p]),
     "hamlet_velocity_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hamlet_density_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hamlet_field_stats_accumulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hamlet_server_create": (ctypes.c_int, [ctypes.POINTER(ServerDesc), ctypes.c_void_p,
                                             ctypes.POINTER(ctypes.c_void_p)]),
     "hamlet_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),

@@ -14,6 +14,9 @@
 // sums stay in registers); every block writes its partial sums, and a second
 // kernel adds them in block order, so the result does not depend on timing.
 // FP64 throughout: the modes are the FP64 masters in both precisions.
+//
+// Also: the last inverse pass of the field maps in a form that adds a state's
+// density contrast or radial velocity, and its square, to running sums.
 #pragma once
 
 #include "common.hpp"
@@ -101,6 +104,57 @@ __global__ void __launch_bounds__(256) k_sphere_moments_sum(const double* __rest
   for (int b = threadIdx.x; b < kMomentsBlocks; b += blockDim.x) s[0] += p[(size_t)b * kMomentsPassValues];
   block_sums<1>(s, red);
   if (threadIdx.x == 0) out[t] = s[0];
+}
+
+// ---------------------------------------------------------------------------
+// Inverse pass 3 adding a state's field to running sums on every node, for
+// the chain's mean and scatter maps: DENSITY, delta (the third array of the
+// density passes); otherwise the radial velocity v_r = v . r / |r| about the observer
+// o = (L/2)(1, 1, 1), which sits on node N/2 of each axis (v_r = 0 there).
+// acc[g] += value and acc[N^3 + g] += value^2, g = (x N + y) N + z; every
+// node belongs to one thread, so the updates need no atomics.
+template <typename T, int N, int NT, bool DENSITY>
+__device__ __forceinline__ void
+inv_z_acc_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ vy, const cplx_t<T>* __restrict__ vz,
+               const cplx_t<T>* __restrict__ tw, double* __restrict__ acc, int x0) {
+  using C = cplx_t<T>;
+  using S = PassShape<T, N>;
+  using LAY = typename S::Pen;
+  constexpr int P = S::PG, F = S::FG;
+  constexpr size_t kGrid = (size_t)N * N * N;
+  __shared__ C buf[LAY::size(F)];
+  __shared__ C twl[N];
+  const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
+  load_twiddles<T, N, NT>(twl, tw);
+  z_tile_spectra<T, N, NT, P, !DENSITY>(vx, vy, vz, x, y0, (1u << P) - 1u, buf);
+  __syncthreads();
+  lds_fft<T, N, F, LAY, NT, +1>(buf, twl);
+  auto comp = [&](int p, int c, int z) {
+    const C v = buf[LAY::idx(z, zslot_f(p, c))];
+    return (double)(zslot_part(p, c) ? v.y : v.x);
+  };
+  for (int idx = threadIdx.x; idx < P * N; idx += NT) {
+    const int z = idx % N, p = idx / N;
+    double val;
+    if constexpr (DENSITY) {
+      val = comp(p, 2, z);
+    } else {
+      const int rx = x - N / 2, ry = y0 + p - N / 2, rz = z - N / 2;
+      const int r2 = rx * rx + ry * ry + rz * rz;
+      const double dot = rx * comp(p, 0, z) + ry * comp(p, 1, z) + rz * comp(p, 2, z);
+      val = r2 > 0 ? dot / sqrt((double)r2) : 0.0;
+    }
+    const size_t g = ((size_t)x * N + (y0 + p)) * N + z;
+    acc[g] += val;
+    acc[kGrid + g] += val * val;
+  }
+}
+
+template <typename T, int N, int NT, bool DENSITY>
+__global__ void __launch_bounds__(NT) k_inv_z_acc(Launch L, int x0, double* acc) {
+  const Pick<T, N> k(L);
+  if (k.mode == kXSkip) return;
+  inv_z_acc_body<T, N, NT, DENSITY>(k.w.v0(), k.w.v1(), k.w.v2(), k.w.tw(), acc, x0);
 }
 
 }  // namespace hamlet

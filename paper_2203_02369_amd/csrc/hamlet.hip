@@ -80,6 +80,7 @@ struct Ops {
   void (*locate)(hamlet_plan*);              // host copies of the workspace addresses it needs
   hamlet_status (*field)(const Batch&, void*);    // the velocity field of the plan's modes, to the caller
   hamlet_status (*density)(const Batch&, void*);  // the density contrast of the plan's modes, to the caller
+  hamlet_status (*stats)(const Batch&, double*);  // delta, v_r and their squares added to running sums
 };
 
 struct hamlet_plan {
@@ -281,6 +282,35 @@ static hamlet_status density_impl(const Batch& b, void* out) {
   return HAMLET_OK;
 }
 
+// One state's delta and radial velocity added to the caller's running sums
+// acc = [sum delta, sum delta^2, sum v_r, sum v_r^2] (N^3 each): the passes
+// of the velocity field, then those of the density contrast, each ending in
+// a z pass that adds instead of storing.
+template <typename T, int N>
+static hamlet_status stats_impl(const Batch& b, double* acc) {
+  using S = PassShape<T, N>;
+  using TH = PassThreads<T, N>;
+  using SL = XSlabs<N>;
+  constexpr size_t kGrid = (size_t)N * N * N;
+  hipStream_t st = b.stream;
+  const Launch sel = launch_table(b);
+  const unsigned nb = (unsigned)b.count;
+  k_inv_x<T, N, TH::XY><<<dim3(S::CHUNKS, N, nb), TH::XY, 0, st>>>(sel);
+  for (int sl = 0; sl < SL::COUNT; ++sl) {
+    const int x0 = sl * SL::SIZE;
+    k_inv_y_all<T, N, TH::XY><<<dim3(S::CHUNKS, SL::SIZE, nb), TH::XY, 0, st>>>(sel, x0);
+    k_inv_z_acc<T, N, TH::ZG, false><<<dim3(N / S::PG, SL::SIZE, nb), TH::ZG, 0, st>>>(sel, x0, acc + 2 * kGrid);
+  }
+  k_inv_x_density<T, N, TH::XY><<<dim3(S::CHUNKS, N, nb), TH::XY, 0, st>>>(sel);
+  for (int sl = 0; sl < SL::COUNT; ++sl) {
+    const int x0 = sl * SL::SIZE;
+    k_inv_y_all<T, N, TH::XY><<<dim3(S::CHUNKS, SL::SIZE, nb), TH::XY, 0, st>>>(sel, x0);
+    k_inv_z_acc<T, N, TH::ZG, true><<<dim3(N / S::PG, SL::SIZE, nb), TH::ZG, 0, st>>>(sel, x0, acc);
+  }
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
 static int batch_gal_or_one(const Batch& b) {
   int m = 1;
   for (int i = 0; i < b.count; ++i) m = std::max(m, b.plan[i]->n_gal);
@@ -390,7 +420,7 @@ template <typename T, int N> static void locate_impl(hamlet_plan* pl) {
 template <typename T, int N> struct OpsFor {
   static constexpr Ops ops{eval_impl<T, N>,      start_impl<T, N>, first_impl<T, N>,  end_impl<T, N>,
                            leap_out_impl<T, N>,   bytes_impl<T, N>, locate_impl<T, N>, field_impl<T, N>,
-                           density_impl<T, N>};
+                           density_impl<T, N>,    stats_impl<T, N>};
 };
 
 template <typename T> static const Ops* pick_ops(int n) {
@@ -1093,6 +1123,19 @@ extern "C" hamlet_status hamlet_density_field(hamlet_plan* plan, const void* mod
   sd.q = (double2*)modes;
   plan->st = sd;
   return plan->ops->density(b, out);
+}
+
+extern "C" hamlet_status hamlet_field_stats_accumulate(hamlet_plan* plan, const void* modes, double* acc) {
+  if (!plan || !modes || !acc) return fail(HAMLET_EINVAL, "NULL argument");
+  Batch b;
+  b.stream = plan->stream;
+  b.count = 1;
+  b.plan[0] = plan;
+  b.mode[0] = kXGrad;
+  StateDev sd{};
+  sd.q = (double2*)modes;
+  plan->st = sd;
+  return plan->ops->stats(b, acc);
 }
 
 // ---------------------------------------------------------------------------

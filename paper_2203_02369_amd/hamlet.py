@@ -249,6 +249,25 @@ def density_field(plan, modes, out=None):
     return out
 
 
+def field_stats_accumulate(plan, modes, acc=None):
+    """Add a state's density contrast and radial velocity on every node, and
+    their squares, to running sums on the plan's stream
+    (hamlet_field_stats_accumulate): acc is a float64 device tensor
+    (4, N, N, N) = [sum delta, sum delta^2, sum v_r, sum v_r^2], zeros when
+    None; returned."""
+    n = plan.n_grid
+    if acc is None:
+        acc = torch.zeros((4, n, n, n), dtype=torch.float64, device=plan.device)
+    elif acc.dtype != torch.float64 or tuple(acc.shape) != (4, n, n, n) or not acc.is_contiguous():
+        raise ValueError("acc must be contiguous float64 (4, %d, %d, %d)" % (n, n, n))
+    elif acc.device != plan.device:
+        raise ValueError("acc must be on %s" % plan.device)
+    m = _check(modes, plan, "modes", "modes")
+    _capi.check(_capi.load().hamlet_field_stats_accumulate(plan.handle, ctypes.c_void_p(m),
+                                                           ctypes.c_void_p(acc.data_ptr())))
+    return acc
+
+
 def sphere_moments(plan, modes, radii, out=None):
     """Monopole and dipole of the velocity field in spheres of the given radii
     (Mpc/h) about the observer, on the plan's stream (hamlet_sphere_moments):

@@ -166,3 +166,34 @@ def test_fields_at_the_paper_scale(hl):
     say("oracle velocity 256^3")
     ref = model.velocity_grids(prob, dhat)
     assert np.abs(v - ref).max() <= 1e-5 * np.abs(ref).max(), np.abs(v - ref).max() / np.abs(ref).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [32, 64])
+def test_field_stats_match_the_oracle(hl, precision, n):
+    # three states added to the running sums of delta, v_r and their squares
+    # (hamlet_field_stats_accumulate), against the oracle's sums
+    m = mocks.plain_fp64_32() if n == 32 else mocks.make_mock(64, 500.0, 2000, 250.0, "inv_r", seed=33)
+    prob = oracle_problem(m)
+    a = start_modes(m)
+    rng = np.random.default_rng(40 + n)
+    amp = np.abs(a).std()
+    shape = a.shape
+    b = hmc.symmetrise(n, amp * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)))
+    states = [a, b, -0.5 * a]
+    say("field stats", n, precision)
+    plan = hl.Plan.from_mock(m, precision=precision)
+    acc = None
+    for s in states:
+        acc = hl.field_stats_accumulate(plan, torch.from_numpy(to_lib_layout(s)).to(plan.device), acc)
+    got = acc.cpu().numpy()
+    plan.close()
+    from oracle import model
+    ref = analysis.field_sums(prob, states)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    dmax = [np.abs(model.density_grid(prob, s)).max() for s in states]
+    vmax = [np.abs(analysis.radial_velocity_grid(prob, s)).max() for s in states]
+    for i, (scale, tl) in enumerate([(sum(dmax), tol), (sum(d * d for d in dmax), 2.5 * tol),
+                                     (sum(vmax), tol), (sum(v * v for v in vmax), 2.5 * tol)]):
+        err = np.abs(got[i] - ref[i]).max()
+        assert err <= tl * scale, (i, err / scale)

@@ -1,7 +1,10 @@
 """Pins of the oracle's sphere moments (Section 5, "Monopole and dipole")
 against values fixed independently of its k-space sums: the field at the
 observer node, quadrature of the band-limited field over the ball, the
-window's own integral, and a single mode in closed form."""
+window's own integral, and a single mode in closed form.  Pins of the radial
+velocity and the field sums: the components along the axes and diagonals
+through the observer, a single mode's radial field in closed form, and
+linearity of the sums."""
 import math
 
 import numpy as np
@@ -123,3 +126,60 @@ def test_single_mode_in_closed_form(mode):
         d_ref = -2.0 * sign * model.H0 * prob.f_growth * a.imag * w * kvec / (k * k) / n ** 3
         assert abs(mono[j] - m_ref) <= 1e-13 * abs(m_ref)
         assert np.allclose(dip[j], d_ref, rtol=1e-13, atol=1e-13 * np.abs(d_ref).max())
+
+
+def test_radial_velocity_on_lines_through_the_observer():
+    n = 16
+    prob, dhat = _problem(n, 160.0, 9)
+    v = model.velocity_grids(prob, dhat)
+    vr = analysis.radial_velocity_grid(prob, dhat)
+    c = n // 2
+    assert vr[c, c, c] == 0.0
+    for d in (1, 3, c - 1):
+        assert abs(vr[c + d, c, c] - v[0, c + d, c, c]) <= 1e-13 * np.abs(v).max()     # +x
+        assert abs(vr[c, c - d, c] + v[1, c, c - d, c]) <= 1e-13 * np.abs(v).max()     # -y
+        assert abs(vr[c, c, c + d] - v[2, c, c, c + d]) <= 1e-13 * np.abs(v).max()     # +z
+        diag = (-v[0, c - d, c + d, c - d] + v[1, c - d, c + d, c - d] - v[2, c - d, c + d, c - d]) / math.sqrt(3.0)
+        assert abs(vr[c - d, c + d, c - d] - diag) <= 1e-13 * np.abs(v).max()
+    # the corner node sits at r = -(L/2)(1, 1, 1)
+    assert abs(vr[0, 0, 0] + v[:, 0, 0, 0].sum() / math.sqrt(3.0)) <= 1e-13 * np.abs(v).max()
+
+
+def test_radial_velocity_of_a_single_mode_in_closed_form():
+    # one mode pair k = (1, 0, 0) kf with dhat = a: v(x) = -(2 H0 f / (N^3 kf))
+    # * Im(a e^{i kf x}) along x only, so v_r = v_x (x - L/2) / |r|
+    n = 16
+    prob, _ = _problem(n, 160.0, 9)
+    dhat = np.zeros(model.half_shape(n), dtype=np.complex128)
+    a = 0.8 + 0.45j
+    dhat[1, 0, 0] = a
+    dhat[n - 1, 0, 0] = np.conj(a)
+    kf = 2.0 * math.pi / prob.box
+    h = prob.box / n
+    xs = np.arange(n) * h
+    vx = -2.0 * model.H0 * prob.f_growth / (n ** 3 * kf) * np.imag(a * np.exp(1j * kf * xs))
+    pos = xs - 0.5 * prob.box
+    rx, ry, rz = np.meshgrid(pos, pos, pos, indexing="ij")
+    r = np.sqrt(rx * rx + ry * ry + rz * rz)
+    ref = np.where(r > 0, vx[:, None, None] * rx / np.where(r > 0, r, 1.0), 0.0)
+    got = analysis.radial_velocity_grid(prob, dhat)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_field_sums_are_linear_in_the_states():
+    n = 8
+    prob, a = _problem(n, 100.0, 12)
+    _, b = _problem(n, 100.0, 13)
+    delta = model.density_grid(prob, a)
+    vr = analysis.radial_velocity_grid(prob, a)
+    one = analysis.field_sums(prob, [a])
+    assert np.array_equal(one, np.stack([delta, delta * delta, vr, vr * vr]))
+    # a state and its negative: the sums cancel, the squares double
+    pm = analysis.field_sums(prob, [a, -a])
+    assert np.abs(pm[0]).max() <= 1e-15 * np.abs(delta).max() and np.abs(pm[2]).max() <= 1e-15 * np.abs(vr).max()
+    assert np.allclose(pm[1], 2 * delta * delta, rtol=1e-14, atol=0) and np.allclose(pm[3], 2 * vr * vr, rtol=1e-14, atol=0)
+    # (a + b) / 2 and (a - b) / 2: the sums give a, the squares (A^2 + B^2) / 2
+    two = analysis.field_sums(prob, [0.5 * (a + b), 0.5 * (a - b)])
+    db = model.density_grid(prob, b)
+    assert np.allclose(two[0], delta, rtol=0, atol=1e-14 * np.abs(delta).max())
+    assert np.allclose(two[1], 0.5 * (delta * delta + db * db), rtol=0, atol=1e-13 * (delta * delta).max())
