@@ -33,6 +33,7 @@ stream served by the plain FP64 path one job at a time.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -265,6 +266,20 @@ def main():
     analysis["field_stats_accumulate"] = {"avg_call_ms": round(fs_ms, 4), "bytes_per_call": 42 * c_bytes,
                                           "achieved": round(42 * c_bytes / (fs_ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
     log("field statistics: %.3f ms per state" % fs_ms)
+    # shells of 10 Mpc/h out past the box corner, over two FP64 grids: 4c
+    # algorithmic (each grid once); the two sweeps read them twice
+    n_sh = int(math.ceil(math.sqrt(3.0) * 0.5 * mock.box / 10.0)) + 1
+    hamlet.shell_stats(plan, acc[0], acc[2], 10.0, n_sh)
+    ev0.record(plan.stream)
+    for _ in range(3):
+        hamlet.shell_stats(plan, acc[0], acc[2], 10.0, n_sh)
+    ev1.record(plan.stream)
+    ev1.synchronize()
+    sh_ms = ev0.elapsed_time(ev1) / 3
+    analysis["shell_stats"] = {"shells": n_sh, "width": 10.0, "avg_call_ms": round(sh_ms, 4), "bytes_per_call": 4 * c_bytes,
+                               "sweeps": 2,
+                               "achieved": round(4 * c_bytes / (sh_ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
+    log("shell statistics: %.3f ms per call" % sh_ms)
     del acc
     plan.close()
     del q, qd, qs

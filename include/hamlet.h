@@ -250,6 +250,24 @@ hamlet_status hamlet_density_field(hamlet_plan* plan, const void* modes, void* o
  * ordering as above. */
 hamlet_status hamlet_field_stats_accumulate(hamlet_plan* plan, const void* modes, double* acc);
 
+/* Statistics of fields in spherical shells about the observer (Section 5,
+ * correlation coefficients: the mean and scatter of delta or v_r in shells,
+ * and the correlation of the reconstruction with the target voxel by voxel).
+ * Shell s holds the nodes j with |r_j| in [s width, (s + 1) width), r_j =
+ * (j - N/2) L / N per axis (the observer is node N/2 of each axis).
+ * a, b (device): N^3 doubles each, [(x N + y) N + z]; b may be NULL (then
+ * b counts as zero).  out (device): n_shells x 6 doubles per shell: node
+ * count, mean of a, scatter of a (population standard deviation), mean of
+ * b, scatter of b, Pearson correlation coefficient of a and b over the
+ * shell's nodes; NaN where undefined (an empty shell, a constant field).
+ * The sums run in double in a fixed order: reruns are bit-identical.
+ * Allocates its partial sums on the plan's stream (stream-ordered).
+ * Errors: HAMLET_EINVAL for NULL buffers, n_shells outside [0, 4096] or a
+ * width that is not positive and finite; HAMLET_ENOMEM.  Asynchronous on
+ * the plan's stream. */
+hamlet_status hamlet_shell_stats(hamlet_plan* plan, const double* a, const double* b, double width,
+                                 int32_t n_shells, double* out);
+
 /* ---- Sphere moments of the velocity field ----
  *
  * Section 5 (monopole and dipole) follows the reconstruction by the moments

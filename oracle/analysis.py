@@ -1,7 +1,8 @@
 """Oracle of the chain's field statistics of Section 5: the monopole and
 dipole moments of the velocity field in spheres about the observer
-("Monopole and dipole"), and the maps of the mean and the scatter along the
-chain of the density contrast and of the radial velocity.
+("Monopole and dipole"), the maps of the mean and the scatter along the
+chain of the density contrast and of the radial velocity, and statistics of
+fields in spherical shells ("Correlation Coefficients").
 
 TEST INFRASTRUCTURE ONLY.  Plain FP64 numpy written from the definitions;
 only the test suite, the smoke check and the CPU baseline leg of the
@@ -135,4 +136,38 @@ def field_sums(prob, states):
         out[1] += delta * delta
         out[2] += vr
         out[3] += vr * vr
+    return out
+
+
+def node_distances(prob):
+    """|x_j - o| (Mpc/h) of every node x_j = j L / N from the observer
+    o = (L/2)(1, 1, 1); shape (N, N, N)."""
+    n = prob.n_grid
+    pos = np.arange(n) * (prob.box / n) - 0.5 * prob.box
+    rx, ry, rz = np.meshgrid(pos, pos, pos, indexing="ij")
+    return np.sqrt(rx * rx + ry * ry + rz * rz)
+
+
+def shell_stats(prob, a, b, width, n_shells):
+    """Per shell s (the nodes at distance in [s width, (s + 1) width)): node
+    count, mean and scatter (population standard deviation) of a and of b,
+    and the Pearson correlation coefficient of a and b over those nodes;
+    NaN where undefined.  b None counts as zero.  Shape (n_shells, 6)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.zeros_like(a) if b is None else np.asarray(b, dtype=np.float64)
+    shell = np.floor(node_distances(prob) / width).astype(np.int64)
+    out = np.full((n_shells, 6), np.nan)
+    for s in range(n_shells):
+        sel = shell == s
+        cnt = int(np.count_nonzero(sel))
+        out[s, 0] = cnt
+        if cnt == 0:
+            continue
+        xa, xb = a[sel], b[sel]
+        ma, mb = xa.mean(), xb.mean()
+        da, db = xa - ma, xb - mb
+        va, vb = np.mean(da * da), np.mean(db * db)
+        out[s, 1:5] = [ma, math.sqrt(va), mb, math.sqrt(vb)]
+        if va > 0 and vb > 0:
+            out[s, 5] = np.mean(da * db) / math.sqrt(va * vb)
     return out

@@ -16,7 +16,8 @@
 // FP64 throughout: the modes are the FP64 masters in both precisions.
 //
 // Also: the last inverse pass of the field maps in a form that adds a state's
-// density contrast or radial velocity, and its square, to running sums.
+// density contrast or radial velocity, and its square, to running sums; and
+// the statistics of two fields in spherical shells about the observer.
 #pragma once
 
 #include "common.hpp"
@@ -155,6 +156,155 @@ __global__ void __launch_bounds__(NT) k_inv_z_acc(Launch L, int x0, double* acc)
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
   inv_z_acc_body<T, N, NT, DENSITY>(k.w.v0(), k.w.v1(), k.w.v2(), k.w.tw(), acc, x0);
+}
+
+// ---------------------------------------------------------------------------
+// Statistics in spherical shells about the observer (Section 5, correlation
+// coefficients): shell s holds the nodes at distance |r| in
+// [s w, (s + 1) w), r = (j - N/2) h per axis (the observer is node N/2),
+// h = L / N.  Per shell: the node count, mean and scatter (population
+// standard deviation) of fields a and b over its nodes, and their Pearson
+// correlation coefficient.  Two sweeps, as the definitions read: the means,
+// then the sums of the centred products (no cancellation for a field whose
+// scatter is small against its mean).  Each sweep has two stages, both in
+// fixed order: each block sums the nodes of a 4 x 8 x 16 tile per shell that
+// the tile reaches (a few consecutive shells, the range found from the
+// tile's nearest and farthest node), and one block per shell adds those
+// partials in block order.
+// ---------------------------------------------------------------------------
+constexpr int kShellTX = 4, kShellTY = 8, kShellTZ = 16;
+constexpr int kShellThreads = 256;
+constexpr int kShellNodes = kShellTX * kShellTY * kShellTZ;
+constexpr int kShellValues = 3;   // sweep 1: count, sum a, sum b; sweep 2: sum da^2, sum db^2, sum da db
+constexpr int kShellOut = 6;
+constexpr int kShellMax = 4096;
+
+struct ShellGeom {
+  double h, width;   // node spacing, shell width (Mpc/h)
+  int n, n_shells;
+  int slots;         // partials stored per block (most shells a tile reaches)
+};
+
+__host__ __device__ inline int shell_index(int r2, const ShellGeom& g) {
+  return (int)floor(sqrt((double)r2) * g.h / g.width);
+}
+
+// Shells [lo, hi] (hi clamped to the last shell) that tile (bx, by, bz)
+// reaches: the squared distance of its nearest and farthest node, per axis.
+__host__ __device__ inline int2 shell_range(int bx, int by, int bz, const ShellGeom& g) {
+  const int half = g.n / 2;
+  int dmin = 0, dmax = 0;
+  const int start[3] = {bx * kShellTX, by * kShellTY, bz * kShellTZ};
+  const int len[3] = {kShellTX, kShellTY, kShellTZ};
+  for (int a = 0; a < 3; ++a) {
+    const int lo = start[a] - half, hi = start[a] + len[a] - 1 - half;
+    const int alo = lo < 0 ? -lo : lo, ahi = hi < 0 ? -hi : hi;
+    const int mn = (lo <= 0 && hi >= 0) ? 0 : (alo < ahi ? alo : ahi), mx = alo > ahi ? alo : ahi;
+    dmin += mn * mn;
+    dmax += mx * mx;
+  }
+  const int s1 = shell_index(dmax, g);
+  return make_int2(shell_index(dmin, g), s1 < g.n_shells - 1 ? s1 : g.n_shells - 1);
+}
+
+// Stage 1 of a sweep: grid (N / 4, N / 8, N / 16);
+// part[(block * slots + s - lo) * 3 + v].  Sweep 2 (CENTRED) reads the means
+// of shell s from out[s * 6 + 1] and out[s * 6 + 3].
+template <bool CENTRED>
+__global__ void __launch_bounds__(kShellThreads)
+k_shell_part(const double* __restrict__ a, const double* __restrict__ b, ShellGeom g, const double* __restrict__ out,
+             double* __restrict__ part) {
+  __shared__ double red[kShellValues * (kShellThreads / 64)];
+  const int2 range = shell_range(blockIdx.x, blockIdx.y, blockIdx.z, g);
+  if (range.x > range.y) return;   // block-uniform: every node lies beyond the last shell
+  const size_t blk = ((size_t)blockIdx.x * gridDim.y + blockIdx.y) * gridDim.z + blockIdx.z;
+  constexpr int K = kShellNodes / kShellThreads;
+  double va[K], vb[K];
+  int sh[K];
+  const int half = g.n / 2;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = threadIdx.x + k * kShellThreads;
+    const int x = blockIdx.x * kShellTX + i / (kShellTY * kShellTZ);
+    const int y = blockIdx.y * kShellTY + (i / kShellTZ) % kShellTY;
+    const int z = blockIdx.z * kShellTZ + i % kShellTZ;
+    const size_t node = ((size_t)x * g.n + y) * g.n + z;
+    const int rx = x - half, ry = y - half, rz = z - half;
+    sh[k] = shell_index(rx * rx + ry * ry + rz * rz, g);
+    va[k] = a[node];
+    vb[k] = b ? b[node] : 0.0;
+  }
+  for (int s = range.x; s <= range.y && s - range.x < g.slots; ++s) {
+    double acc[kShellValues] = {0.0, 0.0, 0.0};
+    double ma = 0.0, mb = 0.0;
+    if constexpr (CENTRED) {
+      ma = out[(size_t)s * kShellOut + 1];
+      mb = out[(size_t)s * kShellOut + 3];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (sh[k] == s) {
+        if constexpr (CENTRED) {
+          const double da = va[k] - ma, db = vb[k] - mb;
+          acc[0] += da * da;
+          acc[1] += db * db;
+          acc[2] += da * db;
+        } else {
+          acc[0] += 1.0;
+          acc[1] += va[k];
+          acc[2] += vb[k];
+        }
+      }
+    }
+    block_sums<kShellValues>(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int v = 0; v < kShellValues; ++v) part[(blk * g.slots + (s - range.x)) * kShellValues + v] = acc[v];
+    }
+  }
+}
+
+// Stage 2 of a sweep: one block per shell.  out[s * 6 + ...] = count,
+// mean a, scatter a, mean b, scatter b, correlation; sweep 1 writes the
+// count and the means, sweep 2 the rest.  NaN where undefined: an empty
+// shell, or a field constant over it (its correlation).
+template <bool CENTRED>
+__global__ void __launch_bounds__(kShellThreads)
+k_shell_finish(const double* __restrict__ part, ShellGeom g, double* __restrict__ out) {
+  __shared__ double red[kShellValues * (kShellThreads / 64)];
+  const int s = blockIdx.x;
+  const int nbx = g.n / kShellTX, nby = g.n / kShellTY, nbz = g.n / kShellTZ;
+  const int blocks = nbx * nby * nbz;
+  double acc[kShellValues] = {0.0, 0.0, 0.0};
+  for (int blk = threadIdx.x; blk < blocks; blk += kShellThreads) {
+    const int bz = blk % nbz, by = (blk / nbz) % nby, bx = blk / (nbz * nby);
+    const int2 range = shell_range(bx, by, bz, g);
+    if (s < range.x || s > range.y || s - range.x >= g.slots) continue;
+    const double* p = part + ((size_t)blk * g.slots + (s - range.x)) * kShellValues;
+#pragma unroll
+    for (int v = 0; v < kShellValues; ++v) acc[v] += p[v];
+  }
+  block_sums<kShellValues>(acc, red);
+  if (threadIdx.x == 0) {
+    const double nan = __builtin_nan("");
+    double* o = out + (size_t)s * kShellOut;
+    if constexpr (!CENTRED) {
+      const double n = acc[0];
+      o[0] = n;
+      o[1] = n > 0.0 ? acc[1] / n : nan;
+      o[3] = n > 0.0 ? acc[2] / n : nan;
+    } else {
+      const double n = o[0];
+      if (n > 0.0) {
+        const double va = acc[0] / n, vb = acc[1] / n;
+        o[2] = sqrt(va);
+        o[4] = sqrt(vb);
+        o[5] = (va > 0.0 && vb > 0.0) ? (acc[2] / n) / sqrt(va * vb) : nan;
+      } else {
+        o[2] = o[4] = o[5] = nan;
+      }
+    }
+  }
 }
 
 }  // namespace hamlet

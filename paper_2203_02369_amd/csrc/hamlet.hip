@@ -1139,6 +1139,41 @@ extern "C" hamlet_status hamlet_field_stats_accumulate(hamlet_plan* plan, const 
 }
 
 // ---------------------------------------------------------------------------
+// Statistics of two fields in spherical shells (Section 5, correlation
+// coefficients)
+// ---------------------------------------------------------------------------
+extern "C" hamlet_status hamlet_shell_stats(hamlet_plan* plan, const double* a, const double* b, double width,
+                                            int32_t n_shells, double* out) {
+  if (!plan || (n_shells > 0 && (!a || !out))) return fail(HAMLET_EINVAL, "NULL argument");
+  if (n_shells < 0 || n_shells > kShellMax)
+    return fail(HAMLET_EINVAL, "n_shells %d outside [0, %d]", (int)n_shells, kShellMax);
+  if (!(width > 0.0) || !std::isfinite(width)) return fail(HAMLET_EINVAL, "shell width %g is not positive", width);
+  if (n_shells == 0) return HAMLET_OK;
+  ShellGeom g{plan->box / plan->n, width, plan->n, (int)n_shells, 1};
+  const int nbx = plan->n / kShellTX, nby = plan->n / kShellTY, nbz = plan->n / kShellTZ;
+  for (int bx = 0; bx < nbx; ++bx)
+    for (int by = 0; by < nby; ++by)
+      for (int bz = 0; bz < nbz; ++bz) {
+        const int2 r = shell_range(bx, by, bz, g);
+        g.slots = std::max(g.slots, r.y - r.x + 1);
+      }
+  g.slots += 1;   // room for a range one wider on the device (rounding of the square root)
+  const size_t bytes = (size_t)nbx * nby * nbz * g.slots * kShellValues * sizeof(double);
+  double* part = nullptr;
+  if (hipMallocAsync((void**)&part, bytes, plan->stream) != hipSuccess)
+    return fail(HAMLET_ENOMEM, "shell partials: %zu bytes", bytes);
+  // the means, then the centred sums (both sweeps reuse the partials)
+  k_shell_part<false><<<dim3(nbx, nby, nbz), kShellThreads, 0, plan->stream>>>(a, b, g, out, part);
+  k_shell_finish<false><<<n_shells, kShellThreads, 0, plan->stream>>>(part, g, out);
+  k_shell_part<true><<<dim3(nbx, nby, nbz), kShellThreads, 0, plan->stream>>>(a, b, g, out, part);
+  k_shell_finish<true><<<n_shells, kShellThreads, 0, plan->stream>>>(part, g, out);
+  const hipError_t le = hipGetLastError();
+  HIP_TRY(hipFreeAsync(part, plan->stream));
+  if (le != hipSuccess) return fail(HAMLET_EDEVICE, "kernel launch: %s", hipGetErrorString(le));
+  return HAMLET_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Sphere moments of the velocity field (Section 5, monopole and dipole)
 // ---------------------------------------------------------------------------
 template <int N>

@@ -268,6 +268,30 @@ def field_stats_accumulate(plan, modes, acc=None):
     return acc
 
 
+def shell_stats(plan, a, b, width, n_shells, out=None):
+    """Statistics of float64 grids a and b (N, N, N) in spherical shells of
+    the given width (Mpc/h) about the observer, on the plan's stream
+    (hamlet_shell_stats): a float64 device tensor (n_shells, 6) of (count,
+    mean a, scatter a, mean b, scatter b, correlation) per shell; b may be
+    None."""
+    n = plan.n_grid
+    for name, g in (("a", a), ("b", b)):
+        if g is None and name == "b":
+            continue
+        if (not isinstance(g, torch.Tensor) or g.dtype != torch.float64 or tuple(g.shape) != (n, n, n)
+                or not g.is_contiguous() or g.device != plan.device):
+            raise ValueError("%s must be a contiguous float64 (%d, %d, %d) tensor on %s" % (name, n, n, n, plan.device))
+    n_shells = int(n_shells)
+    if out is None:
+        out = torch.empty((max(n_shells, 0), 6), dtype=torch.float64, device=plan.device)
+    elif out.dtype != torch.float64 or out.numel() != 6 * n_shells or not out.is_contiguous() or out.device != plan.device:
+        raise ValueError("out must be contiguous float64 (%d, 6) on %s" % (n_shells, plan.device))
+    _capi.check(_capi.load().hamlet_shell_stats(plan.handle, ctypes.c_void_p(a.data_ptr()),
+                                                ctypes.c_void_p(b.data_ptr() if b is not None else None),
+                                                float(width), n_shells, ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
 def sphere_moments(plan, modes, radii, out=None):
     """Monopole and dipole of the velocity field in spheres of the given radii
     (Mpc/h) about the observer, on the plan's stream (hamlet_sphere_moments):

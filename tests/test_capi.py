@@ -102,6 +102,7 @@ def test_velocity_field_validates_on_the_host():
     assert b"NULL" in lib.hamlet_last_error()
     assert lib.hamlet_density_field(None, None, None) == -1
     assert lib.hamlet_field_stats_accumulate(None, None, None) == -1
+    assert lib.hamlet_shell_stats(None, None, None, 10.0, 4, None) == -1
 
 
 def test_sphere_moments_validate_on_the_host():

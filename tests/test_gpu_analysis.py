@@ -197,3 +197,82 @@ def test_field_stats_match_the_oracle(hl, precision, n):
                                      (sum(vmax), tol), (sum(v * v for v in vmax), 2.5 * tol)]):
         err = np.abs(got[i] - ref[i]).max()
         assert err <= tl * scale, (i, err / scale)
+
+
+def _shell_inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((n, n, n))
+    b = 0.6 * a + 0.8 * rng.standard_normal((n, n, n))
+    return a, b
+
+
+def _check_shells(got, ref, a, b):
+    assert np.array_equal(got[:, 0], ref[:, 0])
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    scale = np.array([1.0, np.abs(a).max(), np.abs(a).max(), np.abs(b).max(), np.abs(b).max(), 1.0])
+    err = np.where(ok, np.abs(got - ref), 0.0) / scale
+    assert err[:, 1:5].max() <= 1e-12 and err[:, 5].max() <= 1e-10, err.max(axis=0)
+
+
+def _margin(prob, width):
+    # no node sits within rounding of a shell boundary unless exactly on it
+    f = analysis.node_distances(prob) / width
+    d = np.abs(f - np.round(f))
+    assert d[d > 0].min() > 1e-9
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_shell_stats_match_the_oracle(hl, n):
+    # hamlet_shell_stats on seeded fields against the oracle, shells out past
+    # the box corner (the last ones empty)
+    m = mocks.plain_fp64_32() if n == 32 else mocks.make_mock(64, 500.0, 2000, 250.0, "inv_r", seed=33)
+    prob = oracle_problem(m)
+    a, b = _shell_inputs(n, 50 + n)
+    plan = hl.Plan.from_mock(m, precision="fp64")
+    ta, tb = torch.from_numpy(a).to(plan.device), torch.from_numpy(b).to(plan.device)
+    rmax = analysis.node_distances(prob).max()
+    for width in ([7.3, 23.1, 10.0] if n == 32 else [10.0, 17.9]):
+        _margin(prob, width)
+        n_shells = int(math.ceil(rmax / width)) + 2
+        say("shell stats", n, width, n_shells)
+        got = hl.shell_stats(plan, ta, tb, width, n_shells).cpu().numpy()
+        _check_shells(got, analysis.shell_stats(prob, a, b, width, n_shells), a, b)
+        again = hl.shell_stats(plan, ta, tb, width, n_shells).cpu().numpy()
+        assert np.array_equal(np.nan_to_num(again, nan=7.0), np.nan_to_num(got, nan=7.0))
+    # b absent: its statistics are those of a zero field
+    got = hl.shell_stats(plan, ta, None, 23.1 if n == 32 else 17.9, 8).cpu().numpy()
+    _check_shells(got, analysis.shell_stats(prob, a, None, 23.1 if n == 32 else 17.9, 8), a, np.ones(1))
+    plan.close()
+
+
+def test_shell_stats_at_the_paper_scale(hl):
+    # 256^3 grid, shells of 10 Mpc/h out past the corner of the 500 Mpc/h box
+    m = mocks.paper_scale_256()
+    prob = oracle_problem(m)
+    a, b = _shell_inputs(256, 256)
+    _margin(prob, 10.0)
+    say("shell stats 256^3")
+    plan = hl.Plan.from_mock(m, precision="fp32")
+    got = hl.shell_stats(plan, torch.from_numpy(a).to(plan.device), torch.from_numpy(b).to(plan.device), 10.0, 45)
+    got = got.cpu().numpy()
+    plan.close()
+    say("oracle shells 256^3")
+    _check_shells(got, analysis.shell_stats(prob, a, b, 10.0, 45), a, b)
+
+
+def test_shell_stats_validate_their_arguments(hl):
+    m = mocks.make_mock(16, 200.0, 50, 80.0, seed=5)
+    plan = hl.Plan.from_mock(m, precision="fp64")
+    a = torch.zeros((16, 16, 16), dtype=torch.float64, device=plan.device)
+    say("shell stats validation")
+    for width, ns in ((0.0, 4), (-1.0, 4), (math.nan, 4), (math.inf, 4), (10.0, -1), (10.0, 5000)):
+        with pytest.raises(Exception):
+            hl.shell_stats(plan, a, a, width, ns)
+    with pytest.raises(ValueError):
+        hl.shell_stats(plan, a.float(), a, 10.0, 4)
+    assert hl.shell_stats(plan, a, a, 10.0, 0).numel() == 0
+    # a constant field: mean the constant, no scatter, no correlation
+    got = hl.shell_stats(plan, a + 2.5, a, 30.0, 3).cpu().numpy()
+    assert np.all(got[:, 1] == 2.5) and np.all(got[:, 2] == 0.0) and np.all(np.isnan(got[:, 5]))
+    plan.close()

@@ -4,7 +4,9 @@ observer node, quadrature of the band-limited field over the ball, the
 window's own integral, and a single mode in closed form.  Pins of the radial
 velocity and the field sums: the components along the axes and diagonals
 through the observer, a single mode's radial field in closed form, and
-linearity of the sums."""
+linearity of the sums.  Pins of the shell statistics: brute force over the
+nodes of a small grid, exact correlations of +-1, and the distance field's
+shell means inside their shells."""
 import math
 
 import numpy as np
@@ -183,3 +185,73 @@ def test_field_sums_are_linear_in_the_states():
     db = model.density_grid(prob, b)
     assert np.allclose(two[0], delta, rtol=0, atol=1e-14 * np.abs(delta).max())
     assert np.allclose(two[1], 0.5 * (delta * delta + db * db), rtol=0, atol=1e-13 * (delta * delta).max())
+
+
+def _shell_problem(n, box):
+    m = mocks.make_mock(n, box, 20, 0.3 * box, "sphere", (0.2, 0.2), seed=2)
+    return oracle_problem(m)
+
+
+def test_shell_stats_by_brute_force():
+    # every node visited in plain loops on a 6^3 grid (observer at node 3)
+    n, box, width = 6, 60.0, 7.0
+    prob = _shell_problem(n, box)
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal((n, n, n))
+    b = 0.5 * a + rng.standard_normal((n, n, n))
+    n_shells = 6
+    members = [[] for _ in range(n_shells)]
+    h = box / n
+    for x in range(n):
+        for y in range(n):
+            for z in range(n):
+                r = math.sqrt(((x - 3) * h) ** 2 + ((y - 3) * h) ** 2 + ((z - 3) * h) ** 2)
+                s = int(r // width)
+                if s < n_shells:
+                    members[s].append((a[x, y, z], b[x, y, z]))
+    got = analysis.shell_stats(prob, a, b, width, n_shells)
+    for s, mem in enumerate(members):
+        assert got[s, 0] == len(mem)
+        if not mem:
+            assert np.all(np.isnan(got[s, 1:]))
+            continue
+        xa = [p[0] for p in mem]
+        xb = [p[1] for p in mem]
+        k = len(mem)
+        ma, mb = sum(xa) / k, sum(xb) / k
+        sa = math.sqrt(sum((v - ma) ** 2 for v in xa) / k)
+        sb = math.sqrt(sum((v - mb) ** 2 for v in xb) / k)
+        assert abs(got[s, 1] - ma) <= 1e-14 and abs(got[s, 3] - mb) <= 1e-14
+        assert abs(got[s, 2] - sa) <= 1e-14 and abs(got[s, 4] - sb) <= 1e-14
+        if k > 1:
+            cov = sum((u - ma) * (v - mb) for u, v in zip(xa, xb)) / k
+            assert abs(got[s, 5] - cov / (sa * sb)) <= 1e-13
+    # the observer's own node is alone in shell 0 here (the next node is 10 away)
+    assert got[0, 0] == 1 and np.isnan(got[0, 5])
+
+
+def test_shell_correlations_and_the_distance_field():
+    n, box = 16, 160.0
+    prob = _shell_problem(n, box)
+    rng = np.random.default_rng(8)
+    a = rng.standard_normal((n, n, n))
+    width = 13.7
+    st = analysis.shell_stats(prob, a, 2.0 * a + 3.0, width, 12)
+    full = st[st[:, 0] > 1]
+    assert np.allclose(full[:, 5], 1.0, atol=1e-13)
+    assert np.allclose(full[:, 3], 2.0 * full[:, 1] + 3.0, atol=1e-13) and np.allclose(full[:, 4], 2.0 * full[:, 2], atol=1e-13)
+    st = analysis.shell_stats(prob, a, -a, width, 12)
+    assert np.allclose(st[st[:, 0] > 1][:, 5], -1.0, atol=1e-13)
+    # the distance field: each shell's mean lies in its own shell, and the
+    # counts add up to the nodes within the outer radius
+    r = analysis.node_distances(prob)
+    st = analysis.shell_stats(prob, r, None, width, 12)
+    for s in range(12):
+        if st[s, 0] > 0:
+            assert s * width <= st[s, 1] < (s + 1) * width and st[s, 2] <= width / 2
+    assert st[:, 0].sum() == np.count_nonzero(r < 12 * width)
+    occupied = st[:, 0] > 0
+    assert np.all(st[occupied, 3] == 0.0) and np.all(st[occupied, 4] == 0.0)
+    # beyond the box corner the shells are empty
+    far = analysis.shell_stats(prob, a, a, 30.0, 12)
+    assert far[-1, 0] == 0 and np.all(np.isnan(far[-1, 1:]))
