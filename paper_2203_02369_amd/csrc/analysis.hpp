@@ -174,6 +174,8 @@ __global__ void __launch_bounds__(NT) k_inv_z_acc(Launch L, int x0, double* acc)
 // ---------------------------------------------------------------------------
 constexpr int kShellTX = 4, kShellTY = 8, kShellTZ = 16;
 constexpr int kShellThreads = 256;
+constexpr int kShellFinishThreads = 1024;
+constexpr int kShellsPerReduce = 1;   // shells a block reduces together (4 measured slower)
 constexpr int kShellNodes = kShellTX * kShellTY * kShellTZ;
 constexpr int kShellValues = 3;   // sweep 1: count, sum a, sum b; sweep 2: sum da^2, sum db^2, sum da db
 constexpr int kShellOut = 6;
@@ -207,17 +209,20 @@ __host__ __device__ inline int2 shell_range(int bx, int by, int bz, const ShellG
   return make_int2(shell_index(dmin, g), s1 < g.n_shells - 1 ? s1 : g.n_shells - 1);
 }
 
-// Stage 1 of a sweep: grid (N / 4, N / 8, N / 16);
-// part[(block * slots + s - lo) * 3 + v].  Sweep 2 (CENTRED) reads the means
+// Stage 1 of a sweep: grid (N / 16, N / 8, N / 4) = (tile z, y, x), z
+// fastest, so that blocks dispatched together read neighbouring pieces of the
+// same rows; part[(block * slots + s - lo) * 3 + v], block = (bx ny + by) nz + bz.  Sweep 2 (CENTRED) reads the means
 // of shell s from out[s * 6 + 1] and out[s * 6 + 3].
 template <bool CENTRED>
 __global__ void __launch_bounds__(kShellThreads)
 k_shell_part(const double* __restrict__ a, const double* __restrict__ b, ShellGeom g, const double* __restrict__ out,
              double* __restrict__ part) {
-  __shared__ double red[kShellValues * (kShellThreads / 64)];
-  const int2 range = shell_range(blockIdx.x, blockIdx.y, blockIdx.z, g);
+  constexpr int V = kShellValues * kShellsPerReduce;
+  __shared__ double red[V * (kShellThreads / 64)];
+  const int bx = blockIdx.z, by = blockIdx.y, bz = blockIdx.x;
+  const int2 range = shell_range(bx, by, bz, g);
   if (range.x > range.y) return;   // block-uniform: every node lies beyond the last shell
-  const size_t blk = ((size_t)blockIdx.x * gridDim.y + blockIdx.y) * gridDim.z + blockIdx.z;
+  const size_t blk = ((size_t)bx * gridDim.y + by) * gridDim.x + bz;
   constexpr int K = kShellNodes / kShellThreads;
   double va[K], vb[K];
   int sh[K];
@@ -225,41 +230,52 @@ k_shell_part(const double* __restrict__ a, const double* __restrict__ b, ShellGe
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int i = threadIdx.x + k * kShellThreads;
-    const int x = blockIdx.x * kShellTX + i / (kShellTY * kShellTZ);
-    const int y = blockIdx.y * kShellTY + (i / kShellTZ) % kShellTY;
-    const int z = blockIdx.z * kShellTZ + i % kShellTZ;
+    const int x = bx * kShellTX + i / (kShellTY * kShellTZ);
+    const int y = by * kShellTY + (i / kShellTZ) % kShellTY;
+    const int z = bz * kShellTZ + i % kShellTZ;
     const size_t node = ((size_t)x * g.n + y) * g.n + z;
     const int rx = x - half, ry = y - half, rz = z - half;
     sh[k] = shell_index(rx * rx + ry * ry + rz * rz, g);
     va[k] = a[node];
     vb[k] = b ? b[node] : 0.0;
   }
-  for (int s = range.x; s <= range.y && s - range.x < g.slots; ++s) {
-    double acc[kShellValues] = {0.0, 0.0, 0.0};
-    double ma = 0.0, mb = 0.0;
-    if constexpr (CENTRED) {
-      ma = out[(size_t)s * kShellOut + 1];
-      mb = out[(size_t)s * kShellOut + 3];
-    }
+  const int last = min(range.y, range.x + g.slots - 1);
+  for (int s0 = range.x; s0 <= last; s0 += kShellsPerReduce) {
+    double acc[V];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (sh[k] == s) {
-        if constexpr (CENTRED) {
-          const double da = va[k] - ma, db = vb[k] - mb;
-          acc[0] += da * da;
-          acc[1] += db * db;
-          acc[2] += da * db;
-        } else {
-          acc[0] += 1.0;
-          acc[1] += va[k];
-          acc[2] += vb[k];
+    for (int v = 0; v < V; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int j = 0; j < kShellsPerReduce; ++j) {
+      const int s = s0 + j;
+      if (s > last) break;
+      double ma = 0.0, mb = 0.0;
+      if constexpr (CENTRED) {
+        ma = out[(size_t)s * kShellOut + 1];
+        mb = out[(size_t)s * kShellOut + 3];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (sh[k] == s) {
+          if constexpr (CENTRED) {
+            const double da = va[k] - ma, db = vb[k] - mb;
+            acc[3 * j + 0] += da * da;
+            acc[3 * j + 1] += db * db;
+            acc[3 * j + 2] += da * db;
+          } else {
+            acc[3 * j + 0] += 1.0;
+            acc[3 * j + 1] += va[k];
+            acc[3 * j + 2] += vb[k];
+          }
         }
       }
     }
-    block_sums<kShellValues>(acc, red);
+    block_sums<V>(acc, red);
     if (threadIdx.x == 0) {
+      for (int j = 0; j < kShellsPerReduce && s0 + j <= last; ++j) {
 #pragma unroll
-      for (int v = 0; v < kShellValues; ++v) part[(blk * g.slots + (s - range.x)) * kShellValues + v] = acc[v];
+        for (int v = 0; v < kShellValues; ++v)
+          part[(blk * g.slots + (s0 + j - range.x)) * kShellValues + v] = acc[3 * j + v];
+      }
     }
   }
 }
@@ -269,14 +285,14 @@ k_shell_part(const double* __restrict__ a, const double* __restrict__ b, ShellGe
 // count and the means, sweep 2 the rest.  NaN where undefined: an empty
 // shell, or a field constant over it (its correlation).
 template <bool CENTRED>
-__global__ void __launch_bounds__(kShellThreads)
+__global__ void __launch_bounds__(kShellFinishThreads)
 k_shell_finish(const double* __restrict__ part, ShellGeom g, double* __restrict__ out) {
-  __shared__ double red[kShellValues * (kShellThreads / 64)];
+  __shared__ double red[kShellValues * (kShellFinishThreads / 64)];
   const int s = blockIdx.x;
   const int nbx = g.n / kShellTX, nby = g.n / kShellTY, nbz = g.n / kShellTZ;
   const int blocks = nbx * nby * nbz;
   double acc[kShellValues] = {0.0, 0.0, 0.0};
-  for (int blk = threadIdx.x; blk < blocks; blk += kShellThreads) {
+  for (int blk = threadIdx.x; blk < blocks; blk += kShellFinishThreads) {
     const int bz = blk % nbz, by = (blk / nbz) % nby, bx = blk / (nbz * nby);
     const int2 range = shell_range(bx, by, bz, g);
     if (s < range.x || s > range.y || s - range.x >= g.slots) continue;

@@ -1151,22 +1151,21 @@ extern "C" hamlet_status hamlet_shell_stats(hamlet_plan* plan, const double* a, 
   if (n_shells == 0) return HAMLET_OK;
   ShellGeom g{plan->box / plan->n, width, plan->n, (int)n_shells, 1};
   const int nbx = plan->n / kShellTX, nby = plan->n / kShellTY, nbz = plan->n / kShellTZ;
-  for (int bx = 0; bx < nbx; ++bx)
-    for (int by = 0; by < nby; ++by)
-      for (int bz = 0; bz < nbz; ++bz) {
-        const int2 r = shell_range(bx, by, bz, g);
-        g.slots = std::max(g.slots, r.y - r.x + 1);
-      }
-  g.slots += 1;   // room for a range one wider on the device (rounding of the square root)
+  // A tile's nearest and farthest nodes are at most its diagonal apart, so
+  // it reaches at most diagonal / width + 2 shells; one more for rounding.
+  const double diag = g.h * std::sqrt((double)((kShellTX - 1) * (kShellTX - 1) + (kShellTY - 1) * (kShellTY - 1) +
+                                               (kShellTZ - 1) * (kShellTZ - 1)));
+  const double bound = std::floor(diag / width) + 3.0;
+  g.slots = (int)std::min(bound, (double)n_shells + 1.0);
   const size_t bytes = (size_t)nbx * nby * nbz * g.slots * kShellValues * sizeof(double);
   double* part = nullptr;
   if (hipMallocAsync((void**)&part, bytes, plan->stream) != hipSuccess)
     return fail(HAMLET_ENOMEM, "shell partials: %zu bytes", bytes);
   // the means, then the centred sums (both sweeps reuse the partials)
-  k_shell_part<false><<<dim3(nbx, nby, nbz), kShellThreads, 0, plan->stream>>>(a, b, g, out, part);
-  k_shell_finish<false><<<n_shells, kShellThreads, 0, plan->stream>>>(part, g, out);
-  k_shell_part<true><<<dim3(nbx, nby, nbz), kShellThreads, 0, plan->stream>>>(a, b, g, out, part);
-  k_shell_finish<true><<<n_shells, kShellThreads, 0, plan->stream>>>(part, g, out);
+  k_shell_part<false><<<dim3(nbz, nby, nbx), kShellThreads, 0, plan->stream>>>(a, b, g, out, part);
+  k_shell_finish<false><<<n_shells, kShellFinishThreads, 0, plan->stream>>>(part, g, out);
+  k_shell_part<true><<<dim3(nbz, nby, nbx), kShellThreads, 0, plan->stream>>>(a, b, g, out, part);
+  k_shell_finish<true><<<n_shells, kShellFinishThreads, 0, plan->stream>>>(part, g, out);
   const hipError_t le = hipGetLastError();
   HIP_TRY(hipFreeAsync(part, plan->stream));
   if (le != hipSuccess) return fail(HAMLET_EDEVICE, "kernel launch: %s", hipGetErrorString(le));
