@@ -93,6 +93,78 @@ def test_retained_degrees_of_freedom(n):
     assert int(w.sum()) == (n - 1) ** 3 - 1
 
 
+def _pk_problem(n_grid, box, pk_of_n2):
+    """An empty-catalogue problem whose P(k) table is pk_of_n2(j), j = |n|^2."""
+    prob = _empty_problem(n_grid=n_grid, box=box)
+    j = np.arange(3 * (n_grid // 2) ** 2 + 1, dtype=np.float64)
+    prob.pk_n2 = pk_of_n2(j)
+    return prob
+
+
+@pytest.mark.parametrize("kvec", [(1, 0, 2), (3, -2, 1), (2, 1, 0), (0, -3, 0)])
+def test_mode_variance_single_mode_closed_form(kvec):
+    # eq:prior-k with P the variance of the complex mode (reading of the
+    # normalisation): a field with the one mode pair +-k at amplitude
+    # |dhat_k| = sigma_k is 2 sigma_k/N^3 cos(k.x) on the nodes, whose mean
+    # square over the box is 2 sigma_k^2 / N^6.  The continuum gives the same
+    # pair 2 P(|k|) / V (the variance of delta is V^-1 sum_k P(|k|)), so the
+    # node mean of delta^2 must equal 2 P(|k|) / V exactly: this fixes the
+    # powers of N and of the box in sigma_k^2 = N^6 P / V.
+    n, box = 16, 300.0
+    prob = _pk_problem(n, box, lambda j: 1e3 * (1.0 + j) ** -1.3)
+    var = model.mode_variance(prob)
+    kx, ky, kz = kvec
+    dhat = np.zeros(model.half_shape(n), dtype=np.complex128)
+    dhat[kx % n, ky % n, kz] = math.sqrt(var[kx % n, ky % n, kz])
+    if kz == 0:
+        # both members of the pair are stored on the kz = 0 plane (real value)
+        dhat[-kx % n, -ky % n, 0] = dhat[kx % n, ky % n, 0]
+    assert np.array_equal(hmc.symmetrise(n, dhat), dhat)
+    delta = model.density_grid(prob, dhat)
+    pk = prob.pk_n2[kx * kx + ky * ky + kz * kz]
+    expect = 2.0 * pk / box ** 3
+    assert abs(float(np.mean(delta ** 2)) - expect) <= 1e-12 * expect
+    # the real-space amplitude of the cosine itself
+    assert abs(float(np.abs(delta).max()) - 2.0 * math.sqrt(var[kx % n, ky % n, kz]) / n ** 3) <= 1e-12 * expect ** 0.5
+
+
+@pytest.mark.parametrize("shape", ["flat", "bbks"])
+def test_mode_variance_field_variance(shape):
+    # Fields drawn with <|dhat_k|^2> = sigma_k^2 (complex Gaussian per
+    # independent mode, Hermitian partners mirrored) must have
+    # <delta(x)^2> = V^-1 sum_k P(|k|) over the retained modes of the whole
+    # spectrum: the discrete form of the variance integral of P(k).  The node
+    # and draw mean of delta^2 is compared with it; its relative standard
+    # deviation is (sum_pairs sigma^4)^(1/2) / sum_pairs sigma^2 / sqrt(draws),
+    # and the bound is 5 of those.
+    n, box, draws = 16, 200.0, 40
+    if shape == "flat":
+        prob = _pk_problem(n, box, lambda j: np.full(j.shape, 2.5e3))
+    else:
+        m = mocks.make_mock(n, box, 1, 50.0, seed=1)
+        prob = _pk_problem(n, box, lambda j: np.asarray(m.pk_n2, dtype=np.float64))
+    var = model.mode_variance(prob)
+    canon = hmc.canonical_mask(n)
+    nx, ny, nz = model.mode_indices(n)
+    n2 = nx * nx + ny * ny + nz * nz
+    # every retained mode of the full N^3 spectrum is a stored canonical
+    # entry or the partner -k of one: 2 per canonical entry
+    expect = 2.0 * float(np.sum(prob.pk_n2[n2][canon])) / box ** 3
+    rng = np.random.default_rng(2203)
+    acc = 0.0
+    for _ in range(draws):
+        z = rng.standard_normal(var.shape) + 1j * rng.standard_normal(var.shape)
+        dhat = hmc.symmetrise(n, np.sqrt(0.5 * var) * z)
+        acc += float(np.mean(model.density_grid(prob, dhat) ** 2))
+    got = acc / draws
+    s2 = var[canon]
+    rel_sd = math.sqrt(float(np.sum(s2 * s2))) / float(np.sum(s2)) / math.sqrt(draws)
+    assert abs(got / expect - 1.0) <= 5.0 * rel_sd, (got, expect, rel_sd)
+    # a factor of two in the normalisation (the variance of the real part read
+    # as P, or N^3 for N^6 / V) lies far outside this bound
+    assert 5.0 * rel_sd < 0.1
+
+
 def test_pack_unpack_roundtrip_is_hermitian():
     n = 8
     rng = np.random.default_rng(2)
