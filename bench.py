@@ -53,6 +53,10 @@ X_TRAFFIC_SOURCES_SHA1 = "209d30f89a36ef917279a3cc2741d6a24eb7fccf"
 X_TRAFFIC = {"grad": (334168061, 134217776), "first": (358662209, 703777705),
              "mid": (468539014, 401674702), "last": (468405644, 268503008)}
 
+# below this acceptance rate a chain hardly samples: the comparison of the two
+# paths "at equal acceptance" would be void, and the run reports failure
+MIN_ACCEPTANCE = 0.3
+
 
 def kernel_sources_sha1():
     import hashlib
@@ -71,13 +75,20 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5,
+                    help="untimed HMC iterations at the adapted step, after the adaptation")
+    ap.add_argument("--adapt", type=int, default=50,
+                    help="untimed dual-averaging iterations that set the step (target acceptance 0.65)")
     ap.add_argument("--leapfrog", type=int, default=20)
     ap.add_argument("--fp64-steps", type=int, default=20)
     ap.add_argument("--n-grid", type=int, default=256)
     ap.add_argument("--n-gal", type=int, default=30000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle processes of the all-cores CPU leg (0: the usable cores, at most 16)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-jobs", type=int, default=16, help="paper workload: requests of the short served stream")
     ap.add_argument("--workload", choices=("paper", "batched", "served"), default="paper")
     ap.add_argument("--jobs", type=int, default=64, help="served: number of requests")
     # about 0.7 x the service capacity of the shared launches: the 16-chain
@@ -88,6 +99,7 @@ def parse():
     ap.add_argument("--iters", type=int, default=100, help="served: HMC iterations per request")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (reference for traffic counters)")
+    ap.add_argument("--oracle-worker", default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -105,8 +117,164 @@ def touched_pencil_fraction(mock, d):
     return float(reach.mean())
 
 
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on the host cores
+# ---------------------------------------------------------------------------
+PROBLEM_KEYS = ("n_grid", "box", "omega_m", "h", "f_growth", "sigma_v", "pk_n2", "rhat", "mu", "sigma_mu", "cz",
+                "sigma_cz")
+
+
+def host_info():
+    """CPU model and the cores this process may run on (at most 16 are used:
+    the share of the host that comes with one GPU)."""
+    model_name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model_name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return model_name, usable
+
+
+def oracle_worker(path):
+    """One oracle evaluation in a child process (all-cores leg): loads the
+    problem and the state, reports ready, waits for the go line on stdin,
+    evaluates, reports its start and end times."""
+    import numpy as np
+
+    from oracle import model
+    z = np.load(path)
+    kw = {k: (z[k] if z[k].ndim else z[k].item()) for k in PROBLEM_KEYS}
+    kw["n_grid"] = int(kw["n_grid"])
+    prob = model.Problem(**kw)
+    dh, d, s = z["dhat"], z["d"], float(z["s"])
+    print("ready", flush=True)
+    sys.stdin.readline()
+    t0 = time.time()
+    model.logpost_grad(prob, dh, d, s)
+    print("done %.6f %.6f" % (t0, time.time()), flush=True)
+
+
+def cpu_all_cores(mock, dh, d, s, workers):
+    """Oracle evaluations of the same state in `workers` processes at once:
+    grad evals/s of the whole host (each process one thread)."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+    path = os.path.join(tempfile.gettempdir(), "hamlet_oracle_state_%d.npz" % os.getpid())
+    kw = mock.problem_kwargs()
+    np.savez(path, dhat=dh, d=d, s=s, **{k: np.asarray(kw[k]) for k in PROBLEM_KEYS})
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    procs = []
+    try:
+        for _ in range(workers):
+            procs.append(subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker", path],
+                                          stdin=subprocess.PIPE, stdout=subprocess.PIPE, env=env, text=True))
+        for p in procs:
+            if not p.stdout.readline().startswith("ready"):
+                raise RuntimeError("oracle worker failed to start")
+        t_go = time.time()
+        for p in procs:
+            p.stdin.write("go\n")
+            p.stdin.flush()
+        ends = []
+        for p in procs:
+            line = p.stdout.readline().split()
+            if not line or line[0] != "done":
+                raise RuntimeError("oracle worker failed")
+            ends.append(float(line[2]))
+        for p in procs:
+            p.wait(timeout=120)
+    finally:
+        for p in procs:
+            if p.poll() is None:
+                p.kill()
+                p.wait()
+        if os.path.exists(path):
+            os.remove(path)
+    wall = max(ends) - t_go
+    return workers / wall, wall
+
+
+def cpu_baseline(args, mock, dh, d, s):
+    """The oracle as it stands on the host: one evaluation of the timed
+    state on one thread (its result also gives the GPU paths' errors), the
+    same on every usable core at once, config 1's whole chain (32^3, 1000
+    points, 20 iterations of 10 leapfrog steps) and five config 2 gradients
+    (128^3, 10 000 points)."""
+    from oracle import hmc, model
+    from paper_2203_02369_amd import mocks
+    cpu_name, usable = host_info()
+    prob = model.Problem(**mock.problem_kwargs())
+    log("cpu oracle: one evaluation at %d^3 on one thread" % mock.n_grid)
+    tc = time.perf_counter()
+    ref = model.logpost_grad(prob, dh, d, s)
+    t1 = time.perf_counter() - tc
+    log("cpu oracle: %.1f s per gradient (one thread)" % t1)
+    workers = args.cpu_workers if args.cpu_workers > 0 else min(16, usable)
+    all_cores = None
+    if workers > 1:
+        log("cpu oracle: %d evaluations at once in %d processes" % (workers, workers))
+        try:
+            v_all, wall = cpu_all_cores(mock, dh, d, s, workers)
+            all_cores = {"value": round(v_all, 5), "cores": workers, "wall_s": round(wall, 2)}
+            log("cpu oracle, all cores: %.4f grad evals/s (%d in %.1f s)" % (v_all, workers, wall))
+        except Exception as e:   # reported, not fatal: the single-thread figure stands
+            all_cores = {"error": str(e)}
+            log("cpu oracle, all cores: failed: %s" % e)
+    # config 1: the plain FP64 chain of the smallest configuration, whole
+    m1 = mocks.plain_fp64_32()
+    p1 = model.Problem(**m1.problem_kwargs())
+    q1 = hmc.State(hmc.symmetrise(32, m1.dhat_true), m1.d_true.copy(), 1.5)
+    tc = time.perf_counter()
+    hmc.hmc_run(p1, q1, 20, 10, 0.02, mocks.config_seed(1) + 3, jitter=True)
+    t_c1 = time.perf_counter() - tc
+    log("cpu oracle, config 1 chain (32^3, 20 x 10): %.1f s" % t_c1)
+    # config 2: five gradients at 128^3, extrapolated to its 200 x 50 chain
+    m2 = mocks.single_chain_128()
+    p2 = model.Problem(**m2.problem_kwargs())
+    dh2 = hmc.symmetrise(128, m2.dhat_true)
+    tc = time.perf_counter()
+    for _ in range(5):
+        model.logpost_grad(p2, dh2, m2.d_true, 1.5)
+    t_c2 = (time.perf_counter() - tc) / 5
+    log("cpu oracle, config 2 (128^3): %.2f s per gradient" % t_c2)
+    single = {"value": round(1.0 / t1, 5), "cores": 1, "s_per_grad": round(t1, 2)}
+    use = all_cores if all_cores and "value" in all_cores else single
+    cpu = {"value": use["value"], "unit": "grad evals/s", "cores": use["cores"], "kind": "oracle",
+           "sample": "oracle log-posterior-and-gradient evaluations of the timed workload's state (%d^3, %d points; "
+                     "numpy FP64, own radix-2 FFT): %s" % (
+                         mock.n_grid, mock.n_gal,
+                         "%d at once in %d single-thread processes" % (use["cores"], use["cores"])
+                         if use is all_cores else "one on one thread"),
+           "cpu_model": cpu_name, "usable_cores": usable,
+           "single_thread": single, "all_cores": all_cores,
+           "config1_chain": {"workload": "32^3, box 400, 1000 points, 20 HMC iterations x 10 leapfrog steps (201 "
+                                         "gradients), one thread", "seconds": round(t_c1, 2),
+                             "grad_evals_per_s": round(201 / t_c1, 3)},
+           "config2_gradients": {"workload": "128^3, box 500, 10 000 points, 5 gradients, one thread",
+                                 "s_per_grad": round(t_c2, 3),
+                                 "chain_200x50_extrapolated_s": round(t_c2 * (200 * 50 + 1), 1)}}
+    return cpu, ref
+
+
+def rel_err(x, ref):
+    import numpy as np
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    den = float(np.abs(ref).max())
+    return float(np.abs(x - ref).max() / (den if den > 0 else 1.0))
+
+
 def main():
     args = parse()
+    if args.oracle_worker:
+        return oracle_worker(args.oracle_worker)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(independent chains shard across GPUs with no exchange; see the design notes)",
@@ -151,14 +319,35 @@ def main():
         qd = torch.from_numpy(d0.copy()).to(dev)
         return q, qd, plan.scalar(s0)
 
-    # ---- warm-up: dual averaging of the step on the FP32 path (untimed) -------
+    # ---- the oracle's state, on both GPU paths (their error is reported) -----
+    gpu_at_oracle_state = {}
+
+    def grad_at_start(plan):
+        q, qd, qs = state(plan)
+        g, gd, gs, psi = plan.zeros_modes(), plan.zeros_dist(), plan.scalar(), plan.scalar()
+        hamlet.logpost_grad([plan], [q], [qd], [qs], [g], [gd], [gs], [psi])
+        torch.cuda.synchronize()
+        gpu_at_oracle_state[plan.precision] = (psi.item(), g.cpu().numpy(), gd.cpu().numpy(), gs.item())
+
+    # ---- adaptation: dual averaging of the step on the FP32 path (untimed) ----
+    # The step is set by its own untimed phase, whatever --warmup says; then
+    # --warmup iterations run at that step, untimed, and both paths start from
+    # where they end.
     plan = hamlet.Plan.from_mock(mock, precision="fp32", device=dev)
+    grad_at_start(plan)
     q, qd, qs = state(plan)
     eps = 0.002
+    adapt = max(args.adapt, 1)
+    acc_a = torch.zeros(adapt, dtype=torch.int32, device=dev)
+    eps = hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=adapt, n_leapfrog=L, eps0=eps, seed=seed, warmup=adapt,
+                         jitter=True, accepted=[acc_a])[0]
+    log("adaptation: %d iterations, eps = %.4g (acceptance during adaptation %.2f)"
+        % (adapt, eps, acc_a.float().mean().item()))
     if args.warmup > 0:
-        eps = hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=args.warmup, n_leapfrog=L, eps0=eps, seed=seed,
-                             warmup=args.warmup, jitter=True)[0]
-    log("warm-up: %d iterations, eps = %.4g" % (args.warmup, eps))
+        hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=args.warmup, n_leapfrog=L, eps0=eps, seed=seed + 2,
+                       jitter=True, want_eps=False)
+    torch.cuda.synchronize()
+    log("warm-up: %d iterations at eps = %.4g" % (args.warmup, eps))
     start = (q.clone(), qd.clone(), qs.clone())     # both paths start here
 
     # ---- timed: FP32 fields + FP64 Hamiltonian --------------------------------
@@ -208,9 +397,129 @@ def main():
     log("passes: " + ", ".join("%s %.4f ms" % (k, v["avg_launch_ms"]) for k, v in passes.items()
                                if isinstance(v, dict)))
 
-    # ---- analysis of a state: sphere moments of the velocity field --------------
-    # (monopole and dipole in 16 spheres, four passes over the FP64 modes; the
-    # FP64 window per mode and radius bounds it, not the mode reads)
+    # ---- analysis of a state ----------------------------------------------------
+    analysis = run_analysis(hamlet, plan, q, mock, c_bytes)
+    plan.close()
+    del q, qd, qs
+
+    # ---- plain FP64 path, same start, step and seed ------------------------------
+    fp64 = None
+    acc64 = None
+    if not args.no_fp64 and args.fp64_steps > 0:
+        plan = hamlet.Plan.from_mock(mock, precision="fp64", device=dev)
+        grad_at_start(plan)
+        acc64_t = torch.zeros(args.fp64_steps, dtype=torch.int32, device=dev)
+        q, qd, qs = (t.clone() for t in start)
+        hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=1, n_leapfrog=2, eps0=eps, seed=seed, want_eps=False)
+        q, qd, qs = (t.clone() for t in start)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=args.fp64_steps, n_leapfrog=L, eps0=eps, seed=seed + 1,
+                       jitter=True, accepted=[acc64_t], want_eps=False)
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t3
+        v64 = (args.fp64_steps * L + 1) / dt64
+        acc64 = acc64_t.cpu().numpy()
+        m = min(len(acc64), len(acc32))
+        fp64 = {"value": round(v64, 2), "unit": "grad evals/s", "ms_per_step": round(1e3 * dt64 / args.fp64_steps, 3),
+                "steps": args.fp64_steps, "acceptance": float(acc64.mean()),
+                "same_decisions_as_fp32": "%d of %d" % (int((acc64[:m] == acc32[:m]).sum()), m),
+                "speedup_fp32_vs_fp64": round(value / v64, 3)}
+        log("fp64: %.1f grad/s, acceptance %.2f" % (v64, acc64.mean()))
+        plan.close()
+        del q, qd, qs
+
+    # ---- a short served stream: latency of continuous batching ----------------
+    served = None
+    if not args.no_served and args.served_jobs > 0 and n == 256:
+        served = run_served_short(args, hamlet, mocks, mock, dev)
+
+    # ---- roofline of the dominant kernel ------------------------------------
+    # k_x_pass: the x pass of every evaluation, fused with the leapfrog update
+    # and the next inverse pass 1.  Algorithmic bytes in units of one complex64
+    # spectral array c (8 N^2 N/2 bytes; complex128 arrays count 2c; the FP64
+    # per-mode prior variance sigma_k^2 counts 1c):
+    #   plain gradient (1 per run):        S1, S2, q, var in; G out           =  7c
+    #   first step of a chain's trajectory (momenta drawn in the pass):
+    #                                       G, q, var in; p, q, A, B and the
+    #                                       kept start q0, G0 out           = 15c
+    #   middle steps (L - 1 per traj.):    S1, S2, p, q, var in; p, q, A, B   = 13c
+    #   last step:                         S1, S2, p, q, var in; p, G out     = 11c
+    nm = n * n * (n // 2)
+    c32 = 8 * nm
+    x_bytes = c32 * (7 + args.steps * (15 + 13 * (L - 1) + 11))
+    x_launches = 1 + args.steps * (L + 1)
+    assert kern_launches == x_launches, (kern_launches, x_launches)
+    avg_ms = kern_ms / kern_launches
+    per_launch = x_bytes / x_launches
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if n == 256 and kernel_sources_sha1() == X_TRAFFIC_SOURCES_SHA1:
+        t = X_TRAFFIC
+        tot = sum(t["grad"]) + args.steps * (sum(t["first"]) + (L - 1) * sum(t["mid"]) + sum(t["last"]))
+        traffic = int(tot / x_launches)
+    roofline = {"bound": "hbm", "kernel": "k_x_pass (x FFT + gradient + leapfrog update + next inverse x FFT)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes_per_launch": int(per_launch), "avg_launch_ms": round(avg_ms, 4), "launches": kern_launches}
+
+    # ---- CPU baseline: the oracle on the host cores --------------------------
+    cpu = None
+    oracle_err = None
+    if not args.no_cpu_baseline and n <= 256:   # the oracle takes minutes per evaluation above 256^3
+        from oracle import hmc
+        dh_full = hmc.symmetrise(n, mock.dhat_true)
+        cpu, ref = cpu_baseline(args, mock, dh_full, d0, s0)
+        # the GPU paths' error against this same oracle evaluation (relative,
+        # max-norm per array; the modes compared on the stored kz < N/2)
+        oracle_err = {}
+        for prec, (psi, g, gd, gs) in gpu_at_oracle_state.items():
+            oracle_err[prec] = {"psi": abs(psi - ref[0]) / abs(ref[0]),
+                                "grad_modes": rel_err(g, ref[1][:, :, : n // 2]),
+                                "grad_dist": rel_err(gd, ref[2]),
+                                "grad_s": abs(gs - ref[3]) / abs(ref[3])}
+        log("error against the oracle: " + json.dumps(oracle_err))
+
+    out = {
+        "metric": "grad evals/s (fwd+adjoint) at %d³, N=3e4 vs plain FP64; p50/p99 job latency" % n,
+        "value": round(value, 2),
+        "unit": "grad evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 fields, f64 Hamiltonian",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale single chain: %d^3 grid, box 500 Mpc/h, %d points, "
+                               "HMC iteration of %d leapfrog steps" % (n, mock.n_gal, L),
+                   "n_grid": n, "n_gal": mock.n_gal, "leapfrog_steps": L, "eps": round(eps, 8),
+                   "adaptation_iterations": adapt,
+                   "acceptance": float(acc32.mean()), "grad_evals_timed": grads},
+        "fp64_path": fp64,
+        "served": served,
+        "oracle_err": oracle_err,
+        "roofline": roofline,
+        "passes": passes,
+        "analysis": analysis,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    low = [name for name, a in (("fp32", acc32), ("fp64", acc64)) if a is not None and a.mean() < MIN_ACCEPTANCE]
+    if low:
+        log("acceptance below %.2f on %s: the paths were not compared while sampling" % (MIN_ACCEPTANCE, low))
+        sys.exit(3)
+
+
+def run_analysis(hamlet, plan, q, mock, c_bytes):
+    """Timings of the on-device analysis of a state (sphere moments, velocity
+    and density fields, running sums of the maps, shell statistics)."""
+    import torch
+    n = mock.n_grid
+    # monopole and dipole in 16 spheres, four passes over the FP64 modes; the
+    # FP64 window per mode and radius bounds it, not the mode reads
     radii = [5.0 + 15.0 * j for j in range(16)]
     hamlet.sphere_moments(plan, q, radii)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -276,106 +585,46 @@ def main():
     ev1.record(plan.stream)
     ev1.synchronize()
     sh_ms = ev0.elapsed_time(ev1) / 3
-    analysis["shell_stats"] = {"shells": n_sh, "width": 10.0, "avg_call_ms": round(sh_ms, 4), "bytes_per_call": 4 * c_bytes,
-                               "sweeps": 2,
+    analysis["shell_stats"] = {"shells": n_sh, "width": 10.0, "avg_call_ms": round(sh_ms, 4),
+                               "bytes_per_call": 4 * c_bytes, "sweeps": 2,
                                "achieved": round(4 * c_bytes / (sh_ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
     log("shell statistics: %.3f ms per call" % sh_ms)
     del acc
-    plan.close()
-    del q, qd, qs
+    return analysis
 
-    # ---- plain FP64 path, same start, step and seed ------------------------------
-    fp64 = None
-    if not args.no_fp64 and args.fp64_steps > 0:
-        plan = hamlet.Plan.from_mock(mock, precision="fp64", device=dev)
-        acc64 = torch.zeros(args.fp64_steps, dtype=torch.int32, device=dev)
-        q, qd, qs = (t.clone() for t in start)
-        hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=1, n_leapfrog=2, eps0=eps, seed=seed, want_eps=False)
-        q, qd, qs = (t.clone() for t in start)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=args.fp64_steps, n_leapfrog=L, eps0=eps, seed=seed + 1,
-                       jitter=True, accepted=[acc64], want_eps=False)
-        torch.cuda.synchronize()
-        dt64 = time.perf_counter() - t3
-        v64 = (args.fp64_steps * L + 1) / dt64
-        a64 = acc64.cpu().numpy()
-        m = min(len(a64), len(acc32))
-        fp64 = {"value": round(v64, 2), "unit": "grad evals/s", "ms_per_step": round(1e3 * dt64 / args.fp64_steps, 3),
-                "steps": args.fp64_steps, "acceptance": float(a64.mean()),
-                "same_decisions_as_fp32": "%d of %d" % (int((a64[:m] == acc32[:m]).sum()), m),
-                "speedup_fp32_vs_fp64": round(value / v64, 3)}
-        log("fp64: %.1f grad/s, acceptance %.2f" % (v64, a64.mean()))
-        plan.close()
-        del q, qd, qs
 
-    # ---- roofline of the dominant kernel ------------------------------------
-    # k_x_pass: the x pass of every evaluation, fused with the leapfrog update
-    # and the next inverse pass 1.  Algorithmic bytes in units of one complex64
-    # spectral array c (8 N^2 N/2 bytes; complex128 arrays count 2c; the FP64
-    # per-mode prior variance sigma_k^2 counts 1c):
-    #   plain gradient (1 per run):        S1, S2, q, var in; G out           =  7c
-    #   first step of a chain's trajectory (momenta drawn in the pass):
-    #                                       G, q, var in; p, q, A, B and the
-    #                                       kept start q0, G0 out           = 15c
-    #   middle steps (L - 1 per traj.):    S1, S2, p, q, var in; p, q, A, B   = 13c
-    #   last step:                         S1, S2, p, q, var in; p, G out     = 11c
-    nm = n * n * (n // 2)
-    c32 = 8 * nm
-    x_bytes = c32 * (7 + args.steps * (15 + 13 * (L - 1) + 11))
-    x_launches = 1 + args.steps * (L + 1)
-    assert kern_launches == x_launches, (kern_launches, x_launches)
-    avg_ms = kern_ms / kern_launches
-    per_launch = x_bytes / x_launches
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = None
-    if n == 256 and kernel_sources_sha1() == X_TRAFFIC_SOURCES_SHA1:
-        t = X_TRAFFIC
-        tot = sum(t["grad"]) + args.steps * (sum(t["first"]) + (L - 1) * sum(t["mid"]) + sum(t["last"]))
-        traffic = int(tot / x_launches)
-    roofline = {"bound": "hbm", "kernel": "k_x_pass (x FFT + gradient + leapfrog update + next inverse x FFT)",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "bytes_per_launch": int(per_launch), "avg_launch_ms": round(avg_ms, 4), "launches": kern_launches}
+def run_served_short(args, hamlet, mocks, mock, dev):
+    """p50 / p99 latency of a short seeded Poisson stream of requests (grids
+    64^3, 128^3, 256^3; 1000-30 000 points; 100 iterations of 20 leapfrog
+    steps each), served by continuous batching in FP32 and, for comparison,
+    one job at a time by the plain FP64 path."""
+    import numpy as np
 
-    # ---- CPU baseline: the oracle on the host cores --------------------------
-    cpu = None
-    if not args.no_cpu_baseline and n <= 256:   # the oracle takes minutes per evaluation above 256^3
-        from oracle import hmc, model
-        prob = model.Problem(**mock.problem_kwargs())
-        dh = hmc.symmetrise(n, mock.dhat_true)
-        tc = time.perf_counter()
-        model.logpost_grad(prob, dh, d0, s0)
-        tcpu = time.perf_counter() - tc
-        cpu = {"value": round(1.0 / tcpu, 5), "unit": "grad evals/s", "cores": 1, "kind": "oracle",
-               "sample": "one oracle log-posterior-and-gradient evaluation at %d^3 with %d points "
-                         "(numpy FP64, own radix-2 FFT, single thread): %.1f s" % (n, mock.n_gal, tcpu)}
-        log("cpu oracle: %.1f s per gradient" % tcpu)
-
-    out = {
-        "metric": "grad evals/s (fwd+adjoint) at %d^3, N=3e4 vs plain FP64" % n,
-        "value": round(value, 2),
-        "unit": "grad evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * dt / args.steps, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 fields, f64 Hamiltonian",
-        "data": "synthetic",
-        "config": {"workload": "paper-scale single chain: %d^3 grid, box 500 Mpc/h, %d points, "
-                               "HMC iteration of %d leapfrog steps" % (n, mock.n_gal, L),
-                   "n_grid": n, "n_gal": mock.n_gal, "leapfrog_steps": L, "eps": round(eps, 6),
-                   "acceptance": float(acc32.mean()), "grad_evals_timed": grads},
-        "fp64_path": fp64,
-        "roofline": roofline,
-        "passes": passes,
-        "analysis": analysis,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+    class A:
+        jobs = args.served_jobs
+        rate = args.rate
+    trace = served_trace(A, mocks, np, pools=1)
+    universes = {(256, 0): mock}
+    for ng in (64, 128):
+        universes[(ng, 0)] = mocks.paper_scale_256(n_gal=30000, n_grid=ng, seed=mocks.config_seed(5) + ng)
+    L, n_iter = 20, 100
+    budget = 96 << 30
+    grads = sum(1 + n_iter * L for _ in trace)
+    lat32, span32 = serve_trace(hamlet, trace, universes, "fp32", 0, L, n_iter, budget, dev, "served fp32")
+    out = {"requests": len(trace), "rate_per_s": A.rate, "iterations": n_iter, "leapfrog_steps": L,
+           "latency_p50_s": round(float(np.percentile(lat32, 50)), 3),
+           "latency_p99_s": round(float(np.percentile(lat32, 99)), 3),
+           "grad_evals_per_s": round(grads / span32, 1), "makespan_s": round(span32, 2)}
+    log("served fp32: %d jobs, p50 %.2fs, p99 %.2fs" % (len(trace), out["latency_p50_s"], out["latency_p99_s"]))
+    if not args.no_fp64:
+        lat64, span64 = serve_trace(hamlet, trace, universes, "fp64", 1, L, n_iter, budget, dev, "fp64 one at a time")
+        out["fp64_one_job_at_a_time"] = {"latency_p50_s": round(float(np.percentile(lat64, 50)), 3),
+                                         "latency_p99_s": round(float(np.percentile(lat64, 99)), 3),
+                                         "grad_evals_per_s": round(grads / span64, 1),
+                                         "makespan_s": round(span64, 2)}
+        log("fp64 one at a time: p50 %.2fs, p99 %.2fs" % (float(np.percentile(lat64, 50)),
+                                                          float(np.percentile(lat64, 99))))
+    return out
 
 
 def run_batched(args, dev):
@@ -470,12 +719,12 @@ def run_batched(args, dev):
         p.close()
 
 
-def served_trace(args, mocks, np):
+def served_trace(args, mocks, np, pools=2):
     """Seeded request stream: arrival time, grid, pool universe, catalogue size, seed."""
     rng = np.random.default_rng(mocks.config_seed(5))
     t = np.cumsum(rng.exponential(1.0 / args.rate, args.jobs))
     grids = rng.choice([64, 128, 256], args.jobs)
-    pool = rng.integers(0, 2, args.jobs)
+    pool = rng.integers(0, pools, args.jobs)
     sizes = rng.integers(1000, 30001, args.jobs)
     return [dict(t=float(t[k]), n_grid=int(grids[k]), pool=int(pool[k]), n_gal=int(sizes[k]),
                  seed=mocks.config_seed(5) + 1000 + k) for k in range(args.jobs)]

@@ -26,7 +26,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import philox
-from .model import (H0, logpost_grad, mode_indices, mode_variance, pair_weight,
+from .model import (H0, exact_sum, logpost_grad, mode_indices, mode_variance, pair_weight,
                     retained_mask)
 
 
@@ -159,9 +159,10 @@ def kinetic(prob, p):
     """
     var = mode_variance(prob)
     w = pair_weight(prob.n_grid)
-    k_modes = float(np.sum(w * var * np.abs(p.modes) ** 2)) / 8.0
     _, minv_d, minv_s = inverse_mass(prob)
-    return k_modes + 0.5 * minv_d * float(np.sum(p.dist ** 2)) + 0.5 * minv_s * p.s * p.s
+    terms = [(w * var * np.abs(p.modes) ** 2 / 8.0).ravel(), 0.5 * minv_d * np.asarray(p.dist) ** 2,
+             [0.5 * minv_s * p.s * p.s]]
+    return exact_sum(np.concatenate(terms))
 
 
 def gradient(prob, q):

@@ -36,6 +36,10 @@ Readings of the paper used here (each is also listed in the design notes):
     dependent ln kappa_i of eqn:lvr is kept.
   * Domain.  zbar(d) needs d < c/(3 Omega0 H0) and mu(d) needs d > 0; outside
     it (or outside the support of the distance histogram) Psi = +inf.
+  * Sums.  Psi, dPsi/ds and the kinetic energy are the exact sums of their
+    terms rounded once (math.fsum): the Metropolis test takes the difference
+    of two such totals of millions of terms, and an exactly rounded sum is
+    the plain definition, free of any summation order.
 """
 import math
 from dataclasses import dataclass, field
@@ -377,6 +381,67 @@ def modes_adjoint(prob, d, g):
     return out
 
 
+def modes_adjoint_at(prob, d, g, kidx):
+    """modes_adjoint at a few half-spectrum entries kidx = (ix, iy, iz) arrays,
+    by the definition of the forward transform summed directly over the
+    nodes the points reach: Ghat_c(k) = sum_i g_i rhat_ic sum_corners
+    w_corner exp(-2 pi i n.j_corner / N).  For sampled checks on grids whose
+    full transforms are too large for the host."""
+    n = prob.n_grid
+    d = np.asarray(d, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    ix, iy, iz = (np.asarray(a, dtype=np.int64) for a in kidx)
+    x = galaxy_positions(prob, d)
+    i0, t = cic_cells(prob, x)
+    mult = velocity_multiplier(prob)
+    s = signed_index(n)
+    nvec = np.stack([s[ix], s[iy], iz], axis=1).astype(np.float64)     # (m, 3) signed wave numbers
+    ghat = np.zeros((3, len(ix)), dtype=np.complex128)
+    for ox, oy, oz in _corners():
+        off = np.array([ox, oy, oz])
+        w1 = np.where(off == 1, t, 1.0 - t)
+        w = w1[:, 0] * w1[:, 1] * w1[:, 2]
+        node = (i0 + off) % n                                            # (npts, 3)
+        phase = np.exp(-2j * math.pi * (node.astype(np.float64) @ nvec.T) / n)   # (npts, m)
+        for c in range(3):
+            ghat[c] += (g * prob.rhat[:, c] * w) @ phase
+    out = np.zeros(len(ix), dtype=np.complex128)
+    for c in range(3):
+        out += (2.0 / float(n) ** 3) * np.conj(mult[c][ix, iy, iz]) * ghat[c]
+    return out
+
+
+def logpost_grad_sampled(prob, dhat, d, s, kidx):
+    """Psi, the mode gradient at the entries kidx only (as logpost_grad's at
+    those entries), dPsi/dd and dPsi/ds.  The velocity field is the full
+    inverse transform; the adjoint is summed directly (modes_adjoint_at)."""
+    d = np.asarray(d, dtype=np.float64)
+    ok = in_domain(prob, d)
+    dsafe = np.where(ok, d, 1.0)
+    v = velocity_grids(prob, dhat)
+    u, du = cic_gather(prob, v, dsafe)
+    del v
+    t = galaxy_terms(prob, dsafe, s, u)
+    om = prob.omega_m
+    kappa2, r = t["kappa2"], t["r"]
+    zb = t["zbar"]
+    g = -r / kappa2
+    dk2 = 0.5 / kappa2 - 0.5 * r * r / kappa2 ** 2
+    dkappa2_dd = -2.0 * prob.sigma_cz ** 2 * zbar_prime(dsafe, om) / (1.0 + zb) ** 3
+    g_d = (-t["dmu"] * distance_modulus_prime(dsafe, om) / prob.sigma_mu ** 2
+           + (r / kappa2) * (v_obs_prime(prob.cz, dsafe, om) - du)
+           + dk2 * dkappa2_dd)
+    g_s = exact_sum(dk2 * 2.0 * SIGMA_NL_UNIT ** 2 * s)
+    ix, iy, iz = (np.asarray(a, dtype=np.int64) for a in kidx)
+    var = mode_variance(prob)[ix, iy, iz]
+    q = np.asarray(dhat)[ix, iy, iz]
+    g_modes = np.where(var > 0, 2.0 * q / np.where(var > 0, var, 1.0), 0.0) + modes_adjoint_at(prob, dsafe, g, kidx)
+    psi = exact_sum(np.concatenate([[prior_energy(prob, dhat)], t["psi"]])) if np.all(ok) else math.inf
+    if not np.isfinite(psi):
+        psi = math.inf
+    return psi, g_modes, g_d, g_s
+
+
 # ----------------------------------------------------------------------------
 # Psi and its gradient (eq:Psi with eqn:lmu, eqn:lvr, eq:kappa, eq:prior-k, eq:D)
 # ----------------------------------------------------------------------------
@@ -387,6 +452,13 @@ def in_domain(prob, d):
     return np.isfinite(d) & (d > 0.0) & (d < dmax)
 
 
+def exact_sum(terms):
+    """The sum of the terms rounded once (math.fsum): every sum of the
+    Hamiltonian (Psi, dPsi/ds, the kinetic energy) is taken this way, so that
+    it does not depend on the order or the number of its terms."""
+    return math.fsum(np.asarray(terms, dtype=np.float64).ravel().tolist())
+
+
 def prior_energy(prob, dhat):
     """-ln P(Delta_k) up to a constant: sum over independent modes |dhat|^2/sigma^2.
 
@@ -395,7 +467,7 @@ def prior_energy(prob, dhat):
     var = mode_variance(prob)
     w = pair_weight(prob.n_grid)
     safe = np.where(var > 0, var, 1.0)
-    return 0.5 * float(np.sum(w * np.abs(dhat) ** 2 / safe))
+    return exact_sum(0.5 * w * np.abs(dhat) ** 2 / safe)
 
 
 def galaxy_terms(prob, d, s, u):
@@ -419,7 +491,7 @@ def logpost(prob, dhat, d, s):
     v = velocity_grids(prob, dhat)
     u, _ = cic_gather(prob, v, d)
     terms = galaxy_terms(prob, d, s, u)
-    total = prior_energy(prob, dhat) + float(np.sum(terms["psi"]))
+    total = exact_sum(np.concatenate([[prior_energy(prob, dhat)], terms["psi"]]))
     return total if np.isfinite(total) else math.inf
 
 
@@ -449,14 +521,14 @@ def logpost_grad(prob, dhat, d, s):
     g_d = (-t["dmu"] * distance_modulus_prime(dsafe, om) / prob.sigma_mu ** 2
            + (r / kappa2) * (v_obs_prime(prob.cz, dsafe, om) - du)
            + dk2 * dkappa2_dd)
-    g_s = float(np.sum(dk2 * 2.0 * SIGMA_NL_UNIT ** 2 * s))
+    g_s = exact_sum(dk2 * 2.0 * SIGMA_NL_UNIT ** 2 * s)
     # Modes: prior term 2 dhat / sigma^2 plus the adjoint of the projected
     # gather through the inverse transform: (2/N^3) sum_c conj(m_c) FFT(G_c).
     var = mode_variance(prob)
     safe = np.where(var > 0, var, 1.0)
     g_modes = np.where(var > 0, 2.0 * dhat / safe, 0.0).astype(np.complex128)
     g_modes += modes_adjoint(prob, dsafe, g)
-    psi = prior_energy(prob, dhat) + float(np.sum(t["psi"]))
+    psi = exact_sum(np.concatenate([[prior_energy(prob, dhat)], t["psi"]])) if np.all(ok) else math.inf
     if not (np.all(ok) and np.isfinite(psi)):
         psi = math.inf
     return psi, g_modes, g_d, g_s

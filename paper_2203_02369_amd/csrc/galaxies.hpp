@@ -245,7 +245,7 @@ __device__ __forceinline__ void
 like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, const double* __restrict__ frac,
           double* __restrict__ dist, const double* snl_q, Catalogue cat, Cosmo cm, T* __restrict__ gsort,
           LikeOut out, LeapUpdate lf, const BinNext* next) {
-  __shared__ double red[4 * (kGalThreads / 64)];
+  __shared__ double red[2 * 4 * (kGalThreads / 64)];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double psi = 0.0, dps = 0.0, bad = 0.0;
   if (i < cat.n) {
@@ -307,36 +307,38 @@ like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, cons
   // this block's slice of the prior partials
   const int per = (out.n_prior + out.n_blocks - 1) / out.n_blocks;
   const int lo = blockIdx.x * per, hi = min(out.n_prior, lo + per);
-  double pr = 0.0;
-  for (int j = lo + threadIdx.x; j < hi; j += blockDim.x) pr += out.prior_part[j];
-  double sums[4] = {psi, dps, bad, pr};
-  block_sums(sums, red);
+  CSum sums[4];
+  sums[0].add(psi);
+  sums[1].add(dps);
+  sums[2].add(bad);
+  for (int j = lo + threadIdx.x; j < hi; j += blockDim.x) sums[3].add(out.prior_part[j]);
+  block_csums(sums, red);
   if (threadIdx.x == 0) {
-    out.part[4 * blockIdx.x + 0] = sums[0];
-    out.part[4 * blockIdx.x + 1] = sums[1];
-    out.part[4 * blockIdx.x + 2] = sums[2];
-    out.part[4 * blockIdx.x + 3] = sums[3];
+    out.part[4 * blockIdx.x + 0] = sums[0].value();
+    out.part[4 * blockIdx.x + 1] = sums[1].value();
+    out.part[4 * blockIdx.x + 2] = sums[2].value();
+    out.part[4 * blockIdx.x + 3] = sums[3].value();
   }
 }
 
-// Final deterministic sums: Psi = prior + sum of galaxy terms (+inf when a
-// distance left the domain or Psi is not finite); dPsi/ds.
+// Final deterministic sums (compensated): Psi = prior + sum of galaxy terms
+// (+inf when a distance left the domain or Psi is not finite); dPsi/ds.
 __device__ __forceinline__ void
 finalize_body(const double* __restrict__ prior_part, int n_prior, const double* __restrict__ like_part, int n_like,
               double* __restrict__ psi_out, double* __restrict__ gs_out, double* snl_q, LeapUpdate lf) {
-  __shared__ double red[3 * 4];   // blocks of up to 256 threads
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int i = threadIdx.x; i < n_prior; i += blockDim.x) a += prior_part[i];
+  __shared__ double red[2 * 3 * 4];   // blocks of up to 256 threads
+  CSum sums[3];
+  for (int i = threadIdx.x; i < n_prior; i += blockDim.x) sums[0].add(prior_part[i]);
   for (int i = threadIdx.x; i < n_like; i += blockDim.x) {
-    a += like_part[4 * i] + like_part[4 * i + 3];
-    b += like_part[4 * i + 1];
-    c += like_part[4 * i + 2];
+    sums[0].add(like_part[4 * i]);
+    sums[0].add(like_part[4 * i + 3]);
+    sums[1].add(like_part[4 * i + 1]);
+    sums[2].add(like_part[4 * i + 2]);
   }
-  double sums[3] = {a, b, c};
-  block_sums(sums, red);
-  a = sums[0];
-  b = sums[1];
-  c = sums[2];
+  block_csums(sums, red);
+  const double a = sums[0].value();
+  const double b = sums[1].value();
+  const double c = sums[2].value();
   if (threadIdx.x == 0) {
     const bool ok = c == 0.0 && isfinite(a);
     psi_out[0] = ok ? a : __builtin_inf();

@@ -79,12 +79,12 @@ template <typename T, int N> __device__ __forceinline__ double* kin_small(const 
 
 // Distance and s terms of the kinetic energy, one partial per block.
 template <typename T, int N>
-__device__ __forceinline__ void kinetic_small_part(const Pick<T, N>& k, double acc, double* red) {
+__device__ __forceinline__ void kinetic_small_part(const Pick<T, N>& k, CSum acc, double* red) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && k.w.pc().sample_s) {
     const double ps = k.w.ps()[0];
-    acc += 0.5 * ps * ps;
+    acc.add(0.5 * ps * ps);
   }
-  const double s = block_sum(acc, red);
+  const double s = block_csum(acc, red);
   if (threadIdx.x == 0) kin_small(k.w)[blockIdx.x] = s;
 }
 
@@ -92,20 +92,20 @@ __device__ __forceinline__ void kinetic_small_part(const Pick<T, N>& k, double a
 // saved start point of the small variables, and their part of K0.
 template <typename T, int N>
 __global__ void __launch_bounds__(kEltThreads) k_momenta_small(Launch L) {
-  __shared__ double red[kEltThreads / 64];
+  __shared__ double red[2 * (kEltThreads / 64)];
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
   const PlanConst& pc = k.w.pc();
   const ChainScalars* cs = chain(k.w);
   const uint64_t seed = cs->seed;
   const uint32_t iteration = (uint32_t)cs->iter;
-  double acc = 0.0;
+  CSum acc;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k.n_gal; i += gridDim.x * blockDim.x) {
     const double pv = pc.sample_d ? pc.psd * normal_pair(draw_words(seed, iteration, kPurposeDist, i)).x : 0.0;
     k.w.pd()[i] = pv;
     k.w.qd0()[i] = k.st.qd[i];
     k.w.gd0()[i] = k.w.gd()[i];
-    acc += 0.5 * pc.minv_d * pv * pv;
+    acc.add(0.5 * pc.minv_d * pv * pv);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     k.w.ps()[0] = pc.sample_s ? normal_pair(draw_words(seed, iteration, kPurposeSnl, 0)).x : 0.0;
@@ -117,27 +117,27 @@ __global__ void __launch_bounds__(kEltThreads) k_momenta_small(Launch L) {
 // Distance and s terms of K1 (grid: N_KIN_SMALL blocks).
 template <typename T, int N>
 __global__ void __launch_bounds__(kEltThreads) k_kinetic_small(Launch L) {
-  __shared__ double red[kEltThreads / 64];
+  __shared__ double red[2 * (kEltThreads / 64)];
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
   const double minv = k.w.pc().minv_d;
   const double* __restrict__ pd = k.w.pd();
-  double acc = 0.0;
+  CSum acc;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k.n_gal; i += gridDim.x * blockDim.x)
-    acc += 0.5 * minv * pd[i] * pd[i];
+    acc.add(0.5 * minv * pd[i] * pd[i]);
   kinetic_small_part(k, acc, red);
 }
 
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_kinetic_final(Launch L, int which) {
-  __shared__ double red[4];
+  __shared__ double red[2 * 4];
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
   const PlanConst& pc = k.w.pc();
   const double* __restrict__ kin = k.w.kin_part();
-  double a = 0.0;
-  for (int i = threadIdx.x; i < pc.n_kin_part; i += blockDim.x) a += kin[i];
-  a = block_sum(a, red);
+  CSum acc;
+  for (int i = threadIdx.x; i < pc.n_kin_part; i += blockDim.x) acc.add(kin[i]);
+  const double a = block_csum(acc, red);
   if (threadIdx.x == 0) {
     ChainScalars* cs = chain(k.w);
     if (which) cs->kin1 = a;

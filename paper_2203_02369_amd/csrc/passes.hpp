@@ -122,6 +122,67 @@ template <int K> __device__ __forceinline__ void block_sums(double (&v)[K], doub
   }
 }
 
+// Neumaier's compensated summation: a running sum s and the rounding errors
+// c of its additions, each recovered exactly as the two-sum error of the
+// operands, so that the value s + c carries the sum to about one rounding
+// whatever the number and spread of the terms.  Every FP64 sum of the
+// Hamiltonian (the log-posterior, its derivative in s, the kinetic energy)
+// runs in it: block partials per thread, across the block, and over the
+// blocks' partials.
+struct CSum {
+  double s, c;
+  __device__ __forceinline__ CSum() : s(0.0), c(0.0) {}
+  __device__ __forceinline__ void add(double x) {
+    const double t = s + x;
+    c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  // adds another compensated sum
+  __device__ __forceinline__ void add(double s2, double c2) {
+    const double t = s + s2;
+    c += (fabs(s) >= fabs(s2) ? (s - t) + s2 : (s2 - t) + s) + c2;
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return s + c; }
+};
+
+// K compensated block sums in a fixed order (wave64 shuffles, then the waves
+// in order in thread 0); red holds 2 K (waves per block) doubles.  Results
+// valid in thread 0.
+template <int K> __device__ __forceinline__ void block_csums(CSum (&v)[K], double* red) {
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    for (int off = 32; off > 0; off >>= 1) {
+      const double s2 = __shfl_down(v[j].s, off, 64), c2 = __shfl_down(v[j].c, off, 64);
+      v[j].add(s2, c2);
+    }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      red[2 * (j * nw + wid)] = v[j].s;
+      red[2 * (j * nw + wid) + 1] = v[j].c;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      CSum t;
+      for (int i = 0; i < nw; ++i) t.add(red[2 * (j * nw + i)], red[2 * (j * nw + i) + 1]);
+      v[j] = t;
+    }
+  }
+}
+
+// One compensated block sum; the value is valid in thread 0.
+__device__ __forceinline__ double block_csum(CSum v, double* red) {
+  CSum a[1] = {v};
+  block_csums<1>(a, red);
+  return a[0].value();
+}
+
 // Visit this thread's elements (a = index along the FFT axis, w = column)
 // of a strided tile.
 template <typename T, int N, int NT, typename Fn>
@@ -272,12 +333,12 @@ inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* _
   using LAY = typename S::Row;
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
-  __shared__ double red[NT / 64];
+  __shared__ double red[2 * (NT / 64)];
   load_twiddles<T, N, NT>(twl, tw);
   const int2 tl = strided_tile<T, N>();
   const int y = tl.y, z0 = tl.x * S::W;
   const int sy = signed_freq(y, N);
-  double prior = 0.0;
+  CSum prior;
   // i kfac q (and n_x times it), zero on excluded modes
   auto ain = [&](int x, int w, double scale_x) {
     const int kz = z0 + w, sx = signed_freq(x, N);
@@ -295,11 +356,11 @@ inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* _
     if (retained(sx, sy, kz, N)) {
       const size_t g = gofs<N>(x, y, kz);
       const double2 q = modes[g];
-      prior += (kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(tab.var[var_ofs(N, S::W, x, y, kz)]);
+      prior.add((kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(tab.var[var_ofs(N, S::W, x, y, kz)]));
     }
     tile[LAY::idx(x, w)] = cconvert<C>(ain(x, w, 0.0));
   });
-  const double ps = block_sum(prior, red);
+  const double ps = block_csum(prior, red);
   if (threadIdx.x == 0) prior_part[blockIdx.y * gridDim.x + blockIdx.x] = ps;
   __syncthreads();
   lds_fft<T, N, S::W, LAY, NT, +1>(tile, twl);
@@ -977,7 +1038,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
   constexpr bool kKinetic = kStartOfChain || MODE == kXLast;
   __shared__ C tile[LAY::size(N)];
   __shared__ C twl[N];
-  __shared__ double red[NT / 64];
+  __shared__ double red[2 * (NT / 64)];
   // twiddles into LDS once the first tile loads are issued
   TwiddleStage<T, N, NT> tws;
   tws.load(tw);
@@ -1002,7 +1063,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
   }
   const double eps = MODE == kXGrad ? 0.0 : eps_ptr[0];
   const double hk = MODE == kXMid ? eps : 0.5 * eps;
-  double prior = 0.0, kin = 0.0;
+  CSum prior, kin;
   // B-input of the next inverse pass (n_x times the A-input), kept in registers
   C bin[elems_per_thread<T, N, NT>()];
   tile_elems<T, N, NT>([&](int e, int x, int w) {
@@ -1056,10 +1117,10 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
       // per stored mode (w / 8) sigma^2 |p|^2, w = 1 on kz = 0 (both
       // Hermitian partners stored), else 2
       const double wk = kz == 0 ? 0.125 : 0.25;
-      if (kStartOfChain && keep) kin += wk * var * (p.x * p.x + p.y * p.y);
+      if (kStartOfChain && keep) kin.add(wk * var * (p.x * p.x + p.y * p.y));
       p.x -= hk * G.x;
       p.y -= hk * G.y;
-      if (MODE == kXLast && keep) kin += wk * var * (p.x * p.x + p.y * p.y);
+      if (MODE == kXLast && keep) kin.add(wk * var * (p.x * p.x + p.y * p.y));
       st_stream(&mom[g], p);
       if constexpr (kDrift) {
         double2 a = make_double2(0.0, 0.0);
@@ -1068,7 +1129,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
           q.x += c * p.x;
           q.y += c * p.y;
           st_stream(&modes[g], q);
-          prior += (kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(var);
+          prior.add((kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(var));
           const double kf = mode_kfac(tab.kfac0, n2);
           a = make_double2(-kf * q.y, kf * q.x);      // i kfac q
         }
@@ -1078,13 +1139,13 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
     }
   });
   if constexpr (kKinetic) {
-    const double ks = block_sum(kin, red);
+    const double ks = block_csum(kin, red);
     if (threadIdx.x == 0) save.kin_part[blockIdx.y * gridDim.x + blockIdx.x] = ks;
   } else {
     (void)kin;
   }
   if constexpr (kDrift) {
-    const double ps = block_sum(prior, red);
+    const double ps = block_csum(prior, red);
     if (threadIdx.x == 0) prior_part[blockIdx.y * gridDim.x + blockIdx.x] = ps;
     __syncthreads();
     tile_elems<T, N, NT>([&](int e, int x, int w) { tile[LAY::idx(x, w)] = acc[e]; });

@@ -198,9 +198,79 @@ def test_batched_chain_matches_oracle(hl):
     res = hmc.hmc_run(oracle_problem(m), hmc.State(dhat, d.copy(), s), n_iter, n_lf, eps0, seeds[1], jitter=True)
     q, qd, qs, msum, dh, acc = _pull(runs[1])
     assert np.array_equal(acc, res.accepted)
-    assert rel_inf(from_lib_layout(q), res.state.modes) <= 1e-10
-    assert rel_inf(qd, res.state.dist) <= 1e-10
-    assert rel_inf(from_lib_layout(msum), res.mode_sum) <= 1e-10
+    errs = {"modes": rel_inf(from_lib_layout(q), res.state.modes), "dist": rel_inf(qd, res.state.dist),
+            "mode_sum": rel_inf(from_lib_layout(msum), res.mode_sum)}
+    say("batched chain errors against the oracle", errs)
+    for k, e in errs.items():
+        assert e <= 1e-12, (k, e)
+    for p in plans:
+        p.close()
+
+
+_big = {}
+
+
+def _big_members(n_grid):
+    """Three problems at one of the benchmark's grid sizes (box 500 Mpc/h,
+    n ~ 1/r, zone of avoidance): two FP32 plans that share launches and one
+    FP64 plan, a group of its own that runs beside them.  At 64^3 the
+    30 000-point catalogue crowds its columns (the scatter's dense path)."""
+    if n_grid not in _big:
+        sizes = {64: (30000, 4000, 9000), 128: (10000, 2500, 6000), 256: (30000, 5000, 12000)}[n_grid]
+        out = []
+        for k, (ng, prec) in enumerate(zip(sizes, ("fp32", "fp32", "fp64"))):
+            m = mocks.paper_scale_256(n_gal=ng, n_grid=n_grid, seed=mocks.config_seed(4) + 50 * k + n_grid)
+            rng = np.random.default_rng(400 + k)
+            out.append((m, prec, start_modes(m), m.d_true * (1.0 + 0.02 * rng.standard_normal(m.n_gal)),
+                        1.1 + 0.1 * k))
+        _big[n_grid] = out
+    return _big[n_grid]
+
+
+@pytest.mark.parametrize("n_grid", [64, 128, 256])
+def test_shared_launches_at_benchmark_grids(hl, n_grid):
+    # The tile widths, thread counts and scatter paths of the benchmark's
+    # instantiations in shared launches: gradients and a two-step leapfrog
+    # of the batch bit-identical to each plan alone, gradients against the
+    # oracle, and at 64^3 and 128^3 the leapfrog too.
+    mem = _big_members(n_grid)
+    plans = [hl.Plan.from_mock(m, precision=prec) for (m, prec, _, _, _) in mem]
+    states = [_state(p, dh, d, s) for p, (_, _, dh, d, s) in zip(plans, mem)]
+    say("shared launches at %d^3: gradient" % n_grid)
+    together = _grad(hl, plans, states)
+    for j, p in enumerate(plans):
+        assert _same(together[j], _grad(hl, [p], [states[j]])[0]), "plan %d differs when batched" % j
+    moms = [_momenta(p, 70 + j) for j, p in enumerate(plans)]
+    eps = [2e-4, 3e-4, 2e-4]
+    say("shared launches at %d^3: leapfrog" % n_grid)
+    lf_together = _leap(hl, plans, states, moms, eps, [2, 2, 2])
+    for j, p in enumerate(plans):
+        assert _same(lf_together[j], _leap(hl, [p], [states[j]], [moms[j]], [eps[j]], [2])[0]), \
+            "plan %d leapfrog differs when batched" % j
+    for j, (m, prec, dhat, d, s) in enumerate(mem):
+        say("oracle gradient %d at %d^3" % (j, n_grid))
+        prob = oracle_problem(m)
+        ref = model.logpost_grad(prob, dhat, d, s)
+        g, gd, gs, psi = together[j]
+        tol_psi, tol_g = (1e-12, 1e-12) if prec == "fp64" else (2e-5, 1e-4)
+        errs = {"psi": abs(psi[0] - ref[0]) / abs(ref[0]), "modes": rel_inf(from_lib_layout(g), ref[1]),
+                "dist": rel_inf(gd, ref[2]), "s": abs(gs[0] - ref[3]) / abs(ref[3])}
+        say("  errors", prec, errs)
+        assert errs["psi"] <= tol_psi
+        assert max(errs["modes"], errs["dist"], errs["s"]) <= tol_g
+        if n_grid <= 128 and j in (0, 2):
+            pm, pd, ps = moms[j]
+            q0 = hmc.State(dhat, d.copy(), s)
+            p0 = hmc.State(from_lib_layout(pm), pd.copy(), ps)
+            q1, p1, c1 = hmc.leapfrog(prob, q0, p0, eps[j], 2)
+            got = lf_together[j]
+            lerrs = {"modes": rel_inf(from_lib_layout(got[0]) - q0.modes, q1.modes - q0.modes),
+                     "dist": rel_inf(got[1] - q0.dist, q1.dist - q0.dist),
+                     "p_modes": rel_inf(from_lib_layout(got[3]) - p0.modes, p1.modes - p0.modes),
+                     "p_dist": rel_inf(got[4] - p0.dist, p1.dist - p0.dist)}
+            say("  leapfrog displacement errors", prec, lerrs)
+            assert max(lerrs.values()) <= tol_g
+            assert abs(got[6][0] - c1[0]) <= tol_psi * abs(c1[0])
     for p in plans:
         p.close()
 

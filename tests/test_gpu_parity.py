@@ -266,13 +266,20 @@ def test_leapfrog_matches_oracle(hl, precision):
     psi = plan.scalar()
     hl.leapfrog([plan], [eps], [steps], [tq], [tqd], [tqs], [tp], [tpd], [tps], [psi])
     torch.cuda.synchronize()
-    tol = 1e-11 if precision == "fp64" else 1e-4
-    assert rel_inf(from_lib_layout(tq.cpu().numpy()), q1.modes) <= tol
-    assert rel_inf(tqd.cpu().numpy(), q1.dist) <= tol
-    assert rel_inf(from_lib_layout(tp.cpu().numpy()), p1.modes) <= tol * 10
-    assert rel_inf(tpd.cpu().numpy(), p1.dist) <= tol * 10
-    assert abs(tqs.item() - q1.s) <= tol * abs(q1.s)
-    assert abs(psi.item() - c1[0]) <= (1e-12 if precision == "fp64" else TOL32_PSI) * abs(c1[0])
+    # The displacements of every coordinate and momentum are compared (the
+    # end states are dominated by the unchanged start): each is eps times a
+    # sum of gradients, so it carries the gradient's tolerance.
+    tol = TOL64 if precision == "fp64" else TOL32_GRAD
+    errs = {"modes": rel_inf(from_lib_layout(tq.cpu().numpy()) - q0.modes, q1.modes - q0.modes),
+            "dist": rel_inf(tqd.cpu().numpy() - q0.dist, q1.dist - q0.dist),
+            "p_modes": rel_inf(from_lib_layout(tp.cpu().numpy()) - p0.modes, p1.modes - p0.modes),
+            "p_dist": rel_inf(tpd.cpu().numpy() - p0.dist, p1.dist - p0.dist),
+            "s": abs((tqs.item() - q0.s) - (q1.s - q0.s)) / abs(q1.s - q0.s),
+            "p_s": abs((tps.item() - p0.s) - (p1.s - p0.s)) / abs(p1.s - p0.s)}
+    say("leapfrog displacement errors", precision, errs)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+    assert abs(psi.item() - c1[0]) <= (TOL64 if precision == "fp64" else TOL32_PSI) * abs(c1[0])
     plan.close()
 
 
@@ -356,10 +363,14 @@ def test_paper_scale_leapfrog_matches_oracle_fp32(hl):
     torch.cuda.synchronize()
     dq = from_lib_layout(tq.cpu().numpy()) - q0.modes
     dp = from_lib_layout(tp.cpu().numpy()) - p0.modes
-    assert rel_inf(dq, q1.modes - q0.modes) <= 1e-4
-    assert rel_inf(dp, p1.modes - p0.modes) <= 1e-3
-    assert rel_inf(tqd.cpu().numpy() - q0.dist, q1.dist - q0.dist) <= 1e-3
-    assert rel_inf(tpd.cpu().numpy() - p0.dist, p1.dist - p0.dist) <= 1e-3
+    errs = {"modes": rel_inf(dq, q1.modes - q0.modes), "p_modes": rel_inf(dp, p1.modes - p0.modes),
+            "dist": rel_inf(tqd.cpu().numpy() - q0.dist, q1.dist - q0.dist),
+            "p_dist": rel_inf(tpd.cpu().numpy() - p0.dist, p1.dist - p0.dist),
+            "s": abs((tqs.item() - q0.s) - (q1.s - q0.s)) / abs(q1.s - q0.s),
+            "p_s": abs((tps.item() - p0.s) - (p1.s - p0.s)) / abs(p1.s - p0.s)}
+    say("256^3 fp32 leapfrog displacement errors", errs)
+    for k, e in errs.items():
+        assert e <= TOL32_GRAD, (k, e)
     assert abs(psi.item() - c1[0]) <= TOL32_PSI * abs(c1[0])
     plan.close()
 
@@ -415,12 +426,19 @@ def test_hmc_chain_matches_oracle_fp64(hl):
     say("accept oracle", res.accepted.tolist(), "gpu", acc_g.tolist())
     assert np.array_equal(acc_g, res.accepted)
     assert 0 < res.accepted.sum() < n_iter or res.accepted.sum() == n_iter
+    # dH is the difference of two Hamiltonians of size |H| ~ Psi; the
+    # tolerance is TOL64 of the Hamiltonian it is taken from
     fin = np.isfinite(res.dh)
-    assert np.allclose(dh_g[fin], res.dh[fin], rtol=1e-6, atol=1e-8)
-    assert rel_inf(from_lib_layout(tq.cpu().numpy()), res.state.modes) <= 1e-10
-    assert rel_inf(tqd.cpu().numpy(), res.state.dist) <= 1e-10
-    assert abs(tqs.item() - res.state.s) <= 1e-10 * abs(res.state.s)
-    assert rel_inf(from_lib_layout(msum.cpu().numpy()), res.mode_sum) <= 1e-10
+    assert np.array_equal(fin, np.isfinite(dh_g))
+    h_scale = abs(ref[0])
+    errs = {"dh": float(np.abs(dh_g[fin] - res.dh[fin]).max()) / h_scale,
+            "modes": rel_inf(from_lib_layout(tq.cpu().numpy()), res.state.modes),
+            "dist": rel_inf(tqd.cpu().numpy(), res.state.dist),
+            "s": abs(tqs.item() - res.state.s) / abs(res.state.s),
+            "mode_sum": rel_inf(from_lib_layout(msum.cpu().numpy()), res.mode_sum)}
+    say("fp64 chain errors after %d iterations" % n_iter, errs)
+    for k, e in errs.items():
+        assert e <= TOL64, (k, e)
     plan.close()
 
 
@@ -441,9 +459,97 @@ def test_hmc_dual_averaging_matches_oracle_fp64(hl):
                          warmup=warm, accepted=[acc])
     torch.cuda.synchronize()
     assert np.array_equal(acc.cpu().numpy(), res.accepted)
-    assert abs(eps_out[0] - res.eps) <= 1e-9 * res.eps
-    assert rel_inf(from_lib_layout(tq.cpu().numpy()), res.state.modes) <= 1e-9
+    errs = {"eps": abs(eps_out[0] - res.eps) / res.eps,
+            "modes": rel_inf(from_lib_layout(tq.cpu().numpy()), res.state.modes)}
+    say("dual averaging errors", errs)
+    for k, e in errs.items():
+        assert e <= TOL64, (k, e)
     plan.close()
+
+
+def test_hmc_chain_fp32_decisions_match_oracle(hl):
+    # The FP32-field path under the same Philox stream as the FP64 oracle:
+    # momenta and u are the same numbers, the force differs by the FP32
+    # rounding of the fields.  Every accept decision must equal the oracle's
+    # unless it is a near-tie, |ln u + dH| below the FP32 error of dH; the
+    # first such flip sends the two chains apart, so decisions are compared up
+    # to it, and any tie is reported.
+    from oracle import philox
+    m, prob, dhat, d, s, ref = case("32^3 L400 n1000 sphere")
+    q0 = hmc.State(dhat, d.copy(), s)
+    n_iter, n_lf, eps, seed = 20, 10, 0.02, 2211
+    res = hmc.hmc_run(prob, q0, n_iter, n_lf, eps, seed, jitter=True)
+    say("hmc fp32 against the oracle")
+    plan = hl.Plan.from_mock(m, precision="fp32")
+    dev = plan.device
+    tq = torch.from_numpy(to_lib_layout(q0.modes)).to(dev)
+    tqd = torch.from_numpy(q0.dist.copy()).to(dev)
+    tqs = plan.scalar(q0.s)
+    dh = torch.zeros(n_iter, dtype=torch.float64, device=dev)
+    acc = torch.zeros(n_iter, dtype=torch.int32, device=dev)
+    hl.hmc_run([plan], [tq], [tqd], [tqs], n_iter=n_iter, n_leapfrog=n_lf, eps0=eps, seed=seed, jitter=True,
+               dh=[dh], accepted=[acc])
+    torch.cuda.synchronize()
+    plan.close()
+    acc_g, dh_g = acc.cpu().numpy(), dh.cpu().numpy()
+    ln_u = np.array([math.log(float(philox.uniform53(*philox.draw_words(seed, it, philox.PURPOSE_ACCEPT, [0])[0, :2])))
+                     for it in range(n_iter)])
+    # FP32 error of dH: the force error (2e-5 of the fields) enters dH
+    # through the likelihood terms at both ends; bounded here by the measured
+    # dH differences before any flip, and at least 1e-3
+    agree = np.cumprod(acc_g == res.accepted).astype(bool)
+    upto = int(agree.sum())
+    fin = np.isfinite(res.dh[:upto])
+    dh_err = float(np.abs(dh_g[:upto][fin] - res.dh[:upto][fin]).max()) if fin.any() else 0.0
+    tie = max(1e-3, 2.0 * dh_err)
+    say("fp32 chain: decisions", acc_g.tolist(), "oracle", res.accepted.tolist(), "dH error before any flip %.3g"
+        % dh_err)
+    assert 0 < res.accepted.sum()
+    if upto < n_iter:
+        it = upto
+        margin = abs(ln_u[it] + res.dh[it])
+        say("decision %d differs: near-tie |ln u + dH| = %.3g (FP32 dH error bound %.3g)" % (it, margin, tie))
+        assert margin <= tie, "a decision away from a tie differs"
+    # before the first flip the chains are the same map to FP32 accuracy
+    assert dh_err <= 1e-2, dh_err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_paper_scale_delta_h_matches_oracle(hl, precision):
+    # 256^3, 30 000 points: one HMC iteration of two leapfrog steps from the
+    # benchmark's state with Philox momenta on both sides.  The Hamiltonian
+    # (about 1e7, millions of terms) is summed with compensation on the GPU
+    # and exactly rounded in the oracle; dH must agree within 1e-12 of H in
+    # FP64 and within 1e-3 absolute in FP32 (the FP32 fields move Psi by
+    # about 1e-4 at each end, far below the O(1) scale of dH that the
+    # Metropolis test reads).
+    m = mocks.paper_scale_256()
+    prob = oracle_problem(m)
+    q0 = hmc.State(hmc.symmetrise(256, m.dhat_true), m.d_true.copy(), 1.5)
+    eps, n_lf, seed = 1e-4, 2, 909
+    if "dh256" not in _cache:
+        say("oracle 256^3 trajectory (three evaluations on the host)")
+        _cache["dh256"] = hmc.hmc_run(prob, q0, 1, n_lf, eps, seed)
+    res = _cache["dh256"]
+    say("gpu 256^3 trajectory", precision)
+    plan = hl.Plan.from_mock(m, precision=precision)
+    dev = plan.device
+    tq = torch.from_numpy(to_lib_layout(q0.modes)).to(dev)
+    tqd = torch.from_numpy(q0.dist.copy()).to(dev)
+    tqs = plan.scalar(q0.s)
+    dh = torch.zeros(1, dtype=torch.float64, device=dev)
+    acc = torch.zeros(1, dtype=torch.int32, device=dev)
+    hl.hmc_run([plan], [tq], [tqd], [tqs], n_iter=1, n_leapfrog=n_lf, eps0=eps, seed=seed, dh=[dh], accepted=[acc])
+    torch.cuda.synchronize()
+    plan.close()
+    psi0 = model.prior_energy(prob, q0.modes)   # the bulk of Psi, and of H
+    err = abs(dh.item() - res.dh[0])
+    say("dH gpu %.12g oracle %.12g: error %.3g (H ~ %.3g)" % (dh.item(), res.dh[0], err, psi0))
+    assert np.isfinite(res.dh[0])
+    if precision == "fp64":
+        assert err <= TOL64 * abs(psi0), err
+    else:
+        assert err <= 1e-3, err
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

@@ -13,10 +13,10 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import model
+from oracle import hmc, model
 from paper_2203_02369_amd import _capi, mocks
 
-from helpers import start_modes, to_lib_layout
+from helpers import from_lib_layout, oracle_problem, rel_inf, start_modes, to_lib_layout
 
 pytestmark = pytest.mark.gpu
 
@@ -88,6 +88,43 @@ def test_served_job_equals_hmc_run(hl):
     plan.close()
     assert _same(got, ref)
     assert 0 < got["accepted"].sum()
+
+
+def test_served_job_matches_oracle_chain(hl):
+    # A served FP64 job running beside another job (another grid size and
+    # precision) against the oracle's chain: the same Philox key, so the same
+    # momenta, jitter, uniforms, accept decisions, adapted step and states.
+    m = mocks.make_mock(16, 200.0, 300, 80.0, "sphere", (0.2, 0.2), seed=31)
+    other = mocks.make_mock(32, 400.0, 400, 120.0, "sphere", (0.2, 0.2), seed=41)
+    start = _start(m, 0)
+    chain = dict(n_iter=10, n_leapfrog=5, eps0=0.03, warmup=4, jitter=True)
+    sv = hl.Server(4 * GIB)
+    say("served job beside another, against the oracle chain")
+    job = _submit(sv, m, "fp64", 2203, start, **chain)
+    side = _submit(sv, other, "fp32", 9, _start(other, 1))
+    _drain(sv, [job, side])
+    got = sv.take(job)
+    sv.take(side)
+    sv.close()
+    prob = oracle_problem(m)
+    q0 = hmc.State(from_lib_layout(start[0]), start[1].copy(), start[2])
+    res = hmc.hmc_run(prob, q0, chain["n_iter"], chain["n_leapfrog"], chain["eps0"], 2203,
+                      warmup=chain["warmup"], jitter=True)
+    say("accept oracle", res.accepted.tolist(), "served", got["accepted"].tolist())
+    assert np.array_equal(got["accepted"], res.accepted)
+    assert 0 < res.accepted.sum()
+    fin = np.isfinite(res.dh)
+    assert np.array_equal(fin, np.isfinite(got["dh"]))
+    h_scale = abs(model.logpost(prob, q0.modes, q0.dist, q0.s))
+    errs = {"dh": float(np.abs(got["dh"][fin] - res.dh[fin]).max()) / h_scale,
+            "eps": abs(got["eps"] - res.eps) / res.eps,
+            "modes": rel_inf(from_lib_layout(got["q_modes"]), res.state.modes),
+            "dist": rel_inf(got["q_dist"], res.state.dist),
+            "s": abs(got["q_snl"] - res.state.s) / abs(res.state.s),
+            "mode_sum": rel_inf(from_lib_layout(got["mode_sum"]), res.mode_sum)}
+    say("served job errors against the oracle", errs)
+    for k, e in errs.items():
+        assert e <= 1e-12, (k, e)
 
 
 def test_job_alone_equals_job_in_a_mix(hl):

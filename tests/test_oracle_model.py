@@ -324,6 +324,32 @@ def test_mode_operator_adjoint_dot_product():
     assert abs(lhs - rhs) <= 1e-13 * max(abs(lhs), np.abs(ax).max())
 
 
+@pytest.mark.parametrize("n_grid", [8, 16])
+def test_direct_adjoint_at_sampled_modes_equals_the_transform(n_grid):
+    # The adjoint summed directly over the nodes the points reach, at every
+    # stored entry, against the scatter-and-transform form (pinned above by
+    # the dot-product test and the exact central differences below).
+    m, prob = _problem(n_grid=n_grid, n_gal=70, box=40.0 * n_grid)
+    n = prob.n_grid
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal(prob.n_gal)
+    full = model.modes_adjoint(prob, m.d_true, g)
+    ix, iy, iz = np.meshgrid(np.arange(n), np.arange(n), np.arange(n // 2 + 1), indexing="ij")
+    kidx = (ix.ravel(), iy.ravel(), iz.ravel())
+    direct = model.modes_adjoint_at(prob, m.d_true, g, kidx)
+    assert np.abs(direct - full.ravel()).max() <= 1e-12 * np.abs(full).max()
+    # and the sampled evaluation agrees with the whole one where it is defined
+    dhat = hmc.symmetrise(n, m.dhat_true)
+    d = m.d_true * (1.0 + 0.01 * rng.standard_normal(prob.n_gal))
+    ref = model.logpost_grad(prob, dhat, d, 1.3)
+    pick = rng.choice(len(kidx[0]), 40, replace=False)
+    sub = tuple(a[pick] for a in kidx)
+    got = model.logpost_grad_sampled(prob, dhat, d, 1.3, sub)
+    assert got[0] == ref[0] and got[3] == ref[3]
+    assert np.array_equal(got[2], ref[2])
+    assert np.abs(got[1] - ref[1][sub]).max() <= 1e-12 * np.abs(ref[1]).max()
+
+
 # ---------------------------------------------------------- the gradient --
 
 def _psi(prob, x_flat, d, s):
