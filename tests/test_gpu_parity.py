@@ -15,7 +15,7 @@ import torch
 from oracle import hmc, model
 from paper_2203_02369_amd import mocks
 
-from helpers import from_lib_layout, oracle_problem, rel_inf, start_modes, to_lib_layout
+from helpers import check_adapted_chain, from_lib_layout, oracle_problem, rel_inf, start_modes, to_lib_layout
 
 pytestmark = pytest.mark.gpu
 
@@ -455,15 +455,14 @@ def test_hmc_dual_averaging_matches_oracle_fp64(hl):
     tqd = torch.from_numpy(q0.dist.copy()).to(dev)
     tqs = plan.scalar(q0.s)
     acc = torch.zeros(n_iter, dtype=torch.int32, device=dev)
+    dh = torch.zeros(n_iter, dtype=torch.float64, device=dev)
     eps_out = hl.hmc_run([plan], [tq], [tqd], [tqs], n_iter=n_iter, n_leapfrog=n_lf, eps0=eps, seed=seed,
-                         warmup=warm, accepted=[acc])
+                         warmup=warm, accepted=[acc], dh=[dh])
     torch.cuda.synchronize()
     assert np.array_equal(acc.cpu().numpy(), res.accepted)
-    errs = {"eps": abs(eps_out[0] - res.eps) / res.eps,
-            "modes": rel_inf(from_lib_layout(tq.cpu().numpy()), res.state.modes)}
-    say("dual averaging errors", errs)
-    for k, e in errs.items():
-        assert e <= TOL64, (k, e)
+    check_adapted_chain(res, warm, eps_out[0], dh.cpu().numpy(), {"modes": (from_lib_layout(tq.cpu().numpy()),
+                                                                           res.state.modes, q0.modes)},
+                        abs(model.logpost(prob, q0.modes, q0.dist, q0.s)))
     plan.close()
 
 
