@@ -268,6 +268,21 @@ hamlet_status hamlet_field_stats_accumulate(hamlet_plan* plan, const void* modes
 hamlet_status hamlet_shell_stats(hamlet_plan* plan, const double* a, const double* b, double width,
                                  int32_t n_shells, double* out);
 
+/* As hamlet_shell_stats, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the partial sums live in a static device array of 32 MiB
+ * that each device the library runs on holds until the process ends; the
+ * call allocates and frees nothing.  Its partials need (N/4)(N/8)(N/16)
+ * tiles x (shells a tile reaches) x 24 bytes, at most 4.7 MB at 256^3 with
+ * shells of 10 Mpc/h; a call that would need more than 32 MiB fails with
+ * HAMLET_EINVAL before anything is enqueued.  Every call on a device shares
+ * that device's array: calls that overlap on one device (two streams, or
+ * two host threads) race and must be ordered by the caller.  Results equal
+ * hamlet_shell_stats bit for bit.  The first call on a device looks up the
+ * array's address there (no allocation).  Asynchronous on the plan's stream. */
+hamlet_status hamlet_shell_stats_static(hamlet_plan* plan, const double* a, const double* b, double width,
+                                        int32_t n_shells, double* out);
+
 /* ---- Sphere moments of the velocity field ----
  *
  * Section 5 (monopole and dipole) follows the reconstruction by the moments

@@ -107,6 +107,8 @@ SIGNATURES = {
     "hamlet_field_stats_accumulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hamlet_shell_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                           ctypes.c_int32, ctypes.c_void_p]),
+    "hamlet_shell_stats_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                                 ctypes.c_int32, ctypes.c_void_p]),
     "hamlet_server_create": (ctypes.c_int, [ctypes.POINTER(ServerDesc), ctypes.c_void_p,
                                             ctypes.POINTER(ctypes.c_void_p)]),
     "hamlet_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),

@@ -84,6 +84,7 @@ struct Ops {
 };
 
 struct hamlet_plan {
+  int device = 0;                  // the HIP device the plan was created on
   int n = 0, prec = 0, n_gal = 0, sample_d = 1, sample_s = 1, n_hist = 0;
   double box = 0, om = 0, h = 0, f = 0, sigma_v = 0, hist_w = 5.0, minv_d = 0;
   hipStream_t stream = nullptr;
@@ -621,7 +622,10 @@ static hamlet_status plan_make(const hamlet_plan_desc* desc, const hamlet_catalo
   st = check_catalog(cat);
   if (st != HAMLET_OK) return st;
   const double w = desc->hist_width > 0 ? desc->hist_width : 5.0;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return fail(HAMLET_EDEVICE, "hipGetDevice failed");
   hamlet_plan* pl = new hamlet_plan();
+  pl->device = device;
   fill_plan_scalars(pl, desc, cat->n, distance_prior_bins(cat, desc->omega_m, w));
   pl->stream = stream;
   pl->pooled = pooled;
@@ -1142,8 +1146,40 @@ extern "C" hamlet_status hamlet_field_stats_accumulate(hamlet_plan* plan, const 
 // Statistics of two fields in spherical shells (Section 5, correlation
 // coefficients)
 // ---------------------------------------------------------------------------
-extern "C" hamlet_status hamlet_shell_stats(hamlet_plan* plan, const double* a, const double* b, double width,
-                                            int32_t n_shells, double* out) {
+// Scratch of the allocation-free variant: a file-scope device array, one
+// copy per device, held until the process ends.  In host code `scratch`
+// names a host-side stand-in, not a device address: the array's address on
+// each device is looked up once, with that device current, and only that
+// address reaches kernels.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+static hamlet_status static_scratch(int device, double** out) {
+  static std::mutex mu;
+  static std::map<int, double*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) {
+    *out = it->second;
+    return HAMLET_OK;
+  }
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != device) HIP_TRY(hipSetDevice(device));
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess || !p) return fail(HAMLET_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  addr[device] = static_cast<double*>(p);
+  *out = static_cast<double*>(p);
+  return HAMLET_OK;
+}
+
+// Both sweeps of the shell statistics, with their partial sums in `part`
+// (hipMallocAsync on the plan's stream when `fixed` is false, else the
+// device's static scratch).
+static hamlet_status shell_stats_run(hamlet_plan* plan, const double* a, const double* b, double width,
+                                     int32_t n_shells, double* out, bool fixed) {
   if (!plan || (n_shells > 0 && (!a || !out))) return fail(HAMLET_EINVAL, "NULL argument");
   if (n_shells < 0 || n_shells > kShellMax)
     return fail(HAMLET_EINVAL, "n_shells %d outside [0, %d]", (int)n_shells, kShellMax);
@@ -1159,17 +1195,37 @@ extern "C" hamlet_status hamlet_shell_stats(hamlet_plan* plan, const double* a, 
   g.slots = (int)std::min(bound, (double)n_shells + 1.0);
   const size_t bytes = (size_t)nbx * nby * nbz * g.slots * kShellValues * sizeof(double);
   double* part = nullptr;
-  if (hipMallocAsync((void**)&part, bytes, plan->stream) != hipSuccess)
+  if (fixed) {
+    if (bytes > kStaticScratchBytes)
+      return fail(HAMLET_EINVAL,
+                  "shell partials need %zu bytes (%d shells per %dx%dx%d tile on %d^3), the static scratch holds %zu: "
+                  "use wider or fewer shells, or hamlet_shell_stats",
+                  bytes, g.slots, kShellTX, kShellTY, kShellTZ, plan->n, kStaticScratchBytes);
+    hamlet_status st = static_scratch(plan->device, &part);
+    if (st != HAMLET_OK) return st;
+  } else if (hipMallocAsync((void**)&part, bytes, plan->stream) != hipSuccess) {
     return fail(HAMLET_ENOMEM, "shell partials: %zu bytes", bytes);
-  // the means, then the centred sums (both sweeps reuse the partials)
+  }
+  // the means, then the centred sums (both sweeps reuse the partials; every
+  // partial the finish stage reads is written by the part stage before it)
   k_shell_part<false><<<dim3(nbz, nby, nbx), kShellThreads, 0, plan->stream>>>(a, b, g, out, part);
   k_shell_finish<false><<<n_shells, kShellFinishThreads, 0, plan->stream>>>(part, g, out);
   k_shell_part<true><<<dim3(nbz, nby, nbx), kShellThreads, 0, plan->stream>>>(a, b, g, out, part);
   k_shell_finish<true><<<n_shells, kShellFinishThreads, 0, plan->stream>>>(part, g, out);
   const hipError_t le = hipGetLastError();
-  HIP_TRY(hipFreeAsync(part, plan->stream));
+  if (!fixed) HIP_TRY(hipFreeAsync(part, plan->stream));
   if (le != hipSuccess) return fail(HAMLET_EDEVICE, "kernel launch: %s", hipGetErrorString(le));
   return HAMLET_OK;
+}
+
+extern "C" hamlet_status hamlet_shell_stats(hamlet_plan* plan, const double* a, const double* b, double width,
+                                            int32_t n_shells, double* out) {
+  return shell_stats_run(plan, a, b, width, n_shells, out, false);
+}
+
+extern "C" hamlet_status hamlet_shell_stats_static(hamlet_plan* plan, const double* a, const double* b, double width,
+                                                   int32_t n_shells, double* out) {
+  return shell_stats_run(plan, a, b, width, n_shells, out, true);
 }
 
 // ---------------------------------------------------------------------------

@@ -268,12 +268,14 @@ def field_stats_accumulate(plan, modes, acc=None):
     return acc
 
 
-def shell_stats(plan, a, b, width, n_shells, out=None):
+def shell_stats(plan, a, b, width, n_shells, out=None, static_scratch=False):
     """Statistics of float64 grids a and b (N, N, N) in spherical shells of
     the given width (Mpc/h) about the observer, on the plan's stream
     (hamlet_shell_stats): a float64 device tensor (n_shells, 6) of (count,
     mean a, scatter a, mean b, scatter b, correlation) per shell; b may be
-    None."""
+    None.  static_scratch=True calls hamlet_shell_stats_static, which
+    allocates nothing (pass `out` as well to keep the call free of torch
+    allocations)."""
     n = plan.n_grid
     for name, g in (("a", a), ("b", b)):
         if g is None and name == "b":
@@ -286,9 +288,10 @@ def shell_stats(plan, a, b, width, n_shells, out=None):
         out = torch.empty((max(n_shells, 0), 6), dtype=torch.float64, device=plan.device)
     elif out.dtype != torch.float64 or out.numel() != 6 * n_shells or not out.is_contiguous() or out.device != plan.device:
         raise ValueError("out must be contiguous float64 (%d, 6) on %s" % (n_shells, plan.device))
-    _capi.check(_capi.load().hamlet_shell_stats(plan.handle, ctypes.c_void_p(a.data_ptr()),
-                                                ctypes.c_void_p(b.data_ptr() if b is not None else None),
-                                                float(width), n_shells, ctypes.c_void_p(out.data_ptr())))
+    lib = _capi.load()
+    fn = lib.hamlet_shell_stats_static if static_scratch else lib.hamlet_shell_stats
+    _capi.check(fn(plan.handle, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr() if b is not None else None),
+                   float(width), n_shells, ctypes.c_void_p(out.data_ptr())))
     return out
 
 
