@@ -16,7 +16,9 @@ Stream layout shared with the GPU path (a reading: the paper states none):
     key     = (seed & 0xffffffff, seed >> 32)
     counter = (index & 0xffffffff, index >> 32, iteration, purpose)
     index of a mode: (kx N + ky) N/2 + kz; of a distance: its catalogue
-    position; of sigma_NL and of the accept/jitter draws: 0.
+    position; of sigma_NL and of the accept/jitter draws: 0; of a NUTS
+    direction or new-subtree draw: the doubling j; of a NUTS merge: the node
+    ((j * 16 + height) << 32) | position.
 Uniforms: u = ((x >> 11) + 1) * 2^-53 in (0, 1], x = (w1 << 32) | w0 built
 from two 32-bit output words.  Normals: Box-Muller on two such uniforms.
 """
@@ -33,6 +35,13 @@ PURPOSE_DIST = 1
 PURPOSE_SNL = 2
 PURPOSE_ACCEPT = 3
 PURPOSE_JITTER = 4
+# the No-U-Turn sampler's draws: direction of each doubling (index: the
+# doubling), the merge of the two halves of a subtree (index: doubling,
+# height and position of the node) and the move to a new subtree's sample
+# (index: the doubling)
+PURPOSE_NUTS_DIR = 5
+PURPOSE_NUTS_MERGE = 6
+PURPOSE_NUTS_TOP = 7
 
 
 def philox4x32_10(counter, key):

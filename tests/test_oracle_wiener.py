@@ -11,8 +11,9 @@ from oracle import hmc, model, wiener
 from paper_2203_02369_amd import mocks
 
 
-def integrated_autocorrelation_time(x):
-    """Geyer's initial monotone sequence estimator, per column of x (n_s, m)."""
+def integrated_autocorrelation_time(x, floor=1.0):
+    """Geyer's initial monotone sequence estimator, per column of x (n_s, m),
+    at least `floor` (below 1 for antithetic chains such as NUTS often gives)."""
     n = x.shape[0]
     xc = x - x.mean(axis=0)
     f = np.fft.rfft(xc, n=2 * n, axis=0)
@@ -28,7 +29,7 @@ def integrated_autocorrelation_time(x):
             g = min(g, prev)
             prev = g
             tau += 2.0 * g
-        out[j] = max(tau, 1.0)
+        out[j] = max(tau, floor)
     return out
 
 
