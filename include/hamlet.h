@@ -187,6 +187,60 @@ hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_plans, const h
                              void* const* mode_sum, double* const* dh, int32_t* const* accepted,
                              double* eps_out);
 
+/* ---- The No-U-Turn sampler ----
+ *
+ * Section 3.3 samples with the No-U-Turn sampler of Hoffman & Gelman (JMLR
+ * 15, 2014), whose step is tuned by their dual averaging.  Each iteration
+ * draws momenta r0 ~ N(0, M) (eq:M_ab; the stream and index of
+ * hamlet_hmc_run's momenta), a slice variable ln u = ln U - H0 (U in (0, 1],
+ * purpose of the Metropolis uniform), then doubles the trajectory in random
+ * directions, 2^j leapfrog steps at doubling j, until a subtree or the whole
+ * trajectory turns back ((theta+ - theta-) . r < 0 at either end, over the
+ * independent real coordinates), a leaf leaves the slice by more than
+ * Delta_max = 1000, or max_depth doublings are done.  Within a doubling
+ * the two halves of every subtree merge with probability n''/(n' + n'') for
+ * the second half's sample (n = leaves in the slice); after a doubling the
+ * chain moves to its sample with probability min(1, n'/n).  Each decision
+ * takes one uniform of the chain's Philox4x32-10 stream: direction of
+ * doubling j (purpose 5, index j), merge of the node of height h and
+ * position k in doubling j (purpose 6, index ((16 j + h) << 32) | k), move
+ * after doubling j (purpose 7, index j); "with probability a/b" is U b <= a,
+ * direction -1 iff U <= 1/2.  During the first `warmup` iterations the step
+ * adapts to the mean acceptance statistic alpha / n_alpha of the leaves; its
+ * averaged value is kept after them. */
+typedef struct {
+  int32_t n_iter;           /* NUTS iterations */
+  int32_t warmup;           /* iterations of dual averaging (the step is fixed after them) */
+  int32_t max_depth;        /* most doublings per iteration, 1 .. 12 (Hoffman & Gelman use 10) */
+  int32_t reserved;         /* 0 */
+  double eps0;              /* initial step */
+  double target_accept;     /* dual-averaging target of alpha / n_alpha (Section 3.3: 0.65) */
+  uint64_t seed;            /* Philox4x32-10 key of plan j's chain: seed + j (or seeds[j]) */
+  const uint64_t* seeds;    /* host, n_plans keys, or NULL */
+} hamlet_nuts_opts;
+
+/* Runs n_iter NUTS iterations of each plan's chain from its state q_*
+ * (device, in: start, out: last state), on the plans' streams.  mode_sum[j]
+ * (device, may be NULL) accumulates the post-warm-up states (eq:int_mc
+ * numerator).  Host outputs per iteration (each may be NULL, n_iter entries):
+ * depth[j] doublings done, n_leapfrog[j] leapfrog steps (gradient
+ * evaluations), leaf[j] 2 ints per iteration, (doubling, position in it) of
+ * the leaf the chain moved to, (-1, 0) if it stayed, accept_stat[j] the
+ * iteration's alpha / n_alpha.  eps_out (host, may be NULL): the step after
+ * warm-up.  Plans of one grid size and precision advance their trees
+ * together, one leapfrog step per chain in shared launches; each chain's
+ * numbers do not depend on which others share them.  The host builds the
+ * trees and reads two scalars per chain and step back, so the call returns
+ * when the chains are done.  Device memory: the first call on a plan
+ * allocates, and keeps until hamlet_plan_destroy, 3 max_depth + 12 state-
+ * sized buffers (modes, distances, s: 134 MB each at 256^3; a call with a
+ * larger max_depth reallocates them).  Errors: HAMLET_EINVAL for bad
+ * arguments, HAMLET_ENOMEM when the buffers do not fit. */
+hamlet_status hamlet_nuts_run(hamlet_plan* const* plans, int32_t n_plans, const hamlet_nuts_opts* opts,
+                              void* const* q_modes, double* const* q_dist, double* const* q_snl,
+                              void* const* mode_sum, int32_t* const* depth, int32_t* const* n_leapfrog,
+                              int32_t* const* leaf, double* const* accept_stat, double* eps_out);
+
 /* ---- The paper's flat parameter vector ----
  *
  * Section 3.1 orders the parameters of the posterior as one real vector:

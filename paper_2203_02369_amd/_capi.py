@@ -64,6 +64,19 @@ class HmcOpts(ctypes.Structure):
     ]
 
 
+class NutsOpts(ctypes.Structure):
+    _fields_ = [
+        ("n_iter", ctypes.c_int32),
+        ("warmup", ctypes.c_int32),
+        ("max_depth", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("eps0", ctypes.c_double),
+        ("target_accept", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("seeds", ctypes.POINTER(ctypes.c_uint64)),
+    ]
+
+
 class ServerDesc(ctypes.Structure):
     _fields_ = [
         ("hbm_budget", ctypes.c_size_t),
@@ -97,6 +110,9 @@ SIGNATURES = {
                                        c_double_pp, c_void_pp, c_double_pp, c_double_pp, c_double_pp]),
     "hamlet_hmc_run": (ctypes.c_int, [c_void_pp, ctypes.c_int32, ctypes.POINTER(HmcOpts), c_void_pp, c_double_pp,
                                       c_double_pp, c_void_pp, c_double_pp, ctypes.POINTER(c_int32_p), c_double_p]),
+    "hamlet_nuts_run": (ctypes.c_int, [c_void_pp, ctypes.c_int32, ctypes.POINTER(NutsOpts), c_void_pp, c_double_pp,
+                                       c_double_pp, c_void_pp, ctypes.POINTER(c_int32_p), ctypes.POINTER(c_int32_p),
+                                       ctypes.POINTER(c_int32_p), c_double_pp, c_double_p]),
     "hamlet_flat_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "hamlet_pack_flat": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, c_double_p, c_double_p]),
     "hamlet_unpack_flat": (ctypes.c_int, [ctypes.c_void_p, c_double_p, ctypes.c_void_p, c_double_p, c_double_p]),

@@ -22,6 +22,7 @@
 #include "passes.hpp"
 #include "galaxies.hpp"
 #include "hmc.hpp"
+#include "nuts.hpp"
 #include "workspace.hpp"
 
 using namespace hamlet;
@@ -81,6 +82,8 @@ struct Ops {
   hamlet_status (*field)(const Batch&, void*);    // the velocity field of the plan's modes, to the caller
   hamlet_status (*density)(const Batch&, void*);  // the density contrast of the plan's modes, to the caller
   hamlet_status (*stats)(const Batch&, double*);  // delta, v_r and their squares added to running sums
+  hamlet_status (*nuts_start)(const Batch&);      // NUTS: momenta r0 (st.p, st.pd, st.ps) and K0
+  hamlet_status (*kin1)(const Batch&);            // kinetic energy after a trajectory's last step -> K1
 };
 
 struct hamlet_plan {
@@ -105,6 +108,7 @@ struct hamlet_plan {
   bool pooled = false;             // workspace from the stream-ordered pool
   int n_prior_part = 0, n_like_part = 0, n_kin_part = 0;
   bool chain_ready = false;        // chain state and cached gradient valid (resume)
+  struct NutsMem* nuts = nullptr;  // buffers of the No-U-Turn sampler (first hamlet_nuts_run)
   const Ops* ops = nullptr;
   // event timing of one kernel kind (hamlet_profile_start / stop)
   int prof_kind = -1;
@@ -383,6 +387,35 @@ static hamlet_status end_impl(const Batch& b) {
   return HAMLET_OK;
 }
 
+// Start of a NUTS iteration: momenta r0 ~ N(0, M) of every coordinate into
+// the state's momenta (st.p, st.pd, st.ps) and K0 = K(r0) into the chain
+// scalars.
+template <typename T, int N>
+static hamlet_status nuts_start_impl(const Batch& b) {
+  if (b.count <= 0) return HAMLET_OK;
+  const Launch sel = launch_table(b, 0);
+  const unsigned nb = (unsigned)b.count;
+  using F = FixedLayout<N, sizeof(T)>;
+  k_nuts_momenta<T, N><<<dim3(F::N_PRIOR, 1, nb), kEltThreads, 0, b.stream>>>(sel);
+  k_momenta_small<T, N><<<dim3(F::N_KIN_SMALL, 1, nb), kEltThreads, 0, b.stream>>>(sel);
+  k_kinetic_final<T, N><<<dim3(1, 1, nb), 256, 0, b.stream>>>(sel, 0);
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
+// K1 after a trajectory's last step: the mode part summed by its x pass,
+// the distances and s here.
+template <typename T, int N>
+static hamlet_status kin1_impl(const Batch& b) {
+  if (b.count <= 0) return HAMLET_OK;
+  const Launch sel = launch_table(b, 0);
+  const unsigned nb = (unsigned)b.count;
+  k_kinetic_small<T, N><<<dim3(FixedLayout<N, sizeof(T)>::N_KIN_SMALL, 1, nb), kEltThreads, 0, b.stream>>>(sel);
+  k_kinetic_final<T, N><<<dim3(1, 1, nb), 256, 0, b.stream>>>(sel, 1);
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
 template <typename T, int N>
 static hamlet_status leap_out_impl(const Batch& b) {
   if (b.count <= 0) return HAMLET_OK;
@@ -421,7 +454,7 @@ template <typename T, int N> static void locate_impl(hamlet_plan* pl) {
 template <typename T, int N> struct OpsFor {
   static constexpr Ops ops{eval_impl<T, N>,      start_impl<T, N>, first_impl<T, N>,  end_impl<T, N>,
                            leap_out_impl<T, N>,   bytes_impl<T, N>, locate_impl<T, N>, field_impl<T, N>,
-                           density_impl<T, N>,    stats_impl<T, N>};
+                           density_impl<T, N>,    stats_impl<T, N>, nuts_start_impl<T, N>, kin1_impl<T, N>};
 };
 
 template <typename T> static const Ops* pick_ops(int n) {
@@ -672,9 +705,57 @@ extern "C" hamlet_status hamlet_plan_create(const hamlet_plan_desc* desc, const 
   return HAMLET_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Device memory of a plan's No-U-Turn chain: the two ends of the trajectory
+// (coordinates, momenta, gradient each), pools of kept coordinates (tree
+// candidates and the first leaves of subtrees) and kept momenta, the dot
+// products' partials and the values read back after each step.  A "set" is
+// one state-shaped allocation: modes | distances | small coordinates.
+// ---------------------------------------------------------------------------
+struct NutsSet {
+  double2* modes = nullptr;
+  double* dist = nullptr;
+  double* small = nullptr;
+};
+
+struct NutsMem {
+  int depth = 0;                  // most doublings the pools serve
+  size_t set_bytes = 0;
+  char* base = nullptr;
+  NutsSet end[2][3];              // [side: 0 = minus, 1 = plus][0 coordinates, 1 momenta, 2 gradient]
+  std::vector<NutsSet> theta, mom;   // pools
+  double* part = nullptr;         // dot partials: (depth + 1) slots x kNutsDotBlocks x 2
+  double* back = nullptr;         // device: Psi, K0, K1, then 2 per dot slot
+  double* host = nullptr;         // pinned copy of `back`
+  size_t back_count = 0;
+};
+
+static size_t nuts_set_bytes(const hamlet_plan* pl) {
+  return align256(16 * pl->modes_count()) + align256(8 * (size_t)std::max(pl->n_gal, 1)) + 256;
+}
+
+static NutsSet nuts_set_at(char* p, const hamlet_plan* pl) {
+  NutsSet s;
+  s.modes = (double2*)p;
+  p += align256(16 * pl->modes_count());
+  s.dist = (double*)p;
+  p += align256(8 * (size_t)std::max(pl->n_gal, 1));
+  s.small = (double*)p;
+  return s;
+}
+
+static void nuts_free(hamlet_plan* pl) {
+  if (!pl->nuts) return;
+  if (pl->nuts->base) (void)hipFree(pl->nuts->base);
+  if (pl->nuts->host) (void)hipHostFree(pl->nuts->host);
+  delete pl->nuts;
+  pl->nuts = nullptr;
+}
+
 extern "C" hamlet_status hamlet_plan_destroy(hamlet_plan* pl) {
   if (!pl) return HAMLET_OK;
   hipError_t e1 = hipStreamSynchronize(pl->stream);
+  nuts_free(pl);
   for (auto& ev : pl->prof_pool) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
@@ -1064,6 +1145,562 @@ extern "C" hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_pla
     }
     if ((st = streams_release(plans, g, gstream[gi])) != HAMLET_OK) return st;
   }
+  return HAMLET_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The No-U-Turn sampler (Section 3.3: Hoffman & Gelman's efficient NUTS with
+// slice variable and dual averaging)
+//
+// The host builds each chain's tree in the order of the recursive algorithm
+// (a stack of completed first halves per height replaces the recursion); the
+// device does every leapfrog step (the fused passes, one step per tick, in
+// shared launches across chains), the kinetic energies and the dot products
+// of the no-U-turn tests.  The trajectory's two ends are advanced in place;
+// a leaf that the tree still needs later (a subtree's first leaf, a
+// candidate sample) is written out by the first pass of the next step from
+// that end, which reads it anyway.  Every decision takes its uniform from the
+// counter-based stream: direction of doubling j, merge of a subtree's halves,
+// move to a new subtree's sample, slice variable.
+// ---------------------------------------------------------------------------
+constexpr double kNutsDeltaMax = 1000.0;
+constexpr int kNutsMaxDepth = 12;
+
+static double host_uniform(uint64_t seed, int iteration, uint32_t purpose, uint64_t index) {
+  const Philox4 w = draw_words(seed, (uint32_t)iteration, purpose, index);
+  return uniform53(w.v[0], w.v[1]);
+}
+
+static hamlet_status nuts_alloc(hamlet_plan* pl, int depth) {
+  if (pl->nuts && pl->nuts->depth >= depth) return HAMLET_OK;
+  HIP_TRY(hipStreamSynchronize(pl->stream));
+  nuts_free(pl);
+  std::unique_ptr<NutsMem> m(new NutsMem());
+  m->depth = depth;
+  m->set_bytes = nuts_set_bytes(pl);
+  const int n_theta = 2 * depth + 4, n_mom = depth + 2;
+  const size_t sets = 6 + (size_t)n_theta + (size_t)n_mom;
+  const size_t part_bytes = align256(8 * 2 * (size_t)kNutsDotBlocks * (depth + 1));
+  m->back_count = 3 + 2 * (size_t)(depth + 1);
+  const size_t total = sets * m->set_bytes + part_bytes + align256(8 * m->back_count);
+  if (hipMalloc((void**)&m->base, total) != hipSuccess) return fail(HAMLET_ENOMEM, "NUTS buffers: %zu bytes", total);
+  if (hipHostMalloc((void**)&m->host, 8 * m->back_count, hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(m->base);
+    return fail(HAMLET_ENOMEM, "NUTS read-back buffer");
+  }
+  char* p = m->base;
+  for (int side = 0; side < 2; ++side)
+    for (int k = 0; k < 3; ++k, p += m->set_bytes) m->end[side][k] = nuts_set_at(p, pl);
+  for (int k = 0; k < n_theta; ++k, p += m->set_bytes) m->theta.push_back(nuts_set_at(p, pl));
+  for (int k = 0; k < n_mom; ++k, p += m->set_bytes) m->mom.push_back(nuts_set_at(p, pl));
+  m->part = (double*)p;
+  p += part_bytes;
+  m->back = (double*)p;
+  if (hipMemsetAsync(m->base, 0, sets * m->set_bytes, pl->stream) != hipSuccess) {
+    (void)hipFree(m->base);
+    (void)hipHostFree(m->host);
+    return fail(HAMLET_EDEVICE, "NUTS buffers: clear failed");
+  }
+  pl->nuts = m.release();
+  return HAMLET_OK;
+}
+
+// A reference to a kept state: the chain's own state (the start of the
+// iteration), the current state of one end, or a pool set.
+enum NRefKind : int8_t { kRefNone = 0, kRefStart = 1, kRefEnd = 2, kRefPool = 3 };
+struct NRef {
+  int8_t kind = kRefNone;
+  int idx = 0;
+};
+
+// A completed subtree: its sample, counts, subtree test, acceptance sums and
+// where its sample's leaf sits (doubling, position).
+struct NutsNode {
+  NRef cand;
+  int n = 0, s = 1, n_alpha = 0, wj = -1, wt = 0;
+  double alpha = 0.0;
+};
+
+struct NutsChain {
+  hamlet_plan* pl = nullptr;
+  double2* q = nullptr;           // the chain's state (caller's buffers)
+  double* qd = nullptr;
+  double* qs = nullptr;
+  double2* msum = nullptr;
+  int32_t *o_depth = nullptr, *o_leaves = nullptr, *o_where = nullptr;
+  double* o_alpha = nullptr;
+  uint64_t seed = 0;
+  int n_iter = 0, warmup = 0, max_depth = 10;
+  // dual averaging (Hoffman & Gelman) of the step
+  double eps = 0.0, target = 0.65, da_mu = 0.0, da_hbar = 0.0, da_leb = 0.0, da_m = 0.0;
+  // the iteration
+  int it = 0, phase = 0;          // phase 0: start of an iteration, 1: building the tree
+  double h0 = 0.0, ln_u = 0.0;
+  int n_top = 1, j = 0, v = 1, t = 0, leaves = 0, n_alpha = 0;
+  double alpha = 0.0;
+  NRef sample;
+  int swj = -1, swt = 0;
+  NutsNode stack[kNutsMaxDepth];            // completed first halves, by height
+  NRef first_q[kNutsMaxDepth + 1], first_p[kNutsMaxDepth + 1];   // first leaf of the node being built, by height
+  std::vector<int> rc_theta, rc_mom;        // reference counts of the pool sets
+  bool done() const { return it >= n_iter; }
+};
+
+static void nref_release(NutsChain& c, NRef& r, bool mom) {
+  if (r.kind == kRefPool) --(mom ? c.rc_mom : c.rc_theta)[r.idx];
+  r = NRef{};
+}
+
+static void nref_copy(NutsChain& c, NRef& dst, const NRef& src, bool mom) {
+  nref_release(c, dst, mom);
+  dst = src;
+  if (dst.kind == kRefPool) ++(mom ? c.rc_mom : c.rc_theta)[dst.idx];
+}
+
+static int nuts_pool_take(std::vector<int>& rc) {
+  for (size_t k = 0; k < rc.size(); ++k)
+    if (rc[k] == 0) return (int)k;
+  return -1;
+}
+
+// Every reference to the current state of end `side` is moved to a pool set
+// (into which the next step from that end writes the state); returns the
+// pool sets (-1: none needed) for the coordinates and the momenta.
+static hamlet_status nuts_keep_end(NutsChain& c, int side, int* theta, int* mom) {
+  *theta = *mom = -1;
+  auto move = [&](NRef& r, bool is_mom, int* slot) -> hamlet_status {
+    if (r.kind != kRefEnd || r.idx != side) return HAMLET_OK;
+    std::vector<int>& rc = is_mom ? c.rc_mom : c.rc_theta;
+    if (*slot < 0) {
+      *slot = nuts_pool_take(rc);
+      if (*slot < 0) return fail(HAMLET_EDEVICE, "NUTS %s pool exhausted", is_mom ? "momentum" : "state");
+    }
+    r.kind = kRefPool;
+    r.idx = *slot;
+    ++rc[*slot];
+    return HAMLET_OK;
+  };
+  hamlet_status st = move(c.sample, false, theta);
+  for (int h = 0; h < kNutsMaxDepth && st == HAMLET_OK; ++h) st = move(c.stack[h].cand, false, theta);
+  for (int h = 0; h <= kNutsMaxDepth && st == HAMLET_OK; ++h) {
+    st = move(c.first_q[h], false, theta);
+    if (st == HAMLET_OK) st = move(c.first_p[h], true, mom);
+  }
+  return st;
+}
+
+static void nuts_clear_doubling(NutsChain& c) {
+  for (int h = 0; h < kNutsMaxDepth; ++h) {
+    nref_release(c, c.stack[h].cand, false);
+    c.stack[h] = NutsNode{};
+  }
+  for (int h = 0; h <= kNutsMaxDepth; ++h) {
+    nref_release(c, c.first_q[h], false);
+    nref_release(c, c.first_p[h], true);
+  }
+}
+
+static void nuts_new_doubling(NutsChain& c) {
+  nuts_clear_doubling(c);
+  c.v = host_uniform(c.seed, c.it, kPurposeNutsDir, (uint64_t)c.j) <= 0.5 ? -1 : 1;
+  c.t = 0;
+}
+
+static hamlet_status copy_async(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes == 0 || dst == src) return HAMLET_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+  return HAMLET_OK;
+}
+
+// Copies the coordinates (modes, distances, s) of one state to another.
+static hamlet_status copy_state(const hamlet_plan* pl, double2* dq, double* dd, double* ds, const double2* sq,
+                                const double* sd, const double* ss, hipStream_t st) {
+  hamlet_status r = copy_async(dq, sq, 16 * pl->modes_count(), st);
+  if (r == HAMLET_OK && pl->n_gal > 0) r = copy_async(dd, sd, 8 * (size_t)pl->n_gal, st);
+  if (r == HAMLET_OK) r = copy_async(ds, ss, 8, st);
+  return r;
+}
+
+static hamlet_status copy_set(const hamlet_plan* pl, const NutsSet& d, const NutsSet& s, hipStream_t st) {
+  return copy_state(pl, d.modes, d.dist, d.small, s.modes, s.dist, s.small, st);
+}
+
+// The coordinates a reference points to.
+static NutsSet nuts_ref_set(const NutsChain& c, const NRef& r) {
+  const NutsMem* m = c.pl->nuts;
+  if (r.kind == kRefEnd) return m->end[r.idx][0];
+  if (r.kind == kRefPool) return m->theta[r.idx];
+  NutsSet s;
+  s.modes = c.q;
+  s.dist = c.pl->n_gal ? c.qd : m->end[0][0].dist;
+  s.small = c.qs;
+  return s;
+}
+
+static hamlet_status nuts_dot(const hamlet_plan* pl, const NutsSet& qa, const NutsSet& qb, const NutsSet& ra,
+                              const NutsSet& rb, int slot, hipStream_t st) {
+  NutsDotArgs a;
+  a.qa = qa.modes; a.qb = qb.modes; a.ra = ra.modes; a.rb = rb.modes;
+  a.da = qa.dist; a.db = qb.dist; a.pda = ra.dist; a.pdb = rb.dist;
+  a.sa = qa.small; a.sb = qb.small; a.psa = ra.small; a.psb = rb.small;
+  a.n_gal = pl->n_gal;
+  a.use_d = pl->sample_d && pl->n_gal > 0;
+  a.use_s = pl->sample_s;
+  a.part = pl->nuts->part + (size_t)slot * 2 * kNutsDotBlocks;
+  a.out = pl->nuts->back + 3 + 2 * slot;
+  switch (pl->n) {
+    case 16: k_nuts_dot<16><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a); break;
+    case 32: k_nuts_dot<32><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a); break;
+    case 64: k_nuts_dot<64><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a); break;
+    case 128: k_nuts_dot<128><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a); break;
+    case 256: k_nuts_dot<256><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a); break;
+    case 512: k_nuts_dot<512><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a); break;
+    default: return fail(HAMLET_EUNSUPPORTED, "grid size %d", pl->n);
+  }
+  k_nuts_dot_final<<<1, 256, 0, st>>>(a.part, kNutsDotBlocks, a.out);
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
+// Enqueues one tick of a group's chains: the start of an iteration (the
+// gradient at the chain's state, both ends set to it, momenta, K0) or one
+// leapfrog step from the end being extended (K1, and the dot products of
+// the no-U-turn tests that end at the new leaf); then the read-back.
+static hamlet_status nuts_enqueue(hipStream_t st, const std::vector<NutsChain*>& chains) {
+  Batch first, eval, start, kin;
+  first.stream = eval.stream = start.stream = kin.stream = st;
+  const Ops* ops = nullptr;
+  hamlet_status r = HAMLET_OK;
+  for (NutsChain* c : chains) {
+    if (c->done()) continue;
+    hamlet_plan* pl = c->pl;
+    NutsMem* m = pl->nuts;
+    ops = pl->ops;
+    StateDev sd{};
+    sd.psi = &pl->cs->psi;
+    sd.eps = pl->eps_slot;
+    if (c->phase == 0) {
+      k_set_chain_iter<<<1, 64, 0, st>>>(pl->cs, c->it);
+      const NutsSet& e = m->end[0][0];
+      if ((r = copy_state(pl, e.modes, e.dist, e.small, c->q, c->qd, c->qs, st)) != HAMLET_OK) return r;
+      sd.q = e.modes; sd.qd = e.dist; sd.qs = e.small;
+      sd.p = m->end[0][1].modes; sd.pd = m->end[0][1].dist; sd.ps = m->end[0][1].small;
+      sd.g = m->end[0][2].modes; sd.gd = m->end[0][2].dist; sd.gs = m->end[0][2].small;
+      pl->st = sd;
+      batch_add(eval, pl, kXGrad);
+      batch_add(start, pl, 0);
+    } else {
+      const int side = c->v < 0 ? 0 : 1;
+      if (c->t == 0) k_set_scalar<<<1, 64, 0, st>>>(pl->eps_slot, (double)c->v * c->eps);
+      int kt = -1, kp = -1;
+      if ((r = nuts_keep_end(*c, side, &kt, &kp)) != HAMLET_OK) return r;
+      const NutsSet *E = m->end[side];
+      sd.q = E[0].modes; sd.qd = E[0].dist; sd.qs = E[0].small;
+      sd.p = E[1].modes; sd.pd = E[1].dist; sd.ps = E[1].small;
+      sd.g = E[2].modes; sd.gd = E[2].dist; sd.gs = E[2].small;
+      if (kt >= 0) {
+        sd.sv_q = m->theta[kt].modes; sd.sv_qd = m->theta[kt].dist; sd.sv_qs = m->theta[kt].small;
+      }
+      if (kp >= 0) {
+        sd.sv_p = m->mom[kp].modes; sd.sv_pd = m->mom[kp].dist; sd.sv_ps = m->mom[kp].small;
+      }
+      pl->st = sd;
+      batch_add(first, pl, kXFirst);
+      batch_add(eval, pl, kXLast);
+      batch_add(kin, pl, 0);
+    }
+  }
+  if (!ops) return HAMLET_OK;
+  if ((r = ops->first(first)) != HAMLET_OK) return r;
+  if ((r = ops->eval(eval)) != HAMLET_OK) return r;
+  // both ends of a new trajectory start at the chain's state, with its gradient
+  for (NutsChain* c : chains) {
+    if (c->done() || c->phase != 0) continue;
+    const NutsMem* m = c->pl->nuts;
+    if ((r = copy_set(c->pl, m->end[1][0], m->end[0][0], st)) != HAMLET_OK) return r;
+    if ((r = copy_set(c->pl, m->end[1][2], m->end[0][2], st)) != HAMLET_OK) return r;
+  }
+  if ((r = ops->nuts_start(start)) != HAMLET_OK) return r;
+  if ((r = ops->kin1(kin)) != HAMLET_OK) return r;
+  for (NutsChain* c : chains) {
+    if (c->done()) continue;
+    hamlet_plan* pl = c->pl;
+    NutsMem* m = pl->nuts;
+    if (c->phase == 0) {
+      if ((r = copy_set(pl, m->end[1][1], m->end[0][1], st)) != HAMLET_OK) return r;
+    } else {
+      const int side = c->v < 0 ? 0 : 1;
+      // the nodes of height h >= 1 that the new leaf completes: their first
+      // leaf (kept in the pools) against the leaf, now the end's state
+      for (int h = 1; h <= c->j && ((c->t + 1) & ((1 << h) - 1)) == 0; ++h) {
+        const NRef& fq = c->first_q[h];
+        const NRef& fp = c->first_p[h];
+        if (fq.kind != kRefPool || fp.kind != kRefPool) return fail(HAMLET_EDEVICE, "NUTS: first leaf not kept");
+        if ((r = nuts_dot(pl, m->theta[fq.idx], m->end[side][0], m->mom[fp.idx], m->end[side][1], h - 1, st)) !=
+            HAMLET_OK)
+          return r;
+      }
+      // the doubling's last leaf: the test over the whole trajectory
+      if (c->t + 1 == (1 << c->j)) {
+        if ((r = nuts_dot(pl, m->end[0][0], m->end[1][0], m->end[0][1], m->end[1][1], m->depth, st)) != HAMLET_OK)
+          return r;
+      }
+    }
+    k_nuts_collect<<<1, 64, 0, st>>>(pl->cs, m->back);
+    HIP_TRY(hipMemcpyAsync(m->host, m->back, 8 * m->back_count, hipMemcpyDeviceToHost, st));
+  }
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
+// End of an iteration: the sample becomes the chain's state (and enters the
+// running sum past warm-up), the outputs are recorded, the step is adapted.
+static hamlet_status nuts_end_iteration(NutsChain& c, hipStream_t st) {
+  hamlet_plan* pl = c.pl;
+  if (c.sample.kind != kRefStart) {
+    const NutsSet s = nuts_ref_set(c, c.sample);
+    hamlet_status r = copy_state(pl, c.q, c.qd, c.qs, s.modes, s.dist, s.small, st);
+    if (r != HAMLET_OK) return r;
+  }
+  if (c.msum && c.it >= c.warmup) {
+    const size_t nm = pl->modes_count();
+    k_add_modes<<<(unsigned)std::min<size_t>(blocks_for(nm, kEltThreads), 4096), kEltThreads, 0, st>>>(c.msum, c.q, nm);
+    LAUNCH_CHECK();
+  }
+  const double stat = c.alpha / (double)c.n_alpha;
+  if (c.o_depth) c.o_depth[c.it] = c.j;
+  if (c.o_leaves) c.o_leaves[c.it] = c.leaves;
+  if (c.o_where) {
+    c.o_where[2 * c.it] = c.swj;
+    c.o_where[2 * c.it + 1] = c.swt;
+  }
+  if (c.o_alpha) c.o_alpha[c.it] = stat;
+  if (c.it < c.warmup) {
+    // Hoffman & Gelman's dual averaging (gamma 0.05, t0 10, kappa 0.75)
+    c.da_m += 1.0;
+    const double m = c.da_m;
+    const double eta = 1.0 / (m + 10.0);
+    c.da_hbar = (1.0 - eta) * c.da_hbar + eta * (c.target - stat);
+    const double log_eps = c.da_mu - std::sqrt(m) / 0.05 * c.da_hbar;
+    const double wgt = std::pow(m, -0.75);
+    c.da_leb = wgt * log_eps + (1.0 - wgt) * c.da_leb;
+    c.eps = c.it == c.warmup - 1 ? std::exp(c.da_leb) : std::exp(log_eps);
+  }
+  nuts_clear_doubling(c);
+  nref_release(c, c.sample, false);
+  ++c.it;
+  c.phase = 0;
+  return HAMLET_OK;
+}
+
+// The read-back of a leaf: slice and divergence tests, the merges of the
+// subtrees it completes (with their no-U-turn tests), and at the end of a
+// doubling the move to its sample and the test over the whole trajectory.
+static hamlet_status nuts_leaf(NutsChain& c, const double* back, hipStream_t st) {
+  const int j = c.j, t = c.t, v = c.v, side = v < 0 ? 0 : 1;
+  double H = back[0] + back[2];
+  if (!std::isfinite(H)) H = HUGE_VAL;
+  ++c.leaves;
+  NutsNode cur;
+  cur.cand.kind = kRefEnd;
+  cur.cand.idx = side;
+  cur.n = c.ln_u <= -H ? 1 : 0;
+  cur.s = c.ln_u < kNutsDeltaMax - H ? 1 : 0;
+  cur.alpha = std::isfinite(H) ? std::min(1.0, std::exp(c.h0 - H)) : 0.0;
+  cur.n_alpha = 1;
+  cur.wj = j;
+  cur.wt = t;
+  // the first leaf of the nodes that start here (heights 1 .. trailing zeros of t)
+  if (j >= 1 && (t & 1) == 0) {
+    int hf = j;
+    if (t != 0) {
+      hf = 0;
+      while (((t >> hf) & 1) == 0) ++hf;
+    }
+    NRef eq, ep;
+    eq.kind = ep.kind = kRefEnd;
+    eq.idx = ep.idx = side;
+    for (int h = 1; h <= hf && h <= j; ++h) {
+      nref_copy(c, c.first_q[h], eq, false);
+      nref_copy(c, c.first_p[h], ep, true);
+    }
+  }
+  int h = 0;
+  bool pushed = false, failed = cur.s == 0;
+  while (!failed && h < j) {
+    const int k = t >> h;
+    if ((k & 1) == 0) {             // a first half: it waits for its sibling
+      c.stack[h] = cur;
+      pushed = true;
+      break;
+    }
+    NutsNode left = c.stack[h];
+    c.stack[h] = NutsNode{};
+    const double u = host_uniform(c.seed, c.it, kPurposeNutsMerge,
+                                  ((uint64_t)(j * 16 + h + 1) << 32) | (uint64_t)(k >> 1));
+    const bool right = cur.n > 0 && u * (double)(left.n + cur.n) <= (double)cur.n;
+    NutsNode mg = left;
+    if (right) {
+      nref_release(c, mg.cand, false);
+      mg.cand = cur.cand;
+      mg.wj = cur.wj;
+      mg.wt = cur.wt;
+    } else {
+      nref_release(c, cur.cand, false);
+    }
+    mg.n = left.n + cur.n;
+    mg.alpha = left.alpha + cur.alpha;
+    mg.n_alpha = left.n_alpha + cur.n_alpha;
+    const double* d = back + 3 + 2 * h;
+    const int ok = ((double)v * d[0] >= 0.0 && (double)v * d[1] >= 0.0) ? 1 : 0;
+    mg.s = cur.s * ok;
+    nref_release(c, c.first_q[h + 1], false);
+    nref_release(c, c.first_p[h + 1], true);
+    cur = mg;
+    ++h;
+    failed = cur.s == 0;
+  }
+  if (pushed) {
+    ++c.t;
+    return HAMLET_OK;
+  }
+  if (failed) {
+    // the recursion returns from here: a second half adds its sums to its
+    // first half's, a first half returns alone
+    for (; h < j; ++h) {
+      if (((t >> h) & 1) != 0) {
+        cur.alpha = c.stack[h].alpha + cur.alpha;
+        cur.n_alpha = c.stack[h].n_alpha + cur.n_alpha;
+      }
+    }
+  }
+  // the doubling is done: move to its sample with probability min(1, n'/n)
+  if (!failed && cur.n > 0 &&
+      host_uniform(c.seed, c.it, kPurposeNutsTop, (uint64_t)j) * (double)c.n_top <= (double)cur.n) {
+    nref_release(c, c.sample, false);
+    c.sample = cur.cand;
+    cur.cand = NRef{};
+    c.swj = cur.wj;
+    c.swt = cur.wt;
+  }
+  nref_release(c, cur.cand, false);
+  c.n_top += cur.n;
+  c.alpha += cur.alpha;
+  c.n_alpha += cur.n_alpha;
+  int s_top = 0;
+  if (!failed) {
+    const double* d = back + 3 + 2 * c.pl->nuts->depth;
+    s_top = (d[0] >= 0.0 && d[1] >= 0.0) ? 1 : 0;
+  }
+  ++c.j;
+  if (s_top && c.j < c.max_depth) {
+    nuts_new_doubling(c);
+    return HAMLET_OK;
+  }
+  return nuts_end_iteration(c, st);
+}
+
+static hamlet_status nuts_finish(hipStream_t st, const std::vector<NutsChain*>& chains) {
+  HIP_TRY(hipStreamSynchronize(st));
+  for (NutsChain* c : chains) {
+    if (c->done()) continue;
+    const double* back = c->pl->nuts->host;
+    if (c->phase == 0) {
+      // H0 = Psi + K(r0); slice variable ln u = ln U - H0
+      c->h0 = back[0] + back[1];
+      c->ln_u = std::log(host_uniform(c->seed, c->it, kPurposeAccept, 0)) - c->h0;
+      c->n_top = 1;
+      c->j = 0;
+      c->leaves = 0;
+      c->alpha = 0.0;
+      c->n_alpha = 0;
+      c->sample = NRef{};
+      c->sample.kind = kRefStart;
+      c->swj = -1;
+      c->swt = 0;
+      c->phase = 1;
+      nuts_new_doubling(*c);
+    } else {
+      hamlet_status r = nuts_leaf(*c, back, st);
+      if (r != HAMLET_OK) return r;
+    }
+  }
+  return HAMLET_OK;
+}
+
+extern "C" hamlet_status hamlet_nuts_run(hamlet_plan* const* plans, int32_t n_plans, const hamlet_nuts_opts* o,
+                                         void* const* q_modes, double* const* q_dist, double* const* q_snl,
+                                         void* const* mode_sum, int32_t* const* depth, int32_t* const* n_leapfrog,
+                                         int32_t* const* leaf, double* const* accept_stat, double* eps_out) {
+  hamlet_status st = check_plans(plans, n_plans);
+  if (st != HAMLET_OK) return st;
+  if (!o) return fail(HAMLET_EINVAL, "opts is NULL");
+  if (o->n_iter < 0 || o->warmup < 0) return fail(HAMLET_EINVAL, "n_iter/warmup out of range");
+  if (o->max_depth < 1 || o->max_depth > kNutsMaxDepth)
+    return fail(HAMLET_EINVAL, "max_depth %d outside [1, %d]", (int)o->max_depth, kNutsMaxDepth);
+  if (!(o->eps0 > 0) || !std::isfinite(o->eps0)) return fail(HAMLET_EINVAL, "eps0 must be positive");
+  if (!(o->target_accept > 0 && o->target_accept < 1)) return fail(HAMLET_EINVAL, "target_accept must be in (0,1)");
+  if (!q_modes || !q_snl) return fail(HAMLET_EINVAL, "NULL argument array");
+  for (int j = 0; j < n_plans; ++j) {
+    hamlet_plan* pl = plans[j];
+    if (!q_modes[j] || !q_snl[j]) return fail(HAMLET_EINVAL, "plan %d: NULL buffer", j);
+    if (pl->n_gal > 0 && (!q_dist || !q_dist[j])) return fail(HAMLET_EINVAL, "plan %d: NULL distance buffer", j);
+  }
+  for (int j = 0; j < n_plans; ++j)
+    if ((st = nuts_alloc(plans[j], o->max_depth)) != HAMLET_OK) return st;
+  const std::vector<std::vector<int>> groups = group_plans(plans, n_plans);
+  const std::vector<hipStream_t> gstream = group_streams(plans, groups);
+  std::vector<NutsChain> chains(n_plans);
+  std::vector<std::vector<NutsChain*>> gch(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    if ((st = streams_join(plans, groups[gi], gstream[gi])) != HAMLET_OK) return st;
+    for (int j : groups[gi]) {
+      hamlet_plan* pl = plans[j];
+      NutsChain& c = chains[j];
+      c.pl = pl;
+      c.q = (double2*)q_modes[j];
+      c.qd = pl->n_gal ? q_dist[j] : nullptr;
+      c.qs = q_snl[j];
+      c.msum = mode_sum ? (double2*)mode_sum[j] : nullptr;
+      c.o_depth = depth ? depth[j] : nullptr;
+      c.o_leaves = n_leapfrog ? n_leapfrog[j] : nullptr;
+      c.o_where = leaf ? leaf[j] : nullptr;
+      c.o_alpha = accept_stat ? accept_stat[j] : nullptr;
+      c.seed = o->seeds ? o->seeds[j] : o->seed + (uint64_t)j;
+      c.n_iter = o->n_iter;
+      c.warmup = o->warmup;
+      c.max_depth = o->max_depth;
+      c.eps = o->eps0;
+      c.target = o->target_accept;
+      c.da_mu = std::log(10.0 * o->eps0);
+      c.rc_theta.assign(pl->nuts->theta.size(), 0);
+      c.rc_mom.assign(pl->nuts->mom.size(), 0);
+      // the chain scalars carry the key for the device's momentum draws
+      k_chain_init<<<1, 1, 0, gstream[gi]>>>(pl->cs, o->eps0, o->target_accept, c.seed, 0, 0);
+      LAUNCH_CHECK();
+      pl->chain_ready = false;
+      gch[gi].push_back(&c);
+    }
+  }
+  for (;;) {
+    bool any = false;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      bool act = false;
+      for (NutsChain* c : gch[gi]) act = act || !c->done();
+      if (!act) continue;
+      any = true;
+      if ((st = nuts_enqueue(gstream[gi], gch[gi])) != HAMLET_OK) return st;
+    }
+    if (!any) break;
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+      if ((st = nuts_finish(gstream[gi], gch[gi])) != HAMLET_OK) return st;
+  }
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    HIP_TRY(hipStreamSynchronize(gstream[gi]));
+    if ((st = streams_release(plans, groups[gi], gstream[gi])) != HAMLET_OK) return st;
+  }
+  if (eps_out)
+    for (int j = 0; j < n_plans; ++j) eps_out[j] = chains[j].eps;
   return HAMLET_OK;
 }
 

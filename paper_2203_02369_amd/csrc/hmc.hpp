@@ -81,7 +81,7 @@ template <typename T, int N> __device__ __forceinline__ double* kin_small(const 
 template <typename T, int N>
 __device__ __forceinline__ void kinetic_small_part(const Pick<T, N>& k, CSum acc, double* red) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && k.w.pc().sample_s) {
-    const double ps = k.w.ps()[0];
+    const double ps = k.st.ps[0];
     acc.add(0.5 * ps * ps);
   }
   const double s = block_csum(acc, red);
@@ -102,13 +102,13 @@ __global__ void __launch_bounds__(kEltThreads) k_momenta_small(Launch L) {
   CSum acc;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k.n_gal; i += gridDim.x * blockDim.x) {
     const double pv = pc.sample_d ? pc.psd * normal_pair(draw_words(seed, iteration, kPurposeDist, i)).x : 0.0;
-    k.w.pd()[i] = pv;
+    k.st.pd[i] = pv;
     k.w.qd0()[i] = k.st.qd[i];
     k.w.gd0()[i] = k.w.gd()[i];
     acc.add(0.5 * pc.minv_d * pv * pv);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    k.w.ps()[0] = pc.sample_s ? normal_pair(draw_words(seed, iteration, kPurposeSnl, 0)).x : 0.0;
+    k.st.ps[0] = pc.sample_s ? normal_pair(draw_words(seed, iteration, kPurposeSnl, 0)).x : 0.0;
     k.w.qs0()[0] = k.st.qs[0];
   }
   kinetic_small_part(k, acc, red);
@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(kEltThreads) k_kinetic_small(Launch L) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
   const double minv = k.w.pc().minv_d;
-  const double* __restrict__ pd = k.w.pd();
+  const double* __restrict__ pd = k.st.pd;
   CSum acc;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k.n_gal; i += gridDim.x * blockDim.x)
     acc.add(0.5 * minv * pd[i] * pd[i]);
@@ -157,6 +157,8 @@ __global__ void __launch_bounds__(kEltThreads) k_small_kick_drift(Launch L) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const double e = st.eps[0];
   if (i < k.n_gal) {
+    if (st.sv_qd) st.sv_qd[i] = st.qd[i];
+    if (st.sv_pd) st.sv_pd[i] = st.pd[i];
     if (pc.sample_d) {
       const double pv = st.pd[i] - 0.5 * e * st.gd[i];
       st.pd[i] = pv;
@@ -164,10 +166,14 @@ __global__ void __launch_bounds__(kEltThreads) k_small_kick_drift(Launch L) {
     }
     bin_point(i, st.qd[i], catalogue(k.w, k.n_gal), cosmo(k.w), N, bin_out(k.w));
   }
-  if (i == 0 && pc.sample_s) {
-    const double pv = st.ps[0] - 0.5 * e * st.gs[0];
-    st.ps[0] = pv;
-    st.qs[0] += e * pv;
+  if (i == 0) {
+    if (st.sv_qs) st.sv_qs[0] = st.qs[0];
+    if (st.sv_ps) st.sv_ps[0] = st.ps[0];
+    if (pc.sample_s) {
+      const double pv = st.ps[0] - 0.5 * e * st.gs[0];
+      st.ps[0] = pv;
+      st.qs[0] += e * pv;
+    }
   }
 }
 

@@ -1002,6 +1002,8 @@ struct ChainSave {
   double* kin_part;
   uint64_t seed;
   uint32_t iteration;
+  double2* sv_q;   // first step outside a chain: keep the start point's modes here (or nullptr)
+  double2* sv_p;   // and its momenta
 };
 
 // ---------------------------------------------------------------------------
@@ -1113,6 +1115,11 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
         }
       } else {
         p = ld_stream(&mom[g]);
+      }
+      if constexpr (MODE == kXFirst && !CHAIN) {
+        // the state this step starts from, kept where the caller asks
+        if (save.sv_q) st_stream(&save.sv_q[g], q);
+        if (save.sv_p) st_stream(&save.sv_p[g], p);
       }
       // per stored mode (w / 8) sigma^2 |p|^2, w = 1 on kz = 0 (both
       // Hermitian partners stored), else 2
@@ -1250,7 +1257,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
                                                                                     double plane_scale) {
   const Pick<T, N> k(L);
   if (k.mode != MODE) return;
-  ChainSave save{k.w.q0(), k.w.g0(), k.w.kin_part(), 0, 0};
+  ChainSave save{k.w.q0(), k.w.g0(), k.w.kin_part(), 0, 0, k.st.sv_q, k.st.sv_p};
   if constexpr (CHAIN) {
     const ChainScalars* cs = k.w.chain();
     save.seed = cs->seed;

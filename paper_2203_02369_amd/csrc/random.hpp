@@ -14,7 +14,7 @@ namespace hamlet {
 // ---------------------------------------------------------------------------
 struct Philox4 { uint32_t v[4]; };
 
-__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+__host__ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                  uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
@@ -28,15 +28,21 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
   Philox4 o; o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3; return o;
 }
 
-enum Purpose : uint32_t { kPurposeModes = 0, kPurposeDist = 1, kPurposeSnl = 2, kPurposeAccept = 3, kPurposeJitter = 4 };
+// Purposes of the draws.  The No-U-Turn sampler's: the direction of doubling
+// j (index j), the merge of a subtree's halves (index ((j * 16 + height) <<
+// 32) | position), the move to a new subtree's sample (index j).
+enum Purpose : uint32_t {
+  kPurposeModes = 0, kPurposeDist = 1, kPurposeSnl = 2, kPurposeAccept = 3, kPurposeJitter = 4,
+  kPurposeNutsDir = 5, kPurposeNutsMerge = 6, kPurposeNutsTop = 7
+};
 
-__device__ __forceinline__ Philox4 draw_words(uint64_t seed, uint32_t iteration, uint32_t purpose, uint64_t index) {
+__host__ __device__ __forceinline__ Philox4 draw_words(uint64_t seed, uint32_t iteration, uint32_t purpose, uint64_t index) {
   return philox4x32_10((uint32_t)index, (uint32_t)(index >> 32), iteration, purpose,
                        (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
 // ((x >> 11) + 1) 2^-53 in (0, 1], x = (hi << 32) | lo.
-__device__ __forceinline__ double uniform53(uint32_t lo, uint32_t hi) {
+__host__ __device__ __forceinline__ double uniform53(uint32_t lo, uint32_t hi) {
   const uint64_t x = ((uint64_t)hi << 32) | lo;
   return ((double)(x >> 11) + 1.0) * 0x1.0p-53;
 }

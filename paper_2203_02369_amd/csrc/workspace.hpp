@@ -57,6 +57,15 @@ struct StateDev {
   int32_t* acc;            // accept flag per chain iteration (or nullptr)
   double2* msum;           // running sum of post-warm-up mode samples (or nullptr)
   double* psi_out;         // Psi of a leapfrog end point
+  // Where the first step of a leapfrog call keeps the state it starts from
+  // (coordinates and momenta, before its kick and drift), or nullptr: the
+  // No-U-Turn sampler keeps the leaves its tree still needs this way.
+  double2* sv_q;
+  double2* sv_p;
+  double* sv_qd;
+  double* sv_pd;
+  double* sv_qs;
+  double* sv_ps;
 };
 
 struct Launch {

@@ -363,6 +363,49 @@ def hmc_run(plans, q_modes, q_dist, q_snl, *, n_iter, n_leapfrog, eps0, seed, wa
     return list(eps_out) if want_eps else None
 
 
+def nuts_run(plans, q_modes, q_dist, q_snl, *, n_iter, eps0, seed, warmup=0, max_depth=10, target_accept=0.65,
+             mode_sum=None, seeds=None):
+    """Runs the No-U-Turn chains (hamlet_nuts_run); the state tensors are
+    updated in place.  Returns, per plan, a dict of numpy arrays over the
+    iterations: depth (doublings), leaves (leapfrog steps), where (n_iter, 2:
+    doubling and position of the leaf moved to, (-1, 0) if none), alpha (the
+    acceptance statistic), and eps, the step after warm-up."""
+    plans, hp = _plans(plans)
+    nplan = len(plans)
+    n_iter = int(n_iter)
+    qm = [_check(t, p, "modes", "q_modes") for t, p in zip(q_modes, plans)]
+    qd = [_check(t, p, "dist", "q_dist") for t, p in zip(q_dist, plans)]
+    qs = [_check(t, p, "scalar", "q_snl") for t, p in zip(q_snl, plans)]
+    ms = [_check(t, p, "modes", "mode_sum") for t, p in zip(mode_sum, plans)] if mode_sum else None
+    opts = _capi.NutsOpts(n_iter=n_iter, warmup=int(warmup), max_depth=int(max_depth), reserved=0, eps0=float(eps0),
+                          target_accept=float(target_accept), seed=int(seed) & 0xFFFFFFFFFFFFFFFF)
+    if seeds is not None:
+        if len(seeds) != nplan:
+            raise ValueError("seeds needs one key per plan")
+        keys = (ctypes.c_uint64 * nplan)(*[int(k) & 0xFFFFFFFFFFFFFFFF for k in seeds])
+        opts.seeds = ctypes.cast(keys, ctypes.POINTER(ctypes.c_uint64))
+    outs = [dict(depth=np.zeros(max(n_iter, 1), dtype=np.int32), leaves=np.zeros(max(n_iter, 1), dtype=np.int32),
+                 where=np.zeros((max(n_iter, 1), 2), dtype=np.int32), alpha=np.zeros(max(n_iter, 1)))
+            for _ in plans]
+
+    def host_ptrs(key, ctype):
+        arr = (ctypes.POINTER(ctype) * nplan)()
+        for i, o in enumerate(outs):
+            arr[i] = o[key].ctypes.data_as(ctypes.POINTER(ctype))
+        return arr
+    eps_out = (ctypes.c_double * nplan)()
+    _capi.check(_capi.load().hamlet_nuts_run(hp, nplan, ctypes.byref(opts), _vp(qm), _dpp(qd), _dpp(qs),
+                                             _vp(ms) if ms else None, host_ptrs("depth", ctypes.c_int32),
+                                             host_ptrs("leaves", ctypes.c_int32), host_ptrs("where", ctypes.c_int32),
+                                             host_ptrs("alpha", ctypes.c_double),
+                                             ctypes.cast(eps_out, c_double_p)))
+    for i, o in enumerate(outs):
+        for k in ("depth", "leaves", "where", "alpha"):
+            o[k] = o[k][:n_iter]
+        o["eps"] = eps_out[i]
+    return outs
+
+
 # -- serving ---------------------------------------------------------------------
 
 SERVER_STATES = {-1: "failed", 0: "queued", 1: "running", 2: "finished"}

@@ -15,7 +15,8 @@ import torch
 from oracle import hmc, model
 from paper_2203_02369_amd import mocks
 
-from helpers import check_adapted_chain, from_lib_layout, oracle_problem, rel_inf, start_modes, to_lib_layout
+from helpers import (check_adapted_chain, from_lib_layout, oracle_problem, path_length, rel_inf, start_modes,
+                     to_lib_layout)
 
 pytestmark = pytest.mark.gpu
 
@@ -447,7 +448,9 @@ def test_hmc_dual_averaging_matches_oracle_fp64(hl):
     prob = oracle_problem(m)
     q0 = hmc.State(start_modes(m), m.d_true.copy(), 1.3)
     n_iter, n_lf, eps, seed, warm = 16, 6, 0.05, 77, 12
-    res = hmc.hmc_run(prob, q0, n_iter, n_lf, eps, seed, warmup=warm)
+    path = [q0.modes]
+    res = hmc.hmc_run(prob, q0, n_iter, n_lf, eps, seed, warmup=warm,
+                      callback=lambda it, q, dh, acc, e: path.append(q.modes.copy()))
     say("hmc dual averaging fp64")
     plan = hl.Plan.from_mock(m, precision="fp64")
     dev = plan.device
@@ -461,7 +464,7 @@ def test_hmc_dual_averaging_matches_oracle_fp64(hl):
     torch.cuda.synchronize()
     assert np.array_equal(acc.cpu().numpy(), res.accepted)
     check_adapted_chain(res, warm, eps_out[0], dh.cpu().numpy(), {"modes": (from_lib_layout(tq.cpu().numpy()),
-                                                                           res.state.modes, q0.modes)},
+                                                                           res.state.modes, path_length(path))},
                         abs(model.logpost(prob, q0.modes, q0.dist, q0.s)))
     plan.close()
 

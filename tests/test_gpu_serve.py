@@ -16,7 +16,8 @@ import torch
 from oracle import hmc, model
 from paper_2203_02369_amd import _capi, mocks
 
-from helpers import check_adapted_chain, from_lib_layout, oracle_problem, rel_inf, start_modes, to_lib_layout
+from helpers import (check_adapted_chain, from_lib_layout, oracle_problem, path_length, rel_inf, start_modes,
+                     to_lib_layout)
 
 pytestmark = pytest.mark.gpu
 
@@ -108,19 +109,21 @@ def test_served_job_matches_oracle_chain(hl):
     sv.close()
     prob = oracle_problem(m)
     q0 = hmc.State(from_lib_layout(start[0]), start[1].copy(), start[2])
+    path = []
     res = hmc.hmc_run(prob, q0, chain["n_iter"], chain["n_leapfrog"], chain["eps0"], 2203,
-                      warmup=chain["warmup"], jitter=True)
+                      warmup=chain["warmup"], jitter=True, callback=lambda it, q, dh, acc, e: path.append(q.copy()))
+    path = [q0] + path
     say("accept oracle", res.accepted.tolist(), "served", got["accepted"].tolist())
     assert np.array_equal(got["accepted"], res.accepted)
     assert 0 < res.accepted.sum()
     h_scale = abs(model.logpost(prob, q0.modes, q0.dist, q0.s))
     # the tolerances of a chain with an adapted step (see the parity tests)
-    n_post = chain["n_iter"] - chain["warmup"]
     check_adapted_chain(res, chain["warmup"], got["eps"], got["dh"], {
-        "modes": (from_lib_layout(got["q_modes"]), res.state.modes, q0.modes),
-        "dist": (got["q_dist"], res.state.dist, q0.dist),
-        "s": (np.array([got["q_snl"]]), np.array([res.state.s]), np.array([q0.s])),
-        "mode_sum": (from_lib_layout(got["mode_sum"]), res.mode_sum, n_post * q0.modes)}, h_scale)
+        "modes": (from_lib_layout(got["q_modes"]), res.state.modes, path_length([x.modes for x in path])),
+        "dist": (got["q_dist"], res.state.dist, path_length([x.dist for x in path])),
+        "s": (np.array([got["q_snl"]]), np.array([res.state.s]), path_length([np.array([x.s]) for x in path])),
+        "mode_sum": (from_lib_layout(got["mode_sum"]), res.mode_sum, path_length([x.modes for x in path]))},
+        h_scale)
 
 
 def test_job_alone_equals_job_in_a_mix(hl):
