@@ -88,6 +88,8 @@ def parse():
                     help="oracle processes of the all-cores CPU leg (0: the usable cores, at most 16)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--nuts-iters", type=int, default=4, help="No-U-Turn iterations timed on the same chain (0: none)")
+    ap.add_argument("--nuts-depth", type=int, default=6, help="most doublings per No-U-Turn iteration")
     ap.add_argument("--served-jobs", type=int, default=16, help="paper workload: requests of the short served stream")
     ap.add_argument("--workload", choices=("paper", "batched", "served"), default="paper")
     ap.add_argument("--jobs", type=int, default=64, help="served: number of requests")
@@ -397,6 +399,28 @@ def main():
     log("passes: " + ", ".join("%s %.4f ms" % (k, v["avg_launch_ms"]) for k, v in passes.items()
                                if isinstance(v, dict)))
 
+    # ---- the No-U-Turn sampler on the same chain (trees of at most 2^6 - 1 steps) ----
+    nuts = None
+    if args.nuts_iters > 0:
+        q2, qd2, qs2 = (t.clone() for t in start)
+        hamlet.nuts_run([plan], [q2], [qd2], [qs2], n_iter=1, eps0=eps, seed=seed + 5, max_depth=2)
+        q2, qd2, qs2 = (t.clone() for t in start)
+        torch.cuda.synchronize()
+        tn = time.perf_counter()
+        res = hamlet.nuts_run([plan], [q2], [qd2], [qs2], n_iter=args.nuts_iters, eps0=eps, seed=seed + 5,
+                              max_depth=args.nuts_depth)[0]
+        torch.cuda.synchronize()
+        dtn = time.perf_counter() - tn
+        leaves = int(res["leaves"].sum())
+        nuts = {"value": round(leaves / dtn, 2), "unit": "grad evals/s", "iterations": args.nuts_iters,
+                "max_depth": args.nuts_depth, "eps": round(eps, 8), "mean_depth": float(res["depth"].mean()),
+                "leapfrog_steps": leaves, "mean_accept_stat": round(float(res["alpha"].mean()), 4),
+                "moved": int((res["where"][:, 0] >= 0).sum()),
+                "vs_hmc_grad_evals": round(leaves / dtn / value, 3)}
+        log("nuts: %d iterations, %d leapfrog steps in %.3fs: %.1f grad/s, mean depth %.1f"
+            % (args.nuts_iters, leaves, dtn, leaves / dtn, res["depth"].mean()))
+        del q2, qd2, qs2
+
     # ---- analysis of a state ----------------------------------------------------
     analysis = run_analysis(hamlet, plan, q, mock, c_bytes)
     plan.close()
@@ -499,6 +523,7 @@ def main():
                    "adaptation_iterations": adapt,
                    "acceptance": float(acc32.mean()), "grad_evals_timed": grads},
         "fp64_path": fp64,
+        "nuts": nuts,
         "served": served,
         "oracle_err": oracle_err,
         "roofline": roofline,

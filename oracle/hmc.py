@@ -28,6 +28,7 @@ import numpy as np
 from . import philox
 from .model import (H0, exact_sum, logpost_grad, mode_indices, mode_variance, pair_weight,
                     retained_mask)
+from .model import mode_dof as model_mode_dof
 
 
 # ----------------------------------------------------------------------------
@@ -83,18 +84,22 @@ def unpack_modes(n, vec):
     return symmetrise(n, out.reshape(n, n, n // 2 + 1))
 
 
-def pack_state(n, modes, dist, s):
+def pack_state(n, modes, dist, s, cosmo=None):
     """The whole flat parameter vector of Section 3.1 (eq:q): Re and Im of
-    the independent modes, then the n distances, then s = sigma_NL/100."""
-    return np.concatenate([pack_modes(n, modes), np.asarray(dist, dtype=float), [float(s)]])
+    the independent modes, then the n distances, then s = sigma_NL/100 (and
+    u8, phi when the cosmological parameters are sampled)."""
+    tail = [float(s)] + ([] if cosmo is None else [float(c) for c in cosmo])
+    return np.concatenate([pack_modes(n, modes), np.asarray(dist, dtype=float), tail])
 
 
-def unpack_state(n, vec, n_gal):
-    """Inverse of pack_state: (modes with mirror entries filled, dist, s)."""
+def unpack_state(n, vec, n_gal, cosmo=False):
+    """Inverse of pack_state: (modes with mirror entries filled, dist, s[,
+    (u8, phi)])."""
     m2 = (n - 1) ** 3 - 1
     vec = np.asarray(vec, dtype=float)
-    assert vec.size == m2 + n_gal + 1
-    return unpack_modes(n, vec[:m2]), vec[m2:m2 + n_gal].copy(), float(vec[m2 + n_gal])
+    assert vec.size == m2 + n_gal + (3 if cosmo else 1)
+    out = (unpack_modes(n, vec[:m2]), vec[m2:m2 + n_gal].copy(), float(vec[m2 + n_gal]))
+    return out + (vec[m2 + n_gal + 1:].copy(),) if cosmo else out
 
 
 # ----------------------------------------------------------------------------
@@ -106,9 +111,11 @@ class State:
     modes: np.ndarray     # complex (N, N, N/2+1)
     dist: np.ndarray      # (n,)
     s: float              # sigma_NL / 100 km/s
+    cosmo: np.ndarray = None   # (u8, phi) when the cosmological parameters are sampled
 
     def copy(self):
-        return State(self.modes.copy(), self.dist.copy(), float(self.s))
+        return State(self.modes.copy(), self.dist.copy(), float(self.s),
+                     None if self.cosmo is None else np.array(self.cosmo, dtype=float))
 
 
 def inverse_mass(prob):
@@ -118,6 +125,16 @@ def inverse_mass(prob):
     minv_d = (prob.sigma_v / H0) ** 2 if prob.sample_distances else 0.0
     minv_s = 1.0 if prob.sample_sigma_nl else 0.0
     return minv_modes, minv_d, minv_s
+
+
+def cosmo_inverse_mass(prob):
+    """M^-1 of (u8, phi) (a reading; eq:M_ab has no such coordinates): the
+    inverse curvature of the prior in u8 at the fiducial amplitude, 1 / (2 D)
+    with D real mode coordinates, and 1 / n for phi (each point carries
+    information of order one on the amplitude of its velocity)."""
+    if not prob.sample_cosmology:
+        return np.zeros(2)
+    return np.array([1.0 / (2.0 * model_mode_dof(prob.n_grid)), 1.0 / max(prob.n_gal, 1)])
 
 
 def draw_momenta(prob, seed, iteration):
@@ -149,7 +166,11 @@ def draw_momenta(prob, seed, iteration):
         ps = float(zs[0])
     else:
         ps = 0.0
-    return State(pm, pd, ps)
+    pc = None
+    if prob.sample_cosmology:
+        z0, z1 = philox.normal_pair(philox.draw_words(seed, iteration, philox.PURPOSE_COSMO, [0]))
+        pc = np.array([float(z0[0]), float(z1[0])]) / np.sqrt(cosmo_inverse_mass(prob))
+    return State(pm, pd, ps, pc)
 
 
 def kinetic(prob, p):
@@ -162,11 +183,16 @@ def kinetic(prob, p):
     _, minv_d, minv_s = inverse_mass(prob)
     terms = [(w * var * np.abs(p.modes) ** 2 / 8.0).ravel(), 0.5 * minv_d * np.asarray(p.dist) ** 2,
              [0.5 * minv_s * p.s * p.s]]
+    if prob.sample_cosmology:
+        terms.append(0.5 * cosmo_inverse_mass(prob) * np.asarray(p.cosmo) ** 2)
     return exact_sum(np.concatenate(terms))
 
 
 def gradient(prob, q):
-    return logpost_grad(prob, q.modes, q.dist, q.s)
+    """(Psi, dPsi/dmodes, dPsi/dd, dPsi/ds, dPsi/d(u8, phi) or None) at q."""
+    if prob.sample_cosmology:
+        return logpost_grad(prob, q.modes, q.dist, q.s, cosmo=q.cosmo)
+    return logpost_grad(prob, q.modes, q.dist, q.s) + (None,)
 
 
 def leapfrog(prob, q, p, eps, n_steps, cached=None):
@@ -179,20 +205,27 @@ def leapfrog(prob, q, p, eps, n_steps, cached=None):
     p = p.copy()
     if cached is None:
         cached = gradient(prob, q)
-    psi, gm, gd, gs = cached
+    psi, gm, gd, gs, gc = cached
     minv_m, minv_d, minv_s = inverse_mass(prob)
+    minv_c = cosmo_inverse_mass(prob)
     for _ in range(n_steps):
         p.modes = p.modes - 0.5 * eps * gm
         p.dist = p.dist - 0.5 * eps * gd if prob.sample_distances else p.dist
         p.s = p.s - 0.5 * eps * gs if prob.sample_sigma_nl else p.s
+        if prob.sample_cosmology:
+            p.cosmo = p.cosmo - 0.5 * eps * gc
         q.modes = q.modes + eps * minv_m * p.modes
         q.dist = q.dist + eps * minv_d * p.dist
         q.s = q.s + eps * minv_s * p.s
-        psi, gm, gd, gs = gradient(prob, q)
+        if prob.sample_cosmology:
+            q.cosmo = q.cosmo + eps * minv_c * p.cosmo
+        psi, gm, gd, gs, gc = gradient(prob, q)
         p.modes = p.modes - 0.5 * eps * gm
         p.dist = p.dist - 0.5 * eps * gd if prob.sample_distances else p.dist
         p.s = p.s - 0.5 * eps * gs if prob.sample_sigma_nl else p.s
-    return q, p, (psi, gm, gd, gs)
+        if prob.sample_cosmology:
+            p.cosmo = p.cosmo - 0.5 * eps * gc
+    return q, p, (psi, gm, gd, gs, gc)
 
 
 # ----------------------------------------------------------------------------

@@ -40,6 +40,14 @@ Readings of the paper used here (each is also listed in the design notes):
     terms rounded once (math.fsum): the Metropolis test takes the difference
     of two such totals of millions of terms, and an exactly rounded sum is
     the plain definition, free of any summation order.
+  * Cosmological parameters in q (Section 6, item 3: sigma_8 and the growth
+    rate estimated with the field).  With `sample_cosmology` two more
+    coordinates join s: u8 = sigma_8 / sigma_8,fid, which scales P(k) by
+    u8^2, and phi = f / f_fid, which scales the velocity multiplier.  Both
+    have flat priors on (0, inf) (Psi = +inf elsewhere).  The prior of the
+    modes is then the normalised Gaussian of variance u8^2 sigma_k^2, whose
+    u8-dependent part is E / u8^2 + D ln u8 with E the fiducial prior
+    energy and D = (N-1)^3 - 1 the number of real mode coordinates.
 """
 import math
 from dataclasses import dataclass, field
@@ -173,6 +181,7 @@ class Problem:
     hist_width: float = 5.0
     sample_distances: bool = True
     sample_sigma_nl: bool = True
+    sample_cosmology: bool = False
     hist: DistanceHistogram = field(default=None)
 
     def __post_init__(self):
@@ -255,8 +264,14 @@ def hermitian_partner_index(n):
     return (neg[:, None] * n + neg[None, :]) * nh
 
 
-def velocity_multiplier(prob):
-    """m_c(k) = i a H0 f k_c / k^2 on the half spectrum (eq:vel-field), a = 1.
+def mode_dof(n):
+    """Real coordinates of the retained modes: (N-1)^3 - 1."""
+    return (n - 1) ** 3 - 1
+
+
+def velocity_multiplier(prob, phi=1.0):
+    """m_c(k) = i a H0 f k_c / k^2 on the half spectrum (eq:vel-field), a = 1,
+    with f = phi f_fid.
 
     Returns complex array (3, N, N, N/2+1); zero on excluded modes.
     """
@@ -267,7 +282,7 @@ def velocity_multiplier(prob):
     k2 = kvec[0] ** 2 + kvec[1] ** 2 + kvec[2] ** 2
     keep = retained_mask(n)
     safe = np.where(keep, k2, 1.0)
-    amp = H0 * prob.f_growth
+    amp = H0 * prob.f_growth * phi
     return np.stack([np.where(keep, 1j * amp * kc / safe, 0.0) for kc in kvec])
 
 
@@ -275,10 +290,10 @@ def velocity_multiplier(prob):
 # The velocity field and its interpolation (eq:vel-field, eqn:lvr)
 # ----------------------------------------------------------------------------
 
-def velocity_grids(prob, dhat):
+def velocity_grids(prob, dhat, phi=1.0):
     """v_c(x_j) = N^-3 sum_k m_c(k) dhat_k exp(+i k.x_j) for c = x, y, z."""
     n = prob.n_grid
-    mult = velocity_multiplier(prob)
+    mult = velocity_multiplier(prob, phi)
     out = np.empty((3, n, n, n))
     for c in range(3):
         field_c = ifftn_unnormalised(full_spectrum(mult[c] * dhat)) / float(n) ** 3
@@ -358,13 +373,13 @@ def cic_scatter(prob, d, g):
     return out
 
 
-def project_gather(prob, dhat, d):
+def project_gather(prob, dhat, d, phi=1.0):
     """The linear map from modes to u_i = rhat_i . v(d_i rhat_i) at fixed d."""
-    u, _ = cic_gather(prob, velocity_grids(prob, dhat), np.asarray(d, dtype=np.float64))
+    u, _ = cic_gather(prob, velocity_grids(prob, dhat, phi), np.asarray(d, dtype=np.float64))
     return u
 
 
-def modes_adjoint(prob, d, g):
+def modes_adjoint(prob, d, g, phi=1.0):
     """Gradient of sum_i g_i u_i with respect to the modes (at fixed d).
 
     (2/N^3) sum_c conj(m_c(k)) Ghat_c(k), Ghat_c the forward transform of the
@@ -372,7 +387,7 @@ def modes_adjoint(prob, d, g):
     """
     n = prob.n_grid
     grids = cic_scatter(prob, np.asarray(d, dtype=np.float64), np.asarray(g, dtype=np.float64))
-    mult = velocity_multiplier(prob)
+    mult = velocity_multiplier(prob, phi)
     nh = n // 2 + 1
     out = np.zeros(half_shape(n), dtype=np.complex128)
     for c in range(3):
@@ -381,7 +396,7 @@ def modes_adjoint(prob, d, g):
     return out
 
 
-def modes_adjoint_at(prob, d, g, kidx):
+def modes_adjoint_at(prob, d, g, kidx, phi=1.0):
     """modes_adjoint at a few half-spectrum entries kidx = (ix, iy, iz) arrays,
     by the definition of the forward transform summed directly over the
     nodes the points reach: Ghat_c(k) = sum_i g_i rhat_ic sum_corners
@@ -393,7 +408,7 @@ def modes_adjoint_at(prob, d, g, kidx):
     ix, iy, iz = (np.asarray(a, dtype=np.int64) for a in kidx)
     x = galaxy_positions(prob, d)
     i0, t = cic_cells(prob, x)
-    mult = velocity_multiplier(prob)
+    mult = velocity_multiplier(prob, phi)
     s = signed_index(n)
     nvec = np.stack([s[ix], s[iy], iz], axis=1).astype(np.float64)     # (m, 3) signed wave numbers
     ghat = np.zeros((3, len(ix)), dtype=np.complex128)
@@ -459,15 +474,26 @@ def exact_sum(terms):
     return math.fsum(np.asarray(terms, dtype=np.float64).ravel().tolist())
 
 
-def prior_energy(prob, dhat):
+def prior_energy(prob, dhat, u8=1.0):
     """-ln P(Delta_k) up to a constant: sum over independent modes |dhat|^2/sigma^2.
 
-    On the half spectrum: (1/2) sum_k w_k |dhat_k|^2 / sigma_k^2.
+    On the half spectrum: (1/2) sum_k w_k |dhat_k|^2 / sigma_k^2, the energy E
+    of the fiducial spectrum.  With P scaled by u8^2 (sigma_8 = u8 sigma_8,fid)
+    the Gaussian's normalisation enters: E / u8^2 + D ln u8, D real mode
+    coordinates (exactly E at u8 = 1).
     """
     var = mode_variance(prob)
     w = pair_weight(prob.n_grid)
     safe = np.where(var > 0, var, 1.0)
-    return exact_sum(0.5 * w * np.abs(dhat) ** 2 / safe)
+    e = exact_sum(0.5 * w * np.abs(dhat) ** 2 / safe)
+    return e / (u8 * u8) + mode_dof(prob.n_grid) * math.log(u8)
+
+
+def _cosmo(prob, cosmo):
+    """(u8, phi) of a state: the fiducial (1, 1) unless the problem samples them."""
+    if not prob.sample_cosmology or cosmo is None:
+        return 1.0, 1.0
+    return float(cosmo[0]), float(cosmo[1])
 
 
 def galaxy_terms(prob, d, s, u):
@@ -483,31 +509,38 @@ def galaxy_terms(prob, d, s, u):
     return dict(zbar=zb, kappa2=kappa2, dmu=dmu, r=r, psi=psi)
 
 
-def logpost(prob, dhat, d, s):
-    """Psi(q) = -ln Pi(q) up to constants (eq:Psi)."""
+def logpost(prob, dhat, d, s, cosmo=None):
+    """Psi(q) = -ln Pi(q) up to constants (eq:Psi); cosmo = (u8, phi) when the
+    problem samples the cosmological parameters."""
     d = np.asarray(d, dtype=np.float64)
-    if not np.all(in_domain(prob, d)):
+    u8, phi = _cosmo(prob, cosmo)
+    if not np.all(in_domain(prob, d)) or not (u8 > 0.0 and phi > 0.0):
         return math.inf
-    v = velocity_grids(prob, dhat)
+    v = velocity_grids(prob, dhat, phi)
     u, _ = cic_gather(prob, v, d)
     terms = galaxy_terms(prob, d, s, u)
-    total = exact_sum(np.concatenate([[prior_energy(prob, dhat)], terms["psi"]]))
+    total = exact_sum(np.concatenate([[prior_energy(prob, dhat, u8)], terms["psi"]]))
     return total if np.isfinite(total) else math.inf
 
 
-def logpost_grad(prob, dhat, d, s):
+def logpost_grad(prob, dhat, d, s, cosmo=None):
     """Psi(q) and its analytic gradient.
 
     Returns (psi, g_modes, g_d, g_s) where g_modes is on the half spectrum in
     the complex convention G_k = dPsi/dRe dhat_k + i dPsi/dIm dhat_k, taken
     with respect to the independent coordinates of each mode (on the kz = 0
-    plane the stored partner carries the conjugate).
+    plane the stored partner carries the conjugate).  When the problem
+    samples the cosmological parameters, cosmo = (u8, phi) and a fifth entry
+    (dPsi/du8, dPsi/dphi) follows:
+        dPsi/du8 = -2 E / u8^3 + D / u8      (the prior; E at u8 = 1)
+        dPsi/dphi = sum_i g_i u_i / phi      (u_i is linear in phi)
     """
     n = prob.n_grid
     d = np.asarray(d, dtype=np.float64)
     ok = in_domain(prob, d)
     dsafe = np.where(ok, d, 1.0)
-    v = velocity_grids(prob, dhat)
+    u8, phi = _cosmo(prob, cosmo)
+    v = velocity_grids(prob, dhat, phi)
     u, du = cic_gather(prob, v, dsafe)
     t = galaxy_terms(prob, dsafe, s, u)
     om = prob.omega_m
@@ -526,9 +559,15 @@ def logpost_grad(prob, dhat, d, s):
     # gather through the inverse transform: (2/N^3) sum_c conj(m_c) FFT(G_c).
     var = mode_variance(prob)
     safe = np.where(var > 0, var, 1.0)
-    g_modes = np.where(var > 0, 2.0 * dhat / safe, 0.0).astype(np.complex128)
-    g_modes += modes_adjoint(prob, dsafe, g)
-    psi = exact_sum(np.concatenate([[prior_energy(prob, dhat)], t["psi"]])) if np.all(ok) else math.inf
-    if not (np.all(ok) and np.isfinite(psi)):
+    g_modes = np.where(var > 0, 2.0 * dhat / (u8 * u8 * safe), 0.0).astype(np.complex128)
+    g_modes += modes_adjoint(prob, dsafe, g, phi)
+    good = np.all(ok) and u8 > 0.0 and phi > 0.0
+    psi = exact_sum(np.concatenate([[prior_energy(prob, dhat, u8)], t["psi"]])) if good else math.inf
+    if not (good and np.isfinite(psi)):
         psi = math.inf
-    return psi, g_modes, g_d, g_s
+    if cosmo is None or not prob.sample_cosmology:
+        return psi, g_modes, g_d, g_s
+    e = prior_energy(prob, dhat)
+    g_u8 = -2.0 * e / u8 ** 3 + mode_dof(n) / u8
+    g_phi = exact_sum(g * u) / phi
+    return psi, g_modes, g_d, g_s, np.array([g_u8, g_phi])

@@ -91,6 +91,8 @@ class PosteriorTarget:
             terms.append((q_plus.dist - q_minus.dist) * p.dist)
         if self.prob.sample_sigma_nl:
             terms.append([(q_plus.s - q_minus.s) * p.s])
+        if self.prob.sample_cosmology:
+            terms.append((np.asarray(q_plus.cosmo) - np.asarray(q_minus.cosmo)) * np.asarray(p.cosmo))
         return exact_sum(np.concatenate(terms))
 
 
