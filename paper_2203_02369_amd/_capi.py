@@ -36,6 +36,7 @@ class PlanDesc(ctypes.Structure):
         ("hist_width", ctypes.c_double),
         ("sample_distances", ctypes.c_int32),
         ("sample_sigma_nl", ctypes.c_int32),
+        ("sample_cosmology", ctypes.c_int32),
     ]
 
 

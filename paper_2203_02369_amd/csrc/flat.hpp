@@ -1,5 +1,5 @@
 // The paper's flat parameter vector (Section 3.1): Re of the independent
-// modes, Im of them, the distances, s.
+// modes, Im of them, the distances, s (and u8, phi when sampled).
 //
 // Independent modes are the retained stored entries with kz > 0 and, on the
 // kz = 0 plane, the canonical member of each Hermitian pair (ny > 0, or
@@ -39,10 +39,11 @@ __device__ __forceinline__ int64_t flat_rank(int n, int x, int y, int kz) {
   return rows * (h - 1) + canon_before + within;
 }
 
-// flat <- (modes, dist, s).  Grid over max(stored entries, n + 1).
+// flat <- (modes, dist, the ns small coordinates).  Grid over max(stored
+// entries, n + ns).
 __global__ void __launch_bounds__(256)
 k_pack_flat(const double2* __restrict__ modes, const double* __restrict__ dist, const double* __restrict__ snl,
-            double* __restrict__ flat, int n, int n_gal) {
+            double* __restrict__ flat, int n, int n_gal, int ns) {
   const int h = n / 2;
   const size_t total = (size_t)n * n * h;
   const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -58,13 +59,14 @@ k_pack_flat(const double2* __restrict__ modes, const double* __restrict__ dist, 
     }
   }
   if (g < (size_t)n_gal) flat[2 * m + g] = dist[g];
-  if (g == 0) flat[2 * m + n_gal] = snl[0];
+  if (g < (size_t)ns) flat[2 * m + n_gal + g] = snl[g];
 }
 
-// (modes, dist, s) <- flat.  Grid over max(stored entries, n + 1).
+// (modes, dist, the ns small coordinates) <- flat.  Grid over max(stored
+// entries, n + ns).
 __global__ void __launch_bounds__(256)
 k_unpack_flat(const double* __restrict__ flat, double2* __restrict__ modes, double* __restrict__ dist,
-              double* __restrict__ snl, int n, int n_gal) {
+              double* __restrict__ snl, int n, int n_gal, int ns) {
   const int h = n / 2;
   const size_t total = (size_t)n * n * h;
   const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -86,7 +88,7 @@ k_unpack_flat(const double* __restrict__ flat, double2* __restrict__ modes, doub
     modes[g] = v;
   }
   if (g < (size_t)n_gal) dist[g] = flat[2 * m + g];
-  if (g == 0) snl[0] = flat[2 * m + n_gal];
+  if (g < (size_t)ns) snl[g] = flat[2 * m + n_gal + g];
 }
 
 }  // namespace hamlet

@@ -232,9 +232,13 @@ struct BinNext {
   int n_grid;
 };
 
+// Values per block of the likelihood's partial sums: Psi, dPsi/ds, invalid
+// distances, a slice of the prior partials, sum g_i u_i (for dPsi/dphi).
+constexpr int kLikeVals = 8;
+
 struct LikeOut {
   double* g_dist;     // dPsi/dd by galaxy id (n)
-  double* part;       // 4 per block: Psi, dPsi/ds, invalid, a slice of the prior partials
+  double* part;       // kLikeVals per block (see above)
   const double* prior_part;   // prior partials of the x pass
   int n_prior;
   int n_blocks;               // this plan's blocks (ceil(n / block size)); block b sums slice b
@@ -245,9 +249,9 @@ __device__ __forceinline__ void
 like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, const double* __restrict__ frac,
           double* __restrict__ dist, const double* snl_q, Catalogue cat, Cosmo cm, T* __restrict__ gsort,
           LikeOut out, LeapUpdate lf, const BinNext* next) {
-  __shared__ double red[2 * 4 * (kGalThreads / 64)];
+  __shared__ double red[2 * 5 * (kGalThreads / 64)];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double psi = 0.0, dps = 0.0, bad = 0.0;
+  double psi = 0.0, dps = 0.0, bad = 0.0, gu = 0.0;
   if (i < cat.n) {
     const int s = bpos[i];
     const double tx = frac[3 * i], ty = frac[3 * i + 1];
@@ -295,6 +299,7 @@ like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, cons
     dps = dk2 * 2.0 * kSigmaNlUnit * kSigmaNlUnit * sv;
     out.g_dist[i] = gd;
     gsort[s] = (T)(-r / kappa2);
+    gu = (-r / kappa2) * u;   // u is linear in the growth rate: dPsi/dphi = sum g u / phi
     if (lf.p) {
       const double e = lf.eps[0];
       const double pv = lf.p[i] - lf.kick * e * gd;
@@ -307,47 +312,83 @@ like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, cons
   // this block's slice of the prior partials
   const int per = (out.n_prior + out.n_blocks - 1) / out.n_blocks;
   const int lo = blockIdx.x * per, hi = min(out.n_prior, lo + per);
-  CSum sums[4];
+  CSum sums[5];
   sums[0].add(psi);
   sums[1].add(dps);
   sums[2].add(bad);
   for (int j = lo + threadIdx.x; j < hi; j += blockDim.x) sums[3].add(out.prior_part[j]);
+  sums[4].add(gu);
   block_csums(sums, red);
   if (threadIdx.x == 0) {
-    out.part[4 * blockIdx.x + 0] = sums[0].value();
-    out.part[4 * blockIdx.x + 1] = sums[1].value();
-    out.part[4 * blockIdx.x + 2] = sums[2].value();
-    out.part[4 * blockIdx.x + 3] = sums[3].value();
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out.part[kLikeVals * blockIdx.x + v] = sums[v].value();
   }
 }
 
+// The small coordinates at the final sums: where they are, their momenta and
+// gradient, and the leapfrog update of them once the gradient is known.
+struct SmallState {
+  double* q;            // s, and u8, phi when sampled
+  double* p;            // momenta, or nullptr: no update
+  double* g;            // dPsi/d(s, u8, phi) out
+  double* cosmo_eval;   // u8 and phi of this evaluation, kept for the adjoint pass
+  const double* eps;
+  double kick;          // 1 for merged half kicks, 0.5 for the last half kick
+  int drift;
+  int sample_s, sample_c;
+  double minv_u8, minv_phi, d_modes;
+};
+
 // Final deterministic sums (compensated): Psi = prior + sum of galaxy terms
 // (+inf when a distance left the domain or Psi is not finite); dPsi/ds.
+// With u8 and phi sampled the prior is E / u8^2 + D ln u8 (E the fiducial
+// prior energy, D real mode coordinates), dPsi/du8 = -2 E / u8^3 + D / u8,
+// dPsi/dphi = sum g_i u_i / phi, and Psi = +inf unless u8, phi > 0.
 __device__ __forceinline__ void
 finalize_body(const double* __restrict__ prior_part, int n_prior, const double* __restrict__ like_part, int n_like,
-              double* __restrict__ psi_out, double* __restrict__ gs_out, double* snl_q, LeapUpdate lf) {
-  __shared__ double red[2 * 3 * 4];   // blocks of up to 256 threads
-  CSum sums[3];
+              double* __restrict__ psi_out, const SmallState& sm) {
+  __shared__ double red[2 * 5 * 4];   // blocks of up to 256 threads
+  CSum sums[5];                       // prior, galaxy terms, dPsi/ds, invalid, sum g u
   for (int i = threadIdx.x; i < n_prior; i += blockDim.x) sums[0].add(prior_part[i]);
   for (int i = threadIdx.x; i < n_like; i += blockDim.x) {
-    sums[0].add(like_part[4 * i]);
-    sums[0].add(like_part[4 * i + 3]);
-    sums[1].add(like_part[4 * i + 1]);
-    sums[2].add(like_part[4 * i + 2]);
+    const double* lp = like_part + (size_t)kLikeVals * i;
+    sums[1].add(lp[0]);
+    sums[0].add(lp[3]);
+    sums[2].add(lp[1]);
+    sums[3].add(lp[2]);
+    sums[4].add(lp[4]);
   }
   block_csums(sums, red);
-  const double a = sums[0].value();
-  const double b = sums[1].value();
-  const double c = sums[2].value();
-  if (threadIdx.x == 0) {
-    const bool ok = c == 0.0 && isfinite(a);
-    psi_out[0] = ok ? a : __builtin_inf();
-    if (gs_out) gs_out[0] = b;
-    if (lf.p) {
-      const double e = lf.eps[0];
-      const double pv = lf.p[0] - lf.kick * e * b;
-      lf.p[0] = pv;
-      if (lf.drift) snl_q[0] = snl_q[0] + e * lf.minv * pv;
+  if (threadIdx.x != 0) return;
+  const double e = sums[0].value();
+  double psi;
+  bool ok = sums[3].value() == 0.0;
+  double g[kSmallMax] = {sums[2].value(), 0.0, 0.0};
+  if (sm.sample_c) {
+    const double u8 = sm.q[1], phi = sm.q[2];
+    ok = ok && u8 > 0.0 && phi > 0.0;
+    psi = e / (u8 * u8) + sm.d_modes * log(u8) + sums[1].value();
+    g[1] = -2.0 * e / (u8 * u8 * u8) + sm.d_modes / u8;
+    g[2] = sums[4].value() / phi;
+    sm.cosmo_eval[0] = u8;
+    sm.cosmo_eval[1] = phi;
+  } else {
+    CSum tot = sums[0];
+    tot.add(sums[1].s, sums[1].c);
+    psi = tot.value();
+  }
+  psi_out[0] = ok && isfinite(psi) ? psi : __builtin_inf();
+  const int ns = sm.sample_c ? kSmallMax : 1;
+  for (int k = 0; k < ns; ++k)
+    if (sm.g) sm.g[k] = g[k];
+  if (sm.p) {
+    const double eps = sm.eps[0];
+    const double minv[kSmallMax] = {1.0, sm.minv_u8, sm.minv_phi};
+    for (int k = 0; k < ns; ++k) {
+      if (k == 0 && !sm.sample_s) continue;
+      const double pv = sm.p[k] - sm.kick * eps * g[k];
+      sm.p[k] = pv;
+      if (sm.drift) sm.q[k] = sm.q[k] + eps * minv[k] * pv;
     }
   }
 }
@@ -463,6 +504,28 @@ __device__ __forceinline__ LeapUpdate leap_update(int x_mode, int sample, double
   return lf;
 }
 
+// The small coordinates of a plan in an evaluation of mode k.mode: kicked
+// (merged half kicks and a drift inside a trajectory, a last half kick at
+// its end) unless it is a plain gradient.
+template <typename T, int N> __device__ __forceinline__ SmallState small_state(const Pick<T, N>& k) {
+  const PlanConst& pc = k.w.pc();
+  SmallState sm;
+  sm.q = k.st.qs;
+  sm.g = k.st.gs;
+  sm.cosmo_eval = k.w.cosmo_eval();
+  sm.eps = k.st.eps;
+  sm.sample_s = pc.sample_s;
+  sm.sample_c = pc.sample_c;
+  sm.minv_u8 = pc.minv_u8;
+  sm.minv_phi = pc.minv_phi;
+  sm.d_modes = pc.d_modes;
+  const bool update = k.mode != kXGrad && (pc.sample_s || pc.sample_c);
+  sm.p = update ? k.st.ps : nullptr;
+  sm.kick = k.mode == kXMid ? 1.0 : 0.5;
+  sm.drift = k.mode == kXMid ? 1 : 0;
+  return sm;
+}
+
 template <typename T, int N>
 __global__ void __launch_bounds__(kGalThreads) k_like(Launch L) {
   const Pick<T, N> k(L);
@@ -489,8 +552,7 @@ __global__ void __launch_bounds__(kGalThreads) k_like(Launch L) {
   __syncthreads();
   if (!last) return;
   __threadfence();
-  finalize_body(k.w.prior_part(), 0, k.w.like_part(), pc.n_like_part, k.st.psi, k.st.gs, k.st.qs,
-                leap_update(k.mode, pc.sample_s, k.st.ps, k.st.eps, 1.0));
+  finalize_body(k.w.prior_part(), 0, k.w.like_part(), pc.n_like_part, k.st.psi, small_state(k));
   if (threadIdx.x == 0) *k.w.ticket() = 0;
 }
 
@@ -501,8 +563,7 @@ __global__ void __launch_bounds__(256) k_finalize(Launch L) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
   const PlanConst& pc = k.w.pc();
-  finalize_body(k.w.prior_part(), pc.n_prior_part, k.w.like_part(), pc.n_like_part, k.st.psi, k.st.gs, k.st.qs,
-                leap_update(k.mode, pc.sample_s, k.st.ps, k.st.eps, 1.0));
+  finalize_body(k.w.prior_part(), pc.n_prior_part, k.w.like_part(), pc.n_like_part, k.st.psi, small_state(k));
 }
 
 }  // namespace hamlet

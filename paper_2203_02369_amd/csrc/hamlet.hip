@@ -88,8 +88,9 @@ struct Ops {
 
 struct hamlet_plan {
   int device = 0;                  // the HIP device the plan was created on
-  int n = 0, prec = 0, n_gal = 0, sample_d = 1, sample_s = 1, n_hist = 0;
+  int n = 0, prec = 0, n_gal = 0, sample_d = 1, sample_s = 1, sample_c = 0, n_hist = 0;
   double box = 0, om = 0, h = 0, f = 0, sigma_v = 0, hist_w = 5.0, minv_d = 0;
+  double minv_u8 = 0, minv_phi = 0;
   hipStream_t stream = nullptr;
   hipEvent_t order_ev = nullptr;   // orders shared launches against this plan's stream
   char* base = nullptr;            // the workspace (one allocation)
@@ -116,6 +117,7 @@ struct hamlet_plan {
   size_t prof_used = 0;
   bool prof_failed = false;
   size_t modes_count() const { return (size_t)n * n * (n / 2); }
+  int n_small() const { return sample_c ? kSmallMax : 1; }   // s, and u8, phi when sampled
 };
 
 // Bracket one launch of kernel kind `kind` with events when it is armed on
@@ -608,6 +610,10 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
   pc.minv_d = pl->minv_d;
   pc.psd = kH0 / pl->sigma_v;
   pc.kfac0 = kH0 * pl->f / ((double)pl->n * pl->n * pl->n * kf);
+  pc.sample_c = pl->sample_c;
+  pc.minv_u8 = pl->minv_u8;
+  pc.minv_phi = pl->minv_phi;
+  pc.d_modes = std::pow((double)(pl->n - 1), 3.0) - 1.0;
   HIP_TRY(hipMemcpyAsync(pl->consts, &pc, sizeof(pc), hipMemcpyHostToDevice, st));
   return HAMLET_OK;
 }
@@ -626,6 +632,12 @@ static void fill_plan_scalars(hamlet_plan* pl, const hamlet_plan_desc* d, int64_
   pl->minv_d = pl->sample_d ? (pl->sigma_v / kH0) * (pl->sigma_v / kH0) : 0.0;
   pl->n_gal = (int)n_gal;
   pl->n_hist = n_hist;
+  // u8 = sigma_8 / sigma_8,fid and phi = f / f_fid: inverse masses 1 / (2 D)
+  // (the prior's curvature in u8 at u8 = 1, D real mode coordinates) and 1 / n
+  pl->sample_c = d->sample_cosmology ? 1 : 0;
+  const double dof = std::pow((double)(pl->n - 1), 3.0) - 1.0;
+  pl->minv_u8 = pl->sample_c ? 1.0 / (2.0 * dof) : 0.0;
+  pl->minv_phi = pl->sample_c ? 1.0 / (double)std::max<int64_t>(n_gal, 1) : 0.0;
 }
 
 // Upper bound of the histogram bin count for the footprint query: the
@@ -1042,7 +1054,7 @@ extern "C" hamlet_status hamlet_leapfrog(hamlet_plan* const* plans, int32_t n_pl
       sd.ps = p_snl[j];
       sd.g = pl->gcache;
       sd.gd = pl->gd;
-      sd.gs = &pl->cs->gs;
+      sd.gs = &pl->cs->gs[0];
       sd.psi = &pl->cs->psi;
       sd.eps = pl->eps_slot;
       sd.psi_out = psi[j];
@@ -1102,7 +1114,7 @@ extern "C" hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_pla
       sd.ps = pl->ps;
       sd.g = pl->gcache;
       sd.gd = pl->gd;
-      sd.gs = &pl->cs->gs;
+      sd.gs = &pl->cs->gs[0];
       sd.psi = &pl->cs->psi;
       sd.eps = &pl->cs->eps_it;
       sd.dh = dh ? dh[j] : nullptr;
@@ -1317,7 +1329,7 @@ static hamlet_status copy_state(const hamlet_plan* pl, double2* dq, double* dd, 
                                 const double* sd, const double* ss, hipStream_t st) {
   hamlet_status r = copy_async(dq, sq, 16 * pl->modes_count(), st);
   if (r == HAMLET_OK && pl->n_gal > 0) r = copy_async(dd, sd, 8 * (size_t)pl->n_gal, st);
-  if (r == HAMLET_OK) r = copy_async(ds, ss, 8, st);
+  if (r == HAMLET_OK) r = copy_async(ds, ss, 8 * (size_t)pl->n_small(), st);
   return r;
 }
 
@@ -1346,6 +1358,7 @@ static hamlet_status nuts_dot(const hamlet_plan* pl, const NutsSet& qa, const Nu
   a.n_gal = pl->n_gal;
   a.use_d = pl->sample_d && pl->n_gal > 0;
   a.use_s = pl->sample_s;
+  a.use_c = pl->sample_c;
   a.part = pl->nuts->part + (size_t)slot * 2 * kNutsDotBlocks;
   a.out = pl->nuts->back + 3 + 2 * slot;
   switch (pl->n) {
@@ -1709,12 +1722,12 @@ extern "C" hamlet_status hamlet_nuts_run(hamlet_plan* const* plans, int32_t n_pl
 // ---------------------------------------------------------------------------
 extern "C" hamlet_status hamlet_flat_size(const hamlet_plan* plan, int64_t* n_flat) {
   if (!plan || !n_flat) return fail(HAMLET_EINVAL, "NULL argument");
-  *n_flat = 2 * flat_modes(plan->n) + plan->n_gal + 1;
+  *n_flat = 2 * flat_modes(plan->n) + plan->n_gal + plan->n_small();
   return HAMLET_OK;
 }
 
 static unsigned flat_blocks(const hamlet_plan* pl) {
-  return blocks_for(std::max(pl->modes_count(), (size_t)pl->n_gal + 1), 256);
+  return blocks_for(std::max(pl->modes_count(), (size_t)pl->n_gal + pl->n_small()), 256);
 }
 
 extern "C" hamlet_status hamlet_pack_flat(hamlet_plan* plan, const void* modes, const double* dist,
@@ -1722,7 +1735,7 @@ extern "C" hamlet_status hamlet_pack_flat(hamlet_plan* plan, const void* modes, 
   if (!plan || !modes || !snl || !flat) return fail(HAMLET_EINVAL, "NULL argument");
   if (plan->n_gal > 0 && !dist) return fail(HAMLET_EINVAL, "NULL distance buffer");
   k_pack_flat<<<flat_blocks(plan), 256, 0, plan->stream>>>((const double2*)modes, dist, snl, flat, plan->n,
-                                                           plan->n_gal);
+                                                           plan->n_gal, plan->n_small());
   LAUNCH_CHECK();
   return HAMLET_OK;
 }
@@ -1732,7 +1745,7 @@ extern "C" hamlet_status hamlet_unpack_flat(hamlet_plan* plan, const double* fla
   if (!plan || !flat || !modes || !snl) return fail(HAMLET_EINVAL, "NULL argument");
   if (plan->n_gal > 0 && !dist) return fail(HAMLET_EINVAL, "NULL distance buffer");
   k_unpack_flat<<<flat_blocks(plan), 256, 0, plan->stream>>>(flat, (double2*)modes, dist, snl, plan->n,
-                                                             plan->n_gal);
+                                                             plan->n_gal, plan->n_small());
   LAUNCH_CHECK();
   return HAMLET_OK;
 }
@@ -2099,7 +2112,7 @@ static hamlet_status job_admit(hamlet_server* sv, Job* j) {
     else
       HIP_TRY(hipMemcpyAsync(j->qd, pl->dz, 8 * (size_t)pl->n_gal, hipMemcpyDeviceToDevice, s));
   }
-  k_set_scalar<<<1, 64, 0, s>>>(j->qs, j->q_snl);
+  k_set_small<<<1, 64, 0, s>>>(j->qs, j->q_snl, pl->n_small());
   k_chain_init<<<1, 1, 0, s>>>(pl->cs, j->opts.eps0, j->opts.target_accept, j->opts.seed, j->opts.warmup,
                                j->opts.jitter_eps);
   LAUNCH_CHECK();
@@ -2112,7 +2125,7 @@ static hamlet_status job_admit(hamlet_server* sv, Job* j) {
   sd.ps = pl->ps;
   sd.g = pl->gcache;
   sd.gd = pl->gd;
-  sd.gs = &pl->cs->gs;
+  sd.gs = &pl->cs->gs[0];
   sd.psi = &pl->cs->psi;
   sd.eps = &pl->cs->eps_it;
   sd.dh = j->dh;

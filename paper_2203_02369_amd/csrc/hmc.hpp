@@ -49,6 +49,13 @@ __global__ void k_set_scalar(double* dst, double v) {
   if (threadIdx.x == 0) dst[0] = v;
 }
 
+// The small coordinates of a start state: s, then u8 = phi = 1 (the
+// fiducial cosmology) when they are sampled.
+__global__ void k_set_small(double* dst, double s, int ns) {
+  if (threadIdx.x == 0) dst[0] = s;
+  if (threadIdx.x > 0 && threadIdx.x < ns) dst[threadIdx.x] = 1.0;
+}
+
 __global__ void k_chain_init(ChainScalars* cs, double eps0, double target, uint64_t seed, int warmup, int jitter) {
   cs->eps = eps0;
   cs->eps_it = eps0;
@@ -80,9 +87,16 @@ template <typename T, int N> __device__ __forceinline__ double* kin_small(const 
 // Distance and s terms of the kinetic energy, one partial per block.
 template <typename T, int N>
 __device__ __forceinline__ void kinetic_small_part(const Pick<T, N>& k, CSum acc, double* red) {
-  if (blockIdx.x == 0 && threadIdx.x == 0 && k.w.pc().sample_s) {
-    const double ps = k.st.ps[0];
-    acc.add(0.5 * ps * ps);
+  const PlanConst& pc = k.w.pc();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (pc.sample_s) {
+      const double ps = k.st.ps[0];
+      acc.add(0.5 * ps * ps);
+    }
+    if (pc.sample_c) {
+      acc.add(0.5 * pc.minv_u8 * k.st.ps[1] * k.st.ps[1]);
+      acc.add(0.5 * pc.minv_phi * k.st.ps[2] * k.st.ps[2]);
+    }
   }
   const double s = block_csum(acc, red);
   if (threadIdx.x == 0) kin_small(k.w)[blockIdx.x] = s;
@@ -110,6 +124,14 @@ __global__ void __launch_bounds__(kEltThreads) k_momenta_small(Launch L) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     k.st.ps[0] = pc.sample_s ? normal_pair(draw_words(seed, iteration, kPurposeSnl, 0)).x : 0.0;
     k.w.qs0()[0] = k.st.qs[0];
+    if (pc.sample_c) {
+      // (u8, phi) from one pair: p ~ N(0, M), M = 1 / minv
+      const double2 z = normal_pair(draw_words(seed, iteration, kPurposeCosmo, 0));
+      k.st.ps[1] = z.x / sqrt(pc.minv_u8);
+      k.st.ps[2] = z.y / sqrt(pc.minv_phi);
+      k.w.qs0()[1] = k.st.qs[1];
+      k.w.qs0()[2] = k.st.qs[2];
+    }
   }
   kinetic_small_part(k, acc, red);
 }
@@ -167,12 +189,17 @@ __global__ void __launch_bounds__(kEltThreads) k_small_kick_drift(Launch L) {
     bin_point(i, st.qd[i], catalogue(k.w, k.n_gal), cosmo(k.w), N, bin_out(k.w));
   }
   if (i == 0) {
-    if (st.sv_qs) st.sv_qs[0] = st.qs[0];
-    if (st.sv_ps) st.sv_ps[0] = st.ps[0];
-    if (pc.sample_s) {
-      const double pv = st.ps[0] - 0.5 * e * st.gs[0];
-      st.ps[0] = pv;
-      st.qs[0] += e * pv;
+    const int ns = pc.sample_c ? kSmallMax : 1;
+    for (int j = 0; j < ns; ++j) {
+      if (st.sv_qs) st.sv_qs[j] = st.qs[j];
+      if (st.sv_ps) st.sv_ps[j] = st.ps[j];
+    }
+    const double minv[kSmallMax] = {1.0, pc.minv_u8, pc.minv_phi};
+    for (int j = 0; j < ns; ++j) {
+      if (j == 0 && !pc.sample_s) continue;
+      const double pv = st.ps[j] - 0.5 * e * st.gs[j];
+      st.ps[j] = pv;
+      st.qs[j] += e * minv[j] * pv;
     }
   }
 }
@@ -191,7 +218,7 @@ __global__ void k_iter_begin(Launch L) {
   }
   cs->eps_it = e;
   cs->psi_saved = cs->psi;
-  cs->gs_saved = cs->gs;
+  for (int j = 0; j < kSmallMax; ++j) cs->gs_saved[j] = cs->gs[j];
   // set by the trajectory; equal (no change of H) when it has no steps
   cs->kin0 = 0.0;
   cs->kin1 = 0.0;
@@ -228,7 +255,7 @@ __global__ void k_accept(Launch L) {
   }
   if (!acc) {
     cs->psi = cs->psi_saved;
-    cs->gs = cs->gs_saved;
+    for (int j = 0; j < kSmallMax; ++j) cs->gs[j] = cs->gs_saved[j];
   }
   cs->iter = it + 1;
 }
@@ -265,7 +292,10 @@ __global__ void __launch_bounds__(kEltThreads) k_restore_accumulate(Launch L) {
       k.st.qd[i] = k.w.qd0()[i];
       k.w.gd()[i] = k.w.gd0()[i];
     }
-    if (i == 0) k.st.qs[0] = k.w.qs0()[0];
+    if (i == 0) {
+      const int ns = k.w.pc().sample_c ? kSmallMax : 1;
+      for (int j = 0; j < ns; ++j) k.st.qs[j] = k.w.qs0()[j];
+    }
   }
 }
 

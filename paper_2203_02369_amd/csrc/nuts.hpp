@@ -58,7 +58,7 @@ struct NutsDotArgs {
   const double2 *qa, *qb, *ra, *rb;
   const double *da, *db, *pda, *pdb;
   const double *sa, *sb, *psa, *psb;
-  int n_gal, use_d, use_s;
+  int n_gal, use_d, use_s, use_c;   // use_c: u8 and phi (small[1], small[2])
   double* part;      // 2 per block
   double* out;       // 2 results
 };
@@ -85,10 +85,12 @@ __global__ void __launch_bounds__(kEltThreads) k_nuts_dot(NutsDotArgs a) {
       acc[1].add(d * a.pdb[i]);
     }
   }
-  if (a.use_s && blockIdx.x == 0 && threadIdx.x == 0) {
-    const double d = a.sb[0] - a.sa[0];
-    acc[0].add(d * a.psa[0]);
-    acc[1].add(d * a.psb[0]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int j = a.use_s ? 0 : 1; j < (a.use_c ? kSmallMax : 1); ++j) {
+      const double d = a.sb[j] - a.sa[j];
+      acc[0].add(d * a.psa[j]);
+      acc[1].add(d * a.psb[j]);
+    }
   }
   block_csums<2>(acc, red);
   if (threadIdx.x == 0) {

@@ -78,7 +78,9 @@ template <typename T, int N> struct PassShape {
 // kfac = H0 f / (N^3 k_f n^2) is computed from n^2.
 struct ModeTables {
   const double* var;       // sigma_k^2 per mode, [ky][kz / W][kx][kz % W]
-  double kfac0;            // H0 f / (N^3 k_f)
+  double kfac0;            // H0 f / (N^3 k_f) of the state now (the inverse pass)
+  double kfac_adj;         // the same at the point whose gradient the adjoint pass takes
+  double inv_a;            // 1 / u8^2 there (the prior of the modes scales with u8^2)
 };
 __device__ __forceinline__ double mode_kfac(double kfac0, int n2) { return n2 > 0 ? kfac0 / (double)n2 : 0.0; }
 __device__ __forceinline__ double inv_or_zero(double v) { return v > 0.0 ? 1.0 / v : 0.0; }
@@ -1081,7 +1083,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
     if constexpr (kFromSpectra) {
       if (keep) {
         const C tv = cadd(acc[e], tile[LAY::idx(x, w)]);
-        const double iv2 = 2.0 * inv_or_zero(var), kf2 = 2.0 * mode_kfac(tab.kfac0, n2);
+        const double iv2 = 2.0 * inv_or_zero(var) * tab.inv_a, kf2 = 2.0 * mode_kfac(tab.kfac_adj, n2);
         // -2 i kfac t = (2 kfac t.y, -2 kfac t.x)
         G = make_double2(iv2 * q.x + kf2 * (double)tv.y, iv2 * q.y - kf2 * (double)tv.x);
       }
@@ -1177,8 +1179,25 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
 // from a, b and, in the leapfrog modes, writes the next A, B over them
 // (every tile reads its own entries before it writes them).
 // ---------------------------------------------------------------------------
+// Tables of the fiducial cosmology (f, sigma_8 as given).
 template <typename T, int N> __device__ __forceinline__ ModeTables tables(const Ws<T, N>& w) {
-  return ModeTables{w.mvar(), w.pc().kfac0};
+  return ModeTables{w.mvar(), w.pc().kfac0, w.pc().kfac0, 1.0};
+}
+
+// Tables of an evaluation: with u8 and phi sampled, the multiplier of the
+// state now (phi has drifted on by the time the x pass of a leapfrog step
+// runs) and, for the adjoint and the prior gradient, u8 and phi where the
+// final sums took the gradient.
+template <typename T, int N> __device__ __forceinline__ ModeTables tables(const Ws<T, N>& w, const StateDev& st) {
+  const PlanConst& pc = w.pc();
+  ModeTables t{w.mvar(), pc.kfac0, pc.kfac0, 1.0};
+  if (pc.sample_c && st.qs) {   // (the field of a state alone, without them, takes the fiducial ones)
+    const double* ce = w.cosmo_eval();
+    t.kfac0 = pc.kfac0 * st.qs[2];
+    t.kfac_adj = pc.kfac0 * ce[1];
+    t.inv_a = 1.0 / (ce[0] * ce[0]);
+  }
+  return t;
 }
 
 template <typename T, int N> __device__ __forceinline__ Binned<T> binned(const Ws<T, N>& w) {
@@ -1195,7 +1214,7 @@ template <typename T, int N, int NT>
 __global__ void __launch_bounds__(NT) k_inv_x(Launch L) {
   const Pick<T, N> k(L);
   if (k.mode != kXGrad) return;
-  inv_x_body<T, N, NT>(k.st.q, tables(k.w), k.w.tw(), k.w.a(), k.w.b(), k.w.prior_part());
+  inv_x_body<T, N, NT>(k.st.q, tables(k.w, k.st), k.w.tw(), k.w.a(), k.w.b(), k.w.prior_part());
 }
 
 template <typename T, int N, int NT>
@@ -1263,7 +1282,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
     save.seed = cs->seed;
     save.iteration = (uint32_t)cs->iter;
   }
-  x_pass_body<T, N, MODE, NT, CHAIN>(k.w.a(), k.w.b(), k.st.q, k.st.p, k.st.g, tables(k.w), k.w.tw(), k.st.eps,
+  x_pass_body<T, N, MODE, NT, CHAIN>(k.w.a(), k.w.b(), k.st.q, k.st.p, k.st.g, tables(k.w, k.st), k.w.tw(), k.st.eps,
                                      k.w.a(), k.w.b(), k.w.prior_part(), plane_scale, save);
 }
 

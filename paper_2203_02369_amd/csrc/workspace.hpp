@@ -26,17 +26,24 @@ constexpr int kMaxBatch = 16;
 // kXSkip.
 enum XMode { kXSkip = -1, kXGrad = 0, kXFirst = 1, kXMid = 2, kXLast = 3 };
 
+// The small coordinates of a state: s = sigma_NL / 100 km/s, and when the
+// plan samples the cosmological parameters u8 = sigma_8 / sigma_8,fid and
+// phi = f / f_fid (kSmallMax values: q_snl, p_snl, g_snl hold 1 or 3).
+constexpr int kSmallMax = 3;
+
 // Per-plan constants, at the start of the workspace.
 struct PlanConst {
   int n_gal, n_hist, sample_d, sample_s;
-  int n_prior_part, n_like_part, n_kin_part, pad;
+  int n_prior_part, n_like_part, n_kin_part, sample_c;   // sample_c: u8 and phi sampled
   double om, h;            // Omega_0, little h (for mu)
   double box, spacing;     // L, L / N
   double dmax;             // c / (3 Omega_0 H0): domain of zbar(d)
   double hist_w;           // bin width of the distance prior, Mpc/h
   double minv_d;           // inverse mass of a distance, (sigma_v / H0)^2
   double psd;              // sqrt of the mass of a distance, H0 / sigma_v
-  double kfac0;            // H0 f / (N^3 k_f), k_f = 2 pi / L
+  double kfac0;            // H0 f / (N^3 k_f), k_f = 2 pi / L (fiducial f)
+  double minv_u8, minv_phi;   // inverse masses of u8 and phi
+  double d_modes;          // real mode coordinates, (N-1)^3 - 1
 };
 
 // What one call works on: the coordinates, their momenta, where the
@@ -114,7 +121,7 @@ template <int N, int R> struct FixedLayout {
   static constexpr size_t cursor = align256(off + 4 * (size_t(N) * N + 1));
   static constexpr size_t prior_part = align256(cursor + 4 * size_t(N) * N);
   static constexpr size_t kin_part = align256(prior_part + 8 * size_t(N_PRIOR));
-  static constexpr size_t small = align256(kin_part + 8 * size_t(N_KIN));   // qs0, ps, eps_slot, most, ticket
+  static constexpr size_t small = align256(kin_part + 8 * size_t(N_KIN));   // qs0, ps, eps_slot, most, ticket, cosmo_eval
   static constexpr size_t mom_part = align256(small + 256);       // sphere-moment partial sums
   static constexpr size_t mvar = align256(mom_part + kMomentsPartBytes);
   static constexpr size_t a = align256(mvar + 8 * NM);
@@ -136,7 +143,7 @@ template <int R> struct GalaxyUnits {
   static constexpr size_t mu = 3, smu = 4, cz = 5, scz = 6;
   static constexpr size_t frac = 7;        // 3 doubles
   static constexpr size_t gd = 10, gd0 = 11, qd0 = 12, pd = 13;
-  static constexpr size_t like_part = 14;  // 3 doubles per block of 256 galaxies
+  static constexpr size_t like_part = 14;  // kLikeVals doubles per block of 256 galaxies
   static constexpr size_t key = 15, cellz = 16, slot = 17, iz = 18;   // ints
   static constexpr size_t rx = 19, ry = 20, rz = 21, tx = 22, ty = 23, tz = 24, gsort = 25;   // reals
   static constexpr size_t bpos = 26;       // binned index of each galaxy
@@ -164,8 +171,10 @@ struct ChainScalars {
   double eps;          // step size of the chain (adapted during warm-up)
   double eps_it;       // step of the current iteration (jittered)
   double da_mu, da_hbar, da_log_eps_bar, da_m;
-  double psi, gs;              // Psi and dPsi/ds at the current state
-  double psi_saved, gs_saved;  // at the start of the trajectory
+  double psi;                  // Psi at the current state
+  double gs[kSmallMax];        // dPsi/d(s, u8, phi) there
+  double psi_saved;            // at the start of the trajectory
+  double gs_saved[kSmallMax];
   double kin0, kin1;
   double target;
   uint64_t seed;
@@ -176,6 +185,7 @@ struct ChainScalars {
   int post;            // last iteration was past warm-up
 };
 static_assert(sizeof(ChainScalars) <= FixedLayout<16, 8>::chain_bytes, "chain scalars block");
+static_assert(sizeof(PlanConst) <= 256, "plan constants block");
 
 // Typed view of a plan's workspace.
 template <typename T, int N> struct Ws {
@@ -196,11 +206,14 @@ template <typename T, int N> struct Ws {
   __host__ __device__ int* cursor() const { return at<int>(F::cursor); }
   __host__ __device__ double* prior_part() const { return at<double>(F::prior_part); }
   __host__ __device__ double* kin_part() const { return at<double>(F::kin_part); }
-  __host__ __device__ double* qs0() const { return at<double>(F::small); }
-  __host__ __device__ double* ps() const { return at<double>(F::small + 8); }
-  __host__ __device__ double* eps_slot() const { return at<double>(F::small + 16); }
-  __host__ __device__ int* most() const { return at<int>(F::small + 24); }   // most points in one column
-  __host__ __device__ int* ticket() const { return at<int>(F::small + 28); } // likelihood blocks done
+  __host__ __device__ double* qs0() const { return at<double>(F::small); }          // kSmallMax
+  __host__ __device__ double* ps() const { return at<double>(F::small + 24); }      // kSmallMax
+  __host__ __device__ double* eps_slot() const { return at<double>(F::small + 48); }
+  __host__ __device__ int* most() const { return at<int>(F::small + 56); }   // most points in one column
+  __host__ __device__ int* ticket() const { return at<int>(F::small + 60); } // likelihood blocks done
+  // u8 and phi where the evaluation's gradient is taken (the adjoint pass
+  // reads them after the small coordinates have drifted on)
+  __host__ __device__ double* cosmo_eval() const { return at<double>(F::small + 64); }
   __host__ __device__ double* mvar() const { return at<double>(F::mvar); }
   __host__ __device__ C* a() const { return at<C>(F::a); }
   __host__ __device__ C* b() const { return at<C>(F::b); }

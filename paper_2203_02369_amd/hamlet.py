@@ -34,7 +34,7 @@ def _stream_handle(stream, device):
 
 
 def _problem(n_grid, box, omega_m, h, f_growth, sigma_v, pk_n2, rhat, mu, sigma_mu, cz, sigma_cz, hist_width,
-             precision, sample_distances, sample_sigma_nl):
+             precision, sample_distances, sample_sigma_nl, sample_cosmology=False):
     """hamlet_plan_desc and hamlet_catalog of a problem, and the arrays they point into."""
     pk = _f64(pk_n2)
     rh = _f64(rhat).reshape(-1)
@@ -46,7 +46,7 @@ def _problem(n_grid, box, omega_m, h, f_growth, sigma_v, pk_n2, rhat, mu, sigma_
                           omega_m=float(omega_m), h=float(h), f_growth=float(f_growth),
                           sigma_v=float(sigma_v), pk_n2=_dptr(pk), n_pk=len(pk),
                           hist_width=float(hist_width), sample_distances=int(bool(sample_distances)),
-                          sample_sigma_nl=int(bool(sample_sigma_nl)))
+                          sample_sigma_nl=int(bool(sample_sigma_nl)), sample_cosmology=int(bool(sample_cosmology)))
     cat = _capi.Catalog(n=n, rhat=_dptr(rh), mu=_dptr(arrays[0]), sigma_mu=_dptr(arrays[1]),
                         cz=_dptr(arrays[2]), sigma_cz=_dptr(arrays[3]))
     return desc, cat, n, (pk, rh, arrays)
@@ -57,14 +57,15 @@ class Plan:
 
     def __init__(self, *, n_grid, box, omega_m, h, f_growth, sigma_v, pk_n2, rhat, mu, sigma_mu, cz, sigma_cz,
                  hist_width=5.0, precision="fp32", sample_distances=True, sample_sigma_nl=True,
-                 stream=None, device=None):
+                 sample_cosmology=False, stream=None, device=None):
         lib = _capi.load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.n_grid = int(n_grid)
         self.precision = precision
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         desc, cat, n, _keep = _problem(n_grid, box, omega_m, h, f_growth, sigma_v, pk_n2, rhat, mu, sigma_mu, cz,
-                                       sigma_cz, hist_width, precision, sample_distances, sample_sigma_nl)
+                                       sigma_cz, hist_width, precision, sample_distances, sample_sigma_nl,
+                                       sample_cosmology)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _capi.check(lib.hamlet_plan_create(ctypes.byref(desc), ctypes.byref(cat),
@@ -72,6 +73,8 @@ class Plan:
         self._handle = handle
         self.n_gal = n
         self.mode_shape = (self.n_grid, self.n_grid, self.n_grid // 2)
+        # small coordinates: s, and u8 = sigma_8 / sigma_8,fid, phi = f / f_fid when sampled
+        self.n_small = 3 if sample_cosmology else 1
 
     @classmethod
     def from_mock(cls, mock, **kw):
@@ -106,6 +109,12 @@ class Plan:
     def scalar(self, value=0.0):
         return torch.full((1,), float(value), dtype=torch.float64, device=self.device)
 
+    def small(self, s=0.0, u8=1.0, phi=1.0):
+        """The small coordinates of a state (or momenta, gradient): (s,) or
+        (s, u8, phi) when the plan samples the cosmological parameters."""
+        vals = [s, u8, phi][: self.n_small]
+        return torch.tensor(vals, dtype=torch.float64, device=self.device)
+
 
 def footprint_bytes(n_grid, n_gal, precision="fp32", pk_len=None):
     """Device bytes a plan of this size would own (hamlet_plan_footprint_bytes)."""
@@ -138,6 +147,9 @@ def _check(t, plan, kind, name):
     elif kind == "scalar":
         if t.dtype != torch.float64 or t.numel() < 1:
             raise ValueError("%s must be float64 (1,)" % name)
+    elif kind == "small":
+        if t.dtype != torch.float64 or t.numel() < plan.n_small:
+            raise ValueError("%s must be float64 (%d,)" % (name, plan.n_small))
     elif kind == "iter_f64":
         if t.dtype != torch.float64:
             raise ValueError("%s must be float64" % name)
@@ -175,8 +187,8 @@ def logpost_grad(plans, q_modes, q_dist, q_snl, g_modes, g_dist, g_snl, psi, per
     hamlet_logpost_grad_entries with per_entry=True)."""
     plans, hp = _plans(plans)
     args = []
-    for kind, name, ts in (("modes", "q_modes", q_modes), ("dist", "q_dist", q_dist), ("scalar", "q_snl", q_snl),
-                           ("modes", "g_modes", g_modes), ("dist", "g_dist", g_dist), ("scalar", "g_snl", g_snl),
+    for kind, name, ts in (("modes", "q_modes", q_modes), ("dist", "q_dist", q_dist), ("small", "q_snl", q_snl),
+                           ("modes", "g_modes", g_modes), ("dist", "g_dist", g_dist), ("small", "g_snl", g_snl),
                            ("scalar", "psi", psi)):
         args.append([_check(t, p, kind, name) for t, p in zip(ts, plans)])
     lib = _capi.load()
@@ -203,7 +215,7 @@ def pack_flat(plan, modes, dist, snl, flat=None):
         flat = torch.empty(flat_size(plan), dtype=torch.float64, device=plan.device)
     elif flat.dtype != torch.float64 or flat.numel() != flat_size(plan) or not flat.is_contiguous():
         raise ValueError("flat must be contiguous float64 (%d,)" % flat_size(plan))
-    m, d, s = _check(modes, plan, "modes", "modes"), _check(dist, plan, "dist", "dist"), _check(snl, plan, "scalar", "snl")
+    m, d, s = _check(modes, plan, "modes", "modes"), _check(dist, plan, "dist", "dist"), _check(snl, plan, "small", "snl")
     _capi.check(_capi.load().hamlet_pack_flat(plan.handle, ctypes.c_void_p(m), _ptr(d), _ptr(s),
                                               _ptr(_check(flat, plan, "iter_f64", "flat"))))
     return flat
@@ -214,7 +226,7 @@ def unpack_flat(plan, flat, modes, dist, snl):
     distances, s) of a flat vector, on the plan's stream (hamlet_unpack_flat)."""
     if flat.dtype != torch.float64 or flat.numel() != flat_size(plan) or not flat.is_contiguous():
         raise ValueError("flat must be contiguous float64 (%d,)" % flat_size(plan))
-    m, d, s = _check(modes, plan, "modes", "modes"), _check(dist, plan, "dist", "dist"), _check(snl, plan, "scalar", "snl")
+    m, d, s = _check(modes, plan, "modes", "modes"), _check(dist, plan, "dist", "dist"), _check(snl, plan, "small", "snl")
     _capi.check(_capi.load().hamlet_unpack_flat(plan.handle, _ptr(_check(flat, plan, "iter_f64", "flat")),
                                                 ctypes.c_void_p(m), _ptr(d), _ptr(s)))
 
@@ -315,8 +327,8 @@ def leapfrog(plans, eps, n_steps, q_modes, q_dist, q_snl, p_modes, p_dist, p_snl
     """n_steps kick-drift-kick steps in place (hamlet_leapfrog)."""
     plans, hp = _plans(plans)
     args = []
-    for kind, name, ts in (("modes", "q_modes", q_modes), ("dist", "q_dist", q_dist), ("scalar", "q_snl", q_snl),
-                           ("modes", "p_modes", p_modes), ("dist", "p_dist", p_dist), ("scalar", "p_snl", p_snl),
+    for kind, name, ts in (("modes", "q_modes", q_modes), ("dist", "q_dist", q_dist), ("small", "q_snl", q_snl),
+                           ("modes", "p_modes", p_modes), ("dist", "p_dist", p_dist), ("small", "p_snl", p_snl),
                            ("scalar", "psi", psi)):
         args.append([_check(t, p, kind, name) for t, p in zip(ts, plans)])
     e = (ctypes.c_double * len(plans))(*[float(x) for x in eps])
@@ -337,7 +349,7 @@ def hmc_run(plans, q_modes, q_dist, q_snl, *, n_iter, n_leapfrog, eps0, seed, wa
     nplan = len(plans)
     qm = [_check(t, p, "modes", "q_modes") for t, p in zip(q_modes, plans)]
     qd = [_check(t, p, "dist", "q_dist") for t, p in zip(q_dist, plans)]
-    qs = [_check(t, p, "scalar", "q_snl") for t, p in zip(q_snl, plans)]
+    qs = [_check(t, p, "small", "q_snl") for t, p in zip(q_snl, plans)]
     ms = [_check(t, p, "modes", "mode_sum") for t, p in zip(mode_sum, plans)] if mode_sum else None
     dd = [_check(t, p, "iter_f64", "dh") for t, p in zip(dh, plans)] if dh else None
     aa = [_check(t, p, "iter_i32", "accepted") for t, p in zip(accepted, plans)] if accepted else None
@@ -375,7 +387,7 @@ def nuts_run(plans, q_modes, q_dist, q_snl, *, n_iter, eps0, seed, warmup=0, max
     n_iter = int(n_iter)
     qm = [_check(t, p, "modes", "q_modes") for t, p in zip(q_modes, plans)]
     qd = [_check(t, p, "dist", "q_dist") for t, p in zip(q_dist, plans)]
-    qs = [_check(t, p, "scalar", "q_snl") for t, p in zip(q_snl, plans)]
+    qs = [_check(t, p, "small", "q_snl") for t, p in zip(q_snl, plans)]
     ms = [_check(t, p, "modes", "mode_sum") for t, p in zip(mode_sum, plans)] if mode_sum else None
     opts = _capi.NutsOpts(n_iter=n_iter, warmup=int(warmup), max_depth=int(max_depth), reserved=0, eps0=float(eps0),
                           target_accept=float(target_accept), seed=int(seed) & 0xFFFFFFFFFFFFFFFF)
@@ -438,13 +450,13 @@ class Server:
 
     def submit(self, *, n_iter, n_leapfrog, eps0, seed, warmup=0, jitter=False, target_accept=0.65,
                q_modes=None, q_dist=None, q_snl=1.0, precision="fp32", hist_width=5.0, sample_distances=True,
-               sample_sigma_nl=True, **problem):
+               sample_sigma_nl=True, sample_cosmology=False, **problem):
         """Queue a job; `problem` holds the Plan keywords (n_grid, box, ...,
         sigma_cz).  q_modes: complex (N, N, N/2) or None (zero field); q_dist:
         (n,) or None (redshift distances)."""
         desc, cat, n, _keep = _problem(hist_width=hist_width, precision=precision,
                                        sample_distances=sample_distances, sample_sigma_nl=sample_sigma_nl,
-                                       **problem)
+                                       sample_cosmology=sample_cosmology, **problem)
         ng = int(problem["n_grid"])
         opts = HmcOpts(n_iter=int(n_iter), n_leapfrog=int(n_leapfrog), warmup=int(warmup),
                        jitter_eps=int(bool(jitter)), eps0=float(eps0), target_accept=float(target_accept),

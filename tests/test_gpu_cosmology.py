@@ -1,0 +1,216 @@
+"""sigma_8 and the growth rate sampled with the field (sample_cosmology):
+the GPU path against the oracle through the C ABI.
+
+The small coordinates are (s, u8, phi).  Psi and every gradient component
+(modes, distances, s, u8, phi) at 1e-12 (FP64) and 2e-5 / 1e-4 (FP32); the
+leapfrog's displacements likewise; an HMC chain and a No-U-Turn chain with
+the same decisions as the oracle's; plans with and without the coordinates
+in one shared launch equal to each plan alone; the flat vector with its two
+extra entries equal to the oracle's.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hmc, model, nuts
+from paper_2203_02369_amd import mocks
+
+from helpers import TOL64, from_lib_layout, oracle_problem, rel_inf, start_modes, to_lib_layout
+
+pytestmark = pytest.mark.gpu
+
+TOL32_PSI, TOL32_GRAD = 2e-5, 1e-4
+COSMO = np.array([0.93, 1.12])
+
+
+@pytest.fixture(scope="module")
+def hl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_02369_amd import hamlet
+    return hamlet
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    "16^3 n300": lambda: mocks.make_mock(16, 200.0, 300, 80.0, "sphere", (0.2, 0.2), seed=31),
+    "64^3 n2000 ZoA": lambda: mocks.make_mock(64, 500.0, 2000, 250.0, "inv_r", (0.15, 0.25), zoa_deg=10.0, seed=33),
+}
+
+
+def _state(plan, dhat, d, s, c):
+    dev = plan.device
+    return (torch.from_numpy(to_lib_layout(dhat)).to(dev), torch.from_numpy(np.ascontiguousarray(d)).to(dev),
+            plan.small(s, *c))
+
+
+def _start(m, k=0):
+    rng = np.random.default_rng(700 + k)
+    return start_modes(m), m.d_true * (1.0 + 0.02 * rng.standard_normal(m.n_gal)), 1.3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_cosmology_gradient_matches_oracle(hl, name, precision):
+    m = CASES[name]()
+    dhat, d, s = _start(m)
+    prob = oracle_problem(m, sample_cosmology=True)
+    ref = model.logpost_grad(prob, dhat, d, s, cosmo=COSMO)
+    assert np.isfinite(ref[0])
+    say("cosmology gradient", name, precision)
+    plan = hl.Plan.from_mock(m, precision=precision, sample_cosmology=True)
+    q, qd, qs = _state(plan, dhat, d, s, COSMO)
+    g, gd, gs, psi = plan.zeros_modes(), plan.zeros_dist(), plan.small(), plan.scalar()
+    hl.logpost_grad([plan], [q], [qd], [qs], [g], [gd], [gs], [psi])
+    torch.cuda.synchronize()
+    small = gs.cpu().numpy()
+    errs = {"psi": abs(psi.item() - ref[0]) / abs(ref[0]),
+            "modes": rel_inf(from_lib_layout(g.cpu().numpy()), ref[1]), "dist": rel_inf(gd.cpu().numpy(), ref[2]),
+            "s": abs(small[0] - ref[3]) / abs(ref[3]), "u8": abs(small[1] - ref[4][0]) / abs(ref[4][0]),
+            "phi": abs(small[2] - ref[4][1]) / abs(ref[4][1])}
+    say("  errors", errs)
+    tol_psi, tol_g = (TOL64, TOL64) if precision == "fp64" else (TOL32_PSI, TOL32_GRAD)
+    assert errs["psi"] <= tol_psi
+    for k in ("modes", "dist", "s", "u8", "phi"):
+        assert errs[k] <= tol_g, (k, errs[k])
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cosmology_leapfrog_matches_oracle(hl, precision):
+    m = mocks.plain_fp64_32()
+    dhat, d, s = _start(m, 1)
+    prob = oracle_problem(m, sample_cosmology=True)
+    q0 = hmc.State(dhat, d.copy(), s, COSMO.copy())
+    p0 = hmc.draw_momenta(prob, 31, 0)
+    eps, steps = 0.02, 6
+    q1, p1, c1 = hmc.leapfrog(prob, q0, p0, eps, steps)
+    say("cosmology leapfrog", precision)
+    plan = hl.Plan.from_mock(m, precision=precision, sample_cosmology=True)
+    tq, tqd, tqs = _state(plan, dhat, d, s, COSMO)
+    tp = torch.from_numpy(to_lib_layout(p0.modes)).to(plan.device)
+    tpd = torch.from_numpy(p0.dist.copy()).to(plan.device)
+    tps = plan.small(p0.s, *p0.cosmo)
+    psi = plan.scalar()
+    hl.leapfrog([plan], [eps], [steps], [tq], [tqd], [tqs], [tp], [tpd], [tps], [psi])
+    torch.cuda.synchronize()
+    qs_g, ps_g = tqs.cpu().numpy(), tps.cpu().numpy()
+    small_q0 = np.array([q0.s, *q0.cosmo])
+    small_q1 = np.array([q1.s, *q1.cosmo])
+    small_p0 = np.array([p0.s, *p0.cosmo])
+    small_p1 = np.array([p1.s, *p1.cosmo])
+    errs = {"modes": rel_inf(from_lib_layout(tq.cpu().numpy()) - q0.modes, q1.modes - q0.modes),
+            "dist": rel_inf(tqd.cpu().numpy() - q0.dist, q1.dist - q0.dist),
+            "p_modes": rel_inf(from_lib_layout(tp.cpu().numpy()) - p0.modes, p1.modes - p0.modes),
+            "p_dist": rel_inf(tpd.cpu().numpy() - p0.dist, p1.dist - p0.dist)}
+    for j, nm in enumerate(("s", "u8", "phi")):
+        errs[nm] = abs((qs_g[j] - small_q0[j]) - (small_q1[j] - small_q0[j])) / abs(small_q1[j] - small_q0[j])
+        errs["p_" + nm] = abs((ps_g[j] - small_p0[j]) - (small_p1[j] - small_p0[j])) / abs(small_p1[j] - small_p0[j])
+    say("  displacement errors", errs)
+    tol = TOL64 if precision == "fp64" else TOL32_GRAD
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+    assert abs(psi.item() - c1[0]) <= (TOL64 if precision == "fp64" else TOL32_PSI) * abs(c1[0])
+    plan.close()
+
+
+def test_cosmology_hmc_chain_matches_oracle(hl):
+    m = CASES["16^3 n300"]()
+    dhat, d, s = _start(m, 2)
+    prob = oracle_problem(m, sample_cosmology=True)
+    q0 = hmc.State(dhat, d.copy(), s, COSMO.copy())
+    n_iter, n_lf, eps, seed = 12, 8, 0.03, 3030
+    res = hmc.hmc_run(prob, q0, n_iter, n_lf, eps, seed, jitter=True)
+    say("cosmology hmc: accept", res.accepted.tolist())
+    plan = hl.Plan.from_mock(m, precision="fp64", sample_cosmology=True)
+    tq, tqd, tqs = _state(plan, dhat, d, s, COSMO)
+    acc = torch.zeros(n_iter, dtype=torch.int32, device=plan.device)
+    dh = torch.zeros(n_iter, dtype=torch.float64, device=plan.device)
+    hl.hmc_run([plan], [tq], [tqd], [tqs], n_iter=n_iter, n_leapfrog=n_lf, eps0=eps, seed=seed, jitter=True,
+               accepted=[acc], dh=[dh])
+    torch.cuda.synchronize()
+    assert np.array_equal(acc.cpu().numpy(), res.accepted)
+    assert 0 < res.accepted.sum()
+    small = tqs.cpu().numpy()
+    fin = np.isfinite(res.dh)
+    errs = {"dh": float(np.abs(dh.cpu().numpy()[fin] - res.dh[fin]).max()) / abs(model.prior_energy(prob, dhat)),
+            "modes": rel_inf(from_lib_layout(tq.cpu().numpy()), res.state.modes),
+            "dist": rel_inf(tqd.cpu().numpy(), res.state.dist),
+            "small": rel_inf(small, np.array([res.state.s, *res.state.cosmo]))}
+    say("  chain errors", errs, "u8, phi:", small[1:], "from", COSMO)
+    for k, e in errs.items():
+        assert e <= TOL64, (k, e)
+    assert np.abs(small[1:] - COSMO).max() > 1e-4          # the cosmological coordinates moved
+    plan.close()
+
+
+def test_cosmology_nuts_matches_oracle(hl):
+    m = CASES["16^3 n300"]()
+    dhat, d, s = _start(m, 3)
+    prob = oracle_problem(m, sample_cosmology=True, sample_distances=False)
+    q0 = hmc.State(dhat, d.copy(), s, COSMO.copy())
+    n_iter, eps, seed, depth = 5, 0.05, 4141, 8
+    res = nuts.nuts_run(nuts.PosteriorTarget(prob), q0, n_iter, eps, seed, max_depth=depth)
+    say("cosmology nuts oracle", res.depth.tolist(), res.leaves.tolist(), res.where.tolist())
+    plan = hl.Plan.from_mock(m, precision="fp64", sample_cosmology=True, sample_distances=False)
+    tq, tqd, tqs = _state(plan, dhat, d, s, COSMO)
+    got = hl.nuts_run([plan], [tq], [tqd], [tqs], n_iter=n_iter, eps0=eps, seed=seed, max_depth=depth)[0]
+    torch.cuda.synchronize()
+    assert np.array_equal(got["depth"], res.depth)
+    assert np.array_equal(got["leaves"], res.leaves)
+    assert np.array_equal(got["where"], res.where)
+    small = tqs.cpu().numpy()
+    errs = {"modes": rel_inf(from_lib_layout(tq.cpu().numpy()), res.state.modes),
+            "small": rel_inf(small, np.array([res.state.s, *res.state.cosmo]))}
+    say("  nuts errors", errs)
+    for k, e in errs.items():
+        assert e <= TOL64, (k, e)
+    plan.close()
+
+
+def test_mixed_batch_equals_alone(hl):
+    # a plan with the cosmological coordinates and one without, same grid
+    # and precision: one shared launch per kernel
+    m1 = CASES["16^3 n300"]()
+    m2 = mocks.make_mock(16, 200.0, 200, 80.0, "sphere", (0.2, 0.2), seed=36)
+    plans = [hl.Plan.from_mock(m1, precision="fp32", sample_cosmology=True), hl.Plan.from_mock(m2, precision="fp32")]
+    starts = [_start(m1, 4), _start(m2, 5)]
+    cos = [COSMO, None]
+
+    def grad(idx):
+        sts = [_state(plans[k], *starts[k], cos[k] if cos[k] is not None else ()) for k in idx]
+        outs = [(plans[k].zeros_modes(), plans[k].zeros_dist(), plans[k].small(), plans[k].scalar()) for k in idx]
+        hl.logpost_grad([plans[k] for k in idx], [x[0] for x in sts], [x[1] for x in sts], [x[2] for x in sts],
+                        [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs], [o[3] for o in outs])
+        torch.cuda.synchronize()
+        return [tuple(t.cpu().numpy() for t in o) for o in outs]
+    say("mixed batch")
+    together = grad([0, 1])
+    for k in range(2):
+        alone = grad([k])[0]
+        assert all(np.array_equal(a, b) for a, b in zip(together[k], alone)), k
+    for p in plans:
+        p.close()
+
+
+def test_cosmology_flat_vector_matches_oracle(hl):
+    m = CASES["16^3 n300"]()
+    dhat, d, s = _start(m, 6)
+    plan = hl.Plan.from_mock(m, precision="fp64", sample_cosmology=True)
+    tq, tqd, tqs = _state(plan, dhat, d, s, COSMO)
+    flat = hl.pack_flat(plan, tq, tqd, tqs)
+    torch.cuda.synchronize()
+    ref = hmc.pack_state(16, dhat, d, s, COSMO)
+    got = flat.cpu().numpy()
+    assert got.shape == ref.shape and np.array_equal(got, ref)
+    q2, d2, s2 = plan.zeros_modes(), plan.zeros_dist(), plan.small()
+    hl.unpack_flat(plan, flat, q2, d2, s2)
+    torch.cuda.synchronize()
+    assert np.array_equal(s2.cpu().numpy(), np.array([s, *COSMO]))
+    plan.close()
