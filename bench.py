@@ -265,6 +265,22 @@ def cpu_baseline(args, mock, dh, d, s):
     return cpu, ref
 
 
+def schedule_info(hamlet, grids, precisions=("fp32", "fp64")):
+    """The kernel schedule the library runs at each grid size, and where it
+    comes from (the autotuner's JSON cache when it has the grid)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(hamlet.__file__)), "tuned_schedules.json")
+    tuned = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            tuned = json.load(f).get("schedules", {})
+    out = {}
+    for prec in precisions:
+        for n in grids:
+            src = "autotuned" if str(n) in tuned.get(prec, {}) else "default"
+            out.setdefault(prec, {})[str(n)] = dict(hamlet.schedule(n, prec), source=src)
+    return out
+
+
 def rel_err(x, ref):
     import numpy as np
     x = np.asarray(x)
@@ -526,6 +542,7 @@ def main():
         "nuts": nuts,
         "served": served,
         "oracle_err": oracle_err,
+        "schedule": schedule_info(hamlet, [n]),
         "roofline": roofline,
         "passes": passes,
         "analysis": analysis,
@@ -730,6 +747,7 @@ def run_batched(args, dev):
                                "share every launch, the grid sizes run side by side" % L,
                    "chains": [[p.n_grid, p.n_gal] for p in plans], "leapfrog_steps": L,
                    "acceptance": round(rate, 3), "grad_evals_timed": grads},
+        "schedule": schedule_info(hamlet, sorted({p.n_grid for p in plans}), ("fp32",)),
         "one_at_a_time": {"value": round(v_seq, 2), "unit": "grad evals/s",
                           "speedup_shared_vs_one_at_a_time": round(value / v_seq, 3)},
         "roofline": {"bound": "hbm", "kernel": "k_x_pass<float, 256> over the five 256^3 chains of one launch",

@@ -460,6 +460,28 @@ typedef enum {
 hamlet_status hamlet_profile_start(hamlet_plan* plan, int32_t kernel);
 hamlet_status hamlet_profile_stop(hamlet_plan* plan, double* total_ms, int64_t* launches);
 
+/* The kernel schedule this library was built with for a grid size and
+ * precision: what the autotuner chose where it timed alternatives on the
+ * MI355X (tuned_schedules.json beside the library), else the hand-picked
+ * defaults.  Not part of the method; it describes how the passes of the
+ * evaluation are launched, so that a measurement can name it. */
+typedef struct {
+  int32_t threads_xy;        /* threads per block: the y passes (and a plain gradient's inverse x pass) */
+  int32_t threads_x;         /* the fused x pass */
+  int32_t threads_gather;    /* the inverse z pass with the CIC gather */
+  int32_t threads_scatter;   /* the forward z pass with the CIC scatter */
+  int32_t tile_width;        /* kz columns per tile of the x and y passes */
+  int32_t pencils_scatter;   /* z pencils per tile of the scatter */
+  int32_t pencils_gather;    /* z pencils per tile of the gather */
+  int32_t radix_plan;        /* index of the radix plan of the length-n transforms */
+  int32_t radix[3];          /* its radices, stage by stage (0 past the last) */
+} hamlet_schedule;
+
+/* Fills *out for grid size n_grid and precision (hamlet_precision).
+ * HAMLET_EINVAL: NULL out or unknown precision; HAMLET_EUNSUPPORTED: a
+ * grid size this library does not hold.  Needs no GPU. */
+hamlet_status hamlet_schedule_get(int32_t precision, int32_t n_grid, hamlet_schedule* out);
+
 /* Message of the last non-OK status on this thread ("" if none). */
 const char* hamlet_last_error(void);
 

@@ -7,7 +7,8 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libhamlet.so")
+# HAMLET_LIB names another build of the library (the autotuner's candidates)
+LIB_PATH = os.environ.get("HAMLET_LIB") or os.path.join(_PKG, "libhamlet.so")
 
 HAMLET_OK = 0
 HAMLET_FP64 = 0
@@ -63,6 +64,12 @@ class HmcOpts(ctypes.Structure):
         ("resume", ctypes.c_int32),
         ("seeds", ctypes.POINTER(ctypes.c_uint64)),
     ]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in (
+        "threads_xy", "threads_x", "threads_gather", "threads_scatter", "tile_width", "pencils_scatter",
+        "pencils_gather", "radix_plan")] + [("radix", ctypes.c_int32 * 3)]
 
 
 class NutsOpts(ctypes.Structure):
@@ -138,6 +145,7 @@ SIGNATURES = {
                                           c_double_p, c_double_p, c_int32_p, c_double_p]),
     "hamlet_profile_start": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "hamlet_profile_stop": (ctypes.c_int, [ctypes.c_void_p, c_double_p, ctypes.POINTER(ctypes.c_int64)]),
+    "hamlet_schedule_get": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Schedule)]),
     "hamlet_last_error": (ctypes.c_char_p, []),
 }
 

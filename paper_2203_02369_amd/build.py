@@ -11,8 +11,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libhamlet.so")
 SOURCES = [os.path.join(PKG, "csrc", "hamlet.hip")]
-HEADERS = ["common.hpp", "fft.hpp", "workspace.hpp", "random.hpp", "flat.hpp", "passes.hpp", "galaxies.hpp", "hmc.hpp",
-           "analysis.hpp"]
+HEADERS = ["common.hpp", "schedule.hpp", "tuned.hpp", "fft.hpp", "workspace.hpp", "random.hpp", "flat.hpp", "passes.hpp",
+           "galaxies.hpp", "hmc.hpp", "nuts.hpp", "analysis.hpp"]
 
 ARCH = "gfx950"
 FLAGS = [
@@ -35,19 +35,24 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False):
-    """Compile every HIP source into libhamlet.so; always recompiles."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-                               "-o", tmp] + SOURCES
+def build(verbose=False, out=None, defines=(), quiet=False):
+    """Compile every HIP source into libhamlet.so (or `out`, with extra -D
+    `defines`: the autotuner's candidate libraries); always recompiles.
+    quiet: the compiler's messages go into the exception, not stderr."""
+    lib = out or LIB
+    tmp = lib + ".tmp"
+    cmd = [hipcc()] + FLAGS + ["-D" + d for d in defines] + ["-I", os.path.join(ROOT, "include"), "-I",
+                                                             os.path.join(PKG, "csrc"), "-o", tmp] + SOURCES
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
+        if quiet:
+            raise RuntimeError("hipcc failed building %s:\n%s" % (os.path.basename(lib), (res.stdout + res.stderr)[-4000:]))
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed building libhamlet.so")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

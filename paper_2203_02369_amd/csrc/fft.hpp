@@ -17,6 +17,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "schedule.hpp"
 
 namespace hamlet {
 
@@ -178,38 +179,19 @@ __device__ __forceinline__ void lds_stage(cplx_t<T>* buf, const cplx_t<T>* tw) {
   __syncthreads();
 }
 
-// Radix plan per length; the whole transform of a batch in LDS.
+// The whole transform of a batch in LDS, in the Stockham stages of the
+// schedule's radix plan (schedule.hpp); a stage's span is the product of
+// the radices before it.
 // Callers must have synchronised the LDS contents before the call; on
 // return the result is in place and synchronised.
 template <typename T, int N, int B, typename LAY, int NT, int SIGN, bool TWP = false>
 __device__ __forceinline__ void lds_fft(cplx_t<T>* buf, const cplx_t<T>* tw) {
   static_assert(N >= 8 && N <= 1024 && (N & (N - 1)) == 0, "FFT length must be 8..1024, power of two");
-  if constexpr (N == 8) {
-    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
-  } else if constexpr (N == 16) {
-    lds_stage<T, N, 4, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
-    lds_stage<T, N, 4, 4, B, LAY, NT, SIGN, TWP>(buf, tw);
-  } else if constexpr (N == 32) {
-    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
-    lds_stage<T, N, 4, 8, B, LAY, NT, SIGN, TWP>(buf, tw);
-  } else if constexpr (N == 64) {
-    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
-    lds_stage<T, N, 8, 8, B, LAY, NT, SIGN, TWP>(buf, tw);
-  } else if constexpr (N == 128) {
-    lds_stage<T, N, 16, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
-    lds_stage<T, N, 8, 16, B, LAY, NT, SIGN, TWP>(buf, tw);
-  } else if constexpr (N == 256) {
-    lds_stage<T, N, 16, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
-    lds_stage<T, N, 16, 16, B, LAY, NT, SIGN, TWP>(buf, tw);
-  } else if constexpr (N == 512) {
-    lds_stage<T, N, 8, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
-    lds_stage<T, N, 8, 8, B, LAY, NT, SIGN, TWP>(buf, tw);
-    lds_stage<T, N, 8, 64, B, LAY, NT, SIGN, TWP>(buf, tw);
-  } else {
-    lds_stage<T, N, 16, 1, B, LAY, NT, SIGN, TWP>(buf, tw);
-    lds_stage<T, N, 8, 16, B, LAY, NT, SIGN, TWP>(buf, tw);
-    lds_stage<T, N, 8, 128, B, LAY, NT, SIGN, TWP>(buf, tw);
-  }
+  constexpr RadixPlan RP = radix_plan(N, Sched<T, N>::RADIX);
+  static_assert(RP.r[0] * (RP.r[1] ? RP.r[1] : 1) * (RP.r[2] ? RP.r[2] : 1) == N, "radices multiply to N");
+  lds_stage<T, N, RP.r[0], 1, B, LAY, NT, SIGN, TWP>(buf, tw);
+  if constexpr (RP.r[1] > 0) lds_stage<T, N, RP.r[1], RP.r[0], B, LAY, NT, SIGN, TWP>(buf, tw);
+  if constexpr (RP.r[2] > 0) lds_stage<T, N, RP.r[2], RP.r[0] * RP.r[1], B, LAY, NT, SIGN, TWP>(buf, tw);
 }
 
 // Stage the N-entry twiddle table into LDS (caller synchronises).

@@ -459,14 +459,19 @@ template <typename T, int N> struct OpsFor {
                            density_impl<T, N>,    stats_impl<T, N>, nuts_start_impl<T, N>, kin1_impl<T, N>};
 };
 
+template <typename T, int N> static const Ops* ops_if_built() {
+  if constexpr (has_grid(N)) return &OpsFor<T, N>::ops;
+  else return nullptr;
+}
+
 template <typename T> static const Ops* pick_ops(int n) {
   switch (n) {
-    case 16: return &OpsFor<T, 16>::ops;
-    case 32: return &OpsFor<T, 32>::ops;
-    case 64: return &OpsFor<T, 64>::ops;
-    case 128: return &OpsFor<T, 128>::ops;
-    case 256: return &OpsFor<T, 256>::ops;
-    case 512: return &OpsFor<T, 512>::ops;
+    case 16: return ops_if_built<T, 16>();
+    case 32: return ops_if_built<T, 32>();
+    case 64: return ops_if_built<T, 64>();
+    case 128: return ops_if_built<T, 128>();
+    case 256: return ops_if_built<T, 256>();
+    case 512: return ops_if_built<T, 512>();
     default: return nullptr;
   }
 }
@@ -477,7 +482,7 @@ template <typename T> static const Ops* pick_ops(int n) {
 static hamlet_status check_desc(const hamlet_plan_desc* d) {
   if (!d) return fail(HAMLET_EINVAL, "desc is NULL");
   const int n = d->n_grid;
-  if (n != 16 && n != 32 && n != 64 && n != 128 && n != 256 && n != 512)
+  if ((n != 16 && n != 32 && n != 64 && n != 128 && n != 256 && n != 512) || !pick_ops<float>(n))
     return fail(HAMLET_EUNSUPPORTED, "n_grid %d: built for 16, 32, 64, 128, 256, 512", n);
   if (d->precision != HAMLET_FP64 && d->precision != HAMLET_FP32_FP64E)
     return fail(HAMLET_EINVAL, "precision %d", d->precision);
@@ -545,6 +550,22 @@ struct Staging {
 // Enqueues the plan's set-up on its stream: tables, twiddles, catalogue,
 // distance prior, constants.  Reads the catalogue arrays and `sg` until the
 // stream reaches the end of the set-up.
+// The x pass's tile width of a plan's grid and precision, in whose tiles
+// sigma^2 is laid out (the schedule's W).
+template <typename T> static int tile_width_of(int n) {
+  switch (n) {
+    case 16: return Sched<T, 16>::W;
+    case 32: return Sched<T, 32>::W;
+    case 64: return Sched<T, 64>::W;
+    case 128: return Sched<T, 128>::W;
+    case 256: return Sched<T, 256>::W;
+    default: return Sched<T, 512>::W;
+  }
+}
+static int scheduled_tile_width(int prec, int n) {
+  return prec == HAMLET_FP64 ? tile_width_of<double>(n) : tile_width_of<float>(n);
+}
+
 static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const hamlet_catalog* c, Staging& sg) {
   const int n = pl->n;
   const size_t npk = 3 * (size_t)(n / 2) * (n / 2) + 1;
@@ -568,8 +589,7 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
   }
   hipStream_t st = pl->stream;
   HIP_TRY(hipMemcpyAsync(pl->var, var.data(), npk * 8, hipMemcpyHostToDevice, st));
-  // the x pass's tile width, in whose tiles sigma^2 is laid out
-  const int w = tile_width(pl->prec == HAMLET_FP64 ? 8 : 4, n);
+  const int w = scheduled_tile_width(pl->prec, n);
   k_fill_mode_var<<<blocks_for(pl->modes_count(), kEltThreads), kEltThreads, 0, st>>>(pl->mvar, pl->var, n, w);
   LAUNCH_CHECK();
   if (pl->prec == HAMLET_FP64)
@@ -1349,6 +1369,10 @@ static NutsSet nuts_ref_set(const NutsChain& c, const NRef& r) {
   return s;
 }
 
+template <int N> static void nuts_dot_launch(const NutsDotArgs& a, hipStream_t st) {
+  if constexpr (has_grid(N)) k_nuts_dot<N><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a);
+}
+
 static hamlet_status nuts_dot(const hamlet_plan* pl, const NutsSet& qa, const NutsSet& qb, const NutsSet& ra,
                               const NutsSet& rb, int slot, hipStream_t st) {
   NutsDotArgs a;
@@ -1362,12 +1386,12 @@ static hamlet_status nuts_dot(const hamlet_plan* pl, const NutsSet& qa, const Nu
   a.part = pl->nuts->part + (size_t)slot * 2 * kNutsDotBlocks;
   a.out = pl->nuts->back + 3 + 2 * slot;
   switch (pl->n) {
-    case 16: k_nuts_dot<16><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a); break;
-    case 32: k_nuts_dot<32><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a); break;
-    case 64: k_nuts_dot<64><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a); break;
-    case 128: k_nuts_dot<128><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a); break;
-    case 256: k_nuts_dot<256><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a); break;
-    case 512: k_nuts_dot<512><<<kNutsDotBlocks, kEltThreads, 0, st>>>(a); break;
+    case 16: nuts_dot_launch<16>(a, st); break;
+    case 32: nuts_dot_launch<32>(a, st); break;
+    case 64: nuts_dot_launch<64>(a, st); break;
+    case 128: nuts_dot_launch<128>(a, st); break;
+    case 256: nuts_dot_launch<256>(a, st); break;
+    case 512: nuts_dot_launch<512>(a, st); break;
     default: return fail(HAMLET_EUNSUPPORTED, "grid size %d", pl->n);
   }
   k_nuts_dot_final<<<1, 256, 0, st>>>(a.part, kNutsDotBlocks, a.out);
@@ -1884,7 +1908,8 @@ extern "C" hamlet_status hamlet_shell_stats_static(hamlet_plan* plan, const doub
 template <int N>
 static void moments_pass(const hamlet_plan* pl, const double2* modes, const MomentRadii& rad, double kf,
                          double mono_scale, double dip_scale, double* part) {
-  k_sphere_moments<N><<<kMomentsBlocks, 256, 0, pl->stream>>>(modes, rad, kf, mono_scale, dip_scale, part);
+  if constexpr (has_grid(N))
+    k_sphere_moments<N><<<kMomentsBlocks, 256, 0, pl->stream>>>(modes, rad, kf, mono_scale, dip_scale, part);
 }
 
 extern "C" hamlet_status hamlet_sphere_moments(hamlet_plan* plan, const void* modes, const double* radii,
@@ -2293,6 +2318,43 @@ extern "C" hamlet_status hamlet_profile_stop(hamlet_plan* pl, double* total_ms, 
   *launches = (int64_t)pl->prof_used;
   pl->prof_used = 0;
   if (pl->prof_failed) return fail(HAMLET_EDEVICE, "event creation or record failed while profiling");
+  return HAMLET_OK;
+}
+
+template <typename T, int N> static void schedule_of(hamlet_schedule* o) {
+  using SC = Sched<T, N>;
+  o->threads_xy = SC::XY;
+  o->threads_x = SC::X;
+  o->threads_gather = SC::ZG;
+  o->threads_scatter = SC::ZS;
+  o->tile_width = SC::W;
+  o->pencils_scatter = SC::PZ;
+  o->pencils_gather = SC::PG;
+  o->radix_plan = SC::RADIX < radix_plans(N) ? SC::RADIX : 0;
+  const RadixPlan rp = radix_plan(N, SC::RADIX);
+  for (int i = 0; i < 3; ++i) o->radix[i] = rp.r[i];
+}
+
+template <typename T> static bool schedule_for(int n, hamlet_schedule* o) {
+  switch (n) {
+    case 16: schedule_of<T, 16>(o); break;
+    case 32: schedule_of<T, 32>(o); break;
+    case 64: schedule_of<T, 64>(o); break;
+    case 128: schedule_of<T, 128>(o); break;
+    case 256: schedule_of<T, 256>(o); break;
+    case 512: schedule_of<T, 512>(o); break;
+    default: return false;
+  }
+  return pick_ops<T>(n) != nullptr;
+}
+
+extern "C" hamlet_status hamlet_schedule_get(int32_t precision, int32_t n_grid, hamlet_schedule* out) {
+  if (!out) return fail(HAMLET_EINVAL, "NULL argument");
+  bool ok;
+  if (precision == HAMLET_FP64) ok = schedule_for<double>(n_grid, out);
+  else if (precision == HAMLET_FP32_FP64E) ok = schedule_for<float>(n_grid, out);
+  else return fail(HAMLET_EINVAL, "precision %d", precision);
+  if (!ok) return fail(HAMLET_EUNSUPPORTED, "n_grid %d: not built into this library", n_grid);
   return HAMLET_OK;
 }
 

@@ -34,12 +34,13 @@ namespace hamlet {
 
 constexpr int kPassThreads = 256;
 
-// Threads per block of each pass kind (tuned on the MI355X).
+// Threads per block of each pass kind: the schedule of the grid size and
+// real type (schedule.hpp; the autotuner's choice where it has one).
 template <typename T, int N> struct PassThreads {
-  static constexpr int XY = N >= 512 ? 512 : 256;       // k_inv_x, k_inv_y, k_fwd_y
-  static constexpr int X = 512;                          // k_x_pass
-  static constexpr int ZG = 256;                         // k_inv_z_gather
-  static constexpr int ZS = 256;                         // k_fwd_z_scatter
+  static constexpr int XY = Sched<T, N>::XY;   // k_inv_x, k_inv_y, k_fwd_y
+  static constexpr int X = Sched<T, N>::X;     // k_x_pass
+  static constexpr int ZG = Sched<T, N>::ZG;   // k_inv_z_gather
+  static constexpr int ZS = Sched<T, N>::ZS;   // k_fwd_z_scatter
 };
 
 // The y and z passes of each direction may run slab by slab in x so that the
@@ -52,12 +53,9 @@ template <int N> struct XSlabs {
 
 template <typename T, int N> struct PassShape {
   using C = cplx_t<T>;
-  static constexpr int PMAX = sizeof(T) == 4 ? 8 : 4;
-  static constexpr int W = tile_width(sizeof(T), N);       // kz columns per strided tile
-  static constexpr int P = PMAX < N ? PMAX : N;             // pencils per z tile (scatter)
-  // pencils per tile of the gather: half as many at 512^3, where its LDS
-  // transform buffer would otherwise keep two tiles per compute unit
-  static constexpr int PG = N >= 512 ? P / 2 : P;
+  static constexpr int W = Sched<T, N>::W;                  // kz columns per strided tile
+  static constexpr int P = Sched<T, N>::PZ;                 // pencils per z tile (scatter)
+  static constexpr int PG = Sched<T, N>::PG;                // pencils per z tile (gather)
   static constexpr int FG = 3 * PG / 2;
   static constexpr int H = N / 2;
   static constexpr int CHUNKS = H / W;

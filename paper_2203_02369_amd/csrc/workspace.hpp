@@ -13,6 +13,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "schedule.hpp"
 
 namespace hamlet {
 
@@ -95,19 +96,16 @@ constexpr int kMomentsPassValues = 4 * kMomentsRadiiPerPass;
 constexpr size_t kMomentsPartBytes =
     8 * size_t(kMomentsBlocks) * kMomentsPassValues * (kMomentsMaxRadii / kMomentsRadiiPerPass);
 
-// kz columns per strided tile of the x and y passes: 16 (FP32) or 8 (FP64),
-// halved at N = 512 so that a tile of N rows keeps the LDS and registers it
-// has at 256, and at most N/2.  The per-mode sigma^2 array is laid out in
-// these tiles, so the passes, the layout and the host all take it from here.
-__host__ __device__ constexpr int tile_width(int real_bytes, int n) {
-  const int w = (real_bytes == 4 ? 16 : 8) / (n >= 512 ? 2 : 1);
-  return w < n / 2 ? w : n / 2;
+// The x pass's tile width of a grid size and real width (bytes): sigma^2
+// per mode is laid out in these tiles (schedule.hpp).
+template <int N, int R> constexpr int layout_tile_width() {
+  return R == 4 ? Sched<float, N>::W : Sched<double, N>::W;
 }
 
 template <int N, int R> struct FixedLayout {
   static constexpr size_t NM = size_t(N) * N * (N / 2);          // stored modes
   static constexpr size_t NPK = 3 * size_t(N / 2) * (N / 2) + 1; // |n|^2 table
-  static constexpr int W = tile_width(R, N);
+  static constexpr int W = layout_tile_width<N, R>();
   static constexpr int N_PRIOR = N * ((N / 2) / W);              // x-pass blocks
   static constexpr int N_KIN_SMALL = 64;                         // blocks of the distance and s terms
   static constexpr int N_KIN = N_PRIOR + N_KIN_SMALL;            // kinetic-energy partials

@@ -524,6 +524,18 @@ class Server:
 
 # -- measurement ---------------------------------------------------------------
 
+def schedule(n_grid, precision="fp32"):
+    """The kernel schedule the loaded library uses for a grid size and
+    precision (hamlet_schedule_get), as a dict; the radix plan as its
+    radices ("16x16")."""
+    out = _capi.Schedule()
+    prec = 0 if precision == "fp64" else 1
+    _capi.check(_capi.load().hamlet_schedule_get(prec, int(n_grid), ctypes.byref(out)))
+    res = {name: int(getattr(out, name)) for name, _ in _capi.Schedule._fields_ if name != "radix"}
+    res["radix"] = "x".join(str(r) for r in out.radix if r)
+    return res
+
+
 PROFILE_KERNELS = {"bin": 0, "inv_x": 1, "inv_y": 2, "inv_z_gather": 3, "like": 4, "fwd_z_scatter": 5,
                    "fwd_y": 6, "fwd_x": 7}
 
