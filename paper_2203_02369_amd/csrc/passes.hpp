@@ -455,105 +455,87 @@ __device__ __forceinline__ int zslot_part(int p, int c) {
   return c == 0 ? 0 : (c == 1 ? 1 : (p & 1));
 }
 
-// The spectra of a z tile into LDS (a barrier must follow): for each
-// transform f of the tile (P pencils from y0), Z = A + i B with A, B the
-// Hermitian half spectra of its two real pencils (Nyquist entry zero, DC
-// entries real).  Pencils whose bit in tp is clear are taken as zero and not
-// loaded.
+// The spectra of a z tile, loaded into registers (load) and then written
+// into LDS (put; a barrier must follow): for each transform f of the tile (P
+// pencils from y0), Z = A + i B with A, B the Hermitian half spectra of its
+// two real pencils (Nyquist entry zero, DC entries real).  Pencils whose bit
+// in tp is clear are taken as zero and not loaded.  Splitting the two lets a
+// pass issue the next tile's loads before it transforms the current one.
 // NZ: the third array carries n_z (velocity component z); without it the
 // third array is taken as it is (a scalar field).
-template <typename T, int N, int NT, int P, bool NZ = true>
-__device__ __forceinline__ void
-z_tile_spectra(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ vy, const cplx_t<T>* __restrict__ vz,
-               int x, int y0, unsigned tp, cplx_t<T>* buf) {
+template <typename T, int N, int NT, int P, bool NZ = true> struct ZSpectra {
   using C = cplx_t<T>;
   using LAY = typename PassShape<T, N>::Pen;
-  constexpr int H = N / 2, F = 3 * P / 2;
-  auto touched = [&](int q) { return ((tp >> q) & 1u) != 0; };
-  // Build Z = A + i B with A, B the Hermitian half spectra of the two real
-  // pencils of each transform (Nyquist entry zero, DC entries real).
-  auto put = [&](int k, int f, C av, C bv) {
-    if (k == 0) {
-      buf[LAY::idx(0, f)] = cmake<C>(av.x, bv.x);
-      buf[LAY::idx(H, f)] = cmake<C>((T)0, (T)0);
-    } else {
-      buf[LAY::idx(k, f)] = cmake<C>(av.x - bv.y, av.y + bv.x);          // A + i B
-      buf[LAY::idx(N - k, f)] = cmake<C>(av.x + bv.y, bv.x - av.y);      // conj(A) + i conj(B)
-    }
-  };
+  static constexpr int H = N / 2, F = 3 * P / 2;
+  // FP32: two consecutive kz per thread (16-byte loads); FP64: one
+  static constexpr int KT = sizeof(C) == 8 ? 2 : 1;
+  static constexpr int HK = H / KT, IT = (F * HK + NT - 1) / NT;
+  struct alignas(16) CK { C v[KT]; };
+  CK av[IT], bv[IT];
+
   // Real pencils of transform f: pa in the real part, pb in the imaginary
   // part, from vx / vy (f = 3m, 3m + 2) or n_z vz (f = 3m + 1).
-  auto sources = [&](int f, int& pa, int& pb) {
+  __device__ __forceinline__ static bool sources(int f, int& pa, int& pb) {
     const int m = f / 3, r = f % 3;
     pa = 2 * m + (r == 2 ? 1 : 0);
     pb = r == 1 ? 2 * m + 1 : pa;
     return r == 1;
-  };
-  // Every load of a thread is issued before the first wait: loads into
-  // registers, then the spectra into LDS.
-  if constexpr (sizeof(C) == 8) {
-    // FP32: two consecutive kz per thread, 16-byte loads
-    struct C2 { C a, b; };
-    constexpr int H2 = H / 2, IT = (F * H2 + NT - 1) / NT;
-    C2 av[IT], bv[IT];
+  }
+
+  // Every load of a thread is issued before any wait.
+  __device__ __forceinline__ void load(const C* __restrict__ vx, const C* __restrict__ vy,
+                                       const C* __restrict__ vz, int x, int y0, unsigned tp) {
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int idx = threadIdx.x + it * NT;
-      const C zero = cmake<C>((T)0, (T)0);
-      av[it] = bv[it] = C2{zero, zero};
-      if (idx < F * H2) {
-        const int k = 2 * (idx % H2), f = idx / H2;
+#pragma unroll
+      for (int j = 0; j < KT; ++j) av[it].v[j] = bv[it].v[j] = cmake<C>((T)0, (T)0);
+      if (idx < F * HK) {
+        const int k = KT * (idx % HK), f = idx / HK;
         int pa, pb;
         const bool zc = sources(f, pa, pb);
-        if (touched(pa)) av[it] = ld_stream(reinterpret_cast<const C2*>(&(zc ? vz : vx)[gofs<N>(x, y0 + pa, k)]));
-        if (touched(pb)) bv[it] = ld_stream(reinterpret_cast<const C2*>(&(zc ? vz : vy)[gofs<N>(x, y0 + pb, k)]));
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      if (idx < F * H2) {
-        const int k = 2 * (idx % H2), f = idx / H2;
-        int pa, pb;
-        if (sources(f, pa, pb) && NZ) {
-          av[it].a = cscale(av[it].a, (T)k);
-          av[it].b = cscale(av[it].b, (T)(k + 1));
-          bv[it].a = cscale(bv[it].a, (T)k);
-          bv[it].b = cscale(bv[it].b, (T)(k + 1));
-        }
-        put(k, f, av[it].a, bv[it].a);
-        put(k + 1, f, av[it].b, bv[it].b);
-      }
-    }
-  } else {
-    constexpr int IT = (F * H + NT - 1) / NT;
-    C av[IT], bv[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      av[it] = bv[it] = cmake<C>((T)0, (T)0);
-      if (idx < F * H) {
-        const int k = idx % H, f = idx / H;
-        int pa, pb;
-        const bool zc = sources(f, pa, pb);
-        if (touched(pa)) av[it] = ld_stream(&(zc ? vz : vx)[gofs<N>(x, y0 + pa, k)]);
-        if (touched(pb)) bv[it] = ld_stream(&(zc ? vz : vy)[gofs<N>(x, y0 + pb, k)]);
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * NT;
-      if (idx < F * H) {
-        const int k = idx % H, f = idx / H;
-        int pa, pb;
-        if (sources(f, pa, pb) && NZ) {
-          av[it] = cscale(av[it], (T)k);
-          bv[it] = cscale(bv[it], (T)k);
-        }
-        put(k, f, av[it], bv[it]);
+        if ((tp >> pa) & 1u) av[it] = ld_stream(reinterpret_cast<const CK*>(&(zc ? vz : vx)[gofs<N>(x, y0 + pa, k)]));
+        if ((tp >> pb) & 1u) bv[it] = ld_stream(reinterpret_cast<const CK*>(&(zc ? vz : vy)[gofs<N>(x, y0 + pb, k)]));
       }
     }
   }
+
+  __device__ __forceinline__ void put(C* buf) const {
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      if (idx < F * HK) {
+        const int k0 = KT * (idx % HK), f = idx / HK;
+        int pa, pb;
+        const bool zc = sources(f, pa, pb);
+#pragma unroll
+        for (int j = 0; j < KT; ++j) {
+          const int k = k0 + j;
+          C av_ = av[it].v[j], bv_ = bv[it].v[j];
+          if (zc && NZ) {
+            av_ = cscale(av_, (T)k);
+            bv_ = cscale(bv_, (T)k);
+          }
+          if (k == 0) {
+            buf[LAY::idx(0, f)] = cmake<C>(av_.x, bv_.x);
+            buf[LAY::idx(H, f)] = cmake<C>((T)0, (T)0);
+          } else {
+            buf[LAY::idx(k, f)] = cmake<C>(av_.x - bv_.y, av_.y + bv_.x);        // A + i B
+            buf[LAY::idx(N - k, f)] = cmake<C>(av_.x + bv_.y, bv_.x - av_.y);    // conj(A) + i conj(B)
+          }
+        }
+      }
+    }
+  }
+};
+
+template <typename T, int N, int NT, int P, bool NZ = true>
+__device__ __forceinline__ void
+z_tile_spectra(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict__ vy, const cplx_t<T>* __restrict__ vz,
+               int x, int y0, unsigned tp, cplx_t<T>* buf) {
+  ZSpectra<T, N, NT, P, NZ> sp;
+  sp.load(vx, vy, vz, x, y0, tp);
+  sp.put(buf);
 }
 
 // ---------------------------------------------------------------------------
