@@ -75,7 +75,7 @@ typedef enum {
 /* Problem statement (Section 2; the grid and box of Section 5.1).  All
  * pointers are host memory, read during hamlet_plan_create only. */
 typedef struct {
-  int32_t n_grid;           /* N: 16, 32, 64, 128, 256 or 512 */
+  int32_t n_grid;           /* N: 16, 32, 64, 128, 256, 512 or 1024 */
   int32_t precision;        /* hamlet_precision */
   double box;               /* L, Mpc/h */
   double omega_m;           /* Omega0 of zbar(d) (Section 2.2) */

@@ -472,6 +472,7 @@ template <typename T> static const Ops* pick_ops(int n) {
     case 128: return ops_if_built<T, 128>();
     case 256: return ops_if_built<T, 256>();
     case 512: return ops_if_built<T, 512>();
+    case 1024: return ops_if_built<T, 1024>();
     default: return nullptr;
   }
 }
@@ -482,8 +483,8 @@ template <typename T> static const Ops* pick_ops(int n) {
 static hamlet_status check_desc(const hamlet_plan_desc* d) {
   if (!d) return fail(HAMLET_EINVAL, "desc is NULL");
   const int n = d->n_grid;
-  if ((n != 16 && n != 32 && n != 64 && n != 128 && n != 256 && n != 512) || !pick_ops<float>(n))
-    return fail(HAMLET_EUNSUPPORTED, "n_grid %d: built for 16, 32, 64, 128, 256, 512", n);
+  if ((n != 16 && n != 32 && n != 64 && n != 128 && n != 256 && n != 512 && n != 1024) || !pick_ops<float>(n))
+    return fail(HAMLET_EUNSUPPORTED, "n_grid %d: built for 16, 32, 64, 128, 256, 512, 1024", n);
   if (d->precision != HAMLET_FP64 && d->precision != HAMLET_FP32_FP64E)
     return fail(HAMLET_EINVAL, "precision %d", d->precision);
   if (!(d->box > 0) || !std::isfinite(d->box)) return fail(HAMLET_EINVAL, "box must be positive");
@@ -559,7 +560,8 @@ template <typename T> static int tile_width_of(int n) {
     case 64: return Sched<T, 64>::W;
     case 128: return Sched<T, 128>::W;
     case 256: return Sched<T, 256>::W;
-    default: return Sched<T, 512>::W;
+    case 512: return Sched<T, 512>::W;
+    default: return Sched<T, 1024>::W;
   }
 }
 static int scheduled_tile_width(int prec, int n) {
@@ -1392,6 +1394,7 @@ static hamlet_status nuts_dot(const hamlet_plan* pl, const NutsSet& qa, const Nu
     case 128: nuts_dot_launch<128>(a, st); break;
     case 256: nuts_dot_launch<256>(a, st); break;
     case 512: nuts_dot_launch<512>(a, st); break;
+    case 1024: nuts_dot_launch<1024>(a, st); break;
     default: return fail(HAMLET_EUNSUPPORTED, "grid size %d", pl->n);
   }
   k_nuts_dot_final<<<1, 256, 0, st>>>(a.part, kNutsDotBlocks, a.out);
@@ -1938,6 +1941,7 @@ extern "C" hamlet_status hamlet_sphere_moments(hamlet_plan* plan, const void* mo
       case 128: moments_pass<128>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
       case 256: moments_pass<256>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
       case 512: moments_pass<512>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
+      case 1024: moments_pass<1024>(plan, q, rad, kf, mono_scale, dip_scale, part); break;
       default: return fail(HAMLET_EUNSUPPORTED, "grid size %d", plan->n);
     }
   }
@@ -2343,6 +2347,7 @@ template <typename T> static bool schedule_for(int n, hamlet_schedule* o) {
     case 128: schedule_of<T, 128>(o); break;
     case 256: schedule_of<T, 256>(o); break;
     case 512: schedule_of<T, 512>(o); break;
+    case 1024: schedule_of<T, 1024>(o); break;
     default: return false;
   }
   return pick_ops<T>(n) != nullptr;

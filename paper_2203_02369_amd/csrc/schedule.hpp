@@ -15,12 +15,12 @@
 namespace hamlet {
 
 // kz columns per strided tile of the x and y passes: 16 (FP32) or 8 (FP64),
-// halved at N = 512 so that a tile of N rows keeps the LDS and registers it
-// has at 256, and at most N/2.  The per-mode sigma^2 array is laid out in
-// these tiles, so the passes, the layout and the host all take the width
-// from the schedule.
+// halved at N = 512 and again at 1024 so that a tile of N rows keeps the
+// LDS and registers it has at 256, and at most N/2.  The per-mode sigma^2
+// array is laid out in these tiles, so the passes, the layout and the host
+// all take the width from the schedule.
 __host__ __device__ constexpr int default_tile_width(int real_bytes, int n) {
-  const int w = (real_bytes == 4 ? 16 : 8) / (n >= 512 ? 2 : 1);
+  const int w = (real_bytes == 4 ? 16 : 8) / (n >= 1024 ? 4 : (n >= 512 ? 2 : 1));
   return w < n / 2 ? w : n / 2;
 }
 

@@ -7,7 +7,7 @@ import pytest
 
 from paper_2203_02369_amd import autotune, hamlet
 
-GRIDS = (16, 32, 64, 128, 256, 512)
+GRIDS = (16, 32, 64, 128, 256, 512, 1024)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
