@@ -22,6 +22,8 @@ schedule is timed again against the default before it is trusted.
     python -m paper_2203_02369_amd.autotune select FILE [FILE ...]          # CPU: JSON + tuned.hpp
     python -m paper_2203_02369_amd.autotune time --out V --only default --current   # GPU: combined
     python -m paper_2203_02369_amd.autotune verify V                        # CPU: record it
+    python -m paper_2203_02369_amd.autotune build --refine --grids ...      # CPU: moves from the tuned
+    python -m paper_2203_02369_amd.autotune select --refine FILE            # CPU: merge them
     python -m paper_2203_02369_amd.autotune header                          # CPU: tuned.hpp from JSON
 """
 import argparse
@@ -39,7 +41,7 @@ MANIFEST = os.path.join(TUNE_DIR, "manifest.json")
 TUNED_JSON = os.path.join(PKG, "tuned_schedules.json")
 TUNED_HPP = os.path.join(PKG, "csrc", "tuned.hpp")
 
-GRIDS = (64, 128, 256, 512)
+GRIDS = (64, 128, 256, 512, 1024)
 PRECISIONS = ("fp32", "fp64")
 KINDS = ("bin", "inv_y", "inv_z_gather", "like", "fwd_z_scatter", "fwd_y", "fwd_x")
 FFT_KINDS = ("inv_y", "inv_z_gather", "fwd_z_scatter", "fwd_y", "fwd_x")
@@ -49,7 +51,7 @@ PARAMS = {
     "X": ("HAMLET_SCHED_X", (256, 512, 1024), "threads_x", ("fwd_x",)),
     "ZG": ("HAMLET_SCHED_ZG", (128, 256, 512), "threads_gather", ("inv_z_gather",)),
     "ZS": ("HAMLET_SCHED_ZS", (128, 256, 512), "threads_scatter", ("fwd_z_scatter",)),
-    "W": ("HAMLET_SCHED_W_SHIFT", (-1, 1), "tile_width", ("inv_y", "fwd_y", "fwd_x")),
+    "W": ("HAMLET_SCHED_W_SHIFT", (-1, 1, 2), "tile_width", ("inv_y", "fwd_y", "fwd_x")),
     "PZ": ("HAMLET_SCHED_PZ_SHIFT", (-1, 1), "pencils_scatter", ("fwd_z_scatter",)),
     "PG": ("HAMLET_SCHED_PG_SHIFT", (-1, 1), "pencils_gather", ("inv_z_gather",)),
     "RADIX": ("HAMLET_SCHED_RADIX", None, "radix_plan", FFT_KINDS),
@@ -60,6 +62,12 @@ FIELD_MEMBER = {"threads_xy": "XY", "threads_x": "X", "threads_gather": "ZG", "t
 MARGIN = 0.03          # a change must gain at least this fraction of the deciding kernels' time
 EPS = 0.001            # leapfrog step of the timed trajectories (well inside the stable range)
 ITER, LEAP, REPS = 3, 10, 2
+
+
+def trajectory(n):
+    """(iterations, leapfrog steps) of each timed run: shorter at 1024^3,
+    where one gradient takes tens of milliseconds."""
+    return (1, 5) if n >= 1024 else (ITER, LEAP)
 SEED = 20220304
 
 
@@ -68,19 +76,24 @@ def radix_plans(n):
     return {16: 2, 32: 3, 64: 3, 128: 3, 256: 4, 512: 3}.get(n, 1)
 
 
-def candidates(grids):
+def candidates(grids, refine=False):
+    """One-parameter moves from the defaults, or (refine) from the schedule
+    the committed tuned.hpp holds: a second sweep catches parameters whose
+    best value moved once the others were chosen."""
     out = []
     for n in grids:
-        base = ["HAMLET_ONLY_N=%d" % n, "HAMLET_SCHED_DEFAULTS"]
-        out.append({"name": "n%d_default" % n, "n": n, "param": None, "value": None, "defines": base})
+        base = ["HAMLET_ONLY_N=%d" % n] + ([] if refine else ["HAMLET_SCHED_DEFAULTS"])
+        pre = "n%d_%s" % (n, "r" if refine else "")
+        out.append({"name": pre + ("tuned" if refine else "default"), "n": n, "param": None, "value": None,
+                    "defines": base})
         for param, (macro, values, _field, _kinds) in PARAMS.items():
             if values is None:
-                values = range(1, radix_plans(n))
+                values = range(0 if refine else 1, radix_plans(n))
             for v in values:
-                if param in ("XY", "X", "ZG", "ZS") and v == default_threads(param, n):
+                if not refine and param in ("XY", "X", "ZG", "ZS") and v == default_threads(param, n):
                     continue
                 tag = ("m%d" % -v) if v < 0 else str(v)
-                out.append({"name": "n%d_%s%s" % (n, param, tag), "n": n, "param": param, "value": v,
+                out.append({"name": pre + "%s%s" % (param, tag), "n": n, "param": param, "value": v,
                             "defines": base + ["%s=%d" % (macro, v)]})
     for c in out:
         c["lib"] = os.path.join("_build", "tune", c["name"] + ".so")
@@ -96,7 +109,8 @@ def default_threads(param, n):
 def cmd_build(args):
     from . import build
     os.makedirs(TUNE_DIR, exist_ok=True)
-    cands = candidates(args.grids)
+    cands = [c for c in candidates(args.grids, args.refine) if c["param"] is None or not args.params
+             or c["param"] in args.params]
 
     def one(c):
         t = time.time()
@@ -151,7 +165,10 @@ def measure(n, ref_path, save_ref, precisions):
         q, qd, qs = start()
         g, gd, gs, psi = plan.zeros_modes(), plan.zeros_dist(), plan.scalar(), plan.scalar()
         hamlet.logpost_grad([plan], [q], [qd], [qs], [g], [gd], [gs], [psi])
-        gn = g.cpu().numpy()
+        # the mode gradient on a fixed strided sample of at most 4M entries
+        flat = g.reshape(-1)
+        gn = flat[:: max(1, flat.numel() >> 22)].cpu().numpy()
+        del flat
         gdn = gd.cpu().numpy()
         psin = float(psi.item())
         entry = {"schedule": hamlet.schedule(n, prec)}
@@ -170,8 +187,9 @@ def measure(n, ref_path, save_ref, precisions):
             entry["ok"] = all(err[k] <= tol[k] for k in err)
         # warm-up trajectory, then each kernel kind timed over ITER
         # trajectories of LEAP steps, REPS times (the fastest is kept)
+        n_it, n_lf = trajectory(n)
         q, qd, qs = start()
-        hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=1, n_leapfrog=LEAP, eps0=EPS, seed=SEED, want_eps=False)
+        hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=1, n_leapfrog=n_lf, eps0=EPS, seed=SEED, want_eps=False)
         kinds = {}
         for _ in range(REPS):
             for kind in KINDS:
@@ -179,18 +197,18 @@ def measure(n, ref_path, save_ref, precisions):
                 timer = hamlet.KernelTimer(plan, hamlet.PROFILE_KERNELS[kind])
                 torch.cuda.synchronize()
                 timer.start()
-                hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=ITER, n_leapfrog=LEAP, eps0=EPS, seed=SEED,
+                hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=n_it, n_leapfrog=n_lf, eps0=EPS, seed=SEED,
                                want_eps=False)
                 ms, launches = timer.stop()
-                per = ms / (ITER * LEAP)
+                per = ms / (n_it * n_lf)
                 kinds[kind] = min(kinds.get(kind, float("inf")), per)
         # the whole gradient, wall clock (no events armed)
         q, qd, qs = start()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=ITER, n_leapfrog=LEAP, eps0=EPS, seed=SEED, want_eps=False)
+        hamlet.hmc_run([plan], [q], [qd], [qs], n_iter=n_it, n_leapfrog=n_lf, eps0=EPS, seed=SEED, want_eps=False)
         torch.cuda.synchronize()
-        entry["wall_ms_per_grad"] = round((time.perf_counter() - t) * 1e3 / (ITER * LEAP), 5)
+        entry["wall_ms_per_grad"] = round((time.perf_counter() - t) * 1e3 / (n_it * n_lf), 5)
         entry["kinds_ms_per_grad"] = {k: round(v, 5) for k, v in kinds.items()}
         entry["kernel_ms_per_grad"] = round(sum(kinds.values()), 5)
         res["precisions"][prec] = entry
@@ -256,8 +274,12 @@ def cmd_time(args):
 # -- selection (CPU) -------------------------------------------------------------
 
 def select(results, margin=MARGIN):
-    """Per (precision, grid): the default schedule with every one-parameter
-    change that gains more than `margin` on the kernels it shapes."""
+    """Per (precision, grid): the base schedule (the defaults, or the tuned
+    one in a refinement sweep) with the one-parameter changes that gain more
+    than `margin` on the kernels they shape.  Changes are taken in order of
+    their gain, and one that shapes a kernel an earlier change shaped is left
+    out: each was timed against the base alone, so only changes to disjoint
+    kernels are known to add up."""
     chosen, gains = {}, {}
     by_n = {}
     for r in results:
@@ -272,7 +294,7 @@ def select(results, margin=MARGIN):
                 continue
             b = base["precisions"][prec]
             sched = {k: v for k, v in b["schedule"].items() if k != "radix"}
-            g = {}
+            moves = []
             for param, (_macro, _values, field, kinds) in PARAMS.items():
                 def cost(e):
                     return sum(e["kinds_ms_per_grad"][k] for k in kinds)
@@ -282,14 +304,20 @@ def select(results, margin=MARGIN):
                     if r["param"] != param or e is None or not e.get("ok", False):
                         continue
                     if e["schedule"][field] == b["schedule"][field]:
-                        continue   # clamped back to the default
+                        continue   # clamped back to the base value
                     if cost(e) < best_cost:
                         best, best_cost = e, cost(e)
                 if best is not None and best_cost < (1.0 - margin) * cost(b):
-                    sched[field] = best["schedule"][field]
-                    g[param] = {"value": best["schedule"][field], "default": b["schedule"][field],
-                                "kernels": list(kinds), "ms_per_grad": round(best_cost, 5),
-                                "default_ms_per_grad": round(cost(b), 5)}
+                    moves.append((cost(b) - best_cost, param, field, kinds, best, best_cost, cost(b)))
+            g, shaped = {}, set()
+            for gain, param, field, kinds, best, best_cost, base_cost in sorted(moves, key=lambda m: -m[0]):
+                if shaped & set(kinds):
+                    continue
+                shaped |= set(kinds)
+                sched[field] = best["schedule"][field]
+                g[param] = {"value": best["schedule"][field], "default": b["schedule"][field],
+                            "kernels": list(kinds), "ms_per_grad": round(best_cost, 5),
+                            "default_ms_per_grad": round(base_cost, 5)}
             chosen.setdefault(prec, {})[str(n)] = sched
             gains.setdefault(prec, {})[str(n)] = g
     return chosen, gains
@@ -325,6 +353,27 @@ def cmd_select(args):
         meta = {k: d[k] for k in ("device", "eps", "iterations", "leapfrog", "reps")}
     chosen, gains = select(results)
     defaults = {}
+    if args.refine:
+        # a sweep from the tuned schedules: merge into the committed choice,
+        # whose defaults stay the hand-picked schedules
+        with open(TUNED_JSON) as f:
+            old = json.load(f)
+        defaults = old["defaults"]
+        for prec, per_n in chosen.items():
+            for n, sched in per_n.items():
+                old["schedules"].setdefault(prec, {})[n] = sched
+                old.setdefault("refined", {}).setdefault(prec, {})[n] = gains[prec][n]
+        old["timings"] += [{"name": r["name"], **{p: {"kernel_ms_per_grad": e["kernel_ms_per_grad"],
+                                                      "kinds_ms_per_grad": e["kinds_ms_per_grad"]}
+                                                  for p, e in r["precisions"].items()}} for r in results]
+        with open(TUNED_JSON, "w") as f:
+            json.dump(old, f, indent=1)
+        write_header(old["schedules"], defaults)
+        for prec in PRECISIONS:
+            for n, g in sorted(gains.get(prec, {}).items(), key=lambda kv: int(kv[0])):
+                print(prec, n, "refined:", {k: (v["default"], "->", v["value"]) for k, v in g.items()})
+        print("merged into", TUNED_JSON, "and wrote", TUNED_HPP)
+        return
     for r in results:
         if r["param"] is None:
             for prec, e in r["precisions"].items():
@@ -390,6 +439,8 @@ def main(argv=None):
     b = sub.add_parser("build")
     b.add_argument("--grids", type=int, nargs="+", default=list(GRIDS))
     b.add_argument("--jobs", type=int, default=4)
+    b.add_argument("--refine", action="store_true", help="moves from the tuned schedules, not the defaults")
+    b.add_argument("--params", nargs="+", default=None, help="only these parameters (%s)" % ", ".join(PARAMS))
     t = sub.add_parser("time")
     t.add_argument("--out", required=True)
     t.add_argument("--grids", type=int, nargs="+", default=list(GRIDS))
@@ -403,6 +454,7 @@ def main(argv=None):
     m.add_argument("--precisions", nargs="+", default=list(PRECISIONS))
     s = sub.add_parser("select")
     s.add_argument("files", nargs="+")
+    s.add_argument("--refine", action="store_true", help="merge a sweep from the tuned schedules")
     v = sub.add_parser("verify")
     v.add_argument("file")
     sub.add_parser("header")

@@ -86,26 +86,33 @@ def test_selection_takes_gains_above_the_margin_only():
         _result("x", 256, "X", 1024, {"fp32": (with_(threads_x=1024), times(fwd_x=0.27))}, kinds),
         # the scatter 1% faster: inside the margin, not taken
         _result("zs", 256, "ZS", 512, {"fp32": (with_(threads_scatter=512), times(fwd_z_scatter=0.297))}, kinds),
+        # the scatter 10% faster with 4-pencil tiles (kernels disjoint from the x pass): taken
+        _result("pz", 256, "PZ", -1, {"fp32": (with_(pencils_scatter=4), times(fwd_z_scatter=0.27))}, kinds),
         # the gather much faster but the gradient differs: rejected
         _result("pg", 256, "PG", 1, {"fp32": (with_(pencils_gather=16), times(inv_z_gather=0.1))}, kinds, ok=False),
         # a shift clamped back to the default schedule: ignored
         _result("w", 256, "W", 1, {"fp32": (BASE, times(inv_y=0.05))}, kinds),
-        # faster y passes but a slower x pass under a wider tile: the deciding
-        # kernels (y passes and x pass) sum to more, not taken
-        _result("w2", 256, "W", -1, {"fp32": (with_(tile_width=8), times(inv_y=0.08, fwd_y=0.08, fwd_x=0.4))},
+        # a narrower tile: faster y passes and x pass (5% on them), but it
+        # shapes the x pass, which the larger gain above already changed
+        _result("w2", 256, "W", -1, {"fp32": (with_(tile_width=8), times(inv_y=0.095, fwd_y=0.095, fwd_x=0.285))},
                 kinds),
-        # a radix plan faster over the transforms as a whole: taken
-        _result("r", 256, "RADIX", 2, {"fp32": (with_(radix_plan=2, radix="16x4x4"),
-                                                times(inv_y=0.08, fwd_y=0.08, fwd_x=0.28))}, kinds),
     ]
     chosen, gains = autotune.select(res)
     s = chosen["fp32"]["256"]
     assert s["threads_x"] == 1024
     assert s["threads_scatter"] == 256
+    assert s["pencils_scatter"] == 4
     assert s["pencils_gather"] == 8
     assert s["tile_width"] == 16
-    assert s["radix_plan"] == 2
-    assert set(gains["fp32"]["256"]) == {"X", "RADIX"}
+    assert set(gains["fp32"]["256"]) == {"X", "PZ"}
+    # a radix plan faster over the transforms as a whole shapes every
+    # transform kernel: with the larger gain it is taken alone
+    res.append(_result("r", 256, "RADIX", 2, {"fp32": (with_(radix_plan=2, radix="16x4x4"),
+                                                       times(inv_y=0.08, fwd_y=0.08, fwd_x=0.26))}, kinds))
+    chosen, gains = autotune.select(res)
+    s = chosen["fp32"]["256"]
+    assert s["radix_plan"] == 2 and s["threads_x"] == 512 and s["pencils_scatter"] == 8
+    assert set(gains["fp32"]["256"]) == {"RADIX"}
 
 
 def test_header_lists_only_changed_fields(tmp_path, monkeypatch):
