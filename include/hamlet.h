@@ -88,21 +88,25 @@ typedef struct {
   double hist_width;        /* bin width of the distance prior (eq:D), Mpc/h; <= 0: 5 */
   int32_t sample_distances; /* 0: distances frozen (no momentum) */
   int32_t sample_sigma_nl;  /* 0: s frozen */
-  int32_t sample_cosmology; /* 1: sigma_8 and f sampled with the field (Section 6, item 3), see below */
+  int32_t sample_cosmology; /* 1: h, sigma_8 and f sampled with the field (Section 6, item 3), see below */
 } hamlet_plan_desc;
 
-/* Cosmological parameters in q.  With sample_cosmology = 1 the state has two
- * more coordinates after s: u8 = sigma_8 / sigma_8,fid, which scales P(k)
- * (pk_n2) by u8^2, and phi = f / f_fid, which scales f_growth.  Both have
- * flat priors on (0, inf) (Psi = +inf elsewhere); the prior of the modes is
- * the normalised Gaussian of variance u8^2 sigma_k^2, so Psi gains
- * E (1/u8^2 - 1) + D ln u8 (E the prior energy at u8 = 1, D = (N-1)^3 - 1
- * real mode coordinates), and dPsi/dphi = sum_i (dPsi/du_i) u_i / phi.
- * Inverse masses: 1 / (2 D) for u8, 1 / max(n, 1) for phi.  Every "snl"
- * buffer of such a plan (q_snl, g_snl, p_snl, the s of hamlet_hmc_run and
- * hamlet_nuts_run) then holds 3 doubles (s, u8, phi) and the flat vector 2m +
- * n + 3 entries; the field, density and statistics entry points use the
- * fiducial f.  A served job with sampled cosmology starts at u8 = phi = 1
+/* Cosmological parameters in q.  With sample_cosmology = 1 the state has
+ * three more coordinates after s: u8 = sigma_8 / sigma_8,fid, which scales
+ * P(k) (pk_n2) by u8^2, phi = f / f_fid, which scales f_growth, and
+ * eta = h / h_fid, which scales h.  All three have flat priors on (0, inf)
+ * (Psi = +inf elsewhere); the prior of the modes is the normalised Gaussian
+ * of variance u8^2 sigma_k^2, so Psi gains E (1/u8^2 - 1) + D ln u8 (E the
+ * prior energy at u8 = 1, D = (N-1)^3 - 1 real mode coordinates), and
+ * dPsi/dphi = sum_i (dPsi/du_i) u_i / phi.  With distances in Mpc/h, h
+ * enters only the distance modulus, mu(d) = 5 log10(d_L / (eta h)) + 25, so
+ * dPsi/deta = sum_i (dmu_i / sigma_mu,i^2) 5 / (eta ln 10).  Inverse masses:
+ * 1 / (2 D) for u8, 1 / max(n, 1) for phi, 1 / sum_i (5 / ln 10)^2 /
+ * sigma_mu,i^2 for eta (1 without points).  Every "snl" buffer of such a plan
+ * (q_snl, g_snl, p_snl, the s of hamlet_hmc_run and hamlet_nuts_run) then
+ * holds 4 doubles (s, u8, phi, eta) and the flat vector 2m + n + 4 entries;
+ * the field, density and statistics entry points use the fiducial f.  A
+ * served job with sampled cosmology starts at u8 = phi = eta = 1
  * (hamlet_server_take returns s only). */
 
 /* Catalogue (Section 2, Section 5.1): n points, host arrays of length n.
@@ -269,7 +273,7 @@ hamlet_status hamlet_nuts_run(hamlet_plan* const* plans, int32_t n_plans, const 
  * (G = dPsi/dRe + i dPsi/dIm per independent coordinate, dPsi/dd, dPsi/ds)
  * packing gives dPsi/dq in the same order. */
 
-/* Length 2m + n + 1 (+2 with sampled cosmology) of the plan's flat vector
+/* Length 2m + n + 1 (+3 with sampled cosmology) of the plan's flat vector
  * (host only). */
 hamlet_status hamlet_flat_size(const hamlet_plan* plan, int64_t* n_flat);
 

@@ -87,17 +87,17 @@ def unpack_modes(n, vec):
 def pack_state(n, modes, dist, s, cosmo=None):
     """The whole flat parameter vector of Section 3.1 (eq:q): Re and Im of
     the independent modes, then the n distances, then s = sigma_NL/100 (and
-    u8, phi when the cosmological parameters are sampled)."""
+    u8, phi, eta when the cosmological parameters are sampled)."""
     tail = [float(s)] + ([] if cosmo is None else [float(c) for c in cosmo])
     return np.concatenate([pack_modes(n, modes), np.asarray(dist, dtype=float), tail])
 
 
 def unpack_state(n, vec, n_gal, cosmo=False):
     """Inverse of pack_state: (modes with mirror entries filled, dist, s[,
-    (u8, phi)])."""
+    (u8, phi, eta)])."""
     m2 = (n - 1) ** 3 - 1
     vec = np.asarray(vec, dtype=float)
-    assert vec.size == m2 + n_gal + (3 if cosmo else 1)
+    assert vec.size == m2 + n_gal + (4 if cosmo else 1)
     out = (unpack_modes(n, vec[:m2]), vec[m2:m2 + n_gal].copy(), float(vec[m2 + n_gal]))
     return out + (vec[m2 + n_gal + 1:].copy(),) if cosmo else out
 
@@ -111,7 +111,7 @@ class State:
     modes: np.ndarray     # complex (N, N, N/2+1)
     dist: np.ndarray      # (n,)
     s: float              # sigma_NL / 100 km/s
-    cosmo: np.ndarray = None   # (u8, phi) when the cosmological parameters are sampled
+    cosmo: np.ndarray = None   # (u8, phi, eta) when the cosmological parameters are sampled
 
     def copy(self):
         return State(self.modes.copy(), self.dist.copy(), float(self.s),
@@ -128,13 +128,17 @@ def inverse_mass(prob):
 
 
 def cosmo_inverse_mass(prob):
-    """M^-1 of (u8, phi) (a reading; eq:M_ab has no such coordinates): the
-    inverse curvature of the prior in u8 at the fiducial amplitude, 1 / (2 D)
-    with D real mode coordinates, and 1 / n for phi (each point carries
-    information of order one on the amplitude of its velocity)."""
+    """M^-1 of (u8, phi, eta) (a reading; eq:M_ab has no such coordinates):
+    the inverse curvature of the prior in u8 at the fiducial amplitude,
+    1 / (2 D) with D real mode coordinates; 1 / n for phi (each point carries
+    information of order one on the amplitude of its velocity); and for eta
+    the inverse curvature of the distance-modulus terms at eta = 1 with the
+    distances held, 1 / sum_i (5 / ln 10)^2 / sigma_mu,i^2 (1 without points)."""
     if not prob.sample_cosmology:
-        return np.zeros(2)
-    return np.array([1.0 / (2.0 * model_mode_dof(prob.n_grid)), 1.0 / max(prob.n_gal, 1)])
+        return np.zeros(3)
+    c = (5.0 / math.log(10.0)) ** 2
+    curv = float(np.sum(c / np.asarray(prob.sigma_mu, dtype=float) ** 2)) if prob.n_gal > 0 else 1.0
+    return np.array([1.0 / (2.0 * model_mode_dof(prob.n_grid)), 1.0 / max(prob.n_gal, 1), 1.0 / curv])
 
 
 def draw_momenta(prob, seed, iteration):
@@ -168,8 +172,9 @@ def draw_momenta(prob, seed, iteration):
         ps = 0.0
     pc = None
     if prob.sample_cosmology:
-        z0, z1 = philox.normal_pair(philox.draw_words(seed, iteration, philox.PURPOSE_COSMO, [0]))
-        pc = np.array([float(z0[0]), float(z1[0])]) / np.sqrt(cosmo_inverse_mass(prob))
+        # u8 and phi from the pair at index 0, eta from the first of index 1
+        z0, z1 = philox.normal_pair(philox.draw_words(seed, iteration, philox.PURPOSE_COSMO, [0, 1]))
+        pc = np.array([float(z0[0]), float(z1[0]), float(z0[1])]) / np.sqrt(cosmo_inverse_mass(prob))
     return State(pm, pd, ps, pc)
 
 
@@ -189,7 +194,7 @@ def kinetic(prob, p):
 
 
 def gradient(prob, q):
-    """(Psi, dPsi/dmodes, dPsi/dd, dPsi/ds, dPsi/d(u8, phi) or None) at q."""
+    """(Psi, dPsi/dmodes, dPsi/dd, dPsi/ds, dPsi/d(u8, phi, eta) or None) at q."""
     if prob.sample_cosmology:
         return logpost_grad(prob, q.modes, q.dist, q.s, cosmo=q.cosmo)
     return logpost_grad(prob, q.modes, q.dist, q.s) + (None,)

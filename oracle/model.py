@@ -40,14 +40,18 @@ Readings of the paper used here (each is also listed in the design notes):
     terms rounded once (math.fsum): the Metropolis test takes the difference
     of two such totals of millions of terms, and an exactly rounded sum is
     the plain definition, free of any summation order.
-  * Cosmological parameters in q (Section 6, item 3: sigma_8 and the growth
-    rate estimated with the field).  With `sample_cosmology` two more
-    coordinates join s: u8 = sigma_8 / sigma_8,fid, which scales P(k) by
-    u8^2, and phi = f / f_fid, which scales the velocity multiplier.  Both
-    have flat priors on (0, inf) (Psi = +inf elsewhere).  The prior of the
-    modes is then the normalised Gaussian of variance u8^2 sigma_k^2, whose
-    u8-dependent part is E / u8^2 + D ln u8 with E the fiducial prior
-    energy and D = (N-1)^3 - 1 the number of real mode coordinates.
+  * Cosmological parameters in q (Section 6, item 3: H0, sigma_8 and the
+    growth rate estimated with the field).  With `sample_cosmology` three
+    more coordinates join s: u8 = sigma_8 / sigma_8,fid, which scales P(k)
+    by u8^2, phi = f / f_fid, which scales the velocity multiplier, and
+    eta = h / h_fid.  All three have flat priors on (0, inf) (Psi = +inf
+    elsewhere).  The prior of the modes is then the normalised Gaussian of
+    variance u8^2 sigma_k^2, whose u8-dependent part is E / u8^2 + D ln u8
+    with E the fiducial prior energy and D = (N-1)^3 - 1 the number of real
+    mode coordinates.  With distances in Mpc/h and H0 = 100 h km/s/Mpc, h
+    enters only the distance modulus (d_L / h in Mpc): mu(d) moves by
+    -5 log10 eta, the zero point of every distance modulus at once
+    (Section 6, item 4's calibration by a Hubble parameter).
 """
 import math
 from dataclasses import dataclass, field
@@ -490,19 +494,21 @@ def prior_energy(prob, dhat, u8=1.0):
 
 
 def _cosmo(prob, cosmo):
-    """(u8, phi) of a state: the fiducial (1, 1) unless the problem samples them."""
+    """(u8, phi, eta) of a state: the fiducial (1, 1, 1) unless the problem
+    samples them."""
     if not prob.sample_cosmology or cosmo is None:
-        return 1.0, 1.0
-    return float(cosmo[0]), float(cosmo[1])
+        return 1.0, 1.0, 1.0
+    return float(cosmo[0]), float(cosmo[1]), float(cosmo[2])
 
 
-def galaxy_terms(prob, d, s, u):
-    """Per-galaxy pieces of Psi: returns dict of arrays (all FP64)."""
+def galaxy_terms(prob, d, s, u, eta=1.0):
+    """Per-galaxy pieces of Psi: returns dict of arrays (all FP64); eta =
+    h / h_fid."""
     om = prob.omega_m
     zb = zbar(d, om)
     snl = SIGMA_NL_UNIT * s
     kappa2 = snl * snl + prob.sigma_cz ** 2 / (1.0 + zb) ** 2
-    dmu = prob.mu - distance_modulus(d, om, prob.h)
+    dmu = prob.mu - distance_modulus(d, om, prob.h * eta)
     r = v_obs(prob.cz, d, om) - u
     psi = (dmu * dmu / (2.0 * prob.sigma_mu ** 2) + r * r / (2.0 * kappa2)
            + 0.5 * np.log(kappa2) - prob.hist.log_density(d))
@@ -510,15 +516,15 @@ def galaxy_terms(prob, d, s, u):
 
 
 def logpost(prob, dhat, d, s, cosmo=None):
-    """Psi(q) = -ln Pi(q) up to constants (eq:Psi); cosmo = (u8, phi) when the
-    problem samples the cosmological parameters."""
+    """Psi(q) = -ln Pi(q) up to constants (eq:Psi); cosmo = (u8, phi, eta)
+    when the problem samples the cosmological parameters."""
     d = np.asarray(d, dtype=np.float64)
-    u8, phi = _cosmo(prob, cosmo)
-    if not np.all(in_domain(prob, d)) or not (u8 > 0.0 and phi > 0.0):
+    u8, phi, eta = _cosmo(prob, cosmo)
+    if not np.all(in_domain(prob, d)) or not (u8 > 0.0 and phi > 0.0 and eta > 0.0):
         return math.inf
     v = velocity_grids(prob, dhat, phi)
     u, _ = cic_gather(prob, v, d)
-    terms = galaxy_terms(prob, d, s, u)
+    terms = galaxy_terms(prob, d, s, u, eta)
     total = exact_sum(np.concatenate([[prior_energy(prob, dhat, u8)], terms["psi"]]))
     return total if np.isfinite(total) else math.inf
 
@@ -530,19 +536,21 @@ def logpost_grad(prob, dhat, d, s, cosmo=None):
     the complex convention G_k = dPsi/dRe dhat_k + i dPsi/dIm dhat_k, taken
     with respect to the independent coordinates of each mode (on the kz = 0
     plane the stored partner carries the conjugate).  When the problem
-    samples the cosmological parameters, cosmo = (u8, phi) and a fifth entry
-    (dPsi/du8, dPsi/dphi) follows:
+    samples the cosmological parameters, cosmo = (u8, phi, eta) and a fifth
+    entry (dPsi/du8, dPsi/dphi, dPsi/deta) follows:
         dPsi/du8 = -2 E / u8^3 + D / u8      (the prior; E at u8 = 1)
         dPsi/dphi = sum_i g_i u_i / phi      (u_i is linear in phi)
+        dPsi/deta = sum_i (dmu_i / sigma_mu,i^2) 5 / (eta ln 10)
+                                             (mu_i(d) moves by -5 log10 eta)
     """
     n = prob.n_grid
     d = np.asarray(d, dtype=np.float64)
     ok = in_domain(prob, d)
     dsafe = np.where(ok, d, 1.0)
-    u8, phi = _cosmo(prob, cosmo)
+    u8, phi, eta = _cosmo(prob, cosmo)
     v = velocity_grids(prob, dhat, phi)
     u, du = cic_gather(prob, v, dsafe)
-    t = galaxy_terms(prob, dsafe, s, u)
+    t = galaxy_terms(prob, dsafe, s, u, eta if eta > 0.0 else 1.0)
     om = prob.omega_m
     kappa2, r = t["kappa2"], t["r"]
     zb = t["zbar"]
@@ -561,7 +569,7 @@ def logpost_grad(prob, dhat, d, s, cosmo=None):
     safe = np.where(var > 0, var, 1.0)
     g_modes = np.where(var > 0, 2.0 * dhat / (u8 * u8 * safe), 0.0).astype(np.complex128)
     g_modes += modes_adjoint(prob, dsafe, g, phi)
-    good = np.all(ok) and u8 > 0.0 and phi > 0.0
+    good = np.all(ok) and u8 > 0.0 and phi > 0.0 and eta > 0.0
     psi = exact_sum(np.concatenate([[prior_energy(prob, dhat, u8)], t["psi"]])) if good else math.inf
     if not (good and np.isfinite(psi)):
         psi = math.inf
@@ -570,4 +578,5 @@ def logpost_grad(prob, dhat, d, s, cosmo=None):
     e = prior_energy(prob, dhat)
     g_u8 = -2.0 * e / u8 ** 3 + mode_dof(n) / u8
     g_phi = exact_sum(g * u) / phi
-    return psi, g_modes, g_d, g_s, np.array([g_u8, g_phi])
+    g_eta = exact_sum(t["dmu"] / prob.sigma_mu ** 2) * 5.0 / (eta * math.log(10.0))
+    return psi, g_modes, g_d, g_s, np.array([g_u8, g_phi, g_eta])

@@ -42,7 +42,8 @@ PURPOSE_JITTER = 4
 PURPOSE_NUTS_DIR = 5
 PURPOSE_NUTS_MERGE = 6
 PURPOSE_NUTS_TOP = 7
-# momenta of the cosmological coordinates (index 0: the pair (u8, phi))
+# momenta of the cosmological coordinates (index 0: the pair (u8, phi);
+# index 1: eta from the first of its pair)
 PURPOSE_COSMO = 8
 
 

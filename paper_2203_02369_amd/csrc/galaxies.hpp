@@ -22,9 +22,10 @@ struct Catalogue {
 };
 
 struct Cosmo {
-  double om, h;            // Omega_0, little h (for mu)
+  double om, h;            // Omega_0, little h (for mu; times eta when sampled)
   double box, spacing;     // L, L / N
   double dmax;             // c / (3 Omega_0 H0): domain of zbar(d)
+  int sample_c;            // eta = h / h_fid is the fourth small coordinate
 };
 
 // Optional leapfrog update of a block of coordinates right after their
@@ -233,7 +234,8 @@ struct BinNext {
 };
 
 // Values per block of the likelihood's partial sums: Psi, dPsi/ds, invalid
-// distances, a slice of the prior partials, sum g_i u_i (for dPsi/dphi).
+// distances, a slice of the prior partials, sum g_i u_i (for dPsi/dphi),
+// sum dmu_i / sigma_mu,i^2 (for dPsi/deta).
 constexpr int kLikeVals = 8;
 
 struct LikeOut {
@@ -249,9 +251,9 @@ __device__ __forceinline__ void
 like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, const double* __restrict__ frac,
           double* __restrict__ dist, const double* snl_q, Catalogue cat, Cosmo cm, T* __restrict__ gsort,
           LikeOut out, LeapUpdate lf, const BinNext* next) {
-  __shared__ double red[2 * 5 * (kGalThreads / 64)];
+  __shared__ double red[2 * 6 * (kGalThreads / 64)];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double psi = 0.0, dps = 0.0, bad = 0.0, gu = 0.0;
+  double psi = 0.0, dps = 0.0, bad = 0.0, gu = 0.0, dmw = 0.0;
   if (i < cat.n) {
     const int s = bpos[i];
     const double tx = frac[3 * i], ty = frac[3 * i + 1];
@@ -280,7 +282,9 @@ like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, cons
     const double scz = cat.sigma_cz[i];
     const double snl = kSigmaNlUnit * sv;
     const double kappa2 = snl * snl + scz * scz / (opz * opz);
-    const double mu_d = 5.0 * log10(d * opz / cm.h) + 25.0;
+    // h = eta h_fid when sampled: d_L / h in Mpc
+    const double hh = cm.sample_c ? cm.h * snl_q[3] : cm.h;
+    const double mu_d = 5.0 * log10(d * opz / hh) + 25.0;
     const double mup = (5.0 / log(10.0)) * (opz + d * zbp) / (d * opz);
     const double smu = cat.sigma_mu[i];
     const double dmu = cat.mu[i] - mu_d;
@@ -300,6 +304,7 @@ like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, cons
     out.g_dist[i] = gd;
     gsort[s] = (T)(-r / kappa2);
     gu = (-r / kappa2) * u;   // u is linear in the growth rate: dPsi/dphi = sum g u / phi
+    dmw = dmu / (smu * smu);  // mu(d) moves by -5 log10 eta: dPsi/deta = sum dmw 5 / (eta ln 10)
     if (lf.p) {
       const double e = lf.eps[0];
       const double pv = lf.p[i] - lf.kick * e * gd;
@@ -312,43 +317,45 @@ like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, cons
   // this block's slice of the prior partials
   const int per = (out.n_prior + out.n_blocks - 1) / out.n_blocks;
   const int lo = blockIdx.x * per, hi = min(out.n_prior, lo + per);
-  CSum sums[5];
+  CSum sums[6];
   sums[0].add(psi);
   sums[1].add(dps);
   sums[2].add(bad);
   for (int j = lo + threadIdx.x; j < hi; j += blockDim.x) sums[3].add(out.prior_part[j]);
   sums[4].add(gu);
+  sums[5].add(dmw);
   block_csums(sums, red);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) out.part[kLikeVals * blockIdx.x + v] = sums[v].value();
+    for (int v = 0; v < 6; ++v) out.part[kLikeVals * blockIdx.x + v] = sums[v].value();
   }
 }
 
 // The small coordinates at the final sums: where they are, their momenta and
 // gradient, and the leapfrog update of them once the gradient is known.
 struct SmallState {
-  double* q;            // s, and u8, phi when sampled
+  double* q;            // s, and u8, phi, eta when sampled
   double* p;            // momenta, or nullptr: no update
-  double* g;            // dPsi/d(s, u8, phi) out
+  double* g;            // dPsi/d(s, u8, phi, eta) out
   double* cosmo_eval;   // u8 and phi of this evaluation, kept for the adjoint pass
   const double* eps;
   double kick;          // 1 for merged half kicks, 0.5 for the last half kick
   int drift;
   int sample_s, sample_c;
-  double minv_u8, minv_phi, d_modes;
+  double minv_u8, minv_phi, minv_eta, d_modes;
 };
 
 // Final deterministic sums (compensated): Psi = prior + sum of galaxy terms
 // (+inf when a distance left the domain or Psi is not finite); dPsi/ds.
-// With u8 and phi sampled the prior is E / u8^2 + D ln u8 (E the fiducial
-// prior energy, D real mode coordinates), dPsi/du8 = -2 E / u8^3 + D / u8,
-// dPsi/dphi = sum g_i u_i / phi, and Psi = +inf unless u8, phi > 0.
+// With u8, phi and eta sampled the prior is E / u8^2 + D ln u8 (E the
+// fiducial prior energy, D real mode coordinates), dPsi/du8 = -2 E / u8^3 +
+// D / u8, dPsi/dphi = sum g_i u_i / phi, dPsi/deta = sum (dmu_i /
+// sigma_mu,i^2) 5 / (eta ln 10), and Psi = +inf unless u8, phi, eta > 0.
 __device__ __forceinline__ void
 finalize_body(const double* __restrict__ prior_part, int n_prior, const double* __restrict__ like_part, int n_like,
               double* __restrict__ psi_out, const SmallState& sm) {
-  __shared__ double red[2 * 5 * 4];   // blocks of up to 256 threads
-  CSum sums[5];                       // prior, galaxy terms, dPsi/ds, invalid, sum g u
+  __shared__ double red[2 * 6 * 4];   // blocks of up to 256 threads
+  CSum sums[6];                       // prior, galaxy terms, dPsi/ds, invalid, sum g u, sum dmu / sigma^2
   for (int i = threadIdx.x; i < n_prior; i += blockDim.x) sums[0].add(prior_part[i]);
   for (int i = threadIdx.x; i < n_like; i += blockDim.x) {
     const double* lp = like_part + (size_t)kLikeVals * i;
@@ -357,19 +364,21 @@ finalize_body(const double* __restrict__ prior_part, int n_prior, const double* 
     sums[2].add(lp[1]);
     sums[3].add(lp[2]);
     sums[4].add(lp[4]);
+    sums[5].add(lp[5]);
   }
   block_csums(sums, red);
   if (threadIdx.x != 0) return;
   const double e = sums[0].value();
   double psi;
   bool ok = sums[3].value() == 0.0;
-  double g[kSmallMax] = {sums[2].value(), 0.0, 0.0};
+  double g[kSmallMax] = {sums[2].value(), 0.0, 0.0, 0.0};
   if (sm.sample_c) {
-    const double u8 = sm.q[1], phi = sm.q[2];
-    ok = ok && u8 > 0.0 && phi > 0.0;
+    const double u8 = sm.q[1], phi = sm.q[2], eta = sm.q[3];
+    ok = ok && u8 > 0.0 && phi > 0.0 && eta > 0.0;
     psi = e / (u8 * u8) + sm.d_modes * log(u8) + sums[1].value();
     g[1] = -2.0 * e / (u8 * u8 * u8) + sm.d_modes / u8;
     g[2] = sums[4].value() / phi;
+    g[3] = sums[5].value() * 5.0 / (eta * log(10.0));
     sm.cosmo_eval[0] = u8;
     sm.cosmo_eval[1] = phi;
   } else {
@@ -383,7 +392,7 @@ finalize_body(const double* __restrict__ prior_part, int n_prior, const double* 
     if (sm.g) sm.g[k] = g[k];
   if (sm.p) {
     const double eps = sm.eps[0];
-    const double minv[kSmallMax] = {1.0, sm.minv_u8, sm.minv_phi};
+    const double minv[kSmallMax] = {1.0, sm.minv_u8, sm.minv_phi, sm.minv_eta};
     for (int k = 0; k < ns; ++k) {
       if (k == 0 && !sm.sample_s) continue;
       const double pv = sm.p[k] - sm.kick * eps * g[k];
@@ -454,6 +463,7 @@ template <typename T, int N> __device__ __forceinline__ Cosmo cosmo(const Ws<T, 
   const PlanConst& pc = w.pc();
   Cosmo c;
   c.om = pc.om; c.h = pc.h; c.box = pc.box; c.spacing = pc.spacing; c.dmax = pc.dmax;
+  c.sample_c = pc.sample_c;
   return c;
 }
 
@@ -518,6 +528,7 @@ template <typename T, int N> __device__ __forceinline__ SmallState small_state(c
   sm.sample_c = pc.sample_c;
   sm.minv_u8 = pc.minv_u8;
   sm.minv_phi = pc.minv_phi;
+  sm.minv_eta = pc.minv_eta;
   sm.d_modes = pc.d_modes;
   const bool update = k.mode != kXGrad && (pc.sample_s || pc.sample_c);
   sm.p = update ? k.st.ps : nullptr;

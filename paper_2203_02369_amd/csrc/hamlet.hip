@@ -90,7 +90,7 @@ struct hamlet_plan {
   int device = 0;                  // the HIP device the plan was created on
   int n = 0, prec = 0, n_gal = 0, sample_d = 1, sample_s = 1, sample_c = 0, n_hist = 0;
   double box = 0, om = 0, h = 0, f = 0, sigma_v = 0, hist_w = 5.0, minv_d = 0;
-  double minv_u8 = 0, minv_phi = 0;
+  double minv_u8 = 0, minv_phi = 0, minv_eta = 0;
   hipStream_t stream = nullptr;
   hipEvent_t order_ev = nullptr;   // orders shared launches against this plan's stream
   char* base = nullptr;            // the workspace (one allocation)
@@ -117,7 +117,7 @@ struct hamlet_plan {
   size_t prof_used = 0;
   bool prof_failed = false;
   size_t modes_count() const { return (size_t)n * n * (n / 2); }
-  int n_small() const { return sample_c ? kSmallMax : 1; }   // s, and u8, phi when sampled
+  int n_small() const { return sample_c ? kSmallMax : 1; }   // s, and u8, phi, eta when sampled
 };
 
 // Bracket one launch of kernel kind `kind` with events when it is armed on
@@ -635,12 +635,14 @@ static hamlet_status upload(hamlet_plan* pl, const hamlet_plan_desc* d, const ha
   pc.sample_c = pl->sample_c;
   pc.minv_u8 = pl->minv_u8;
   pc.minv_phi = pl->minv_phi;
+  pc.minv_eta = pl->minv_eta;
   pc.d_modes = std::pow((double)(pl->n - 1), 3.0) - 1.0;
   HIP_TRY(hipMemcpyAsync(pl->consts, &pc, sizeof(pc), hipMemcpyHostToDevice, st));
   return HAMLET_OK;
 }
 
-static void fill_plan_scalars(hamlet_plan* pl, const hamlet_plan_desc* d, int64_t n_gal, int n_hist) {
+static void fill_plan_scalars(hamlet_plan* pl, const hamlet_plan_desc* d, const hamlet_catalog* cat, int n_hist) {
+  const int64_t n_gal = cat->n;
   pl->n = d->n_grid;
   pl->prec = d->precision;
   pl->box = d->box;
@@ -654,12 +656,18 @@ static void fill_plan_scalars(hamlet_plan* pl, const hamlet_plan_desc* d, int64_
   pl->minv_d = pl->sample_d ? (pl->sigma_v / kH0) * (pl->sigma_v / kH0) : 0.0;
   pl->n_gal = (int)n_gal;
   pl->n_hist = n_hist;
-  // u8 = sigma_8 / sigma_8,fid and phi = f / f_fid: inverse masses 1 / (2 D)
-  // (the prior's curvature in u8 at u8 = 1, D real mode coordinates) and 1 / n
+  // u8 = sigma_8 / sigma_8,fid, phi = f / f_fid and eta = h / h_fid:
+  // inverse masses 1 / (2 D) (the prior's curvature in u8 at u8 = 1, D real
+  // mode coordinates), 1 / n, and the inverse curvature of the distance
+  // modulus terms in eta at eta = 1, 1 / sum_i (5 / ln 10)^2 / sigma_mu,i^2
   pl->sample_c = d->sample_cosmology ? 1 : 0;
   const double dof = std::pow((double)(pl->n - 1), 3.0) - 1.0;
   pl->minv_u8 = pl->sample_c ? 1.0 / (2.0 * dof) : 0.0;
   pl->minv_phi = pl->sample_c ? 1.0 / (double)std::max<int64_t>(n_gal, 1) : 0.0;
+  const double c5 = (5.0 / std::log(10.0)) * (5.0 / std::log(10.0));
+  double curv = 0.0;
+  for (int64_t i = 0; i < n_gal; ++i) curv += c5 / (cat->sigma_mu[i] * cat->sigma_mu[i]);
+  pl->minv_eta = pl->sample_c ? (n_gal > 0 ? 1.0 / curv : 1.0) : 0.0;
 }
 
 // Upper bound of the histogram bin count for the footprint query: the
@@ -693,7 +701,7 @@ static hamlet_status plan_make(const hamlet_plan_desc* desc, const hamlet_catalo
   if (hipGetDevice(&device) != hipSuccess) return fail(HAMLET_EDEVICE, "hipGetDevice failed");
   hamlet_plan* pl = new hamlet_plan();
   pl->device = device;
-  fill_plan_scalars(pl, desc, cat->n, distance_prior_bins(cat, desc->omega_m, w));
+  fill_plan_scalars(pl, desc, cat, distance_prior_bins(cat, desc->omega_m, w));
   pl->stream = stream;
   pl->pooled = pooled;
   pl->ops = pl->prec == HAMLET_FP64 ? pick_ops<double>(pl->n) : pick_ops<float>(pl->n);

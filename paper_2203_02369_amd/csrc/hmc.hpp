@@ -96,6 +96,7 @@ __device__ __forceinline__ void kinetic_small_part(const Pick<T, N>& k, CSum acc
     if (pc.sample_c) {
       acc.add(0.5 * pc.minv_u8 * k.st.ps[1] * k.st.ps[1]);
       acc.add(0.5 * pc.minv_phi * k.st.ps[2] * k.st.ps[2]);
+      acc.add(0.5 * pc.minv_eta * k.st.ps[3] * k.st.ps[3]);
     }
   }
   const double s = block_csum(acc, red);
@@ -125,12 +126,14 @@ __global__ void __launch_bounds__(kEltThreads) k_momenta_small(Launch L) {
     k.st.ps[0] = pc.sample_s ? normal_pair(draw_words(seed, iteration, kPurposeSnl, 0)).x : 0.0;
     k.w.qs0()[0] = k.st.qs[0];
     if (pc.sample_c) {
-      // (u8, phi) from one pair: p ~ N(0, M), M = 1 / minv
+      // (u8, phi) from one pair, eta from the first of the next: p ~ N(0, M),
+      // M = 1 / minv
       const double2 z = normal_pair(draw_words(seed, iteration, kPurposeCosmo, 0));
+      const double2 z2 = normal_pair(draw_words(seed, iteration, kPurposeCosmo, 1));
       k.st.ps[1] = z.x / sqrt(pc.minv_u8);
       k.st.ps[2] = z.y / sqrt(pc.minv_phi);
-      k.w.qs0()[1] = k.st.qs[1];
-      k.w.qs0()[2] = k.st.qs[2];
+      k.st.ps[3] = z2.x / sqrt(pc.minv_eta);
+      for (int j = 1; j < kSmallMax; ++j) k.w.qs0()[j] = k.st.qs[j];
     }
   }
   kinetic_small_part(k, acc, red);
@@ -194,7 +197,7 @@ __global__ void __launch_bounds__(kEltThreads) k_small_kick_drift(Launch L) {
       if (st.sv_qs) st.sv_qs[j] = st.qs[j];
       if (st.sv_ps) st.sv_ps[j] = st.ps[j];
     }
-    const double minv[kSmallMax] = {1.0, pc.minv_u8, pc.minv_phi};
+    const double minv[kSmallMax] = {1.0, pc.minv_u8, pc.minv_phi, pc.minv_eta};
     for (int j = 0; j < ns; ++j) {
       if (j == 0 && !pc.sample_s) continue;
       const double pv = st.ps[j] - 0.5 * e * st.gs[j];

@@ -34,7 +34,7 @@ __host__ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t 
 enum Purpose : uint32_t {
   kPurposeModes = 0, kPurposeDist = 1, kPurposeSnl = 2, kPurposeAccept = 3, kPurposeJitter = 4,
   kPurposeNutsDir = 5, kPurposeNutsMerge = 6, kPurposeNutsTop = 7,
-  kPurposeCosmo = 8   // momenta of u8 and phi (index 0: the pair)
+  kPurposeCosmo = 8   // momenta of u8 and phi (index 0: the pair), eta (index 1: its first)
 };
 
 __host__ __device__ __forceinline__ Philox4 draw_words(uint64_t seed, uint32_t iteration, uint32_t purpose, uint64_t index) {

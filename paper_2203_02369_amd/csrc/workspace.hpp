@@ -28,14 +28,15 @@ constexpr int kMaxBatch = 16;
 enum XMode { kXSkip = -1, kXGrad = 0, kXFirst = 1, kXMid = 2, kXLast = 3 };
 
 // The small coordinates of a state: s = sigma_NL / 100 km/s, and when the
-// plan samples the cosmological parameters u8 = sigma_8 / sigma_8,fid and
-// phi = f / f_fid (kSmallMax values: q_snl, p_snl, g_snl hold 1 or 3).
-constexpr int kSmallMax = 3;
+// plan samples the cosmological parameters u8 = sigma_8 / sigma_8,fid,
+// phi = f / f_fid and eta = h / h_fid (kSmallMax values: q_snl, p_snl, g_snl
+// hold 1 or 4).
+constexpr int kSmallMax = 4;
 
 // Per-plan constants, at the start of the workspace.
 struct PlanConst {
   int n_gal, n_hist, sample_d, sample_s;
-  int n_prior_part, n_like_part, n_kin_part, sample_c;   // sample_c: u8 and phi sampled
+  int n_prior_part, n_like_part, n_kin_part, sample_c;   // sample_c: u8, phi and eta sampled
   double om, h;            // Omega_0, little h (for mu)
   double box, spacing;     // L, L / N
   double dmax;             // c / (3 Omega_0 H0): domain of zbar(d)
@@ -43,7 +44,7 @@ struct PlanConst {
   double minv_d;           // inverse mass of a distance, (sigma_v / H0)^2
   double psd;              // sqrt of the mass of a distance, H0 / sigma_v
   double kfac0;            // H0 f / (N^3 k_f), k_f = 2 pi / L (fiducial f)
-  double minv_u8, minv_phi;   // inverse masses of u8 and phi
+  double minv_u8, minv_phi, minv_eta;   // inverse masses of u8, phi and eta
   double d_modes;          // real mode coordinates, (N-1)^3 - 1
 };
 
@@ -170,7 +171,7 @@ struct ChainScalars {
   double eps_it;       // step of the current iteration (jittered)
   double da_mu, da_hbar, da_log_eps_bar, da_m;
   double psi;                  // Psi at the current state
-  double gs[kSmallMax];        // dPsi/d(s, u8, phi) there
+  double gs[kSmallMax];        // dPsi/d(s, u8, phi, eta) there
   double psi_saved;            // at the start of the trajectory
   double gs_saved[kSmallMax];
   double kin0, kin1;
@@ -184,6 +185,7 @@ struct ChainScalars {
 };
 static_assert(sizeof(ChainScalars) <= FixedLayout<16, 8>::chain_bytes, "chain scalars block");
 static_assert(sizeof(PlanConst) <= 256, "plan constants block");
+static_assert(16 * kSmallMax + 32 <= 256, "small-coordinate block (qs0, ps, eps, most, ticket, cosmo_eval)");
 
 // Typed view of a plan's workspace.
 template <typename T, int N> struct Ws {
@@ -204,14 +206,14 @@ template <typename T, int N> struct Ws {
   __host__ __device__ int* cursor() const { return at<int>(F::cursor); }
   __host__ __device__ double* prior_part() const { return at<double>(F::prior_part); }
   __host__ __device__ double* kin_part() const { return at<double>(F::kin_part); }
-  __host__ __device__ double* qs0() const { return at<double>(F::small); }          // kSmallMax
-  __host__ __device__ double* ps() const { return at<double>(F::small + 24); }      // kSmallMax
-  __host__ __device__ double* eps_slot() const { return at<double>(F::small + 48); }
-  __host__ __device__ int* most() const { return at<int>(F::small + 56); }   // most points in one column
-  __host__ __device__ int* ticket() const { return at<int>(F::small + 60); } // likelihood blocks done
+  __host__ __device__ double* qs0() const { return at<double>(F::small); }                    // kSmallMax
+  __host__ __device__ double* ps() const { return at<double>(F::small + 8 * kSmallMax); }     // kSmallMax
+  __host__ __device__ double* eps_slot() const { return at<double>(F::small + 16 * kSmallMax); }
+  __host__ __device__ int* most() const { return at<int>(F::small + 16 * kSmallMax + 8); }   // most points in one column
+  __host__ __device__ int* ticket() const { return at<int>(F::small + 16 * kSmallMax + 12); } // likelihood blocks done
   // u8 and phi where the evaluation's gradient is taken (the adjoint pass
   // reads them after the small coordinates have drifted on)
-  __host__ __device__ double* cosmo_eval() const { return at<double>(F::small + 64); }
+  __host__ __device__ double* cosmo_eval() const { return at<double>(F::small + 16 * kSmallMax + 16); }
   __host__ __device__ double* mvar() const { return at<double>(F::mvar); }
   __host__ __device__ C* a() const { return at<C>(F::a); }
   __host__ __device__ C* b() const { return at<C>(F::b); }

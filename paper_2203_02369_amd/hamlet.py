@@ -73,8 +73,9 @@ class Plan:
         self._handle = handle
         self.n_gal = n
         self.mode_shape = (self.n_grid, self.n_grid, self.n_grid // 2)
-        # small coordinates: s, and u8 = sigma_8 / sigma_8,fid, phi = f / f_fid when sampled
-        self.n_small = 3 if sample_cosmology else 1
+        # small coordinates: s, and u8 = sigma_8 / sigma_8,fid, phi = f / f_fid,
+        # eta = h / h_fid when sampled
+        self.n_small = 4 if sample_cosmology else 1
 
     @classmethod
     def from_mock(cls, mock, **kw):
@@ -109,10 +110,10 @@ class Plan:
     def scalar(self, value=0.0):
         return torch.full((1,), float(value), dtype=torch.float64, device=self.device)
 
-    def small(self, s=0.0, u8=1.0, phi=1.0):
+    def small(self, s=0.0, u8=1.0, phi=1.0, eta=1.0):
         """The small coordinates of a state (or momenta, gradient): (s,) or
-        (s, u8, phi) when the plan samples the cosmological parameters."""
-        vals = [s, u8, phi][: self.n_small]
+        (s, u8, phi, eta) when the plan samples the cosmological parameters."""
+        vals = [s, u8, phi, eta][: self.n_small]
         return torch.tensor(vals, dtype=torch.float64, device=self.device)
 
 

@@ -1,11 +1,12 @@
-"""sigma_8 and the growth rate sampled with the field (sample_cosmology):
+"""h, sigma_8 and the growth rate sampled with the field (sample_cosmology):
 the GPU path against the oracle through the C ABI.
 
-The small coordinates are (s, u8, phi).  Psi and every gradient component
-(modes, distances, s, u8, phi) at 1e-12 (FP64) and 2e-5 / 1e-4 (FP32); the
+The small coordinates are (s, u8, phi, eta).  Psi and every gradient
+component (modes, distances, s, u8, phi, eta) at 1e-12 (FP64) and 2e-5 /
+1e-4 (FP32); the
 leapfrog's displacements likewise; an HMC chain and a No-U-Turn chain with
 the same decisions as the oracle's; plans with and without the coordinates
-in one shared launch equal to each plan alone; the flat vector with its two
+in one shared launch equal to each plan alone; the flat vector with its three
 extra entries equal to the oracle's.
 """
 import sys
@@ -22,7 +23,7 @@ from helpers import TOL64, from_lib_layout, oracle_problem, rel_inf, start_modes
 pytestmark = pytest.mark.gpu
 
 TOL32_PSI, TOL32_GRAD = 2e-5, 1e-4
-COSMO = np.array([0.93, 1.12])
+COSMO = np.array([0.93, 1.12, 0.97])
 
 
 @pytest.fixture(scope="module")
@@ -73,11 +74,11 @@ def test_cosmology_gradient_matches_oracle(hl, name, precision):
     errs = {"psi": abs(psi.item() - ref[0]) / abs(ref[0]),
             "modes": rel_inf(from_lib_layout(g.cpu().numpy()), ref[1]), "dist": rel_inf(gd.cpu().numpy(), ref[2]),
             "s": abs(small[0] - ref[3]) / abs(ref[3]), "u8": abs(small[1] - ref[4][0]) / abs(ref[4][0]),
-            "phi": abs(small[2] - ref[4][1]) / abs(ref[4][1])}
+            "phi": abs(small[2] - ref[4][1]) / abs(ref[4][1]), "eta": abs(small[3] - ref[4][2]) / abs(ref[4][2])}
     say("  errors", errs)
     tol_psi, tol_g = (TOL64, TOL64) if precision == "fp64" else (TOL32_PSI, TOL32_GRAD)
     assert errs["psi"] <= tol_psi
-    for k in ("modes", "dist", "s", "u8", "phi"):
+    for k in ("modes", "dist", "s", "u8", "phi", "eta"):
         assert errs[k] <= tol_g, (k, errs[k])
     plan.close()
 
@@ -109,7 +110,7 @@ def test_cosmology_leapfrog_matches_oracle(hl, precision):
             "dist": rel_inf(tqd.cpu().numpy() - q0.dist, q1.dist - q0.dist),
             "p_modes": rel_inf(from_lib_layout(tp.cpu().numpy()) - p0.modes, p1.modes - p0.modes),
             "p_dist": rel_inf(tpd.cpu().numpy() - p0.dist, p1.dist - p0.dist)}
-    for j, nm in enumerate(("s", "u8", "phi")):
+    for j, nm in enumerate(("s", "u8", "phi", "eta")):
         errs[nm] = abs((qs_g[j] - small_q0[j]) - (small_q1[j] - small_q0[j])) / abs(small_q1[j] - small_q0[j])
         errs["p_" + nm] = abs((ps_g[j] - small_p0[j]) - (small_p1[j] - small_p0[j])) / abs(small_p1[j] - small_p0[j])
     say("  displacement errors", errs)
@@ -143,7 +144,7 @@ def test_cosmology_hmc_chain_matches_oracle(hl):
             "modes": rel_inf(from_lib_layout(tq.cpu().numpy()), res.state.modes),
             "dist": rel_inf(tqd.cpu().numpy(), res.state.dist),
             "small": rel_inf(small, np.array([res.state.s, *res.state.cosmo]))}
-    say("  chain errors", errs, "u8, phi:", small[1:], "from", COSMO)
+    say("  chain errors", errs, "u8, phi, eta:", small[1:], "from", COSMO)
     for k, e in errs.items():
         assert e <= TOL64, (k, e)
     assert np.abs(small[1:] - COSMO).max() > 1e-4          # the cosmological coordinates moved

@@ -1,12 +1,15 @@
 """Pins of the cosmological coordinates of the oracle (Section 6, item 3:
-sigma_8 and the growth rate estimated with the field): u8 = sigma_8 /
-sigma_8,fid scales P(k) by u8^2, phi = f / f_fid scales the velocity field.
+H0, sigma_8 and the growth rate estimated with the field): u8 = sigma_8 /
+sigma_8,fid scales P(k) by u8^2, phi = f / f_fid scales the velocity field,
+eta = h / h_fid sets the zero point of the distance moduli.
 
 The prior with u8 must be the normalised Gaussian of variance u8^2 sigma_k^2
 (checked against scipy's normal log-density, term for term); the velocity
 field must be linear in the growth rate and obey linear continuity with the
-scaled f; the gradient in (u8, phi) against central differences (Psi is
-smooth in both), the mode gradient away from the fiducial point against
+scaled f; Psi at eta must equal Psi at the fiducial h with every observed
+distance modulus moved by +5 log10 eta (the luminosity distance in Mpc is
+d_L / h); the gradient in (u8, phi, eta) against central differences (Psi is
+smooth in all three), the mode gradient away from the fiducial point against
 exact central differences; the leapfrog with the new coordinates reversible.
 """
 import math
@@ -59,7 +62,28 @@ def test_growth_rate_scales_the_velocity_field():
     assert np.allclose(-div / model.H0, phi * prob.f_growth * delta, atol=1e-9 * np.abs(delta).max())
 
 
-@pytest.mark.parametrize("cosmo", [(1.0, 1.0), (0.9, 1.2)])
+def test_hubble_parameter_moves_the_distance_modulus_zero_point():
+    m, prob = _problem()
+    n = prob.n_grid
+    dhat = hmc.symmetrise(n, m.dhat_true)
+    d = m.d_true.copy()
+    s = 1.3
+    for eta in (0.93, 1.0, 1.08):
+        got = model.logpost(prob, dhat, d, s, cosmo=np.array([1.0, 1.0, eta]))
+        # the same universe measured with h = eta h_fid: d_L / h in Mpc, so
+        # the predicted modulus drops by 5 log10 eta; equivalently every
+        # observed modulus rises by as much at the fiducial h
+        args = m.problem_kwargs()
+        args.update(sample_cosmology=True, mu=np.asarray(prob.mu) + 5.0 * math.log10(eta))
+        ref = model.logpost(model.Problem(**args), dhat, d, s, cosmo=np.array([1.0, 1.0, 1.0]))
+        assert abs(got - ref) <= 1e-12 * abs(ref), (eta, got, ref)
+    # a smaller h puts every point farther in Mpc: with the moduli of the mock
+    # (drawn at h_fid) the fit is best near eta = 1
+    psis = [model.logpost(prob, dhat, d, s, cosmo=np.array([1.0, 1.0, e])) for e in (0.8, 1.0, 1.25)]
+    assert psis[1] < psis[0] and psis[1] < psis[2]
+
+
+@pytest.mark.parametrize("cosmo", [(1.0, 1.0, 1.0), (0.9, 1.2, 0.95)])
 def test_cosmology_gradient_central_differences(cosmo):
     m, prob = _problem()
     n = prob.n_grid
@@ -70,7 +94,7 @@ def test_cosmology_gradient_central_differences(cosmo):
     c = np.array(cosmo)
     psi, gm, gd, gs, gc = model.logpost_grad(prob, dhat, d, s, cosmo=c)
     assert psi == model.logpost(prob, dhat, d, s, cosmo=c)
-    for a in range(2):
+    for a in range(3):
         h = 1e-5 * c[a]
         cp, cm = c.copy(), c.copy()
         cp[a] += h
@@ -89,17 +113,18 @@ def test_cosmology_gradient_central_differences(cosmo):
         fd = (model.logpost(prob, hmc.unpack_modes(n, xp), d, s, cosmo=c)
               - model.logpost(prob, hmc.unpack_modes(n, xm), d, s, cosmo=c)) / (2 * h)
         assert abs(fd - g_flat[j]) <= 1e-6 * np.abs(g_flat).max(), (j, fd, g_flat[j])
-    # outside (0, inf) x (0, inf) the posterior vanishes
-    assert model.logpost(prob, dhat, d, s, cosmo=np.array([-0.1, 1.0])) == math.inf
-    assert model.logpost(prob, dhat, d, s, cosmo=np.array([1.0, 0.0])) == math.inf
+    # outside (0, inf)^3 the posterior vanishes
+    assert model.logpost(prob, dhat, d, s, cosmo=np.array([-0.1, 1.0, 1.0])) == math.inf
+    assert model.logpost(prob, dhat, d, s, cosmo=np.array([1.0, 0.0, 1.0])) == math.inf
+    assert model.logpost(prob, dhat, d, s, cosmo=np.array([1.0, 1.0, -0.5])) == math.inf
 
 
 def test_leapfrog_with_cosmology_is_reversible():
     m, prob = _problem()
     n = prob.n_grid
-    q0 = hmc.State(hmc.symmetrise(n, m.dhat_true), m.d_true.copy(), 1.2, np.array([1.05, 0.95]))
+    q0 = hmc.State(hmc.symmetrise(n, m.dhat_true), m.d_true.copy(), 1.2, np.array([1.05, 0.95, 1.02]))
     p0 = hmc.draw_momenta(prob, 9, 0)
-    assert p0.cosmo is not None and p0.cosmo.shape == (2,)
+    assert p0.cosmo is not None and p0.cosmo.shape == (3,)
     q1, p1, _ = hmc.leapfrog(prob, q0, p0, 0.05, 12)
     assert np.abs(q1.cosmo - q0.cosmo).max() > 1e-4          # the new coordinates moved
     back = hmc.State(p1.modes * -1, -p1.dist, -p1.s, -p1.cosmo)
@@ -109,6 +134,6 @@ def test_leapfrog_with_cosmology_is_reversible():
     # the kinetic energy carries the new momenta with their masses
     kin = hmc.kinetic(prob, p0)
     p0c = p0.copy()
-    p0c.cosmo = np.zeros(2)
+    p0c.cosmo = np.zeros(3)
     assert abs(kin - hmc.kinetic(prob, p0c) - 0.5 * float(np.sum(hmc.cosmo_inverse_mass(prob) * p0.cosmo ** 2))) \
         <= 1e-12 * kin
