@@ -32,8 +32,6 @@
 
 namespace hamlet {
 
-constexpr int kPassThreads = 256;
-
 // Threads per block of each pass kind: the schedule of the grid size and
 // real type (schedule.hpp; the autotuner's choice where it has one).
 template <typename T, int N> struct PassThreads {
