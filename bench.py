@@ -49,9 +49,9 @@ HBM_PEAK_GBS = 8000.0
 # (--copy-calibration: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  Bytes read and
 # written per launch for the plain-gradient, first, middle and last variants.
 # Valid only for the kernel sources they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "b963ca070d75286044b5d6270d955ab6326ed5aa"
-X_TRAFFIC = {"grad": (334102269, 134217984), "first": (335658732, 670220640),
-             "mid": (468507996, 401674784), "last": (468375283, 268502304)}
+X_TRAFFIC_SOURCES_SHA1 = "a4f434317317c7dac2ba1ee668056f4fe0388f62"
+X_TRAFFIC = {"grad": (334118650, 134217984), "first": (335646446, 670230528),
+             "mid": (468496606, 401674624), "last": (468375283, 268503296)}
 
 # below this acceptance rate a chain hardly samples: the comparison of the two
 # paths "at equal acceptance" would be void, and the run reports failure
