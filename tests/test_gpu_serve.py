@@ -126,6 +126,39 @@ def test_served_job_matches_oracle_chain(hl):
         h_scale)
 
 
+def test_served_job_with_cosmology_matches_oracle_chain(hl):
+    # A served FP64 job that samples u8, phi and eta (a served job starts them
+    # at 1): the oracle's chain from the same point makes the same decisions
+    # and reaches the same states.  The server hands back s alone of the small
+    # coordinates; the other three steer every mode and distance.
+    m = mocks.make_mock(16, 200.0, 300, 80.0, "sphere", (0.2, 0.2), seed=31)
+    start = _start(m, 3)
+    chain = dict(n_iter=8, n_leapfrog=5, eps0=0.03, warmup=3, jitter=True)
+    sv = hl.Server(4 * GIB)
+    say("served job with the cosmological coordinates, against the oracle chain")
+    job = _submit(sv, m, "fp64", 2207, start, sample_cosmology=True, **chain)
+    _drain(sv, [job])
+    got = sv.take(job)
+    sv.close()
+    prob = oracle_problem(m, sample_cosmology=True)
+    q0 = hmc.State(from_lib_layout(start[0]), start[1].copy(), start[2], np.ones(3))
+    path = []
+    res = hmc.hmc_run(prob, q0, chain["n_iter"], chain["n_leapfrog"], chain["eps0"], 2207,
+                      warmup=chain["warmup"], jitter=True, callback=lambda it, q, dh, acc, e: path.append(q.copy()))
+    path = [q0] + path
+    say("accept oracle", res.accepted.tolist(), "served", got["accepted"].tolist(), "cosmo", res.state.cosmo)
+    assert np.array_equal(got["accepted"], res.accepted)
+    assert 0 < res.accepted.sum()
+    assert np.abs(res.state.cosmo - 1.0).max() > 1e-6          # the coordinates moved in the chain
+    h_scale = abs(model.logpost(prob, q0.modes, q0.dist, q0.s, cosmo=q0.cosmo))
+    check_adapted_chain(res, chain["warmup"], got["eps"], got["dh"], {
+        "modes": (from_lib_layout(got["q_modes"]), res.state.modes, path_length([x.modes for x in path])),
+        "dist": (got["q_dist"], res.state.dist, path_length([x.dist for x in path])),
+        "s": (np.array([got["q_snl"]]), np.array([res.state.s]), path_length([np.array([x.s]) for x in path])),
+        "mode_sum": (from_lib_layout(got["mode_sum"]), res.mode_sum, path_length([x.modes for x in path]))},
+        h_scale)
+
+
 def test_job_alone_equals_job_in_a_mix(hl):
     x = mocks.make_mock(32, 400.0, 400, 120.0, "sphere", (0.2, 0.2), seed=41)
     sx = _start(x, 1)
