@@ -48,8 +48,9 @@ HBM_PEAK_GBS = 8000.0
 # points, each scaled by what the counter reads for a plain 1 GiB device copy
 # (--copy-calibration: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  Bytes read and
 # written per launch for the plain-gradient, first, middle and last variants.
-# Valid only for the kernel sources they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "a4f434317317c7dac2ba1ee668056f4fe0388f62"
+# Valid only for the kernel sources and the 256^3 FP32 schedule they were
+# taken on (hash below).
+X_TRAFFIC_SOURCES_SHA1 = "beb1f3aaa0db289090ec435fd65e4c4dd6e7467a"
 X_TRAFFIC = {"grad": (334118650, 134217984), "first": (335646446, 670230528),
              "mid": (468496606, 401674624), "last": (468375283, 268503296)}
 
@@ -58,12 +59,17 @@ X_TRAFFIC = {"grad": (334118650, 134217984), "first": (335646446, 670230528),
 MIN_ACCEPTANCE = 0.3
 
 
-def kernel_sources_sha1():
+def kernel_sources_sha1(sched):
+    """Hash of the kernel sources and of the launch schedule the library runs
+    for the grid (threads, tiles, radix plan): together they fix the code of
+    that grid's kernels, whatever the schedules of other grids."""
     import hashlib
+    import json
     h = hashlib.sha1()
-    for f in ("passes.hpp", "fft.hpp", "common.hpp", "workspace.hpp", "random.hpp", "schedule.hpp", "tuned.hpp"):
+    for f in ("passes.hpp", "fft.hpp", "common.hpp", "workspace.hpp", "random.hpp", "schedule.hpp"):
         with open(os.path.join(ROOT, "paper_2203_02369_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    h.update(json.dumps(sched, sort_keys=True).encode())
     return h.hexdigest()
 
 
@@ -494,7 +500,7 @@ def main():
     per_launch = x_bytes / x_launches
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     traffic = None
-    if n == 256 and kernel_sources_sha1() == X_TRAFFIC_SOURCES_SHA1:
+    if n == 256 and kernel_sources_sha1(hamlet.schedule(n, "fp32")) == X_TRAFFIC_SOURCES_SHA1:
         t = X_TRAFFIC
         tot = sum(t["grad"]) + args.steps * (sum(t["first"]) + (L - 1) * sum(t["mid"]) + sum(t["last"]))
         traffic = int(tot / x_launches)

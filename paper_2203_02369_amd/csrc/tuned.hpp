@@ -7,12 +7,13 @@ namespace hamlet {
 
 template <> struct Tuned<float, 64> : DefaultSched<float, 64> {
   static constexpr int PG = 4;
-  static constexpr int PZ = 4;
+  static constexpr int PZ = 2;
   static constexpr int W = 8;
 };
 
 template <> struct Tuned<float, 128> : DefaultSched<float, 128> {
   static constexpr int PZ = 4;
+  static constexpr int ZS = 128;
 };
 
 template <> struct Tuned<float, 512> : DefaultSched<float, 512> {
@@ -30,10 +31,14 @@ template <> struct Tuned<float, 1024> : DefaultSched<float, 1024> {
 
 template <> struct Tuned<double, 128> : DefaultSched<double, 128> {
   static constexpr int RADIX = 2;
+  static constexpr int ZS = 128;
+  static constexpr int X = 256;
 };
 
 template <> struct Tuned<double, 512> : DefaultSched<double, 512> {
   static constexpr int PZ = 8;
+  static constexpr int ZS = 512;
+  static constexpr int X = 1024;
   static constexpr int W = 8;
 };
 
