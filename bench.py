@@ -43,16 +43,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of k_x_pass<float, 256> per launch, from two rocprofv3 --pmc
-# runs (FETCH_SIZE, then WRITE_SIZE) of this script at 256^3 with 30 000
-# points, each scaled by what the counter reads for a plain 1 GiB device copy
-# (--copy-calibration: FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  Bytes read and
-# written per launch for the plain-gradient, first, middle and last variants.
-# Valid only for the kernel sources and the 256^3 FP32 schedule they were
-# taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "beb1f3aaa0db289090ec435fd65e4c4dd6e7467a"
-X_TRAFFIC = {"grad": (334118650, 134217984), "first": (335646446, 670230528),
-             "mid": (468496606, 401674624), "last": (468375283, 268503296)}
+# HBM traffic of k_x_pass<float, 256> per launch in a chain (complex64 chain
+# state), from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of this
+# script at 256^3 with 30 000 points, each scaled by what the counter reads
+# for a plain 1 GiB device copy (--copy-calibration: FETCH_SIZE x 1.9999,
+# WRITE_SIZE x 1.0000).  Bytes read and written per launch for the
+# plain-gradient, first, middle and last variants.  Valid only for the kernel
+# sources and the 256^3 FP32 schedule they were taken on (hash below).
+X_TRAFFIC_SOURCES_SHA1 = "0d4deda194800a7de083df1a47140d4358010f3e"
+X_TRAFFIC = {"grad": (267569070, 67108864), "first": (201500367, 402261939),
+             "mid": (334885258, 267979024), "last": (334749068, 134283456)}
 
 # below this acceptance rate a chain hardly samples: the comparison of the two
 # paths "at equal acceptance" would be void, and the run reports failure
@@ -483,17 +483,19 @@ def main():
     # ---- roofline of the dominant kernel ------------------------------------
     # k_x_pass: the x pass of every evaluation, fused with the leapfrog update
     # and the next inverse pass 1.  Algorithmic bytes in units of one complex64
-    # spectral array c (8 N^2 N/2 bytes; complex128 arrays count 2c; the FP64
-    # per-mode prior variance sigma_k^2 counts 1c):
-    #   plain gradient (1 per run):        S1, S2, q, var in; G out           =  7c
+    # spectral array c (8 N^2 N/2 bytes; the FP64 per-mode prior variance
+    # sigma_k^2 counts 1c).  The FP32 path's chain keeps its modes q, momenta
+    # p and cached gradient G (and the start point q0, G0) in complex64, 1c
+    # each:
+    #   plain gradient (1 per run):        S1, S2, q, var in; G out           = 5c
     #   first step of a chain's trajectory (momenta drawn in the pass):
     #                                       G, q, var in; p, q, A, B and the
-    #                                       kept start q0, G0 out           = 15c
-    #   middle steps (L - 1 per traj.):    S1, S2, p, q, var in; p, q, A, B   = 13c
-    #   last step:                         S1, S2, p, q, var in; p, G out     = 11c
+    #                                       kept start q0, G0 out           = 9c
+    #   middle steps (L - 1 per traj.):    S1, S2, p, q, var in; p, q, A, B   = 9c
+    #   last step:                         S1, S2, p, q, var in; p, G out     = 7c
     nm = n * n * (n // 2)
     c32 = 8 * nm
-    x_bytes = c32 * (7 + args.steps * (15 + 13 * (L - 1) + 11))
+    x_bytes = c32 * (5 + args.steps * (9 + 9 * (L - 1) + 7))
     x_launches = 1 + args.steps * (L + 1)
     assert kern_launches == x_launches, (kern_launches, x_launches)
     avg_ms = kern_ms / kern_launches
@@ -726,11 +728,12 @@ def run_batched(args, dev):
     log("one at a time: %.3fs: %.1f grad/s" % (dt_seq, v_seq))
     rate = float(np.mean([a.cpu().numpy()[args.warmup:].mean() for a in acc]))
 
-    # roofline of the x pass of the 256^3 group (5 chains per launch):
-    # per chain and iteration first 15c, L - 1 middle 13c, last 11c.
+    # roofline of the x pass of the 256^3 group (5 chains per launch, chain
+    # states in complex64): per chain and iteration first 9c, L - 1 middle 9c,
+    # last 7c.
     n256 = [p for p in plans if p.n_grid == 256]
     c32 = 8 * 256 * 256 * 128
-    per_iter = len(n256) * c32 * (15 + 13 * (L - 1) + 11)
+    per_iter = len(n256) * c32 * (9 + 9 * (L - 1) + 7)
     assert kern_launches == args.steps * (L + 1), (kern_launches, args.steps * (L + 1))
     avg_ms = kern_ms / kern_launches
     per_launch = per_iter * args.steps / kern_launches

@@ -34,6 +34,17 @@ template <typename To, typename From> __device__ __forceinline__ To cconvert(Fro
   To r; r.x = static_cast<decltype(r.x)>(a.x); r.y = static_cast<decltype(r.y)>(a.y); return r;
 }
 
+// Storage type of a chain's mode state (modes, momenta, cached gradient,
+// saved start point): complex128, or complex64 for the chains of the FP32
+// path.  Updates are computed in FP64 and rounded to the storage type
+// before any use, so that the energies and gradients are those of the state
+// as stored.
+template <bool S32> struct StateElt { using type = double2; };
+template <> struct StateElt<true> { using type = float2; };
+template <typename Q> __device__ __forceinline__ double2 widen(Q v) { return make_double2((double)v.x, (double)v.y); }
+template <typename Q> __device__ __forceinline__ Q narrow(double2 v) { return cconvert<Q>(v); }
+template <typename Q> __device__ __forceinline__ double2 rounded(double2 v) { return widen(narrow<Q>(v)); }
+
 // Streaming (non-temporal) loads and stores, for the arrays a pass reads or
 // writes once: on the MI355X they stream about 15 % faster than plain
 // accesses (a 1 GiB copy: 5.2 vs 4.6 TB/s) and leave the caches to data that

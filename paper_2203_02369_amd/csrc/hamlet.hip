@@ -68,6 +68,9 @@ struct Batch {
   int8_t mode[kMaxBatch] = {};
   double plane_scale = 1.0;   // kXGrad: factor on the kz = 0 plane of the gradient
   bool chain = false;         // first steps: trajectories of chains (momenta drawn here, start kept)
+  // the plans' modes, momenta and cached gradients are chain states, which
+  // the FP32 path stores in complex64 (FP64 plans ignore it)
+  bool chain_state = false;
 };
 
 // Launch sequences and workspace layout, one instantiation per (precision, N).
@@ -105,6 +108,7 @@ struct hamlet_plan {
   int *count = nullptr, *off = nullptr, *most = nullptr;
   double2* gcache = nullptr;
   double2* pm = nullptr;
+  float2* qc = nullptr;            // a chain's complex64 modes (FP32 plans), else nullptr
   double *gd = nullptr, *qd0 = nullptr, *pd = nullptr, *ps = nullptr, *eps_slot = nullptr, *dz = nullptr;
   bool pooled = false;             // workspace from the stream-ordered pool
   int n_prior_part = 0, n_like_part = 0, n_kin_part = 0;
@@ -180,6 +184,24 @@ static bool batch_has(const Batch& b, int mode) {
   return false;
 }
 
+// Chain states in complex64: the FP32 path's chains (kS32<T> is true only
+// for float, so no such variant of the FP64 kernels is built).
+template <typename T> constexpr bool kS32 = sizeof(T) == 4;
+template <typename T> static bool chain_f32(const Batch& b) { return kS32<T> && b.chain_state; }
+
+// The x passes of an evaluation (gradient, middle or last leapfrog step).
+template <typename T, int N, bool S32>
+static void x_passes(const Batch& b, const Launch& sel, dim3 g_xy) {
+  using TH = PassThreads<T, N>;
+  hipStream_t st = b.stream;
+  if (batch_has(b, kXGrad))
+    TIMED(b, HAMLET_K_FWD_X, (k_x_pass<T, N, kXGrad, TH::X, false, S32><<<g_xy, TH::X, 0, st>>>(sel, b.plane_scale)));
+  if (batch_has(b, kXMid))
+    TIMED(b, HAMLET_K_FWD_X, (k_x_pass<T, N, kXMid, TH::X, false, S32><<<g_xy, TH::X, 0, st>>>(sel, 1.0)));
+  if (batch_has(b, kXLast))
+    TIMED(b, HAMLET_K_FWD_X, (k_x_pass<T, N, kXLast, TH::X, false, S32><<<g_xy, TH::X, 0, st>>>(sel, 1.0)));
+}
+
 // One log-posterior-and-gradient evaluation of every plan of the batch:
 // bin, inverse passes with the gather, likelihood, final sums (Psi,
 // dPsi/ds), forward passes with the scatter, and the x pass (gradient, or
@@ -214,7 +236,12 @@ static hamlet_status eval_impl(const Batch& b) {
   }
   const dim3 g_xy(S::CHUNKS, N, nb);
   const dim3 g_xy_slab(S::CHUNKS, SL::SIZE, nb), g_z_slab(N / S::P, SL::SIZE, nb), g_zg_slab(N / S::PG, SL::SIZE, nb);
-  if (batch_has(b, kXGrad)) TIMED(b, HAMLET_K_INV_X, (k_inv_x<T, N, TH::XY><<<g_xy, TH::XY, 0, st>>>(sel)));
+  if (batch_has(b, kXGrad)) {
+    if (chain_f32<T>(b))
+      TIMED(b, HAMLET_K_INV_X, (k_inv_x<T, N, TH::XY, kS32<T>><<<g_xy, TH::XY, 0, st>>>(sel)));
+    else
+      TIMED(b, HAMLET_K_INV_X, (k_inv_x<T, N, TH::XY><<<g_xy, TH::XY, 0, st>>>(sel)));
+  }
   for (int sl = 0; sl < SL::COUNT; ++sl) {
     const int x0 = sl * SL::SIZE;
     TIMED(b, HAMLET_K_INV_Y, (k_inv_y<T, N, TH::XY><<<g_xy_slab, TH::XY, 0, st>>>(sel, x0)));
@@ -238,12 +265,10 @@ static hamlet_status eval_impl(const Batch& b) {
     TIMED(b, HAMLET_K_FWD_Z, (k_fwd_z_scatter<T, N, TH::ZS><<<g_z_slab, TH::ZS, 0, st>>>(sel, x0)));
     TIMED(b, HAMLET_K_FWD_Y, (k_fwd_y<T, N, TH::XY><<<g_xy_slab, TH::XY, 0, st>>>(sel, x0)));
   }
-  if (batch_has(b, kXGrad))
-    TIMED(b, HAMLET_K_FWD_X, (k_x_pass<T, N, kXGrad, TH::X><<<g_xy, TH::X, 0, st>>>(sel, b.plane_scale)));
-  if (batch_has(b, kXMid))
-    TIMED(b, HAMLET_K_FWD_X, (k_x_pass<T, N, kXMid, TH::X><<<g_xy, TH::X, 0, st>>>(sel, 1.0)));
-  if (batch_has(b, kXLast))
-    TIMED(b, HAMLET_K_FWD_X, (k_x_pass<T, N, kXLast, TH::X><<<g_xy, TH::X, 0, st>>>(sel, 1.0)));
+  if (chain_f32<T>(b))
+    x_passes<T, N, kS32<T>>(b, sel, g_xy);
+  else
+    x_passes<T, N, false>(b, sel, g_xy);
   LAUNCH_CHECK();
   return HAMLET_OK;
 }
@@ -353,8 +378,12 @@ static hamlet_status first_impl(const Batch& b) {
   if (b.chain) {
     // a chain's trajectory: the pass also draws the mode momenta, keeps the
     // start point and sums the mode part of K0, which is completed here
-    TIMED(b, HAMLET_K_FWD_X,
-          (k_x_pass<T, N, kXFirst, TH::X, true><<<dim3(S::CHUNKS, N, nb), TH::X, 0, b.stream>>>(sel, 1.0)));
+    if (chain_f32<T>(b))
+      TIMED(b, HAMLET_K_FWD_X, (k_x_pass<T, N, kXFirst, TH::X, true, kS32<T>>
+                                <<<dim3(S::CHUNKS, N, nb), TH::X, 0, b.stream>>>(sel, 1.0)));
+    else
+      TIMED(b, HAMLET_K_FWD_X,
+            (k_x_pass<T, N, kXFirst, TH::X, true><<<dim3(S::CHUNKS, N, nb), TH::X, 0, b.stream>>>(sel, 1.0)));
     k_kinetic_final<T, N><<<dim3(1, 1, nb), 256, 0, b.stream>>>(sel, 0);
   } else {
     TIMED(b, HAMLET_K_FWD_X,
@@ -383,8 +412,11 @@ static hamlet_status end_impl(const Batch& b) {
     k_kinetic_final<T, N><<<dim3(1, 1, nb), 256, 0, b.stream>>>(kin, 1);
   }
   k_accept<T, N><<<dim3(1, 1, nb), 64, 0, b.stream>>>(sel);
-  k_restore_accumulate<T, N><<<dim3(blocks_for(std::max(nm, (size_t)batch_gal_or_one(b)), kEltThreads), 1, nb),
-                               kEltThreads, 0, b.stream>>>(sel);
+  const dim3 g_rest(blocks_for(std::max(nm, (size_t)batch_gal_or_one(b)), kEltThreads), 1, nb);
+  if (chain_f32<T>(b))
+    k_restore_accumulate<T, N, kS32<T>><<<g_rest, kEltThreads, 0, b.stream>>>(sel);
+  else
+    k_restore_accumulate<T, N><<<g_rest, kEltThreads, 0, b.stream>>>(sel);
   LAUNCH_CHECK();
   return HAMLET_OK;
 }
@@ -446,6 +478,7 @@ template <typename T, int N> static void locate_impl(hamlet_plan* pl) {
   pl->most = w.most();
   pl->gcache = w.gcache();
   pl->pm = w.pm();
+  pl->qc = sizeof(T) == 4 ? w.qc() : nullptr;
   pl->gd = w.gd(); pl->qd0 = w.qd0(); pl->pd = w.pd(); pl->ps = w.ps(); pl->eps_slot = w.eps_slot();
   pl->dz = w.dz();
   pl->n_prior_part = F::N_PRIOR;
@@ -953,10 +986,26 @@ struct ChainRun {
   bool active() const { return need_grad || iter < todo; }
 };
 
+// The modes of an FP32 plan's chain into its complex64 state, and back
+// (only the retained modes are written back).
+static hamlet_status chain_modes_in(const hamlet_plan* pl, const double2* q, hipStream_t s) {
+  const size_t nm = pl->modes_count();
+  k_modes_narrow<<<blocks_for(nm, kEltThreads), kEltThreads, 0, s>>>(q, pl->qc, nm);
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
+static hamlet_status chain_modes_out(const hamlet_plan* pl, double2* q, hipStream_t s) {
+  k_modes_widen<<<blocks_for(pl->modes_count(), kEltThreads), kEltThreads, 0, s>>>(pl->qc, q, pl->n);
+  LAUNCH_CHECK();
+  return HAMLET_OK;
+}
+
 static hamlet_status tick_group(hipStream_t stream, const std::vector<ChainRun*>& runs) {
   Batch start, first, eval, end;
   start.stream = first.stream = eval.stream = end.stream = stream;
   first.chain = true;
+  start.chain_state = first.chain_state = eval.chain_state = end.chain_state = true;
   const Ops* ops = nullptr;
   for (ChainRun* r : runs) {
     if (!r->active()) continue;
@@ -1137,6 +1186,11 @@ extern "C" hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_pla
       hamlet_plan* pl = plans[j];
       StateDev sd{};
       sd.q = (double2*)q_modes[j];
+      if (pl->qc) {
+        // the FP32 path's chain runs on complex64 modes
+        if ((st = chain_modes_in(pl, (const double2*)q_modes[j], s0)) != HAMLET_OK) return st;
+        sd.q = (double2*)pl->qc;
+      }
       sd.qd = pl->n_gal ? q_dist[j] : pl->qd0;
       sd.qs = q_snl[j];
       sd.p = pl->pm;
@@ -1180,6 +1234,8 @@ extern "C" hamlet_status hamlet_hmc_run(hamlet_plan* const* plans, int32_t n_pla
   for (int j = 0; j < n_plans; ++j) plans[j]->chain_ready = true;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const std::vector<int>& g = groups[gi];
+    for (int j : g)
+      if (plans[j]->qc && (st = chain_modes_out(plans[j], (double2*)q_modes[j], gstream[gi])) != HAMLET_OK) return st;
     if (eps_out) {
       hipStream_t s0 = gstream[gi];
       for (int j : g) HIP_TRY(hipMemcpyAsync(&eps_out[j], &plans[j]->cs->eps, sizeof(double), hipMemcpyDeviceToHost, s0));
@@ -2155,6 +2211,12 @@ static hamlet_status job_admit(hamlet_server* sv, Job* j) {
   LAUNCH_CHECK();
   StateDev sd{};
   sd.q = j->q;
+  if (pl->qc) {
+    // the FP32 path's chain runs on complex64 modes (back into j->q when done)
+    hamlet_status cs = chain_modes_in(pl, j->q, s);
+    if (cs != HAMLET_OK) return cs;
+    sd.q = (double2*)pl->qc;
+  }
   sd.qd = pl->n_gal ? j->qd : pl->qd0;
   sd.qs = j->qs;
   sd.p = pl->pm;
@@ -2260,6 +2322,7 @@ extern "C" hamlet_status hamlet_server_tick(hamlet_server* sv, hamlet_server_sta
       still.push_back(j);
       continue;
     }
+    if (j->plan->qc && (st = chain_modes_out(j->plan, j->q, sv->stream)) != HAMLET_OK) return st;
     HIP_TRY(hipEventRecord(j->done, sv->stream));
     j->state = 2;
   }

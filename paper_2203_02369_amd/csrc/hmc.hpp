@@ -265,23 +265,26 @@ __global__ void k_accept(Launch L) {
 
 // After the test: on rejection restore the saved state and its cached
 // gradient; past warm-up add the (possibly restored) modes to the running
-// sum of samples.
-template <typename T, int N>
+// sum of samples (FP64).  S32: the chain state is stored in complex64.
+template <typename T, int N, bool S32 = false>
 __global__ void __launch_bounds__(kEltThreads) k_restore_accumulate(Launch L) {
+  using Q = typename StateElt<S32>::type;
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
   const size_t total = (size_t)N * N * (N / 2);
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const ChainScalars* cs = chain(k.w);
   const int rejected = !cs->accept;
+  Q* sq = reinterpret_cast<Q*>(k.st.q);
   if (i < total) {
     double2 q = make_double2(0.0, 0.0);
     if (rejected) {
-      q = ld_stream(&k.w.q0()[i]);
-      st_stream(&k.st.q[i], q);
-      st_stream(&k.w.gcache()[i], ld_stream(&k.w.g0()[i]));
+      const Q q0 = ld_stream(&reinterpret_cast<const Q*>(k.w.q0())[i]);
+      st_stream(&sq[i], q0);
+      st_stream(&reinterpret_cast<Q*>(k.w.gcache())[i], ld_stream(&reinterpret_cast<const Q*>(k.w.g0())[i]));
+      q = widen(q0);
     } else if (cs->post && k.st.msum) {
-      q = ld_stream(&k.st.q[i]);
+      q = widen(ld_stream(&sq[i]));
     }
     if (cs->post && k.st.msum) {
       double2 a = ld_stream(&k.st.msum[i]);
@@ -300,6 +303,24 @@ __global__ void __launch_bounds__(kEltThreads) k_restore_accumulate(Launch L) {
       for (int j = 0; j < ns; ++j) k.st.qs[j] = k.w.qs0()[j];
     }
   }
+}
+
+// A chain's modes into and out of the complex64 state of the FP32 path's
+// chains: every entry rounded in, only the retained modes written back (the
+// caller's other entries keep their values).
+__global__ void __launch_bounds__(kEltThreads) k_modes_narrow(const double2* __restrict__ in, float2* __restrict__ out,
+                                                              size_t count) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = narrow<float2>(in[i]);
+}
+
+__global__ void __launch_bounds__(kEltThreads) k_modes_widen(const float2* __restrict__ in, double2* __restrict__ out,
+                                                             int n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int hz = n / 2;
+  if (i >= (size_t)n * n * hz) return;
+  const int kz = (int)(i % hz), y = (int)((i / hz) % n), x = (int)(i / ((size_t)hz * n));
+  if (retained(signed_freq(x, n), signed_freq(y, n), kz, n)) out[i] = widen(in[i]);
 }
 
 // End of a leapfrog call: Psi of the end point to the caller's slot.

@@ -322,9 +322,9 @@ __host__ __device__ inline size_t var_ofs(int n, int w, int kx, int ky, int kz) 
 // ---------------------------------------------------------------------------
 // DENSITY: A = q / N^3 (the density contrast's spectrum) instead of the
 // velocity multiplier's i kfac q.
-template <typename T, int N, int NT, bool DENSITY = false>
+template <typename T, int N, int NT, bool DENSITY = false, typename Q = double2>
 __device__ __forceinline__ void
-inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* __restrict__ tw,
+inv_x_body(const Q* __restrict__ modes, ModeTables tab, const cplx_t<T>* __restrict__ tw,
         cplx_t<T>* __restrict__ outA, cplx_t<T>* __restrict__ outB, double* __restrict__ prior_part) {
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
@@ -341,7 +341,7 @@ inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* _
   auto ain = [&](int x, int w, double scale_x) {
     const int kz = z0 + w, sx = signed_freq(x, N);
     if (!retained(sx, sy, kz, N)) return make_double2(0.0, 0.0);
-    const double2 q = modes[gofs<N>(x, y, kz)];
+    const double2 q = widen(modes[gofs<N>(x, y, kz)]);
     if constexpr (DENSITY) {
       const double sc = (scale_x != 0.0 ? scale_x * sx : 1.0) / ((double)N * N * N);
       return make_double2(sc * q.x, sc * q.y);
@@ -353,7 +353,7 @@ inv_x_body(const double2* __restrict__ modes, ModeTables tab, const cplx_t<T>* _
     const int kz = z0 + w, sx = signed_freq(x, N);
     if (retained(sx, sy, kz, N)) {
       const size_t g = gofs<N>(x, y, kz);
-      const double2 q = modes[g];
+      const double2 q = widen(modes[g]);
       prior.add((kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(tab.var[var_ofs(N, S::W, x, y, kz)]));
     }
     tile[LAY::idx(x, w)] = cconvert<C>(ain(x, w, 0.0));
@@ -1003,10 +1003,10 @@ struct ChainSave {
 //   kXLast  : G from S1, S2; kick p -= (eps/2) G; write G to `gcache`.
 // (eq:hamilton integrated by kick-drift-kick leapfrog, mass matrix eq:M_ab.)
 // ---------------------------------------------------------------------------
-template <typename T, int N, int MODE, int NT, bool CHAIN>
+template <typename T, int N, int MODE, int NT, bool CHAIN, typename Q>
 __device__ __forceinline__ void
-x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ modes, double2* __restrict__ mom,
-            double2* __restrict__ gcache, ModeTables tab, const cplx_t<T>* __restrict__ tw,
+x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* __restrict__ mom,
+            Q* __restrict__ gcache, ModeTables tab, const cplx_t<T>* __restrict__ tw,
             const double* __restrict__ eps_ptr, cplx_t<T>* outA, cplx_t<T>* outB, double* __restrict__ prior_part,
             double plane_scale, ChainSave save) {
   using C = cplx_t<T>;
@@ -1028,6 +1028,12 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
   const int y = tl.y, z0 = tl.x * S::W;
   const int sy = signed_freq(y, N);
   C acc[elems_per_thread<T, N, NT>()];
+  // complex64 momenta of a leapfrog step are loaded before the second
+  // transform, whose time hides their latency (complex128 ones, or more than
+  // eight per thread, would spill)
+  constexpr bool kPrefetchP =
+      kFromSpectra && MODE != kXGrad && sizeof(Q) == 8 && elems_per_thread<T, N, NT>() <= 8;
+  Q ppf[elems_per_thread<T, N, NT>()];
   if constexpr (kFromSpectra) {
     tile_vecs<T, N, NT>([&](int, int x, int w) { vec_to_lds<T, LAY>(tile, x, w, vec_load<T>(&s2[gofs<N>(x, y, z0 + w)])); });
     tws.store(twl);
@@ -1036,6 +1042,8 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
     tile_elems<T, N, NT>([&](int e, int x, int w) { acc[e] = cscale(tile[LAY::idx(x, w)], (T)signed_freq(x, N)); });
     __syncthreads();
     tile_vecs<T, N, NT>([&](int, int x, int w) { vec_to_lds<T, LAY>(tile, x, w, vec_load<T>(&s1[gofs<N>(x, y, z0 + w)])); });
+    if constexpr (kPrefetchP)
+      tile_elems<T, N, NT>([&](int e, int x, int w) { ppf[e] = ld_stream(&mom[gofs<N>(x, y, z0 + w)]); });
     __syncthreads();
     lds_fft<T, N, S::W, LAY, NT, -1>(tile, twl);
   } else {
@@ -1056,7 +1064,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
     const double var = keep ? ld_stream(&tab.var[var_ofs(N, S::W, x, y, kz)]) : 0.0;
     // the mode, read once (gradient and drift)
     double2 q = make_double2(0.0, 0.0);
-    if (kStartOfChain || (keep && (kFromSpectra || kDrift))) q = ld_stream(&modes[g]);
+    if (kStartOfChain || (keep && (kFromSpectra || kDrift))) q = widen(ld_stream(&modes[g]));
     double2 G = make_double2(0.0, 0.0);
     if constexpr (kFromSpectra) {
       if (keep) {
@@ -1066,18 +1074,19 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
         G = make_double2(iv2 * q.x + kf2 * (double)tv.y, iv2 * q.y - kf2 * (double)tv.x);
       }
     } else {
-      G = ld_stream(&gcache[g]);
+      G = widen(ld_stream(&gcache[g]));
     }
     if constexpr (MODE == kXGrad) {
       // plane_scale 0.5: gradient per stored entry (each Hermitian partner of
       // the kz = 0 plane taken as its own variable carries half)
-      st_stream(&gcache[g], kz == 0 ? make_double2(plane_scale * G.x, plane_scale * G.y) : G);
+      st_stream(&gcache[g], narrow<Q>(kz == 0 ? make_double2(plane_scale * G.x, plane_scale * G.y) : G));
     }
-    if constexpr (MODE == kXLast) st_stream(&gcache[g], G);
+    if constexpr (MODE == kXLast) st_stream(&gcache[g], narrow<Q>(G));
     if constexpr (kStartOfChain) {
-      // the start of the trajectory, kept for a rejection
-      st_stream(&save.q0[g], q);
-      st_stream(&save.g0[g], G);
+      // the start of the trajectory, kept for a rejection (both already in
+      // the storage type)
+      st_stream(&reinterpret_cast<Q*>(save.q0)[g], narrow<Q>(q));
+      st_stream(&reinterpret_cast<Q*>(save.g0)[g], narrow<Q>(G));
     }
     if constexpr (MODE != kXGrad) {
       double2 p = make_double2(0.0, 0.0);
@@ -1091,15 +1100,20 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
           const size_t src = mirror ? gofs<N>((N - x) & (N - 1), (N - y) & (N - 1), 0) : g;
           const double2 z = normal_pair(draw_words(save.seed, save.iteration, kPurposeModes, src));
           const double sc = sqrt(2.0 * inv_or_zero(var));
-          p = make_double2(sc * z.x, mirror ? -sc * z.y : sc * z.y);
+          // drawn in FP64; K0 and the kick take the value as stored
+          p = rounded<Q>(make_double2(sc * z.x, mirror ? -sc * z.y : sc * z.y));
         }
+      } else if constexpr (kPrefetchP) {
+        p = widen(ppf[e]);
       } else {
-        p = ld_stream(&mom[g]);
+        p = widen(ld_stream(&mom[g]));
       }
       if constexpr (MODE == kXFirst && !CHAIN) {
-        // the state this step starts from, kept where the caller asks
-        if (save.sv_q) st_stream(&save.sv_q[g], q);
-        if (save.sv_p) st_stream(&save.sv_p[g], p);
+        // the state this step starts from, kept where the caller asks (the
+        // callers outside chains hold complex128 states)
+        static_assert(sizeof(Q) == 16, "complex128 state outside chains");
+        if (save.sv_q) st_stream(&save.sv_q[g], narrow<double2>(q));
+        if (save.sv_p) st_stream(&save.sv_p[g], narrow<double2>(p));
       }
       // per stored mode (w / 8) sigma^2 |p|^2, w = 1 on kz = 0 (both
       // Hermitian partners stored), else 2
@@ -1107,15 +1121,17 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, double2* __restrict__ mode
       if (kStartOfChain && keep) kin.add(wk * var * (p.x * p.x + p.y * p.y));
       p.x -= hk * G.x;
       p.y -= hk * G.y;
+      p = rounded<Q>(p);
       if (MODE == kXLast && keep) kin.add(wk * var * (p.x * p.x + p.y * p.y));
-      st_stream(&mom[g], p);
+      st_stream(&mom[g], narrow<Q>(p));
       if constexpr (kDrift) {
         double2 a = make_double2(0.0, 0.0);
         if (keep) {
           const double c = eps * (0.5 * var);
           q.x += c * p.x;
           q.y += c * p.y;
-          st_stream(&modes[g], q);
+          q = rounded<Q>(q);   // the prior energy and the next gradient are those of the stored modes
+          st_stream(&modes[g], narrow<Q>(q));
           prior.add((kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(var));
           const double kf = mode_kfac(tab.kfac0, n2);
           a = make_double2(-kf * q.y, kf * q.x);      // i kfac q
@@ -1188,11 +1204,14 @@ template <typename T, int N> __device__ __forceinline__ Binned<T> binned(const W
   return b;
 }
 
-template <typename T, int N, int NT>
+// S32: the plans' modes are a chain state in complex64 (st.q points to it).
+template <typename T, int N, int NT, bool S32 = false>
 __global__ void __launch_bounds__(NT) k_inv_x(Launch L) {
+  using Q = typename StateElt<S32>::type;
   const Pick<T, N> k(L);
   if (k.mode != kXGrad) return;
-  inv_x_body<T, N, NT>(k.st.q, tables(k.w, k.st), k.w.tw(), k.w.a(), k.w.b(), k.w.prior_part());
+  inv_x_body<T, N, NT, false, Q>(reinterpret_cast<const Q*>(k.st.q), tables(k.w, k.st), k.w.tw(), k.w.a(), k.w.b(),
+                                 k.w.prior_part());
 }
 
 template <typename T, int N, int NT>
@@ -1246,12 +1265,15 @@ __global__ void __launch_bounds__(NT) k_fwd_y(Launch L, int x0) {
 
 // One launch per mode present in a batch; plans in another mode return.
 // CHAIN: the first step of a chain's trajectory, which also draws the
-// momenta, keeps the start point and sums K0.  Four waves per SIMD (two
-// blocks per compute unit): the FP64 middle step spills a few registers for
-// it and still gains 5 %, the first step 10 % in both precisions.
-template <typename T, int N, int MODE, int NT, bool CHAIN = false>
+// momenta, keeps the start point and sums K0.  S32: the chain state (modes,
+// momenta, cached gradient, start point) is stored in complex64.  Four
+// waves per SIMD (two blocks per compute unit): the FP64 middle step spills
+// a few registers for it and still gains 5 %, the first step 10 % in both
+// precisions.
+template <typename T, int N, int MODE, int NT, bool CHAIN = false, bool S32 = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_x_pass(Launch L,
                                                                                     double plane_scale) {
+  using Q = typename StateElt<S32>::type;
   const Pick<T, N> k(L);
   if (k.mode != MODE) return;
   ChainSave save{k.w.q0(), k.w.g0(), k.w.kin_part(), 0, 0, k.st.sv_q, k.st.sv_p};
@@ -1260,8 +1282,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
     save.seed = cs->seed;
     save.iteration = (uint32_t)cs->iter;
   }
-  x_pass_body<T, N, MODE, NT, CHAIN>(k.w.a(), k.w.b(), k.st.q, k.st.p, k.st.g, tables(k.w, k.st), k.w.tw(), k.st.eps,
-                                     k.w.a(), k.w.b(), k.w.prior_part(), plane_scale, save);
+  x_pass_body<T, N, MODE, NT, CHAIN, Q>(k.w.a(), k.w.b(), reinterpret_cast<Q*>(k.st.q), reinterpret_cast<Q*>(k.st.p),
+                                        reinterpret_cast<Q*>(k.st.g), tables(k.w, k.st), k.w.tw(), k.st.eps,
+                                        k.w.a(), k.w.b(), k.w.prior_part(), plane_scale, save);
 }
 
 }  // namespace hamlet

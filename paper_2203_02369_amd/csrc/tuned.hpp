@@ -35,6 +35,10 @@ template <> struct Tuned<double, 128> : DefaultSched<double, 128> {
   static constexpr int X = 256;
 };
 
+template <> struct Tuned<double, 256> : DefaultSched<double, 256> {
+  static constexpr int RADIX = 3;
+};
+
 template <> struct Tuned<double, 512> : DefaultSched<double, 512> {
   static constexpr int PZ = 8;
   static constexpr int ZS = 512;

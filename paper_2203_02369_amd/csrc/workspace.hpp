@@ -132,7 +132,8 @@ template <int N, int R> struct FixedLayout {
   static constexpr size_t q0 = gcache + 16 * NM;
   static constexpr size_t g0 = q0 + 16 * NM;
   static constexpr size_t pm = g0 + 16 * NM;
-  static constexpr size_t end = pm + 16 * NM;                    // start of the galaxy region
+  static constexpr size_t qc = pm + 16 * NM;                     // a chain's complex64 modes (FP32 path)
+  static constexpr size_t end = qc + (R == 4 ? 8 * NM : 0);      // start of the galaxy region
 };
 
 // Per-galaxy arrays, in galaxy units (8 bytes per galaxy, rounded up to 256
@@ -224,6 +225,7 @@ template <typename T, int N> struct Ws {
   __host__ __device__ double2* q0() const { return at<double2>(F::q0); }
   __host__ __device__ double2* g0() const { return at<double2>(F::g0); }
   __host__ __device__ double2* pm() const { return at<double2>(F::pm); }
+  __host__ __device__ float2* qc() const { return at<float2>(F::qc); }
   __host__ __device__ double* rhat() const { return gal<double>(G::rhat); }
   __host__ __device__ double* mu() const { return gal<double>(G::mu); }
   __host__ __device__ double* smu() const { return gal<double>(G::smu); }

@@ -522,9 +522,16 @@ def test_paper_scale_delta_h_matches_oracle(hl, precision):
     # benchmark's state with Philox momenta on both sides.  The Hamiltonian
     # (about 1e7, millions of terms) is summed with compensation on the GPU
     # and exactly rounded in the oracle; dH must agree within 1e-12 of H in
-    # FP64 and within 1e-3 absolute in FP32 (the FP32 fields move Psi by
-    # about 1e-4 at each end, far below the O(1) scale of dH that the
-    # Metropolis test reads).
+    # FP64.  In FP32 the fields move Psi by about 1e-4 at each end (1e-3
+    # allowed), and the chain stores its modes and momenta in FP32: every
+    # stored update rounds each of the D real coordinates x_i by at most
+    # 2^-24 |x_i|, which moves H by sum_i (dH/dx_i) delta_i, a sum of
+    # independent terms of variance <= (2^-24 x_i dH/dx_i)^2 / 3.  For modes
+    # and momenta near their Gaussian scale, x_i dH/dx_i ~ z^2 (E z^4 = 3),
+    # so each rounding of all coordinates moves H by about sqrt(D) 2^-24.  A
+    # two-step trajectory rounds five times (half kick and drift, merged kick
+    # and drift, last half kick; the momenta drawn at the start are stored
+    # rounded before K0 reads them): allowed at four standard deviations.
     m = mocks.paper_scale_256()
     prob = oracle_problem(m)
     q0 = hmc.State(hmc.symmetrise(256, m.dhat_true), m.d_true.copy(), 1.5)
@@ -551,7 +558,10 @@ def test_paper_scale_delta_h_matches_oracle(hl, precision):
     if precision == "fp64":
         assert err <= TOL64 * abs(psi0), err
     else:
-        assert err <= 1e-3, err
+        n_real = 2 * int(np.count_nonzero(to_lib_layout(q0.modes)))   # real mode coordinates (about)
+        rounding = 4.0 * math.sqrt(5 * n_real) * 2.0 ** -24
+        say("FP32 dH bound: 1e-3 + state rounding %.3g" % rounding)
+        assert err <= 1e-3 + rounding, err
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
