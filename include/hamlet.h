@@ -69,7 +69,8 @@ typedef enum {
 typedef enum {
   HAMLET_FP64 = 0,          /* every transform, gather and scatter in FP64 */
   HAMLET_FP32_FP64E = 1     /* transforms, gather, scatter in FP32; Hamiltonian,
-                               likelihood, dH, Metropolis test, momenta in FP64 */
+                               likelihood, dH, Metropolis test, momentum draws in
+                               FP64; a chain's mode state stored in complex64 */
 } hamlet_precision;
 
 /* Problem statement (Section 2; the grid and box of Section 5.1).  All
@@ -192,9 +193,16 @@ typedef struct {
  * iteration = the chain's own count), n_leapfrog steps, Metropolis-Hastings
  * test ln u < -dH (a rejected trajectory repeats the state), dual averaging
  * of eps during the chain's first `warmup` iterations.
- * q_* (device, in/out): start state in, last state out.
+ * q_* (device, in/out): start state in, last state out.  A plan of
+ *   precision HAMLET_FP32_FP64E runs its chain on a complex64 copy of the
+ *   modes in its workspace (its momenta, cached gradient and kept start
+ *   point in complex64 too; every update computed in FP64 and rounded before
+ *   use, so H and dH are those of the stored state): q_modes[j] is rounded to
+ *   complex64 on entry, and on return its retained modes hold the chain's
+ *   last state (widened exactly); its other entries are left as they were.
  * mode_sum[j] (device, may be NULL): sum over post-warm-up iterations of the
- *   chain's mode state (eq:int_mc numerator); accumulated onto its contents.
+ *   chain's mode state (eq:int_mc numerator); accumulated onto its contents
+ *   in FP64.
  * dh[j], accepted[j] (device, may be NULL): indexed by the chain's iteration
  *   count, so n_iter entries for a fresh chain (more when resumed).
  * eps_out (host, may be NULL): n_plans, the step after warm-up (synchronises).
@@ -434,7 +442,9 @@ hamlet_status hamlet_server_job_state(hamlet_server* server, int64_t job_id, int
 /* Copies a finished job's results to host memory and releases it; each
  * pointer may be NULL.  mode_sum: N*N*N/2 double complex, the sum of the
  * post-warm-up states (eq:int_mc numerator); q_modes, q_dist, q_snl: the last
- * state; dh, accepted: n_iter; eps: the step after warm-up. */
+ * state (an HAMLET_FP32_FP64E job's chain runs on complex64 modes, as in
+ * hamlet_hmc_run: its retained modes come back widened from them, the other
+ * entries as submitted); dh, accepted: n_iter; eps: the step after warm-up. */
 hamlet_status hamlet_server_take(hamlet_server* server, int64_t job_id, double* mode_sum, double* q_modes,
                                  double* q_dist, double* q_snl, double* dh, int32_t* accepted, double* eps);
 
