@@ -352,12 +352,12 @@ hamlet_status hamlet_shell_stats(hamlet_plan* plan, const double* a, const doubl
 
 /* As hamlet_shell_stats, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
- * allocation): the partial sums live in a static device array of 32 MiB
+ * allocation): the partial sums live in a static device array of 4 MiB
  * that each device the library runs on holds until the process ends; the
- * call allocates and frees nothing.  Its partials need (N/4)(N/8)(N/16)
- * tiles x (shells a tile reaches) x 24 bytes, at most 4.7 MB at 256^3 with
- * shells of 10 Mpc/h; a call that would need more than 32 MiB fails with
- * HAMLET_EINVAL before anything is enqueued.  Every call on a device shares
+ * call allocates and frees nothing.  Its partials need n_shells x N x 24
+ * bytes (one per shell and x plane: 276 KB at 256^3 with 45 shells); a call
+ * that would need more than 4 MiB (more than 682 shells at 256^3, 170 at
+ * 1024^3) fails with HAMLET_EINVAL before anything is enqueued.  Every call on a device shares
  * that device's array: calls that overlap on one device (two streams, or
  * two host threads) race and must be ordered by the caller.  Results equal
  * hamlet_shell_stats bit for bit.  The first call on a device looks up the

@@ -166,17 +166,21 @@ __global__ void __launch_bounds__(NT) k_inv_z_acc(Launch L, int x0, double* acc)
 // standard deviation) of fields a and b over its nodes, and their Pearson
 // correlation coefficient.  Two sweeps, as the definitions read: the means,
 // then the sums of the centred products (no cancellation for a field whose
-// scatter is small against its mean).  Each sweep has two stages, both in
-// fixed order: each block sums the nodes of a 4 x 8 x 16 tile per shell that
-// the tile reaches (a few consecutive shells, the range found from the
-// tile's nearest and farthest node), and one block per shell adds those
-// partials in block order.
+// scatter is small against its mean).
+//
+// Each sweep runs shell by shell.  Block (x, s) adds the nodes of shell s
+// in the plane x: in a row y within reach, the nodes that can lie in the
+// shell form at most two runs of z (|r_z| between bounds found from the
+// shell's radii, widened by a node on each side), and each candidate counts
+// only if shell_index puts it in s, so every node is assigned exactly as
+// node by node.  Groups of 16 lanes take the rows in turn and walk the runs
+// 16 nodes at a time (128-byte pieces of a row), each lane summing in
+// order; one block sum at the end.  The finish adds the N plane partials of
+// a shell in x order, so reruns are bit-identical.
 // ---------------------------------------------------------------------------
-constexpr int kShellTX = 4, kShellTY = 8, kShellTZ = 16;
 constexpr int kShellThreads = 256;
-constexpr int kShellFinishThreads = 1024;
-constexpr int kShellsPerReduce = 1;   // shells a block reduces together (4 measured slower)
-constexpr int kShellNodes = kShellTX * kShellTY * kShellTZ;
+constexpr int kShellGroup = 16;          // lanes that walk one row
+constexpr int kShellFinishThreads = 256;
 constexpr int kShellValues = 3;   // sweep 1: count, sum a, sum b; sweep 2: sum da^2, sum db^2, sum da db
 constexpr int kShellOut = 6;
 constexpr int kShellMax = 4096;
@@ -184,119 +188,102 @@ constexpr int kShellMax = 4096;
 struct ShellGeom {
   double h, width;   // node spacing, shell width (Mpc/h)
   int n, n_shells;
-  int slots;         // partials stored per block (most shells a tile reaches)
 };
 
 __host__ __device__ inline int shell_index(int r2, const ShellGeom& g) {
   return (int)floor(sqrt((double)r2) * g.h / g.width);
 }
 
-// Shells [lo, hi] (hi clamped to the last shell) that tile (bx, by, bz)
-// reaches: the squared distance of its nearest and farthest node, per axis.
-__host__ __device__ inline int2 shell_range(int bx, int by, int bz, const ShellGeom& g) {
-  const int half = g.n / 2;
-  int dmin = 0, dmax = 0;
-  const int start[3] = {bx * kShellTX, by * kShellTY, bz * kShellTZ};
-  const int len[3] = {kShellTX, kShellTY, kShellTZ};
-  for (int a = 0; a < 3; ++a) {
-    const int lo = start[a] - half, hi = start[a] + len[a] - 1 - half;
-    const int alo = lo < 0 ? -lo : lo, ahi = hi < 0 ? -hi : hi;
-    const int mn = (lo <= 0 && hi >= 0) ? 0 : (alo < ahi ? alo : ahi), mx = alo > ahi ? alo : ahi;
-    dmin += mn * mn;
-    dmax += mx * mx;
-  }
-  const int s1 = shell_index(dmax, g);
-  return make_int2(shell_index(dmin, g), s1 < g.n_shells - 1 ? s1 : g.n_shells - 1);
+// Squared radii (in nodes^2) that bound shell s, widened by 2 for the
+// rounding of shell_index at the shell's faces: every node of the shell has
+// r2 in [lo, hi].
+__device__ __forceinline__ double2 shell_r2_bounds(int s, const ShellGeom& g) {
+  const double c = g.width / g.h;
+  const double r0 = s * c, r1 = (s + 1) * c;
+  return make_double2(r0 * r0 - 2.0, r1 * r1 + 2.0);
 }
 
-// Stage 1 of a sweep: grid (N / 16, N / 8, N / 4) = (tile z, y, x), z
-// fastest, so that blocks dispatched together read neighbouring pieces of the
-// same rows; part[(block * slots + s - lo) * 3 + v], block = (bx ny + by) nz + bz.  Sweep 2 (CENTRED) reads the means
-// of shell s from out[s * 6 + 1] and out[s * 6 + 3].
+// Per plane x, shell s: partial sums into part[(s N + x) 3 + v].  Sweep 2
+// (CENTRED) reads the means of shell s from out[s * 6 + 1] and out[s * 6 + 3].
 template <bool CENTRED>
 __global__ void __launch_bounds__(kShellThreads)
 k_shell_part(const double* __restrict__ a, const double* __restrict__ b, ShellGeom g, const double* __restrict__ out,
              double* __restrict__ part) {
-  constexpr int V = kShellValues * kShellsPerReduce;
-  __shared__ double red[V * (kShellThreads / 64)];
-  const int bx = blockIdx.z, by = blockIdx.y, bz = blockIdx.x;
-  const int2 range = shell_range(bx, by, bz, g);
-  if (range.x > range.y) return;   // block-uniform: every node lies beyond the last shell
-  const size_t blk = ((size_t)bx * gridDim.y + by) * gridDim.x + bz;
-  constexpr int K = kShellNodes / kShellThreads;
-  double va[K], vb[K];
-  int sh[K];
-  const int half = g.n / 2;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = threadIdx.x + k * kShellThreads;
-    const int x = bx * kShellTX + i / (kShellTY * kShellTZ);
-    const int y = by * kShellTY + (i / kShellTZ) % kShellTY;
-    const int z = bz * kShellTZ + i % kShellTZ;
-    const size_t node = ((size_t)x * g.n + y) * g.n + z;
-    const int rx = x - half, ry = y - half, rz = z - half;
-    sh[k] = shell_index(rx * rx + ry * ry + rz * rz, g);
-    va[k] = a[node];
-    vb[k] = b ? b[node] : 0.0;
+  __shared__ double red[kShellValues * (kShellThreads / 64)];
+  const int x = blockIdx.x, s = blockIdx.y, n = g.n, half = n / 2;
+  const int rx = x - half;
+  const double2 bd = shell_r2_bounds(s, g);
+  double ma = 0.0, mb = 0.0;
+  if constexpr (CENTRED) {
+    ma = out[(size_t)s * kShellOut + 1];
+    mb = out[(size_t)s * kShellOut + 3];
   }
-  const int last = min(range.y, range.x + g.slots - 1);
-  for (int s0 = range.x; s0 <= last; s0 += kShellsPerReduce) {
-    double acc[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) acc[v] = 0.0;
-#pragma unroll
-    for (int j = 0; j < kShellsPerReduce; ++j) {
-      const int s = s0 + j;
-      if (s > last) break;
-      double ma = 0.0, mb = 0.0;
-      if constexpr (CENTRED) {
-        ma = out[(size_t)s * kShellOut + 1];
-        mb = out[(size_t)s * kShellOut + 3];
-      }
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (sh[k] == s) {
+  double acc[kShellValues] = {0.0, 0.0, 0.0};
+  const double reach = bd.y - (double)rx * rx;   // ry^2 + rz^2 at most this
+  if (reach >= 0.0) {
+    const double ry_reach = sqrt(reach);   // (compared before any conversion: a wide shell can reach far)
+    const int ry_max = ry_reach >= half ? half : min((int)floor(ry_reach) + 1, half);
+    const int group = threadIdx.x / kShellGroup, lane = threadIdx.x % kShellGroup;
+    constexpr int kGroups = kShellThreads / kShellGroup;
+    for (int ry = -ry_max + group; ry <= min(ry_max, half - 1); ry += kGroups) {
+      const int rho2 = rx * rx + ry * ry;
+      const double hi = bd.y - rho2;
+      if (hi < 0.0) continue;
+      const double lo = bd.x - rho2, slo = lo <= 0.0 ? 0.0 : sqrt(lo), shi = sqrt(hi);
+      if (slo > half + 1) continue;   // the shell starts beyond this row's nodes
+      const int a0 = max(0, (int)floor(slo) - 1);
+      const int a1 = shi >= half ? half : (int)ceil(shi) + 1;
+      const size_t row = ((size_t)x * n + (ry + half)) * n + half;   // node of r_z = 0
+      // the runs r_z in [-a1, -a0] and [a0, a1] (one run when a0 = 0),
+      // clipped to the grid's r_z in [-N/2, N/2 - 1]
+      for (int run = 0; run < 2; ++run) {
+        int z0, z1;
+        if (run == 0) {
+          z0 = -min(a1, half);
+          z1 = a0 == 0 ? min(a1, half - 1) : -a0;
+        } else {
+          if (a0 == 0) break;
+          z0 = a0;
+          z1 = min(a1, half - 1);
+        }
+        for (int rz = z0 + lane; rz <= z1; rz += kShellGroup) {
+          if (shell_index(rho2 + rz * rz, g) != s) continue;
+          const size_t node = row + rz;
+          const double va = a[node], vb = b ? b[node] : 0.0;
           if constexpr (CENTRED) {
-            const double da = va[k] - ma, db = vb[k] - mb;
-            acc[3 * j + 0] += da * da;
-            acc[3 * j + 1] += db * db;
-            acc[3 * j + 2] += da * db;
+            const double da = va - ma, db = vb - mb;
+            acc[0] += da * da;
+            acc[1] += db * db;
+            acc[2] += da * db;
           } else {
-            acc[3 * j + 0] += 1.0;
-            acc[3 * j + 1] += va[k];
-            acc[3 * j + 2] += vb[k];
+            acc[0] += 1.0;
+            acc[1] += va;
+            acc[2] += vb;
           }
         }
       }
     }
-    block_sums<V>(acc, red);
-    if (threadIdx.x == 0) {
-      for (int j = 0; j < kShellsPerReduce && s0 + j <= last; ++j) {
+  }
+  block_sums<kShellValues>(acc, red);
+  if (threadIdx.x == 0) {
 #pragma unroll
-        for (int v = 0; v < kShellValues; ++v)
-          part[(blk * g.slots + (s0 + j - range.x)) * kShellValues + v] = acc[3 * j + v];
-      }
-    }
+    for (int v = 0; v < kShellValues; ++v) part[((size_t)s * n + x) * kShellValues + v] = acc[v];
   }
 }
 
-// Stage 2 of a sweep: one block per shell.  out[s * 6 + ...] = count,
-// mean a, scatter a, mean b, scatter b, correlation; sweep 1 writes the
-// count and the means, sweep 2 the rest.  NaN where undefined: an empty
-// shell, or a field constant over it (its correlation).
+// Stage 2 of a sweep: one block per shell adds its N plane partials in x
+// order.  out[s * 6 + ...] = count, mean a, scatter a, mean b, scatter b,
+// correlation; sweep 1 writes the count and the means, sweep 2 the rest.
+// NaN where undefined: an empty shell, or a field constant over it (its
+// correlation).
 template <bool CENTRED>
 __global__ void __launch_bounds__(kShellFinishThreads)
 k_shell_finish(const double* __restrict__ part, ShellGeom g, double* __restrict__ out) {
   __shared__ double red[kShellValues * (kShellFinishThreads / 64)];
   const int s = blockIdx.x;
-  const int nbx = g.n / kShellTX, nby = g.n / kShellTY, nbz = g.n / kShellTZ;
-  const int blocks = nbx * nby * nbz;
   double acc[kShellValues] = {0.0, 0.0, 0.0};
-  for (int blk = threadIdx.x; blk < blocks; blk += kShellFinishThreads) {
-    const int bz = blk % nbz, by = (blk / nbz) % nby, bx = blk / (nbz * nby);
-    const int2 range = shell_range(bx, by, bz, g);
-    if (s < range.x || s > range.y || s - range.x >= g.slots) continue;
-    const double* p = part + ((size_t)blk * g.slots + (s - range.x)) * kShellValues;
+  for (int x = threadIdx.x; x < g.n; x += kShellFinishThreads) {
+    const double* p = part + ((size_t)s * g.n + x) * kShellValues;
 #pragma unroll
     for (int v = 0; v < kShellValues; ++v) acc[v] += p[v];
   }
@@ -305,17 +292,17 @@ k_shell_finish(const double* __restrict__ part, ShellGeom g, double* __restrict_
     const double nan = __builtin_nan("");
     double* o = out + (size_t)s * kShellOut;
     if constexpr (!CENTRED) {
-      const double n = acc[0];
-      o[0] = n;
-      o[1] = n > 0.0 ? acc[1] / n : nan;
-      o[3] = n > 0.0 ? acc[2] / n : nan;
+      const double cnt = acc[0];
+      o[0] = cnt;
+      o[1] = cnt > 0.0 ? acc[1] / cnt : nan;
+      o[3] = cnt > 0.0 ? acc[2] / cnt : nan;
     } else {
-      const double n = o[0];
-      if (n > 0.0) {
-        const double va = acc[0] / n, vb = acc[1] / n;
+      const double cnt = o[0];
+      if (cnt > 0.0) {
+        const double va = acc[0] / cnt, vb = acc[1] / cnt;
         o[2] = sqrt(va);
         o[4] = sqrt(vb);
-        o[5] = (va > 0.0 && vb > 0.0) ? (acc[2] / n) / sqrt(va * vb) : nan;
+        o[5] = (va > 0.0 && vb > 0.0) ? (acc[2] / cnt) / sqrt(va * vb) : nan;
       } else {
         o[2] = o[4] = o[5] = nan;
       }

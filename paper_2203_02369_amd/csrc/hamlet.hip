@@ -1892,7 +1892,7 @@ extern "C" hamlet_status hamlet_field_stats_accumulate(hamlet_plan* plan, const 
 // names a host-side stand-in, not a device address: the array's address on
 // each device is looked up once, with that device current, and only that
 // address reaches kernels.
-constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+constexpr size_t kStaticScratchBytes = size_t(4) << 20;
 static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
 
 static hamlet_status static_scratch(int device, double** out) {
@@ -1926,22 +1926,16 @@ static hamlet_status shell_stats_run(hamlet_plan* plan, const double* a, const d
     return fail(HAMLET_EINVAL, "n_shells %d outside [0, %d]", (int)n_shells, kShellMax);
   if (!(width > 0.0) || !std::isfinite(width)) return fail(HAMLET_EINVAL, "shell width %g is not positive", width);
   if (n_shells == 0) return HAMLET_OK;
-  ShellGeom g{plan->box / plan->n, width, plan->n, (int)n_shells, 1};
-  const int nbx = plan->n / kShellTX, nby = plan->n / kShellTY, nbz = plan->n / kShellTZ;
-  // A tile's nearest and farthest nodes are at most its diagonal apart, so
-  // it reaches at most diagonal / width + 2 shells; one more for rounding.
-  const double diag = g.h * std::sqrt((double)((kShellTX - 1) * (kShellTX - 1) + (kShellTY - 1) * (kShellTY - 1) +
-                                               (kShellTZ - 1) * (kShellTZ - 1)));
-  const double bound = std::floor(diag / width) + 3.0;
-  g.slots = (int)std::min(bound, (double)n_shells + 1.0);
-  const size_t bytes = (size_t)nbx * nby * nbz * g.slots * kShellValues * sizeof(double);
+  const ShellGeom g{plan->box / plan->n, width, plan->n, (int)n_shells};
+  // one partial per shell and x plane
+  const size_t bytes = (size_t)n_shells * plan->n * kShellValues * sizeof(double);
   double* part = nullptr;
   if (fixed) {
     if (bytes > kStaticScratchBytes)
       return fail(HAMLET_EINVAL,
-                  "shell partials need %zu bytes (%d shells per %dx%dx%d tile on %d^3), the static scratch holds %zu: "
-                  "use wider or fewer shells, or hamlet_shell_stats",
-                  bytes, g.slots, kShellTX, kShellTY, kShellTZ, plan->n, kStaticScratchBytes);
+                  "shell partials need %zu bytes (%d shells x %d planes), the static scratch holds %zu: "
+                  "use fewer shells, or hamlet_shell_stats",
+                  bytes, (int)n_shells, plan->n, kStaticScratchBytes);
     hamlet_status st = static_scratch(plan->device, &part);
     if (st != HAMLET_OK) return st;
   } else if (hipMallocAsync((void**)&part, bytes, plan->stream) != hipSuccess) {
@@ -1949,9 +1943,10 @@ static hamlet_status shell_stats_run(hamlet_plan* plan, const double* a, const d
   }
   // the means, then the centred sums (both sweeps reuse the partials; every
   // partial the finish stage reads is written by the part stage before it)
-  k_shell_part<false><<<dim3(nbz, nby, nbx), kShellThreads, 0, plan->stream>>>(a, b, g, out, part);
+  const dim3 grid(plan->n, n_shells);
+  k_shell_part<false><<<grid, kShellThreads, 0, plan->stream>>>(a, b, g, out, part);
   k_shell_finish<false><<<n_shells, kShellFinishThreads, 0, plan->stream>>>(part, g, out);
-  k_shell_part<true><<<dim3(nbz, nby, nbx), kShellThreads, 0, plan->stream>>>(a, b, g, out, part);
+  k_shell_part<true><<<grid, kShellThreads, 0, plan->stream>>>(a, b, g, out, part);
   k_shell_finish<true><<<n_shells, kShellFinishThreads, 0, plan->stream>>>(part, g, out);
   const hipError_t le = hipGetLastError();
   if (!fixed) HIP_TRY(hipFreeAsync(part, plan->stream));

@@ -70,8 +70,8 @@ def test_static_scratch_equals_the_allocating_call(hl):
 
 
 def test_static_scratch_refuses_oversized_partials(hl):
-    # 4096 shells of 0.01 Mpc/h on 64^3: every 4x8x16 tile would need a slot
-    # per shell, 512 tiles x 4097 slots x 24 bytes > 32 MiB
+    # 4096 shells of 0.01 Mpc/h on 64^3: one partial per shell and x plane,
+    # 4096 x 64 x 24 bytes > 4 MiB
     m = mocks.make_mock(64, 500.0, 10, 50.0, seed=3)
     plan = hl.Plan.from_mock(m, precision="fp64")
     a, b = _fields(64, plan.device, 7)
