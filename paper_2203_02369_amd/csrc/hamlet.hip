@@ -102,7 +102,7 @@ struct hamlet_plan {
   // workspace addresses used by the host
   PlanConst* consts = nullptr;
   ChainScalars* cs = nullptr;
-  double *var = nullptr, *mvar = nullptr, *hist = nullptr, *mom_part = nullptr;
+  double *var = nullptr, *mvar = nullptr, *hist = nullptr, *mom_part = nullptr, *wtab = nullptr;
   void* tw = nullptr;
   double *rhat = nullptr, *mu = nullptr, *smu = nullptr, *cz = nullptr, *scz = nullptr;
   int *count = nullptr, *off = nullptr, *most = nullptr;
@@ -470,6 +470,7 @@ template <typename T, int N> static void locate_impl(hamlet_plan* pl) {
   pl->var = w.var_n2();
   pl->mvar = w.mvar();
   pl->mom_part = w.template at<double>(F::mom_part);
+  pl->wtab = w.template at<double>(F::wtab);
   pl->hist = w.hist(pl->n_gal);
   pl->tw = w.tw();
   pl->rhat = w.rhat(); pl->mu = w.mu(); pl->smu = w.smu(); pl->cz = w.cz(); pl->scz = w.scz();
@@ -1970,8 +1971,11 @@ extern "C" hamlet_status hamlet_shell_stats_static(hamlet_plan* plan, const doub
 template <int N>
 static void moments_pass(const hamlet_plan* pl, const double2* modes, const MomentRadii& rad, double kf,
                          double mono_scale, double dip_scale, double* part) {
-  if constexpr (has_grid(N))
-    k_sphere_moments<N><<<kMomentsBlocks, 256, 0, pl->stream>>>(modes, rad, kf, mono_scale, dip_scale, part);
+  if constexpr (has_grid(N)) {
+    constexpr int kN2 = 3 * (N / 2) * (N / 2) + 1;
+    k_sphere_window<N><<<blocks_for((size_t)kN2 * kMomentsRadiiPerPass, 256), 256, 0, pl->stream>>>(rad, kf, pl->wtab);
+    k_sphere_moments<N><<<kMomentsBlocks, 256, 0, pl->stream>>>(modes, rad, pl->wtab, mono_scale, dip_scale, part);
+  }
 }
 
 extern "C" hamlet_status hamlet_sphere_moments(hamlet_plan* plan, const void* modes, const double* radii,

@@ -91,7 +91,7 @@ constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // per pass over the modes, blocks of a pass (one partial sum per block and
 // value), values per pass.
 constexpr int kMomentsMaxRadii = 16;
-constexpr int kMomentsRadiiPerPass = 4;
+constexpr int kMomentsRadiiPerPass = 8;
 constexpr int kMomentsBlocks = 1024;
 constexpr int kMomentsPassValues = 4 * kMomentsRadiiPerPass;
 constexpr size_t kMomentsPartBytes =
@@ -122,7 +122,8 @@ template <int N, int R> struct FixedLayout {
   static constexpr size_t kin_part = align256(prior_part + 8 * size_t(N_PRIOR));
   static constexpr size_t small = align256(kin_part + 8 * size_t(N_KIN));   // qs0, ps, eps_slot, most, ticket, cosmo_eval
   static constexpr size_t mom_part = align256(small + 256);       // sphere-moment partial sums
-  static constexpr size_t mvar = align256(mom_part + kMomentsPartBytes);
+  static constexpr size_t wtab = align256(mom_part + kMomentsPartBytes);   // sphere window by |n|^2, one pass
+  static constexpr size_t mvar = align256(wtab + 8 * size_t(kMomentsRadiiPerPass) * NPK);
   static constexpr size_t a = align256(mvar + 8 * NM);
   static constexpr size_t b = a + 2 * R * NM;
   static constexpr size_t v0 = b + 2 * R * NM;
