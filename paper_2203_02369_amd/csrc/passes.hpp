@@ -1018,7 +1018,17 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
   // trajectory (K0), after the last kick (K1)
   constexpr bool kStartOfChain = CHAIN && MODE == kXFirst;
   constexpr bool kKinetic = kStartOfChain || MODE == kXLast;
-  __shared__ C tile[LAY::size(N)];
+  // Paired tiles: where two tiles fit the LDS of two blocks per compute
+  // unit, S2 and S1 sit side by side (columns [0, W) and [W, 2W)) and are
+  // transformed as one batch of 2W columns, and so are the next A and B: two
+  // transforms instead of four, with every thread busy in each stage (a
+  // W-wide batch of 256-point transforms has half as many butterflies per
+  // stage as 512 threads), and no tile held in registers across a transform.
+  // Otherwise one tile at a time.
+  constexpr bool kPair = 2 * LAY::size(N) * (int)sizeof(C) <= 72 * 1024;
+  using LAY2 = RowLayout<C, 2 * S::W>;
+  constexpr int kTileSize = kPair ? LAY2::size(N) : LAY::size(N);
+  __shared__ C tile[kTileSize];
   __shared__ C twl[N];
   __shared__ double red[2 * (NT / 64)];
   // twiddles into LDS once the first tile loads are issued
@@ -1027,14 +1037,24 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
   const int2 tl = strided_tile<T, N>();
   const int y = tl.y, z0 = tl.x * S::W;
   const int sy = signed_freq(y, N);
-  C acc[elems_per_thread<T, N, NT>()];
+  C acc[kPair ? 1 : elems_per_thread<T, N, NT>()];
   // complex64 momenta of a leapfrog step are loaded before the second
-  // transform, whose time hides their latency (complex128 ones, or more than
-  // eight per thread, would spill)
+  // forward transform of unpaired tiles, whose time hides their latency
+  // (complex128 ones, more than eight per thread, or across a paired
+  // transform, they would spill)
   constexpr bool kPrefetchP =
-      kFromSpectra && MODE != kXGrad && sizeof(Q) == 8 && elems_per_thread<T, N, NT>() <= 8;
+      kFromSpectra && !kPair && MODE != kXGrad && sizeof(Q) == 8 && elems_per_thread<T, N, NT>() <= 8;
   Q ppf[elems_per_thread<T, N, NT>()];
-  if constexpr (kFromSpectra) {
+  if constexpr (kFromSpectra && kPair) {
+    tile_vecs<T, N, NT>([&](int, int x, int w) { vec_to_lds<T, LAY2>(tile, x, w, vec_load<T>(&s2[gofs<N>(x, y, z0 + w)])); });
+    tile_vecs<T, N, NT>(
+        [&](int, int x, int w) { vec_to_lds<T, LAY2>(tile, x, S::W + w, vec_load<T>(&s1[gofs<N>(x, y, z0 + w)])); });
+    if constexpr (kPrefetchP)
+      tile_elems<T, N, NT>([&](int e, int x, int w) { ppf[e] = ld_stream(&mom[gofs<N>(x, y, z0 + w)]); });
+    tws.store(twl);
+    __syncthreads();
+    lds_fft<T, N, 2 * S::W, LAY2, NT, -1>(tile, twl);
+  } else if constexpr (kFromSpectra) {
     tile_vecs<T, N, NT>([&](int, int x, int w) { vec_to_lds<T, LAY>(tile, x, w, vec_load<T>(&s2[gofs<N>(x, y, z0 + w)])); });
     tws.store(twl);
     __syncthreads();
@@ -1054,8 +1074,9 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
   const double eps = MODE == kXGrad ? 0.0 : eps_ptr[0];
   const double hk = MODE == kXMid ? eps : 0.5 * eps;
   CSum prior, kin;
-  // B-input of the next inverse pass (n_x times the A-input), kept in registers
-  C bin[elems_per_thread<T, N, NT>()];
+  // B-input of the next inverse pass (n_x times the A-input), kept in
+  // registers, or in the tile's second half when paired
+  C bin[kPair ? 1 : elems_per_thread<T, N, NT>()];
   tile_elems<T, N, NT>([&](int e, int x, int w) {
     const int kz = z0 + w, sx = signed_freq(x, N);
     const size_t g = gofs<N>(x, y, kz);
@@ -1068,7 +1089,11 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
     double2 G = make_double2(0.0, 0.0);
     if constexpr (kFromSpectra) {
       if (keep) {
-        const C tv = cadd(acc[e], tile[LAY::idx(x, w)]);
+        C tv;
+        if constexpr (kPair)
+          tv = cadd(cscale(tile[LAY2::idx(x, w)], (T)sx), tile[LAY2::idx(x, S::W + w)]);
+        else
+          tv = cadd(acc[e], tile[LAY::idx(x, w)]);
         const double iv2 = 2.0 * inv_or_zero(var) * tab.inv_a, kf2 = 2.0 * mode_kfac(tab.kfac_adj, n2);
         // -2 i kfac t = (2 kfac t.y, -2 kfac t.x)
         G = make_double2(iv2 * q.x + kf2 * (double)tv.y, iv2 * q.y - kf2 * (double)tv.x);
@@ -1136,8 +1161,15 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
           const double kf = mode_kfac(tab.kfac0, n2);
           a = make_double2(-kf * q.y, kf * q.x);      // i kfac q
         }
-        acc[e] = cconvert<C>(a);                       // A-input (acc is free now)
-        bin[e] = cconvert<C>(make_double2((double)sx * a.x, (double)sx * a.y));
+        const C ain = cconvert<C>(a), bn = cconvert<C>(make_double2((double)sx * a.x, (double)sx * a.y));
+        if constexpr (kPair) {
+          // over this element's own spectra, which only this thread reads
+          tile[LAY2::idx(x, w)] = ain;
+          tile[LAY2::idx(x, S::W + w)] = bn;
+        } else {
+          acc[e] = ain;                                // A-input (acc is free now)
+          bin[e] = bn;
+        }
       }
     }
   });
@@ -1147,7 +1179,16 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
   } else {
     (void)kin;
   }
-  if constexpr (kDrift) {
+  if constexpr (kDrift && kPair) {
+    const double ps = block_csum(prior, red);
+    if (threadIdx.x == 0) prior_part[blockIdx.y * gridDim.x + blockIdx.x] = ps;
+    __syncthreads();
+    lds_fft<T, N, 2 * S::W, LAY2, NT, +1>(tile, twl);
+    tile_vecs<T, N, NT>([&](int, int x, int w) { vec_store<T>(&outA[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY2>(tile, x, w)); });
+    tile_vecs<T, N, NT>(
+        [&](int, int x, int w) { vec_store<T>(&outB[gofs<N>(x, y, z0 + w)], vec_from_lds<T, LAY2>(tile, x, S::W + w)); });
+    (void)bin;
+  } else if constexpr (kDrift) {
     const double ps = block_csum(prior, red);
     if (threadIdx.x == 0) prior_part[blockIdx.y * gridDim.x + blockIdx.x] = ps;
     __syncthreads();
