@@ -345,7 +345,9 @@ def hmc_run(plans, q_modes, q_dist, q_snl, *, n_iter, n_leapfrog, eps0, seed, wa
 
     Chain j's key is seeds[j] when given, else seed + j.  resume=True
     continues each plan's chain from its previous run (then dh/accepted are
-    indexed by the chain's own iteration count)."""
+    indexed by the chain's own iteration count).  An FP32 plan's chain runs
+    on complex64 modes: its retained modes come back rounded to complex64,
+    its other entries as given."""
     plans, hp = _plans(plans)
     nplan = len(plans)
     qm = [_check(t, p, "modes", "q_modes") for t, p in zip(q_modes, plans)]
