@@ -50,9 +50,9 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE x 1.0000).  Bytes read and written per launch for the
 # plain-gradient, first, middle and last variants.  Valid only for the kernel
 # sources and the 256^3 FP32 schedule they were taken on (hash below).
-X_TRAFFIC_SOURCES_SHA1 = "85d2bdc1995d1ffd935ca747555cdd1128b2498c"
-X_TRAFFIC = {"grad": (267520499, 67108864), "first": (201450252, 402262829),
-             "mid": (334786617, 267978739), "last": (334696287, 134283273)}
+X_TRAFFIC_SOURCES_SHA1 = "9e46300b20a5b8024faa96d2813c0b7ffaab4eaf"
+X_TRAFFIC = {"grad": (268557978, 67108864), "first": (201956438, 402806974),
+             "mid": (335807401, 268506150), "last": (335733054, 134283580)}
 
 # below this acceptance rate a chain hardly samples: the comparison of the two
 # paths "at equal acceptance" would be void, and the run reports failure

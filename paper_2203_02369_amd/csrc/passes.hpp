@@ -1077,15 +1077,21 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
   // B-input of the next inverse pass (n_x times the A-input), kept in
   // registers, or in the tile's second half when paired
   C bin[kPair ? 1 : elems_per_thread<T, N, NT>()];
-  tile_elems<T, N, NT>([&](int e, int x, int w) {
+  // The update of element (x, w) of the tile.  Its state in the storage
+  // type goes through io: q() the mode, p() the momentum, g_() the cached
+  // gradient, and set_q/p/gc/q0/g0 what it writes (the mode where it drifts,
+  // the momentum, the cached gradient of the plain gradient and the last
+  // step, the kept start point).  ElemIo reads and writes the arrays where
+  // the update needs them; PairIo holds two elements in registers for the
+  // caller to move as one 16-byte access.
+  auto step = [&](int e, int x, int w, double var_ld, auto& io) {
     const int kz = z0 + w, sx = signed_freq(x, N);
-    const size_t g = gofs<N>(x, y, kz);
     const bool keep = retained(sx, sy, kz, N);
     const int n2 = sx * sx + sy * sy + kz * kz;
-    const double var = keep ? ld_stream(&tab.var[var_ofs(N, S::W, x, y, kz)]) : 0.0;
+    const double var = keep ? var_ld : 0.0;
     // the mode, read once (gradient and drift)
     double2 q = make_double2(0.0, 0.0);
-    if (kStartOfChain || (keep && (kFromSpectra || kDrift))) q = widen(ld_stream(&modes[g]));
+    if (kStartOfChain || (keep && (kFromSpectra || kDrift))) q = widen(io.q());
     double2 G = make_double2(0.0, 0.0);
     if constexpr (kFromSpectra) {
       if (keep) {
@@ -1099,19 +1105,19 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
         G = make_double2(iv2 * q.x + kf2 * (double)tv.y, iv2 * q.y - kf2 * (double)tv.x);
       }
     } else {
-      G = widen(ld_stream(&gcache[g]));
+      G = widen(io.g_());
     }
     if constexpr (MODE == kXGrad) {
       // plane_scale 0.5: gradient per stored entry (each Hermitian partner of
       // the kz = 0 plane taken as its own variable carries half)
-      st_stream(&gcache[g], narrow<Q>(kz == 0 ? make_double2(plane_scale * G.x, plane_scale * G.y) : G));
+      io.set_gc(narrow<Q>(kz == 0 ? make_double2(plane_scale * G.x, plane_scale * G.y) : G));
     }
-    if constexpr (MODE == kXLast) st_stream(&gcache[g], narrow<Q>(G));
+    if constexpr (MODE == kXLast) io.set_gc(narrow<Q>(G));
     if constexpr (kStartOfChain) {
       // the start of the trajectory, kept for a rejection (both already in
       // the storage type)
-      st_stream(&reinterpret_cast<Q*>(save.q0)[g], narrow<Q>(q));
-      st_stream(&reinterpret_cast<Q*>(save.g0)[g], narrow<Q>(G));
+      io.set_q0(narrow<Q>(q));
+      io.set_g0(narrow<Q>(G));
     }
     if constexpr (MODE != kXGrad) {
       double2 p = make_double2(0.0, 0.0);
@@ -1122,21 +1128,20 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
         // nx > 0) takes the conjugate of the partner's draw
         if (keep) {
           const bool mirror = kz == 0 && (sy < 0 || (sy == 0 && sx < 0));
-          const size_t src = mirror ? gofs<N>((N - x) & (N - 1), (N - y) & (N - 1), 0) : g;
+          const size_t src = mirror ? gofs<N>((N - x) & (N - 1), (N - y) & (N - 1), 0) : gofs<N>(x, y, kz);
           const double2 z = normal_pair(draw_words(save.seed, save.iteration, kPurposeModes, src));
           const double sc = sqrt(2.0 * inv_or_zero(var));
           // drawn in FP64; K0 and the kick take the value as stored
           p = rounded<Q>(make_double2(sc * z.x, mirror ? -sc * z.y : sc * z.y));
         }
-      } else if constexpr (kPrefetchP) {
-        p = widen(ppf[e]);
       } else {
-        p = widen(ld_stream(&mom[g]));
+        p = widen(io.p());
       }
       if constexpr (MODE == kXFirst && !CHAIN) {
         // the state this step starts from, kept where the caller asks (the
         // callers outside chains hold complex128 states)
         static_assert(sizeof(Q) == 16, "complex128 state outside chains");
+        const size_t g = gofs<N>(x, y, kz);
         if (save.sv_q) st_stream(&save.sv_q[g], narrow<double2>(q));
         if (save.sv_p) st_stream(&save.sv_p[g], narrow<double2>(p));
       }
@@ -1148,7 +1153,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
       p.y -= hk * G.y;
       p = rounded<Q>(p);
       if (MODE == kXLast && keep) kin.add(wk * var * (p.x * p.x + p.y * p.y));
-      st_stream(&mom[g], narrow<Q>(p));
+      io.set_p(narrow<Q>(p));
       if constexpr (kDrift) {
         double2 a = make_double2(0.0, 0.0);
         if (keep) {
@@ -1156,7 +1161,7 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
           q.x += c * p.x;
           q.y += c * p.y;
           q = rounded<Q>(q);   // the prior energy and the next gradient are those of the stored modes
-          st_stream(&modes[g], narrow<Q>(q));
+          io.set_q(narrow<Q>(q));
           prior.add((kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(var));
           const double kf = mode_kfac(tab.kfac0, n2);
           a = make_double2(-kf * q.y, kf * q.x);      // i kfac q
@@ -1172,7 +1177,76 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
         }
       }
     }
-  });
+  };
+  // Complex64 chain state in paired tiles: two consecutive kz per lane, so
+  // that the modes, momenta, cached gradient and sigma^2 move as 16-byte
+  // accesses like the spectra (half the memory instructions of one mode per
+  // lane: the middle step 158 -> 138 us at 256^3).  Otherwise one element per
+  // lane (16-byte complex128 state, or tiles held in registers).
+  constexpr bool kPairedState = kPair && sizeof(Q) == 8 && ColVec<T>::K == 2;
+  struct ElemIo {
+    Q *modes, *mom, *gcache, *q0, *g0;
+    size_t g;
+    const Q* pre;   // the momentum loaded ahead, or nullptr
+    __device__ Q q() const { return ld_stream(&modes[g]); }
+    __device__ Q p() const { return pre ? *pre : ld_stream(&mom[g]); }
+    __device__ Q g_() const { return ld_stream(&gcache[g]); }
+    __device__ void set_q(Q v) const { st_stream(&modes[g], v); }
+    __device__ void set_p(Q v) const { st_stream(&mom[g], v); }
+    __device__ void set_gc(Q v) const { st_stream(&gcache[g], v); }
+    __device__ void set_q0(Q v) const { st_stream(&q0[g], v); }
+    __device__ void set_g0(Q v) const { st_stream(&g0[g], v); }
+  };
+  struct PairIo {
+    Q qs, ps, gs, q0s, g0s;
+    __device__ Q q() const { return qs; }
+    __device__ Q p() const { return ps; }
+    __device__ Q g_() const { return gs; }
+    __device__ void set_q(Q v) { qs = v; }
+    __device__ void set_p(Q v) { ps = v; }
+    __device__ void set_gc(Q v) { gs = v; }
+    __device__ void set_q0(Q v) { q0s = v; }
+    __device__ void set_g0(Q v) { g0s = v; }
+  };
+  Q* const q0a = reinterpret_cast<Q*>(save.q0);
+  Q* const g0a = reinterpret_cast<Q*>(save.g0);
+  if constexpr (kPairedState) {
+    struct alignas(16) QPair { Q v[2]; };
+    tile_vecs<T, N, NT>([&](int, int x, int w) {   // w even: elements w and w + 1
+      const size_t g = gofs<N>(x, y, z0 + w);
+      const double2 var2 = ld_stream(reinterpret_cast<const double2*>(&tab.var[var_ofs(N, S::W, x, y, z0 + w)]));
+      const QPair qv = ld_stream(reinterpret_cast<const QPair*>(&modes[g]));
+      QPair pv{}, gv{};
+      if constexpr (!kFromSpectra) gv = ld_stream(reinterpret_cast<const QPair*>(&gcache[g]));
+      if constexpr (MODE != kXGrad && !kStartOfChain) pv = ld_stream(reinterpret_cast<const QPair*>(&mom[g]));
+      PairIo io[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        io[j].qs = qv.v[j];   // (an excluded mode is written back as it was read)
+        io[j].ps = pv.v[j];
+        io[j].gs = gv.v[j];
+      }
+      step(0, x, w, var2.x, io[0]);
+      step(0, x, w + 1, var2.y, io[1]);
+      if constexpr (MODE == kXGrad || MODE == kXLast)
+        st_stream(reinterpret_cast<QPair*>(&gcache[g]), QPair{{io[0].gs, io[1].gs}});
+      if constexpr (kStartOfChain) {
+        st_stream(reinterpret_cast<QPair*>(&q0a[g]), QPair{{io[0].q0s, io[1].q0s}});
+        st_stream(reinterpret_cast<QPair*>(&g0a[g]), QPair{{io[0].g0s, io[1].g0s}});
+      }
+      if constexpr (MODE != kXGrad) st_stream(reinterpret_cast<QPair*>(&mom[g]), QPair{{io[0].ps, io[1].ps}});
+      if constexpr (kDrift) st_stream(reinterpret_cast<QPair*>(&modes[g]), QPair{{io[0].qs, io[1].qs}});
+    });
+  } else {
+    tile_elems<T, N, NT>([&](int e, int x, int w) {
+      const int kz = z0 + w;
+      const bool keep = retained(signed_freq(x, N), sy, kz, N);
+      const double var_ld = keep ? ld_stream(&tab.var[var_ofs(N, S::W, x, y, kz)]) : 0.0;
+      ElemIo io{modes, mom, gcache, q0a, g0a, gofs<N>(x, y, kz), nullptr};
+      if constexpr (kPrefetchP) io.pre = &ppf[e];
+      step(e, x, w, var_ld, io);
+    });
+  }
   if constexpr (kKinetic) {
     const double ks = block_csum(kin, red);
     if (threadIdx.x == 0) save.kin_part[blockIdx.y * gridDim.x + blockIdx.x] = ks;
