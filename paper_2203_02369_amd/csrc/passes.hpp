@@ -1077,126 +1077,14 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
   // B-input of the next inverse pass (n_x times the A-input), kept in
   // registers, or in the tile's second half when paired
   C bin[kPair ? 1 : elems_per_thread<T, N, NT>()];
-  // The update of element (x, w) of the tile.  Its state in the storage
-  // type goes through io: q() the mode, p() the momentum, g_() the cached
-  // gradient, and set_q/p/gc/q0/g0 what it writes (the mode where it drifts,
-  // the momentum, the cached gradient of the plain gradient and the last
-  // step, the kept start point).  ElemIo reads and writes the arrays where
-  // the update needs them; PairIo holds two elements in registers for the
-  // caller to move as one 16-byte access.
-  auto step = [&](int e, int x, int w, double var_ld, auto& io) {
-    const int kz = z0 + w, sx = signed_freq(x, N);
-    const bool keep = retained(sx, sy, kz, N);
-    const int n2 = sx * sx + sy * sy + kz * kz;
-    const double var = keep ? var_ld : 0.0;
-    // the mode, read once (gradient and drift)
-    double2 q = make_double2(0.0, 0.0);
-    if (kStartOfChain || (keep && (kFromSpectra || kDrift))) q = widen(io.q());
-    double2 G = make_double2(0.0, 0.0);
-    if constexpr (kFromSpectra) {
-      if (keep) {
-        C tv;
-        if constexpr (kPair)
-          tv = cadd(cscale(tile[LAY2::idx(x, w)], (T)sx), tile[LAY2::idx(x, S::W + w)]);
-        else
-          tv = cadd(acc[e], tile[LAY::idx(x, w)]);
-        const double iv2 = 2.0 * inv_or_zero(var) * tab.inv_a, kf2 = 2.0 * mode_kfac(tab.kfac_adj, n2);
-        // -2 i kfac t = (2 kfac t.y, -2 kfac t.x)
-        G = make_double2(iv2 * q.x + kf2 * (double)tv.y, iv2 * q.y - kf2 * (double)tv.x);
-      }
-    } else {
-      G = widen(io.g_());
-    }
-    if constexpr (MODE == kXGrad) {
-      // plane_scale 0.5: gradient per stored entry (each Hermitian partner of
-      // the kz = 0 plane taken as its own variable carries half)
-      io.set_gc(narrow<Q>(kz == 0 ? make_double2(plane_scale * G.x, plane_scale * G.y) : G));
-    }
-    if constexpr (MODE == kXLast) io.set_gc(narrow<Q>(G));
-    if constexpr (kStartOfChain) {
-      // the start of the trajectory, kept for a rejection (both already in
-      // the storage type)
-      io.set_q0(narrow<Q>(q));
-      io.set_g0(narrow<Q>(G));
-    }
-    if constexpr (MODE != kXGrad) {
-      double2 p = make_double2(0.0, 0.0);
-      if constexpr (kStartOfChain) {
-        // momentum refresh p ~ N(0, M): Re and Im of a retained mode each
-        // with variance 2 / sigma_k^2; an entry of the kz = 0 plane whose
-        // Hermitian partner (-kx, -ky, 0) is canonical (ny > 0, or ny = 0 and
-        // nx > 0) takes the conjugate of the partner's draw
-        if (keep) {
-          const bool mirror = kz == 0 && (sy < 0 || (sy == 0 && sx < 0));
-          const size_t src = mirror ? gofs<N>((N - x) & (N - 1), (N - y) & (N - 1), 0) : gofs<N>(x, y, kz);
-          const double2 z = normal_pair(draw_words(save.seed, save.iteration, kPurposeModes, src));
-          const double sc = sqrt(2.0 * inv_or_zero(var));
-          // drawn in FP64; K0 and the kick take the value as stored
-          p = rounded<Q>(make_double2(sc * z.x, mirror ? -sc * z.y : sc * z.y));
-        }
-      } else {
-        p = widen(io.p());
-      }
-      if constexpr (MODE == kXFirst && !CHAIN) {
-        // the state this step starts from, kept where the caller asks (the
-        // callers outside chains hold complex128 states)
-        static_assert(sizeof(Q) == 16, "complex128 state outside chains");
-        const size_t g = gofs<N>(x, y, kz);
-        if (save.sv_q) st_stream(&save.sv_q[g], narrow<double2>(q));
-        if (save.sv_p) st_stream(&save.sv_p[g], narrow<double2>(p));
-      }
-      // per stored mode (w / 8) sigma^2 |p|^2, w = 1 on kz = 0 (both
-      // Hermitian partners stored), else 2
-      const double wk = kz == 0 ? 0.125 : 0.25;
-      if (kStartOfChain && keep) kin.add(wk * var * (p.x * p.x + p.y * p.y));
-      p.x -= hk * G.x;
-      p.y -= hk * G.y;
-      p = rounded<Q>(p);
-      if (MODE == kXLast && keep) kin.add(wk * var * (p.x * p.x + p.y * p.y));
-      io.set_p(narrow<Q>(p));
-      if constexpr (kDrift) {
-        double2 a = make_double2(0.0, 0.0);
-        if (keep) {
-          const double c = eps * (0.5 * var);
-          q.x += c * p.x;
-          q.y += c * p.y;
-          q = rounded<Q>(q);   // the prior energy and the next gradient are those of the stored modes
-          io.set_q(narrow<Q>(q));
-          prior.add((kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(var));
-          const double kf = mode_kfac(tab.kfac0, n2);
-          a = make_double2(-kf * q.y, kf * q.x);      // i kfac q
-        }
-        const C ain = cconvert<C>(a), bn = cconvert<C>(make_double2((double)sx * a.x, (double)sx * a.y));
-        if constexpr (kPair) {
-          // over this element's own spectra, which only this thread reads
-          tile[LAY2::idx(x, w)] = ain;
-          tile[LAY2::idx(x, S::W + w)] = bn;
-        } else {
-          acc[e] = ain;                                // A-input (acc is free now)
-          bin[e] = bn;
-        }
-      }
-    }
-  };
   // Complex64 chain state in paired tiles: two consecutive kz per lane, so
   // that the modes, momenta, cached gradient and sigma^2 move as 16-byte
   // accesses like the spectra (half the memory instructions of one mode per
-  // lane: the middle step 158 -> 138 us at 256^3).  Otherwise one element per
-  // lane (16-byte complex128 state, or tiles held in registers).
-  constexpr bool kPairedState = kPair && sizeof(Q) == 8 && ColVec<T>::K == 2;
-  struct ElemIo {
-    Q *modes, *mom, *gcache, *q0, *g0;
-    size_t g;
-    const Q* pre;   // the momentum loaded ahead, or nullptr
-    __device__ Q q() const { return ld_stream(&modes[g]); }
-    __device__ Q p() const { return pre ? *pre : ld_stream(&mom[g]); }
-    __device__ Q g_() const { return ld_stream(&gcache[g]); }
-    __device__ void set_q(Q v) const { st_stream(&modes[g], v); }
-    __device__ void set_p(Q v) const { st_stream(&mom[g], v); }
-    __device__ void set_gc(Q v) const { st_stream(&gcache[g], v); }
-    __device__ void set_q0(Q v) const { st_stream(&q0[g], v); }
-    __device__ void set_g0(Q v) const { st_stream(&g0[g], v); }
-  };
+  // lane: the middle step 158 -> 138 us at 256^3; at 512^3 the two elements'
+  // state spilled and the pass was 5 % slower).  Otherwise one element per
+  // lane (16-byte complex128 state, larger grids, or tiles held in
+  // registers), in the form those passes were tuned with.
+  constexpr bool kPairedState = kPair && sizeof(Q) == 8 && ColVec<T>::K == 2 && N <= 256;
   struct PairIo {
     Q qs, ps, gs, q0s, g0s;
     __device__ Q q() const { return qs; }
@@ -1208,9 +1096,109 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
     __device__ void set_q0(Q v) { q0s = v; }
     __device__ void set_g0(Q v) { g0s = v; }
   };
-  Q* const q0a = reinterpret_cast<Q*>(save.q0);
-  Q* const g0a = reinterpret_cast<Q*>(save.g0);
   if constexpr (kPairedState) {
+    Q* const q0a = reinterpret_cast<Q*>(save.q0);
+    Q* const g0a = reinterpret_cast<Q*>(save.g0);
+    // The update of element (x, w) of the tile (the same as the one-element
+    // form below).  Its state in the storage type goes through io: q() the
+    // mode, p() the momentum, g_() the cached gradient, and set_q/p/gc/q0/g0
+    // what it writes (the mode where it drifts, the momentum, the cached
+    // gradient of the plain gradient and the last step, the kept start
+    // point), held in registers for the caller to move two elements at a time.
+    auto step = [&](int e, int x, int w, double var_ld, auto& io) {
+      const int kz = z0 + w, sx = signed_freq(x, N);
+      const bool keep = retained(sx, sy, kz, N);
+      const int n2 = sx * sx + sy * sy + kz * kz;
+      const double var = keep ? var_ld : 0.0;
+      // the mode, read once (gradient and drift)
+      double2 q = make_double2(0.0, 0.0);
+      if (kStartOfChain || (keep && (kFromSpectra || kDrift))) q = widen(io.q());
+      double2 G = make_double2(0.0, 0.0);
+      if constexpr (kFromSpectra) {
+        if (keep) {
+          C tv;
+          if constexpr (kPair)
+            tv = cadd(cscale(tile[LAY2::idx(x, w)], (T)sx), tile[LAY2::idx(x, S::W + w)]);
+          else
+            tv = cadd(acc[e], tile[LAY::idx(x, w)]);
+          const double iv2 = 2.0 * inv_or_zero(var) * tab.inv_a, kf2 = 2.0 * mode_kfac(tab.kfac_adj, n2);
+          // -2 i kfac t = (2 kfac t.y, -2 kfac t.x)
+          G = make_double2(iv2 * q.x + kf2 * (double)tv.y, iv2 * q.y - kf2 * (double)tv.x);
+        }
+      } else {
+        G = widen(io.g_());
+      }
+      if constexpr (MODE == kXGrad) {
+        // plane_scale 0.5: gradient per stored entry (each Hermitian partner of
+        // the kz = 0 plane taken as its own variable carries half)
+        io.set_gc(narrow<Q>(kz == 0 ? make_double2(plane_scale * G.x, plane_scale * G.y) : G));
+      }
+      if constexpr (MODE == kXLast) io.set_gc(narrow<Q>(G));
+      if constexpr (kStartOfChain) {
+        // the start of the trajectory, kept for a rejection (both already in
+        // the storage type)
+        io.set_q0(narrow<Q>(q));
+        io.set_g0(narrow<Q>(G));
+      }
+      if constexpr (MODE != kXGrad) {
+        double2 p = make_double2(0.0, 0.0);
+        if constexpr (kStartOfChain) {
+          // momentum refresh p ~ N(0, M): Re and Im of a retained mode each
+          // with variance 2 / sigma_k^2; an entry of the kz = 0 plane whose
+          // Hermitian partner (-kx, -ky, 0) is canonical (ny > 0, or ny = 0 and
+          // nx > 0) takes the conjugate of the partner's draw
+          if (keep) {
+            const bool mirror = kz == 0 && (sy < 0 || (sy == 0 && sx < 0));
+            const size_t src = mirror ? gofs<N>((N - x) & (N - 1), (N - y) & (N - 1), 0) : gofs<N>(x, y, kz);
+            const double2 z = normal_pair(draw_words(save.seed, save.iteration, kPurposeModes, src));
+            const double sc = sqrt(2.0 * inv_or_zero(var));
+            // drawn in FP64; K0 and the kick take the value as stored
+            p = rounded<Q>(make_double2(sc * z.x, mirror ? -sc * z.y : sc * z.y));
+          }
+        } else {
+          p = widen(io.p());
+        }
+        if constexpr (MODE == kXFirst && !CHAIN) {
+          // the state this step starts from, kept where the caller asks (the
+          // callers outside chains hold complex128 states)
+          static_assert(sizeof(Q) == 16, "complex128 state outside chains");
+          const size_t g = gofs<N>(x, y, kz);
+          if (save.sv_q) st_stream(&save.sv_q[g], narrow<double2>(q));
+          if (save.sv_p) st_stream(&save.sv_p[g], narrow<double2>(p));
+        }
+        // per stored mode (w / 8) sigma^2 |p|^2, w = 1 on kz = 0 (both
+        // Hermitian partners stored), else 2
+        const double wk = kz == 0 ? 0.125 : 0.25;
+        if (kStartOfChain && keep) kin.add(wk * var * (p.x * p.x + p.y * p.y));
+        p.x -= hk * G.x;
+        p.y -= hk * G.y;
+        p = rounded<Q>(p);
+        if (MODE == kXLast && keep) kin.add(wk * var * (p.x * p.x + p.y * p.y));
+        io.set_p(narrow<Q>(p));
+        if constexpr (kDrift) {
+          double2 a = make_double2(0.0, 0.0);
+          if (keep) {
+            const double c = eps * (0.5 * var);
+            q.x += c * p.x;
+            q.y += c * p.y;
+            q = rounded<Q>(q);   // the prior energy and the next gradient are those of the stored modes
+            io.set_q(narrow<Q>(q));
+            prior.add((kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(var));
+            const double kf = mode_kfac(tab.kfac0, n2);
+            a = make_double2(-kf * q.y, kf * q.x);      // i kfac q
+          }
+          const C ain = cconvert<C>(a), bn = cconvert<C>(make_double2((double)sx * a.x, (double)sx * a.y));
+          if constexpr (kPair) {
+            // over this element's own spectra, which only this thread reads
+            tile[LAY2::idx(x, w)] = ain;
+            tile[LAY2::idx(x, S::W + w)] = bn;
+          } else {
+            acc[e] = ain;                                // A-input (acc is free now)
+            bin[e] = bn;
+          }
+        }
+      }
+    };
     struct alignas(16) QPair { Q v[2]; };
     tile_vecs<T, N, NT>([&](int, int x, int w) {   // w even: elements w and w + 1
       const size_t g = gofs<N>(x, y, z0 + w);
@@ -1238,13 +1226,104 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
       if constexpr (kDrift) st_stream(reinterpret_cast<QPair*>(&modes[g]), QPair{{io[0].qs, io[1].qs}});
     });
   } else {
+    // one element per lane, reading and writing the arrays where the update
+    // needs them (the update of step above, in the form whose register use
+    // the unpaired and complex128 passes were tuned with)
     tile_elems<T, N, NT>([&](int e, int x, int w) {
-      const int kz = z0 + w;
-      const bool keep = retained(signed_freq(x, N), sy, kz, N);
-      const double var_ld = keep ? ld_stream(&tab.var[var_ofs(N, S::W, x, y, kz)]) : 0.0;
-      ElemIo io{modes, mom, gcache, q0a, g0a, gofs<N>(x, y, kz), nullptr};
-      if constexpr (kPrefetchP) io.pre = &ppf[e];
-      step(e, x, w, var_ld, io);
+      const int kz = z0 + w, sx = signed_freq(x, N);
+      const size_t g = gofs<N>(x, y, kz);
+      const bool keep = retained(sx, sy, kz, N);
+      const int n2 = sx * sx + sy * sy + kz * kz;
+      const double var = keep ? ld_stream(&tab.var[var_ofs(N, S::W, x, y, kz)]) : 0.0;
+      // the mode, read once (gradient and drift)
+      double2 q = make_double2(0.0, 0.0);
+      if (kStartOfChain || (keep && (kFromSpectra || kDrift))) q = widen(ld_stream(&modes[g]));
+      double2 G = make_double2(0.0, 0.0);
+      if constexpr (kFromSpectra) {
+        if (keep) {
+          C tv;
+          if constexpr (kPair)
+            tv = cadd(cscale(tile[LAY2::idx(x, w)], (T)sx), tile[LAY2::idx(x, S::W + w)]);
+          else
+            tv = cadd(acc[e], tile[LAY::idx(x, w)]);
+          const double iv2 = 2.0 * inv_or_zero(var) * tab.inv_a, kf2 = 2.0 * mode_kfac(tab.kfac_adj, n2);
+          // -2 i kfac t = (2 kfac t.y, -2 kfac t.x)
+          G = make_double2(iv2 * q.x + kf2 * (double)tv.y, iv2 * q.y - kf2 * (double)tv.x);
+        }
+      } else {
+        G = widen(ld_stream(&gcache[g]));
+      }
+      if constexpr (MODE == kXGrad) {
+        // plane_scale 0.5: gradient per stored entry (each Hermitian partner of
+        // the kz = 0 plane taken as its own variable carries half)
+        st_stream(&gcache[g], narrow<Q>(kz == 0 ? make_double2(plane_scale * G.x, plane_scale * G.y) : G));
+      }
+      if constexpr (MODE == kXLast) st_stream(&gcache[g], narrow<Q>(G));
+      if constexpr (kStartOfChain) {
+        // the start of the trajectory, kept for a rejection (both already in
+        // the storage type)
+        st_stream(&reinterpret_cast<Q*>(save.q0)[g], narrow<Q>(q));
+        st_stream(&reinterpret_cast<Q*>(save.g0)[g], narrow<Q>(G));
+      }
+      if constexpr (MODE != kXGrad) {
+        double2 p = make_double2(0.0, 0.0);
+        if constexpr (kStartOfChain) {
+          // momentum refresh p ~ N(0, M): Re and Im of a retained mode each
+          // with variance 2 / sigma_k^2; an entry of the kz = 0 plane whose
+          // Hermitian partner (-kx, -ky, 0) is canonical (ny > 0, or ny = 0 and
+          // nx > 0) takes the conjugate of the partner's draw
+          if (keep) {
+            const bool mirror = kz == 0 && (sy < 0 || (sy == 0 && sx < 0));
+            const size_t src = mirror ? gofs<N>((N - x) & (N - 1), (N - y) & (N - 1), 0) : g;
+            const double2 z = normal_pair(draw_words(save.seed, save.iteration, kPurposeModes, src));
+            const double sc = sqrt(2.0 * inv_or_zero(var));
+            // drawn in FP64; K0 and the kick take the value as stored
+            p = rounded<Q>(make_double2(sc * z.x, mirror ? -sc * z.y : sc * z.y));
+          }
+        } else if constexpr (kPrefetchP) {
+          p = widen(ppf[e]);
+        } else {
+          p = widen(ld_stream(&mom[g]));
+        }
+        if constexpr (MODE == kXFirst && !CHAIN) {
+          // the state this step starts from, kept where the caller asks (the
+          // callers outside chains hold complex128 states)
+          static_assert(sizeof(Q) == 16, "complex128 state outside chains");
+          if (save.sv_q) st_stream(&save.sv_q[g], narrow<double2>(q));
+          if (save.sv_p) st_stream(&save.sv_p[g], narrow<double2>(p));
+        }
+        // per stored mode (w / 8) sigma^2 |p|^2, w = 1 on kz = 0 (both
+        // Hermitian partners stored), else 2
+        const double wk = kz == 0 ? 0.125 : 0.25;
+        if (kStartOfChain && keep) kin.add(wk * var * (p.x * p.x + p.y * p.y));
+        p.x -= hk * G.x;
+        p.y -= hk * G.y;
+        p = rounded<Q>(p);
+        if (MODE == kXLast && keep) kin.add(wk * var * (p.x * p.x + p.y * p.y));
+        st_stream(&mom[g], narrow<Q>(p));
+        if constexpr (kDrift) {
+          double2 a = make_double2(0.0, 0.0);
+          if (keep) {
+            const double c = eps * (0.5 * var);
+            q.x += c * p.x;
+            q.y += c * p.y;
+            q = rounded<Q>(q);   // the prior energy and the next gradient are those of the stored modes
+            st_stream(&modes[g], narrow<Q>(q));
+            prior.add((kz == 0 ? 0.5 : 1.0) * (q.x * q.x + q.y * q.y) * inv_or_zero(var));
+            const double kf = mode_kfac(tab.kfac0, n2);
+            a = make_double2(-kf * q.y, kf * q.x);      // i kfac q
+          }
+          const C ain = cconvert<C>(a), bn = cconvert<C>(make_double2((double)sx * a.x, (double)sx * a.y));
+          if constexpr (kPair) {
+            // over this element's own spectra, which only this thread reads
+            tile[LAY2::idx(x, w)] = ain;
+            tile[LAY2::idx(x, S::W + w)] = bn;
+          } else {
+            acc[e] = ain;                                // A-input (acc is free now)
+            bin[e] = bn;
+          }
+        }
+      }
     });
   }
   if constexpr (kKinetic) {
