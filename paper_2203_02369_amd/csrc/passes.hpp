@@ -1024,8 +1024,9 @@ x_pass_body(const cplx_t<T>* s1, const cplx_t<T>* s2, Q* __restrict__ modes, Q* 
   // transforms instead of four, with every thread busy in each stage (a
   // W-wide batch of 256-point transforms has half as many butterflies per
   // stage as 512 threads), and no tile held in registers across a transform.
-  // Otherwise one tile at a time.
-  constexpr bool kPair = 2 * LAY::size(N) * (int)sizeof(C) <= 72 * 1024;
+  // Otherwise one tile at a time (also at 512^3 in FP32, whose two tiles just
+  // fill 72 KB: paired there, the x pass was 7 % slower).
+  constexpr bool kPair = 2 * LAY::size(N) * (int)sizeof(C) < 72 * 1024;
   using LAY2 = RowLayout<C, 2 * S::W>;
   constexpr int kTileSize = kPair ? LAY2::size(N) : LAY::size(N);
   __shared__ C tile[kTileSize];
