@@ -551,7 +551,7 @@ inv_z_gather_body(const cplx_t<T>* __restrict__ vx, const cplx_t<T>* __restrict_
   using C = cplx_t<T>;
   using S = PassShape<T, N>;
   using LAY = typename S::Pen;
-  constexpr int P = S::PG, H = S::H, F = S::FG;
+  constexpr int P = S::PG, F = S::FG;
   __shared__ C buf[LAY::size(F)];
   __shared__ C twl[N];
   const int x = x0 + blockIdx.y, y0 = blockIdx.x * P;
