@@ -200,3 +200,49 @@ def test_512_leapfrog_is_reversible_fp64(hl):
     assert rel_inf(qd.cpu().numpy(), d) <= 1e-10
     assert abs(qs.item() - 1.5) <= 1e-10
     plan.close()
+
+
+@pytest.mark.timeout(600)
+def test_512_fp32_chain_matches_fp64_chain(hl):
+    # Above 256^3 the FP32 chain updates its complex64 state one mode per
+    # lane (below, two).  Same start, same Philox stream: the FP32 chain's
+    # dH differs from the FP64 chain's by the FP32 fields (1e-3 allowed, as
+    # at 256^3) plus the rounding of its stored state, about sqrt(D) 2^-24
+    # per update of all D real mode coordinates, seven updates per 3-step
+    # trajectory, allowed at four standard deviations; the accept decisions
+    # agree unless |ln u + dH| is within that bound.  The retained modes
+    # come back as complex64 values.
+    from oracle import philox
+    kw, qn, d, var = problem()
+    n_iter, n_lf, eps, seed = 2, 3, 1.2e-4, 5120
+    res = {}
+    for precision in ("fp64", "fp32"):
+        say("512^3 %s chain" % precision)
+        plan = hl.Plan(**kw, precision=precision)
+        dev = plan.device
+        q = torch.from_numpy(qn).to(dev)
+        qd = torch.from_numpy(d).to(dev)
+        qs = plan.scalar(1.5)
+        dh = torch.zeros(n_iter, dtype=torch.float64, device=dev)
+        acc = torch.zeros(n_iter, dtype=torch.int32, device=dev)
+        hl.hmc_run([plan], [q], [qd], [qs], n_iter=n_iter, n_leapfrog=n_lf, eps0=eps, seed=seed, dh=[dh],
+                   accepted=[acc])
+        torch.cuda.synchronize()
+        res[precision] = (dh.cpu().numpy(), acc.cpu().numpy(), q.cpu().numpy())
+        plan.close()
+    dh64, acc64, _ = res["fp64"]
+    dh32, acc32, q32 = res["fp32"]
+    n_real = 2 * int(np.count_nonzero(var))
+    bound = 1e-3 + 4.0 * math.sqrt(7 * n_real) * 2.0 ** -24
+    err = float(np.abs(dh32 - dh64).max())
+    say("512^3 chains: dH fp64 %s fp32 %s, max difference %.3g (bound %.3g); decisions %s %s"
+        % (dh64.tolist(), dh32.tolist(), err, bound, acc64.tolist(), acc32.tolist()))
+    assert np.all(np.isfinite(dh64)) and err <= bound
+    for it in range(n_iter):
+        if acc32[it] != acc64[it]:
+            ln_u = math.log(float(philox.uniform53(*philox.draw_words(seed, it, philox.PURPOSE_ACCEPT, [0])[0, :2])))
+            assert abs(ln_u + dh64[it]) <= bound, "a decision away from a tie differs"
+            break
+    keep = var > 0
+    r = q32[keep]
+    assert np.array_equal(r, r.astype(np.complex64).astype(np.complex128))
