@@ -6,7 +6,12 @@
 
 namespace hamlet {
 
-constexpr int kGalThreads = 256;
+// Block sizes: one thread per point.  The binning kernels run in blocks of
+// one wave, spread over more compute units; the likelihood kernel in blocks
+// of four (its partial sums are per block, and its last block sums them all:
+// smaller blocks made launches that carry several plans slower).
+constexpr int kGalThreads = 64;
+constexpr int kLikeThreads = 256;
 
 // Catalogue and distance-prior data on the device (by galaxy id).
 struct Catalogue {
@@ -251,7 +256,7 @@ __device__ __forceinline__ void
 like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, const double* __restrict__ frac,
           double* __restrict__ dist, const double* snl_q, Catalogue cat, Cosmo cm, T* __restrict__ gsort,
           LikeOut out, LeapUpdate lf, const BinNext* next) {
-  __shared__ double red[2 * 6 * (kGalThreads / 64)];
+  __shared__ double red[2 * 6 * (kLikeThreads / 64)];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double psi = 0.0, dps = 0.0, bad = 0.0, gu = 0.0, dmw = 0.0;
   if (i < cat.n) {
@@ -538,7 +543,7 @@ template <typename T, int N> __device__ __forceinline__ SmallState small_state(c
 }
 
 template <typename T, int N>
-__global__ void __launch_bounds__(kGalThreads) k_like(Launch L) {
+__global__ void __launch_bounds__(kLikeThreads) k_like(Launch L) {
   const Pick<T, N> k(L);
   if (k.mode == kXSkip) return;
   if ((int)(blockIdx.x * blockDim.x) >= k.n_gal) return;   // whole block past this catalogue

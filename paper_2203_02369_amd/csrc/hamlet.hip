@@ -249,7 +249,7 @@ static hamlet_status eval_impl(const Batch& b) {
   }
   LAUNCH_CHECK();
   if (ng > 0) {
-    TIMED(b, HAMLET_K_LIKE, (k_like<T, N><<<dim3(blocks_for(ng, kGalThreads), 1, nb), kGalThreads, 0, st>>>(sel)));
+    TIMED(b, HAMLET_K_LIKE, (k_like<T, N><<<dim3(blocks_for(ng, kLikeThreads), 1, nb), kLikeThreads, 0, st>>>(sel)));
     LAUNCH_CHECK();
   }
   // plans without points still need their final sums (prior only)
@@ -483,7 +483,7 @@ template <typename T, int N> static void locate_impl(hamlet_plan* pl) {
   pl->gd = w.gd(); pl->qd0 = w.qd0(); pl->pd = w.pd(); pl->ps = w.ps(); pl->eps_slot = w.eps_slot();
   pl->dz = w.dz();
   pl->n_prior_part = F::N_PRIOR;
-  pl->n_like_part = pl->n_gal > 0 ? (int)blocks_for(pl->n_gal, kGalThreads) : 0;
+  pl->n_like_part = pl->n_gal > 0 ? (int)blocks_for(pl->n_gal, kLikeThreads) : 0;
   pl->n_kin_part = F::N_KIN;
 }
 

@@ -144,7 +144,7 @@ template <int R> struct GalaxyUnits {
   static constexpr size_t mu = 3, smu = 4, cz = 5, scz = 6;
   static constexpr size_t frac = 7;        // 3 doubles
   static constexpr size_t gd = 10, gd0 = 11, qd0 = 12, pd = 13;
-  static constexpr size_t like_part = 14;  // kLikeVals doubles per block of 256 galaxies
+  static constexpr size_t like_part = 14;  // kLikeVals doubles per likelihood block
   static constexpr size_t key = 15, cellz = 16, slot = 17, iz = 18;   // ints
   static constexpr size_t rx = 19, ry = 20, rz = 21, tx = 22, ty = 23, tz = 24, gsort = 25;   // reals
   static constexpr size_t bpos = 26;       // binned index of each galaxy
