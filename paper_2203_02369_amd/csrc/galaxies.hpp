@@ -232,10 +232,12 @@ bin_rank_body(const int* __restrict__ off, const int* __restrict__ key, const in
 // written for a deterministic final sum.
 // ---------------------------------------------------------------------------
 // Binning of the next evaluation, done by the likelihood kernel inside a
-// trajectory (after the drift of the distances).
+// trajectory (after the drift of the distances) when `rebin` is set.  Passed
+// by value: a pointer to a local copy would put it in scratch memory.
 struct BinNext {
   BinOut out;
   int n_grid;
+  bool rebin;
 };
 
 // Values per block of the likelihood's partial sums: Psi, dPsi/ds, invalid
@@ -255,7 +257,7 @@ template <typename T>
 __device__ __forceinline__ void
 like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, const double* __restrict__ frac,
           double* __restrict__ dist, const double* snl_q, Catalogue cat, Cosmo cm, T* __restrict__ gsort,
-          LikeOut out, LeapUpdate lf, const BinNext* next) {
+          LikeOut out, LeapUpdate lf, BinNext next) {
   __shared__ double red[2 * 6 * (kLikeThreads / 64)];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double psi = 0.0, dps = 0.0, bad = 0.0, gu = 0.0, dmw = 0.0;
@@ -316,7 +318,7 @@ like_body(const cplx_t<T>* __restrict__ part, const int* __restrict__ bpos, cons
       lf.p[i] = pv;
       if (lf.drift) dist[i] = dist[i] + e * lf.minv * pv;
     }
-    if (next) bin_point(i, dist[i], cat, cm, next->n_grid, next->out);
+    if (next.rebin) bin_point(i, dist[i], cat, cm, next.n_grid, next.out);
     bad = (ok_d && ok_h) ? 0.0 : 1.0;
   }
   // this block's slice of the prior partials
@@ -554,10 +556,9 @@ __global__ void __launch_bounds__(kLikeThreads) k_like(Launch L) {
   lo.prior_part = k.w.prior_part();
   lo.n_prior = pc.n_prior_part;
   lo.n_blocks = pc.n_like_part;
-  const BinNext next{bin_out(k.w), N};
   like_body<T>(k.w.part(), k.w.bpos(), k.w.frac(), k.st.qd, k.st.qs, catalogue(k.w, k.n_gal), cosmo(k.w),
                k.w.gsort(), lo, leap_update(k.mode, pc.sample_d, k.st.pd, k.st.eps, pc.minv_d),
-               k.mode == kXMid ? &next : nullptr);
+               BinNext{bin_out(k.w), N, k.mode == kXMid});
   // The plan's last block to finish completes the evaluation: it sums every
   // block's partials in block order (the final sums) and resets the ticket.
   __shared__ int last;
