@@ -199,21 +199,31 @@ bin_rank_body(const int* __restrict__ off, const int* __restrict__ key, const in
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cat.n) return;
   const int k = key[i], z = cell_z[i];
+  // the point's own record, loaded before the walk so that it arrives meanwhile
+  const T r0 = (T)cat.rhat[3 * i + 0], r1 = (T)cat.rhat[3 * i + 1], r2 = (T)cat.rhat[3 * i + 2];
+  const T f0 = (T)frac[3 * i + 0], f1 = (T)frac[3 * i + 1], f2 = (T)frac[3 * i + 2];
   const int s0 = off[k], s1 = off[k + 1];
+  // members four at a time: their ids, then their z cells, each group of
+  // loads in flight together
+  constexpr int U = 4;
   int rank = 0;
-  for (int s = s0; s < s1; ++s) {
-    const int j = placed[s];
-    const int zj = cell_z[j];
-    rank += (zj < z || (zj == z && j < i)) ? 1 : 0;
+  for (int s = s0; s < s1; s += U) {
+    int j[U], zj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = s + u < s1 ? placed[s + u] : -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) zj[u] = j[u] >= 0 ? cell_z[j[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) rank += (j[u] >= 0 && (zj[u] < z || (zj[u] == z && j[u] < i))) ? 1 : 0;
   }
   const int pos = s0 + rank;
   bpos[i] = pos;
-  rx[pos] = (T)cat.rhat[3 * i + 0];
-  ry[pos] = (T)cat.rhat[3 * i + 1];
-  rz[pos] = (T)cat.rhat[3 * i + 2];
-  tx[pos] = (T)frac[3 * i + 0];
-  ty[pos] = (T)frac[3 * i + 1];
-  tz[pos] = (T)frac[3 * i + 2];
+  rx[pos] = r0;
+  ry[pos] = r1;
+  rz[pos] = r2;
+  tx[pos] = f0;
+  ty[pos] = f1;
+  tz[pos] = f2;
   iz[pos] = z;
 }
 
